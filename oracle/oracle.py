@@ -1,0 +1,361 @@
+"""Reference (oracle) implementation of the quasi-orthogonal inverse-operator method.
+
+TEST INFRASTRUCTURE ONLY.  A plain, slow, FP64 CPU implementation that the HIP
+library is checked against.  It shares no code with the HIP path; only tests,
+the smoke check and the benchmark's CPU-baseline leg use it.
+
+Paper: S. Wang and A. Zhou, "A quasi-orthogonal method based on the inverse
+operator for Schroedinger eigenvalue problems".  Section / equation references
+below are to that paper:
+
+  * Sec. 2.1   inner-product matrices <U,V>, <U,V>_a and the energy E(U)
+  * Sec. 3.1   inverse operator G = (-Lap + V)^{-1} and the Grassmann gradient
+  * Sec. 4.1   the two-stage scheme (predictor / corrector), the operator A_U,
+               its Cayley form, and the auxiliary matrices O_n, A_n, B_n
+  * Sec. 5     Algorithm 1 (the driver) and the error measures err_U, err_i
+
+Discretisation (the paper uses quadratic finite elements; this build uses a
+finite-difference grid): a grid function is a vector of interior values, the
+L2 inner product is the mass-weighted sum (u,v) = h^d * sum_i u_i v_i with
+h^d = prod(h_k), and the operator is H_sigma = -kappa*Lap_h + V + sigma.
+
+Readings of the paper taken here (each also listed in the design notes):
+  R1  G is applied to a block by per-column Jacobi-PCG (``solve``); a direct
+      sparse factorisation (``solve_direct``) is available for exact tests.
+  R2  In A_U V = G U <U,V> - U <U, G V> the second term is evaluated with the
+      symmetry of G as U <G U, V> = U <P, V>, P the computed G U, so A_U is
+      exactly skew for the computed P and no solve with G V is needed.
+  R3  The implicit predictor is solved exactly: since A_U maps into
+      span{U, P}, U_hat = U X + P Y and the scheme reduces to a linear system
+      for the coefficient matrices (``predictor``).
+  R4  O_n in the corrector is the computed <U_hat, U_hat> - I (the literal
+      second line of the scheme).
+  R5  Warm starts: G U_n starts from the previous G U_hat; G U_hat starts from
+      P (X + C Y) with C = <U,U>^{-1} <U,P> (exact when span U is invariant).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libqo_oracle.so")
+_SRC_PATH = os.path.join(_HERE, "qo_oracle.c")
+_lib = None
+
+ORC_OK, ORC_NOT_SPD, ORC_NOCONV, ORC_NONFINITE = 0, 1, 2, 3
+
+
+def build_lib(force: bool = False) -> str:
+    """Compile the C part of the oracle with gcc (plain -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH) or (
+        os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC_PATH)
+    ):
+        import subprocess
+
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC_PATH, "-lm"]
+        )
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build_lib()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.orc_apply.argtypes = [ctypes.c_int, ip, dp, ctypes.c_double, ctypes.c_double,
+                                  dp, dp, dp, ctypes.c_int]
+        lib.orc_apply.restype = None
+        lib.orc_quad.argtypes = lib.orc_apply.argtypes
+        lib.orc_quad.restype = None
+        lib.orc_pcg.argtypes = [ctypes.c_int, ip, dp, ctypes.c_double, ctypes.c_double,
+                                dp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_int, ip, ip]
+        lib.orc_pcg.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _fcols(X, ng):
+    """Column-major (ng, ncols) FP64 view; columns contiguous."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X.reshape(ng, 1)
+    return np.asfortranarray(X)
+
+
+@dataclass
+class Problem:
+    """Discrete problem: grid, operator H_sigma = -kappa Lap_h + V + sigma (Sec. 2.1/2.2)."""
+
+    dim: int
+    n: tuple
+    V: np.ndarray
+    L: tuple = (1.0, 1.0, 1.0)
+    kappa: float = 0.5
+    sigma: float = 0.0
+    h: np.ndarray = field(init=False)
+    w: float = field(init=False)
+    ng: int = field(init=False)
+
+    def __post_init__(self):
+        n = tuple(int(v) for v in self.n)[: self.dim]
+        self.n = n
+        self.h = np.array([self.L[k] / (n[k] + 1) for k in range(self.dim)], dtype=np.float64)
+        # weight of the discrete L2 inner product (mass matrix of the FD grid)
+        self.w = float(np.prod(self.h))
+        self.ng = int(np.prod(n))
+        self.V = np.ascontiguousarray(np.asarray(self.V, dtype=np.float64).reshape(self.ng))
+        self._n3 = np.array(list(n) + [1] * (3 - self.dim), dtype=np.int32)
+        self._h3 = np.array(list(self.h) + [1.0] * (3 - self.dim), dtype=np.float64)
+
+    # ---- Sec. 2.1: inner-product matrices --------------------------------
+    def inner(self, X, Y):
+        """<X, Y> = ((x_i, y_j))_{ij} with the grid L2 inner product."""
+        return self.w * (np.asarray(X).T @ np.asarray(Y))
+
+    # ---- the operator and its inverse -----------------------------------
+    def apply(self, X):
+        """H_sigma X, column by column."""
+        X = _fcols(X, self.ng)
+        Y = np.empty_like(X, order="F")
+        _load().orc_apply(self.dim, _ip(self._n3), _dp(self._h3), self.kappa, self.sigma,
+                          _dp(self.V), _dp(X), _dp(Y), X.shape[1])
+        return Y
+
+    def quad(self, X):
+        """x_j . (H_sigma x_j) per column (unweighted)."""
+        X = _fcols(X, self.ng)
+        out = np.empty(X.shape[1], dtype=np.float64)
+        _load().orc_quad(self.dim, _ip(self._n3), _dp(self._h3), self.kappa, self.sigma,
+                         _dp(self.V), _dp(X), _dp(out), X.shape[1])
+        return out
+
+    def solve(self, B, X0=None, tol=1e-10, maxit=10000):
+        """G B = H_sigma^{-1} B by per-column Jacobi-PCG (reading R1).
+
+        Returns (X, iters, status, col_status)."""
+        B = _fcols(B, self.ng)
+        if X0 is None:
+            X = np.zeros_like(B, order="F")
+            use_x0 = 0
+        else:
+            X = np.array(_fcols(X0, self.ng), order="F", copy=True)
+            use_x0 = 1
+        iters = np.zeros(B.shape[1], dtype=np.int32)
+        cst = np.zeros(B.shape[1], dtype=np.int32)
+        st = _load().orc_pcg(self.dim, _ip(self._n3), _dp(self._h3), self.kappa, self.sigma,
+                             _dp(self.V), _dp(B), _dp(X), B.shape[1], tol, maxit, use_x0,
+                             _ip(iters), _ip(cst))
+        return X, iters, int(st), cst
+
+    def sparse_matrix(self):
+        """H_sigma as a scipy sparse matrix (Kronecker sum of 1-D second differences)."""
+        import scipy.sparse as sp
+
+        mats = []
+        for k in range(self.dim):
+            m = self.n[k]
+            T = sp.diags([np.full(m - 1, -1.0), np.full(m, 2.0), np.full(m - 1, -1.0)],
+                         [-1, 0, 1]) * (self.kappa / self.h[k] ** 2)
+            mats.append(T.tocsr())
+        H = sp.csr_matrix((self.ng, self.ng))
+        for k in range(self.dim):
+            left = sp.identity(int(np.prod(self.n[k + 1:])) if k + 1 < self.dim else 1)
+            right = sp.identity(int(np.prod(self.n[:k])) if k > 0 else 1)
+            # x fastest: axis 0 is the innermost Kronecker factor
+            H = H + sp.kron(sp.kron(left, mats[k]), right)
+        H = H + sp.diags(self.V + self.sigma)
+        return H.tocsc()
+
+    def solve_direct(self, B):
+        """G B by a sparse LU factorisation (exact up to rounding)."""
+        import scipy.sparse.linalg as spla
+
+        if not hasattr(self, "_lu"):
+            self._lu = spla.splu(self.sparse_matrix())
+        B = _fcols(B, self.ng)
+        return np.asfortranarray(self._lu.solve(np.ascontiguousarray(B)))
+
+    # ---- Sec. 2.1 energy ---------------------------------------------------
+    def energy(self, U):
+        """(E(U), E_sigma(U)): E = 1/2 tr <U,U>_a with a(u,v) = (u, H v); E_sigma with H_sigma."""
+        U = _fcols(U, self.ng)
+        e_sigma = 0.5 * self.w * float(np.sum(self.quad(U)))
+        e = e_sigma - 0.5 * self.sigma * float(np.trace(self.inner(U, U)))
+        return e, e_sigma
+
+
+# ---------------------------------------------------------------------------
+# Sec. 4.1: the two stages of the scheme
+# ---------------------------------------------------------------------------
+
+def predictor(prob: Problem, U, P, tau):
+    """First stage of the scheme: (U_hat - U)/tau = A_U U_tilde, U_tilde = (U_hat + U)/2.
+
+    A_U V = P <U,V> - U <P,V> (reading R2) maps into span{U, P}, so
+    U_hat = U X + P Y.  With U_tilde = U (X+I)/2 + P Y/2 the stage reads
+        Y = tau <U, U_tilde>,   X = I - tau <P, U_tilde>.
+    Writing X = I + tau b, Y = tau a and alpha = tau/2 this is the linear system
+        (I - alpha M) a - alpha S b   = S
+        alpha R a + (I + alpha M^T) b = -M^T
+    with S = <U,U>, M = <U,P>, R = <P,P>.  Returns (U_hat, X, Y, (S, M, R))."""
+    N = U.shape[1]
+    S = prob.inner(U, U)
+    M = prob.inner(U, P)
+    R = prob.inner(P, P)
+    alpha = 0.5 * tau
+    I = np.eye(N)
+    K = np.block([[I - alpha * M, -alpha * S], [alpha * R, I + alpha * M.T]])
+    rhs = np.vstack([S, -M.T])
+    sol = np.linalg.solve(K, rhs)
+    a, b = sol[:N], sol[N:]
+    X = I + tau * b
+    Y = tau * a
+    U_hat = np.asfortranarray(U @ X + P @ Y)
+    return U_hat, X, Y, (S, M, R)
+
+
+def corrector(prob: Problem, U_hat, Q, tau):
+    """Second stage: U_{n+1} = U_hat - tau G U_hat (<U_hat,U_hat> - I), Q = G U_hat (reading R4).
+
+    Returns (U_next, O, A, B) with O = <U_hat,U_hat> - I, A = <U_hat, Q>, B = <Q, Q>
+    (the auxiliary matrices of Sec. 4.1; O equals O_n when the first stage preserves
+    the Gram matrix)."""
+    N = U_hat.shape[1]
+    S_hat = prob.inner(U_hat, U_hat)
+    S_hat = 0.5 * (S_hat + S_hat.T)
+    O = S_hat - np.eye(N)
+    A = prob.inner(U_hat, Q)
+    Bm = prob.inner(Q, Q)
+    U_next = np.asfortranarray(U_hat - tau * (Q @ O))
+    return U_next, O, A, Bm
+
+
+def grad_norm(prob: Problem, U, P):
+    """|| grad_G E_G(U) || = || G U - U <G U, U> || in the grid L2 norm (Sec. 3.1, Alg. 1)."""
+    Mt = prob.inner(P, U)
+    Gr = P - U @ Mt
+    return float(np.sqrt(prob.w * np.sum(Gr * Gr)))
+
+
+@dataclass
+class StepStats:
+    energy: float
+    energy_shifted: float
+    orth_err_fro: float
+    grad_norm: float
+    pcg_iters: tuple
+    pcg_iters_cols: tuple = ()
+
+
+class Oracle:
+    """Algorithm 1 driver with a fixed time step (Sec. 5)."""
+
+    def __init__(self, prob: Problem, U0, tol=1e-10, maxit=20000, warm_start=True,
+                 direct=False):
+        self.prob = prob
+        self.U = np.array(_fcols(U0, prob.ng), order="F", copy=True)
+        self.tol = tol
+        self.maxit = maxit
+        self.warm = warm_start
+        self.direct = direct
+        self.prevQ = None
+        self.n = 0
+        self.last = {}
+
+    def _G(self, B, X0):
+        if self.direct:
+            return self.prob.solve_direct(B), np.zeros(B.shape[1], dtype=np.int32)
+        X, it, st, _ = self.prob.solve(B, X0=X0, tol=self.tol, maxit=self.maxit)
+        if st != ORC_OK:
+            raise RuntimeError(f"oracle PCG failed with status {st}")
+        return X, it
+
+    def step(self, tau):
+        prob, U = self.prob, self.U
+        x0 = self.prevQ if (self.warm and self.prevQ is not None) else None
+        P, itP = self._G(U, x0)
+        gnorm = grad_norm(prob, U, P)
+        U_hat, X, Y, (S, M, R) = predictor(prob, U, P, tau)
+        x0Q = None
+        if self.warm:
+            C = np.linalg.solve(S, M)
+            x0Q = np.asfortranarray(P @ (X + C @ Y))
+        Q, itQ = self._G(U_hat, x0Q)
+        U_next, O, A, Bm = corrector(prob, U_hat, Q, tau)
+        self.last = dict(P=P, U_hat=U_hat, Q=Q, X=X, Y=Y, S=S, M=M, R=R, O=O, A=A, B=Bm,
+                         U_prev=U)
+        self.U = U_next
+        self.prevQ = Q
+        self.n += 1
+        e, es = prob.energy(U_next)
+        return StepStats(e, es, float(np.linalg.norm(O)), gnorm,
+                         (int(itP.max(initial=0)), int(itQ.max(initial=0))),
+                         (tuple(int(v) for v in itP), tuple(int(v) for v in itQ)))
+
+    def run(self, tau, nsteps):
+        return [self.step(tau) for _ in range(nsteps)]
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5: eigenvalue read-out and error measures
+# ---------------------------------------------------------------------------
+
+def ritz(prob: Problem, U):
+    """Rayleigh-Ritz on span U: K c = theta S c, K = <U, H_sigma U>, S = <U,U>.
+
+    Returns (lambda ascending, coefficient matrix c); lambda = theta - sigma."""
+    import scipy.linalg as sla
+
+    U = _fcols(U, prob.ng)
+    K = prob.inner(U, prob.apply(U))
+    K = 0.5 * (K + K.T)
+    S = prob.inner(U, U)
+    S = 0.5 * (S + S.T)
+    theta, c = sla.eigh(K, S)
+    return theta - prob.sigma, c
+
+
+def paper_eigenvalues(prob: Problem, U, P):
+    """lambda_i = eigenvalues of <G U, U>^{-1} (Sec. 5 definition of err_i), minus the shift."""
+    T = prob.inner(P, U)
+    T = 0.5 * (T + T.T)
+    mu = np.linalg.eigvalsh(T)
+    return np.sort(1.0 / mu) - prob.sigma
+
+
+def err_eigen(lam, lam_ref):
+    """err_i = |lambda_i - lambda_i^*| / |lambda_i^*| (Sec. 5)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    lam_ref = np.asarray(lam_ref, dtype=np.float64)
+    return np.abs(lam - lam_ref) / np.abs(lam_ref)
+
+
+def err_state(Un, Uend):
+    """err_U = ||U_n - U_end|| / ||U_end|| (Sec. 5)."""
+    return float(np.linalg.norm(np.asarray(Un) - np.asarray(Uend)) / np.linalg.norm(Uend))
+
+
+def subspace_sin(A, B):
+    """sin of the largest principal angle between span A and span B (Euclidean)."""
+    qa, _ = np.linalg.qr(np.asarray(A))
+    qb, _ = np.linalg.qr(np.asarray(B))
+    r = qb - qa @ (qa.T @ qb)
+    return float(np.linalg.norm(r, 2))

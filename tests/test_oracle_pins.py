@@ -1,0 +1,363 @@
+"""Pins of the oracle against facts fixed by the paper and by mathematics (CPU only).
+
+Each test names what it pins.  None of them compares the oracle with itself:
+closed forms, brute-force dense linear algebra, the paper's identities and
+worked numbers, and invariants of the scheme.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2605_25149_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense_H(dim, n, L, kappa, sigma, V):
+    """Dense H_sigma assembled entry by entry from the 5/7-point stencil (independent of the oracle)."""
+    n = list(n)
+    h = [L[k] / (n[k] + 1) for k in range(dim)]
+    ng = int(np.prod(n))
+    H = np.zeros((ng, ng))
+    strides = [1, n[0], n[0] * (n[1] if dim > 1 else 1)]
+    for idx in range(ng):
+        coords = []
+        rem = idx
+        for k in range(dim):
+            coords.append(rem % n[k])
+            rem //= n[k]
+        H[idx, idx] = V[idx] + sigma + sum(2 * kappa / h[k] ** 2 for k in range(dim))
+        for k in range(dim):
+            if coords[k] > 0:
+                H[idx, idx - strides[k]] = -kappa / h[k] ** 2
+            if coords[k] < n[k] - 1:
+                H[idx, idx + strides[k]] = -kappa / h[k] ** 2
+    return H
+
+
+def sep_1d(n, L, kappa, vfun):
+    """1-D dense eigenvalues of -kappa d2/dx2 + v(x) on n interior points."""
+    h = L / (n + 1)
+    x = (np.arange(n) + 1) * h
+    T = (np.diag(np.full(n, 2 * kappa / h**2) + vfun(x))
+         + np.diag(np.full(n - 1, -kappa / h**2), 1) + np.diag(np.full(n - 1, -kappa / h**2), -1))
+    return np.linalg.eigvalsh(T)
+
+
+# ---------------------------------------------------------------------------
+# operator
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,L", [(2, (9, 7), (1.0, 1.3)), (3, (6, 5, 7), (1.0, 0.8, 1.2))])
+def test_stencil_sine_modes(oracle_mod, dim, n, L):
+    """V = 0: the sine modes are eigenvectors of -kappa Lap_h with eigenvalue
+    sum_k 4 kappa / h_k^2 sin^2(m_k pi h_k / (2 L_k)) (closed form)."""
+    O = oracle_mod
+    prob = O.Problem(dim, n, np.zeros(int(np.prod(n))), L=L, kappa=0.5, sigma=0.0)
+    xs = inputs.grid_coords(n, L)
+    for modes in [(1, 1, 1), (2, 3, 1), (n[0], 1, 2)]:
+        u = np.ones(prob.ng)
+        lam = 0.0
+        for k in range(dim):
+            m = modes[k]
+            u *= np.sin(m * np.pi * xs[k] / L[k])
+            lam += 4 * 0.5 / prob.h[k] ** 2 * np.sin(m * np.pi * prob.h[k] / (2 * L[k])) ** 2
+        Hu = prob.apply(u)[:, 0]
+        assert np.max(np.abs(Hu - lam * u)) <= 1e-12 * lam
+
+
+@pytest.mark.parametrize("dim,n", [(2, (5, 4)), (3, (3, 4, 3))])
+def test_stencil_dense_bruteforce(oracle_mod, dim, n):
+    """H_sigma X equals the dense stencil matrix times X, and the sparse (direct-mode)
+    matrix equals the dense one."""
+    O = oracle_mod
+    rng = np.random.default_rng(5)
+    L = (1.0, 1.1, 0.9)[:dim]
+    V = rng.standard_normal(int(np.prod(n)))
+    prob = O.Problem(dim, n, V, L=L, kappa=0.7, sigma=0.3)
+    H = dense_H(dim, n, L, 0.7, 0.3, V)
+    X = rng.standard_normal((prob.ng, 3))
+    np.testing.assert_allclose(prob.apply(X), H @ X, rtol=0, atol=1e-12 * np.abs(H).max())
+    np.testing.assert_allclose(prob.sparse_matrix().toarray(), H, rtol=0, atol=1e-12 * np.abs(H).max())
+    q = prob.quad(X)
+    np.testing.assert_allclose(q, np.einsum("ij,ij->j", X, H @ X), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# inverse operator
+# ---------------------------------------------------------------------------
+
+def test_pcg_matches_dense_solve(oracle_mod):
+    """PCG: true residual <= tol-level and the solution agrees with a dense solve."""
+    O = oracle_mod
+    n = (7, 6, 5)
+    V = inputs.gaussian_wells(n, seed=0)
+    prob = O.Problem(3, n, V)
+    H = dense_H(3, n, (1, 1, 1), 0.5, 0.0, prob.V)
+    B = inputs.random_block(prob.ng, 4, seed=3)
+    X, it, st, _ = prob.solve(B, tol=1e-12)
+    assert st == O.ORC_OK and np.all(it > 0)
+    Xd = np.linalg.solve(H, B)
+    assert np.max(np.abs(X - Xd)) <= 1e-9 * np.max(np.abs(Xd))
+    res = np.linalg.norm(B - H @ X, axis=0) / np.linalg.norm(B, axis=0)
+    assert np.all(res <= 1e-11)
+    # a warm start at the solution converges in zero iterations
+    X2, it2, st2, _ = prob.solve(B, X0=Xd, tol=1e-10)
+    assert st2 == O.ORC_OK and np.all(it2 == 0)
+
+
+def test_pcg_error_paths(oracle_mod):
+    O = oracle_mod
+    n = (6, 6)
+    prob = O.Problem(2, n, np.zeros(36))
+    B = inputs.random_block(36, 2, seed=1)
+    _, _, st, _ = prob.solve(B, tol=1e-12, maxit=3)
+    assert st == O.ORC_NOCONV
+    neg = O.Problem(2, n, np.zeros(36), sigma=-1e5)  # indefinite: p.Hp <= 0 appears
+    _, _, st, _ = neg.solve(B, tol=1e-12)
+    assert st == O.ORC_NOT_SPD
+    Bn = B.copy()
+    Bn[3, 1] = np.nan
+    _, _, st, cst = prob.solve(Bn, tol=1e-12)
+    assert st == O.ORC_NONFINITE and cst[1] == O.ORC_NONFINITE and cst[0] == O.ORC_OK
+
+
+# ---------------------------------------------------------------------------
+# Sec. 4.1: the scheme
+# ---------------------------------------------------------------------------
+
+def _tiny_problem(O, seed=0, n=(5, 4)):
+    V = inputs.harmonic(n, 30.0)
+    return O.Problem(len(n), n, V)
+
+
+def test_predictor_is_cayley_transform(oracle_mod):
+    """First stage = Cayley transform (I - tau/2 A)^{-1} (I + tau/2 A) U_n of the skew
+    operator A V = P<U,V> - U<P,V>, which is left multiplication by the Ng x Ng matrix
+    w (P U^T - U P^T).  Brute force with an arbitrary (non-symmetric <U,P>) P."""
+    O = oracle_mod
+    prob = _tiny_problem(O)
+    rng = np.random.default_rng(11)
+    U = rng.standard_normal((prob.ng, 3))
+    P = rng.standard_normal((prob.ng, 3)) * 0.1
+    tau = 0.7
+    U_hat, X, Y, (S, M, R) = O.predictor(prob, U, P, tau)
+    K = prob.w * (P @ U.T - U @ P.T)
+    I = np.eye(prob.ng)
+    ref = np.linalg.solve(I - 0.5 * tau * K, (I + 0.5 * tau * K) @ U)
+    assert np.max(np.abs(U_hat - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # the implicit equation itself, with A applied from its definition
+    Ut = 0.5 * (U_hat + U)
+    AUt = P @ prob.inner(U, Ut) - U @ prob.inner(P, Ut)
+    assert np.max(np.abs((U_hat - U) / tau - AUt)) <= 1e-12 * np.max(np.abs(AUt))
+    # Gram preservation (Sec. 4.1, non-expansion lemma, first stage)
+    np.testing.assert_allclose(prob.inner(U_hat, U_hat), S, rtol=0, atol=1e-12 * np.abs(S).max())
+
+
+def _run(O, prob, U0, tau, nsteps, **kw):
+    orc = O.Oracle(prob, U0, **kw)
+    stats = []
+    mats = []
+    for _ in range(nsteps):
+        S_before = prob.inner(orc.U, orc.U)
+        st = orc.step(tau)
+        stats.append(st)
+        mats.append((S_before, orc.last, orc.U))
+    return orc, stats, mats
+
+
+def test_gram_recurrence_and_energy_identity(oracle_mod):
+    """With exact solves (direct mode):
+      O_{n+1} = O_n - tau (A_n O_n + O_n A_n) + tau^2 O_n B_n O_n      (Sec. 4.1)
+      E(U_{n+1}) - E(U_hat) = -tau tr(<U_n,U_n> O_n) + tau^2/2 tr(A_n O_n^2)   (Sec. 4.2)
+    (energies of the operator whose inverse is G, i.e. the shifted energy)."""
+    O = oracle_mod
+    prob = _tiny_problem(O, n=(8, 7))
+    U0 = inputs.random_block(prob.ng, 3, seed=2)
+    tau = 0.5 * 20.0
+    orc, stats, mats = _run(O, prob, U0, tau, 4, direct=True)
+    for S_before, last, U_next in mats:
+        N = S_before.shape[0]
+        On = S_before - np.eye(N)
+        A, B = last["A"], last["B"]
+        lhs = prob.inner(U_next, U_next) - np.eye(N)
+        rhs = On - tau * (A @ On + On @ A) + tau**2 * On @ B @ On
+        assert np.max(np.abs(lhs - rhs)) <= 1e-10 * max(1.0, np.abs(On).max())
+        _, e_next = prob.energy(U_next)
+        _, e_hat = prob.energy(last["U_hat"])
+        d_ref = -tau * np.trace(S_before @ On) + 0.5 * tau**2 * np.trace(A @ On @ On)
+        assert abs((e_next - e_hat) - d_ref) <= 1e-9 * max(1.0, abs(e_hat))
+
+
+def test_separable_closed_form_cfg_small(oracle_mod):
+    """2-D unit square 32x32, V = 50|x - c|^2, N = 4, tau = 0.9 lambda_1, 200 steps from a
+    random non-orthogonal start: Ritz values vs the Kronecker sum of 1-D dense spectra."""
+    O = oracle_mod
+    n = (32, 32)
+    V = inputs.harmonic(n, 100.0)
+    prob = O.Problem(2, n, V)
+    mu = sep_1d(32, 1.0, 0.5, lambda x: 50 * (x - 0.5) ** 2)
+    lam = np.sort(np.add.outer(mu, mu).ravel())
+    assert abs(lam[0] - 12.9544687) < 1e-6
+    U0 = inputs.random_block(prob.ng, 4, seed=1)
+    tau = 0.9 * lam[0]
+    orc, stats, _ = _run(O, prob, U0, tau, 200, tol=1e-12)
+    l, _ = O.ritz(prob, orc.U)
+    err = O.err_eigen(l, lam[:4])
+    assert np.all(err[:3] <= 1e-10)
+    assert err[3] <= 1e-5
+    # energy dissipation (shifted energy; sigma = 0 here), quasi-orthogonality reached
+    es = np.array([s.energy_shifted for s in stats])
+    assert np.all(np.diff(es) <= 1e-9 * np.abs(es[1:]))
+    assert stats[-1].orth_err_fro <= 1e-12
+    # E -> 1/2 sum lambda at convergence (Sec. 5 reports E(U_end) against 1/2 sum lambda_ref)
+    assert abs(stats[-1].energy - 0.5 * lam[:4].sum()) <= 1e-5 * lam[:4].sum()
+    # asymptotic rate of the gradient: log-contraction per step ~ tau (1/lam_N - 1/lam_N+1)
+    g = np.array([s.grad_norm for s in stats])
+    rate = -np.log(g[-1] / g[-41]) / 40
+    pred = tau * (1 / lam[3] - 1 / lam[4])
+    assert 0.75 * pred <= rate <= 1.25 * pred
+
+
+def test_dense_eigh_tiny_3d(oracle_mod):
+    """3-D 6^3 Gaussian wells, N = 4 (lambda_4 = 25.8 < lambda_5 = 37.6): converged Ritz values equal the lowest dense eigenvalues,
+    paper-mode eigenvalues equal them too once <U,U> = I, and the gradient vanishes."""
+    O = oracle_mod
+    n = (6, 6, 6)
+    V = inputs.gaussian_wells(n, seed=0)
+    prob = O.Problem(3, n, V)
+    H = dense_H(3, n, (1, 1, 1), 0.5, 0.0, prob.V)
+    ev = np.linalg.eigvalsh(H)
+    U0 = inputs.random_block(prob.ng, 4, seed=1)
+    tau = 0.9 * ev[0]
+    orc, stats, _ = _run(O, prob, U0, tau, 400, direct=True)
+    l, _ = O.ritz(prob, orc.U)
+    np.testing.assert_allclose(l, ev[:4], rtol=1e-10)
+    P = prob.solve_direct(orc.U)
+    np.testing.assert_allclose(O.paper_eigenvalues(prob, orc.U, P), ev[:4], rtol=1e-9)
+    assert O.grad_norm(prob, orc.U, P) <= 1e-7
+
+
+def test_paper_example1_fd(oracle_mod):
+    """Paper Example 1 (Sec. 5) on a finite-difference grid: the converged Ritz values approach
+    the exact oscillator eigenvalues 1, 2, 2, 3, 3, 3 stated in the paper, with O(h^2) error."""
+    O = oracle_mod
+    g = json.load(open(os.path.join(GOLDEN, "harmonic_table1.json")))
+    a = g["domain_half_width"]
+    exact = np.array(g["exact_first_6"])
+    errs = []
+    for m in (39, 79):
+        n = (m, m)
+        V = inputs.harmonic(n, 1.0, centre=(a, a), L=(2 * a, 2 * a))
+        prob = O.Problem(2, n, V, L=(2 * a, 2 * a))
+        mu = sep_1d(m, 2 * a, 0.5, lambda x: 0.5 * (x - a) ** 2)
+        lam_fd = np.sort(np.add.outer(mu, mu).ravel())[:7]
+        # i.i.d. N(0,1) values scaled by |Omega|^{-1/2} so that E<U0,U0> = I
+        U0 = inputs.random_block(prob.ng, 6, seed=1) / (2 * a)
+        orc, stats, _ = _run(O, prob, U0, 0.9 * lam_fd[0], 250, direct=True)
+        l, _ = O.ritz(prob, orc.U)
+        np.testing.assert_allclose(l, lam_fd[:6], rtol=1e-8)
+        errs.append(np.max(np.abs(l - exact)))
+    h_ratio = (2 * a / 40) / (2 * a / 80)
+    assert errs[0] < 0.05 and errs[1] < errs[0] / (0.8 * h_ratio**2)
+
+
+def test_quasi_stiefel_invariance_and_contraction(oracle_mod):
+    """U_0 in M_>= and tau below the bounds of Sec. 4.1 / 4.3: O_n stays positive semidefinite,
+    <U_{n+1},U_{n+1}> <= <U_n,U_n>, ||O_{n+1}||^2 <= (1 - tau/E(U_0)) ||O_n||^2."""
+    O = oracle_mod
+    n = (10, 9)
+    V = inputs.harmonic(n, 60.0)
+    prob = O.Problem(2, n, V)
+    H = dense_H(2, n, (1, 1), 0.5, 0.0, prob.V)
+    lam1 = np.linalg.eigvalsh(H)[0]
+    rng = np.random.default_rng(7)
+    Qb, _ = np.linalg.qr(rng.standard_normal((prob.ng, 3)))
+    U0 = Qb / np.sqrt(prob.w) @ np.diag([1.3, 1.1, 1.02])
+    S0 = prob.inner(U0, U0)
+    E0, _ = prob.energy(U0)
+    tau = min(lam1 / (3 * np.linalg.eigvalsh(S0).max()), E0) * 0.99
+    orc, stats, mats = _run(O, prob, U0, tau, 30, direct=True)
+    prev_norm = np.linalg.norm(S0 - np.eye(3))
+    for S_before, last, U_next in mats:
+        S_next = prob.inner(U_next, U_next)
+        O_next = S_next - np.eye(3)
+        assert np.linalg.eigvalsh(O_next).min() >= -1e-12
+        assert np.linalg.eigvalsh(S_before - S_next).min() >= -1e-12
+        nrm = np.linalg.norm(O_next)
+        assert nrm**2 <= (1 - tau / E0) * prev_norm**2 + 1e-24
+        prev_norm = nrm
+        # Sec. 4.1 matrix bounds: A_n <= S/lambda_1, B_n <= A_n/lambda_1
+        A, B = last["A"], last["B"]
+        assert np.linalg.eigvalsh(S_before / lam1 - 0.5 * (A + A.T)).min() >= -1e-12
+        assert np.linalg.eigvalsh(0.5 * (A + A.T) / lam1 - B).min() >= -1e-12
+
+
+def test_spectral_bounds_random(oracle_mod):
+    """Sec. 3.3 lemma: 1/(2E(U)) <= lambda(<U, G U>) <= lambda_max(<U,U>)/lambda_1."""
+    O = oracle_mod
+    n = (8, 8)
+    prob = O.Problem(2, n, inputs.harmonic(n, 40.0))
+    H = dense_H(2, n, (1, 1), 0.5, 0.0, prob.V)
+    lam1 = np.linalg.eigvalsh(H)[0]
+    U = inputs.random_block(prob.ng, 4, seed=9)
+    P = prob.solve_direct(U)
+    T = prob.inner(U, P)
+    ev = np.linalg.eigvalsh(0.5 * (T + T.T))
+    E, _ = prob.energy(U)
+    assert ev.min() >= 1 / (2 * E) * (1 - 1e-12)
+    assert ev.max() <= np.linalg.eigvalsh(prob.inner(U, U)).max() / lam1 * (1 + 1e-12)
+
+
+def test_scaling_metamorphic(oracle_mod):
+    """H -> 2H (kappa, V, sigma doubled) with tau -> 2 tau gives the same trajectory:
+    G halves and tau doubles, so every stage is unchanged."""
+    O = oracle_mod
+    n = (12, 10)
+    V = inputs.harmonic(n, 80.0)
+    p1 = O.Problem(2, n, V, kappa=0.5)
+    p2 = O.Problem(2, n, 2 * V, kappa=1.0)
+    U0 = inputs.random_block(p1.ng, 3, seed=4)
+    tau = 10.0
+    o1, s1, _ = _run(O, p1, U0, tau, 8, tol=1e-12)
+    o2, s2, _ = _run(O, p2, U0, 2 * tau, 8, tol=1e-12)
+    assert np.max(np.abs(o1.U - o2.U)) <= 1e-12 * np.max(np.abs(o1.U))
+    assert [s.pcg_iters for s in s1] == [s.pcg_iters for s in s2]
+
+
+def test_right_orthogonal_equivariance(oracle_mod):
+    """U_0 -> U_0 Q (Q orthogonal) gives U_n -> U_n Q: A_{UQ} = A_U and O -> Q^T O Q."""
+    O = oracle_mod
+    n = (9, 8)
+    prob = O.Problem(2, n, inputs.harmonic(n, 70.0))
+    U0 = inputs.random_block(prob.ng, 3, seed=6)
+    Qm, _ = np.linalg.qr(np.random.default_rng(1).standard_normal((3, 3)))
+    o1, _, _ = _run(O, prob, U0, 8.0, 6, direct=True)
+    o2, _, _ = _run(O, prob, U0 @ Qm, 8.0, 6, direct=True)
+    assert np.max(np.abs(o1.U @ Qm - o2.U)) <= 1e-11 * np.max(np.abs(o1.U))
+
+
+def test_orthonormal_start_stays_orthonormal(oracle_mod):
+    """<U_0,U_0> = I implies O_n = 0 for all n (discrete analogue of Sec. 3.1)."""
+    O = oracle_mod
+    n = (9, 9)
+    prob = O.Problem(2, n, inputs.harmonic(n, 50.0))
+    rng = np.random.default_rng(3)
+    Qb, _ = np.linalg.qr(rng.standard_normal((prob.ng, 3)))
+    U0 = Qb / np.sqrt(prob.w)
+    orc, stats, _ = _run(O, prob, U0, 9.0, 10, direct=True)
+    assert max(s.orth_err_fro for s in stats) <= 1e-13
+
+
+def test_paper_hydrogen_tables(oracle_mod):
+    """The paper's worked numbers (Sec. 5, Tables 2-3): E_ref = 1/2 sum lambda_ref, and the
+    printed err_i follow from the printed lambda_i and lambda_ref with the err_i definition."""
+    O = oracle_mod
+    g = json.load(open(os.path.join(GOLDEN, "hydrogen_tables.json")))
+    assert abs(0.5 * sum(g["lambda_ref"]) - g["E_ref"]) <= 1e-15
+    err = O.err_eigen(g["lambda_computed"], g["lambda_ref"])
+    np.testing.assert_allclose(err, g["err_printed"], rtol=2e-3)
+    # E(U_end) - 1/2 sum lambda_i is at the level of the solution accuracy
+    assert abs(g["E_end"] - 0.5 * sum(g["lambda_computed"])) <= 1e-9

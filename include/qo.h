@@ -1,0 +1,166 @@
+/*
+ * qo.h -- C ABI of libqo_hip.so, the MI355X (gfx950) implementation of one
+ * evolution step of the quasi-orthogonal inverse-operator method for the N
+ * lowest eigenpairs of the discrete Schroedinger operator H = -kappa Lap_h + V.
+ *
+ * Paper: S. Wang and A. Zhou, "A quasi-orthogonal method based on the inverse
+ * operator for Schroedinger eigenvalue problems".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grid: dim = 2 or 3, n[k] interior points per axis of the box
+ *    [0,L_0] x [0,L_1] (x [0,L_2]), spacing h_k = L_k / (n_k + 1), homogeneous
+ *    Dirichlet data.  Ng = n_0 n_1 (n_2).  A grid function is Ng values with x
+ *    fastest: index i + n_0 (j + n_1 k).
+ *  - Block: N grid functions stored column-major, column j at offset j*ld
+ *    (ld >= Ng), every column a contiguous grid function.  This is the
+ *    coefficient-matrix orientation of the paper's Sec. 5 (C in R^{Ng x N}).
+ *  - Inner product (Sec. 2.1): <X,Y> = ((x_i, y_j))_ij with the grid L2 inner
+ *    product (u,v) = h^d sum_i u_i v_i, h^d = prod_k h_k.
+ *  - Operator: H_sigma = -kappa Lap_h + V + sigma (5-point stencil in 2-D,
+ *    7-point in 3-D); the shift sigma is the one allowed by the Garding remark
+ *    at the end of Sec. 2.2 and must make H_sigma positive definite.  The
+ *    inverse operator of Sec. 3.1 is G = H_sigma^{-1}.
+ *  - Pointers flagged on_device are HIP device pointers (e.g. a torch tensor's
+ *    data_ptr()); others are host pointers.  The caller owns every pointer it
+ *    passes; the library owns the workspace it allocates in qo_create and frees
+ *    it in qo_destroy.  All device work is ordered on the stream given to
+ *    qo_create; host outputs are complete when a call returns.
+ *  - Every function returns a qo_status and never aborts.  Arguments are
+ *    validated before any device work.  qo_last_error(h) gives a message for
+ *    the last failing call on h.  A handle is not thread-safe; distinct handles
+ *    are independent.
+ */
+#ifndef QO_H
+#define QO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qo_ctx *qo_handle;
+
+typedef enum {
+    QO_OK = 0,
+    QO_ERR_ARG = 1,        /* invalid argument, null pointer, unsupported size */
+    QO_ERR_ALLOC = 2,      /* device or host allocation failed */
+    QO_ERR_DEVICE = 3,     /* a HIP runtime call failed */
+    QO_ERR_STATE = 4,      /* call out of order (no potential / no state yet) */
+    QO_ERR_NOT_SPD = 5,    /* <U,U> not positive definite, or p.H_sigma p <= 0 in PCG */
+    QO_ERR_PCG_NOCONV = 6, /* PCG (or refinement) hit its iteration limit */
+    QO_ERR_NONFINITE = 7   /* NaN or Inf met in the data */
+} qo_status;
+
+typedef enum { QO_FP64 = 0, QO_MIXED = 1 } qo_precision;
+typedef enum { QO_EIG_RITZ = 0, QO_EIG_PAPER = 1 } qo_eig_mode;
+
+typedef struct {
+    int dim;                 /* 2 or 3 */
+    int n[3];                /* interior points per axis (n[2] ignored when dim == 2) */
+    double L[3];             /* box side lengths */
+    double kinetic;          /* kappa: 0.5 for H = -1/2 Lap + V (Sec. 5), 1.0 for a(u,v) of Sec. 2.1 */
+    int N;                   /* number of eigenpairs, 1 <= N < Ng */
+    double sigma;            /* shift of H */
+    double pcg_tol;          /* per-column stop: ||r|| <= pcg_tol ||b|| (recursive residual) */
+    int pcg_maxit;           /* PCG iterations per solve (per refinement round in QO_MIXED) */
+    int pcg_check;           /* host polls convergence every pcg_check iterations (>= 1) */
+    int precision;           /* qo_precision */
+    double refine_inner_tol; /* QO_MIXED: relative tolerance of each FP32 inner PCG solve */
+    int warm_start;          /* 1: G U_n starts from the previous G U_hat and G U_hat from
+                                P (X + C Y); 0: both start from zero */
+} qo_config;
+
+typedef struct {
+    double energy;         /* E(U_{n+1}) = 1/2 tr <U, H U> (Sec. 2.2), unshifted */
+    double energy_shifted; /* E_sigma(U_{n+1}) = 1/2 tr <U, H_sigma U>: the dissipated quantity */
+    double orth_err_fro;   /* ||<U_hat,U_hat> - I||_F, i.e. ||O_n||_F (Sec. 4.1) */
+    double grad_norm;      /* ||G U_n - U_n <G U_n, U_n>|| (Sec. 3.1, Alg. 1 stop test) */
+    int pcg_iters[2];      /* max over columns of PCG iterations for G U_n and G U_hat
+                              (QO_MIXED: summed over refinement rounds) */
+    int refine_rounds[2];  /* QO_MIXED: refinement rounds per solve; 1 in QO_FP64 */
+    int energy_rose;       /* 1 if E_sigma increased in this step (tau too large) */
+    int step_index;        /* n + 1 after the step */
+    double t_phase_ms[8];  /* solve1, gram1, small, update, solve2, gram2, correct, energy */
+} qo_step_stats;
+
+/* Block and matrix selectors of the diagnostic getters. */
+typedef enum { QO_BLOCK_U = 0, QO_BLOCK_UHAT = 1, QO_BLOCK_P = 2, QO_BLOCK_Q = 3 } qo_block;
+typedef enum {
+    QO_MAT_S = 0, /* <U_n,U_n>                          */
+    QO_MAT_M = 1, /* <U_n, G U_n>                       */
+    QO_MAT_R = 2, /* <G U_n, G U_n>                     */
+    QO_MAT_X = 3, /* U_hat = U_n X + (G U_n) Y          */
+    QO_MAT_Y = 4,
+    QO_MAT_O = 5, /* <U_hat,U_hat> - I   (O_n, Sec. 4.1) */
+    QO_MAT_A = 6, /* <U_hat, G U_hat>    (A_n, Sec. 4.1) */
+    QO_MAT_B = 7  /* <G U_hat, G U_hat>  (B_n, Sec. 4.1) */
+} qo_matrix;
+
+/* Create a solver for the grid and options in cfg.  hip_stream is a
+ * hipStream_t (NULL: the default stream).  Allocates the device workspace
+ * (about 7 blocks of Ng x N doubles in QO_FP64, plus 3 FP32 blocks in
+ * QO_MIXED).  Sizes: 1 <= N < Ng, n_0 <= 2048.  On error *out is NULL. */
+qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out);
+
+/* Potential V: Ng values, x fastest (the V of H = -kappa Lap + V, Sec. 2.1). */
+qo_status qo_set_potential(qo_handle h, const double *V, int on_device);
+
+/* Current iterate U_n (Ng x N, column-major, leading dimension ld >= Ng).
+ * Resets the step counter and drops the warm-start vectors. */
+qo_status qo_set_state(qo_handle h, const double *U, long ld, int on_device);
+qo_status qo_get_state(qo_handle h, double *U, long ld, int on_device);
+
+/* nsteps evolution steps of the two-stage scheme of Sec. 4.1 (Alg. 1 with a
+ * fixed step tau): P = G U_n; U_hat = Cayley transform of U_n by the skew
+ * operator A V = P<U_n,V> - U_n<P,V> (solved exactly through an N x N
+ * system); Q = G U_hat; U_{n+1} = U_hat - tau Q (<U_hat,U_hat> - I).
+ * Transactional: on error U_n and the step counter are unchanged.  last (may
+ * be NULL) receives the statistics of the last step taken. */
+qo_status qo_step(qo_handle h, double tau, int nsteps, qo_step_stats *last);
+
+/* E(U_n) and E_sigma(U_n) of the current iterate (Sec. 2.2). Host outputs. */
+qo_status qo_energy(qo_handle h, double *E, double *E_shifted);
+
+/* S = <U_n,U_n> and K = <U_n, H_sigma U_n> (N x N column-major host arrays;
+ * K may be NULL). */
+qo_status qo_gram(qo_handle h, double *S, double *K);
+
+/* Eigenvalue read-out of Sec. 5.  QO_EIG_RITZ: Rayleigh-Ritz on span U_n,
+ * K c = theta S c, lambda = theta - sigma; evecs (may be NULL) receives U_n c
+ * (Ng x N, leading dimension ld, S-orthonormal).  QO_EIG_PAPER: lambda =
+ * eigenvalues of <G U_n, U_n>^{-1} minus sigma (needs one extra solve; evecs
+ * must be NULL).  evals: N host doubles, ascending. */
+qo_status qo_eigenpairs(qo_handle h, int mode, double *evals, double *evecs, long ld,
+                        int on_device);
+
+qo_status qo_destroy(qo_handle h);
+const char *qo_status_string(qo_status s);
+const char *qo_last_error(qo_handle h);
+
+/* ---- kernel-level entry points (device pointers, ncols <= N, ld >= Ng) ---- */
+
+/* Y = H_sigma X (the stencil of the operator, Sec. 2.1 discretised). */
+qo_status qo_apply(qo_handle h, const double *X, double *Y, long ld, int ncols);
+
+/* X = G B = H_sigma^{-1} B per column (Sec. 3.1), Jacobi-PCG in FP64, or in
+ * QO_MIXED FP32 PCG inside FP64 iterative refinement.  use_x0: X holds the
+ * starting guess.  iters (host, ncols ints, may be NULL): iterations per
+ * column (QO_MIXED: summed over rounds). */
+qo_status qo_solve(qo_handle h, const double *B, double *X, long ld, int ncols, int use_x0,
+                   int *iters);
+
+/* G = <Z,Z> for Z = [X | Y] (2 ncols columns): the 2ncols x 2ncols Gram matrix
+ * of Sec. 2.1, column-major host output.  BF16 tiles with FP32 accumulation
+ * in QO_MIXED, FP64 otherwise. */
+qo_status qo_gram_pair(qo_handle h, const double *X, const double *Y, long ld, int ncols,
+                       double *G);
+
+/* Diagnostics of the last step: a block (Ng x N into out with leading
+ * dimension ld) or an N x N matrix (column-major host array). */
+qo_status qo_get_block(qo_handle h, int which, double *out, long ld, int on_device);
+qo_status qo_get_matrix(qo_handle h, int which, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QO_H */

@@ -1,0 +1,319 @@
+"""ctypes binding of libqo_hip.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts arguments and
+owns nothing but the handle.  PyTorch provides device memory and the stream.
+
+Block convention: a block of ``ncols`` grid functions is a float64 CUDA tensor
+of shape ``(ncols, Ng)`` whose rows are contiguous (``stride(1) == 1``); row j
+is column j of the column-major Ng x ncols block of the C ABI and
+``stride(0)`` is its leading dimension.  ``as_block`` / ``to_numpy`` convert
+from / to NumPy ``(Ng, ncols)`` arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqo_hip.so")
+
+QO_OK, QO_ERR_ARG, QO_ERR_ALLOC, QO_ERR_DEVICE, QO_ERR_STATE = 0, 1, 2, 3, 4
+QO_ERR_NOT_SPD, QO_ERR_PCG_NOCONV, QO_ERR_NONFINITE = 5, 6, 7
+QO_FP64, QO_MIXED = 0, 1
+QO_EIG_RITZ, QO_EIG_PAPER = 0, 1
+BLOCKS = {"U": 0, "U_hat": 1, "P": 2, "Q": 3}
+MATRICES = {"S": 0, "M": 1, "R": 2, "X": 3, "Y": 4, "O": 5, "A": 6, "B": 7}
+
+EXPORTS = [
+    "qo_create", "qo_set_potential", "qo_set_state", "qo_get_state", "qo_step", "qo_energy",
+    "qo_gram", "qo_eigenpairs", "qo_destroy", "qo_status_string", "qo_last_error", "qo_apply",
+    "qo_solve", "qo_gram_pair", "qo_get_block", "qo_get_matrix",
+]
+
+
+class QoConfig(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("L", ctypes.c_double * 3),
+        ("kinetic", ctypes.c_double), ("N", ctypes.c_int), ("sigma", ctypes.c_double),
+        ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int), ("pcg_check", ctypes.c_int),
+        ("precision", ctypes.c_int), ("refine_inner_tol", ctypes.c_double),
+        ("warm_start", ctypes.c_int),
+    ]
+
+
+class QoStepStats(ctypes.Structure):
+    _fields_ = [
+        ("energy", ctypes.c_double), ("energy_shifted", ctypes.c_double),
+        ("orth_err_fro", ctypes.c_double), ("grad_norm", ctypes.c_double),
+        ("pcg_iters", ctypes.c_int * 2), ("refine_rounds", ctypes.c_int * 2),
+        ("energy_rose", ctypes.c_int), ("step_index", ctypes.c_int),
+        ("t_phase_ms", ctypes.c_double * 8),
+    ]
+
+    def as_dict(self):
+        return {
+            "energy": self.energy, "energy_shifted": self.energy_shifted,
+            "orth_err_fro": self.orth_err_fro, "grad_norm": self.grad_norm,
+            "pcg_iters": tuple(self.pcg_iters), "refine_rounds": tuple(self.refine_rounds),
+            "energy_rose": bool(self.energy_rose), "step_index": self.step_index,
+            "t_phase_ms": tuple(self.t_phase_ms),
+        }
+
+
+class QOError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_status_name(status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libqo_hip.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(the HIP library is the only compute path)")
+    lib = ctypes.CDLL(path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    H = ctypes.c_void_p
+    sig = {
+        "qo_create": ([ctypes.POINTER(QoConfig), vp, ctypes.POINTER(H)], ctypes.c_int),
+        "qo_set_potential": ([H, vp, ctypes.c_int], ctypes.c_int),
+        "qo_set_state": ([H, vp, ctypes.c_long, ctypes.c_int], ctypes.c_int),
+        "qo_get_state": ([H, vp, ctypes.c_long, ctypes.c_int], ctypes.c_int),
+        "qo_step": ([H, ctypes.c_double, ctypes.c_int, ctypes.POINTER(QoStepStats)], ctypes.c_int),
+        "qo_energy": ([H, dp, dp], ctypes.c_int),
+        "qo_gram": ([H, vp, vp], ctypes.c_int),
+        "qo_eigenpairs": ([H, ctypes.c_int, vp, vp, ctypes.c_long, ctypes.c_int], ctypes.c_int),
+        "qo_destroy": ([H], ctypes.c_int),
+        "qo_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "qo_last_error": ([H], ctypes.c_char_p),
+        "qo_apply": ([H, vp, vp, ctypes.c_long, ctypes.c_int], ctypes.c_int),
+        "qo_solve": ([H, vp, vp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ip], ctypes.c_int),
+        "qo_gram_pair": ([H, vp, vp, ctypes.c_long, ctypes.c_int, vp], ctypes.c_int),
+        "qo_get_block": ([H, ctypes.c_int, vp, ctypes.c_long, ctypes.c_int], ctypes.c_int),
+        "qo_get_matrix": ([H, ctypes.c_int, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _status_name(s):
+    names = {0: "QO_OK", 1: "QO_ERR_ARG", 2: "QO_ERR_ALLOC", 3: "QO_ERR_DEVICE",
+             4: "QO_ERR_STATE", 5: "QO_ERR_NOT_SPD", 6: "QO_ERR_PCG_NOCONV",
+             7: "QO_ERR_NONFINITE"}
+    return names.get(int(s), f"status {s}")
+
+
+def as_block(a, device="cuda"):
+    """NumPy (Ng, ncols) -> float64 CUDA tensor (ncols, Ng) in the ABI block layout."""
+    import torch
+
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a[:, None]
+    return torch.from_numpy(np.ascontiguousarray(a.T)).to(device)
+
+
+def to_numpy(t):
+    """Block tensor (ncols, Ng) -> NumPy (Ng, ncols)."""
+    return np.asfortranarray(t.detach().to("cpu").numpy().T)
+
+
+def _check_block(t, ng, ncols=None):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("blocks are float64 CUDA tensors of shape (ncols, Ng)")
+    if t.dim() != 2 or t.shape[1] != ng or t.stride(1) != 1:
+        raise ValueError(f"block must have shape (ncols, {ng}) with contiguous rows")
+    if ncols is not None and t.shape[0] != ncols:
+        raise ValueError(f"block must have {ncols} rows")
+    return t.stride(0) if t.shape[0] > 1 else ng
+
+
+class Solver:
+    """One handle of the HIP library: grid, potential, iterate and workspace."""
+
+    def __init__(self, dim, n, N, L=(1.0, 1.0, 1.0), kinetic=0.5, sigma=0.0, pcg_tol=1e-10,
+                 pcg_maxit=20000, pcg_check=8, precision="fp64", refine_inner_tol=1e-5,
+                 warm_start=True, stream=None):
+        import torch
+
+        self.lib = load_library()
+        cfg = QoConfig()
+        cfg.dim = dim
+        nn = list(n) + [1] * (3 - len(n))
+        LL = list(L) + [1.0] * (3 - len(L))
+        for k in range(3):
+            cfg.n[k] = int(nn[k])
+            cfg.L[k] = float(LL[k])
+        cfg.kinetic = kinetic
+        cfg.N = N
+        cfg.sigma = sigma
+        cfg.pcg_tol = pcg_tol
+        cfg.pcg_maxit = pcg_maxit
+        cfg.pcg_check = pcg_check
+        cfg.precision = {"fp64": QO_FP64, "mixed": QO_MIXED}[precision]
+        cfg.refine_inner_tol = refine_inner_tol
+        cfg.warm_start = 1 if warm_start else 0
+        self.cfg = cfg
+        self.dim, self.N = dim, N
+        self.ng = int(np.prod(nn[:dim]))
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = ctypes.c_void_p()
+        st = self.lib.qo_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.byref(self.h))
+        if st != QO_OK:
+            raise QOError(st, "qo_create failed")
+
+    # -- plumbing
+    def _chk(self, st):
+        if st != QO_OK:
+            msg = self.lib.qo_last_error(self.h)
+            raise QOError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if self.h:
+            self.lib.qo_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- problem data
+    def set_potential(self, V):
+        import torch
+
+        if isinstance(V, torch.Tensor):
+            V = V.detach().to(dtype=torch.float64).contiguous()
+            if V.numel() != self.ng:
+                raise ValueError("potential must have Ng values")
+            if V.is_cuda:
+                self._chk(self.lib.qo_set_potential(self.h, ctypes.c_void_p(V.data_ptr()), 1))
+                return
+            V = V.numpy()
+        V = np.ascontiguousarray(np.asarray(V, dtype=np.float64).reshape(-1))
+        if V.size != self.ng:
+            raise ValueError("potential must have Ng values")
+        self._chk(self.lib.qo_set_potential(self.h, V.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def set_state(self, U):
+        """U: block tensor (N, Ng) or NumPy (Ng, N)."""
+        if isinstance(U, np.ndarray):
+            U = as_block(U)
+        ld = _check_block(U, self.ng, self.N)
+        self._chk(self.lib.qo_set_state(self.h, ctypes.c_void_p(U.data_ptr()), ld, 1))
+
+    def get_state(self):
+        import torch
+
+        out = torch.empty((self.N, self.ng), dtype=torch.float64, device="cuda")
+        self._chk(self.lib.qo_get_state(self.h, ctypes.c_void_p(out.data_ptr()), self.ng, 1))
+        return out
+
+    # -- the method
+    def step(self, tau, nsteps=1):
+        s = QoStepStats()
+        self._chk(self.lib.qo_step(self.h, float(tau), int(nsteps), ctypes.byref(s)))
+        return s.as_dict()
+
+    def energy(self):
+        e, es = ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.qo_energy(self.h, ctypes.byref(e), ctypes.byref(es)))
+        return e.value, es.value
+
+    def gram(self):
+        S = np.zeros((self.N, self.N), order="F")
+        K = np.zeros((self.N, self.N), order="F")
+        self._chk(self.lib.qo_gram(self.h, S.ctypes.data_as(ctypes.c_void_p),
+                                   K.ctypes.data_as(ctypes.c_void_p)))
+        return S, K
+
+    def eigenpairs(self, mode="ritz", vectors=False):
+        import torch
+
+        ev = np.zeros(self.N)
+        m = {"ritz": QO_EIG_RITZ, "paper": QO_EIG_PAPER}[mode]
+        vec = None
+        vp = ctypes.c_void_p()
+        if vectors:
+            vec = torch.empty((self.N, self.ng), dtype=torch.float64, device="cuda")
+            vp = ctypes.c_void_p(vec.data_ptr())
+        self._chk(self.lib.qo_eigenpairs(self.h, m, ev.ctypes.data_as(ctypes.c_void_p), vp,
+                                         self.ng, 1))
+        return (ev, vec) if vectors else ev
+
+    # -- kernel-level calls
+    def apply(self, X, Y=None):
+        import torch
+
+        ld = _check_block(X, self.ng)
+        if Y is None:
+            Y = torch.empty_like(X)
+        if _check_block(Y, self.ng, X.shape[0]) != ld:
+            raise ValueError("X and Y need the same leading dimension")
+        self._chk(self.lib.qo_apply(self.h, ctypes.c_void_p(X.data_ptr()),
+                                    ctypes.c_void_p(Y.data_ptr()), ld, X.shape[0]))
+        return Y
+
+    def solve(self, B, X0=None):
+        import torch
+
+        ld = _check_block(B, self.ng)
+        ncols = B.shape[0]
+        if X0 is None:
+            X = torch.zeros_like(B)
+            use = 0
+        else:
+            X = X0.clone()
+            use = 1
+        if _check_block(X, self.ng, ncols) != ld:
+            raise ValueError("B and X need the same leading dimension")
+        its = (ctypes.c_int * max(ncols, 1))()
+        self._chk(self.lib.qo_solve(self.h, ctypes.c_void_p(B.data_ptr()),
+                                    ctypes.c_void_p(X.data_ptr()), ld, ncols, use, its))
+        return X, np.array(its[:ncols])
+
+    def gram_pair(self, X, Y):
+        ld = _check_block(X, self.ng)
+        ncols = X.shape[0]
+        if _check_block(Y, self.ng, ncols) != ld:
+            raise ValueError("X and Y need the same shape and leading dimension")
+        G = np.zeros((2 * ncols, 2 * ncols), order="F")
+        self._chk(self.lib.qo_gram_pair(self.h, ctypes.c_void_p(X.data_ptr()),
+                                        ctypes.c_void_p(Y.data_ptr()), ld, ncols,
+                                        G.ctypes.data_as(ctypes.c_void_p)))
+        return G
+
+    def get_block(self, name):
+        import torch
+
+        out = torch.empty((self.N, self.ng), dtype=torch.float64, device="cuda")
+        self._chk(self.lib.qo_get_block(self.h, BLOCKS[name], ctypes.c_void_p(out.data_ptr()),
+                                        self.ng, 1))
+        return out
+
+    def get_matrix(self, name):
+        M = np.zeros((self.N, self.N), order="F")
+        self._chk(self.lib.qo_get_matrix(self.h, MATRICES[name], M.ctypes.data_as(ctypes.c_void_p)))
+        return M

@@ -1,0 +1,859 @@
+// C ABI of libqo_hip (declared in include/qo.h) and the step engine: the
+// sequence of kernels of one evolution step of the two-stage scheme of
+// Sec. 4.1, the batched PCG driver for the inverse operator of Sec. 3.1, and
+// the eigenvalue read-out of Sec. 5.
+//
+// Step n (all device work on the handle's stream):
+//   solve    P = G U_n                      (Jacobi-PCG; QO_MIXED: FP32 PCG in FP64 refinement)
+//   gram1    [U P]^T [U P] h^d  -> S = <U,U>, M = <U,P>, R = <P,P>
+//   small    N x N predictor system in the basis {U, W}, W = P - U C, C = S^{-1} M:
+//              R_W = R - M^T C,  D = C S - M^T,  alpha = tau/2
+//              (I + alpha^2 R_W S - alpha D) b = D - alpha R_W S
+//              a = S (I + alpha b),  X = I + tau (b - C a),  Y = tau a
+//            (the exact solution of the implicit first stage; its matrix is
+//             close to I, unlike the 2N x 2N system in the basis {U, P})
+//   update   U_hat = U X + P Y;  warm start x0 = P (X + C Y) for the next solve
+//   solve    Q = G U_hat
+//   gram2    [U_hat Q]^T [U_hat Q] h^d -> O = <U_hat,U_hat> - I, A_n, B_n
+//   correct  U_{n+1} = U_hat - tau Q O
+//   energy   E_sigma = 1/2 h^d sum_j u_j . H_sigma u_j  (stencil pass)
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qo.h"
+#include "qo_internal.h"
+
+using namespace qo;
+
+namespace {
+
+struct Buf {
+    void *p = nullptr;
+};
+
+}  // namespace
+
+struct qo_ctx {
+    qo_config cfg{};
+    hipStream_t st = nullptr;
+    int device = 0;
+    Grid g{};
+    long ng = 0, ld = 0;
+    int N = 0;
+    double w = 1.0;
+    bool mixed = false;
+
+    // per-point arrays
+    double *vs = nullptr, *dinv = nullptr;
+    float *vs32 = nullptr, *dinv32 = nullptr;
+    // blocks (ld x N)
+    double *U = nullptr, *Uh = nullptr, *PQ[2] = {nullptr, nullptr}, *r = nullptr,
+           *pa = nullptr, *pb = nullptr, *W = nullptr, *W2 = nullptr;
+    float *r32 = nullptr, *d32 = nullptr, *rr32 = nullptr, *pa32 = nullptr, *pb32 = nullptr;
+    // reductions and small matrices
+    double *part = nullptr;
+    double *gpart = nullptr;
+    int gnsplit = 1;
+    double *G1 = nullptr, *G2 = nullptr;
+    double *mpool = nullptr;
+    double *colsums = nullptr;
+    double *dscal = nullptr;
+    double *sortwork = nullptr;
+    PcgState ps{};
+    int *mask = nullptr, *nact = nullptr, *dstatus = nullptr;
+    // pinned host
+    int *h_poll = nullptr;
+    double *h_scal = nullptr;
+
+    std::vector<void *> allocs;
+    bool have_V = false, have_U = false, have_warm = false;
+    int cur = 0;
+    const double *lastP = nullptr, *lastQ = nullptr;
+    long nstep = 0;
+    bool have_Es = false;
+    double last_Es = 0.0;
+    std::string err;
+    hipEvent_t ev[9] = {};
+    bool ev_ok = false;
+    std::vector<int> h_its;
+};
+
+namespace {
+
+qo_status fail(qo_ctx *c, qo_status s, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIPC(ctx, call)                                                                    \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ctx, QO_ERR_DEVICE, "%s failed: %s (%s:%d)", #call,                \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                        \
+    } while (0)
+
+#define QOC(call)                       \
+    do {                                \
+        qo_status s_ = (call);          \
+        if (s_ != QO_OK) return s_;     \
+    } while (0)
+
+template <typename T>
+qo_status dalloc(qo_ctx *c, T **p, size_t n) {
+    void *q = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&q, n * sizeof(T));
+    if (e != hipSuccess)
+        return fail(c, QO_ERR_ALLOC, "hipMalloc(%zu bytes) failed: %s", n * sizeof(T),
+                    hipGetErrorString(e));
+    c->allocs.push_back(q);
+    e = hipMemsetAsync(q, 0, n * sizeof(T), c->st);
+    if (e != hipSuccess) return fail(c, QO_ERR_DEVICE, "hipMemsetAsync failed");
+    *p = static_cast<T *>(q);
+    return QO_OK;
+}
+
+int pick_ppt(int pts) {
+    const int raw = (pts + kThreads - 1) / kThreads;
+    const int opts[5] = {1, 2, 4, 6, 8};
+    for (int o : opts)
+        if (o >= raw) return o;
+    return -1;
+}
+
+int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    if (!v || !*v) return dflt;
+    return atoi(v);
+}
+
+void setup_grid(qo_ctx *c) {
+    Grid &g = c->g;
+    const qo_config &cf = c->cfg;
+    g.dim = cf.dim;
+    g.nx = cf.n[0];
+    g.ny = cf.n[1];
+    g.nz = cf.dim == 3 ? cf.n[2] : 1;
+    g.ng = (long)g.nx * g.ny * g.nz;
+    double h[3];
+    for (int k = 0; k < 3; ++k) h[k] = (k < cf.dim) ? cf.L[k] / (cf.n[k] + 1) : 1.0;
+    g.ihx2 = 1.0 / (h[0] * h[0]);
+    g.ihy2 = 1.0 / (h[1] * h[1]);
+    g.ihz2 = cf.dim == 3 ? 1.0 / (h[2] * h[2]) : 0.0;
+    g.kappa = cf.kinetic;
+    g.c0 = 2.0 * cf.kinetic * (g.ihx2 + g.ihy2 + g.ihz2);
+    c->w = h[0] * h[1] * (cf.dim == 3 ? h[2] : 1.0);
+
+    int TY = 1536 / g.nx;
+    if (TY < 1) TY = 1;
+    TY = env_int("QO_TY", TY);
+    if (TY > g.ny) TY = g.ny;
+    if (TY < 1) TY = 1;
+    while (pick_ppt(TY * g.nx) < 0 && TY > 1) --TY;
+    g.TY = TY;
+    g.ppt = pick_ppt(TY * g.nx);
+    g.nbands = (g.ny + TY - 1) / TY;
+    if (cf.dim == 2) {
+        g.ZC = 1;
+        g.nzc = 1;
+    } else {
+        long want = (2048 + (long)c->N * g.nbands - 1) / ((long)c->N * g.nbands);
+        int maxc = g.nz / 16;
+        if (maxc < 1) maxc = 1;
+        if (want > maxc) want = maxc;
+        if (want < 1) want = 1;
+        int ZC = (g.nz + (int)want - 1) / (int)want;
+        ZC = env_int("QO_ZC", ZC);
+        if (ZC < 1) ZC = 1;
+        if (ZC > g.nz) ZC = g.nz;
+        g.ZC = ZC;
+        g.nzc = (g.nz + ZC - 1) / ZC;
+    }
+}
+
+// ----------------------------------------------------------------- solves
+
+qo_status check_poll_err(qo_ctx *c, int code, int col, const char *what) {
+    if (code == 5)
+        return fail(c, QO_ERR_NOT_SPD,
+                    "%s: p.H_sigma p <= 0 in column %d (H_sigma not positive definite; "
+                    "increase sigma)",
+                    what, col);
+    if (code == 7) return fail(c, QO_ERR_NONFINITE, "%s: non-finite value in column %d", what, col);
+    return fail(c, QO_ERR_DEVICE, "%s: device error code %d", what, code);
+}
+
+// Jacobi-PCG on all columns of B (ld c->ld) into X, precision T.
+template <typename T>
+qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *P0, T *P1,
+              int ncols, int use_x0, double tol, const int *mask, int *its_out,
+              const char *what) {
+    const Grid &g = c->g;
+    hipStream_t st = c->st;
+    PcgState s = c->ps;
+    HIPC(c, hipMemsetAsync(s.its, 0, sizeof(int) * ncols, st));
+    int init_err[2] = {0, INT_MAX};
+    HIPC(c, hipMemcpyAsync(s.err, init_err, sizeof init_err, hipMemcpyHostToDevice, st));
+    HIPC(c, launch_pcg_init<T>(g, vs, dinv, B, X, R, c->ld, ncols, use_x0, s.part, st));
+    T *pbuf[2] = {P0, P1};
+    const int check = c->cfg.pcg_check;
+    const int maxit = c->cfg.pcg_maxit;
+    for (int k = 0;; ++k) {
+        HIPC(c, launch_pcg_sweep1<T>(g, vs, dinv, R, pbuf[(k + 1) & 1], pbuf[k & 1], c->ld, ncols,
+                                     k, tol, mask, s, st));
+        if (k % check == 0 || k >= maxit) {
+            HIPC(c, hipMemcpyAsync(c->h_poll, s.active + (k & 1) * ncols, sizeof(int) * ncols,
+                                   hipMemcpyDeviceToHost, st));
+            HIPC(c, hipMemcpyAsync(c->h_poll + ncols, s.err, 2 * sizeof(int),
+                                   hipMemcpyDeviceToHost, st));
+            HIPC(c, hipStreamSynchronize(st));
+            if (c->h_poll[ncols]) return check_poll_err(c, c->h_poll[ncols], c->h_poll[ncols + 1], what);
+            int nact = 0;
+            for (int j = 0; j < ncols; ++j) nact += c->h_poll[j] ? 1 : 0;
+            if (nact == 0) break;
+            if (k >= maxit)
+                return fail(c, QO_ERR_PCG_NOCONV, "%s: %d of %d columns not converged after %d "
+                            "PCG iterations (tol %.3g)", what, nact, ncols, maxit, tol);
+        }
+        HIPC(c, launch_pcg_sweep2<T>(g, vs, dinv, pbuf[k & 1], X, R, c->ld, ncols, k, s, st));
+    }
+    HIPC(c, hipMemcpyAsync(c->h_poll, s.its, sizeof(int) * ncols, hipMemcpyDeviceToHost, st));
+    HIPC(c, hipStreamSynchronize(st));
+    for (int j = 0; j < ncols; ++j) its_out[j] = c->h_poll[j];
+    return QO_OK;
+}
+
+// X = G B for ncols columns of internal-layout blocks.  its: per column.
+qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_x0, int *its,
+                      int *rounds, const char *what) {
+    const double tol = c->cfg.pcg_tol;
+    if (!c->mixed) {
+        *rounds = 1;
+        return pcg<double>(c, c->vs, c->dinv, B, X, c->r, c->pa, c->pb, ncols, use_x0, tol,
+                           nullptr, its, what);
+    }
+    // FP64 iterative refinement around FP32 PCG
+    hipStream_t st = c->st;
+    const Grid &g = c->g;
+    if (!use_x0) HIPC(c, hipMemsetAsync(X, 0, sizeof(double) * c->ld * ncols, st));
+    for (int j = 0; j < ncols; ++j) its[j] = 0;
+    std::vector<int> inner(ncols);
+    const long qs = (long)ncols * g.tiles();
+    const int max_rounds = 30;
+    for (int round = 0;; ++round) {
+        int init_err[2] = {0, INT_MAX};
+        HIPC(c, hipMemcpyAsync(c->ps.err, init_err, sizeof init_err, hipMemcpyHostToDevice, st));
+        HIPC(c, launch_resid(g, c->vs, B, X, c->ld, c->r32, c->ld, ncols, nullptr, c->part, st));
+        HIPC(c, launch_colsum(c->part + qs, g.tiles(), ncols, 2, qs, c->colsums, st));
+        HIPC(c, launch_refine_mask(c->colsums, ncols, tol, c->mask, c->nact, c->ps.err, st));
+        HIPC(c, hipMemcpyAsync(c->h_poll, c->nact, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPC(c, hipMemcpyAsync(c->h_poll + 1, c->ps.err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPC(c, hipStreamSynchronize(st));
+        if (c->h_poll[1]) return check_poll_err(c, c->h_poll[1], c->h_poll[2], what);
+        if (c->h_poll[0] == 0) {
+            *rounds = round;
+            break;
+        }
+        if (round >= max_rounds)
+            return fail(c, QO_ERR_PCG_NOCONV, "%s: refinement did not reach tol %.3g in %d rounds",
+                        what, tol, max_rounds);
+        QOC(pcg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->rr32, c->pa32, c->pb32, ncols, 0,
+                       c->cfg.refine_inner_tol, c->mask, inner.data(), what));
+        for (int j = 0; j < ncols; ++j) its[j] += inner[j];
+        HIPC(c, launch_refine_axpy(X, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, st));
+    }
+    return QO_OK;
+}
+
+qo_status gram(qo_ctx *c, const double *X, const double *Y, long ld, int n, double *G) {
+    if (c->mixed)
+        HIPC(c, launch_gram_bf16(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G, c->st));
+    else
+        HIPC(c, launch_gram_f64(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G, c->st));
+    return QO_OK;
+}
+
+// Gram in FP64 regardless of precision (outputs and diagnostics)
+qo_status gram64(qo_ctx *c, const double *X, const double *Y, long ld, int n, double *G) {
+    HIPC(c, launch_gram_f64(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G, c->st));
+    return QO_OK;
+}
+
+// named N x N matrices in the pool
+enum {
+    MP_SW, MP_C, MP_RW, MP_D, MP_RWS, MP_MAT, MP_RHS, MP_A, MP_X, MP_Y, MP_Z, MP_XR, MP_YR,
+    MP_ZR, MP_O, MP_OR, MP_MS, MP_T1, MP_T2, MP_T3, MP_COUNT
+};
+
+double *mp(qo_ctx *c, int i) { return c->mpool + (size_t)i * c->N * c->N; }
+
+qo_status energy_of(qo_ctx *c, const double *U, double *Es, double *trS) {
+    const Grid &g = c->g;
+    const int N = c->N;
+    const long qs = (long)N * g.tiles();
+    HIPC(c, launch_quad(g, c->vs, U, c->ld, N, c->part, c->st));
+    HIPC(c, launch_colsum(c->part, g.tiles(), N, 2, qs, c->colsums, c->st));
+    HIPC(c, nn_energy_finish(c->colsums, N, c->w, c->dscal + 4, c->st));
+    HIPC(c, hipMemcpyAsync(c->h_scal + 4, c->dscal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           c->st));
+    HIPC(c, hipStreamSynchronize(c->st));
+    *Es = c->h_scal[4];
+    *trS = c->h_scal[5];
+    return QO_OK;
+}
+
+qo_status check_status(qo_ctx *c, const char *what) {
+    int hs = 0;
+    HIPC(c, hipMemcpyAsync(&hs, c->dstatus, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPC(c, hipStreamSynchronize(c->st));
+    if (hs == 5) return fail(c, QO_ERR_NOT_SPD, "%s: matrix not positive definite / singular", what);
+    if (hs == 7) return fail(c, QO_ERR_NONFINITE, "%s: non-finite matrix entries", what);
+    if (hs) return fail(c, QO_ERR_DEVICE, "%s: status %d", what, hs);
+    return QO_OK;
+}
+
+void rec(qo_ctx *c, int i) {
+    if (c->ev_ok) (void)hipEventRecord(c->ev[i], c->st);
+}
+
+qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats) {
+    const int N = c->N;
+    const int N2 = 2 * N;
+    hipStream_t st = c->st;
+    const long ld = c->ld;
+    double *P = c->PQ[c->cur];
+    double *Q = c->PQ[c->cur ^ 1];
+    const int warm = c->cfg.warm_start ? 1 : 0;
+    std::vector<int> itsP(N), itsQ(N);
+    int rP = 0, rQ = 0;
+
+    rec(c, 0);
+    QOC(solve_block(c, c->U, P, N, warm && c->have_warm, itsP.data(), &rP, "solve G U_n"));
+    rec(c, 1);
+    QOC(gram(c, c->U, P, ld, N, c->G1));
+    rec(c, 2);
+    double *S = c->G1;
+    double *M = c->G1 + (size_t)N * N2;
+    double *R = c->G1 + (size_t)N * N2 + N;
+    const double alpha = 0.5 * tau;
+    HIPC(c, hipMemsetAsync(c->dstatus, 0, sizeof(int), st));
+    HIPC(c, nn_grad2(S, M, R, N2, N, mp(c, MP_MS), N, c->dscal + 0, st));
+    // C = S^{-1} M
+    HIPC(c, nn_axpby(mp(c, MP_SW), N, 1.0, S, N2, 0.0, nullptr, N, false, 0.0, N, N, st));
+    HIPC(c, nn_axpby(mp(c, MP_C), N, 1.0, M, N2, 0.0, nullptr, N, false, 0.0, N, N, st));
+    HIPC(c, nn_gj_solve(mp(c, MP_SW), N, mp(c, MP_C), N, N, N, true, c->dstatus, st));
+    // R_W = sym(R - M^T C)
+    HIPC(c, nn_axpby(mp(c, MP_T1), N, 1.0, R, N2, 0.0, nullptr, N, false, 0.0, N, N, st));
+    HIPC(c, nn_gemm(mp(c, MP_T1), N, M, N2, true, mp(c, MP_C), N, false, N, N, N, -1.0, 1.0, 0.0, st));
+    HIPC(c, nn_axpby(mp(c, MP_RW), N, 0.5, mp(c, MP_T1), N, 0.5, mp(c, MP_T1), N, true, 0.0, N, N, st));
+    // D = C S - M^T
+    HIPC(c, nn_gemm(mp(c, MP_D), N, mp(c, MP_C), N, false, S, N2, false, N, N, N, 1.0, 0.0, 0.0, st));
+    HIPC(c, nn_axpby(mp(c, MP_D), N, 1.0, mp(c, MP_D), N, -1.0, M, N2, true, 0.0, N, N, st));
+    // RWS = R_W S
+    HIPC(c, nn_gemm(mp(c, MP_RWS), N, mp(c, MP_RW), N, false, S, N2, false, N, N, N, 1.0, 0.0, 0.0, st));
+    // (I + alpha^2 RWS - alpha D) b = D - alpha RWS
+    HIPC(c, nn_axpby(mp(c, MP_MAT), N, alpha * alpha, mp(c, MP_RWS), N, -alpha, mp(c, MP_D), N, false, 1.0, N, N, st));
+    HIPC(c, nn_axpby(mp(c, MP_RHS), N, 1.0, mp(c, MP_D), N, -alpha, mp(c, MP_RWS), N, false, 0.0, N, N, st));
+    HIPC(c, nn_gj_solve(mp(c, MP_MAT), N, mp(c, MP_RHS), N, N, N, false, c->dstatus, st));
+    double *bm = mp(c, MP_RHS);
+    // a = S + alpha S b
+    HIPC(c, nn_axpby(mp(c, MP_A), N, 1.0, S, N2, 0.0, nullptr, N, false, 0.0, N, N, st));
+    HIPC(c, nn_gemm(mp(c, MP_A), N, S, N2, false, bm, N, false, N, N, N, alpha, 1.0, 0.0, st));
+    // X = I + tau b - tau C a ; Y = tau a ; Z = X + C Y
+    HIPC(c, nn_axpby(mp(c, MP_X), N, tau, bm, N, 0.0, nullptr, N, false, 1.0, N, N, st));
+    HIPC(c, nn_gemm(mp(c, MP_X), N, mp(c, MP_C), N, false, mp(c, MP_A), N, false, N, N, N, -tau, 1.0, 0.0, st));
+    HIPC(c, nn_axpby(mp(c, MP_Y), N, tau, mp(c, MP_A), N, 0.0, nullptr, N, false, 0.0, N, N, st));
+    HIPC(c, nn_axpby(mp(c, MP_Z), N, 1.0, mp(c, MP_X), N, 0.0, nullptr, N, false, 0.0, N, N, st));
+    HIPC(c, nn_gemm(mp(c, MP_Z), N, mp(c, MP_C), N, false, mp(c, MP_Y), N, false, N, N, N, 1.0, 1.0, 0.0, st));
+    // row-major copies for the block update
+    HIPC(c, nn_axpby(mp(c, MP_XR), N, 0.0, nullptr, N, 1.0, mp(c, MP_X), N, true, 0.0, N, N, st));
+    HIPC(c, nn_axpby(mp(c, MP_YR), N, 0.0, nullptr, N, 1.0, mp(c, MP_Y), N, true, 0.0, N, N, st));
+    HIPC(c, nn_axpby(mp(c, MP_ZR), N, 0.0, nullptr, N, 1.0, mp(c, MP_Z), N, true, 0.0, N, N, st));
+    QOC(check_status(c, "predictor N x N solve"));
+    rec(c, 3);
+    HIPC(c, launch_tsgemm(c->Uh, ld, nullptr, c->U, mp(c, MP_XR), P, mp(c, MP_YR), ld, c->ng, N, st));
+    if (warm)
+        HIPC(c, launch_tsgemm(Q, ld, nullptr, P, mp(c, MP_ZR), nullptr, nullptr, ld, c->ng, N, st));
+    rec(c, 4);
+    QOC(solve_block(c, c->Uh, Q, N, warm, itsQ.data(), &rQ, "solve G U_hat"));
+    rec(c, 5);
+    QOC(gram(c, c->Uh, Q, ld, N, c->G2));
+    rec(c, 6);
+    // O = sym(<U_hat,U_hat>) - I ; corrector coefficient -tau O (symmetric => its own transpose)
+    HIPC(c, nn_axpby(mp(c, MP_O), N, 0.5, c->G2, N2, 0.5, c->G2, N2, true, -1.0, N, N, st));
+    HIPC(c, nn_axpby(mp(c, MP_OR), N, -tau, mp(c, MP_O), N, 0.0, nullptr, N, false, 0.0, N, N, st));
+    HIPC(c, nn_fro(mp(c, MP_O), N, N, c->dscal + 1, st));
+    HIPC(c, launch_tsgemm(c->U, ld, c->Uh, nullptr, nullptr, Q, mp(c, MP_OR), ld, c->ng, N, st));
+    rec(c, 7);
+    // the state has moved: commit bookkeeping before the (non-failing) diagnostics
+    c->lastP = P;
+    c->lastQ = Q;
+    c->cur ^= 1;
+    c->have_warm = warm != 0;
+    c->nstep += 1;
+    double Es = 0.0, trS = 0.0;
+    QOC(energy_of(c, c->U, &Es, &trS));
+    rec(c, 8);
+    HIPC(c, hipMemcpyAsync(c->h_scal, c->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(c, hipStreamSynchronize(st));
+    if (stats) {
+        memset(stats, 0, sizeof *stats);
+        stats->energy_shifted = Es;
+        stats->energy = Es - 0.5 * c->cfg.sigma * trS;
+        stats->orth_err_fro = c->h_scal[1];
+        const double g2 = c->h_scal[0];
+        stats->grad_norm = g2 > 0.0 ? sqrt(g2) : 0.0;
+        int mp_ = 0, mq = 0;
+        for (int j = 0; j < N; ++j) {
+            mp_ = itsP[j] > mp_ ? itsP[j] : mp_;
+            mq = itsQ[j] > mq ? itsQ[j] : mq;
+        }
+        stats->pcg_iters[0] = mp_;
+        stats->pcg_iters[1] = mq;
+        stats->refine_rounds[0] = rP;
+        stats->refine_rounds[1] = rQ;
+        stats->energy_rose = (c->have_Es && Es > c->last_Es) ? 1 : 0;
+        stats->step_index = (int)c->nstep;
+        if (c->ev_ok)
+            for (int i = 0; i < 8; ++i) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess)
+                    stats->t_phase_ms[i] = ms;
+            }
+    }
+    c->have_Es = true;
+    c->last_Es = Es;
+    return QO_OK;
+}
+
+qo_status copy_block_in(qo_ctx *c, double *dst, const double *src, long ld, int on_device) {
+    HIPC(c, hipMemcpy2DAsync(dst, c->ld * sizeof(double), src, ld * sizeof(double),
+                             c->ng * sizeof(double), c->N,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->st));
+    HIPC(c, hipStreamSynchronize(c->st));
+    return QO_OK;
+}
+
+qo_status copy_block_out(qo_ctx *c, double *dst, long ld, const double *src, int on_device,
+                         int ncols) {
+    HIPC(c, hipMemcpy2DAsync(dst, ld * sizeof(double), src, c->ld * sizeof(double),
+                             c->ng * sizeof(double), ncols,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->st));
+    HIPC(c, hipStreamSynchronize(c->st));
+    return QO_OK;
+}
+
+__global__ void k_prep_potential(const double *__restrict__ V, long ng, double sigma, double c0,
+                                 double *__restrict__ vs, double *__restrict__ dinv,
+                                 float *__restrict__ vs32, float *__restrict__ dinv32,
+                                 int *__restrict__ bad) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ng;
+         i += (long)gridDim.x * blockDim.x) {
+        const double v = V[i];
+        if (!isfinite(v)) atomicMax(bad, 7);
+        const double s = v + sigma;
+        const double d = 1.0 / (c0 + s);
+        vs[i] = s;
+        dinv[i] = d;
+        if (vs32) {
+            vs32[i] = (float)s;
+            dinv32[i] = (float)(1.0 / ((double)(float)c0 + (double)(float)s));
+        }
+        if (!(c0 + s > 0.0)) atomicMax(bad, 5);
+    }
+}
+
+__global__ void k_scan_finite(const double *__restrict__ X, long ld, long ng, int ncols,
+                              int *__restrict__ bad) {
+    const int c = blockIdx.y;
+    const double *x = X + (long)c * ld;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ng;
+         i += (long)gridDim.x * blockDim.x)
+        if (!isfinite(x[i])) atomicMax(bad, 7);
+}
+
+}  // namespace
+
+// =================================================================== ABI
+
+extern "C" {
+
+const char *qo_status_string(qo_status s) {
+    switch (s) {
+        case QO_OK: return "QO_OK";
+        case QO_ERR_ARG: return "QO_ERR_ARG";
+        case QO_ERR_ALLOC: return "QO_ERR_ALLOC";
+        case QO_ERR_DEVICE: return "QO_ERR_DEVICE";
+        case QO_ERR_STATE: return "QO_ERR_STATE";
+        case QO_ERR_NOT_SPD: return "QO_ERR_NOT_SPD";
+        case QO_ERR_PCG_NOCONV: return "QO_ERR_PCG_NOCONV";
+        case QO_ERR_NONFINITE: return "QO_ERR_NONFINITE";
+    }
+    return "QO_ERR_UNKNOWN";
+}
+
+const char *qo_last_error(qo_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+qo_status qo_destroy(qo_handle h) {
+    if (!h) return QO_ERR_ARG;
+    if (h->st) (void)hipStreamSynchronize(h->st);
+    else (void)hipDeviceSynchronize();
+    for (void *p : h->allocs) (void)hipFree(p);
+    if (h->h_poll) (void)hipHostFree(h->h_poll);
+    if (h->h_scal) (void)hipHostFree(h->h_scal);
+    if (h->ev_ok)
+        for (auto &e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+    return QO_OK;
+}
+
+qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
+    if (!out) return QO_ERR_ARG;
+    *out = nullptr;
+    if (!cfg) return QO_ERR_ARG;
+    const qo_config &c = *cfg;
+    if (c.dim != 2 && c.dim != 3) return QO_ERR_ARG;
+    long ng = 1;
+    for (int k = 0; k < c.dim; ++k) {
+        if (c.n[k] < 1 || !(c.L[k] > 0.0)) return QO_ERR_ARG;
+        ng *= c.n[k];
+    }
+    if (c.n[0] > 2048) return QO_ERR_ARG;
+    if (c.N < 1 || c.N >= ng || c.N > 4096) return QO_ERR_ARG;
+    if (!(c.kinetic > 0.0) || !std::isfinite(c.sigma)) return QO_ERR_ARG;
+    if (!(c.pcg_tol > 0.0) || c.pcg_maxit < 1 || c.pcg_check < 1) return QO_ERR_ARG;
+    if (c.precision != QO_FP64 && c.precision != QO_MIXED) return QO_ERR_ARG;
+    if (c.precision == QO_MIXED && !(c.refine_inner_tol > 0.0 && c.refine_inner_tol < 1.0))
+        return QO_ERR_ARG;
+
+    qo_ctx *h = new (std::nothrow) qo_ctx();
+    if (!h) return QO_ERR_ALLOC;
+    h->cfg = c;
+    h->st = static_cast<hipStream_t>(hip_stream);
+    h->N = c.N;
+    h->mixed = c.precision == QO_MIXED;
+    setup_grid(h);
+    h->ng = h->g.ng;
+    h->ld = (h->ng + 63) / 64 * 64;
+    const int N = h->N;
+    const size_t blk = (size_t)h->ld * N;
+    qo_status s = QO_OK;
+    auto A = [&](auto **p, size_t n) {
+        if (s == QO_OK) s = dalloc(h, p, n);
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) s = QO_ERR_DEVICE;
+    A(&h->vs, h->ng);
+    A(&h->dinv, h->ng);
+    A(&h->U, blk);
+    A(&h->Uh, blk);
+    A(&h->PQ[0], blk);
+    A(&h->PQ[1], blk);
+    A(&h->r, blk);
+    A(&h->pa, blk);
+    A(&h->pb, blk);
+    A(&h->W, blk);
+    A(&h->W2, blk);
+    if (h->mixed) {
+        A(&h->vs32, h->ng);
+        A(&h->dinv32, h->ng);
+        A(&h->r32, blk);
+        A(&h->d32, blk);
+        A(&h->rr32, blk);
+        A(&h->pa32, blk);
+        A(&h->pb32, blk);
+    }
+    const int tiles = h->g.tiles();
+    A(&h->part, (size_t)4 * N * tiles);
+    h->gnsplit = gram_nsplit(h->ng, N);
+    A(&h->gpart, gram_part_elems(N, h->gnsplit));
+    A(&h->G1, (size_t)4 * N * N);
+    A(&h->G2, (size_t)4 * N * N);
+    A(&h->mpool, (size_t)MP_COUNT * N * N);
+    A(&h->colsums, (size_t)4 * N);
+    A(&h->dscal, 16);
+    A(&h->sortwork, (size_t)N + (size_t)N * N);
+    A(&h->ps.rho, (size_t)2 * N);
+    A(&h->ps.active, (size_t)2 * N);
+    A(&h->ps.its, (size_t)N);
+    A(&h->ps.bb, (size_t)N);
+    A(&h->ps.err, 2);
+    A(&h->mask, (size_t)N);
+    A(&h->nact, 1);
+    A(&h->dstatus, 1);
+    h->ps.part = h->part;
+    if (s == QO_OK) {
+        if (hipHostMalloc((void **)&h->h_poll, sizeof(int) * (N + 8)) != hipSuccess ||
+            hipHostMalloc((void **)&h->h_scal, sizeof(double) * 16) != hipSuccess)
+            s = QO_ERR_ALLOC;
+    }
+    if (s == QO_OK) {
+        h->ev_ok = true;
+        for (auto &e : h->ev)
+            if (hipEventCreate(&e) != hipSuccess) h->ev_ok = false;
+        if (hipStreamSynchronize(h->st) != hipSuccess) s = QO_ERR_DEVICE;
+    }
+    if (s != QO_OK) {
+        qo_destroy(h);
+        return s;
+    }
+    *out = h;
+    return QO_OK;
+}
+
+qo_status qo_set_potential(qo_handle h, const double *V, int on_device) {
+    if (!h || !V) return h ? fail(h, QO_ERR_ARG, "null potential") : QO_ERR_ARG;
+    const double *src = V;
+    if (!on_device) {
+        HIPC(h, hipMemcpyAsync(h->W, V, sizeof(double) * h->ng, hipMemcpyHostToDevice, h->st));
+        src = h->W;
+    }
+    HIPC(h, hipMemsetAsync(h->dstatus, 0, sizeof(int), h->st));
+    long blocks = (h->ng + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_prep_potential, dim3((unsigned)blocks), dim3(256), 0, h->st, src, h->ng,
+                       h->cfg.sigma, h->g.c0, h->vs, h->dinv, h->vs32, h->dinv32, h->dstatus);
+    HIPC(h, hipGetLastError());
+    int bad = 0;
+    HIPC(h, hipMemcpyAsync(&bad, h->dstatus, sizeof(int), hipMemcpyDeviceToHost, h->st));
+    HIPC(h, hipStreamSynchronize(h->st));
+    if (bad == 7) {
+        h->have_V = false;
+        return fail(h, QO_ERR_NONFINITE, "potential has non-finite values");
+    }
+    if (bad == 5) {
+        h->have_V = false;
+        return fail(h, QO_ERR_NOT_SPD, "diagonal of H_sigma not positive: increase sigma");
+    }
+    h->have_V = true;
+    h->have_warm = false;
+    return QO_OK;
+}
+
+qo_status qo_set_state(qo_handle h, const double *U, long ld, int on_device) {
+    if (!h) return QO_ERR_ARG;
+    if (!U || ld < h->ng) return fail(h, QO_ERR_ARG, "bad state pointer or ld");
+    QOC(copy_block_in(h, h->U, U, ld, on_device));
+    HIPC(h, hipMemsetAsync(h->dstatus, 0, sizeof(int), h->st));
+    long blocks = (h->ng + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_scan_finite, dim3((unsigned)blocks, h->N), dim3(256), 0, h->st, h->U,
+                       h->ld, h->ng, h->N, h->dstatus);
+    HIPC(h, hipGetLastError());
+    int bad = 0;
+    HIPC(h, hipMemcpyAsync(&bad, h->dstatus, sizeof(int), hipMemcpyDeviceToHost, h->st));
+    HIPC(h, hipStreamSynchronize(h->st));
+    if (bad) {
+        h->have_U = false;
+        return fail(h, QO_ERR_NONFINITE, "state has non-finite values");
+    }
+    h->have_U = true;
+    h->have_warm = false;
+    h->have_Es = false;
+    h->nstep = 0;
+    return QO_OK;
+}
+
+qo_status qo_get_state(qo_handle h, double *U, long ld, int on_device) {
+    if (!h) return QO_ERR_ARG;
+    if (!U || ld < h->ng) return fail(h, QO_ERR_ARG, "bad output pointer or ld");
+    if (!h->have_U) return fail(h, QO_ERR_STATE, "no state set");
+    return copy_block_out(h, U, ld, h->U, on_device, h->N);
+}
+
+qo_status qo_step(qo_handle h, double tau, int nsteps, qo_step_stats *last) {
+    if (!h) return QO_ERR_ARG;
+    if (!(tau > 0.0) || !std::isfinite(tau) || nsteps < 0)
+        return fail(h, QO_ERR_ARG, "tau must be positive and finite, nsteps >= 0");
+    if (!h->have_V || !h->have_U) return fail(h, QO_ERR_STATE, "set potential and state first");
+    for (int i = 0; i < nsteps; ++i) QOC(one_step(h, tau, last));
+    return QO_OK;
+}
+
+qo_status qo_energy(qo_handle h, double *E, double *E_shifted) {
+    if (!h) return QO_ERR_ARG;
+    if (!h->have_V || !h->have_U) return fail(h, QO_ERR_STATE, "set potential and state first");
+    double Es = 0.0, trS = 0.0;
+    QOC(energy_of(h, h->U, &Es, &trS));
+    if (E) *E = Es - 0.5 * h->cfg.sigma * trS;
+    if (E_shifted) *E_shifted = Es;
+    return QO_OK;
+}
+
+qo_status qo_gram(qo_handle h, double *S, double *K) {
+    if (!h || !S) return h ? fail(h, QO_ERR_ARG, "null output") : QO_ERR_ARG;
+    if (!h->have_V || !h->have_U) return fail(h, QO_ERR_STATE, "set potential and state first");
+    const int N = h->N;
+    HIPC(h, launch_apply(h->g, h->vs, h->U, h->W, h->ld, N, h->st));
+    QOC(gram64(h, h->U, h->W, h->ld, N, h->G2));
+    HIPC(h, hipMemcpy2DAsync(S, N * sizeof(double), h->G2, 2 * N * sizeof(double),
+                             N * sizeof(double), N, hipMemcpyDeviceToHost, h->st));
+    if (K)
+        HIPC(h, hipMemcpy2DAsync(K, N * sizeof(double), h->G2 + (size_t)N * 2 * N,
+                                 2 * N * sizeof(double), N * sizeof(double), N,
+                                 hipMemcpyDeviceToHost, h->st));
+    HIPC(h, hipStreamSynchronize(h->st));
+    return QO_OK;
+}
+
+qo_status qo_eigenpairs(qo_handle h, int mode, double *evals, double *evecs, long ld,
+                        int on_device) {
+    if (!h || !evals) return h ? fail(h, QO_ERR_ARG, "null output") : QO_ERR_ARG;
+    if (mode != QO_EIG_RITZ && mode != QO_EIG_PAPER) return fail(h, QO_ERR_ARG, "bad mode");
+    if (mode == QO_EIG_PAPER && evecs) return fail(h, QO_ERR_ARG, "paper mode gives no vectors");
+    if (evecs && ld < h->ng) return fail(h, QO_ERR_ARG, "bad ld");
+    if (!h->have_V || !h->have_U) return fail(h, QO_ERR_STATE, "set potential and state first");
+    const int N = h->N, N2 = 2 * N;
+    hipStream_t st = h->st;
+    double *ev = h->dscal + 8;  // too small for N; use pool
+    ev = mp(h, MP_T3);
+    HIPC(h, hipMemsetAsync(h->dstatus, 0, sizeof(int), st));
+    if (mode == QO_EIG_RITZ) {
+        HIPC(h, launch_apply(h->g, h->vs, h->U, h->W, h->ld, N, st));
+        QOC(gram64(h, h->U, h->W, h->ld, N, h->G2));
+        double *S = h->G2, *K = h->G2 + (size_t)N * N2;
+        // S = V diag(l) V^T ; F = V diag(l)^{-1/2}
+        HIPC(h, nn_axpby(mp(h, MP_T1), N, 0.5, S, N2, 0.5, S, N2, true, 0.0, N, N, st));
+        HIPC(h, nn_jacobi(mp(h, MP_T1), N, N, ev, mp(h, MP_T2), N, nullptr, st));
+        HIPC(h, nn_scale_cols_rsqrt(mp(h, MP_SW), mp(h, MP_T2), N, ev, N, h->dstatus, st));
+        // K' = F^T sym(K) F
+        HIPC(h, nn_axpby(mp(h, MP_T1), N, 0.5, K, N2, 0.5, K, N2, true, 0.0, N, N, st));
+        HIPC(h, nn_gemm(mp(h, MP_T2), N, mp(h, MP_T1), N, false, mp(h, MP_SW), N, false, N, N, N, 1.0, 0.0, 0.0, st));
+        HIPC(h, nn_gemm(mp(h, MP_T1), N, mp(h, MP_SW), N, true, mp(h, MP_T2), N, false, N, N, N, 1.0, 0.0, 0.0, st));
+        HIPC(h, nn_axpby(mp(h, MP_T2), N, 0.5, mp(h, MP_T1), N, 0.5, mp(h, MP_T1), N, true, 0.0, N, N, st));
+        HIPC(h, nn_jacobi(mp(h, MP_T2), N, N, ev, mp(h, MP_Z), N, nullptr, st));
+        HIPC(h, nn_sort(ev, mp(h, MP_Z), N, N, false, h->sortwork, st));
+        HIPC(h, nn_eval_map(ev, ev, N, false, h->cfg.sigma, st));
+        QOC(check_status(h, "Rayleigh-Ritz: <U,U> not positive definite"));
+        if (evecs) {
+            // c = F Z ; vectors = U c
+            HIPC(h, nn_gemm(mp(h, MP_C), N, mp(h, MP_SW), N, false, mp(h, MP_Z), N, false, N, N, N, 1.0, 0.0, 0.0, st));
+            HIPC(h, nn_axpby(mp(h, MP_ZR), N, 0.0, nullptr, N, 1.0, mp(h, MP_C), N, true, 0.0, N, N, st));
+            if (on_device) {
+                HIPC(h, launch_tsgemm(evecs, ld, nullptr, h->U, mp(h, MP_ZR), nullptr, nullptr, h->ld, h->ng, N, st));
+            } else {
+                HIPC(h, launch_tsgemm(h->W, h->ld, nullptr, h->U, mp(h, MP_ZR), nullptr, nullptr, h->ld, h->ng, N, st));
+                QOC(copy_block_out(h, evecs, ld, h->W, 0, N));
+            }
+        }
+    } else {
+        // P = G U (side-effect free: scratch start from the warm-start block)
+        std::vector<int> its(N);
+        int rounds = 0;
+        HIPC(h, hipMemcpyAsync(h->W2, h->PQ[h->cur], sizeof(double) * h->ld * N,
+                               hipMemcpyDeviceToDevice, st));
+        QOC(solve_block(h, h->U, h->W2, N, h->have_warm ? 1 : 0, its.data(), &rounds,
+                        "solve G U (paper eigenvalues)"));
+        QOC(gram64(h, h->U, h->W2, h->ld, N, h->G2));
+        double *M = h->G2 + (size_t)N * N2;
+        HIPC(h, nn_axpby(mp(h, MP_T1), N, 0.5, M, N2, 0.5, M, N2, true, 0.0, N, N, st));
+        HIPC(h, nn_jacobi(mp(h, MP_T1), N, N, ev, mp(h, MP_T2), N, nullptr, st));
+        HIPC(h, nn_eval_map(ev, ev, N, true, h->cfg.sigma, st));
+        HIPC(h, nn_sort(ev, nullptr, N, N, false, h->sortwork, st));
+    }
+    HIPC(h, hipMemcpyAsync(evals, ev, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HIPC(h, hipStreamSynchronize(st));
+    return QO_OK;
+}
+
+qo_status qo_apply(qo_handle h, const double *X, double *Y, long ld, int ncols) {
+    if (!h) return QO_ERR_ARG;
+    if (!X || !Y || ld < h->ng || ncols < 0 || ncols > h->N)
+        return fail(h, QO_ERR_ARG, "bad arguments to qo_apply");
+    if (!h->have_V) return fail(h, QO_ERR_STATE, "set the potential first");
+    HIPC(h, launch_apply(h->g, h->vs, X, Y, ld, ncols, h->st));
+    HIPC(h, hipStreamSynchronize(h->st));
+    return QO_OK;
+}
+
+qo_status qo_solve(qo_handle h, const double *B, double *X, long ld, int ncols, int use_x0,
+                   int *iters) {
+    if (!h) return QO_ERR_ARG;
+    if (!B || !X || ld < h->ng || ncols < 0 || ncols > h->N)
+        return fail(h, QO_ERR_ARG, "bad arguments to qo_solve");
+    if (!h->have_V) return fail(h, QO_ERR_STATE, "set the potential first");
+    if (ncols == 0) return QO_OK;
+    hipStream_t st = h->st;
+    const size_t row = h->ng * sizeof(double), lds = ld * sizeof(double),
+                 ldi = h->ld * sizeof(double);
+    HIPC(h, hipMemcpy2DAsync(h->W, ldi, B, lds, row, ncols, hipMemcpyDeviceToDevice, st));
+    if (use_x0) HIPC(h, hipMemcpy2DAsync(h->W2, ldi, X, lds, row, ncols, hipMemcpyDeviceToDevice, st));
+    std::vector<int> its(ncols);
+    int rounds = 0;
+    QOC(solve_block(h, h->W, h->W2, ncols, use_x0 ? 1 : 0, its.data(), &rounds, "qo_solve"));
+    HIPC(h, hipMemcpy2DAsync(X, lds, h->W2, ldi, row, ncols, hipMemcpyDeviceToDevice, st));
+    HIPC(h, hipStreamSynchronize(st));
+    if (iters)
+        for (int j = 0; j < ncols; ++j) iters[j] = its[j];
+    return QO_OK;
+}
+
+qo_status qo_gram_pair(qo_handle h, const double *X, const double *Y, long ld, int ncols,
+                       double *G) {
+    if (!h) return QO_ERR_ARG;
+    if (!X || !Y || !G || ld < h->ng || ncols < 1 || ncols > h->N)
+        return fail(h, QO_ERR_ARG, "bad arguments to qo_gram_pair");
+    QOC(gram(h, X, Y, ld, ncols, h->G2));
+    HIPC(h, hipMemcpyAsync(G, h->G2, sizeof(double) * 4 * ncols * ncols, hipMemcpyDeviceToHost,
+                           h->st));
+    HIPC(h, hipStreamSynchronize(h->st));
+    return QO_OK;
+}
+
+qo_status qo_get_block(qo_handle h, int which, double *out, long ld, int on_device) {
+    if (!h) return QO_ERR_ARG;
+    if (!out || ld < h->ng) return fail(h, QO_ERR_ARG, "bad output");
+    const double *src = nullptr;
+    switch (which) {
+        case QO_BLOCK_U: src = h->have_U ? h->U : nullptr; break;
+        case QO_BLOCK_UHAT: src = h->nstep > 0 ? h->Uh : nullptr; break;
+        case QO_BLOCK_P: src = h->lastP; break;
+        case QO_BLOCK_Q: src = h->lastQ; break;
+        default: return fail(h, QO_ERR_ARG, "bad block selector");
+    }
+    if (!src) return fail(h, QO_ERR_STATE, "block not available yet");
+    return copy_block_out(h, out, ld, src, on_device, h->N);
+}
+
+qo_status qo_get_matrix(qo_handle h, int which, double *out) {
+    if (!h) return QO_ERR_ARG;
+    if (!out) return fail(h, QO_ERR_ARG, "null output");
+    if (h->nstep == 0) return fail(h, QO_ERR_STATE, "no step taken yet");
+    const int N = h->N;
+    const size_t N2 = 2 * (size_t)N;
+    const double *src = nullptr;
+    size_t lds = N;
+    switch (which) {
+        case QO_MAT_S: src = h->G1; lds = N2; break;
+        case QO_MAT_M: src = h->G1 + N * N2; lds = N2; break;
+        case QO_MAT_R: src = h->G1 + N * N2 + N; lds = N2; break;
+        case QO_MAT_X: src = mp(h, MP_X); break;
+        case QO_MAT_Y: src = mp(h, MP_Y); break;
+        case QO_MAT_O: src = mp(h, MP_O); break;
+        case QO_MAT_A: src = h->G2 + N * N2; lds = N2; break;
+        case QO_MAT_B: src = h->G2 + N * N2 + N; lds = N2; break;
+        default: return fail(h, QO_ERR_ARG, "bad matrix selector");
+    }
+    HIPC(h, hipMemcpy2DAsync(out, N * sizeof(double), src, lds * sizeof(double),
+                             N * sizeof(double), N, hipMemcpyDeviceToHost, h->st));
+    HIPC(h, hipStreamSynchronize(h->st));
+    return QO_OK;
+}
+
+}  // extern "C"

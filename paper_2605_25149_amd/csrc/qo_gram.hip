@@ -1,0 +1,298 @@
+// Tall-skinny Gram matrices <Z,Z> = w Z^T Z of Z = [X | Y] (Ng x 2n): the
+// inner-product matrices of Sec. 2.1 that the scheme of Sec. 4.1 needs
+// (<U,U>, <U,GU>, <GU,GU> and <U_hat,U_hat>, <U_hat,GU_hat>, <GU_hat,GU_hat>).
+//
+// Split-K over the grid: one wavefront computes one 64x64 tile of the upper
+// block triangle over one chunk of rows with MFMA, writes it as a partial,
+// and a second kernel sums the partials of every entry in a fixed order and
+// mirrors the upper triangle (deterministic, exactly symmetric).
+//
+// Operand trick: the sum over grid rows may visit the rows in any order as
+// long as both operands use the same order, so lane l takes rows
+// k0 + R*(l/16) + s (s < R) for its MFMA slot (l/16, l%16): each lane reads R
+// consecutive doubles of one column instead of a strided gather.
+//   FP64: v_mfma_f64_16x16x4f64, R = 4.
+//   BF16: v_mfma_f32_16x16x32_bf16, R = 8, inputs rounded to nearest-even
+//         from FP64, FP32 accumulation within a chunk, FP64 across chunks.
+#include "qo_internal.h"
+
+namespace qo {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 64;  // output tile edge per wavefront
+
+__device__ __forceinline__ const double *zcol(const double *X, const double *Y, long ld, int n,
+                                              int c) {
+    return c < n ? X + (long)c * ld : Y + (long)(c - n) * ld;
+}
+
+// Round an FP64 value to bfloat16, nearest-even on the 45 dropped mantissa
+// bits (one rounding, no FP32 intermediate).  Magnitudes below the FP32
+// normal range flush to signed zero; beyond it saturate to infinity.
+__device__ __forceinline__ __bf16 f64_to_bf16_rne(double d) {
+    const unsigned long long b = __double_as_longlong(d);
+    const unsigned int sign = (unsigned int)(b >> 63);
+    const int e = (int)((b >> 52) & 0x7ff);
+    unsigned short out;
+    if (e == 0x7ff) {  // inf / nan
+        out = (unsigned short)((sign << 15) | 0x7f80 | (((b & 0xfffffffffffffull) != 0) ? 0x40 : 0));
+    } else {
+        const unsigned long long lsb = (b >> 45) & 1ull;
+        const unsigned long long mag = (b & 0x7fffffffffffffffull) + 0xfffffffffffull + lsb;
+        int ef = (int)(mag >> 52) - 1023 + 127;
+        const unsigned int m7 = (unsigned int)((mag >> 45) & 0x7f);
+        if (e == 0 || ef <= 0) out = (unsigned short)(sign << 15);
+        else if (ef >= 255) out = (unsigned short)((sign << 15) | 0x7f80);
+        else out = (unsigned short)((sign << 15) | ((unsigned)ef << 7) | m7);
+    }
+    return __builtin_bit_cast(__bf16, out);
+}
+
+// Decode the upper-triangular tile pair index.
+__device__ __forceinline__ void tile_pair(int p, int nt, int &ti, int &tj) {
+    int i = 0, rem = p;
+    while (rem >= nt - i) {
+        rem -= nt - i;
+        ++i;
+    }
+    ti = i;
+    tj = i + rem;
+}
+
+__global__ __launch_bounds__(64) void k_gram_f64(const double *__restrict__ X,
+                                                 const double *__restrict__ Y, long ld, long ng,
+                                                 int n, long kchunk, double *__restrict__ part,
+                                                 int vec_ok) {
+    const int nn = 2 * n;
+    const int nt = (nn + TM - 1) / TM;
+    int ti, tj;
+    tile_pair(blockIdx.x, nt, ti, tj);
+    const int split = blockIdx.y;
+    const long kb = (long)split * kchunk;
+    const long ke = min(ng, kb + kchunk);
+    const int lane = threadIdx.x;
+    const int lr = lane & 15, lg = lane >> 4;
+
+    const double *pa[4];
+    const double *pb[4];
+    bool va[4], vb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int ca = ti * TM + 16 * i + lr;
+        const int cb = tj * TM + 16 * i + lr;
+        va[i] = ca < nn;
+        vb[i] = cb < nn;
+        pa[i] = va[i] ? zcol(X, Y, ld, n, ca) : X;
+        pb[i] = vb[i] ? zcol(X, Y, ld, n, cb) : X;
+    }
+    v4d acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    for (long k0 = kb; k0 < ke; k0 += 16) {
+        const long r0 = k0 + 4 * lg;
+        double a[4][4], b[4][4];
+        const bool full = vec_ok && (r0 + 4 <= ke);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (full) {
+                const double2 *qa = reinterpret_cast<const double2 *>(pa[i] + r0);
+                const double2 *qb = reinterpret_cast<const double2 *>(pb[i] + r0);
+                double2 a0 = va[i] ? qa[0] : double2{0.0, 0.0};
+                double2 a1 = va[i] ? qa[1] : double2{0.0, 0.0};
+                double2 b0 = vb[i] ? qb[0] : double2{0.0, 0.0};
+                double2 b1 = vb[i] ? qb[1] : double2{0.0, 0.0};
+                a[i][0] = a0.x; a[i][1] = a0.y; a[i][2] = a1.x; a[i][3] = a1.y;
+                b[i][0] = b0.x; b[i][1] = b0.y; b[i][2] = b1.x; b[i][3] = b1.y;
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const bool in = (r0 + s) < ke;
+                    a[i][s] = (va[i] && in) ? pa[i][r0 + s] : 0.0;
+                    b[i][s] = (vb[i] && in) ? pb[i][r0 + s] : 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j],
+                                                                    0, 0, 0);
+    }
+    // FP64 16x16 accumulator layout: value v of lane l is row l/16 + 4v, column l%16
+    double *out = part + (long)split * nn * nn;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = ti * TM + 16 * i + lg + 4 * v;
+                const int c = tj * TM + 16 * j + lr;
+                if (r < nn && c < nn) out[(long)c * nn + r] = acc[i][j][v];
+            }
+}
+
+__global__ __launch_bounds__(64) void k_gram_bf16(const double *__restrict__ X,
+                                                  const double *__restrict__ Y, long ld, long ng,
+                                                  int n, long kchunk, double *__restrict__ part,
+                                                  int vec_ok) {
+    const int nn = 2 * n;
+    const int nt = (nn + TM - 1) / TM;
+    int ti, tj;
+    tile_pair(blockIdx.x, nt, ti, tj);
+    const int split = blockIdx.y;
+    const long kb = (long)split * kchunk;
+    const long ke = min(ng, kb + kchunk);
+    const int lane = threadIdx.x;
+    const int lr = lane & 15, lg = lane >> 4;
+
+    const double *pa[4];
+    const double *pb[4];
+    bool va[4], vb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int ca = ti * TM + 16 * i + lr;
+        const int cb = tj * TM + 16 * i + lr;
+        va[i] = ca < nn;
+        vb[i] = cb < nn;
+        pa[i] = va[i] ? zcol(X, Y, ld, n, ca) : X;
+        pb[i] = vb[i] ? zcol(X, Y, ld, n, cb) : X;
+    }
+    v4f acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    for (long k0 = kb; k0 < ke; k0 += 32) {
+        const long r0 = k0 + 8 * lg;
+        v8bf a[4], b[4];
+        const bool full = vec_ok && (r0 + 8 <= ke);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double ta[8], tb[8];
+            if (full) {
+                const double2 *qa = reinterpret_cast<const double2 *>(pa[i] + r0);
+                const double2 *qb = reinterpret_cast<const double2 *>(pb[i] + r0);
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    double2 x = va[i] ? qa[h] : double2{0.0, 0.0};
+                    double2 y = vb[i] ? qb[h] : double2{0.0, 0.0};
+                    ta[2 * h] = x.x; ta[2 * h + 1] = x.y;
+                    tb[2 * h] = y.x; tb[2 * h + 1] = y.y;
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const bool in = (r0 + s) < ke;
+                    ta[s] = (va[i] && in) ? pa[i][r0 + s] : 0.0;
+                    tb[s] = (vb[i] && in) ? pb[i][r0 + s] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                a[i][s] = f64_to_bf16_rne(ta[s]);
+                b[i][s] = f64_to_bf16_rne(tb[s]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    double *out = part + (long)split * nn * nn;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = ti * TM + 16 * i + 4 * lg + v;
+                const int c = tj * TM + 16 * j + lr;
+                if (r < nn && c < nn) out[(long)c * nn + r] = (double)acc[i][j][v];
+            }
+}
+
+// G[r][c] = w * sum_s part[s][min(r,c)][max(r,c)]
+__global__ void k_gram_reduce(const double *__restrict__ part, int nn, int nsplit, double w,
+                              double *__restrict__ G) {
+    const long total = (long)nn * nn;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int r = (int)(e % nn), c = (int)(e / nn);
+        const int a = min(r, c), b = max(r, c);
+        const long o = (long)b * nn + a;
+        double s = 0.0;
+        for (int k = 0; k < nsplit; ++k) s += part[(long)k * total + o];
+        G[e] = w * s;
+    }
+}
+
+}  // namespace
+
+int gram_nsplit(long ng, int n) {
+    const int nt = (2 * n + TM - 1) / TM;
+    const int npairs = nt * (nt + 1) / 2;
+    long ns = 4096 / npairs;
+    const long maxk = (ng + 255) / 256;
+    if (ns > maxk) ns = maxk;
+    // keep the partial buffer under 256 MiB
+    const long per = (long)4 * n * n * 8;
+    const long cap = (256L << 20) / per;
+    if (ns > cap) ns = cap;
+    if (ns < 1) ns = 1;
+    return (int)ns;
+}
+
+size_t gram_part_elems(int n, int nsplit) { return (size_t)nsplit * 4 * n * n; }
+
+static hipError_t gram_common(bool bf16, const double *X, const double *Y, long ld, long ng,
+                              int n, double w, double *part, int nsplit, double *G,
+                              hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int nt = (2 * n + TM - 1) / TM;
+    const int npairs = nt * (nt + 1) / 2;
+    long kchunk = (ng + nsplit - 1) / nsplit;
+    kchunk = (kchunk + 31) / 32 * 32;
+    const int vec_ok = (ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
+                       ((reinterpret_cast<uintptr_t>(Y) & 15) == 0);
+    const dim3 grid(npairs, nsplit);
+    if (bf16)
+        hipLaunchKernelGGL(k_gram_bf16, grid, dim3(64), 0, st, X, Y, ld, ng, n, kchunk, part,
+                           vec_ok);
+    else
+        hipLaunchKernelGGL(k_gram_f64, grid, dim3(64), 0, st, X, Y, ld, ng, n, kchunk, part,
+                           vec_ok);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long total = 4L * n * n;
+    long blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)blocks), dim3(256), 0, st, part, 2 * n,
+                       nsplit, w, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_f64(const double *X, const double *Y, long ld, long ng, int n, double w,
+                           double *part, int nsplit, double *G, hipStream_t st) {
+    return gram_common(false, X, Y, ld, ng, n, w, part, nsplit, G, st);
+}
+
+hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, int n, double w,
+                            double *part, int nsplit, double *G, hipStream_t st) {
+    return gram_common(true, X, Y, ld, ng, n, w, part, nsplit, G, st);
+}
+
+}  // namespace qo

@@ -1,0 +1,125 @@
+// Private declarations of libqo_hip: grid descriptor, kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace qo {
+
+// Geometry of one column grid and of its band/z-chunk tiling.
+//   A tile is TY consecutive y-rows (full x extent) of ZC consecutive z-planes;
+//   one workgroup of 256 threads streams one tile of one column, marching in z.
+struct Grid {
+    int dim;
+    int nx, ny, nz;      // nz = 1 in 2-D
+    long ng;             // nx*ny*nz
+    int TY, ZC;          // tile rows, tile planes
+    int nbands, nzc;     // tiles per column = nbands*nzc
+    int ppt;             // points per thread per plane: ceil(TY*nx/256) rounded up to 1,2,4,6,8
+    double ihx2, ihy2, ihz2;  // 1/h_k^2 (ihz2 = 0 in 2-D)
+    double kappa;
+    double c0;           // 2 kappa (ihx2 + ihy2 + ihz2): stencil diagonal without V
+    __host__ __device__ int tiles() const { return nbands * nzc; }
+};
+
+constexpr int kThreads = 256;
+
+// Per-column PCG bookkeeping on the device (double-buffered by iteration parity).
+struct PcgState {
+    double *rho;    // [2][ncap]
+    int *active;    // [2][ncap]
+    int *its;       // [ncap]
+    double *bb;     // [ncap]
+    double *part;   // partial sums [4][ncap * tiles]
+    int *err;       // [2]: error code, first failing column
+};
+
+// ---- stencil family (qo_stencil.hip) ----
+// All take a column count `ncols`, a column stride `ld` and per-point arrays
+// vs = V + sigma and dinv = 1/(c0 + vs) of the matching precision.
+hipError_t launch_apply(const Grid &g, const double *vs, const double *X, double *Y, long ld,
+                        int ncols, hipStream_t st);
+// partial sums per (column, tile): part[0] = x.Hx, part[1] = x.x
+hipError_t launch_quad(const Grid &g, const double *vs, const double *X, long ld, int ncols,
+                       double *part, hipStream_t st);
+// Mixed-precision residual: r = b - H x (FP64), r32 = (float) r; partials rr, bb.
+// Columns with mask[c] == 0 are skipped (their partials are set to zero).
+hipError_t launch_resid(const Grid &g, const double *vs, const double *B, const double *X,
+                        long ld, float *R32, long ld32, int ncols, const int *mask, double *part,
+                        hipStream_t st);
+
+template <typename T>
+hipError_t launch_pcg_init(const Grid &g, const T *vs, const T *dinv, const T *B, T *X, T *R,
+                           long ld, int ncols, int use_x0, double *part, hipStream_t st);
+template <typename T>
+hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T *R,
+                             const T *Pold, T *Pnew, long ld, int ncols, int k, double tol,
+                             const int *mask, PcgState s, hipStream_t st);
+template <typename T>
+hipError_t launch_pcg_sweep2(const Grid &g, const T *vs, const T *dinv, const T *Pn, T *X, T *R,
+                             long ld, int ncols, int k, PcgState s, hipStream_t st);
+
+// Sum partials per column: out[c] = sum_t part[q][c*tiles + t] for q < nq; out is [nq][ncols].
+hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long qstride,
+                         double *out, hipStream_t st);
+
+// x += d (FP64 += FP32) for columns with mask != 0.
+hipError_t launch_refine_axpy(double *X, long ld, const float *D, long ld32, long ng, int ncols,
+                              const int *mask, hipStream_t st);
+// mask[c] = (sqrt(rr[c]) > tol * sqrt(bb[c])); counts into *nactive (device int)
+hipError_t launch_refine_mask(const double *sums, int ncols, double tol, int *mask,
+                              int *nactive, int *err, hipStream_t st);
+
+// ---- Gram (qo_gram.hip) ----
+// G (2n x 2n, col-major, ld 2n) = w * [X Y]^T [X Y]; part: workspace of
+// gram_part_elems(n, nsplit) doubles.
+size_t gram_part_elems(int n, int nsplit);
+int gram_nsplit(long ng, int n);
+hipError_t launch_gram_f64(const double *X, const double *Y, long ld, long ng, int n,
+                           double w, double *part, int nsplit, double *G, hipStream_t st);
+hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, int n,
+                            double w, double *part, int nsplit, double *G, hipStream_t st);
+
+// ---- tall-skinny update (qo_tsgemm.hip) ----
+// Out = C0 + A * Xs + B * Ys  (Ng x n, col-major), small operands given
+// transposed: XsT[i*n + k] = Xs[k][i] (i.e. Xs stored row-major).  Any of C0,
+// A, B may be null.  Out may alias C0 only.
+hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
+                         const double *XsT, const double *B, const double *YsT, long ld,
+                         long ng, int n, hipStream_t st);
+
+// ---- small dense FP64 (qo_small.hip), all column-major with explicit ld ----
+// C = alpha op(A) op(B) + beta C + gamma I
+hipError_t nn_gemm(double *C, int ldc, const double *A, int lda, bool ta, const double *B,
+                   int ldb, bool tb, int m, int n, int k, double alpha, double beta,
+                   double gamma, hipStream_t st);
+// C = a A + b op(B) + g I   (C may alias A or B only when op(B) = B)
+hipError_t nn_axpby(double *C, int ldc, double a, const double *A, int lda, double b,
+                    const double *B, int ldb, bool tb, double g, int m, int n, hipStream_t st);
+// B <- A^{-1} B by Gauss-Jordan on [A | B] (A destroyed).  spd: no pivoting and
+// fail when a pivot is not > 0; else partial pivoting.  status: device int,
+// set to the qo_status code on failure (left untouched on success).
+hipError_t nn_gj_solve(double *A, int lda, double *B, int ldb, int n, int m, bool spd,
+                       int *status, hipStream_t st);
+// Symmetric eigen-decomposition by cyclic Jacobi: A (n x n, destroyed) ->
+// evals (n), V (n x n, ld n) with A = V diag V^T; unsorted.
+hipError_t nn_jacobi(double *A, int lda, int n, double *evals, double *V, int ldv,
+                     double *work, hipStream_t st);
+// Sort evals ascending (or descending) and permute the columns of V (may be null).
+hipError_t nn_sort(double *evals, double *V, int ldv, int n, bool descending, double *work,
+                   hipStream_t st);
+// out[0] = tr(R) - 2 tr(M M) + tr(M S M^T) (squared gradient norm),
+// out[1] = ||A||_F (for A = O)
+hipError_t nn_grad2(const double *S, const double *M, const double *R, int ld, int n,
+                    double *MS, int ldms, double *out, hipStream_t st);
+hipError_t nn_fro(const double *A, int lda, int n, double *out, hipStream_t st);
+// F = V diag(1/sqrt(ev)) (columns scaled); fails (status) if ev <= 0
+hipError_t nn_scale_cols_rsqrt(double *F, const double *V, int ld, const double *ev, int n,
+                               int *status, hipStream_t st);
+// out[i] = 1/ev[i] - sigma  or ev[i] - sigma
+hipError_t nn_eval_map(double *out, const double *ev, int n, bool invert, double sigma,
+                       hipStream_t st);
+// energy finish: out[0] = E_sigma = 0.5 w sum_c sums[0][c], out[1] = w sum_c sums[1][c]
+hipError_t nn_energy_finish(const double *sums, int ncols, double w, double *out,
+                            hipStream_t st);
+
+}  // namespace qo

@@ -1,0 +1,563 @@
+// Stencil family: the discrete operator H_sigma = -kappa Lap_h + V + sigma
+// (5-point in 2-D, 7-point in 3-D, Dirichlet) applied to many columns, and the
+// batched Jacobi-PCG sweeps that apply the inverse operator G = H_sigma^{-1}
+// of Sec. 3.1 to a block.
+//
+// One workgroup (256 threads) streams one tile of one column: TY full x-rows
+// of ZC z-planes.  The operand of the stencil is formed on the fly for the
+// tile plus one halo row on each side and written to a double-buffered LDS
+// plane; the z-neighbours live in registers (z-marching), so every value is
+// read from HBM once per sweep up to the halo rows shared with the
+// neighbouring band.  Per-column dot products are reduced per workgroup with
+// wavefront shuffles and written as partial sums; the next kernel reduces a
+// column's partials in a fixed order, so results are deterministic.
+//
+// PCG per column (Hestenes-Stiefel form, Jacobi preconditioner D = diag(H)^-1):
+//   sweep1(k): from r and the previous p form p = D r + beta p_old on the fly
+//              (beta = rho_k / rho_{k-1}, p = D r at k = 0), store p,
+//              gamma = p . H p  (q = H p is not stored)
+//   sweep2(k): alpha = rho_k / gamma;  x += alpha p;  r -= alpha H p (H p
+//              recomputed from p);  partials of r . D r and r . r
+// The per-column stop test ||r|| <= tol ||b|| is evaluated at the start of
+// sweep1, so a column freezes at the first iteration that passes it.
+#include "qo_internal.h"
+
+namespace qo {
+
+namespace {
+
+struct Red {
+    double v[4][kThreads / 64];
+};
+
+template <int NQ>
+__device__ __forceinline__ void block_sums(double (&v)[NQ], Red &red) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) red.v[q][wid] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) s += red.v[q][w];
+        v[q] = s;
+    }
+}
+
+// Sum of part[c*tiles + t] over t, identical in every thread and every block.
+__device__ __forceinline__ double col_sum(const double *__restrict__ part, int c, int tiles,
+                                          Red &red) {
+    double s[1] = {0.0};
+    for (int t = threadIdx.x; t < tiles; t += kThreads) s[0] += part[(long)c * tiles + t];
+    block_sums<1>(s, red);
+    return s[0];
+}
+
+// The streaming engine.  opnd(i) returns the stencil operand at in-column index
+// i; epi(s, i, centre, Hv) consumes the operator value at each own point.
+template <typename T, int PPT, class Opnd, class Epi>
+__device__ __forceinline__ void engine(const Grid &g, int band, int zc,
+                                       const T *__restrict__ vs, Opnd &opnd, Epi &epi,
+                                       T *__restrict__ lds) {
+    const int tid = threadIdx.x;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int y0 = band * g.TY;
+    const int ty = min(g.TY, ny - y0);
+    const int npts = ty * nx;
+    const int z0 = zc * g.ZC;
+    const int z1 = min(nz, z0 + g.ZC);
+    const long plane = (long)nx * ny;
+    const int ldsz = (g.TY + 2) * nx;
+    const bool has_lo = y0 > 0, has_hi = (y0 + ty) < ny;
+    const T kap = (T)g.kappa, c0 = (T)g.c0;
+    const T ihx2 = (T)g.ihx2, ihy2 = (T)g.ihy2, ihz2 = (T)g.ihz2;
+
+    int xs[PPT];
+    bool val[PPT];
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+        const int t = tid + s * kThreads;
+        val[s] = t < npts;
+        xs[s] = val[s] ? t % nx : 0;
+    }
+    T om[PPT], oc[PPT], op[PPT];
+    {
+        const long b0 = (long)z0 * plane + (long)y0 * nx;
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) {
+            const int t = tid + s * kThreads;
+            om[s] = (val[s] && z0 > 0) ? opnd(b0 - plane + t) : T(0);
+            oc[s] = val[s] ? opnd(b0 + t) : T(0);
+            op[s] = (val[s] && z0 + 1 < nz) ? opnd(b0 + plane + t) : T(0);
+            if (val[s]) lds[nx + t] = oc[s];
+        }
+        for (int hh = tid; hh < nx; hh += kThreads) {
+            lds[hh] = has_lo ? opnd(b0 - nx + hh) : T(0);
+            lds[(ty + 1) * nx + hh] = has_hi ? opnd(b0 + (long)ty * nx + hh) : T(0);
+        }
+    }
+    __syncthreads();
+    for (int z = z0; z < z1; ++z) {
+        const int cur = (z - z0) & 1;
+        const T *__restrict__ L = lds + cur * ldsz;
+        const long b = (long)z * plane + (long)y0 * nx;
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) {
+            if (!val[s]) continue;
+            const int t = tid + s * kThreads;
+            const int x = xs[s];
+            const T xm = x > 0 ? L[nx + t - 1] : T(0);
+            const T xp = x < nx - 1 ? L[nx + t + 1] : T(0);
+            const T ym = L[t];
+            const T yp = L[t + 2 * nx];
+            const long gi = b + t;
+            const T hv = (c0 + vs[gi]) * oc[s] -
+                         kap * (ihx2 * (xm + xp) + ihy2 * (ym + yp) + ihz2 * (om[s] + op[s]));
+            epi(s, gi, oc[s], hv);
+        }
+        if (z + 1 < z1) {
+            T *__restrict__ Ln = lds + (cur ^ 1) * ldsz;
+            const long bn = b + plane;
+#pragma unroll
+            for (int s = 0; s < PPT; ++s) {
+                const int t = tid + s * kThreads;
+                if (val[s]) Ln[nx + t] = op[s];
+            }
+            for (int hh = tid; hh < nx; hh += kThreads) {
+                Ln[hh] = has_lo ? opnd(bn - nx + hh) : T(0);
+                Ln[(ty + 1) * nx + hh] = has_hi ? opnd(bn + (long)ty * nx + hh) : T(0);
+            }
+#pragma unroll
+            for (int s = 0; s < PPT; ++s) {
+                const int t = tid + s * kThreads;
+                om[s] = oc[s];
+                oc[s] = op[s];
+                op[s] = (val[s] && z + 2 < nz) ? opnd(bn + plane + t) : T(0);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void tile_of(const Grid &g, int &col, int &tile, int &band, int &zc) {
+    const int tiles = g.tiles();
+    col = blockIdx.x / tiles;
+    tile = blockIdx.x - col * tiles;
+    band = tile / g.nzc;
+    zc = tile - band * g.nzc;
+}
+
+template <typename T>
+__device__ __forceinline__ T *lds_ptr() {
+    extern __shared__ __align__(16) unsigned char qo_smem[];
+    return reinterpret_cast<T *>(qo_smem);
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <int PPT>
+__global__ __launch_bounds__(kThreads) void k_apply(Grid g, const double *__restrict__ vs,
+                                                    const double *__restrict__ X,
+                                                    double *__restrict__ Y, long ld) {
+    int col, tile, band, zc;
+    tile_of(g, col, tile, band, zc);
+    const double *x = X + (long)col * ld;
+    double *y = Y + (long)col * ld;
+    auto opnd = [&](long i) { return x[i]; };
+    auto epi = [&](int, long i, double, double hv) { y[i] = hv; };
+    engine<double, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<double>());
+}
+
+template <int PPT>
+__global__ __launch_bounds__(kThreads) void k_quad(Grid g, const double *__restrict__ vs,
+                                                   const double *__restrict__ X, long ld,
+                                                   double *__restrict__ part, long qs) {
+    __shared__ Red red;
+    int col, tile, band, zc;
+    tile_of(g, col, tile, band, zc);
+    const double *x = X + (long)col * ld;
+    double acc[2] = {0.0, 0.0};
+    auto opnd = [&](long i) { return x[i]; };
+    auto epi = [&](int, long, double c, double hv) {
+        acc[0] += c * hv;
+        acc[1] += c * c;
+    };
+    engine<double, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<double>());
+    block_sums<2>(acc, red);
+    if (threadIdx.x == 0) {
+        const long o = (long)col * g.tiles() + tile;
+        part[o] = acc[0];
+        part[qs + o] = acc[1];
+    }
+}
+
+template <int PPT>
+__global__ __launch_bounds__(kThreads) void k_resid(Grid g, const double *__restrict__ vs,
+                                                    const double *__restrict__ B,
+                                                    const double *__restrict__ X, long ld,
+                                                    float *__restrict__ R32, long ld32,
+                                                    const int *__restrict__ mask,
+                                                    double *__restrict__ part, long qs) {
+    __shared__ Red red;
+    int col, tile, band, zc;
+    tile_of(g, col, tile, band, zc);
+    const long o = (long)col * g.tiles() + tile;
+    if (mask && !mask[col]) {
+        if (threadIdx.x == 0) part[qs + o] = part[2 * qs + o] = 0.0;
+        return;
+    }
+    const double *x = X + (long)col * ld;
+    const double *b = B + (long)col * ld;
+    float *r32 = R32 + (long)col * ld32;
+    double acc[2] = {0.0, 0.0};
+    auto opnd = [&](long i) { return x[i]; };
+    auto epi = [&](int, long i, double, double hv) {
+        const double bi = b[i];
+        const double r = bi - hv;
+        r32[i] = (float)r;
+        acc[0] += r * r;
+        acc[1] += bi * bi;
+    };
+    engine<double, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<double>());
+    block_sums<2>(acc, red);
+    if (threadIdx.x == 0) {
+        part[qs + o] = acc[0];
+        part[2 * qs + o] = acc[1];
+    }
+}
+
+// r = b - H x0 (or r = b, x = 0); partials rz (q0), rr (q1), bb (q2)
+template <typename T, int PPT>
+__global__ __launch_bounds__(kThreads) void k_pcg_init(Grid g, const T *__restrict__ vs,
+                                                       const T *__restrict__ dinv,
+                                                       const T *__restrict__ B,
+                                                       T *__restrict__ X, T *__restrict__ R,
+                                                       long ld, int use_x0,
+                                                       double *__restrict__ part, long qs) {
+    __shared__ Red red;
+    int col, tile, band, zc;
+    tile_of(g, col, tile, band, zc);
+    T *x = X + (long)col * ld;
+    const T *b = B + (long)col * ld;
+    T *r = R + (long)col * ld;
+    double acc[3] = {0.0, 0.0, 0.0};
+    auto opnd = [&](long i) { return use_x0 ? x[i] : T(0); };
+    auto epi = [&](int, long i, T, T hv) {
+        const T bi = b[i];
+        T ri;
+        if (use_x0) {
+            ri = bi - hv;
+        } else {
+            ri = bi;
+            x[i] = T(0);
+        }
+        r[i] = ri;
+        const double rd = (double)ri;
+        acc[0] += rd * (double)(dinv[i] * ri);
+        acc[1] += rd * rd;
+        acc[2] += (double)bi * (double)bi;
+    };
+    engine<T, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<T>());
+    block_sums<3>(acc, red);
+    if (threadIdx.x == 0) {
+        const long o = (long)col * g.tiles() + tile;
+        part[o] = acc[0];
+        part[qs + o] = acc[1];
+        part[2 * qs + o] = acc[2];
+    }
+}
+
+template <typename T, int PPT>
+__global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__restrict__ vs,
+                                                         const T *__restrict__ dinv,
+                                                         const T *__restrict__ R,
+                                                         const T *__restrict__ Pold,
+                                                         T *__restrict__ Pnew, long ld, int ncols,
+                                                         int k, double tol,
+                                                         const int *__restrict__ mask,
+                                                         PcgState s, long qs) {
+    __shared__ Red red;
+    __shared__ int sh_flag;
+    int col, tile, band, zc;
+    tile_of(g, col, tile, band, zc);
+    const bool lead = tile == 0;
+    const int cur = k & 1, prv = cur ^ 1;
+    const int tiles = g.tiles();
+    int prev_active = (k == 0) ? (mask ? mask[col] : 1) : s.active[prv * ncols + col];
+    if (!prev_active) {
+        if (lead && threadIdx.x == 0) s.active[cur * ncols + col] = 0;
+        return;
+    }
+    const double rz = col_sum(s.part, col, tiles, red);
+    const double rr = col_sum(s.part + qs, col, tiles, red);
+    double bb;
+    if (k == 0) {
+        bb = col_sum(s.part + 2 * qs, col, tiles, red);
+        if (lead && threadIdx.x == 0) s.bb[col] = bb;
+    } else {
+        bb = s.bb[col];
+    }
+    if (threadIdx.x == 0) {
+        int flag = 0;  // 0 run, 1 converged, 2 non-finite
+        if (!isfinite(rz) || !isfinite(rr) || !isfinite(bb)) flag = 2;
+        else if (sqrt(rr) <= tol * sqrt(bb)) flag = 1;
+        sh_flag = flag;
+        if (lead) {
+            s.its[col] = k;
+            s.active[cur * ncols + col] = flag == 0 ? 1 : 0;
+            if (flag == 0) s.rho[cur * ncols + col] = rz;
+            if (flag == 2) {
+                atomicMax(&s.err[0], 7);
+                atomicMin(&s.err[1], col);
+            }
+        }
+    }
+    __syncthreads();
+    if (sh_flag != 0) return;
+    const T beta = (k == 0) ? T(0) : (T)(rz / s.rho[prv * ncols + col]);
+    const T *r = R + (long)col * ld;
+    const T *po = Pold + (long)col * ld;
+    T *pn = Pnew + (long)col * ld;
+    double acc[1] = {0.0};
+    auto opnd = [&](long i) {
+        const T z = dinv[i] * r[i];
+        return k == 0 ? z : z + beta * po[i];
+    };
+    auto epi = [&](int, long i, T c, T hv) {
+        pn[i] = c;
+        acc[0] += (double)c * (double)hv;
+    };
+    engine<T, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<T>());
+    block_sums<1>(acc, red);
+    if (threadIdx.x == 0) s.part[3 * qs + (long)col * tiles + tile] = acc[0];
+}
+
+template <typename T, int PPT>
+__global__ __launch_bounds__(kThreads) void k_pcg_sweep2(Grid g, const T *__restrict__ vs,
+                                                         const T *__restrict__ dinv,
+                                                         const T *__restrict__ Pn,
+                                                         T *__restrict__ X, T *__restrict__ R,
+                                                         long ld, int ncols, int k, PcgState s,
+                                                         long qs) {
+    __shared__ Red red;
+    __shared__ int sh_flag;
+    int col, tile, band, zc;
+    tile_of(g, col, tile, band, zc);
+    const int cur = k & 1;
+    const int tiles = g.tiles();
+    if (!s.active[cur * ncols + col]) return;
+    const double gam = col_sum(s.part + 3 * qs, col, tiles, red);
+    if (threadIdx.x == 0) {
+        int flag = 0;
+        if (!isfinite(gam)) flag = 7;
+        else if (!(gam > 0.0)) flag = 5;
+        sh_flag = flag;
+        if (flag && tile == 0) {
+            atomicMax(&s.err[0], flag);
+            atomicMin(&s.err[1], col);
+        }
+    }
+    __syncthreads();
+    if (sh_flag) return;
+    const T alpha = (T)(s.rho[cur * ncols + col] / gam);
+    const T *p = Pn + (long)col * ld;
+    T *x = X + (long)col * ld;
+    T *r = R + (long)col * ld;
+    double acc[2] = {0.0, 0.0};
+    auto opnd = [&](long i) { return p[i]; };
+    auto epi = [&](int, long i, T c, T hv) {
+        x[i] += alpha * c;
+        const T ri = r[i] - alpha * hv;
+        r[i] = ri;
+        const double rd = (double)ri;
+        acc[0] += rd * (double)(dinv[i] * ri);
+        acc[1] += rd * rd;
+    };
+    engine<T, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<T>());
+    block_sums<2>(acc, red);
+    if (threadIdx.x == 0) {
+        const long o = (long)col * tiles + tile;
+        s.part[o] = acc[0];
+        s.part[qs + o] = acc[1];
+    }
+}
+
+__global__ void k_colsum(const double *__restrict__ part, int tiles, int ncols, int nq, long qs,
+                         double *__restrict__ out) {
+    __shared__ Red red;
+    const int c = blockIdx.x;
+    for (int q = 0; q < nq; ++q) {
+        const double v = col_sum(part + q * qs, c, tiles, red);
+        if (threadIdx.x == 0) out[q * ncols + c] = v;
+    }
+}
+
+__global__ void k_refine_axpy(double *__restrict__ X, long ld, const float *__restrict__ D,
+                              long ld32, long ng, const int *__restrict__ mask) {
+    const int c = blockIdx.y;
+    if (!mask[c]) return;
+    double *x = X + (long)c * ld;
+    const float *d = D + (long)c * ld32;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ng;
+         i += (long)gridDim.x * blockDim.x)
+        x[i] += (double)d[i];
+}
+
+// sums: [0..ncols) = rr, [ncols..2ncols) = bb
+__global__ void k_refine_mask(const double *__restrict__ sums, int ncols, double tol,
+                              int *__restrict__ mask, int *__restrict__ nactive,
+                              int *__restrict__ err) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+        const double rr = sums[c], bb = sums[ncols + c];
+        int m = 0;
+        if (!isfinite(rr) || !isfinite(bb)) {
+            atomicMax(&err[0], 7);
+            atomicMin(&err[1], c);
+        } else {
+            m = sqrt(rr) > tol * sqrt(bb) ? 1 : 0;
+        }
+        mask[c] = m;
+        if (m) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *nactive = cnt;
+}
+
+inline size_t lds_bytes(const Grid &g, size_t elem) { return 2 * (size_t)(g.TY + 2) * g.nx * elem; }
+
+#define QO_DISPATCH_PPT(PPTV, ...)                        \
+    switch (PPTV) {                                       \
+        case 1: { constexpr int P = 1; __VA_ARGS__; } break; \
+        case 2: { constexpr int P = 2; __VA_ARGS__; } break; \
+        case 4: { constexpr int P = 4; __VA_ARGS__; } break; \
+        case 6: { constexpr int P = 6; __VA_ARGS__; } break; \
+        case 8: { constexpr int P = 8; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;               \
+    }
+
+}  // namespace
+
+hipError_t launch_apply(const Grid &g, const double *vs, const double *X, double *Y, long ld,
+                        int ncols, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const dim3 grid(ncols * g.tiles());
+    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL(k_apply<P>, grid, dim3(kThreads),
+                                               lds_bytes(g, 8), st, g, vs, X, Y, ld));
+    return hipGetLastError();
+}
+
+hipError_t launch_quad(const Grid &g, const double *vs, const double *X, long ld, int ncols,
+                       double *part, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const long qs = (long)ncols * g.tiles();
+    const dim3 grid(ncols * g.tiles());
+    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL(k_quad<P>, grid, dim3(kThreads),
+                                               lds_bytes(g, 8), st, g, vs, X, ld, part, qs));
+    return hipGetLastError();
+}
+
+hipError_t launch_resid(const Grid &g, const double *vs, const double *B, const double *X,
+                        long ld, float *R32, long ld32, int ncols, const int *mask, double *part,
+                        hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const long qs = (long)ncols * g.tiles();
+    const dim3 grid(ncols * g.tiles());
+    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL(k_resid<P>, grid, dim3(kThreads),
+                                               lds_bytes(g, 8), st, g, vs, B, X, ld, R32, ld32,
+                                               mask, part, qs));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pcg_init(const Grid &g, const T *vs, const T *dinv, const T *B, T *X, T *R,
+                           long ld, int ncols, int use_x0, double *part, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const long qs = (long)ncols * g.tiles();
+    const dim3 grid(ncols * g.tiles());
+    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_init<T, P>), grid, dim3(kThreads),
+                                               lds_bytes(g, sizeof(T)), st, g, vs, dinv, B, X, R,
+                                               ld, use_x0, part, qs));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T *R,
+                             const T *Pold, T *Pnew, long ld, int ncols, int k, double tol,
+                             const int *mask, PcgState s, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const long qs = (long)ncols * g.tiles();
+    const dim3 grid(ncols * g.tiles());
+    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep1<T, P>), grid, dim3(kThreads),
+                                               lds_bytes(g, sizeof(T)), st, g, vs, dinv, R, Pold,
+                                               Pnew, ld, ncols, k, tol, mask, s, qs));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pcg_sweep2(const Grid &g, const T *vs, const T *dinv, const T *Pn, T *X, T *R,
+                             long ld, int ncols, int k, PcgState s, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const long qs = (long)ncols * g.tiles();
+    const dim3 grid(ncols * g.tiles());
+    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep2<T, P>), grid, dim3(kThreads),
+                                               lds_bytes(g, sizeof(T)), st, g, vs, dinv, Pn, X, R,
+                                               ld, ncols, k, s, qs));
+    return hipGetLastError();
+}
+
+template hipError_t launch_pcg_init<double>(const Grid &, const double *, const double *,
+                                            const double *, double *, double *, long, int, int,
+                                            double *, hipStream_t);
+template hipError_t launch_pcg_init<float>(const Grid &, const float *, const float *,
+                                           const float *, float *, float *, long, int, int,
+                                           double *, hipStream_t);
+template hipError_t launch_pcg_sweep1<double>(const Grid &, const double *, const double *,
+                                              const double *, const double *, double *, long,
+                                              int, int, double, const int *, PcgState,
+                                              hipStream_t);
+template hipError_t launch_pcg_sweep1<float>(const Grid &, const float *, const float *,
+                                             const float *, const float *, float *, long, int,
+                                             int, double, const int *, PcgState, hipStream_t);
+template hipError_t launch_pcg_sweep2<double>(const Grid &, const double *, const double *,
+                                              const double *, double *, double *, long, int, int,
+                                              PcgState, hipStream_t);
+template hipError_t launch_pcg_sweep2<float>(const Grid &, const float *, const float *,
+                                             const float *, float *, float *, long, int, int,
+                                             PcgState, hipStream_t);
+
+hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long qstride,
+                         double *out, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_colsum, dim3(ncols), dim3(kThreads), 0, st, part, tiles, ncols, nq,
+                       qstride, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_axpy(double *X, long ld, const float *D, long ld32, long ng, int ncols,
+                              const int *mask, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    long blocks = (ng + 1023) / 1024;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_refine_axpy, dim3((unsigned)blocks, ncols), dim3(256), 0, st, X, ld, D,
+                       ld32, ng, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_mask(const double *sums, int ncols, double tol, int *mask,
+                              int *nactive, int *err, hipStream_t st) {
+    hipLaunchKernelGGL(k_refine_mask, dim3(1), dim3(256), 0, st, sums, ncols, tol, mask, nactive,
+                       err);
+    return hipGetLastError();
+}
+
+}  // namespace qo

@@ -1,0 +1,259 @@
+"""Throughput of the quasi-orthogonal evolution step on one MI355X.
+
+Workload: 3-D unit cube, 96^3 interior grid (Ng = 884,736), 7-point stencil,
+Dirichlet, H = -1/2 Lap + V with V = 8 Gaussian wells (seed 0), N = 256
+eigenpairs, U0 i.i.d. N(0,1) (seed 1), tau = 0.9 lambda_1 (lambda_1 estimated
+on a 32^3 grid of the same potential), PCG tolerance 1e-10, warm starts.
+One step = one full pass of the scheme (two inverse-operator solves, two Gram
+matrices, the N x N predictor solve, the two block updates and the energy).
+
+value = steps/s of the mixed-precision path (FP32 PCG inside FP64 iterative
+refinement, BF16 Gram tiles with FP32 accumulation, FP64 N x N algebra and
+energy); the FP64 path is timed beside it.  The roofline object describes the
+dominant kernel of the mixed path, measured live with HIP events around every
+launch on the library's stream.  cpu_baseline times the FP64 oracle on a
+bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "steps/s at 96³,N=256: mixed vs FP64 at 1e-8 eig error; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per (grid point x column) of one launch; s = bytes per value
+#   sweep1: read r, p_old; write p        -> 3 s
+#   sweep2: read p, x, r;  write x, r     -> 5 s
+BYTES_PER_COLPT = {"sweep1_f64": 24, "sweep2_f64": 40, "sweep1_f32": 12, "sweep2_f32": 20}
+
+
+def lambda1_estimate(n_coarse=32, seed=0):
+    """Lowest eigenvalue of H on a coarse grid of the same potential (scipy, host)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+
+    from paper_2605_25149_amd import inputs
+
+    n = (n_coarse,) * 3
+    V = inputs.gaussian_wells(n, seed=seed)
+    h = 1.0 / (n_coarse + 1)
+    T = sp.diags([np.full(n_coarse - 1, -1.0), np.full(n_coarse, 2.0),
+                  np.full(n_coarse - 1, -1.0)], [-1, 0, 1]) * (0.5 / h**2)
+    I = sp.identity(n_coarse)
+    H = (sp.kron(sp.kron(I, I), T) + sp.kron(sp.kron(I, T), I) + sp.kron(sp.kron(T, I), I)
+         + sp.diags(V)).tocsc()
+    vals = spla.eigsh(H, k=1, sigma=0.0, which="LM", return_eigenvectors=False)
+    return float(vals[0])
+
+
+def run_gpu(precision, V, U0, n, N, tau, steps, warmup, inner_tol, log):
+    import torch
+
+    from paper_2605_25149_amd import binding
+
+    s = binding.Solver(3, n, N, pcg_tol=1e-10, pcg_maxit=5000, pcg_check=8,
+                       precision=precision, refine_inner_tol=inner_tol)
+    try:
+        s.set_potential(V)
+        s.set_state(U0)
+        for i in range(warmup):
+            st = s.step(tau)
+            log(f"[{precision}] warmup step {i + 1}/{warmup}: iters {st['pcg_iters']} "
+                f"rounds {st['refine_rounds']} E {st['energy']:.10f}")
+        s.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = []
+        for i in range(steps):
+            st = s.step(tau)
+            stats.append(st)
+            log(f"[{precision}] step {i + 1}/{steps}: iters {st['pcg_iters']} "
+                f"rounds {st['refine_rounds']} E {st['energy']:.10f} "
+                f"phases(ms) {[round(x, 1) for x in st['t_phase_ms']]}")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = s.profile_data()
+        s.profile(False)
+        return {"seconds": t1 - t0, "stats": stats, "profile": prof}
+    finally:
+        s.close()
+
+
+def roofline_of(prof, ng):
+    """Dominant PCG sweep kernel: algorithmic bytes per launch / mean launch duration."""
+    best = None
+    for k, bpp in BYTES_PER_COLPT.items():
+        d = prof[k]
+        if d["launches"] == 0 or d["ms"] <= 0:
+            continue
+        if best is None or d["ms"] > prof[best]["ms"]:
+            best = k
+    if best is None:
+        return None
+    d = prof[best]
+    bytes_total = BYTES_PER_COLPT[best] * ng * d["work"]
+    per_launch_bytes = bytes_total / d["launches"]
+    mean_ms = d["ms"] / d["launches"]
+    achieved = per_launch_bytes / (mean_ms * 1e-3) / 1e9
+    return {
+        "kernel": f"k_pcg_{best}",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "launches": d["launches"],
+        "mean_launch_ms": round(mean_ms, 4),
+        "algorithmic_bytes_per_launch": round(per_launch_bytes),
+    }
+
+
+def cpu_baseline(V, U0, n, N, tau, colits_per_step, log):
+    """FP64 oracle on the host: a bounded sample of the same workload, scaled to steps/s.
+
+    Sample: (a) oracle Jacobi-PCG on all N columns of the 96^3 grid for a fixed number of
+    iterations (its column-iteration rate); (b) one pass of the oracle's non-PCG stages
+    (three Gram matrices, the 2N x 2N predictor solve and the block update, the corrector
+    and the energy) on full-size blocks.  Steps/s = 1 / (column-iterations per step /
+    rate + time of (b)), with column-iterations per step taken from the FP64 GPU run
+    (same algorithm and stop rule)."""
+    from oracle import oracle as orc
+
+    prob = orc.Problem(3, n, V)
+    Uf = np.asfortranarray(U0)
+    kit = int(os.environ.get("QO_CPU_PCG_ITERS", "6"))
+    t0 = time.perf_counter()
+    X, its, st, _ = prob.solve(Uf, tol=1e-30, maxit=kit)
+    t_pcg = time.perf_counter() - t0
+    rate = N * kit / t_pcg
+    log(f"[cpu] oracle PCG {N} columns x {kit} iterations: {t_pcg:.2f} s "
+        f"({rate:.1f} column-iterations/s)")
+    P = np.asfortranarray(0.1 * Uf)
+    t0 = time.perf_counter()
+    Uh, Xm, Ym, _ = orc.predictor(prob, Uf, P, tau)
+    Unext, _, _, _ = orc.corrector(prob, Uh, P, tau)
+    prob.energy(Unext)
+    t_rest = time.perf_counter() - t0
+    log(f"[cpu] oracle non-PCG stages: {t_rest:.2f} s")
+    sec_per_step = colits_per_step / rate + t_rest
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": round(1.0 / sec_per_step, 6),
+        "unit": "steps/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"96^3 x {N}: oracle PCG {kit} iterations on all columns "
+                   f"({t_pcg:.1f} s) + one pass of the non-PCG stages ({t_rest:.1f} s); "
+                   f"scaled by {colits_per_step:.0f} column-iterations per step"),
+        "seconds_per_step": round(sec_per_step, 2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=96)
+    ap.add_argument("--N", type=int, default=256)
+    ap.add_argument("--inner-tol", type=float, default=1e-5)
+    ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+
+    def log(msg):
+        if not args.quiet:
+            print(msg, file=sys.stderr, flush=True)
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is a design, not an implementation)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2605_25149_amd import binding, inputs
+
+    binding.load_library()
+    torch.cuda.set_device(0)
+    n = (args.n,) * 3
+    N = args.N
+    ng = int(np.prod(n))
+    t0 = time.perf_counter()
+    V = inputs.gaussian_wells(n, seed=0)
+    U0 = inputs.random_block(ng, N, seed=1)
+    lam1 = lambda1_estimate(32, seed=0)
+    tau = 0.9 * lam1
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s; lambda_1(32^3) = {lam1:.6f}, "
+        f"tau = {tau:.6f}")
+    U0_dev = binding.as_block(U0)
+
+    res = {}
+    for mode in args.modes.split(","):
+        res[mode] = run_gpu(mode, V, U0_dev, n, N, tau, args.steps, args.warmup,
+                            args.inner_tol, log)
+        r = res[mode]
+        log(f"[{mode}] {args.steps} steps in {r['seconds']:.3f} s -> "
+            f"{args.steps / r['seconds']:.4f} steps/s")
+
+    head = "mixed" if "mixed" in res else next(iter(res))
+    rh = res[head]
+    value = args.steps / rh["seconds"]
+    out = {
+        "metric": METRIC,
+        "value": round(value, 6),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * rh["seconds"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"3-D {args.n}^3 Dirichlet 7-point grid (Ng={ng}), 8 Gaussian wells "
+                         f"(seed 0), N={N}, random U0 (seed 1), tau=0.9*lambda_1={tau:.5f}, "
+                         f"PCG tol 1e-10, warm starts; {head} precision"),
+            "grid": list(n), "N": N, "tau": tau, "pcg_tol": 1e-10,
+            "refine_inner_tol": args.inner_tol, "parallelism": "single GPU",
+        },
+    }
+    for mode, r in res.items():
+        its = [st["pcg_iters"] for st in r["stats"]]
+        out[f"{mode}_steps_per_s"] = round(args.steps / r["seconds"], 6)
+        out[f"{mode}_pcg_iters_per_step"] = its
+        out[f"{mode}_kernels"] = {k: {"launches": v["launches"], "ms": round(v["ms"], 3)}
+                                  for k, v in r["profile"].items() if v["launches"]}
+    if "fp64" in res and "mixed" in res:
+        out["speedup_mixed_vs_fp64"] = round(res["fp64"]["seconds"] / res["mixed"]["seconds"], 4)
+    rf = roofline_of(rh["profile"], ng)
+    if rf:
+        out["roofline"] = rf
+    if "fp64" in res:
+        rf64 = roofline_of(res["fp64"]["profile"], ng)
+        if rf64:
+            out["roofline_fp64"] = rf64
+    if not args.no_cpu_baseline:
+        ref = res["fp64"] if "fp64" in res else rh
+        colits = (ref["profile"]["sweep2_f64"]["work"] or ref["profile"]["sweep2_f32"]["work"])
+        colits_per_step = colits / args.steps
+        out["cpu_baseline"] = cpu_baseline(V, U0, n, N, tau, colits_per_step, log)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

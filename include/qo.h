@@ -160,6 +160,26 @@ qo_status qo_gram_pair(qo_handle h, const double *X, const double *Y, long ld, i
 qo_status qo_get_block(qo_handle h, int which, double *out, long ld, int on_device);
 qo_status qo_get_matrix(qo_handle h, int which, double *out);
 
+/* ---- kernel timing (for roofline measurement) ----
+ * When enabled, every launch of the kernels below is bracketed by HIP events
+ * on the handle's stream; durations are harvested at the library's own
+ * synchronisation points.  work[k] counts column-iterations for the PCG sweeps
+ * (bytes moved = bytes per point-column x Ng x work) and launches otherwise. */
+typedef enum {
+    QO_KERNEL_SWEEP1_F64 = 0, QO_KERNEL_SWEEP2_F64 = 1, QO_KERNEL_SWEEP1_F32 = 2,
+    QO_KERNEL_SWEEP2_F32 = 3, QO_KERNEL_GRAM = 4, QO_KERNEL_UPDATE = 5, QO_KERNEL_RESID = 6,
+    QO_KERNEL_COUNT = 8
+} qo_kernel_id;
+typedef struct {
+    long launches[QO_KERNEL_COUNT];
+    double ms[QO_KERNEL_COUNT];
+    double work[QO_KERNEL_COUNT];
+} qo_profile_data;
+
+/* enable != 0 turns timing on and clears the counters; 0 turns it off. */
+qo_status qo_profile(qo_handle h, int enable);
+qo_status qo_profile_get(qo_handle h, qo_profile_data *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,8 +29,9 @@ MATRICES = {"S": 0, "M": 1, "R": 2, "X": 3, "Y": 4, "O": 5, "A": 6, "B": 7}
 EXPORTS = [
     "qo_create", "qo_set_potential", "qo_set_state", "qo_get_state", "qo_step", "qo_energy",
     "qo_gram", "qo_eigenpairs", "qo_destroy", "qo_status_string", "qo_last_error", "qo_apply",
-    "qo_solve", "qo_gram_pair", "qo_get_block", "qo_get_matrix",
+    "qo_solve", "qo_gram_pair", "qo_get_block", "qo_get_matrix", "qo_profile", "qo_profile_get",
 ]
+KERNELS = ["sweep1_f64", "sweep2_f64", "sweep1_f32", "sweep2_f32", "gram", "update", "resid"]
 
 
 class QoConfig(ctypes.Structure):
@@ -60,6 +61,11 @@ class QoStepStats(ctypes.Structure):
             "energy_rose": bool(self.energy_rose), "step_index": self.step_index,
             "t_phase_ms": tuple(self.t_phase_ms),
         }
+
+
+class QoProfileData(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_long * 8), ("ms", ctypes.c_double * 8),
+                ("work", ctypes.c_double * 8)]
 
 
 class QOError(RuntimeError):
@@ -99,6 +105,8 @@ def load_library(path: str = LIB_PATH):
         "qo_gram_pair": ([H, vp, vp, ctypes.c_long, ctypes.c_int, vp], ctypes.c_int),
         "qo_get_block": ([H, ctypes.c_int, vp, ctypes.c_long, ctypes.c_int], ctypes.c_int),
         "qo_get_matrix": ([H, ctypes.c_int, vp], ctypes.c_int),
+        "qo_profile": ([H, ctypes.c_int], ctypes.c_int),
+        "qo_profile_get": ([H, ctypes.POINTER(QoProfileData)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -312,6 +320,16 @@ class Solver:
         self._chk(self.lib.qo_get_block(self.h, BLOCKS[name], ctypes.c_void_p(out.data_ptr()),
                                         self.ng, 1))
         return out
+
+    def profile(self, enable=True):
+        """Turn per-kernel event timing on (clearing counters) or off."""
+        self._chk(self.lib.qo_profile(self.h, 1 if enable else 0))
+
+    def profile_data(self):
+        d = QoProfileData()
+        self._chk(self.lib.qo_profile_get(self.h, ctypes.byref(d)))
+        return {k: {"launches": d.launches[i], "ms": d.ms[i], "work": d.work[i]}
+                for i, k in enumerate(KERNELS)}
 
     def get_matrix(self, name):
         M = np.zeros((self.N, self.N), order="F")

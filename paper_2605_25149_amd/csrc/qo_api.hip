@@ -85,6 +85,15 @@ struct qo_ctx {
     hipEvent_t ev[9] = {};
     bool ev_ok = false;
     std::vector<int> h_its;
+    // kernel timing
+    struct Pend {
+        int kid;
+        hipEvent_t a, b;
+    };
+    bool prof = false;
+    std::vector<hipEvent_t> evpool;
+    std::vector<Pend> pend;
+    qo_profile_data pdata{};
 };
 
 namespace {
@@ -190,6 +199,51 @@ void setup_grid(qo_ctx *c) {
 
 // ----------------------------------------------------------------- solves
 
+// ---- kernel timing
+hipEvent_t prof_event(qo_ctx *c) {
+    if (!c->evpool.empty()) {
+        hipEvent_t e = c->evpool.back();
+        c->evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+hipEvent_t prof_begin(qo_ctx *c) {
+    if (!c->prof) return nullptr;
+    hipEvent_t a = prof_event(c);
+    if (a) (void)hipEventRecord(a, c->st);
+    return a;
+}
+
+void prof_end(qo_ctx *c, int kid, hipEvent_t a) {
+    if (!c->prof || !a) return;
+    hipEvent_t b = prof_event(c);
+    if (!b) {
+        c->evpool.push_back(a);
+        return;
+    }
+    (void)hipEventRecord(b, c->st);
+    c->pend.push_back({kid, a, b});
+}
+
+// call after the stream has been synchronised
+void prof_harvest(qo_ctx *c) {
+    for (auto &p : c->pend) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->pdata.ms[p.kid] += ms;
+            c->pdata.launches[p.kid] += 1;
+            if (p.kid >= QO_KERNEL_GRAM) c->pdata.work[p.kid] += 1.0;
+        }
+        c->evpool.push_back(p.a);
+        c->evpool.push_back(p.b);
+    }
+    c->pend.clear();
+}
+
 qo_status check_poll_err(qo_ctx *c, int code, int col, const char *what) {
     if (code == 5)
         return fail(c, QO_ERR_NOT_SPD,
@@ -215,15 +269,21 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
     T *pbuf[2] = {P0, P1};
     const int check = c->cfg.pcg_check;
     const int maxit = c->cfg.pcg_maxit;
+    const bool f64 = sizeof(T) == 8;
+    const int k1 = f64 ? QO_KERNEL_SWEEP1_F64 : QO_KERNEL_SWEEP1_F32;
+    const int k2 = f64 ? QO_KERNEL_SWEEP2_F64 : QO_KERNEL_SWEEP2_F32;
     for (int k = 0;; ++k) {
+        hipEvent_t ea = prof_begin(c);
         HIPC(c, launch_pcg_sweep1<T>(g, vs, dinv, R, pbuf[(k + 1) & 1], pbuf[k & 1], c->ld, ncols,
                                      k, tol, mask, s, st));
+        prof_end(c, k1, ea);
         if (k % check == 0 || k >= maxit) {
             HIPC(c, hipMemcpyAsync(c->h_poll, s.active + (k & 1) * ncols, sizeof(int) * ncols,
                                    hipMemcpyDeviceToHost, st));
             HIPC(c, hipMemcpyAsync(c->h_poll + ncols, s.err, 2 * sizeof(int),
                                    hipMemcpyDeviceToHost, st));
             HIPC(c, hipStreamSynchronize(st));
+            prof_harvest(c);
             if (c->h_poll[ncols]) return check_poll_err(c, c->h_poll[ncols], c->h_poll[ncols + 1], what);
             int nact = 0;
             for (int j = 0; j < ncols; ++j) nact += c->h_poll[j] ? 1 : 0;
@@ -232,11 +292,22 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
                 return fail(c, QO_ERR_PCG_NOCONV, "%s: %d of %d columns not converged after %d "
                             "PCG iterations (tol %.3g)", what, nact, ncols, maxit, tol);
         }
+        hipEvent_t eb = prof_begin(c);
         HIPC(c, launch_pcg_sweep2<T>(g, vs, dinv, pbuf[k & 1], X, R, c->ld, ncols, k, s, st));
+        prof_end(c, k2, eb);
     }
     HIPC(c, hipMemcpyAsync(c->h_poll, s.its, sizeof(int) * ncols, hipMemcpyDeviceToHost, st));
     HIPC(c, hipStreamSynchronize(st));
-    for (int j = 0; j < ncols; ++j) its_out[j] = c->h_poll[j];
+    prof_harvest(c);
+    double colits = 0.0;
+    for (int j = 0; j < ncols; ++j) {
+        its_out[j] = c->h_poll[j];
+        colits += c->h_poll[j];
+    }
+    if (c->prof) {
+        c->pdata.work[k1] += colits;
+        c->pdata.work[k2] += colits;
+    }
     return QO_OK;
 }
 
@@ -260,12 +331,15 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
     for (int round = 0;; ++round) {
         int init_err[2] = {0, INT_MAX};
         HIPC(c, hipMemcpyAsync(c->ps.err, init_err, sizeof init_err, hipMemcpyHostToDevice, st));
+        hipEvent_t er = prof_begin(c);
         HIPC(c, launch_resid(g, c->vs, B, X, c->ld, c->r32, c->ld, ncols, nullptr, c->part, st));
+        prof_end(c, QO_KERNEL_RESID, er);
         HIPC(c, launch_colsum(c->part + qs, g.tiles(), ncols, 2, qs, c->colsums, st));
         HIPC(c, launch_refine_mask(c->colsums, ncols, tol, c->mask, c->nact, c->ps.err, st));
         HIPC(c, hipMemcpyAsync(c->h_poll, c->nact, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPC(c, hipMemcpyAsync(c->h_poll + 1, c->ps.err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPC(c, hipStreamSynchronize(st));
+        prof_harvest(c);
         if (c->h_poll[1]) return check_poll_err(c, c->h_poll[1], c->h_poll[2], what);
         if (c->h_poll[0] == 0) {
             *rounds = round;
@@ -283,10 +357,20 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
 }
 
 qo_status gram(qo_ctx *c, const double *X, const double *Y, long ld, int n, double *G) {
+    hipEvent_t e = prof_begin(c);
     if (c->mixed)
         HIPC(c, launch_gram_bf16(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G, c->st));
     else
         HIPC(c, launch_gram_f64(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G, c->st));
+    prof_end(c, QO_KERNEL_GRAM, e);
+    return QO_OK;
+}
+
+qo_status tsgemm(qo_ctx *c, double *Out, const double *C0, const double *A, const double *Xr,
+                 const double *Bm, const double *Yr) {
+    hipEvent_t e = prof_begin(c);
+    HIPC(c, launch_tsgemm(Out, c->ld, C0, A, Xr, Bm, Yr, c->ld, c->ng, c->N, c->st));
+    prof_end(c, QO_KERNEL_UPDATE, e);
     return QO_OK;
 }
 
@@ -388,9 +472,8 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats) {
     HIPC(c, nn_axpby(mp(c, MP_ZR), N, 0.0, nullptr, N, 1.0, mp(c, MP_Z), N, true, 0.0, N, N, st));
     QOC(check_status(c, "predictor N x N solve"));
     rec(c, 3);
-    HIPC(c, launch_tsgemm(c->Uh, ld, nullptr, c->U, mp(c, MP_XR), P, mp(c, MP_YR), ld, c->ng, N, st));
-    if (warm)
-        HIPC(c, launch_tsgemm(Q, ld, nullptr, P, mp(c, MP_ZR), nullptr, nullptr, ld, c->ng, N, st));
+    QOC(tsgemm(c, c->Uh, nullptr, c->U, mp(c, MP_XR), P, mp(c, MP_YR)));
+    if (warm) QOC(tsgemm(c, Q, nullptr, P, mp(c, MP_ZR), nullptr, nullptr));
     rec(c, 4);
     QOC(solve_block(c, c->Uh, Q, N, warm, itsQ.data(), &rQ, "solve G U_hat"));
     rec(c, 5);
@@ -400,7 +483,7 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats) {
     HIPC(c, nn_axpby(mp(c, MP_O), N, 0.5, c->G2, N2, 0.5, c->G2, N2, true, -1.0, N, N, st));
     HIPC(c, nn_axpby(mp(c, MP_OR), N, -tau, mp(c, MP_O), N, 0.0, nullptr, N, false, 0.0, N, N, st));
     HIPC(c, nn_fro(mp(c, MP_O), N, N, c->dscal + 1, st));
-    HIPC(c, launch_tsgemm(c->U, ld, c->Uh, nullptr, nullptr, Q, mp(c, MP_OR), ld, c->ng, N, st));
+    QOC(tsgemm(c, c->U, c->Uh, nullptr, nullptr, Q, mp(c, MP_OR)));
     rec(c, 7);
     // the state has moved: commit bookkeeping before the (non-failing) diagnostics
     c->lastP = P;
@@ -413,6 +496,7 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats) {
     rec(c, 8);
     HIPC(c, hipMemcpyAsync(c->h_scal, c->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPC(c, hipStreamSynchronize(st));
+    prof_harvest(c);
     if (stats) {
         memset(stats, 0, sizeof *stats);
         stats->energy_shifted = Es;
@@ -520,6 +604,11 @@ qo_status qo_destroy(qo_handle h) {
     if (h->h_scal) (void)hipHostFree(h->h_scal);
     if (h->ev_ok)
         for (auto &e : h->ev) (void)hipEventDestroy(e);
+    for (auto &p : h->pend) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : h->evpool) (void)hipEventDestroy(e);
     delete h;
     return QO_OK;
 }
@@ -853,6 +942,23 @@ qo_status qo_get_matrix(qo_handle h, int which, double *out) {
     HIPC(h, hipMemcpy2DAsync(out, N * sizeof(double), src, lds * sizeof(double),
                              N * sizeof(double), N, hipMemcpyDeviceToHost, h->st));
     HIPC(h, hipStreamSynchronize(h->st));
+    return QO_OK;
+}
+
+qo_status qo_profile(qo_handle h, int enable) {
+    if (!h) return QO_ERR_ARG;
+    HIPC(h, hipStreamSynchronize(h->st));
+    prof_harvest(h);
+    h->prof = enable != 0;
+    memset(&h->pdata, 0, sizeof h->pdata);
+    return QO_OK;
+}
+
+qo_status qo_profile_get(qo_handle h, qo_profile_data *out) {
+    if (!h || !out) return h ? fail(h, QO_ERR_ARG, "null output") : QO_ERR_ARG;
+    HIPC(h, hipStreamSynchronize(h->st));
+    prof_harvest(h);
+    *out = h->pdata;
     return QO_OK;
 }
 

@@ -70,6 +70,7 @@ struct qo_ctx {
     double *sortwork = nullptr;
     PcgState ps{};
     int *mask = nullptr, *nact = nullptr, *dstatus = nullptr;
+    double *coltol = nullptr;
     // pinned host
     int *h_poll = nullptr;
     double *h_scal = nullptr;
@@ -257,11 +258,12 @@ qo_status check_poll_err(qo_ctx *c, int code, int col, const char *what) {
 // Jacobi-PCG on all columns of B (ld c->ld) into X, precision T.
 template <typename T>
 qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *P0, T *P1,
-              int ncols, int use_x0, double tol, const int *mask, int *its_out,
-              const char *what) {
+              int ncols, int use_x0, double tol, const int *mask, const double *coltol,
+              int *its_out, const char *what) {
     const Grid &g = c->g;
     hipStream_t st = c->st;
     PcgState s = c->ps;
+    s.coltol = coltol;
     HIPC(c, hipMemsetAsync(s.its, 0, sizeof(int) * ncols, st));
     int init_err[2] = {0, INT_MAX};
     HIPC(c, hipMemcpyAsync(s.err, init_err, sizeof init_err, hipMemcpyHostToDevice, st));
@@ -318,7 +320,7 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
     if (!c->mixed) {
         *rounds = 1;
         return pcg<double>(c, c->vs, c->dinv, B, X, c->r, c->pa, c->pb, ncols, use_x0, tol,
-                           nullptr, its, what);
+                           nullptr, nullptr, its, what);
     }
     // FP64 iterative refinement around FP32 PCG
     hipStream_t st = c->st;
@@ -335,7 +337,8 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
         HIPC(c, launch_resid(g, c->vs, B, X, c->ld, c->r32, c->ld, ncols, nullptr, c->part, st));
         prof_end(c, QO_KERNEL_RESID, er);
         HIPC(c, launch_colsum(c->part + qs, g.tiles(), ncols, 2, qs, c->colsums, st));
-        HIPC(c, launch_refine_mask(c->colsums, ncols, tol, c->mask, c->nact, c->ps.err, st));
+        HIPC(c, launch_refine_mask(c->colsums, ncols, tol, c->cfg.refine_inner_tol, c->mask,
+                                   c->coltol, c->nact, c->ps.err, st));
         HIPC(c, hipMemcpyAsync(c->h_poll, c->nact, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPC(c, hipMemcpyAsync(c->h_poll + 1, c->ps.err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPC(c, hipStreamSynchronize(st));
@@ -349,7 +352,7 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
             return fail(c, QO_ERR_PCG_NOCONV, "%s: refinement did not reach tol %.3g in %d rounds",
                         what, tol, max_rounds);
         QOC(pcg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->rr32, c->pa32, c->pb32, ncols, 0,
-                       c->cfg.refine_inner_tol, c->mask, inner.data(), what));
+                       c->cfg.refine_inner_tol, c->mask, c->coltol, inner.data(), what));
         for (int j = 0; j < ncols; ++j) its[j] += inner[j];
         HIPC(c, launch_refine_axpy(X, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, st));
     }
@@ -684,6 +687,7 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
     A(&h->ps.bb, (size_t)N);
     A(&h->ps.err, 2);
     A(&h->mask, (size_t)N);
+    A(&h->coltol, (size_t)N);
     A(&h->nact, 1);
     A(&h->dstatus, 1);
     h->ps.part = h->part;

@@ -31,6 +31,7 @@ struct PcgState {
     double *bb;     // [ncap]
     double *part;   // partial sums [4][ncap * tiles]
     int *err;       // [2]: error code, first failing column
+    const double *coltol;  // optional per-column relative tolerance (else the scalar tol)
 };
 
 // ---- stencil family (qo_stencil.hip) ----
@@ -65,9 +66,11 @@ hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long 
 // x += d (FP64 += FP32) for columns with mask != 0.
 hipError_t launch_refine_axpy(double *X, long ld, const float *D, long ld32, long ng, int ncols,
                               const int *mask, hipStream_t st);
-// mask[c] = (sqrt(rr[c]) > tol * sqrt(bb[c])); counts into *nactive (device int)
-hipError_t launch_refine_mask(const double *sums, int ncols, double tol, int *mask,
-                              int *nactive, int *err, hipStream_t st);
+// mask[c] = (sqrt(rr[c]) > tol * sqrt(bb[c])); counts into *nactive (device int);
+// coltol[c] (may be null): inner FP32 tolerance for the next round
+hipError_t launch_refine_mask(const double *sums, int ncols, double tol, double tol_in,
+                              int *mask, double *coltol, int *nactive, int *err,
+                              hipStream_t st);
 
 // ---- Gram (qo_gram.hip) ----
 // G (2n x 2n, col-major, ld 2n) = w * [X Y]^T [X Y]; part: workspace of

@@ -60,12 +60,22 @@ __device__ __forceinline__ double col_sum(const double *__restrict__ part, int c
     return s[0];
 }
 
-// The streaming engine.  opnd(i) returns the stencil operand at in-column index
-// i; epi(s, i, centre, Hv) consumes the operator value at each own point.
-template <typename T, int PPT, class Opnd, class Epi>
+// The streaming engine.
+//
+//   Ld: stencil operand.   Ld::Raw raw = ld.load(i);  T v = ld.make(raw)
+//   Ep: per-point epilogue. Ep::Raw e = ep.load(i);   ep(s, i, centre, Hv, e)
+//
+// Software pipeline over z-planes: while plane z is computed, the raw global
+// loads of the operand of plane z+3 (own points), of the halo rows of plane
+// z+2, and of V+sigma and the epilogue inputs of plane z+1 are in flight.  The
+// per-plane barrier waits on LDS only, so those loads overlap the barrier and
+// the next plane's arithmetic instead of stalling each plane.
+template <typename T, int PPT, class Ld, class Ep>
 __device__ __forceinline__ void engine(const Grid &g, int band, int zc,
-                                       const T *__restrict__ vs, Opnd &opnd, Epi &epi,
+                                       const T *__restrict__ vs, Ld &ld, Ep &ep,
                                        T *__restrict__ lds) {
+    using LR = typename Ld::Raw;
+    using ER = typename Ep::Raw;
     const int tid = threadIdx.x;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int y0 = band * g.TY;
@@ -76,8 +86,10 @@ __device__ __forceinline__ void engine(const Grid &g, int band, int zc,
     const long plane = (long)nx * ny;
     const int ldsz = (g.TY + 2) * nx;
     const bool has_lo = y0 > 0, has_hi = (y0 + ty) < ny;
+    const bool hown = tid < nx;  // this thread owns halo column tid (prefetched)
     const T kap = (T)g.kappa, c0 = (T)g.c0;
     const T ihx2 = (T)g.ihx2, ihy2 = (T)g.ihy2, ihz2 = (T)g.ihz2;
+    const long lo_off = -(long)nx, hi_off = (long)ty * nx;
 
     int xs[PPT];
     bool val[PPT];
@@ -87,21 +99,35 @@ __device__ __forceinline__ void engine(const Grid &g, int band, int zc,
         val[s] = t < npts;
         xs[s] = val[s] ? t % nx : 0;
     }
-    T om[PPT], oc[PPT], op[PPT];
-    {
-        const long b0 = (long)z0 * plane + (long)y0 * nx;
+    T om[PPT], oc[PPT], op[PPT], vsr[PPT];
+    LR rq[PPT];
+    ER er[PPT];
+    LR hlo = Ld::zero(), hhi = Ld::zero();
+    const long b0 = (long)z0 * plane + (long)y0 * nx;
+    // prologue: operands of planes z0-1, z0 (with halo rows), z0+1
 #pragma unroll
-        for (int s = 0; s < PPT; ++s) {
-            const int t = tid + s * kThreads;
-            om[s] = (val[s] && z0 > 0) ? opnd(b0 - plane + t) : T(0);
-            oc[s] = val[s] ? opnd(b0 + t) : T(0);
-            op[s] = (val[s] && z0 + 1 < nz) ? opnd(b0 + plane + t) : T(0);
-            if (val[s]) lds[nx + t] = oc[s];
-        }
-        for (int hh = tid; hh < nx; hh += kThreads) {
-            lds[hh] = has_lo ? opnd(b0 - nx + hh) : T(0);
-            lds[(ty + 1) * nx + hh] = has_hi ? opnd(b0 + (long)ty * nx + hh) : T(0);
-        }
+    for (int s = 0; s < PPT; ++s) {
+        const int t = tid + s * kThreads;
+        om[s] = (val[s] && z0 > 0) ? ld.make(ld.load(b0 - plane + t)) : T(0);
+        oc[s] = val[s] ? ld.make(ld.load(b0 + t)) : T(0);
+        op[s] = (val[s] && z0 + 1 < nz) ? ld.make(ld.load(b0 + plane + t)) : T(0);
+        if (val[s]) lds[nx + t] = oc[s];
+    }
+    for (int hh = tid; hh < nx; hh += kThreads) {
+        lds[hh] = has_lo ? ld.make(ld.load(b0 + lo_off + hh)) : T(0);
+        lds[(ty + 1) * nx + hh] = has_hi ? ld.make(ld.load(b0 + hi_off + hh)) : T(0);
+    }
+    // prefetch for the first iteration
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+        const int t = tid + s * kThreads;
+        vsr[s] = val[s] ? vs[b0 + t] : T(0);
+        er[s] = val[s] ? ep.load(b0 + t) : Ep::zero();
+        rq[s] = (val[s] && z0 + 2 < nz && z0 + 1 < z1) ? ld.load(b0 + 2 * plane + t) : Ld::zero();
+    }
+    if (hown && z0 + 1 < z1) {
+        if (has_lo) hlo = ld.load(b0 + plane + lo_off + tid);
+        if (has_hi) hhi = ld.load(b0 + plane + hi_off + tid);
     }
     __syncthreads();
     for (int z = z0; z < z1; ++z) {
@@ -117,10 +143,9 @@ __device__ __forceinline__ void engine(const Grid &g, int band, int zc,
             const T xp = x < nx - 1 ? L[nx + t + 1] : T(0);
             const T ym = L[t];
             const T yp = L[t + 2 * nx];
-            const long gi = b + t;
-            const T hv = (c0 + vs[gi]) * oc[s] -
+            const T hv = (c0 + vsr[s]) * oc[s] -
                          kap * (ihx2 * (xm + xp) + ihy2 * (ym + yp) + ihz2 * (om[s] + op[s]));
-            epi(s, gi, oc[s], hv);
+            ep(s, b + t, oc[s], hv, er[s]);
         }
         if (z + 1 < z1) {
             T *__restrict__ Ln = lds + (cur ^ 1) * ldsz;
@@ -130,21 +155,75 @@ __device__ __forceinline__ void engine(const Grid &g, int band, int zc,
                 const int t = tid + s * kThreads;
                 if (val[s]) Ln[nx + t] = op[s];
             }
-            for (int hh = tid; hh < nx; hh += kThreads) {
-                Ln[hh] = has_lo ? opnd(bn - nx + hh) : T(0);
-                Ln[(ty + 1) * nx + hh] = has_hi ? opnd(bn + (long)ty * nx + hh) : T(0);
+            if (hown) {
+                Ln[tid] = has_lo ? ld.make(hlo) : T(0);
+                Ln[(ty + 1) * nx + tid] = has_hi ? ld.make(hhi) : T(0);
+            }
+            for (int hh = tid + kThreads; hh < nx; hh += kThreads) {  // nx > 256 only
+                Ln[hh] = has_lo ? ld.make(ld.load(bn + lo_off + hh)) : T(0);
+                Ln[(ty + 1) * nx + hh] = has_hi ? ld.make(ld.load(bn + hi_off + hh)) : T(0);
             }
 #pragma unroll
             for (int s = 0; s < PPT; ++s) {
                 const int t = tid + s * kThreads;
                 om[s] = oc[s];
                 oc[s] = op[s];
-                op[s] = (val[s] && z + 2 < nz) ? opnd(bn + plane + t) : T(0);
+                op[s] = (val[s] && z + 2 < nz) ? ld.make(rq[s]) : T(0);
+            }
+            // issue the loads the next iterations consume
+#pragma unroll
+            for (int s = 0; s < PPT; ++s) {
+                const int t = tid + s * kThreads;
+                vsr[s] = val[s] ? vs[bn + t] : T(0);
+                er[s] = val[s] ? ep.load(bn + t) : Ep::zero();
+                rq[s] = (val[s] && z + 3 < nz && z + 2 < z1) ? ld.load(bn + 2 * plane + t)
+                                                              : Ld::zero();
+            }
+            if (hown && z + 2 < z1) {
+                if (has_lo) hlo = ld.load(bn + plane + lo_off + tid);
+                if (has_hi) hhi = ld.load(bn + plane + hi_off + tid);
             }
         }
         __syncthreads();
     }
 }
+
+// ---- operand loaders and epilogue building blocks
+
+template <typename T>
+struct LdPlain {  // operand x[i]
+    struct Raw { T x; };
+    const T *__restrict__ x;
+    __device__ static Raw zero() { return {T(0)}; }
+    __device__ Raw load(long i) const { return {x[i]}; }
+    __device__ T make(const Raw &r) const { return r.x; }
+};
+
+template <typename T>
+struct LdZero {  // operand 0 (no loads)
+    struct Raw {};
+    __device__ static Raw zero() { return {}; }
+    __device__ Raw load(long) const { return {}; }
+    __device__ T make(const Raw &) const { return T(0); }
+};
+
+template <typename T>
+struct LdPcgP {  // p = D r + beta p_old  (beta = 0: p = D r, p_old not read)
+    struct Raw { T d, r, p; };
+    const T *__restrict__ dinv;
+    const T *__restrict__ r;
+    const T *__restrict__ po;
+    T beta;
+    bool first;
+    __device__ static Raw zero() { return {T(0), T(0), T(0)}; }
+    __device__ Raw load(long i) const { return {dinv[i], r[i], first ? T(0) : po[i]}; }
+    __device__ T make(const Raw &a) const {
+        const T z = a.d * a.r;
+        return first ? z : z + beta * a.p;
+    }
+};
+
+struct NoRaw {};
 
 __device__ __forceinline__ void tile_of(const Grid &g, int &col, int &tile, int &band, int &zc) {
     const int tiles = g.tiles();
@@ -168,11 +247,15 @@ __global__ __launch_bounds__(kThreads) void k_apply(Grid g, const double *__rest
                                                     double *__restrict__ Y, long ld) {
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
-    const double *x = X + (long)col * ld;
-    double *y = Y + (long)col * ld;
-    auto opnd = [&](long i) { return x[i]; };
-    auto epi = [&](int, long i, double, double hv) { y[i] = hv; };
-    engine<double, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<double>());
+    struct Ep {
+        using Raw = NoRaw;
+        double *__restrict__ y;
+        __device__ static Raw zero() { return {}; }
+        __device__ Raw load(long) const { return {}; }
+        __device__ void operator()(int, long i, double, double hv, const Raw &) { y[i] = hv; }
+    } ep{Y + (long)col * ld};
+    LdPlain<double> l{X + (long)col * ld};
+    engine<double, PPT>(g, band, zc, vs, l, ep, lds_ptr<double>());
 }
 
 template <int PPT>
@@ -182,19 +265,23 @@ __global__ __launch_bounds__(kThreads) void k_quad(Grid g, const double *__restr
     __shared__ Red red;
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
-    const double *x = X + (long)col * ld;
-    double acc[2] = {0.0, 0.0};
-    auto opnd = [&](long i) { return x[i]; };
-    auto epi = [&](int, long, double c, double hv) {
-        acc[0] += c * hv;
-        acc[1] += c * c;
-    };
-    engine<double, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<double>());
-    block_sums<2>(acc, red);
+    struct Ep {
+        using Raw = NoRaw;
+        double acc[2];
+        __device__ static Raw zero() { return {}; }
+        __device__ Raw load(long) const { return {}; }
+        __device__ void operator()(int, long, double c, double hv, const Raw &) {
+            acc[0] += c * hv;
+            acc[1] += c * c;
+        }
+    } ep{{0.0, 0.0}};
+    LdPlain<double> l{X + (long)col * ld};
+    engine<double, PPT>(g, band, zc, vs, l, ep, lds_ptr<double>());
+    block_sums<2>(ep.acc, red);
     if (threadIdx.x == 0) {
         const long o = (long)col * g.tiles() + tile;
-        part[o] = acc[0];
-        part[qs + o] = acc[1];
+        part[o] = ep.acc[0];
+        part[qs + o] = ep.acc[1];
     }
 }
 
@@ -213,27 +300,57 @@ __global__ __launch_bounds__(kThreads) void k_resid(Grid g, const double *__rest
         if (threadIdx.x == 0) part[qs + o] = part[2 * qs + o] = 0.0;
         return;
     }
-    const double *x = X + (long)col * ld;
-    const double *b = B + (long)col * ld;
-    float *r32 = R32 + (long)col * ld32;
-    double acc[2] = {0.0, 0.0};
-    auto opnd = [&](long i) { return x[i]; };
-    auto epi = [&](int, long i, double, double hv) {
-        const double bi = b[i];
-        const double r = bi - hv;
-        r32[i] = (float)r;
-        acc[0] += r * r;
-        acc[1] += bi * bi;
-    };
-    engine<double, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<double>());
-    block_sums<2>(acc, red);
+    struct Ep {
+        struct Raw { double b; };
+        const double *__restrict__ b;
+        float *__restrict__ r32;
+        double acc[2];
+        __device__ static Raw zero() { return {0.0}; }
+        __device__ Raw load(long i) const { return {b[i]}; }
+        __device__ void operator()(int, long i, double, double hv, const Raw &e) {
+            const double r = e.b - hv;
+            r32[i] = (float)r;
+            acc[0] += r * r;
+            acc[1] += e.b * e.b;
+        }
+    } ep{B + (long)col * ld, R32 + (long)col * ld32, {0.0, 0.0}};
+    LdPlain<double> l{X + (long)col * ld};
+    engine<double, PPT>(g, band, zc, vs, l, ep, lds_ptr<double>());
+    block_sums<2>(ep.acc, red);
     if (threadIdx.x == 0) {
-        part[qs + o] = acc[0];
-        part[2 * qs + o] = acc[1];
+        part[qs + o] = ep.acc[0];
+        part[2 * qs + o] = ep.acc[1];
     }
 }
 
 // r = b - H x0 (or r = b, x = 0); partials rz (q0), rr (q1), bb (q2)
+template <typename T>
+struct EpInit {
+    struct Raw { T b, d; };
+    const T *__restrict__ b;
+    const T *__restrict__ dinv;
+    T *__restrict__ x;
+    T *__restrict__ r;
+    bool use_x0;
+    double acc[3];
+    __device__ static Raw zero() { return {T(0), T(0)}; }
+    __device__ Raw load(long i) const { return {b[i], dinv[i]}; }
+    __device__ void operator()(int, long i, T, T hv, const Raw &e) {
+        T ri;
+        if (use_x0) {
+            ri = e.b - hv;
+        } else {
+            ri = e.b;
+            x[i] = T(0);
+        }
+        r[i] = ri;
+        const double rd = (double)ri;
+        acc[0] += rd * (double)(e.d * ri);
+        acc[1] += rd * rd;
+        acc[2] += (double)e.b * (double)e.b;
+    }
+};
+
 template <typename T, int PPT>
 __global__ __launch_bounds__(kThreads) void k_pcg_init(Grid g, const T *__restrict__ vs,
                                                        const T *__restrict__ dinv,
@@ -244,33 +361,21 @@ __global__ __launch_bounds__(kThreads) void k_pcg_init(Grid g, const T *__restri
     __shared__ Red red;
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
-    T *x = X + (long)col * ld;
-    const T *b = B + (long)col * ld;
-    T *r = R + (long)col * ld;
-    double acc[3] = {0.0, 0.0, 0.0};
-    auto opnd = [&](long i) { return use_x0 ? x[i] : T(0); };
-    auto epi = [&](int, long i, T, T hv) {
-        const T bi = b[i];
-        T ri;
-        if (use_x0) {
-            ri = bi - hv;
-        } else {
-            ri = bi;
-            x[i] = T(0);
-        }
-        r[i] = ri;
-        const double rd = (double)ri;
-        acc[0] += rd * (double)(dinv[i] * ri);
-        acc[1] += rd * rd;
-        acc[2] += (double)bi * (double)bi;
-    };
-    engine<T, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<T>());
-    block_sums<3>(acc, red);
+    EpInit<T> ep{B + (long)col * ld, dinv, X + (long)col * ld, R + (long)col * ld,
+                 use_x0 != 0, {0.0, 0.0, 0.0}};
+    if (use_x0) {
+        LdPlain<T> l{X + (long)col * ld};
+        engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
+    } else {
+        LdZero<T> l;
+        engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
+    }
+    block_sums<3>(ep.acc, red);
     if (threadIdx.x == 0) {
         const long o = (long)col * g.tiles() + tile;
-        part[o] = acc[0];
-        part[qs + o] = acc[1];
-        part[2 * qs + o] = acc[2];
+        part[o] = ep.acc[0];
+        part[qs + o] = ep.acc[1];
+        part[2 * qs + o] = ep.acc[2];
     }
 }
 
@@ -304,10 +409,11 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__rest
     } else {
         bb = s.bb[col];
     }
+    const double ctol = s.coltol ? s.coltol[col] : tol;
     if (threadIdx.x == 0) {
         int flag = 0;  // 0 run, 1 converged, 2 non-finite
         if (!isfinite(rz) || !isfinite(rr) || !isfinite(bb)) flag = 2;
-        else if (sqrt(rr) <= tol * sqrt(bb)) flag = 1;
+        else if (sqrt(rr) <= ctol * sqrt(bb)) flag = 1;
         sh_flag = flag;
         if (lead) {
             s.its[col] = k;
@@ -322,22 +428,42 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__rest
     __syncthreads();
     if (sh_flag != 0) return;
     const T beta = (k == 0) ? T(0) : (T)(rz / s.rho[prv * ncols + col]);
-    const T *r = R + (long)col * ld;
-    const T *po = Pold + (long)col * ld;
-    T *pn = Pnew + (long)col * ld;
-    double acc[1] = {0.0};
-    auto opnd = [&](long i) {
-        const T z = dinv[i] * r[i];
-        return k == 0 ? z : z + beta * po[i];
-    };
-    auto epi = [&](int, long i, T c, T hv) {
-        pn[i] = c;
-        acc[0] += (double)c * (double)hv;
-    };
-    engine<T, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<T>());
-    block_sums<1>(acc, red);
-    if (threadIdx.x == 0) s.part[3 * qs + (long)col * tiles + tile] = acc[0];
+    LdPcgP<T> l{dinv, R + (long)col * ld, Pold + (long)col * ld, beta, k == 0};
+    struct Ep {
+        using Raw = NoRaw;
+        T *__restrict__ pn;
+        double acc[1];
+        __device__ static Raw zero() { return {}; }
+        __device__ Raw load(long) const { return {}; }
+        __device__ void operator()(int, long i, T c, T hv, const Raw &) {
+            pn[i] = c;
+            acc[0] += (double)c * (double)hv;
+        }
+    } ep{Pnew + (long)col * ld, {0.0}};
+    engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
+    block_sums<1>(ep.acc, red);
+    if (threadIdx.x == 0) s.part[3 * qs + (long)col * tiles + tile] = ep.acc[0];
 }
+
+template <typename T>
+struct EpSweep2 {
+    struct Raw { T x, r, d; };
+    T *__restrict__ x;
+    T *__restrict__ r;
+    const T *__restrict__ dinv;
+    T alpha;
+    double acc[2];
+    __device__ static Raw zero() { return {T(0), T(0), T(0)}; }
+    __device__ Raw load(long i) const { return {x[i], r[i], dinv[i]}; }
+    __device__ void operator()(int, long i, T c, T hv, const Raw &e) {
+        x[i] = e.x + alpha * c;
+        const T ri = e.r - alpha * hv;
+        r[i] = ri;
+        const double rd = (double)ri;
+        acc[0] += rd * (double)(e.d * ri);
+        acc[1] += rd * rd;
+    }
+};
 
 template <typename T, int PPT>
 __global__ __launch_bounds__(kThreads) void k_pcg_sweep2(Grid g, const T *__restrict__ vs,
@@ -367,25 +493,14 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep2(Grid g, const T *__rest
     __syncthreads();
     if (sh_flag) return;
     const T alpha = (T)(s.rho[cur * ncols + col] / gam);
-    const T *p = Pn + (long)col * ld;
-    T *x = X + (long)col * ld;
-    T *r = R + (long)col * ld;
-    double acc[2] = {0.0, 0.0};
-    auto opnd = [&](long i) { return p[i]; };
-    auto epi = [&](int, long i, T c, T hv) {
-        x[i] += alpha * c;
-        const T ri = r[i] - alpha * hv;
-        r[i] = ri;
-        const double rd = (double)ri;
-        acc[0] += rd * (double)(dinv[i] * ri);
-        acc[1] += rd * rd;
-    };
-    engine<T, PPT>(g, band, zc, vs, opnd, epi, lds_ptr<T>());
-    block_sums<2>(acc, red);
+    LdPlain<T> l{Pn + (long)col * ld};
+    EpSweep2<T> ep{X + (long)col * ld, R + (long)col * ld, dinv, alpha, {0.0, 0.0}};
+    engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
+    block_sums<2>(ep.acc, red);
     if (threadIdx.x == 0) {
         const long o = (long)col * tiles + tile;
-        s.part[o] = acc[0];
-        s.part[qs + o] = acc[1];
+        s.part[o] = ep.acc[0];
+        s.part[qs + o] = ep.acc[1];
     }
 }
 
@@ -410,9 +525,12 @@ __global__ void k_refine_axpy(double *__restrict__ X, long ld, const float *__re
         x[i] += (double)d[i];
 }
 
-// sums: [0..ncols) = rr, [ncols..2ncols) = bb
+// sums: [0..ncols) = rr, [ncols..2ncols) = bb.  For active columns the inner
+// tolerance is what the column still needs (with a safety factor), but no
+// tighter than the FP32 floor tol_in: coltol = clamp(0.3 tol ||b|| / ||r||, tol_in, 0.5).
 __global__ void k_refine_mask(const double *__restrict__ sums, int ncols, double tol,
-                              int *__restrict__ mask, int *__restrict__ nactive,
+                              double tol_in, int *__restrict__ mask,
+                              double *__restrict__ coltol, int *__restrict__ nactive,
                               int *__restrict__ err) {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
@@ -427,6 +545,10 @@ __global__ void k_refine_mask(const double *__restrict__ sums, int ncols, double
             m = sqrt(rr) > tol * sqrt(bb) ? 1 : 0;
         }
         mask[c] = m;
+        if (coltol) {
+            double t = m ? 0.3 * tol * sqrt(bb) / sqrt(rr) : tol_in;
+            coltol[c] = fmin(0.5, fmax(tol_in, t));
+        }
         if (m) atomicAdd(&cnt, 1);
     }
     __syncthreads();
@@ -553,10 +675,11 @@ hipError_t launch_refine_axpy(double *X, long ld, const float *D, long ld32, lon
     return hipGetLastError();
 }
 
-hipError_t launch_refine_mask(const double *sums, int ncols, double tol, int *mask,
-                              int *nactive, int *err, hipStream_t st) {
-    hipLaunchKernelGGL(k_refine_mask, dim3(1), dim3(256), 0, st, sums, ncols, tol, mask, nactive,
-                       err);
+hipError_t launch_refine_mask(const double *sums, int ncols, double tol, double tol_in,
+                              int *mask, double *coltol, int *nactive, int *err,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_refine_mask, dim3(1), dim3(256), 0, st, sums, ncols, tol, tol_in, mask,
+                       coltol, nactive, err);
     return hipGetLastError();
 }
 

@@ -31,9 +31,14 @@ if ROOT not in sys.path:
 METRIC = "steps/s at 96³,N=256: mixed vs FP64 at 1e-8 eig error; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per (grid point x column) of one launch; s = bytes per value
-#   sweep1: read r, p_old; write p        -> 3 s
-#   sweep2: read p, x, r;  write x, r     -> 5 s
-BYTES_PER_COLPT = {"sweep1_f64": 24, "sweep2_f64": 40, "sweep1_f32": 12, "sweep2_f32": 20}
+#   two-sweep form  sweep1: read r, p_old; write p           -> 3 s
+#                   sweep2: read p, x, r;  write x, r        -> 5 s
+#   one-sweep form  cg:     read r, p_old, x; write r, p, x  -> 6 s
+BYTES_PER_COLPT = {"sweep1_f64": 24, "sweep2_f64": 40, "sweep1_f32": 12, "sweep2_f32": 20,
+                   "cg_f64": 48, "cg_f32": 24}
+KERNEL_SYMBOL = {"sweep1_f64": "k_pcg_sweep1<double>", "sweep2_f64": "k_pcg_sweep2<double>",
+                 "sweep1_f32": "k_pcg_sweep1<float>", "sweep2_f32": "k_pcg_sweep2<float>",
+                 "cg_f64": "k_cg_step<double>", "cg_f32": "k_cg_step<float>"}
 
 
 def lambda1_estimate(n_coarse=32, seed=0):
@@ -55,13 +60,13 @@ def lambda1_estimate(n_coarse=32, seed=0):
     return float(vals[0])
 
 
-def run_gpu(precision, V, U0, n, N, tau, steps, warmup, inner_tol, log):
+def run_gpu(precision, V, U0, n, N, tau, steps, warmup, inner_tol, log, variant=1):
     import torch
 
     from paper_2605_25149_amd import binding
 
     s = binding.Solver(3, n, N, pcg_tol=1e-10, pcg_maxit=5000, pcg_check=8,
-                       precision=precision, refine_inner_tol=inner_tol)
+                       precision=precision, refine_inner_tol=inner_tol, pcg_variant=variant)
     try:
         s.set_potential(V)
         s.set_state(U0)
@@ -88,6 +93,52 @@ def run_gpu(precision, V, U0, n, N, tau, steps, warmup, inner_tol, log):
         s.close()
 
 
+def accuracy_gate(V, U0, n, N, tau, K, inner_tol, variant, log, res_tol=1e-5):
+    """Mixed vs FP64 after the same K-step trajectory: Ritz values of the pairs that the FP64
+    run has converged (relative residual ||H u - theta u|| / (|theta| ||u||) <= res_tol)."""
+    import torch
+
+    from paper_2605_25149_amd import binding
+
+    out = {}
+    for mode in ("fp64", "mixed"):
+        s = binding.Solver(3, n, N, pcg_tol=1e-10, pcg_maxit=5000, pcg_check=8, precision=mode,
+                           refine_inner_tol=inner_tol, pcg_variant=variant)
+        try:
+            s.set_potential(V)
+            s.set_state(U0)
+            t0 = time.perf_counter()
+            for i in range(K):
+                st = s.step(tau)
+                if i % 10 == 0 or i == K - 1:
+                    log(f"[accuracy {mode}] step {i + 1}/{K}: iters {st['pcg_iters']} "
+                        f"grad {st['grad_norm']:.3e} |O| {st['orth_err_fro']:.3e} "
+                        f"E {st['energy']:.12f} ({time.perf_counter() - t0:.1f} s)")
+            lam, vec = s.eigenpairs("ritz", vectors=True)
+            Hv = s.apply(vec)
+            theta = torch.as_tensor(lam, device=vec.device) + s.cfg.sigma
+            res = torch.linalg.norm(Hv - theta[:, None] * vec, dim=1) / (
+                theta.abs() * torch.linalg.norm(vec, dim=1))
+            out[mode] = (np.asarray(lam), res.cpu().numpy(), st)
+        finally:
+            s.close()
+    lam64, res64, st64 = out["fp64"]
+    lamm, resm, stm = out["mixed"]
+    conv = res64 <= res_tol
+    rel = np.abs(lamm - lam64) / np.abs(lam64)
+    m = int(conv.sum())
+    return {
+        "steps": K,
+        "converged_pairs": m,
+        "residual_tol": res_tol,
+        "max_rel_eig_diff_converged": float(rel[conv].max()) if m else None,
+        "max_rel_eig_diff_all": float(rel.max()),
+        "gate_1e-8": bool(m > 0 and rel[conv].max() <= 1e-8),
+        "lambda_fp64_first8": [float(x) for x in lam64[:8]],
+        "grad_norm_end": {"fp64": st64["grad_norm"], "mixed": stm["grad_norm"]},
+    }
+
+
 def roofline_of(prof, ng):
     """Dominant PCG sweep kernel: algorithmic bytes per launch / mean launch duration."""
     best = None
@@ -105,7 +156,7 @@ def roofline_of(prof, ng):
     mean_ms = d["ms"] / d["launches"]
     achieved = per_launch_bytes / (mean_ms * 1e-3) / 1e9
     return {
-        "kernel": f"k_pcg_{best}",
+        "kernel": KERNEL_SYMBOL[best],
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -168,7 +219,11 @@ def main():
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--inner-tol", type=float, default=1e-5)
     ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--pcg-variant", type=int, default=0,
+                    help="0: two-sweep Hestenes-Stiefel PCG, 1: one-sweep Chronopoulos-Gear")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy-steps", type=int, default=0,
+                    help="also run the mixed-vs-FP64 eigenvalue gate over this many steps")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
@@ -213,7 +268,7 @@ def main():
     res = {}
     for mode in args.modes.split(","):
         res[mode] = run_gpu(mode, V, U0_dev, n, N, tau, args.steps, args.warmup,
-                            args.inner_tol, log)
+                            args.inner_tol, log, args.pcg_variant)
         r = res[mode]
         log(f"[{mode}] {args.steps} steps in {r['seconds']:.3f} s -> "
             f"{args.steps / r['seconds']:.4f} steps/s")
@@ -239,7 +294,8 @@ def main():
                          f"(seed 0), N={N}, random U0 (seed 1), tau=0.9*lambda_1={tau:.5f}, "
                          f"PCG tol 1e-10, warm starts; {head} precision"),
             "grid": list(n), "N": N, "tau": tau, "pcg_tol": 1e-10,
-            "refine_inner_tol": args.inner_tol, "parallelism": "single GPU",
+            "refine_inner_tol": args.inner_tol, "pcg_variant": args.pcg_variant,
+            "parallelism": "single GPU",
         },
     }
     for mode, r in res.items():
@@ -257,9 +313,12 @@ def main():
         rf64 = roofline_of(res["fp64"]["profile"], ng)
         if rf64:
             out["roofline_fp64"] = rf64
+    if args.accuracy_steps > 0:
+        out["accuracy"] = accuracy_gate(V, U0_dev, n, N, tau, args.accuracy_steps,
+                                        args.inner_tol, args.pcg_variant, log)
     if not args.no_cpu_baseline:
         ref = res["fp64"] if "fp64" in res else rh
-        colits = (ref["profile"]["sweep2_f64"]["work"] or ref["profile"]["sweep2_f32"]["work"])
+        colits = max(ref["profile"][k]["work"] for k in ("sweep2_f64", "sweep2_f32", "cg_f64", "cg_f32"))
         colits_per_step = colits / args.steps
         out["cpu_baseline"] = cpu_baseline(V, U0, n, N, tau, colits_per_step, log)
     print(json.dumps(out), flush=True)

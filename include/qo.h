@@ -68,6 +68,10 @@ typedef struct {
     double refine_inner_tol; /* QO_MIXED: relative tolerance of each FP32 inner PCG solve */
     int warm_start;          /* 1: G U_n starts from the previous G U_hat and G U_hat from
                                 P (X + C Y); 0: both start from zero */
+    int pcg_variant;         /* 0: Hestenes-Stiefel form, two sweeps per iteration;
+                                1: Chronopoulos-Gear form, one sweep per iteration
+                                   (3-D, or 2-D with n_0 <= 256); same iterates in exact
+                                   arithmetic */
 } qo_config;
 
 typedef struct {
@@ -99,7 +103,8 @@ typedef enum {
 /* Create a solver for the grid and options in cfg.  hip_stream is a
  * hipStream_t (NULL: the default stream).  Allocates the device workspace
  * (about 7 blocks of Ng x N doubles in QO_FP64, plus 3 FP32 blocks in
- * QO_MIXED).  Sizes: 1 <= N < Ng, n_0 <= 2048.  On error *out is NULL. */
+ * QO_MIXED).  Sizes: 1 <= N < Ng, n_0 <= 1024 (n_0 <= 256 with pcg_variant 1).
+ * On error *out is NULL. */
 qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out);
 
 /* Potential V: Ng values, x fastest (the V of H = -kappa Lap + V, Sec. 2.1). */
@@ -168,7 +173,7 @@ qo_status qo_get_matrix(qo_handle h, int which, double *out);
 typedef enum {
     QO_KERNEL_SWEEP1_F64 = 0, QO_KERNEL_SWEEP2_F64 = 1, QO_KERNEL_SWEEP1_F32 = 2,
     QO_KERNEL_SWEEP2_F32 = 3, QO_KERNEL_GRAM = 4, QO_KERNEL_UPDATE = 5, QO_KERNEL_RESID = 6,
-    QO_KERNEL_COUNT = 8
+    QO_KERNEL_CG_F64 = 7, QO_KERNEL_CG_F32 = 8, QO_KERNEL_COUNT = 12
 } qo_kernel_id;
 typedef struct {
     long launches[QO_KERNEL_COUNT];

@@ -20,8 +20,9 @@ L2 inner product is the mass-weighted sum (u,v) = h^d * sum_i u_i v_i with
 h^d = prod(h_k), and the operator is H_sigma = -kappa*Lap_h + V + sigma.
 
 Readings of the paper taken here (each also listed in the design notes):
-  R1  G is applied to a block by per-column Jacobi-PCG (``solve``); a direct
-      sparse factorisation (``solve_direct``) is available for exact tests.
+  R1  G is applied to a block by per-column Jacobi-PCG (``solve``, Hestenes-Stiefel
+      or Chronopoulos-Gear form); a direct sparse factorisation (``solve_direct``) is
+      available for exact tests.
   R2  In A_U V = G U <U,V> - U <U, G V> the second term is evaluated with the
       symmetry of G as U <G U, V> = U <P, V>, P the computed G U, so A_U is
       exactly skew for the computed P and no solve with G V is needed.
@@ -80,6 +81,8 @@ def _load():
                                 dp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_int, ip, ip]
         lib.orc_pcg.restype = ctypes.c_int
+        lib.orc_pcg_variant.argtypes = lib.orc_pcg.argtypes + [ctypes.c_int]
+        lib.orc_pcg_variant.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -147,9 +150,10 @@ class Problem:
                          _dp(self.V), _dp(X), _dp(out), X.shape[1])
         return out
 
-    def solve(self, B, X0=None, tol=1e-10, maxit=10000):
+    def solve(self, B, X0=None, tol=1e-10, maxit=10000, variant=0):
         """G B = H_sigma^{-1} B by per-column Jacobi-PCG (reading R1).
 
+        variant 0: Hestenes-Stiefel form; 1: Chronopoulos-Gear (one-reduction) form.
         Returns (X, iters, status, col_status)."""
         B = _fcols(B, self.ng)
         if X0 is None:
@@ -160,9 +164,9 @@ class Problem:
             use_x0 = 1
         iters = np.zeros(B.shape[1], dtype=np.int32)
         cst = np.zeros(B.shape[1], dtype=np.int32)
-        st = _load().orc_pcg(self.dim, _ip(self._n3), _dp(self._h3), self.kappa, self.sigma,
-                             _dp(self.V), _dp(B), _dp(X), B.shape[1], tol, maxit, use_x0,
-                             _ip(iters), _ip(cst))
+        st = _load().orc_pcg_variant(self.dim, _ip(self._n3), _dp(self._h3), self.kappa,
+                                     self.sigma, _dp(self.V), _dp(B), _dp(X), B.shape[1], tol,
+                                     maxit, use_x0, _ip(iters), _ip(cst), int(variant))
         return X, iters, int(st), cst
 
     def sparse_matrix(self):
@@ -269,13 +273,14 @@ class Oracle:
     """Algorithm 1 driver with a fixed time step (Sec. 5)."""
 
     def __init__(self, prob: Problem, U0, tol=1e-10, maxit=20000, warm_start=True,
-                 direct=False):
+                 direct=False, variant=0):
         self.prob = prob
         self.U = np.array(_fcols(U0, prob.ng), order="F", copy=True)
         self.tol = tol
         self.maxit = maxit
         self.warm = warm_start
         self.direct = direct
+        self.variant = variant
         self.prevQ = None
         self.n = 0
         self.last = {}
@@ -283,7 +288,8 @@ class Oracle:
     def _G(self, B, X0):
         if self.direct:
             return self.prob.solve_direct(B), np.zeros(B.shape[1], dtype=np.int32)
-        X, it, st, _ = self.prob.solve(B, X0=X0, tol=self.tol, maxit=self.maxit)
+        X, it, st, _ = self.prob.solve(B, X0=X0, tol=self.tol, maxit=self.maxit,
+                                       variant=self.variant)
         if st != ORC_OK:
             raise RuntimeError(f"oracle PCG failed with status {st}")
         return X, it

@@ -20,9 +20,15 @@
  *
  *  - orc_pcg: the inverse operator G = H_sigma^{-1} of Sec. 3.1 applied to each
  *    column independently.  The paper defines G but does not say how it is
- *    applied; here it is Jacobi-preconditioned conjugate gradients (Hestenes-
- *    Stiefel form), stopped per column at the first iteration whose recursively
- *    updated residual satisfies ||r|| <= tol*||b||.
+ *    applied; here it is Jacobi-preconditioned conjugate gradients, stopped per
+ *    column at the first iteration whose recursively updated residual satisfies
+ *    ||r|| <= tol*||b||.  Two textbook forms of the same iteration:
+ *      variant 0: Hestenes-Stiefel (two inner products per iteration, each
+ *                 needing the previous one);
+ *      variant 1: Chronopoulos-Gear (both inner products of an iteration taken
+ *                 together from u = D r and w = H u; the step length follows from
+ *                 alpha = gamma / (delta - beta gamma / alpha_prev)).
+ *    In exact arithmetic they produce the same iterates.
  *
  * Layout: a block of ncols grid functions is column-major, Ng rows, each
  * column a grid with x fastest: index i + n0*(j + n1*k).
@@ -102,6 +108,10 @@ void orc_quad(int dim, const int *n, const double *h, double kappa, double sigma
     }
 }
 
+int orc_pcg_variant(int dim, const int *n, const double *h, double kappa, double sigma,
+                    const double *V, const double *B, double *X, int ncols, double tol,
+                    int maxit, int use_x0, int *iters, int *col_status, int variant);
+
 static double dot(const double *a, const double *b, long n) {
     double s = 0.0;
     for (long i = 0; i < n; ++i) s += a[i] * b[i];
@@ -115,9 +125,22 @@ static double dot(const double *a, const double *b, long n) {
  *   col_status out (may be NULL): per-column status
  * Returns the worst status over the columns (NONFINITE > NOT_SPD > NOCONV > OK).
  */
+static int cg_one_reduction(int dim, const int *n, const double *h, double kappa,
+                            double sigma, const double *V, const double *Dinv,
+                            const double *b, double *x, long ng, double tol, int maxit,
+                            int use_x0, int *iters, double *r, double *u, double *w,
+                            double *p, double *s);
+
 int orc_pcg(int dim, const int *n, const double *h, double kappa, double sigma,
             const double *V, const double *B, double *X, int ncols, double tol,
             int maxit, int use_x0, int *iters, int *col_status) {
+    return orc_pcg_variant(dim, n, h, kappa, sigma, V, B, X, ncols, tol, maxit, use_x0,
+                           iters, col_status, 0);
+}
+
+int orc_pcg_variant(int dim, const int *n, const double *h, double kappa, double sigma,
+                    const double *V, const double *B, double *X, int ncols, double tol,
+                    int maxit, int use_x0, int *iters, int *col_status, int variant) {
     const long ng = grid_size(dim, n);
     /* Jacobi preconditioner: inverse of the diagonal of H_sigma. */
     double diag0 = 0.0;
@@ -132,11 +155,17 @@ int orc_pcg(int dim, const int *n, const double *h, double kappa, double sigma,
         double *z = (double *)malloc(sizeof(double) * ng);
         double *p = (double *)malloc(sizeof(double) * ng);
         double *q = (double *)malloc(sizeof(double) * ng);
+        double *w = (double *)malloc(sizeof(double) * ng);
 #pragma omp for schedule(dynamic, 1)
         for (int c = 0; c < ncols; ++c) {
             const double *b = B + (long)c * ng;
             double *x = X + (long)c * ng;
             int st = ORC_OK, it = 0;
+            if (variant == 1) {
+                st = cg_one_reduction(dim, n, h, kappa, sigma, V, Dinv, b, x, ng, tol, maxit,
+                                      use_x0, &it, r, z, w, p, q);
+                goto done;
+            }
             if (use_x0) {
                 apply_one(dim, n, h, kappa, sigma, V, x, q);
                 for (long i = 0; i < ng; ++i) r[i] = b[i] - q[i];
@@ -167,6 +196,7 @@ int orc_pcg(int dim, const int *n, const double *h, double kappa, double sigma,
                     for (long i = 0; i < ng; ++i) p[i] = z[i] + beta * p[i];
                 }
             }
+        done:
             iters[c] = it;
             if (col_status) col_status[c] = st;
 #pragma omp critical
@@ -176,8 +206,63 @@ int orc_pcg(int dim, const int *n, const double *h, double kappa, double sigma,
                 if (rank[st] > rank[worst]) worst = st;
             }
         }
-        free(r); free(z); free(p); free(q);
+        free(r); free(z); free(p); free(q); free(w);
     }
     free(Dinv);
     return worst;
+}
+
+/* Chronopoulos-Gear form of Jacobi-PCG for one column (variant 1).
+ *   r = b - H x0; u = D r; w = H u; gamma = r.u; delta = w.u
+ *   beta = 0, alpha = gamma / delta; p = 0
+ *   repeat: p = u + beta p; s = H p; x += alpha p; r -= alpha s
+ *           u = D r; w = H u; gamma' = r.u; delta = w.u; stop test on ||r||
+ *           beta = gamma'/gamma; alpha = gamma' / (delta - beta gamma' / alpha)
+ * (u, w, p, s are work arrays of length ng.) */
+static int cg_one_reduction(int dim, const int *n, const double *h, double kappa,
+                            double sigma, const double *V, const double *Dinv,
+                            const double *b, double *x, long ng, double tol, int maxit,
+                            int use_x0, int *iters, double *r, double *u, double *w,
+                            double *p, double *s) {
+    int it = 0;
+    if (use_x0) {
+        apply_one(dim, n, h, kappa, sigma, V, x, s);
+        for (long i = 0; i < ng; ++i) r[i] = b[i] - s[i];
+    } else {
+        for (long i = 0; i < ng; ++i) { x[i] = 0.0; r[i] = b[i]; }
+    }
+    const double bnorm = sqrt(dot(b, b, ng));
+    for (long i = 0; i < ng; ++i) u[i] = Dinv[i] * r[i];
+    apply_one(dim, n, h, kappa, sigma, V, u, w);
+    double gamma = dot(r, u, ng);
+    double delta = dot(w, u, ng);
+    double rn = sqrt(dot(r, r, ng));
+    *iters = 0;
+    if (!isfinite(gamma) || !isfinite(delta) || !isfinite(rn) || !isfinite(bnorm))
+        return ORC_NONFINITE;
+    if (rn <= tol * bnorm) return ORC_OK;
+    double beta = 0.0, den = delta, alpha = 0.0;
+    for (long i = 0; i < ng; ++i) p[i] = 0.0;
+    for (;;) {
+        if (it >= maxit) { *iters = it; return ORC_NOCONV; }
+        if (!isfinite(den)) { *iters = it; return ORC_NONFINITE; }
+        if (!(den > 0.0)) { *iters = it; return ORC_NOT_SPD; }
+        alpha = gamma / den;
+        for (long i = 0; i < ng; ++i) p[i] = u[i] + beta * p[i];
+        apply_one(dim, n, h, kappa, sigma, V, p, s);
+        for (long i = 0; i < ng; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * s[i]; }
+        ++it;
+        for (long i = 0; i < ng; ++i) u[i] = Dinv[i] * r[i];
+        apply_one(dim, n, h, kappa, sigma, V, u, w);
+        const double gnew = dot(r, u, ng);
+        delta = dot(w, u, ng);
+        rn = sqrt(dot(r, r, ng));
+        if (!isfinite(rn) || !isfinite(gnew)) { *iters = it; return ORC_NONFINITE; }
+        if (rn <= tol * bnorm) break;
+        beta = gnew / gamma;
+        den = delta - beta * gnew / alpha;
+        gamma = gnew;
+    }
+    *iters = it;
+    return ORC_OK;
 }

@@ -31,7 +31,8 @@ EXPORTS = [
     "qo_gram", "qo_eigenpairs", "qo_destroy", "qo_status_string", "qo_last_error", "qo_apply",
     "qo_solve", "qo_gram_pair", "qo_get_block", "qo_get_matrix", "qo_profile", "qo_profile_get",
 ]
-KERNELS = ["sweep1_f64", "sweep2_f64", "sweep1_f32", "sweep2_f32", "gram", "update", "resid"]
+KERNELS = ["sweep1_f64", "sweep2_f64", "sweep1_f32", "sweep2_f32", "gram", "update", "resid",
+           "cg_f64", "cg_f32"]
 
 
 class QoConfig(ctypes.Structure):
@@ -40,7 +41,7 @@ class QoConfig(ctypes.Structure):
         ("kinetic", ctypes.c_double), ("N", ctypes.c_int), ("sigma", ctypes.c_double),
         ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int), ("pcg_check", ctypes.c_int),
         ("precision", ctypes.c_int), ("refine_inner_tol", ctypes.c_double),
-        ("warm_start", ctypes.c_int),
+        ("warm_start", ctypes.c_int), ("pcg_variant", ctypes.c_int),
     ]
 
 
@@ -64,8 +65,8 @@ class QoStepStats(ctypes.Structure):
 
 
 class QoProfileData(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_long * 8), ("ms", ctypes.c_double * 8),
-                ("work", ctypes.c_double * 8)]
+    _fields_ = [("launches", ctypes.c_long * 12), ("ms", ctypes.c_double * 12),
+                ("work", ctypes.c_double * 12)]
 
 
 class QOError(RuntimeError):
@@ -155,7 +156,7 @@ class Solver:
 
     def __init__(self, dim, n, N, L=(1.0, 1.0, 1.0), kinetic=0.5, sigma=0.0, pcg_tol=1e-10,
                  pcg_maxit=20000, pcg_check=8, precision="fp64", refine_inner_tol=1e-5,
-                 warm_start=True, stream=None):
+                 warm_start=True, pcg_variant=0, stream=None):
         import torch
 
         self.lib = load_library()
@@ -175,6 +176,7 @@ class Solver:
         cfg.precision = {"fp64": QO_FP64, "mixed": QO_MIXED}[precision]
         cfg.refine_inner_tol = refine_inner_tol
         cfg.warm_start = 1 if warm_start else 0
+        cfg.pcg_variant = int(pcg_variant)
         self.cfg = cfg
         self.dim, self.N = dim, N
         self.ng = int(np.prod(nn[:dim]))

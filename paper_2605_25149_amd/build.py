@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqo_hip.so")
-SOURCES = ["qo_api.hip", "qo_stencil.hip", "qo_gram.hip", "qo_tsgemm.hip", "qo_small.hip"]
+SOURCES = ["qo_api.hip", "qo_stencil.hip", "qo_cg.hip", "qo_gram.hip", "qo_tsgemm.hip",
+           "qo_small.hip"]
 ARCH = "gfx950"
 
 

@@ -46,7 +46,9 @@ struct qo_ctx {
     qo_config cfg{};
     hipStream_t st = nullptr;
     int device = 0;
-    Grid g{};
+    Grid g{};    // tiling of the two-sweep kernels and the stencil family
+    Grid gcg{};  // tiling of the one-sweep PCG kernels
+    long qsmax = 0;  // partial-sum stride: N * max(tiles)
     long ng = 0, ld = 0;
     int N = 0;
     double w = 1.0;
@@ -57,8 +59,9 @@ struct qo_ctx {
     float *vs32 = nullptr, *dinv32 = nullptr;
     // blocks (ld x N)
     double *U = nullptr, *Uh = nullptr, *PQ[2] = {nullptr, nullptr}, *r = nullptr,
-           *pa = nullptr, *pb = nullptr, *W = nullptr, *W2 = nullptr;
-    float *r32 = nullptr, *d32 = nullptr, *rr32 = nullptr, *pa32 = nullptr, *pb32 = nullptr;
+           *r2 = nullptr, *pa = nullptr, *pb = nullptr, *W = nullptr, *W2 = nullptr;
+    float *r32 = nullptr, *d32 = nullptr, *rr32 = nullptr, *rr32b = nullptr, *pa32 = nullptr,
+          *pb32 = nullptr;
     // reductions and small matrices
     double *part = nullptr;
     double *gpart = nullptr;
@@ -171,7 +174,9 @@ void setup_grid(qo_ctx *c) {
     g.c0 = 2.0 * cf.kinetic * (g.ihx2 + g.ihy2 + g.ihz2);
     c->w = h[0] * h[1] * (cf.dim == 3 ? h[2] : 1.0);
 
-    int TY = 1536 / g.nx;
+    // band height: ~1536 points per plane in 2-D; 3-D bands are kept near 768
+    // points (measured faster for the FP32 sweeps at 96^3 because of occupancy)
+    int TY = (cf.dim == 3 ? 768 : 1536) / g.nx;
     if (TY < 1) TY = 1;
     TY = env_int("QO_TY", TY);
     if (TY > g.ny) TY = g.ny;
@@ -196,6 +201,43 @@ void setup_grid(qo_ctx *c) {
         g.ZC = ZC;
         g.nzc = (g.nz + ZC - 1) / ZC;
     }
+    // one-sweep PCG: rows [-2, TY+1] per plane in at most 5 (8 for wide rows) points per
+    // thread, and 3 + 3 LDS planes of (TY+4) and (TY+2) rows within 64 KiB in FP64
+    Grid &q = c->gcg;
+    q = g;
+    {
+        const int target = g.nx <= 128 ? 5 : 8;
+        int ty = kThreads * target / g.nx - 4;
+        const int ty_lds = ((65536 / (24 * g.nx)) - 6) / 2;
+        if (ty > ty_lds) ty = ty_lds;
+        ty = env_int("QO_CG_TY", ty);
+        if (ty > g.ny) ty = g.ny;
+        if (ty < 1) ty = 1;
+        q.TY = ty;
+        const int raw = ((ty + 4) * g.nx + kThreads - 1) / kThreads;
+        const int opts[6] = {2, 3, 4, 5, 6, 8};
+        q.ppt = -1;
+        for (int o : opts)
+            if (o >= raw) { q.ppt = o; break; }
+        q.nbands = (g.ny + ty - 1) / ty;
+        if (cf.dim == 2) {
+            q.ZC = 1;
+            q.nzc = 1;
+        } else {
+            long want = (2048 + (long)c->N * q.nbands - 1) / ((long)c->N * q.nbands);
+            int maxc = g.nz / 16;
+            if (maxc < 1) maxc = 1;
+            if (want > maxc) want = maxc;
+            if (want < 1) want = 1;
+            int ZC = (g.nz + (int)want - 1) / (int)want;
+            ZC = env_int("QO_CG_ZC", ZC);
+            if (ZC < 1) ZC = 1;
+            if (ZC > g.nz) ZC = g.nz;
+            q.ZC = ZC;
+            q.nzc = (g.nz + ZC - 1) / ZC;
+        }
+    }
+    c->qsmax = (long)c->N * (g.tiles() > q.tiles() ? g.tiles() : q.tiles());
 }
 
 // ----------------------------------------------------------------- solves
@@ -237,7 +279,7 @@ void prof_harvest(qo_ctx *c) {
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             c->pdata.ms[p.kid] += ms;
             c->pdata.launches[p.kid] += 1;
-            if (p.kid >= QO_KERNEL_GRAM) c->pdata.work[p.kid] += 1.0;
+            if (p.kid >= QO_KERNEL_GRAM && p.kid <= QO_KERNEL_RESID) c->pdata.work[p.kid] += 1.0;
         }
         c->evpool.push_back(p.a);
         c->evpool.push_back(p.b);
@@ -313,12 +355,70 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
     return QO_OK;
 }
 
+// One-sweep (Chronopoulos-Gear) Jacobi-PCG on all columns of B into X.
+template <typename T>
+qo_status pcg_cg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R0, T *R1, T *P0,
+                 T *P1, int ncols, int use_x0, double tol, const int *mask,
+                 const double *coltol, int *its_out, const char *what) {
+    const Grid &g = c->gcg;
+    hipStream_t st = c->st;
+    PcgState s = c->ps;
+    s.coltol = coltol;
+    HIPC(c, hipMemsetAsync(s.its, 0, sizeof(int) * ncols, st));
+    int init_err[2] = {0, INT_MAX};
+    HIPC(c, hipMemcpyAsync(s.err, init_err, sizeof init_err, hipMemcpyHostToDevice, st));
+    double *pbuf[2] = {c->part, c->part + 4 * c->qsmax};
+    T *Rb[2] = {R0, R1};
+    T *Pb[2] = {P0, P1};
+    HIPC(c, launch_pcg_init<T>(g, vs, dinv, B, X, R0, c->ld, ncols, use_x0, pbuf[0], st));
+    HIPC(c, launch_cg_delta0<T>(g, vs, dinv, R0, c->ld, ncols, pbuf[0], st));
+    const int check = c->cfg.pcg_check;
+    const int maxit = c->cfg.pcg_maxit;
+    const int kid = sizeof(T) == 8 ? QO_KERNEL_CG_F64 : QO_KERNEL_CG_F32;
+    for (int k = 0;; ++k) {
+        hipEvent_t ea = prof_begin(c);
+        HIPC(c, launch_cg_step<T>(g, vs, dinv, Rb[k & 1], Rb[(k + 1) & 1], Pb[(k + 1) & 1],
+                                  Pb[k & 1], X, c->ld, ncols, k, tol, mask, s, pbuf[k & 1],
+                                  pbuf[(k + 1) & 1], st));
+        prof_end(c, kid, ea);
+        if (k % check == 0 || k >= maxit) {
+            HIPC(c, hipMemcpyAsync(c->h_poll, s.active + (k & 1) * ncols, sizeof(int) * ncols,
+                                   hipMemcpyDeviceToHost, st));
+            HIPC(c, hipMemcpyAsync(c->h_poll + ncols, s.err, 2 * sizeof(int),
+                                   hipMemcpyDeviceToHost, st));
+            HIPC(c, hipStreamSynchronize(st));
+            prof_harvest(c);
+            if (c->h_poll[ncols]) return check_poll_err(c, c->h_poll[ncols], c->h_poll[ncols + 1], what);
+            int nact = 0;
+            for (int j = 0; j < ncols; ++j) nact += c->h_poll[j] ? 1 : 0;
+            if (nact == 0) break;
+            if (k >= maxit)
+                return fail(c, QO_ERR_PCG_NOCONV, "%s: %d of %d columns not converged after %d "
+                            "PCG iterations (tol %.3g)", what, nact, ncols, maxit, tol);
+        }
+    }
+    HIPC(c, hipMemcpyAsync(c->h_poll, s.its, sizeof(int) * ncols, hipMemcpyDeviceToHost, st));
+    HIPC(c, hipStreamSynchronize(st));
+    prof_harvest(c);
+    double colits = 0.0;
+    for (int j = 0; j < ncols; ++j) {
+        its_out[j] = c->h_poll[j];
+        colits += c->h_poll[j];
+    }
+    if (c->prof) c->pdata.work[kid] += colits;
+    return QO_OK;
+}
+
 // X = G B for ncols columns of internal-layout blocks.  its: per column.
 qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_x0, int *its,
                       int *rounds, const char *what) {
     const double tol = c->cfg.pcg_tol;
+    const bool one_sweep = c->cfg.pcg_variant == 1;
     if (!c->mixed) {
         *rounds = 1;
+        if (one_sweep)
+            return pcg_cg<double>(c, c->vs, c->dinv, B, X, c->r, c->r2, c->pa, c->pb, ncols,
+                                  use_x0, tol, nullptr, nullptr, its, what);
         return pcg<double>(c, c->vs, c->dinv, B, X, c->r, c->pa, c->pb, ncols, use_x0, tol,
                            nullptr, nullptr, its, what);
     }
@@ -351,8 +451,14 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
         if (round >= max_rounds)
             return fail(c, QO_ERR_PCG_NOCONV, "%s: refinement did not reach tol %.3g in %d rounds",
                         what, tol, max_rounds);
-        QOC(pcg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->rr32, c->pa32, c->pb32, ncols, 0,
-                       c->cfg.refine_inner_tol, c->mask, c->coltol, inner.data(), what));
+        if (one_sweep)
+            QOC(pcg_cg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->rr32, c->rr32b, c->pa32,
+                              c->pb32, ncols, 0, c->cfg.refine_inner_tol, c->mask, c->coltol,
+                              inner.data(), what));
+        else
+            QOC(pcg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->rr32, c->pa32, c->pb32,
+                           ncols, 0, c->cfg.refine_inner_tol, c->mask, c->coltol, inner.data(),
+                           what));
         for (int j = 0; j < ncols; ++j) its[j] += inner[j];
         HIPC(c, launch_refine_axpy(X, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, st));
     }
@@ -627,7 +733,9 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
         if (c.n[k] < 1 || !(c.L[k] > 0.0)) return QO_ERR_ARG;
         ng *= c.n[k];
     }
-    if (c.n[0] > 2048) return QO_ERR_ARG;
+    if (c.n[0] > 1024) return QO_ERR_ARG;
+    if (c.pcg_variant != 0 && c.pcg_variant != 1) return QO_ERR_ARG;
+    if (c.pcg_variant == 1 && c.n[0] > 256) return QO_ERR_ARG;
     if (c.N < 1 || c.N >= ng || c.N > 4096) return QO_ERR_ARG;
     if (!(c.kinetic > 0.0) || !std::isfinite(c.sigma)) return QO_ERR_ARG;
     if (!(c.pcg_tol > 0.0) || c.pcg_maxit < 1 || c.pcg_check < 1) return QO_ERR_ARG;
@@ -658,6 +766,7 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
     A(&h->PQ[0], blk);
     A(&h->PQ[1], blk);
     A(&h->r, blk);
+    if (c.pcg_variant == 1) A(&h->r2, blk);
     A(&h->pa, blk);
     A(&h->pb, blk);
     A(&h->W, blk);
@@ -668,11 +777,11 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
         A(&h->r32, blk);
         A(&h->d32, blk);
         A(&h->rr32, blk);
+        if (c.pcg_variant == 1) A(&h->rr32b, blk);
         A(&h->pa32, blk);
         A(&h->pb32, blk);
     }
-    const int tiles = h->g.tiles();
-    A(&h->part, (size_t)4 * N * tiles);
+    A(&h->part, (size_t)8 * h->qsmax);
     h->gnsplit = gram_nsplit(h->ng, N);
     A(&h->gpart, gram_part_elems(N, h->gnsplit));
     A(&h->G1, (size_t)4 * N * N);
@@ -682,6 +791,7 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
     A(&h->dscal, 16);
     A(&h->sortwork, (size_t)N + (size_t)N * N);
     A(&h->ps.rho, (size_t)2 * N);
+    A(&h->ps.alpha, (size_t)2 * N);
     A(&h->ps.active, (size_t)2 * N);
     A(&h->ps.its, (size_t)N);
     A(&h->ps.bb, (size_t)N);

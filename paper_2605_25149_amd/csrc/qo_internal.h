@@ -26,6 +26,7 @@ constexpr int kThreads = 256;
 // Per-column PCG bookkeeping on the device (double-buffered by iteration parity).
 struct PcgState {
     double *rho;    // [2][ncap]
+    double *alpha;  // [2][ncap] (one-reduction form)
     int *active;    // [2][ncap]
     int *its;       // [ncap]
     double *bb;     // [ncap]
@@ -58,6 +59,18 @@ hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T 
 template <typename T>
 hipError_t launch_pcg_sweep2(const Grid &g, const T *vs, const T *dinv, const T *Pn, T *X, T *R,
                              long ld, int ncols, int k, PcgState s, hipStream_t st);
+
+// One-reduction (Chronopoulos-Gear) PCG: delta0 = u.Hu with u = D r0 into
+// part[3] (after launch_pcg_init on the same grid), then one sweep per iteration.
+template <typename T>
+hipError_t launch_cg_delta0(const Grid &g, const T *vs, const T *dinv, const T *R, long ld,
+                            int ncols, double *part, hipStream_t st);
+template <typename T>
+hipError_t launch_cg_step(const Grid &g, const T *vs, const T *dinv, const T *Rin, T *Rout,
+                          const T *Pold, T *Pnew, T *X, long ld, int ncols, int k, double tol,
+                          const int *mask, PcgState s, const double *pin, double *pout,
+                          hipStream_t st);
+size_t cg_lds_bytes(const Grid &g, size_t elem);
 
 // Sum partials per column: out[c] = sum_t part[q][c*tiles + t] for q < nq; out is [nq][ncols].
 hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long qstride,

@@ -21,44 +21,15 @@
 // The per-column stop test ||r|| <= tol ||b|| is evaluated at the start of
 // sweep1, so a column freezes at the first iteration that passes it.
 #include "qo_internal.h"
+#include "qo_device.h"
 
 namespace qo {
 
 namespace {
 
-struct Red {
-    double v[4][kThreads / 64];
-};
-
-template <int NQ>
-__device__ __forceinline__ void block_sums(double (&v)[NQ], Red &red) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) red.v[q][wid] = v[q];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) s += red.v[q][w];
-        v[q] = s;
-    }
-}
-
-// Sum of part[c*tiles + t] over t, identical in every thread and every block.
-__device__ __forceinline__ double col_sum(const double *__restrict__ part, int c, int tiles,
-                                          Red &red) {
-    double s[1] = {0.0};
-    for (int t = threadIdx.x; t < tiles; t += kThreads) s[0] += part[(long)c * tiles + t];
-    block_sums<1>(s, red);
-    return s[0];
-}
+using dev::Red;
+using dev::block_sums;
+using dev::col_sum;
 
 // The streaming engine.
 //
@@ -504,6 +475,30 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep2(Grid g, const T *__rest
     }
 }
 
+// delta0 = u . H u with u = D r0 (one-reduction PCG start)
+template <typename T, int PPT>
+__global__ __launch_bounds__(kThreads) void k_cg_delta0(Grid g, const T *__restrict__ vs,
+                                                        const T *__restrict__ dinv,
+                                                        const T *__restrict__ R, long ld,
+                                                        double *__restrict__ part, long qs) {
+    __shared__ Red red;
+    int col, tile, band, zc;
+    tile_of(g, col, tile, band, zc);
+    LdPcgP<T> l{dinv, R + (long)col * ld, nullptr, T(0), true};
+    struct Ep {
+        using Raw = NoRaw;
+        double acc[1];
+        __device__ static Raw zero() { return {}; }
+        __device__ Raw load(long) const { return {}; }
+        __device__ void operator()(int, long, T c, T hv, const Raw &) {
+            acc[0] += (double)c * (double)hv;
+        }
+    } ep{{0.0}};
+    engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
+    block_sums<1>(ep.acc, red);
+    if (threadIdx.x == 0) part[3 * qs + (long)col * g.tiles() + tile] = ep.acc[0];
+}
+
 __global__ void k_colsum(const double *__restrict__ part, int tiles, int ncols, int nq, long qs,
                          double *__restrict__ out) {
     __shared__ Red red;
@@ -561,7 +556,9 @@ inline size_t lds_bytes(const Grid &g, size_t elem) { return 2 * (size_t)(g.TY +
     switch (PPTV) {                                       \
         case 1: { constexpr int P = 1; __VA_ARGS__; } break; \
         case 2: { constexpr int P = 2; __VA_ARGS__; } break; \
+        case 3: { constexpr int P = 3; __VA_ARGS__; } break; \
         case 4: { constexpr int P = 4; __VA_ARGS__; } break; \
+        case 5: { constexpr int P = 5; __VA_ARGS__; } break; \
         case 6: { constexpr int P = 6; __VA_ARGS__; } break; \
         case 8: { constexpr int P = 8; __VA_ARGS__; } break; \
         default: return hipErrorInvalidValue;               \
@@ -656,6 +653,22 @@ template hipError_t launch_pcg_sweep2<double>(const Grid &, const double *, cons
 template hipError_t launch_pcg_sweep2<float>(const Grid &, const float *, const float *,
                                              const float *, float *, float *, long, int, int,
                                              PcgState, hipStream_t);
+
+template <typename T>
+hipError_t launch_cg_delta0(const Grid &g, const T *vs, const T *dinv, const T *R, long ld,
+                            int ncols, double *part, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const long qs = (long)ncols * g.tiles();
+    const dim3 grid(ncols * g.tiles());
+    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_cg_delta0<T, P>), grid, dim3(kThreads),
+                                              lds_bytes(g, sizeof(T)), st, g, vs, dinv, R, ld,
+                                              part, qs));
+    return hipGetLastError();
+}
+template hipError_t launch_cg_delta0<double>(const Grid &, const double *, const double *,
+                                             const double *, long, int, double *, hipStream_t);
+template hipError_t launch_cg_delta0<float>(const Grid &, const float *, const float *,
+                                            const float *, long, int, double *, hipStream_t);
 
 hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long qstride,
                          double *out, hipStream_t st) {

@@ -361,3 +361,31 @@ def test_paper_hydrogen_tables(oracle_mod):
     np.testing.assert_allclose(err, g["err_printed"], rtol=2e-3)
     # E(U_end) - 1/2 sum lambda_i is at the level of the solution accuracy
     assert abs(g["E_end"] - 0.5 * sum(g["lambda_computed"])) <= 1e-9
+
+
+def test_pcg_one_reduction_form(oracle_mod):
+    """The Chronopoulos-Gear form: same solution as a dense solve, iteration counts within a
+    couple of the Hestenes-Stiefel form (same iterates in exact arithmetic), error paths."""
+    O = oracle_mod
+    n = (9, 8, 7)
+    V = inputs.gaussian_wells(n, seed=0)
+    prob = O.Problem(3, n, V)
+    H = dense_H(3, n, (1, 1, 1), 0.5, 0.0, prob.V)
+    B = inputs.random_block(prob.ng, 5, seed=3)
+    X0 = inputs.random_block(prob.ng, 5, seed=8) * 1e-2
+    for x0 in (None, X0):
+        X1, it1, st1, _ = prob.solve(B, X0=x0, tol=1e-12, variant=1)
+        X0r, it0, st0, _ = prob.solve(B, X0=x0, tol=1e-12, variant=0)
+        assert st1 == O.ORC_OK and st0 == O.ORC_OK
+        Xd = np.linalg.solve(H, B)
+        assert np.max(np.abs(X1 - Xd)) <= 1e-9 * np.max(np.abs(Xd))
+        assert np.max(np.abs(it1 - it0)) <= 2
+    _, _, st, _ = prob.solve(B, tol=1e-12, maxit=3, variant=1)
+    assert st == O.ORC_NOCONV
+    p2 = O.Problem(2, (6, 6), np.zeros(36))
+    xs = inputs.grid_coords((6, 6))
+    mode = np.sin(np.pi * xs[0]) * np.sin(np.pi * xs[1])
+    lam1 = 2 * 4 * 0.5 * 7**2 * np.sin(np.pi / 14) ** 2
+    neg = O.Problem(2, (6, 6), np.zeros(36), sigma=-2 * lam1)
+    _, _, st, _ = neg.solve(mode[:, None], tol=1e-12, variant=1)
+    assert st == O.ORC_NOT_SPD

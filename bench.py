@@ -139,6 +139,29 @@ def accuracy_gate(V, U0, n, N, tau, K, inner_tol, variant, log, res_tol=1e-5):
     }
 
 
+def profile_traffic_ratios():
+    """traffic_ratio lines of the committed rocprofv3 summaries, kept only while the kernel
+    source they were measured on is unchanged (sha256 recorded beside them)."""
+    import glob
+    import hashlib
+
+    ratios = {}
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        ok, found = True, {}
+        for line in open(path, encoding="utf-8"):
+            parts = line.split()
+            if len(parts) == 3 and parts[0] == "source_sha256":
+                src = os.path.join(ROOT, parts[1])
+                cur = (hashlib.sha256(open(src, "rb").read()).hexdigest()
+                       if os.path.exists(src) else None)
+                ok = ok and cur == parts[2]
+            elif len(parts) == 3 and parts[0] == "traffic_ratio":
+                found[parts[1]] = float(parts[2])
+        if ok:
+            ratios.update(found)
+    return ratios
+
+
 def roofline_of(prof, ng):
     """Dominant PCG sweep kernel: algorithmic bytes per launch / mean launch duration."""
     best = None
@@ -163,6 +186,7 @@ def roofline_of(prof, ng):
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": None,
+        "traffic_ratio": None,
         "launches": d["launches"],
         "mean_launch_ms": round(mean_ms, 4),
         "algorithmic_bytes_per_launch": round(per_launch_bytes),
@@ -308,6 +332,10 @@ def main():
         out["speedup_mixed_vs_fp64"] = round(res["fp64"]["seconds"] / res["mixed"]["seconds"], 4)
     rf = roofline_of(rh["profile"], ng)
     if rf:
+        ratio = profile_traffic_ratios().get(rf["kernel"])
+        if ratio is not None:
+            rf["traffic"] = round(ratio * rf["algorithmic_bytes_per_launch"])
+            rf["traffic_ratio"] = ratio
         out["roofline"] = rf
     if "fp64" in res:
         rf64 = roofline_of(res["fp64"]["profile"], ng)

@@ -74,6 +74,11 @@ struct qo_ctx {
     PcgState ps{};
     int *mask = nullptr, *nact = nullptr, *dstatus = nullptr;
     double *coltol = nullptr;
+    // reliable-update state of the mixed-precision solve
+    double *zerotol = nullptr, *rref = nullptr, *bb64 = nullptr;
+    int *need = nullptr, *nneed = nullptr;
+    double rel_delta = 0.1;
+    bool rel = true;
     // pinned host
     int *h_poll = nullptr;
     double *h_scal = nullptr;
@@ -409,6 +414,99 @@ qo_status pcg_cg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R0,
     return QO_OK;
 }
 
+// Mixed-precision solve with reliable updates: Jacobi-PCG runs in FP32 on the
+// correction d (x_true = x + d) and is never restarted; at poll points every
+// column whose FP32 recursive residual fell by `rel_delta` since its last
+// replacement (or reached the tolerance) gets x += d, d = 0 and its residual
+// replaced by the FP64 residual b - H x (rounded to FP32).  The search direction
+// is kept, so the Krylov progress of the FP32 iteration is not lost; the FP64
+// residual decides convergence.
+qo_status solve_mixed_rel(qo_ctx *c, const double *B, double *X, int ncols, int use_x0, int *its,
+                          int *rounds, const char *what) {
+    const Grid &g = c->g;
+    hipStream_t st = c->st;
+    PcgState s = c->ps;
+    s.coltol = c->zerotol;  // the FP32 stop test is off; the FP64 residual decides
+    const double tol = c->cfg.pcg_tol;
+    const int tiles = g.tiles();
+    double *outer = c->part + 4 * c->qsmax;
+    if (!use_x0) HIPC(c, hipMemsetAsync(X, 0, sizeof(double) * c->ld * ncols, st));
+    HIPC(c, hipMemsetAsync(c->d32, 0, sizeof(float) * c->ld * ncols, st));
+    HIPC(c, hipMemsetAsync(s.its, 0, sizeof(int) * ncols, st));
+    int init_err[2] = {0, INT_MAX};
+    HIPC(c, hipMemcpyAsync(s.err, init_err, sizeof init_err, hipMemcpyHostToDevice, st));
+    std::vector<int> ones(ncols, 1);
+    HIPC(c, hipMemcpyAsync(c->need, ones.data(), sizeof(int) * ncols, hipMemcpyHostToDevice, st));
+    hipEvent_t er = prof_begin(c);
+    HIPC(c, launch_resid_rel(g, c->vs, c->dinv32, B, X, c->ld, c->r32, ncols, c->need, c->part,
+                             outer, st));
+    prof_end(c, QO_KERNEL_RESID, er);
+    HIPC(c, hipMemsetAsync(c->nact, 0, sizeof(int), st));
+    HIPC(c, launch_rel_finalize(outer, tiles, ncols, c->need, c->mask, c->rref, c->bb64, tol, 1,
+                                c->nact, s.err, st));
+    HIPC(c, hipMemcpyAsync(c->h_poll, c->nact, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPC(c, hipMemcpyAsync(c->h_poll + 1, s.err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPC(c, hipStreamSynchronize(st));
+    prof_harvest(c);
+    if (c->h_poll[1]) return check_poll_err(c, c->h_poll[1], c->h_poll[2], what);
+    int nrep = 1;
+    const int check = c->cfg.pcg_check;
+    const int maxit = c->cfg.pcg_maxit;
+    if (c->h_poll[0] > 0) {
+        float *pbuf[2] = {c->pa32, c->pb32};
+        for (int k = 0;; ++k) {
+            hipEvent_t ea = prof_begin(c);
+            HIPC(c, launch_pcg_sweep1<float>(g, c->vs32, c->dinv32, c->r32, pbuf[(k + 1) & 1],
+                                             pbuf[k & 1], c->ld, ncols, k, tol, c->mask, s, st));
+            prof_end(c, QO_KERNEL_SWEEP1_F32, ea);
+            hipEvent_t eb = prof_begin(c);
+            HIPC(c, launch_pcg_sweep2<float>(g, c->vs32, c->dinv32, pbuf[k & 1], c->d32, c->r32,
+                                             c->ld, ncols, k, s, st));
+            prof_end(c, QO_KERNEL_SWEEP2_F32, eb);
+            if ((k + 1) % check != 0 && k + 1 < maxit) continue;
+            int *act = s.active + (k & 1) * ncols;
+            HIPC(c, hipMemsetAsync(c->nneed, 0, sizeof(int), st));
+            HIPC(c, launch_rel_check(c->part, tiles, ncols, act, c->rref, c->bb64, c->rel_delta,
+                                     tol, c->need, c->nneed, st));
+            HIPC(c, launch_refine_axpy(X, c->ld, c->d32, c->ld, c->ng, ncols, c->need, 1, st));
+            hipEvent_t ec = prof_begin(c);
+            HIPC(c, launch_resid_rel(g, c->vs, c->dinv32, B, X, c->ld, c->r32, ncols, c->need,
+                                     c->part, outer, st));
+            prof_end(c, QO_KERNEL_RESID, ec);
+            HIPC(c, hipMemsetAsync(c->nact, 0, sizeof(int), st));
+            HIPC(c, launch_rel_finalize(outer, tiles, ncols, c->need, act, c->rref, c->bb64, tol,
+                                        0, c->nact, s.err, st));
+            HIPC(c, hipMemcpyAsync(c->h_poll, c->nact, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPC(c, hipMemcpyAsync(c->h_poll + 1, s.err, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                                   st));
+            HIPC(c, hipMemcpyAsync(c->h_poll + 3, c->nneed, sizeof(int), hipMemcpyDeviceToHost,
+                                   st));
+            HIPC(c, hipStreamSynchronize(st));
+            prof_harvest(c);
+            if (c->h_poll[1]) return check_poll_err(c, c->h_poll[1], c->h_poll[2], what);
+            if (c->h_poll[3] > 0) ++nrep;
+            if (c->h_poll[0] == 0) break;
+            if (k + 1 >= maxit)
+                return fail(c, QO_ERR_PCG_NOCONV, "%s: %d of %d columns above tol %.3g after %d "
+                            "FP32 iterations", what, c->h_poll[0], ncols, tol, maxit);
+        }
+    }
+    HIPC(c, hipMemcpyAsync(c->h_poll, s.its, sizeof(int) * ncols, hipMemcpyDeviceToHost, st));
+    HIPC(c, hipStreamSynchronize(st));
+    double colits = 0.0;
+    for (int j = 0; j < ncols; ++j) {
+        // its[j] is the last iteration index in which the column was active
+        its[j] = c->h_poll[j] + 1;
+        colits += its[j];
+    }
+    if (c->prof) {
+        c->pdata.work[QO_KERNEL_SWEEP1_F32] += colits;
+        c->pdata.work[QO_KERNEL_SWEEP2_F32] += colits;
+    }
+    *rounds = nrep;
+    return QO_OK;
+}
+
 // X = G B for ncols columns of internal-layout blocks.  its: per column.
 qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_x0, int *its,
                       int *rounds, const char *what) {
@@ -422,7 +520,8 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
         return pcg<double>(c, c->vs, c->dinv, B, X, c->r, c->pa, c->pb, ncols, use_x0, tol,
                            nullptr, nullptr, its, what);
     }
-    // FP64 iterative refinement around FP32 PCG
+    if (c->rel && !one_sweep) return solve_mixed_rel(c, B, X, ncols, use_x0, its, rounds, what);
+    // FP64 iterative refinement around FP32 PCG (restarted each round)
     hipStream_t st = c->st;
     const Grid &g = c->g;
     if (!use_x0) HIPC(c, hipMemsetAsync(X, 0, sizeof(double) * c->ld * ncols, st));
@@ -460,7 +559,7 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
                            ncols, 0, c->cfg.refine_inner_tol, c->mask, c->coltol, inner.data(),
                            what));
         for (int j = 0; j < ncols; ++j) its[j] += inner[j];
-        HIPC(c, launch_refine_axpy(X, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, st));
+        HIPC(c, launch_refine_axpy(X, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, 0, st));
     }
     return QO_OK;
 }
@@ -798,6 +897,13 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
     A(&h->ps.err, 2);
     A(&h->mask, (size_t)N);
     A(&h->coltol, (size_t)N);
+    A(&h->zerotol, (size_t)N);
+    A(&h->rref, (size_t)N);
+    A(&h->bb64, (size_t)N);
+    A(&h->need, (size_t)N);
+    A(&h->nneed, 1);
+    h->rel = env_int("QO_MIXED_RESTART", 0) == 0;
+    if (const char *d = getenv("QO_REL_DELTA")) h->rel_delta = atof(d);
     A(&h->nact, 1);
     A(&h->dstatus, 1);
     h->ps.part = h->part;

@@ -76,9 +76,19 @@ size_t cg_lds_bytes(const Grid &g, size_t elem);
 hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long qstride,
                          double *out, hipStream_t st);
 
-// x += d (FP64 += FP32) for columns with mask != 0.
-hipError_t launch_refine_axpy(double *X, long ld, const float *D, long ld32, long ng, int ncols,
-                              const int *mask, hipStream_t st);
+// x += d (FP64 += FP32) for columns with mask != 0 (and d = 0 when zero_d).
+hipError_t launch_refine_axpy(double *X, long ld, float *D, long ld32, long ng, int ncols,
+                              const int *mask, int zero_d, hipStream_t st);
+// Reliable updates of the mixed-precision solve (see qo_stencil.hip).
+hipError_t launch_resid_rel(const Grid &g, const double *vs, const float *dinv32, const double *B,
+                            const double *X, long ld, float *R32, int ncols, const int *mask,
+                            double *part, double *outer, hipStream_t st);
+hipError_t launch_rel_check(const double *part, int tiles, int ncols, const int *active,
+                            const double *rref, const double *bb64, double delta, double tol,
+                            int *need, int *nneed, hipStream_t st);
+hipError_t launch_rel_finalize(const double *outer, int tiles, int ncols, const int *need,
+                               int *active, double *rref, double *bb64, double tol, int init,
+                               int *nactive, int *err, hipStream_t st);
 // mask[c] = (sqrt(rr[c]) > tol * sqrt(bb[c])); counts into *nactive (device int);
 // coltol[c] (may be null): inner FP32 tolerance for the next round
 hipError_t launch_refine_mask(const double *sums, int ncols, double tol, double tol_in,

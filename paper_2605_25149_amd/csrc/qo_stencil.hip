@@ -294,6 +294,54 @@ __global__ __launch_bounds__(kThreads) void k_resid(Grid g, const double *__rest
     }
 }
 
+// Residual replacement of the mixed-precision solve (reliable update): for the
+// columns with mask != 0, r = b - H x in FP64, r32 = (float) r.  Partials in the
+// FP32 PCG layout: q0 = r32 . D32 r32, q1 = q2 = ||r32||^2; and in `outer`:
+// [0] ||r||^2 (FP64), [1] ||b||^2.  Unmasked columns are untouched.
+template <int PPT>
+__global__ __launch_bounds__(kThreads) void k_resid_rel(Grid g, const double *__restrict__ vs,
+                                                        const float *__restrict__ dinv32,
+                                                        const double *__restrict__ B,
+                                                        const double *__restrict__ X, long ld,
+                                                        float *__restrict__ R32,
+                                                        const int *__restrict__ mask,
+                                                        double *__restrict__ part, long qs,
+                                                        double *__restrict__ outer) {
+    __shared__ Red red;
+    int col, tile, band, zc;
+    tile_of(g, col, tile, band, zc);
+    if (!mask[col]) return;
+    struct Ep {
+        struct Raw { double b; float d; };
+        const double *__restrict__ b;
+        const float *__restrict__ dinv;
+        float *__restrict__ r32;
+        double acc[4];
+        __device__ static Raw zero() { return {0.0, 0.f}; }
+        __device__ Raw load(long i) const { return {b[i], dinv[i]}; }
+        __device__ void operator()(int, long i, double, double hv, const Raw &e) {
+            const double r = e.b - hv;
+            const float rf = (float)r;
+            r32[i] = rf;
+            acc[0] += (double)rf * (double)(e.d * rf);
+            acc[1] += (double)rf * (double)rf;
+            acc[2] += r * r;
+            acc[3] += e.b * e.b;
+        }
+    } ep{B + (long)col * ld, dinv32, R32 + (long)col * ld, {0.0, 0.0, 0.0, 0.0}};
+    LdPlain<double> l{X + (long)col * ld};
+    engine<double, PPT>(g, band, zc, vs, l, ep, lds_ptr<double>());
+    block_sums<4>(ep.acc, red);
+    if (threadIdx.x == 0) {
+        const long o = (long)col * g.tiles() + tile;
+        part[o] = ep.acc[0];
+        part[qs + o] = ep.acc[1];
+        part[2 * qs + o] = ep.acc[1];
+        outer[o] = ep.acc[2];
+        outer[qs + o] = ep.acc[3];
+    }
+}
+
 // r = b - H x0 (or r = b, x = 0); partials rz (q0), rr (q1), bb (q2)
 template <typename T>
 struct EpInit {
@@ -509,15 +557,63 @@ __global__ void k_colsum(const double *__restrict__ part, int tiles, int ncols, 
     }
 }
 
-__global__ void k_refine_axpy(double *__restrict__ X, long ld, const float *__restrict__ D,
-                              long ld32, long ng, const int *__restrict__ mask) {
+__global__ void k_refine_axpy(double *__restrict__ X, long ld, float *__restrict__ D,
+                              long ld32, long ng, const int *__restrict__ mask, int zero_d) {
     const int c = blockIdx.y;
     if (!mask[c]) return;
     double *x = X + (long)c * ld;
-    const float *d = D + (long)c * ld32;
+    float *d = D + (long)c * ld32;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ng;
-         i += (long)gridDim.x * blockDim.x)
+         i += (long)gridDim.x * blockDim.x) {
         x[i] += (double)d[i];
+        if (zero_d) d[i] = 0.f;
+    }
+}
+
+// Reliable-update bookkeeping, one thread per column.
+//   check:    need[c] = active[c] && (||r32|| < delta rref[c] || ||r32|| <= tol ||b||)
+//   finalize: for need[c]: rref[c] = ||r||; ||r|| <= tol ||b|| -> active[c] = 0 (done)
+__global__ void k_rel_check(const double *__restrict__ part, int tiles, long qs, int ncols,
+                            const int *__restrict__ active, const double *__restrict__ rref,
+                            const double *__restrict__ bb64, double delta, double tol,
+                            int *__restrict__ need, int *__restrict__ nneed) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncols;
+         c += gridDim.x * blockDim.x) {
+        int m = 0;
+        if (active[c]) {
+            double rr = 0.0;
+            for (int t = 0; t < tiles; ++t) rr += part[qs + (long)c * tiles + t];
+            const double rn = sqrt(rr);
+            m = (rn < delta * rref[c] || rn <= tol * sqrt(bb64[c]) || !isfinite(rn)) ? 1 : 0;
+        }
+        need[c] = m;
+        if (m) atomicAdd(nneed, 1);
+    }
+}
+
+__global__ void k_rel_finalize(const double *__restrict__ outer, int tiles, long qs, int ncols,
+                               const int *__restrict__ need, int *__restrict__ active,
+                               double *__restrict__ rref, double *__restrict__ bb64, double tol,
+                               int init, int *__restrict__ nactive, int *__restrict__ err) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncols;
+         c += gridDim.x * blockDim.x) {
+        if (need[c]) {
+            double rr = 0.0, bb = 0.0;
+            for (int t = 0; t < tiles; ++t) {
+                rr += outer[(long)c * tiles + t];
+                bb += outer[qs + (long)c * tiles + t];
+            }
+            if (!isfinite(rr) || !isfinite(bb)) {
+                atomicMax(&err[0], 7);
+                atomicMin(&err[1], c);
+            }
+            rref[c] = sqrt(rr);
+            if (init) bb64[c] = bb;
+            const bool done = sqrt(rr) <= tol * sqrt(bb64[c]);
+            active[c] = done ? 0 : 1;
+        }
+        if (active[c]) atomicAdd(nactive, 1);
+    }
 }
 
 // sums: [0..ncols) = rr, [ncols..2ncols) = bb.  For active columns the inner
@@ -678,13 +774,42 @@ hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long 
     return hipGetLastError();
 }
 
-hipError_t launch_refine_axpy(double *X, long ld, const float *D, long ld32, long ng, int ncols,
-                              const int *mask, hipStream_t st) {
+hipError_t launch_refine_axpy(double *X, long ld, float *D, long ld32, long ng, int ncols,
+                              const int *mask, int zero_d, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
     long blocks = (ng + 1023) / 1024;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_refine_axpy, dim3((unsigned)blocks, ncols), dim3(256), 0, st, X, ld, D,
-                       ld32, ng, mask);
+                       ld32, ng, mask, zero_d);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_rel(const Grid &g, const double *vs, const float *dinv32, const double *B,
+                            const double *X, long ld, float *R32, int ncols, const int *mask,
+                            double *part, double *outer, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const long qs = (long)ncols * g.tiles();
+    const dim3 grid(ncols * g.tiles());
+    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL(k_resid_rel<P>, grid, dim3(kThreads),
+                                              lds_bytes(g, 8), st, g, vs, dinv32, B, X, ld, R32,
+                                              mask, part, qs, outer));
+    return hipGetLastError();
+}
+
+hipError_t launch_rel_check(const double *part, int tiles, int ncols, const int *active,
+                            const double *rref, const double *bb64, double delta, double tol,
+                            int *need, int *nneed, hipStream_t st) {
+    hipLaunchKernelGGL(k_rel_check, dim3((ncols + 255) / 256), dim3(256), 0, st, part, tiles,
+                       (long)ncols * tiles, ncols, active, rref, bb64, delta, tol, need, nneed);
+    return hipGetLastError();
+}
+
+hipError_t launch_rel_finalize(const double *outer, int tiles, int ncols, const int *need,
+                               int *active, double *rref, double *bb64, double tol, int init,
+                               int *nactive, int *err, hipStream_t st) {
+    hipLaunchKernelGGL(k_rel_finalize, dim3((ncols + 255) / 256), dim3(256), 0, st, outer, tiles,
+                       (long)ncols * tiles, ncols, need, active, rref, bb64, tol, init, nactive,
+                       err);
     return hipGetLastError();
 }
 

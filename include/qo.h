@@ -84,6 +84,8 @@ typedef struct {
     int refine_rounds[2];  /* QO_MIXED: refinement rounds per solve; 1 in QO_FP64 */
     int energy_rose;       /* 1 if E_sigma increased in this step (tau too large) */
     int step_index;        /* n + 1 after the step */
+    double orth_err_next;  /* ||O_{n+1}||_F from the Gram recurrence of Sec. 4.1,
+                              O_{n+1} = O_n - tau (A_n O_n + O_n A_n) + tau^2 O_n B_n O_n */
     double t_phase_ms[8];  /* solve1, gram1, small, update, solve2, gram2, correct, energy */
 } qo_step_stats;
 
@@ -137,6 +139,26 @@ qo_status qo_gram(qo_handle h, double *S, double *K);
  * must be NULL).  evals: N host doubles, ascending. */
 qo_status qo_eigenpairs(qo_handle h, int mode, double *evals, double *evecs, long ld,
                         int on_device);
+
+/* Algorithm 1 of Sec. 5: take steps while ||grad_G E_G(U_n)|| > grad_tol, at most
+ * max_steps.  The gradient of U_n is evaluated inside the step (after G U_n), so the
+ * loop stops before updating a U_n that already passes the test.  tau_max > 0
+ * selects the adaptive time step (tau is kept <= tau_max) of the algorithm's "select tau_n <= delta_T": a
+ * step that fails (singular Gram matrix, PCG limit, non-finite data), raises E_sigma
+ * or lets ||<U,U> - I|| grow is undone and retried with tau/2 (E_sigma alone can fall
+ * by shrinking U out of the quasi-Stiefel set when tau is too large); an accepted step
+ * grows tau by 1.25 up to tau_max; tau_max <= 0 keeps tau fixed.  out_steps (may be
+ * NULL): accepted steps; out_tau (may be NULL): the step size at exit; last (may be
+ * NULL): statistics of the last accepted step; *converged (may be NULL): 1 when the
+ * gradient test passed. */
+qo_status qo_run(qo_handle h, double tau, double tau_max, int max_steps, double grad_tol,
+                 int *out_steps, double *out_tau, int *converged, qo_step_stats *last);
+
+/* Gradient of the sum of the N Ritz values of span U_n with respect to the potential:
+ * g_j = d(theta_1 + ... + theta_N)/dV_j = h^d (U S^{-1} U^T)_jj, S = <U,U> (U held fixed;
+ * at convergence this is the Hellmann-Feynman gradient of lambda_1 + ... + lambda_N, the
+ * eigenvalues of Sec. 2.2).  g: Ng values (device pointer when on_device). */
+qo_status qo_eigsum_gradient(qo_handle h, double *g, int on_device);
 
 qo_status qo_destroy(qo_handle h);
 const char *qo_status_string(qo_status s);

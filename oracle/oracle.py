@@ -294,11 +294,16 @@ class Oracle:
             raise RuntimeError(f"oracle PCG failed with status {st}")
         return X, it
 
-    def step(self, tau):
+    def step(self, tau, grad_stop=None):
+        """One step of the scheme; with grad_stop, return None (U_n kept) when
+        ||grad_G E_G(U_n)|| <= grad_stop (the test of Alg. 1, taken before the update)."""
         prob, U = self.prob, self.U
         x0 = self.prevQ if (self.warm and self.prevQ is not None) else None
         P, itP = self._G(U, x0)
         gnorm = grad_norm(prob, U, P)
+        if grad_stop is not None and gnorm <= grad_stop:
+            self.prevQ = P
+            return None
         U_hat, X, Y, (S, M, R) = predictor(prob, U, P, tau)
         x0Q = None
         if self.warm:
@@ -319,6 +324,17 @@ class Oracle:
     def run(self, tau, nsteps):
         return [self.step(tau) for _ in range(nsteps)]
 
+    def algorithm1(self, tau, grad_tol, max_steps):
+        """Alg. 1 with a fixed step: iterate while ||grad_G E_G(U_n)|| > grad_tol.
+        Returns the number of steps taken and the statistics of the last one."""
+        last = None
+        for k in range(max_steps):
+            st = self.step(tau, grad_stop=grad_tol)
+            if st is None:
+                return k, last
+            last = st
+        return max_steps, last
+
 
 # ---------------------------------------------------------------------------
 # Sec. 5: eigenvalue read-out and error measures
@@ -337,6 +353,17 @@ def ritz(prob: Problem, U):
     S = 0.5 * (S + S.T)
     theta, c = sla.eigh(K, S)
     return theta - prob.sigma, c
+
+
+def eigsum_gradient(prob: Problem, U):
+    """d(theta_1 + ... + theta_N)/dV_j for the Ritz values of span U at fixed U:
+    sum theta = tr(S^{-1} K) with K = <U, H U>, dK/dV_j = h^d u_j u_j^T (u_j = row j of U),
+    so the derivative is h^d u_j^T S^{-1} u_j.  At an exact eigenbasis it is the
+    Hellmann-Feynman derivative of lambda_1 + ... + lambda_N (eigenvalues of Sec. 2.2)."""
+    U = np.asarray(U)
+    S = prob.inner(U, U)
+    Sinv = np.linalg.inv(0.5 * (S + S.T))
+    return prob.w * np.einsum("ja,ab,jb->j", U, Sinv, U)
 
 
 def paper_eigenvalues(prob: Problem, U, P):

@@ -30,6 +30,7 @@ EXPORTS = [
     "qo_create", "qo_set_potential", "qo_set_state", "qo_get_state", "qo_step", "qo_energy",
     "qo_gram", "qo_eigenpairs", "qo_destroy", "qo_status_string", "qo_last_error", "qo_apply",
     "qo_solve", "qo_gram_pair", "qo_get_block", "qo_get_matrix", "qo_profile", "qo_profile_get",
+    "qo_run", "qo_eigsum_gradient",
 ]
 KERNELS = ["sweep1_f64", "sweep2_f64", "sweep1_f32", "sweep2_f32", "gram", "update", "resid",
            "cg_f64", "cg_f32"]
@@ -51,7 +52,7 @@ class QoStepStats(ctypes.Structure):
         ("orth_err_fro", ctypes.c_double), ("grad_norm", ctypes.c_double),
         ("pcg_iters", ctypes.c_int * 2), ("refine_rounds", ctypes.c_int * 2),
         ("energy_rose", ctypes.c_int), ("step_index", ctypes.c_int),
-        ("t_phase_ms", ctypes.c_double * 8),
+        ("orth_err_next", ctypes.c_double), ("t_phase_ms", ctypes.c_double * 8),
     ]
 
     def as_dict(self):
@@ -60,6 +61,7 @@ class QoStepStats(ctypes.Structure):
             "orth_err_fro": self.orth_err_fro, "grad_norm": self.grad_norm,
             "pcg_iters": tuple(self.pcg_iters), "refine_rounds": tuple(self.refine_rounds),
             "energy_rose": bool(self.energy_rose), "step_index": self.step_index,
+            "orth_err_next": self.orth_err_next,
             "t_phase_ms": tuple(self.t_phase_ms),
         }
 
@@ -107,6 +109,9 @@ def load_library(path: str = LIB_PATH):
         "qo_get_block": ([H, ctypes.c_int, vp, ctypes.c_long, ctypes.c_int], ctypes.c_int),
         "qo_get_matrix": ([H, ctypes.c_int, vp], ctypes.c_int),
         "qo_profile": ([H, ctypes.c_int], ctypes.c_int),
+        "qo_eigsum_gradient": ([H, vp, ctypes.c_int], ctypes.c_int),
+        "qo_run": ([H, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double, ip,
+                    dp, ip, ctypes.POINTER(QoStepStats)], ctypes.c_int),
         "qo_profile_get": ([H, ctypes.POINTER(QoProfileData)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -246,6 +251,25 @@ class Solver:
         s = QoStepStats()
         self._chk(self.lib.qo_step(self.h, float(tau), int(nsteps), ctypes.byref(s)))
         return s.as_dict()
+
+    def run(self, tau, max_steps, grad_tol=1e-5, tau_max=None):
+        """Algorithm 1: steps until ||grad|| <= grad_tol (adaptive tau when tau_max is given).
+        Returns (steps, tau_at_exit, converged, stats_of_last_step)."""
+        s = QoStepStats()
+        n, c = ctypes.c_int(), ctypes.c_int()
+        t = ctypes.c_double()
+        self._chk(self.lib.qo_run(self.h, float(tau), float(tau_max or 0.0), int(max_steps),
+                                  float(grad_tol), ctypes.byref(n), ctypes.byref(t),
+                                  ctypes.byref(c), ctypes.byref(s)))
+        return n.value, t.value, bool(c.value), s.as_dict()
+
+    def eigsum_gradient(self):
+        """d(sum of the N Ritz values)/dV = h^d diag(U S^{-1} U^T), as a CUDA tensor (Ng,)."""
+        import torch
+
+        g = torch.empty(self.ng, dtype=torch.float64, device="cuda")
+        self._chk(self.lib.qo_eigsum_gradient(self.h, ctypes.c_void_p(g.data_ptr()), 1))
+        return g
 
     def energy(self):
         e, es = ctypes.c_double(), ctypes.c_double()

@@ -625,7 +625,10 @@ void rec(qo_ctx *c, int i) {
     if (c->ev_ok) (void)hipEventRecord(c->ev[i], c->st);
 }
 
-qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats) {
+// grad_stop > 0: after G U_n and the Gram matrix, stop (return QO_OK with
+// *stopped = 1, U_n untouched) when ||grad_G E_G(U_n)|| <= grad_stop.
+qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop = 0.0,
+                   int *stopped = nullptr) {
     const int N = c->N;
     const int N2 = 2 * N;
     hipStream_t st = c->st;
@@ -647,6 +650,22 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats) {
     const double alpha = 0.5 * tau;
     HIPC(c, hipMemsetAsync(c->dstatus, 0, sizeof(int), st));
     HIPC(c, nn_grad2(S, M, R, N2, N, mp(c, MP_MS), N, c->dscal + 0, st));
+    if (stopped) *stopped = 0;
+    if (grad_stop > 0.0) {
+        HIPC(c, hipMemcpyAsync(c->h_scal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPC(c, hipStreamSynchronize(st));
+        const double g2 = c->h_scal[0];
+        if ((g2 > 0.0 ? sqrt(g2) : 0.0) <= grad_stop) {
+            // U_n passes the test: keep it; G U_n is the warm start of a later solve
+            if (stopped) *stopped = 1;
+            if (stats) {
+                memset(stats, 0, sizeof *stats);
+                stats->grad_norm = g2 > 0.0 ? sqrt(g2) : 0.0;
+                stats->step_index = (int)c->nstep;
+            }
+            return QO_OK;
+        }
+    }
     // C = S^{-1} M
     HIPC(c, nn_axpby(mp(c, MP_SW), N, 1.0, S, N2, 0.0, nullptr, N, false, 0.0, N, N, st));
     HIPC(c, nn_axpby(mp(c, MP_C), N, 1.0, M, N2, 0.0, nullptr, N, false, 0.0, N, N, st));
@@ -691,6 +710,20 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats) {
     HIPC(c, nn_axpby(mp(c, MP_O), N, 0.5, c->G2, N2, 0.5, c->G2, N2, true, -1.0, N, N, st));
     HIPC(c, nn_axpby(mp(c, MP_OR), N, -tau, mp(c, MP_O), N, 0.0, nullptr, N, false, 0.0, N, N, st));
     HIPC(c, nn_fro(mp(c, MP_O), N, N, c->dscal + 1, st));
+    // ||O_{n+1}|| by the Gram recurrence with A = sym<U_hat,Q>, B = <Q,Q>
+    {
+        double *Am = mp(c, MP_T1), *T2 = mp(c, MP_T2), *On = mp(c, MP_T3);
+        HIPC(c, nn_axpby(Am, N, 0.5, c->G2 + (size_t)N * N2, N2, 0.5, c->G2 + (size_t)N * N2, N2,
+                         true, 0.0, N, N, st));
+        HIPC(c, nn_axpby(On, N, 1.0, mp(c, MP_O), N, 0.0, nullptr, N, false, 0.0, N, N, st));
+        HIPC(c, nn_gemm(On, N, Am, N, false, mp(c, MP_O), N, false, N, N, N, -tau, 1.0, 0.0, st));
+        HIPC(c, nn_gemm(On, N, mp(c, MP_O), N, false, Am, N, false, N, N, N, -tau, 1.0, 0.0, st));
+        HIPC(c, nn_gemm(T2, N, c->G2 + (size_t)N * N2 + N, N2, false, mp(c, MP_O), N, false, N, N,
+                        N, 1.0, 0.0, 0.0, st));
+        HIPC(c, nn_gemm(On, N, mp(c, MP_O), N, false, T2, N, false, N, N, N, tau * tau, 1.0, 0.0,
+                        st));
+        HIPC(c, nn_fro(On, N, N, c->dscal + 2, st));
+    }
     QOC(tsgemm(c, c->U, c->Uh, nullptr, nullptr, Q, mp(c, MP_OR)));
     rec(c, 7);
     // the state has moved: commit bookkeeping before the (non-failing) diagnostics
@@ -702,7 +735,7 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats) {
     double Es = 0.0, trS = 0.0;
     QOC(energy_of(c, c->U, &Es, &trS));
     rec(c, 8);
-    HIPC(c, hipMemcpyAsync(c->h_scal, c->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(c, hipMemcpyAsync(c->h_scal, c->dscal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPC(c, hipStreamSynchronize(st));
     prof_harvest(c);
     if (stats) {
@@ -722,6 +755,7 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats) {
         stats->refine_rounds[0] = rP;
         stats->refine_rounds[1] = rQ;
         stats->energy_rose = (c->have_Es && Es > c->last_Es) ? 1 : 0;
+        stats->orth_err_next = c->h_scal[2];
         stats->step_index = (int)c->nstep;
         if (c->ev_ok)
             for (int i = 0; i < 8; ++i) {
@@ -769,6 +803,17 @@ __global__ void k_prep_potential(const double *__restrict__ V, long ng, double s
             dinv32[i] = (float)(1.0 / ((double)(float)c0 + (double)(float)s));
         }
         if (!(c0 + s > 0.0)) atomicMax(bad, 5);
+    }
+}
+
+// g[j] = w * sum_c Y[c][j] U[c][j]   (row-wise dot of two column-major blocks)
+__global__ void k_rowdot(const double *__restrict__ Y, const double *__restrict__ U, long ld,
+                         long ng, int n, double w, double *__restrict__ g) {
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < ng;
+         j += (long)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < n; ++c) s += Y[(long)c * ld + j] * U[(long)c * ld + j];
+        g[j] = w * s;
     }
 }
 
@@ -995,6 +1040,64 @@ qo_status qo_step(qo_handle h, double tau, int nsteps, qo_step_stats *last) {
     return QO_OK;
 }
 
+qo_status qo_run(qo_handle h, double tau, double tau_max, int max_steps, double grad_tol,
+                 int *out_steps, double *out_tau, int *converged, qo_step_stats *last) {
+    if (!h) return QO_ERR_ARG;
+    if (!(tau > 0.0) || !std::isfinite(tau) || max_steps < 0 || !(grad_tol >= 0.0) ||
+        !std::isfinite(tau_max))
+        return fail(h, QO_ERR_ARG, "bad tau, tau_max, max_steps or grad_tol");
+    if (!h->have_V || !h->have_U) return fail(h, QO_ERR_STATE, "set potential and state first");
+    const bool adapt = tau_max > 0.0;
+    if (adapt && tau > tau_max) tau = tau_max;
+    int steps = 0, conv = 0;
+    qo_step_stats st{};
+    while (steps < max_steps) {
+        if (adapt) {  // backup for an undo
+            HIPC(h, hipMemcpyAsync(h->W2, h->U, sizeof(double) * h->ld * h->N,
+                                   hipMemcpyDeviceToDevice, h->st));
+        }
+        const int cur0 = h->cur;
+        const bool warm0 = h->have_warm, hasE0 = h->have_Es;
+        const double E0 = h->last_Es;
+        const long n0 = h->nstep;
+        int stopped = 0;
+        const qo_status ss = one_step(h, tau, &st, grad_tol, &stopped);
+        const bool step_failed =
+            ss == QO_ERR_NOT_SPD || ss == QO_ERR_PCG_NOCONV || ss == QO_ERR_NONFINITE;
+        if (ss != QO_OK && !(adapt && step_failed)) return ss;
+        if (ss == QO_OK && stopped) {
+            conv = 1;
+            break;
+        }
+        const bool o_grew = st.orth_err_next > st.orth_err_fro * (1.0 + 1e-12) &&
+                            st.orth_err_next > 1e-10;
+        const bool reject = step_failed || st.energy_rose || o_grew;
+        if (adapt && reject) {
+            if (!(tau > 1e-12 * tau_max))
+                return fail(h, ss != QO_OK ? ss : QO_ERR_NOT_SPD,
+                            "adaptive time step fell below 1e-12 tau_max");
+            // undo: U_n back, its G U_n (in PQ[cur0]) stays the warm start
+            HIPC(h, hipMemcpyAsync(h->U, h->W2, sizeof(double) * h->ld * h->N,
+                                   hipMemcpyDeviceToDevice, h->st));
+            HIPC(h, hipStreamSynchronize(h->st));
+            h->cur = cur0;
+            h->have_warm = ss == QO_OK ? true : warm0;
+            h->have_Es = hasE0;
+            h->last_Es = E0;
+            h->nstep = n0;
+            tau *= 0.5;
+            continue;
+        }
+        ++steps;
+        if (last) *last = st;
+        if (adapt) tau = fmin(tau_max, 1.25 * tau);
+    }
+    if (out_steps) *out_steps = steps;
+    if (out_tau) *out_tau = tau;
+    if (converged) *converged = conv;
+    return QO_OK;
+}
+
 qo_status qo_energy(qo_handle h, double *E, double *E_shifted) {
     if (!h) return QO_ERR_ARG;
     if (!h->have_V || !h->have_U) return fail(h, QO_ERR_STATE, "set potential and state first");
@@ -1077,6 +1180,34 @@ qo_status qo_eigenpairs(qo_handle h, int mode, double *evals, double *evecs, lon
         HIPC(h, nn_sort(ev, nullptr, N, N, false, h->sortwork, st));
     }
     HIPC(h, hipMemcpyAsync(evals, ev, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HIPC(h, hipStreamSynchronize(st));
+    return QO_OK;
+}
+
+qo_status qo_eigsum_gradient(qo_handle h, double *g, int on_device) {
+    if (!h || !g) return h ? fail(h, QO_ERR_ARG, "null output") : QO_ERR_ARG;
+    if (!h->have_U) return fail(h, QO_ERR_STATE, "set the state first");
+    const int N = h->N;
+    hipStream_t st = h->st;
+    // S = <U,U>;  Sinv by Gauss-Jordan (SPD);  Y = U S^{-1};  g = h^d rowdot(Y, U)
+    QOC(gram64(h, h->U, h->U, h->ld, N, h->G2));
+    HIPC(h, hipMemsetAsync(h->dstatus, 0, sizeof(int), st));
+    HIPC(h, nn_axpby(mp(h, MP_T1), N, 1.0, h->G2, 2 * N, 0.0, nullptr, N, false, 0.0, N, N, st));
+    HIPC(h, nn_axpby(mp(h, MP_T2), N, 0.0, nullptr, N, 0.0, nullptr, N, false, 1.0, N, N, st));
+    HIPC(h, nn_gj_solve(mp(h, MP_T1), N, mp(h, MP_T2), N, N, N, true, h->dstatus, st));
+    QOC(check_status(h, "eigsum gradient: <U,U> not positive definite"));
+    // row-major copy of S^{-1} (symmetric up to rounding; symmetrise)
+    HIPC(h, nn_axpby(mp(h, MP_T3), N, 0.5, mp(h, MP_T2), N, 0.5, mp(h, MP_T2), N, true, 0.0, N, N, st));
+    HIPC(h, launch_tsgemm(h->W, h->ld, nullptr, h->U, mp(h, MP_T3), nullptr, nullptr, h->ld, h->ng,
+                          N, st));
+    double *dst = on_device ? g : h->W2;
+    long blocks = (h->ng + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_rowdot, dim3((unsigned)blocks), dim3(256), 0, st, h->W, h->U, h->ld,
+                       h->ng, N, h->w, dst);
+    HIPC(h, hipGetLastError());
+    if (!on_device)
+        HIPC(h, hipMemcpyAsync(g, h->W2, sizeof(double) * h->ng, hipMemcpyDeviceToHost, st));
     HIPC(h, hipStreamSynchronize(st));
     return QO_OK;
 }

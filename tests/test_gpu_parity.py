@@ -349,3 +349,57 @@ def test_error_paths(torch, B):
         with pytest.raises(B.QOError) as e:
             s.step(5.0)
         assert e.value.status == B.QO_ERR_STATE
+
+
+def test_algorithm1_fixed_and_adaptive(torch, B, oracle_mod):
+    """Algorithm 1 (Sec. 5) through qo_run: with a fixed step the number of steps to
+    ||grad|| <= 1e-6 matches the oracle's (within one step: the test compares a floating-point
+    norm with a threshold) and the final state agrees; the adaptive step (undo and halve on an
+    energy rise, grow up to tau_max) converges to the same eigenvalues and keeps E_sigma
+    monotone over accepted steps."""
+    n, N = (32, 32), 4
+    V = inputs.harmonic(n, 100.0)
+    U0 = inputs.random_block(1024, N, seed=1)
+    lam1 = 12.9544687
+    prob = oracle_mod.Problem(2, n, V)
+    ref = oracle_mod.Oracle(prob, U0, tol=1e-12, variant=0)
+    kref, _ = ref.algorithm1(0.9 * lam1, 1e-6, 1000)
+    with B.Solver(2, n, N, pcg_tol=1e-12, pcg_variant=0) as s:
+        s.set_potential(V)
+        s.set_state(U0)
+        k, tau_end, conv, st = s.run(0.9 * lam1, 1000, grad_tol=1e-6)
+        U = B.to_numpy(s.get_state())
+        lam_fixed = s.eigenpairs("ritz")
+    assert conv and abs(k - kref) <= 1
+    if k == kref:
+        assert np.max(np.abs(U - ref.U)) <= 1e-9 * np.max(np.abs(ref.U))
+    with B.Solver(2, n, N, pcg_tol=1e-12, pcg_variant=0) as s:
+        s.set_potential(V)
+        s.set_state(U0)
+        energies = []
+        steps, conv2 = 0, False
+        tau = 0.3 * lam1
+        while steps < 2000 and not conv2:
+            k2, tau, conv2, st = s.run(tau, 1, grad_tol=1e-6, tau_max=3.0 * lam1)
+            steps += k2
+            if k2:
+                energies.append(st["energy_shifted"])
+        lam_ad = s.eigenpairs("ritz")
+    assert conv2
+    assert np.all(np.diff(energies) <= 1e-9 * np.abs(np.array(energies[1:])))
+    np.testing.assert_allclose(lam_ad, lam_fixed, rtol=1e-9)
+
+
+def test_eigsum_gradient(torch, B, oracle_mod):
+    """d(sum of Ritz values)/dV = h^d diag(U S^{-1} U^T) on a non-orthogonal 3-D block:
+    GPU against the oracle's formula (1e-12 relative to the max entry)."""
+    n, N = (13, 11, 10), 5
+    V = inputs.gaussian_wells(n, seed=0)
+    U0 = inputs.random_block(int(np.prod(n)), N, seed=1)
+    prob = oracle_mod.Problem(3, n, V)
+    ref = oracle_mod.eigsum_gradient(prob, U0)
+    with B.Solver(3, n, N) as s:
+        s.set_potential(V)
+        s.set_state(U0)
+        g = s.eigsum_gradient().cpu().numpy()
+    assert np.max(np.abs(g - ref)) <= 1e-12 * np.max(np.abs(ref))

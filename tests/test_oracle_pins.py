@@ -389,3 +389,27 @@ def test_pcg_one_reduction_form(oracle_mod):
     neg = O.Problem(2, (6, 6), np.zeros(36), sigma=-2 * lam1)
     _, _, st, _ = neg.solve(mode[:, None], tol=1e-12, variant=1)
     assert st == O.ORC_NOT_SPD
+
+
+def test_eigsum_gradient_finite_differences(oracle_mod):
+    """d(lambda_1 + ... + lambda_N)/dV_j at an exact eigenbasis equals h^d diag(U S^{-1} U^T)_j
+    (Hellmann-Feynman): checked by central differences of dense eigenvalues on a 5 x 4 x 3 grid."""
+    O = oracle_mod
+    n = (5, 4, 3)
+    V = inputs.gaussian_wells(n, seed=0)
+    prob = O.Problem(3, n, V)
+    H = dense_H(3, n, (1, 1, 1), 0.5, 0.0, prob.V)
+    ev, vec = np.linalg.eigh(H)
+    N = 3
+    assert ev[N] - ev[N - 1] > 1.0
+    U = vec[:, :N] * 1.7 + vec[:, :N] @ np.array([[1, .2, 0], [0, 1, .3], [0, 0, 1.]])  # any basis
+    g = O.eigsum_gradient(prob, U)
+    eps = 1e-4
+    for j in [0, 7, 23, 41, 59]:
+        dV = np.zeros(prob.ng)
+        dV[j] = eps
+        ep = np.linalg.eigvalsh(dense_H(3, n, (1, 1, 1), 0.5, 0.0, prob.V + dV))[:N].sum()
+        em = np.linalg.eigvalsh(dense_H(3, n, (1, 1, 1), 0.5, 0.0, prob.V - dV))[:N].sum()
+        # the discrete eigenvalue problem is H u = lambda u with mass h^d: dlambda/dV_j = u_j^2
+        # for Euclidean-normalised u; in the grid inner product this is h^d * (grid u_j)^2
+        assert abs((ep - em) / (2 * eps) - g[j]) <= 1e-6 * max(1.0, abs(g[j]))

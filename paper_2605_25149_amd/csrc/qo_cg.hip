@@ -63,8 +63,9 @@ __global__ __launch_bounds__(kThreads) void k_cg_step(CgArgs<T> a) {
     __shared__ double sh_alpha, sh_beta;
     const Grid &g = a.g;
     const int tiles = g.tiles();
-    const int col = blockIdx.x / tiles;
-    const int tile = blockIdx.x - col * tiles;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int col = L / tiles;
+    const int tile = L - col * tiles;
     const int band = tile / g.nzc;
     const int zc = tile - band * g.nzc;
     const bool lead = tile == 0;

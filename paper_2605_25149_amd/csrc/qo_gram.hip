@@ -70,9 +70,12 @@ __global__ __launch_bounds__(64) void k_gram_f64(const double *__restrict__ X,
                                                  int vec_ok) {
     const int nn = 2 * n;
     const int nt = (nn + TM - 1) / TM;
+    // pairs of one K-chunk on one XCD: they read the same rows of the 2n columns
+    const int npairs = nt * (nt + 1) / 2;
+    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int split = L / npairs;
     int ti, tj;
-    tile_pair(blockIdx.x, nt, ti, tj);
-    const int split = blockIdx.y;
+    tile_pair(L - split * npairs, nt, ti, tj);
     const long kb = (long)split * kchunk;
     const long ke = min(ng, kb + kchunk);
     const int lane = threadIdx.x;
@@ -149,9 +152,12 @@ __global__ __launch_bounds__(64) void k_gram_bf16(const double *__restrict__ X,
                                                   int vec_ok) {
     const int nn = 2 * n;
     const int nt = (nn + TM - 1) / TM;
+    // pairs of one K-chunk on one XCD: they read the same rows of the 2n columns
+    const int npairs = nt * (nt + 1) / 2;
+    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int split = L / npairs;
     int ti, tj;
-    tile_pair(blockIdx.x, nt, ti, tj);
-    const int split = blockIdx.y;
+    tile_pair(L - split * npairs, nt, ti, tj);
     const long kb = (long)split * kchunk;
     const long ke = min(ng, kb + kchunk);
     const int lane = threadIdx.x;

@@ -23,6 +23,16 @@ struct Grid {
 
 constexpr int kThreads = 256;
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2):
+// dispatch index b runs on XCD b % 8.  Remap so that XCD x works through one
+// contiguous range of logical indices in order; neighbouring tiles (which share
+// halo rows or operand panels) then meet in the same L2.  A bijection of [0, B).
+__device__ __forceinline__ int xcd_remap(int b, int B) {
+    const int x = b & 7, s = b >> 3;
+    const int q = B >> 3, r = B & 7;
+    return x * q + (x < r ? x : r) + s;
+}
+
 // Per-column PCG bookkeeping on the device (double-buffered by iteration parity).
 struct PcgState {
     double *rho;    // [2][ncap]

@@ -198,8 +198,9 @@ struct NoRaw {};
 
 __device__ __forceinline__ void tile_of(const Grid &g, int &col, int &tile, int &band, int &zc) {
     const int tiles = g.tiles();
-    col = blockIdx.x / tiles;
-    tile = blockIdx.x - col * tiles;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    col = L / tiles;
+    tile = L - col * tiles;
     band = tile / g.nzc;
     zc = tile - band * g.nzc;
 }

@@ -27,8 +27,11 @@ __global__ __launch_bounds__(64) void k_tsgemm(double *__restrict__ Out, long ld
                                                int n) {
     const int lane = threadIdx.x;
     const int lr = lane & 15, lg = lane >> 4;
-    const long m0 = (long)blockIdx.x * 64;
-    const int c0 = blockIdx.y * 64;
+    // column tiles of one row panel on one XCD: they read the same rows of A and B
+    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int rt = L / gridDim.y;
+    const long m0 = (long)rt * 64;
+    const int c0 = (L - rt * gridDim.y) * 64;
 
     v4d acc[4][4];  // [column block j][row block i]
 #pragma unroll

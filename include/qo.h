@@ -72,6 +72,15 @@ typedef struct {
                                 1: Chronopoulos-Gear form, one sweep per iteration
                                    (3-D, or 2-D with n_0 <= 256); same iterates in exact
                                    arithmetic */
+    int precond;             /* PCG preconditioner (the solver of G is left open by Sec. 4.1;
+                                the concluding section asks for a better one than the diagonal):
+                                0: Jacobi, M = diag(H_sigma);
+                                1: fast-Poisson, M = kappa (-Lap_h) + vbar with
+                                   vbar = max(0, mean(V + sigma)), inverted exactly by type-I
+                                   discrete sine transforms (FP16 matrix cores, FP32
+                                   accumulation); iteration count independent of h.  Needs
+                                   pcg_variant 0 and n_0, n_1 <= 128, n_2 <= 256 (3-D) or
+                                   n_0, n_1 <= 256 (2-D) */
 } qo_config;
 
 typedef struct {
@@ -169,12 +178,19 @@ const char *qo_last_error(qo_handle h);
 /* Y = H_sigma X (the stencil of the operator, Sec. 2.1 discretised). */
 qo_status qo_apply(qo_handle h, const double *X, double *Y, long ld, int ncols);
 
-/* X = G B = H_sigma^{-1} B per column (Sec. 3.1), Jacobi-PCG in FP64, or in
- * QO_MIXED FP32 PCG inside FP64 iterative refinement.  use_x0: X holds the
+/* X = G B = H_sigma^{-1} B per column (Sec. 3.1), PCG (preconditioner per
+ * cfg.precond) in FP64, or in QO_MIXED FP32 PCG with FP64 residual replacement.  use_x0: X holds the
  * starting guess.  iters (host, ncols ints, may be NULL): iterations per
  * column (QO_MIXED: summed over rounds). */
 qo_status qo_solve(qo_handle h, const double *B, double *X, long ld, int ncols, int use_x0,
                    int *iters);
+
+/* Z = M^{-1} R per column with the fast-Poisson preconditioner of the PCG
+ * (precond = 1; needs the potential, which fixes vbar): the same FP16
+ * transform passes the solve runs, so Z equals the exact M^{-1} R up to FP16
+ * rounding (about 1e-3 relative).  rz (host, ncols doubles, may be NULL):
+ * the per-column sums r_i z_i.  A zero column gives a zero column. */
+qo_status qo_precond(qo_handle h, const double *R, double *Z, long ld, int ncols, double *rz);
 
 /* G = <Z,Z> for Z = [X | Y] (2 ncols columns): the 2ncols x 2ncols Gram matrix
  * of Sec. 2.1, column-major host output.  BF16 tiles with FP32 accumulation
@@ -195,7 +211,8 @@ qo_status qo_get_matrix(qo_handle h, int which, double *out);
 typedef enum {
     QO_KERNEL_SWEEP1_F64 = 0, QO_KERNEL_SWEEP2_F64 = 1, QO_KERNEL_SWEEP1_F32 = 2,
     QO_KERNEL_SWEEP2_F32 = 3, QO_KERNEL_GRAM = 4, QO_KERNEL_UPDATE = 5, QO_KERNEL_RESID = 6,
-    QO_KERNEL_CG_F64 = 7, QO_KERNEL_CG_F32 = 8, QO_KERNEL_COUNT = 12
+    QO_KERNEL_CG_F64 = 7, QO_KERNEL_CG_F32 = 8, QO_KERNEL_DST_FWD = 9, QO_KERNEL_DST_PENCIL = 10,
+    QO_KERNEL_DST_INV = 11, QO_KERNEL_COUNT = 12
 } qo_kernel_id;
 typedef struct {
     long launches[QO_KERNEL_COUNT];

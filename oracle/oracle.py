@@ -33,6 +33,12 @@ Readings of the paper taken here (each also listed in the design notes):
       second line of the scheme).
   R5  Warm starts: G U_n starts from the previous G U_hat; G U_hat starts from
       P (X + C Y) with C = <U,U>^{-1} <U,P> (exact when span U is invariant).
+  R6  The paper leaves the solver of G open and its concluding section asks for a
+      better preconditioner than the diagonal one.  ``solve_fast_poisson`` runs PCG
+      with M = kappa*(-Lap_h) + vbar, vbar = max(0, mean(V + sigma)): the operator
+      with V replaced by a constant, inverted exactly by the orthonormal type-I
+      discrete sine transform, which diagonalises the 1-D Dirichlet second
+      difference (``precond_apply``).  Only the iteration count depends on M.
 """
 from __future__ import annotations
 
@@ -169,6 +175,98 @@ class Problem:
                                      maxit, use_x0, _ip(iters), _ip(cst), int(variant))
         return X, iters, int(st), cst
 
+    # ---- fast-Poisson preconditioner (reading R6) ---------------------------
+    def laplace_eigs(self):
+        """Per axis k: eigenvalues of the 1-D Dirichlet second difference -d^2/dx^2,
+        mu_k[j] = (4 / h_k^2) sin^2(pi (j+1) / (2 (n_k + 1))), j = 0..n_k-1; the
+        eigenvector of mu_k[j] is sin(pi (j+1) (i+1) / (n_k + 1)) over i."""
+        return [4.0 / self.h[k] ** 2 * np.sin(np.pi * np.arange(1, self.n[k] + 1)
+                                              / (2.0 * (self.n[k] + 1))) ** 2
+                for k in range(self.dim)]
+
+    def precond_vbar(self):
+        """vbar = max(0, mean(V + sigma)): keeps M = kappa (-Lap_h) + vbar SPD."""
+        return max(0.0, float(np.mean(self.V)) + self.sigma)
+
+    def precond_apply(self, R):
+        """M^{-1} R per column, M = kappa (-Lap_h) + vbar: forward DST-I along every
+        axis, division by lambda = kappa (mu_x + mu_y (+ mu_z)) + vbar, inverse
+        DST-I (the orthonormal DST-I is its own inverse)."""
+        import scipy.fft as sfft
+
+        R = _fcols(R, self.ng)
+        shape = tuple(reversed(self.n))  # x fastest: C-order (z, y, x)
+        mu = self.laplace_eigs()
+        lam = np.full(shape, self.precond_vbar())
+        for k in range(self.dim):
+            ax = self.dim - 1 - k
+            sh = [1] * self.dim
+            sh[ax] = self.n[k]
+            lam = lam + self.kappa * mu[k].reshape(sh)
+        Z = np.empty_like(R, order="F")
+        for j in range(R.shape[1]):
+            r = R[:, j].reshape(shape)
+            rh = sfft.dstn(r, type=1, norm="ortho")
+            Z[:, j] = sfft.idstn(rh / lam, type=1, norm="ortho").reshape(self.ng)
+        return Z
+
+    def solve_fast_poisson(self, B, X0=None, tol=1e-10, maxit=1000):
+        """G B by per-column PCG with the fast-Poisson preconditioner (reading R6).
+
+        Hestenes-Stiefel form: r = b - H x0; until ||r|| <= tol ||b||: z = M^{-1} r,
+        rho = r.z, p = z + (rho / rho_prev) p, q = H p, alpha = rho / p.q,
+        x += alpha p, r -= alpha q.  A column stops at the first iteration whose
+        residual passes the test; iters counts the updates it took.
+        Returns (X, iters, status, col_status) like ``solve``."""
+        B = _fcols(B, self.ng)
+        nc = B.shape[1]
+        X = np.zeros_like(B, order="F") if X0 is None else np.array(_fcols(X0, self.ng),
+                                                                    order="F", copy=True)
+        R = B - self.apply(X) if X0 is not None else B.copy(order="F")
+        bn = np.linalg.norm(B, axis=0)
+        P = np.zeros_like(B, order="F")
+        rho_prev = np.ones(nc)
+        iters = np.zeros(nc, dtype=np.int32)
+        cst = np.zeros(nc, dtype=np.int32)
+        active = np.ones(nc, dtype=bool)
+        for k in range(maxit + 1):
+            rn = np.linalg.norm(R, axis=0)
+            bad = active & ~(np.isfinite(rn))
+            cst[bad] = ORC_NONFINITE
+            active &= ~bad
+            done = active & (rn <= tol * bn)
+            iters[done] = k
+            active &= ~done
+            if not active.any():
+                break
+            if k == maxit:
+                cst[active] = ORC_NOCONV
+                iters[active] = k
+                break
+            cols = np.nonzero(active)[0]
+            Z = self.precond_apply(R[:, cols])
+            rho = np.einsum("ij,ij->j", R[:, cols], Z)
+            beta = np.zeros(len(cols)) if k == 0 else rho / rho_prev[cols]
+            P[:, cols] = Z + P[:, cols] * beta
+            Q = self.apply(P[:, cols])
+            gam = np.einsum("ij,ij->j", P[:, cols], Q)
+            nspd = gam <= 0
+            if nspd.any():
+                cst[cols[nspd]] = ORC_NOT_SPD
+                active[cols[nspd]] = False
+            alpha = np.where(nspd, 0.0, rho / np.where(nspd, 1.0, gam))
+            X[:, cols] += P[:, cols] * alpha
+            R[:, cols] -= Q * alpha
+            rho_prev[cols] = rho
+        st = ORC_OK
+        if (cst == ORC_NONFINITE).any():
+            st = ORC_NONFINITE
+        elif (cst == ORC_NOT_SPD).any():
+            st = ORC_NOT_SPD
+        elif (cst == ORC_NOCONV).any():
+            st = ORC_NOCONV
+        return X, iters, st, cst
+
     def sparse_matrix(self):
         """H_sigma as a scipy sparse matrix (Kronecker sum of 1-D second differences)."""
         import scipy.sparse as sp
@@ -273,7 +371,7 @@ class Oracle:
     """Algorithm 1 driver with a fixed time step (Sec. 5)."""
 
     def __init__(self, prob: Problem, U0, tol=1e-10, maxit=20000, warm_start=True,
-                 direct=False, variant=0):
+                 direct=False, variant=0, precond="jacobi"):
         self.prob = prob
         self.U = np.array(_fcols(U0, prob.ng), order="F", copy=True)
         self.tol = tol
@@ -281,6 +379,7 @@ class Oracle:
         self.warm = warm_start
         self.direct = direct
         self.variant = variant
+        self.precond = precond
         self.prevQ = None
         self.n = 0
         self.last = {}
@@ -288,8 +387,12 @@ class Oracle:
     def _G(self, B, X0):
         if self.direct:
             return self.prob.solve_direct(B), np.zeros(B.shape[1], dtype=np.int32)
-        X, it, st, _ = self.prob.solve(B, X0=X0, tol=self.tol, maxit=self.maxit,
-                                       variant=self.variant)
+        if self.precond == "fast_poisson":
+            X, it, st, _ = self.prob.solve_fast_poisson(B, X0=X0, tol=self.tol,
+                                                        maxit=min(self.maxit, 1000))
+        else:
+            X, it, st, _ = self.prob.solve(B, X0=X0, tol=self.tol, maxit=self.maxit,
+                                           variant=self.variant)
         if st != ORC_OK:
             raise RuntimeError(f"oracle PCG failed with status {st}")
         return X, it

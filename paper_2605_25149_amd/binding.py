@@ -30,10 +30,11 @@ EXPORTS = [
     "qo_create", "qo_set_potential", "qo_set_state", "qo_get_state", "qo_step", "qo_energy",
     "qo_gram", "qo_eigenpairs", "qo_destroy", "qo_status_string", "qo_last_error", "qo_apply",
     "qo_solve", "qo_gram_pair", "qo_get_block", "qo_get_matrix", "qo_profile", "qo_profile_get",
-    "qo_run", "qo_eigsum_gradient",
+    "qo_run", "qo_eigsum_gradient", "qo_precond",
 ]
 KERNELS = ["sweep1_f64", "sweep2_f64", "sweep1_f32", "sweep2_f32", "gram", "update", "resid",
-           "cg_f64", "cg_f32"]
+           "cg_f64", "cg_f32", "dst_fwd", "dst_pencil", "dst_inv"]
+PRECONDS = {"jacobi": 0, "fast_poisson": 1}
 
 
 class QoConfig(ctypes.Structure):
@@ -43,6 +44,7 @@ class QoConfig(ctypes.Structure):
         ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int), ("pcg_check", ctypes.c_int),
         ("precision", ctypes.c_int), ("refine_inner_tol", ctypes.c_double),
         ("warm_start", ctypes.c_int), ("pcg_variant", ctypes.c_int),
+        ("precond", ctypes.c_int),
     ]
 
 
@@ -113,6 +115,7 @@ def load_library(path: str = LIB_PATH):
         "qo_run": ([H, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double, ip,
                     dp, ip, ctypes.POINTER(QoStepStats)], ctypes.c_int),
         "qo_profile_get": ([H, ctypes.POINTER(QoProfileData)], ctypes.c_int),
+        "qo_precond": ([H, vp, vp, ctypes.c_long, ctypes.c_int, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -161,7 +164,7 @@ class Solver:
 
     def __init__(self, dim, n, N, L=(1.0, 1.0, 1.0), kinetic=0.5, sigma=0.0, pcg_tol=1e-10,
                  pcg_maxit=20000, pcg_check=8, precision="fp64", refine_inner_tol=1e-5,
-                 warm_start=True, pcg_variant=0, stream=None):
+                 warm_start=True, pcg_variant=0, precond="jacobi", stream=None):
         import torch
 
         self.lib = load_library()
@@ -182,6 +185,7 @@ class Solver:
         cfg.refine_inner_tol = refine_inner_tol
         cfg.warm_start = 1 if warm_start else 0
         cfg.pcg_variant = int(pcg_variant)
+        cfg.precond = PRECONDS[precond] if isinstance(precond, str) else int(precond)
         self.cfg = cfg
         self.dim, self.N = dim, N
         self.ng = int(np.prod(nn[:dim]))
@@ -327,6 +331,21 @@ class Solver:
         self._chk(self.lib.qo_solve(self.h, ctypes.c_void_p(B.data_ptr()),
                                     ctypes.c_void_p(X.data_ptr()), ld, ncols, use, its))
         return X, np.array(its[:ncols])
+
+    def precond(self, R):
+        """(Z, rz): Z = M^{-1} R with the fast-Poisson preconditioner, rz = r.z per column."""
+        import torch
+
+        ld = _check_block(R, self.ng)
+        ncols = R.shape[0]
+        Z = torch.empty_like(R)
+        if _check_block(Z, self.ng, ncols) != ld:
+            raise ValueError("R must be a contiguous block")
+        rz = np.zeros(ncols)
+        self._chk(self.lib.qo_precond(self.h, ctypes.c_void_p(R.data_ptr()),
+                                      ctypes.c_void_p(Z.data_ptr()), ld, ncols,
+                                      rz.ctypes.data_as(ctypes.c_void_p)))
+        return Z, rz
 
     def gram_pair(self, X, Y):
         ld = _check_block(X, self.ng)

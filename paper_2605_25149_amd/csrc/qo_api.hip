@@ -19,6 +19,7 @@
 //   energy   E_sigma = 1/2 h^d sum_j u_j . H_sigma u_j  (stencil pass)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -79,6 +80,13 @@ struct qo_ctx {
     int *need = nullptr, *nneed = nullptr;
     double rel_delta = 0.1;
     bool rel = true;
+    // fast-Poisson preconditioner (precond == 1)
+    bool dst = false;
+    DstPlan dp{};
+    _Float16 *dS = nullptr, *t1 = nullptr, *t2 = nullptr;
+    float *dmu = nullptr, *pcs = nullptr, *z32 = nullptr;
+    double *z64 = nullptr, *rzp = nullptr, *dsum = nullptr;
+    double mu0 = 0.0;  // mu_x[0] + mu_y[0] (+ mu_z[0]): smallest eigenvalue of -Lap_h
     // pinned host
     int *h_poll = nullptr;
     double *h_scal = nullptr;
@@ -302,7 +310,28 @@ qo_status check_poll_err(qo_ctx *c, int code, int col, const char *what) {
     return fail(c, QO_ERR_DEVICE, "%s: device error code %d", what, code);
 }
 
-// Jacobi-PCG on all columns of B (ld c->ld) into X, precision T.
+// z = M^{-1} r (fast-Poisson preconditioner) for the columns that PCG iteration
+// k updates; partial sums of r.z into c->rzp.
+template <typename T>
+qo_status precondition(qo_ctx *c, const T *R, T *Z, int ncols, int k, double tol,
+                       const int *mask, const PcgState &s) {
+    hipStream_t st = c->st;
+    const long qs = (long)ncols * c->g.tiles();
+    HIPC(c, launch_pc_prep(k, ncols, mask, s, qs, c->g.tiles(), tol, c->ng, c->pcs, st));
+    hipEvent_t e0 = prof_begin(c);
+    HIPC(c, launch_dst_fwd<T>(c->dp, R, c->ld, ncols, c->t1, c->pcs, st));
+    prof_end(c, QO_KERNEL_DST_FWD, e0);
+    hipEvent_t e1 = prof_begin(c);
+    HIPC(c, launch_dst_pencil(c->dp, c->t1, c->t2, c->ld, ncols, c->pcs, st));
+    prof_end(c, QO_KERNEL_DST_PENCIL, e1);
+    hipEvent_t e2 = prof_begin(c);
+    HIPC(c, launch_dst_inv<T>(c->dp, c->t2, R, Z, c->ld, ncols, c->pcs, c->rzp, st));
+    prof_end(c, QO_KERNEL_DST_INV, e2);
+    return QO_OK;
+}
+
+// PCG on all columns of B (ld c->ld) into X, precision T: Jacobi, or the
+// fast-Poisson preconditioner when c->dst.
 template <typename T>
 qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *P0, T *P1,
               int ncols, int use_x0, double tol, const int *mask, const double *coltol,
@@ -321,10 +350,13 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
     const bool f64 = sizeof(T) == 8;
     const int k1 = f64 ? QO_KERNEL_SWEEP1_F64 : QO_KERNEL_SWEEP1_F32;
     const int k2 = f64 ? QO_KERNEL_SWEEP2_F64 : QO_KERNEL_SWEEP2_F32;
+    T *Z = nullptr;
+    if (c->dst) Z = reinterpret_cast<T *>(f64 ? (void *)c->z64 : (void *)c->z32);
     for (int k = 0;; ++k) {
+        if (Z) QOC(precondition<T>(c, R, Z, ncols, k, tol, mask, s));
         hipEvent_t ea = prof_begin(c);
         HIPC(c, launch_pcg_sweep1<T>(g, vs, dinv, R, pbuf[(k + 1) & 1], pbuf[k & 1], c->ld, ncols,
-                                     k, tol, mask, s, st));
+                                     k, tol, mask, s, st, Z, c->rzp, c->dp.nslab));
         prof_end(c, k1, ea);
         if (k % check == 0 || k >= maxit) {
             HIPC(c, hipMemcpyAsync(c->h_poll, s.active + (k & 1) * ncols, sizeof(int) * ncols,
@@ -356,6 +388,9 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
     if (c->prof) {
         c->pdata.work[k1] += colits;
         c->pdata.work[k2] += colits;
+        if (Z)
+            for (int kid : {(int)QO_KERNEL_DST_FWD, (int)QO_KERNEL_DST_PENCIL, (int)QO_KERNEL_DST_INV})
+                c->pdata.work[kid] += colits;
     }
     return QO_OK;
 }
@@ -455,9 +490,11 @@ qo_status solve_mixed_rel(qo_ctx *c, const double *B, double *X, int ncols, int 
     if (c->h_poll[0] > 0) {
         float *pbuf[2] = {c->pa32, c->pb32};
         for (int k = 0;; ++k) {
+            if (c->dst) QOC(precondition<float>(c, c->r32, c->z32, ncols, k, tol, c->mask, s));
             hipEvent_t ea = prof_begin(c);
             HIPC(c, launch_pcg_sweep1<float>(g, c->vs32, c->dinv32, c->r32, pbuf[(k + 1) & 1],
-                                             pbuf[k & 1], c->ld, ncols, k, tol, c->mask, s, st));
+                                             pbuf[k & 1], c->ld, ncols, k, tol, c->mask, s, st,
+                                             c->dst ? c->z32 : nullptr, c->rzp, c->dp.nslab));
             prof_end(c, QO_KERNEL_SWEEP1_F32, ea);
             hipEvent_t eb = prof_begin(c);
             HIPC(c, launch_pcg_sweep2<float>(g, c->vs32, c->dinv32, pbuf[k & 1], c->d32, c->r32,
@@ -502,6 +539,9 @@ qo_status solve_mixed_rel(qo_ctx *c, const double *B, double *X, int ncols, int 
     if (c->prof) {
         c->pdata.work[QO_KERNEL_SWEEP1_F32] += colits;
         c->pdata.work[QO_KERNEL_SWEEP2_F32] += colits;
+        if (c->dst)
+            for (int kid : {(int)QO_KERNEL_DST_FWD, (int)QO_KERNEL_DST_PENCIL, (int)QO_KERNEL_DST_INV})
+                c->pdata.work[kid] += colits;
     }
     *rounds = nrep;
     return QO_OK;
@@ -520,7 +560,14 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
         return pcg<double>(c, c->vs, c->dinv, B, X, c->r, c->pa, c->pb, ncols, use_x0, tol,
                            nullptr, nullptr, its, what);
     }
-    if (c->rel && !one_sweep) return solve_mixed_rel(c, B, X, ncols, use_x0, its, rounds, what);
+    // Reliable updates keep the FP32 search direction across a residual replacement,
+    // which suits slowly converging Jacobi-PCG (the FP32 and FP64 residuals still agree
+    // when a replacement is due).  With the fast-Poisson preconditioner a few iterations
+    // take the FP32 residual to its rounding floor, the replaced residual is no longer
+    // close to the recursive one, and the kept direction stalls the iteration: there the
+    // inner FP32 solve is restarted each round instead.
+    if (c->rel && !one_sweep && !c->dst)
+        return solve_mixed_rel(c, B, X, ncols, use_x0, its, rounds, what);
     // FP64 iterative refinement around FP32 PCG (restarted each round)
     hipStream_t st = c->st;
     const Grid &g = c->g;
@@ -880,6 +927,8 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
     if (c.n[0] > 1024) return QO_ERR_ARG;
     if (c.pcg_variant != 0 && c.pcg_variant != 1) return QO_ERR_ARG;
     if (c.pcg_variant == 1 && c.n[0] > 256) return QO_ERR_ARG;
+    if (c.precond != 0 && c.precond != 1) return QO_ERR_ARG;
+    if (c.precond == 1 && (c.pcg_variant != 0 || dst_plan_check(c.dim, c.n))) return QO_ERR_ARG;
     if (c.N < 1 || c.N >= ng || c.N > 4096) return QO_ERR_ARG;
     if (!(c.kinetic > 0.0) || !std::isfinite(c.sigma)) return QO_ERR_ARG;
     if (!(c.pcg_tol > 0.0) || c.pcg_maxit < 1 || c.pcg_check < 1) return QO_ERR_ARG;
@@ -951,6 +1000,54 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
     if (const char *d = getenv("QO_REL_DELTA")) h->rel_delta = atof(d);
     A(&h->nact, 1);
     A(&h->dstatus, 1);
+    if (c.precond == 1) {
+        h->dst = true;
+        DstPlan &dp = h->dp;
+        dst_plan_geometry(dp, c.dim, h->g.nx, h->g.ny, h->g.nz);
+        const size_t sx = (size_t)dp.NXP * dp.NXP, sy = (size_t)dp.NYP * dp.NYP,
+                     ss = (size_t)dp.NSP * dp.NSP;
+        A(&h->dS, sx + sy + ss);
+        A(&h->dmu, (size_t)dp.nx + dp.ny + dp.ns);
+        A(&h->t1, blk);
+        A(&h->t2, blk);
+        A(&h->pcs, (size_t)N);
+        A(&h->rzp, (size_t)N * dp.nslab);
+        A(&h->dsum, 1);
+        if (h->mixed) A(&h->z32, blk);
+        else A(&h->z64, blk);
+        if (s == QO_OK) {
+            dp.Sx = h->dS;
+            dp.Sy = h->dS + sx;
+            dp.Ss = h->dS + sx + sy;
+            dp.mux = h->dmu;
+            dp.muy = h->dmu + dp.nx;
+            dp.mus = h->dmu + dp.nx + dp.ny;
+            // eigenvalues of the 1-D Dirichlet -d^2/dx^2: (4/h^2) sin^2(pi (j+1) / (2 (n+1)))
+            std::vector<float> mu;
+            auto push = [&](int n, double L) {
+                const double hh = L / (n + 1);
+                for (int j = 0; j < n; ++j) {
+                    const double sn = std::sin(M_PI * (j + 1) / (2.0 * (n + 1)));
+                    mu.push_back((float)(4.0 * sn * sn / (hh * hh)));
+                }
+            };
+            push(dp.nx, c.L[0]);
+            push(dp.ny, c.L[1]);
+            if (c.dim == 3) push(dp.nz, c.L[2]);
+            else push(dp.ny, c.L[1]);
+            if (hipMemcpy(h->dmu, mu.data(), sizeof(float) * mu.size(), hipMemcpyHostToDevice) !=
+                    hipSuccess ||
+                launch_dst_matrix(dp.nx, dp.NXP, h->dS, h->st) != hipSuccess ||
+                launch_dst_matrix(dp.ny, dp.NYP, h->dS + sx, h->st) != hipSuccess ||
+                launch_dst_matrix(dp.ns, dp.NSP, h->dS + sx + sy, h->st) != hipSuccess)
+                s = QO_ERR_DEVICE;
+            dp.kap = (float)c.kinetic;
+            h->mu0 = (double)mu[0] + (double)mu[dp.nx] * (c.dim == 3 ? 1.0 : 0.0) +
+                     (double)mu[dp.nx + dp.ny];
+            dp.vbar = 0.f;
+            dp.lmin = (float)(c.kinetic * h->mu0);
+        }
+    }
     h->ps.part = h->part;
     if (s == QO_OK) {
         if (hipHostMalloc((void **)&h->h_poll, sizeof(int) * (N + 8)) != hipSuccess ||
@@ -994,6 +1091,16 @@ qo_status qo_set_potential(qo_handle h, const double *V, int on_device) {
     if (bad == 5) {
         h->have_V = false;
         return fail(h, QO_ERR_NOT_SPD, "diagonal of H_sigma not positive: increase sigma");
+    }
+    if (h->dst) {
+        // vbar = max(0, mean(V + sigma)): M = kappa (-Lap_h) + vbar stays SPD
+        HIPC(h, launch_sum(h->vs, h->ng, h->dsum, h->st));
+        double sum = 0.0;
+        HIPC(h, hipMemcpyAsync(&sum, h->dsum, sizeof(double), hipMemcpyDeviceToHost, h->st));
+        HIPC(h, hipStreamSynchronize(h->st));
+        const double vbar = std::max(0.0, sum / (double)h->ng);
+        h->dp.vbar = (float)vbar;
+        h->dp.lmin = (float)(h->cfg.kinetic * h->mu0 + vbar);
     }
     h->have_V = true;
     h->have_warm = false;
@@ -1241,6 +1348,45 @@ qo_status qo_solve(qo_handle h, const double *B, double *X, long ld, int ncols, 
     HIPC(h, hipStreamSynchronize(st));
     if (iters)
         for (int j = 0; j < ncols; ++j) iters[j] = its[j];
+    return QO_OK;
+}
+
+qo_status qo_precond(qo_handle h, const double *R, double *Z, long ld, int ncols, double *rz) {
+    if (!h) return QO_ERR_ARG;
+    if (!R || !Z) return fail(h, QO_ERR_ARG, "null pointer");
+    if (!h->dst) return fail(h, QO_ERR_ARG, "qo_precond needs precond = 1");
+    if (!h->have_V) return fail(h, QO_ERR_STATE, "no potential set");
+    if (ld < h->ng || ncols < 1 || ncols > h->N)
+        return fail(h, QO_ERR_ARG, "bad ld/ncols (ld %ld, ncols %d)", ld, ncols);
+    hipStream_t st = h->st;
+    const size_t row = sizeof(double) * h->ng;
+    HIPC(h, hipMemcpy2DAsync(h->W, sizeof(double) * h->ld, R, sizeof(double) * ld, row, ncols,
+                             hipMemcpyDeviceToDevice, st));
+    HIPC(h, hipMemsetAsync(h->W2, 0, sizeof(double) * h->ld * ncols, st));
+    HIPC(h, launch_col_scale(h->W, h->ld, h->ng, ncols, h->pcs, st));
+    HIPC(h, launch_dst_fwd<double>(h->dp, h->W, h->ld, ncols, h->t1, h->pcs, st));
+    HIPC(h, launch_dst_pencil(h->dp, h->t1, h->t2, h->ld, ncols, h->pcs, st));
+    HIPC(h, launch_dst_inv<double>(h->dp, h->t2, h->W, h->W2, h->ld, ncols, h->pcs, h->rzp, st));
+    HIPC(h, hipMemcpy2DAsync(Z, sizeof(double) * ld, h->W2, sizeof(double) * h->ld, row, ncols,
+                             hipMemcpyDeviceToDevice, st));
+    if (rz) {
+        const int ns = h->dp.nslab;
+        std::vector<double> part((size_t)ncols * ns);
+        std::vector<float> sc(ncols);
+        HIPC(h, hipMemcpyAsync(part.data(), h->rzp, sizeof(double) * part.size(),
+                               hipMemcpyDeviceToHost, st));
+        HIPC(h, hipMemcpyAsync(sc.data(), h->pcs, sizeof(float) * ncols, hipMemcpyDeviceToHost,
+                               st));
+        HIPC(h, hipStreamSynchronize(st));
+        for (int j = 0; j < ncols; ++j) {
+            double t = 0.0;
+            if (sc[j] != 0.f)
+                for (int q = 0; q < ns; ++q) t += part[(size_t)j * ns + q];
+            rz[j] = t;
+        }
+    } else {
+        HIPC(h, hipStreamSynchronize(st));
+    }
     return QO_OK;
 }
 

@@ -1,0 +1,527 @@
+// Fast-Poisson preconditioner for the inverse-operator solves of Sec. 3.1/4.1.
+//
+// The operator G = H_sigma^{-1} is applied by PCG (Sec. 4.1 leaves the linear
+// solver open; the concluding section names a better preconditioner than the
+// diagonal one as the way to cut solver cost).  Here M = kappa (-Lap_h) + vbar,
+// the constant-coefficient part of H_sigma on the same Dirichlet grid with the
+// potential replaced by a constant vbar >= 0, is inverted exactly:
+// -Lap_h is diagonalised by the type-I discrete sine transform along each axis,
+//   S_n[i][j] = sqrt(2/(n+1)) sin(pi (i+1)(j+1)/(n+1)),  S_n = S_n^T = S_n^{-1},
+//   mu_n[j]   = (4/h^2) sin^2(pi (j+1) / (2(n+1)))   (eigenvalues of -d^2/dx^2),
+// so M^{-1} r = S3 diag(1/lambda) S3 r with S3 = S_z (x) S_y (x) S_x and
+// lambda = kappa (mu_x + mu_y + mu_z) + vbar.  The spectrum of M^{-1} H_sigma
+// then no longer depends on h, and the iteration count stops growing with the
+// grid.
+//
+// The transforms are dense contractions with the n x n matrices S (n <= 256),
+// run on MFMA in FP16 with FP32 accumulation.  A preconditioner only has to be
+// a fixed, nearly symmetric SPD operator: its rounding changes the iteration
+// count, never the accuracy of the solve, which the FP64 (or reliable-update)
+// residual decides.  Values are brought to O(1) before every FP16 rounding:
+// r is scaled per column by sqrt(Ng)/||r||, the spectral division uses
+// lambda_min/lambda <= 1, and the inverse transform undoes both.
+//
+// Three passes per application, each streaming the block once:
+//   plane   (forward)  r (T) -> t1 (FP16): transform along x (and y in 3-D)
+//   pencil             t1 -> t2 (FP16):    along the slowest axis, scale by
+//                                          lambda_min/lambda, transform back
+//   plane   (inverse)  t2 -> z (T):        along x (and y), unscale; partial
+//                                          sums of r.z for the PCG step
+// "Plane" is one z-plane in 3-D and a batch of rows in 2-D; the slowest axis
+// is z in 3-D and y in 2-D.
+#include "qo_internal.h"
+#include "qo_device.h"
+
+namespace qo {
+
+namespace {
+
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxWaves = 16;
+
+// Deterministic sum over the block (any multiple of 64 threads up to 1024).
+__device__ __forceinline__ double block_sum(double v, double *red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w];
+    return s;
+}
+
+__device__ __forceinline__ v8h lds8(const _Float16 *p) {
+    return *reinterpret_cast<const v8h *>(p);
+}
+
+__device__ __forceinline__ void st4h(_Float16 *p, v4f a, float f) {
+    v4h h;
+    h[0] = (_Float16)(a[0] * f);
+    h[1] = (_Float16)(a[1] * f);
+    h[2] = (_Float16)(a[2] * f);
+    h[3] = (_Float16)(a[3] * f);
+    *reinterpret_cast<v4h *>(p) = h;
+}
+
+__device__ __forceinline__ float mu_inplane(const DstPlan &p, int m) {
+    if (p.dim == 3) {
+        const int y = m / p.nx;
+        return p.mux[m - y * p.nx] + p.muy[y];
+    }
+    return p.mux[m];
+}
+
+// S_n in FP16, zero-padded to NP x NP (row-major).
+__global__ void k_dst_matrix(int n, int NP, _Float16 *__restrict__ S) {
+    const double c = sqrt(2.0 / (n + 1));
+    const long per = 2L * (n + 1);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NP * NP; e += gridDim.x * blockDim.x) {
+        const int i = e / NP, j = e - i * NP;
+        double v = 0.0;
+        if (i < n && j < n) {
+            const long k = ((long)(i + 1) * (j + 1)) % per;  // exact argument reduction
+            v = c * sin(M_PI * (double)k / (double)(n + 1));
+        }
+        S[e] = (_Float16)(float)v;
+    }
+}
+
+// Sum of vs over the grid (one block), for the constant vbar of M.
+__global__ void k_sum(const double *__restrict__ v, long n, double *__restrict__ out) {
+    __shared__ double red[kMaxWaves];
+    double s = 0.0;
+    for (long i = threadIdx.x; i < n; i += blockDim.x) s += v[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// pcs[c] = sqrt(Ng / ||r_c||^2), 0 for a zero (or non-finite) column.
+__global__ __launch_bounds__(kThreads) void k_col_scale(const double *__restrict__ R, long ld,
+                                                        long ng, float *__restrict__ pcs) {
+    __shared__ double red[kMaxWaves];
+    const int col = blockIdx.x;
+    const double *r = R + (long)col * ld;
+    double s = 0.0;
+    for (long i = threadIdx.x; i < ng; i += blockDim.x) s += r[i] * r[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) pcs[col] = (s > 0.0 && isfinite(s)) ? (float)sqrt((double)ng / s) : 0.f;
+}
+
+// Per-column scale of the forward transform for PCG iteration k, 0 for the
+// columns that skip this iteration.  The activity and convergence decision is
+// the one the first PCG sweep takes (same partial sums, same reduction code),
+// so the preconditioner runs exactly on the columns that sweep then updates.
+__global__ __launch_bounds__(kThreads) void k_pc_prep(int k, int ncols, const int *__restrict__ mask,
+                                                      PcgState s, long qs, int tiles, double tol,
+                                                      long ng, float *__restrict__ pcs) {
+    __shared__ dev::Red red;
+    const int col = blockIdx.x;
+    const int prv = (k & 1) ^ 1;
+    const int prev_active = (k == 0) ? (mask ? mask[col] : 1) : s.active[prv * ncols + col];
+    if (!prev_active) {
+        if (threadIdx.x == 0) pcs[col] = 0.f;
+        return;
+    }
+    const double rr = dev::col_sum(s.part + qs, col, tiles, red);
+    const double bb = (k == 0) ? dev::col_sum(s.part + 2 * qs, col, tiles, red) : s.bb[col];
+    const double ctol = s.coltol ? s.coltol[col] : tol;
+    if (threadIdx.x == 0) {
+        float sc = 0.f;
+        const bool fin = isfinite(rr) && isfinite(bb);
+        if (fin && !(sqrt(rr) <= ctol * sqrt(bb)) && rr > 0.0) sc = (float)sqrt((double)ng / rr);
+        pcs[col] = sc;
+    }
+}
+
+// ---------------------------------------------------------------- plane pass
+//
+// Workgroup = one slab of one column: RP = 16 * waves padded rows of NXP
+// padded x-points in LDS (FP16).  Wave w owns output rows [16w, 16w + 16).
+//   GEMM1  T = X S_x     (A = X rows from LDS, B = rows of S_x: S symmetric)
+//   GEMM2  Y = S_y T     (3-D only; T staged transposed in LDS)
+// Forward: X = sc * r, output FP16.  Inverse: X = t2, output z = Y / (sc lmin)
+// in T, plus the slab's partial sum of r.z.
+template <typename T, bool INV, int NT>
+__global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restrict__ R,
+                                                   const _Float16 *__restrict__ Hin,
+                                                   _Float16 *__restrict__ Hout,
+                                                   T *__restrict__ Z, long ld,
+                                                   const float *__restrict__ pcs,
+                                                   double *__restrict__ rzp) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kMaxWaves];
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int col = L / p.nslab;
+    const int slab = L - col * p.nslab;
+    const float sc = pcs[col];
+    if (sc == 0.f) return;  // column converged or inactive (uniform over the block)
+
+    const int NXP = p.NXP, XP = NXP + 8;
+    const int nx = p.nx;
+    _Float16 *X = reinterpret_cast<_Float16 *>(smem);
+    _Float16 *TT = X + p.RP * XP;
+    const int TP = p.NYP + 8;
+
+    const int row0 = slab * p.rows;
+    const int rows = min(p.rows, (p.dim == 3 ? p.ny : p.ny - row0));
+    const long base = (long)col * ld + (p.dim == 3 ? (long)slab * nx * p.ny : (long)row0 * nx);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+
+    // ---- stage the slab into LDS as FP16 (zero padding)
+    if (!INV) {
+        const int groups = p.RP * (NXP / 4);
+        const bool vec = (nx % 4) == 0;
+        for (int it = tid; it < groups; it += nthr) {
+            const int r = it / (NXP / 4);
+            const int x = (it - r * (NXP / 4)) * 4;
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            if (r < rows) {
+                const T *src = R + base + (long)r * nx + x;
+                if (vec && x < nx) {
+                    if constexpr (sizeof(T) == 4) {
+                        const float4 q = *reinterpret_cast<const float4 *>(src);
+                        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+                    } else {
+                        const double2 q0 = *reinterpret_cast<const double2 *>(src);
+                        const double2 q1 = *reinterpret_cast<const double2 *>(src + 2);
+                        v[0] = (float)q0.x; v[1] = (float)q0.y; v[2] = (float)q1.x; v[3] = (float)q1.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (x + i < nx) v[i] = (float)src[i];
+                }
+            }
+            v4h h;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h[i] = (_Float16)(v[i] * sc);
+            *reinterpret_cast<v4h *>(X + r * XP + x) = h;
+        }
+    } else {
+        const int groups = p.RP * (NXP / 8);
+        const bool vec = (nx % 8) == 0;
+        for (int it = tid; it < groups; it += nthr) {
+            const int r = it / (NXP / 8);
+            const int x = (it - r * (NXP / 8)) * 8;
+            v8h h;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) h[i] = (_Float16)0.f;
+            if (r < rows) {
+                const _Float16 *src = Hin + base + (long)r * nx + x;
+                if (vec && x < nx) {
+                    h = *reinterpret_cast<const v8h *>(src);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (x + i < nx) h[i] = src[i];
+                }
+            }
+            *reinterpret_cast<v8h *>(X + r * XP + x) = h;
+        }
+    }
+    __syncthreads();
+
+    const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+    const int KX = NXP / 32;
+    v4f acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < KX; ++ks) {
+        const v8h a = lds8(X + (16 * w + lr) * XP + 32 * ks + 8 * lg);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const v8h b = *reinterpret_cast<const v8h *>(p.Sx + (16 * j + lr) * NXP + 32 * ks + 8 * lg);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[j], 0, 0, 0);
+        }
+    }
+
+    if (p.dim == 3) {
+        // T^T into LDS, then Y = S_y T
+#pragma unroll
+        for (int j = 0; j < NT; ++j) st4h(TT + (16 * j + lr) * TP + 16 * w + 4 * lg, acc[j], 1.f);
+        __syncthreads();
+        const int KY = p.NYP / 32;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < KY; ++ks) {
+            const v8h a = *reinterpret_cast<const v8h *>(p.Sy + (16 * w + lr) * p.NYP + 32 * ks + 8 * lg);
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const v8h b = lds8(TT + (16 * j + lr) * TP + 32 * ks + 8 * lg);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[j], 0, 0, 0);
+            }
+        }
+    }
+
+    // ---- epilogue: rows 16w + 4lg + v, columns 16j + lr of the slab
+    double rz = 0.0;
+    const float unscale = INV ? 1.f / (sc * p.lmin) : 0.f;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int x = 16 * j + lr;
+        if (x >= nx) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * w + 4 * lg + v;
+            if (r >= rows) continue;
+            const long i = base + (long)r * nx + x;
+            if (!INV) {
+                Hout[i] = (_Float16)acc[j][v];
+            } else {
+                const T zv = (T)(acc[j][v] * unscale);
+                Z[i] = zv;
+                rz += (double)R[i] * (double)zv;
+            }
+        }
+    }
+    if (INV) {
+        rz = block_sum(rz, red);
+        if (tid == 0) rzp[(long)col * p.nslab + slab] = rz;
+    }
+}
+
+// ---------------------------------------------------------------- pencil pass
+//
+// Workgroup = MB consecutive in-plane positions m of one column, all ns
+// slices along the slowest axis.  Wave w owns slowest-axis rows [16w, 16w+16).
+//   GEMM1  Yh = S_s X   (X staged transposed: m-major, slice index contiguous)
+//   scale  Yh[s][m] *= lmin / (kappa (mu_f(m) + mu_s(s)) + vbar)
+//   GEMM2  Z  = S_s Yh
+template <int NJ>
+__global__ __launch_bounds__(1024) void k_dst_pencil(DstPlan p, const _Float16 *__restrict__ Hin,
+                                                     _Float16 *__restrict__ Hout, long ld,
+                                                     const float *__restrict__ pcs) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int MB = 16 * NJ;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int col = L / p.npen;
+    const int pen = L - col * p.npen;
+    if (pcs[col] == 0.f) return;
+    const int NSP = p.NSP, SP = NSP + 8;
+    const int ns = p.ns, nf = p.nf;
+    const int m0 = pen * MB;
+    _Float16 *XT = reinterpret_cast<_Float16 *>(smem);
+    _Float16 *YT = XT + MB * SP;
+    const long base = (long)col * ld;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+
+    {
+        constexpr int G8 = MB / 8;
+        const int items = NSP * G8;
+        const bool vec = (nf % 8) == 0;
+        for (int it = tid; it < items; it += nthr) {
+            const int s = it / G8;
+            const int mm = (it - s * G8) * 8;
+            const int m = m0 + mm;
+            v8h h;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) h[i] = (_Float16)0.f;
+            if (s < ns) {
+                const _Float16 *src = Hin + base + (long)s * nf + m;
+                if (vec && m < nf) {
+                    h = *reinterpret_cast<const v8h *>(src);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (m + i < nf) h[i] = src[i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) XT[(mm + i) * SP + s] = h[i];
+        }
+    }
+    __syncthreads();
+
+    const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+    const int KS = NSP / 32;
+    v4f acc[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < KS; ++ks) {
+        const v8h a = *reinterpret_cast<const v8h *>(p.Ss + (16 * w + lr) * NSP + 32 * ks + 8 * lg);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const v8h b = lds8(XT + (16 * j + lr) * SP + 32 * ks + 8 * lg);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[j], 0, 0, 0);
+        }
+    }
+    // spectral scaling, then Yh^T into LDS
+    float mus[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int s = 16 * w + 4 * lg + v;
+        mus[v] = s < ns ? p.mus[s] : -1.f;
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int m = m0 + 16 * j + lr;
+        const float muf = m < nf ? mu_inplane(p, m) : -1.f;
+        v4h h;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float f = 0.f;
+            if (muf >= 0.f && mus[v] >= 0.f) f = p.lmin / (p.kap * (muf + mus[v]) + p.vbar);
+            h[v] = (_Float16)(acc[j][v] * f);
+        }
+        *reinterpret_cast<v4h *>(YT + (16 * j + lr) * SP + 16 * w + 4 * lg) = h;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < KS; ++ks) {
+        const v8h a = *reinterpret_cast<const v8h *>(p.Ss + (16 * w + lr) * NSP + 32 * ks + 8 * lg);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const v8h b = lds8(YT + (16 * j + lr) * SP + 32 * ks + 8 * lg);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int m = m0 + 16 * j + lr;
+        if (m >= nf) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int s = 16 * w + 4 * lg + v;
+            if (s < ns) Hout[base + (long)s * nf + m] = (_Float16)acc[j][v];
+        }
+    }
+}
+
+constexpr int kPencilNJ = 4;  // MB = 64 positions per pencil workgroup
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+static int pad32(int n) { return (n + 31) / 32 * 32; }
+
+const char *dst_plan_check(int dim, const int n[3]) {
+    if (dim == 3) {
+        if (n[0] > 128 || n[1] > 128) return "DST preconditioner: nx, ny must be <= 128 in 3-D";
+        if (n[2] > 256) return "DST preconditioner: nz must be <= 256";
+    } else {
+        if (n[0] > 256 || n[1] > 256) return "DST preconditioner: nx, ny must be <= 256 in 2-D";
+    }
+    return nullptr;
+}
+
+void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz) {
+    p.dim = dim;
+    p.nx = nx;
+    p.ny = ny;
+    p.nz = dim == 3 ? nz : 1;
+    p.NXP = pad32(nx);
+    p.NYP = pad32(ny);
+    if (dim == 3) {
+        p.ns = nz;
+        p.nf = nx * ny;
+        p.NSP = pad32(nz);
+        p.RP = p.NYP;
+        p.rows = ny;
+        p.nslab = nz;
+    } else {
+        p.ns = ny;
+        p.nf = nx;
+        p.NSP = p.NYP;
+        p.RP = 64;
+        p.rows = 64;
+        p.nslab = (ny + 63) / 64;
+    }
+    p.npen = (p.nf + 16 * kPencilNJ - 1) / (16 * kPencilNJ);
+}
+
+size_t dst_plane_lds(const DstPlan &p) {
+    size_t b = (size_t)p.RP * (p.NXP + 8) * 2;
+    if (p.dim == 3) b += (size_t)p.NXP * (p.NYP + 8) * 2;
+    return b;
+}
+
+size_t dst_pencil_lds(const DstPlan &p) { return 2 * (size_t)16 * kPencilNJ * (p.NSP + 8) * 2; }
+
+hipError_t launch_dst_matrix(int n, int NP, _Float16 *S, hipStream_t st) {
+    hipLaunchKernelGGL(k_dst_matrix, dim3(64), dim3(256), 0, st, n, NP, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(const double *v, long n, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, st, v, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_scale(const double *R, long ld, long ng, int ncols, float *pcs,
+                            hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_col_scale, dim3(ncols), dim3(kThreads), 0, st, R, ld, ng, pcs);
+    return hipGetLastError();
+}
+
+hipError_t launch_pc_prep(int k, int ncols, const int *mask, PcgState s, long qs, int tiles,
+                          double tol, long ng, float *pcs, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pc_prep, dim3(ncols), dim3(kThreads), 0, st, k, ncols, mask, s, qs,
+                       tiles, tol, ng, pcs);
+    return hipGetLastError();
+}
+
+#define QO_DISPATCH_NT(NTV, ...)                              \
+    switch (NTV) {                                            \
+        case 2: { constexpr int NT = 2; __VA_ARGS__; } break;   \
+        case 4: { constexpr int NT = 4; __VA_ARGS__; } break;   \
+        case 6: { constexpr int NT = 6; __VA_ARGS__; } break;   \
+        case 8: { constexpr int NT = 8; __VA_ARGS__; } break;   \
+        case 10: { constexpr int NT = 10; __VA_ARGS__; } break; \
+        case 12: { constexpr int NT = 12; __VA_ARGS__; } break; \
+        case 14: { constexpr int NT = 14; __VA_ARGS__; } break; \
+        case 16: { constexpr int NT = 16; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;                 \
+    }
+
+template <typename T>
+hipError_t launch_dst_fwd(const DstPlan &p, const T *R, long ld, int ncols, _Float16 *t1,
+                          const float *pcs, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
+    QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, false, NT>), grid, block,
+                                                  dst_plane_lds(p), st, p, R, nullptr, t1,
+                                                  nullptr, ld, pcs, nullptr));
+    return hipGetLastError();
+}
+
+hipError_t launch_dst_pencil(const DstPlan &p, const _Float16 *t1, _Float16 *t2, long ld,
+                             int ncols, const float *pcs, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const dim3 grid((unsigned)(ncols * p.npen)), block((unsigned)(64 * (p.NSP / 16)));
+    hipLaunchKernelGGL((k_dst_pencil<kPencilNJ>), grid, block, dst_pencil_lds(p), st, p, t1, t2,
+                       ld, pcs);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, const T *R, T *Z, long ld,
+                          int ncols, const float *pcs, double *rzp, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
+    QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, true, NT>), grid, block,
+                                                  dst_plane_lds(p), st, p, R, t2, nullptr, Z,
+                                                  ld, pcs, rzp));
+    return hipGetLastError();
+}
+
+template hipError_t launch_dst_fwd<double>(const DstPlan &, const double *, long, int,
+                                           _Float16 *, const float *, hipStream_t);
+template hipError_t launch_dst_fwd<float>(const DstPlan &, const float *, long, int, _Float16 *,
+                                          const float *, hipStream_t);
+template hipError_t launch_dst_inv<double>(const DstPlan &, const _Float16 *, const double *,
+                                           double *, long, int, const float *, double *,
+                                           hipStream_t);
+template hipError_t launch_dst_inv<float>(const DstPlan &, const _Float16 *, const float *,
+                                          float *, long, int, const float *, double *,
+                                          hipStream_t);
+
+}  // namespace qo

@@ -45,6 +45,43 @@ struct PcgState {
     const double *coltol;  // optional per-column relative tolerance (else the scalar tol)
 };
 
+// ---- fast-Poisson (DST-I) preconditioner (qo_dst.hip) ----
+// Geometry and tables of M = kappa (-Lap_h) + vbar on the column grid.  The
+// slowest axis is z in 3-D and y in 2-D; a "slab" is one z-plane (3-D) or 64
+// rows (2-D); a pencil workgroup covers 64 consecutive in-slice positions.
+struct DstPlan {
+    int dim, nx, ny, nz;
+    int ns, nf;          // slowest-axis length; points per slowest-axis slice
+    int NXP, NYP, NSP;   // lengths padded to multiples of 32
+    int RP, rows;        // padded / real grid rows per slab
+    int nslab, npen;     // plane and pencil workgroups per column
+    const _Float16 *Sx, *Sy, *Ss;   // DST-I matrices, FP16, row-major, padded with zeros
+    const float *mux, *muy, *mus;   // eigenvalues of the 1-D -Lap_h along x, y, slowest axis
+    float kap, vbar, lmin;          // lambda = kap (mu_x + mu_y + mu_z) + vbar; lmin its minimum
+};
+
+// null if the grid is supported, else the reason
+const char *dst_plan_check(int dim, const int n[3]);
+void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz);
+hipError_t launch_dst_matrix(int n, int NP, _Float16 *S, hipStream_t st);
+hipError_t launch_sum(const double *v, long n, double *out, hipStream_t st);
+// pcs[c] = sqrt(Ng / ||r_c||^2) (0 for a zero column)
+hipError_t launch_col_scale(const double *R, long ld, long ng, int ncols, float *pcs,
+                            hipStream_t st);
+// pcs[c] = sqrt(Ng / ||r_c||^2) for the columns the PCG iteration k updates, else 0
+hipError_t launch_pc_prep(int k, int ncols, const int *mask, PcgState s, long qs, int tiles,
+                          double tol, long ng, float *pcs, hipStream_t st);
+// z = M^{-1} r in three passes: forward plane (r -> t1), pencil (t1 -> t2),
+// inverse plane (t2 -> z, partials rzp[c * nslab + slab] of r.z).
+template <typename T>
+hipError_t launch_dst_fwd(const DstPlan &p, const T *R, long ld, int ncols, _Float16 *t1,
+                          const float *pcs, hipStream_t st);
+hipError_t launch_dst_pencil(const DstPlan &p, const _Float16 *t1, _Float16 *t2, long ld,
+                             int ncols, const float *pcs, hipStream_t st);
+template <typename T>
+hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, const T *R, T *Z, long ld,
+                          int ncols, const float *pcs, double *rzp, hipStream_t st);
+
 // ---- stencil family (qo_stencil.hip) ----
 // All take a column count `ncols`, a column stride `ld` and per-point arrays
 // vs = V + sigma and dinv = 1/(c0 + vs) of the matching precision.
@@ -65,7 +102,8 @@ hipError_t launch_pcg_init(const Grid &g, const T *vs, const T *dinv, const T *B
 template <typename T>
 hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T *R,
                              const T *Pold, T *Pnew, long ld, int ncols, int k, double tol,
-                             const int *mask, PcgState s, hipStream_t st);
+                             const int *mask, PcgState s, hipStream_t st, const T *Z = nullptr,
+                             const double *rzp = nullptr, int rzt = 0);
 template <typename T>
 hipError_t launch_pcg_sweep2(const Grid &g, const T *vs, const T *dinv, const T *Pn, T *X, T *R,
                              long ld, int ncols, int k, PcgState s, hipStream_t st);

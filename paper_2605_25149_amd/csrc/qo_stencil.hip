@@ -194,6 +194,18 @@ struct LdPcgP {  // p = D r + beta p_old  (beta = 0: p = D r, p_old not read)
     }
 };
 
+template <typename T>
+struct LdPcgZ {  // p = z + beta p_old with an explicit preconditioned residual z
+    struct Raw { T z, p; };
+    const T *__restrict__ z;
+    const T *__restrict__ po;
+    T beta;
+    bool first;
+    __device__ static Raw zero() { return {T(0), T(0)}; }
+    __device__ Raw load(long i) const { return {z[i], first ? T(0) : po[i]}; }
+    __device__ T make(const Raw &a) const { return first ? a.z : a.z + beta * a.p; }
+};
+
 struct NoRaw {};
 
 __device__ __forceinline__ void tile_of(const Grid &g, int &col, int &tile, int &band, int &zc) {
@@ -399,7 +411,23 @@ __global__ __launch_bounds__(kThreads) void k_pcg_init(Grid g, const T *__restri
     }
 }
 
-template <typename T, int PPT>
+template <typename T>
+struct EpSweep1 {  // store p, gamma = p . H p
+    using Raw = NoRaw;
+    T *__restrict__ pn;
+    double acc[1];
+    __device__ static Raw zero() { return {}; }
+    __device__ Raw load(long) const { return {}; }
+    __device__ void operator()(int, long i, T c, T hv, const Raw &) {
+        pn[i] = c;
+        acc[0] += (double)c * (double)hv;
+    }
+};
+
+// XZ: the preconditioned residual z is an input (fast-Poisson preconditioner)
+// and r.z comes from that pass's partials rzp (rzt per column); otherwise
+// z = D r is formed on the fly and r.z comes from sweep2's partials.
+template <typename T, int PPT, bool XZ>
 __global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__restrict__ vs,
                                                          const T *__restrict__ dinv,
                                                          const T *__restrict__ R,
@@ -407,7 +435,9 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__rest
                                                          T *__restrict__ Pnew, long ld, int ncols,
                                                          int k, double tol,
                                                          const int *__restrict__ mask,
-                                                         PcgState s, long qs) {
+                                                         PcgState s, long qs,
+                                                         const T *__restrict__ Z,
+                                                         const double *__restrict__ rzp, int rzt) {
     __shared__ Red red;
     __shared__ int sh_flag;
     int col, tile, band, zc;
@@ -420,7 +450,6 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__rest
         if (lead && threadIdx.x == 0) s.active[cur * ncols + col] = 0;
         return;
     }
-    const double rz = col_sum(s.part, col, tiles, red);
     const double rr = col_sum(s.part + qs, col, tiles, red);
     double bb;
     if (k == 0) {
@@ -430,10 +459,14 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__rest
         bb = s.bb[col];
     }
     const double ctol = s.coltol ? s.coltol[col] : tol;
+    // the convergence test first: a converged column's z is not computed
+    const bool conv = sqrt(rr) <= ctol * sqrt(bb);
+    const double rz = (XZ && conv) ? 0.0 : (XZ ? col_sum(rzp, col, rzt, red)
+                                                : col_sum(s.part, col, tiles, red));
     if (threadIdx.x == 0) {
         int flag = 0;  // 0 run, 1 converged, 2 non-finite
         if (!isfinite(rz) || !isfinite(rr) || !isfinite(bb)) flag = 2;
-        else if (sqrt(rr) <= ctol * sqrt(bb)) flag = 1;
+        else if (conv) flag = 1;
         sh_flag = flag;
         if (lead) {
             s.its[col] = k;
@@ -448,19 +481,14 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__rest
     __syncthreads();
     if (sh_flag != 0) return;
     const T beta = (k == 0) ? T(0) : (T)(rz / s.rho[prv * ncols + col]);
-    LdPcgP<T> l{dinv, R + (long)col * ld, Pold + (long)col * ld, beta, k == 0};
-    struct Ep {
-        using Raw = NoRaw;
-        T *__restrict__ pn;
-        double acc[1];
-        __device__ static Raw zero() { return {}; }
-        __device__ Raw load(long) const { return {}; }
-        __device__ void operator()(int, long i, T c, T hv, const Raw &) {
-            pn[i] = c;
-            acc[0] += (double)c * (double)hv;
-        }
-    } ep{Pnew + (long)col * ld, {0.0}};
-    engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
+    EpSweep1<T> ep{Pnew + (long)col * ld, {0.0}};
+    if constexpr (XZ) {
+        LdPcgZ<T> l{Z + (long)col * ld, Pold + (long)col * ld, beta, k == 0};
+        engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
+    } else {
+        LdPcgP<T> l{dinv, R + (long)col * ld, Pold + (long)col * ld, beta, k == 0};
+        engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
+    }
     block_sums<1>(ep.acc, red);
     if (threadIdx.x == 0) s.part[3 * qs + (long)col * tiles + tile] = ep.acc[0];
 }
@@ -709,13 +737,22 @@ hipError_t launch_pcg_init(const Grid &g, const T *vs, const T *dinv, const T *B
 template <typename T>
 hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T *R,
                              const T *Pold, T *Pnew, long ld, int ncols, int k, double tol,
-                             const int *mask, PcgState s, hipStream_t st) {
+                             const int *mask, PcgState s, hipStream_t st, const T *Z,
+                             const double *rzp, int rzt) {
     if (ncols <= 0) return hipSuccess;
     const long qs = (long)ncols * g.tiles();
     const dim3 grid(ncols * g.tiles());
-    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep1<T, P>), grid, dim3(kThreads),
-                                               lds_bytes(g, sizeof(T)), st, g, vs, dinv, R, Pold,
-                                               Pnew, ld, ncols, k, tol, mask, s, qs));
+    if (Z) {
+        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep1<T, P, true>), grid,
+                                                   dim3(kThreads), lds_bytes(g, sizeof(T)), st,
+                                                   g, vs, dinv, R, Pold, Pnew, ld, ncols, k, tol,
+                                                   mask, s, qs, Z, rzp, rzt));
+    } else {
+        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep1<T, P, false>), grid,
+                                                   dim3(kThreads), lds_bytes(g, sizeof(T)), st,
+                                                   g, vs, dinv, R, Pold, Pnew, ld, ncols, k, tol,
+                                                   mask, s, qs, Z, rzp, rzt));
+    }
     return hipGetLastError();
 }
 
@@ -740,10 +777,11 @@ template hipError_t launch_pcg_init<float>(const Grid &, const float *, const fl
 template hipError_t launch_pcg_sweep1<double>(const Grid &, const double *, const double *,
                                               const double *, const double *, double *, long,
                                               int, int, double, const int *, PcgState,
-                                              hipStream_t);
+                                              hipStream_t, const double *, const double *, int);
 template hipError_t launch_pcg_sweep1<float>(const Grid &, const float *, const float *,
                                              const float *, const float *, float *, long, int,
-                                             int, double, const int *, PcgState, hipStream_t);
+                                             int, double, const int *, PcgState, hipStream_t,
+                                             const float *, const double *, int);
 template hipError_t launch_pcg_sweep2<double>(const Grid &, const double *, const double *,
                                               const double *, double *, double *, long, int, int,
                                               PcgState, hipStream_t);

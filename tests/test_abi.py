@@ -64,3 +64,44 @@ def test_create_rejects_bad_config_before_device_work():
     cfg.refine_inner_tol = 0.0
     assert lib.qo_create(ctypes.byref(cfg), None, ctypes.byref(h)) == binding.QO_ERR_ARG
     assert lib.qo_create(None, None, ctypes.byref(h)) == binding.QO_ERR_ARG
+
+
+def test_binding_structs_match_header():
+    """The ctypes mirrors of qo_config / qo_step_stats list the header's members in order."""
+    from paper_2605_25149_amd import binding
+
+    src = open(os.path.join(ROOT, "include", "qo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    for cname, py in [("qo_config", binding.QoConfig), ("qo_step_stats", binding.QoStepStats)]:
+        body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", src).group(1)
+        names = []
+        for decl in body.split(";"):
+            toks = decl.strip().split(None, 1)
+            if len(toks) == 2:
+                names += [re.sub(r"\[.*\]", "", v.strip()) for v in toks[1].split(",")]
+        assert names == [f[0] for f in py._fields_], cname
+
+
+def test_create_rejects_bad_precond_before_device_work():
+    """The fast-Poisson preconditioner's limits are checked before any HIP call."""
+    from paper_2605_25149_amd import binding
+
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libqo_hip.so not built")
+    lib = binding.load_library()
+    cfg = binding.QoConfig()
+    cfg.dim = 3
+    cfg.n[0] = cfg.n[1] = cfg.n[2] = 200  # > 128 per in-plane axis in 3-D
+    for k in range(3):
+        cfg.L[k] = 1.0
+    cfg.kinetic, cfg.N = 0.5, 4
+    cfg.pcg_tol, cfg.pcg_maxit, cfg.pcg_check = 1e-10, 100, 4
+    cfg.precond = 1
+    h = ctypes.c_void_p()
+    assert lib.qo_create(ctypes.byref(cfg), None, ctypes.byref(h)) == binding.QO_ERR_ARG
+    cfg.n[0] = cfg.n[1] = cfg.n[2] = 32
+    cfg.pcg_variant = 1  # the one-sweep form has no preconditioner hook
+    assert lib.qo_create(ctypes.byref(cfg), None, ctypes.byref(h)) == binding.QO_ERR_ARG
+    cfg.pcg_variant = 0
+    cfg.precond = 2
+    assert lib.qo_create(ctypes.byref(cfg), None, ctypes.byref(h)) == binding.QO_ERR_ARG

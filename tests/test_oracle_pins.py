@@ -413,3 +413,74 @@ def test_eigsum_gradient_finite_differences(oracle_mod):
         # the discrete eigenvalue problem is H u = lambda u with mass h^d: dlambda/dV_j = u_j^2
         # for Euclidean-normalised u; in the grid inner product this is h^d * (grid u_j)^2
         assert abs((ep - em) / (2 * eps) - g[j]) <= 1e-6 * max(1.0, abs(g[j]))
+
+
+# ---------------------------------------------------------------------------
+# fast-Poisson preconditioner of the inverse-operator solve (reading R6)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,L,vshift", [(2, (9, 7), (1.0, 1.3), 3.0),
+                                            (3, (6, 5, 7), (1.0, 0.8, 1.2), 0.0),
+                                            (3, (4, 4, 4), (1.0, 1.0, 1.0), -5.0)])
+def test_fast_poisson_precond_is_exact_inverse(oracle_mod, dim, n, L, vshift):
+    """precond_apply equals the dense inverse of kappa (-Lap_h) + vbar assembled
+    entry by entry from the stencil, vbar = max(0, mean(V + sigma)); and the 1-D
+    eigenvalues it uses are those of the dense second-difference matrix."""
+    O = oracle_mod
+    ng = int(np.prod(n))
+    rng = np.random.default_rng(11)
+    V = rng.uniform(-1.0, 1.0, ng) + vshift
+    sigma = 0.3
+    prob = O.Problem(dim, n, V, L=L, sigma=sigma)
+    vbar = max(0.0, float(np.mean(V)) + sigma)
+    assert prob.precond_vbar() == pytest.approx(vbar, rel=1e-14, abs=1e-14)
+    M = dense_H(dim, n, L, 0.5, vbar, np.zeros(ng))
+    R = inputs.random_block(ng, 3, seed=5)
+    Z = prob.precond_apply(R)
+    Zd = np.linalg.solve(M, R)
+    assert np.max(np.abs(Z - Zd)) <= 1e-12 * np.max(np.abs(Zd))
+    for k, mu in enumerate(prob.laplace_eigs()):
+        ref = sep_1d(n[k], L[k], 1.0, lambda x: 0.0 * x)
+        assert np.max(np.abs(np.sort(mu) - ref)) <= 1e-12 * ref.max()
+
+
+def test_fast_poisson_pcg(oracle_mod):
+    """PCG with the fast-Poisson preconditioner reaches the sparse-LU solution, and
+    its iteration count stays flat when h halves while Jacobi's grows."""
+    O = oracle_mod
+    its_fp, its_j = [], []
+    for n in [(8, 8, 8), (16, 16, 16)]:
+        V = inputs.gaussian_wells(n, seed=0)
+        prob = O.Problem(3, n, V)
+        B = inputs.random_block(prob.ng, 3, seed=2)
+        X, it, st, cst = prob.solve_fast_poisson(B, tol=1e-12)
+        assert st == O.ORC_OK and np.all(cst == O.ORC_OK) and np.all(it > 0)
+        Xd = prob.solve_direct(B)
+        assert np.max(np.abs(X - Xd)) <= 1e-9 * np.max(np.abs(Xd))
+        its_fp.append(int(it.max()))
+        its_j.append(int(prob.solve(B, tol=1e-12)[1].max()))
+        # a warm start at the solution takes no iteration
+        _, it0, st0, _ = prob.solve_fast_poisson(B, X0=Xd, tol=1e-10)
+        assert st0 == O.ORC_OK and np.all(it0 == 0)
+    assert its_fp[1] <= its_fp[0] + 2 and its_fp[1] <= 20
+    assert its_j[1] >= 1.5 * its_j[0]
+
+
+def test_fast_poisson_pcg_error_paths(oracle_mod):
+    O = oracle_mod
+    n = (6, 6)
+    prob = O.Problem(2, n, np.zeros(36))
+    B = inputs.random_block(36, 2, seed=1)
+    # with V = 0 the preconditioner is H itself: one iteration solves to rounding
+    X1, it1, st1, _ = prob.solve_fast_poisson(B, tol=1e-12)
+    assert st1 == O.ORC_OK and np.all(it1 == 1)
+    well = O.Problem(2, n, inputs.harmonic(n, 400.0))
+    _, _, st, _ = well.solve_fast_poisson(B, tol=1e-14, maxit=1)
+    assert st == O.ORC_NOCONV
+    neg = O.Problem(2, n, np.zeros(36), sigma=-1e5)  # indefinite H, SPD M (vbar = 0)
+    _, _, st, _ = neg.solve_fast_poisson(B, tol=1e-12)
+    assert st == O.ORC_NOT_SPD
+    Bn = B.copy()
+    Bn[3, 1] = np.nan
+    _, _, st, cst = prob.solve_fast_poisson(Bn, tol=1e-12)
+    assert st == O.ORC_NONFINITE and cst[1] == O.ORC_NONFINITE and cst[0] == O.ORC_OK

@@ -72,6 +72,8 @@ struct qo_ctx {
     double *colsums = nullptr;
     double *dscal = nullptr;
     double *sortwork = nullptr;
+    double *gjw = nullptr;  // blocked Gauss-Jordan workspace
+    int *gjpiv = nullptr;
     PcgState ps{};
     int *mask = nullptr, *nact = nullptr, *dstatus = nullptr;
     double *coltol = nullptr;
@@ -716,7 +718,7 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
     // C = S^{-1} M
     HIPC(c, nn_axpby(mp(c, MP_SW), N, 1.0, S, N2, 0.0, nullptr, N, false, 0.0, N, N, st));
     HIPC(c, nn_axpby(mp(c, MP_C), N, 1.0, M, N2, 0.0, nullptr, N, false, 0.0, N, N, st));
-    HIPC(c, nn_gj_solve(mp(c, MP_SW), N, mp(c, MP_C), N, N, N, true, c->dstatus, st));
+    HIPC(c, nn_gj_solve(mp(c, MP_SW), N, mp(c, MP_C), N, N, N, true, c->dstatus, st, c->gjw, c->gjpiv));
     // R_W = sym(R - M^T C)
     HIPC(c, nn_axpby(mp(c, MP_T1), N, 1.0, R, N2, 0.0, nullptr, N, false, 0.0, N, N, st));
     HIPC(c, nn_gemm(mp(c, MP_T1), N, M, N2, true, mp(c, MP_C), N, false, N, N, N, -1.0, 1.0, 0.0, st));
@@ -729,7 +731,7 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
     // (I + alpha^2 RWS - alpha D) b = D - alpha RWS
     HIPC(c, nn_axpby(mp(c, MP_MAT), N, alpha * alpha, mp(c, MP_RWS), N, -alpha, mp(c, MP_D), N, false, 1.0, N, N, st));
     HIPC(c, nn_axpby(mp(c, MP_RHS), N, 1.0, mp(c, MP_D), N, -alpha, mp(c, MP_RWS), N, false, 0.0, N, N, st));
-    HIPC(c, nn_gj_solve(mp(c, MP_MAT), N, mp(c, MP_RHS), N, N, N, false, c->dstatus, st));
+    HIPC(c, nn_gj_solve(mp(c, MP_MAT), N, mp(c, MP_RHS), N, N, N, false, c->dstatus, st, c->gjw, c->gjpiv));
     double *bm = mp(c, MP_RHS);
     // a = S + alpha S b
     HIPC(c, nn_axpby(mp(c, MP_A), N, 1.0, S, N2, 0.0, nullptr, N, false, 0.0, N, N, st));
@@ -983,6 +985,8 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
     A(&h->colsums, (size_t)4 * N);
     A(&h->dscal, 16);
     A(&h->sortwork, (size_t)N + (size_t)N * N);
+    A(&h->gjw, nn_gj_work_elems(N));
+    A(&h->gjpiv, (size_t)N);
     A(&h->ps.rho, (size_t)2 * N);
     A(&h->ps.alpha, (size_t)2 * N);
     A(&h->ps.active, (size_t)2 * N);
@@ -1301,7 +1305,7 @@ qo_status qo_eigsum_gradient(qo_handle h, double *g, int on_device) {
     HIPC(h, hipMemsetAsync(h->dstatus, 0, sizeof(int), st));
     HIPC(h, nn_axpby(mp(h, MP_T1), N, 1.0, h->G2, 2 * N, 0.0, nullptr, N, false, 0.0, N, N, st));
     HIPC(h, nn_axpby(mp(h, MP_T2), N, 0.0, nullptr, N, 0.0, nullptr, N, false, 1.0, N, N, st));
-    HIPC(h, nn_gj_solve(mp(h, MP_T1), N, mp(h, MP_T2), N, N, N, true, h->dstatus, st));
+    HIPC(h, nn_gj_solve(mp(h, MP_T1), N, mp(h, MP_T2), N, N, N, true, h->dstatus, st, h->gjw, h->gjpiv));
     QOC(check_status(h, "eigsum gradient: <U,U> not positive definite"));
     // row-major copy of S^{-1} (symmetric up to rounding; symmetrise)
     HIPC(h, nn_axpby(mp(h, MP_T3), N, 0.5, mp(h, MP_T2), N, 0.5, mp(h, MP_T2), N, true, 0.0, N, N, st));

@@ -172,8 +172,12 @@ hipError_t nn_axpby(double *C, int ldc, double a, const double *A, int lda, doub
 // B <- A^{-1} B by Gauss-Jordan on [A | B] (A destroyed).  spd: no pivoting and
 // fail when a pivot is not > 0; else partial pivoting.  status: device int,
 // set to the qo_status code on failure (left untouched on success).
+// n <= kGjBlockedMax with work (nn_gj_work_elems(n) doubles) and piv (n ints): blocked
+// multi-workgroup form; otherwise one workgroup.
+constexpr int kGjBlockedMax = 512;
 hipError_t nn_gj_solve(double *A, int lda, double *B, int ldb, int n, int m, bool spd,
-                       int *status, hipStream_t st);
+                       int *status, hipStream_t st, double *work = nullptr, int *piv = nullptr);
+size_t nn_gj_work_elems(int n);
 // Symmetric eigen-decomposition by cyclic Jacobi: A (n x n, destroyed) ->
 // evals (n), V (n x n, ld n) with A = V diag V^T; unsorted.
 hipError_t nn_jacobi(double *A, int lda, int n, double *evals, double *V, int ldv,

@@ -160,6 +160,203 @@ __global__ __launch_bounds__(GJT) void k_gj(double *__restrict__ A, int lda,
     if (tid == 0 && fail_sh) atomicMax(status, fail_sh);
 }
 
+// ---- blocked Gauss-Jordan on [A | B] (n <= 512) ----------------------------
+//
+// Panels of b pivot columns (32 for n <= 256, else 16).  The panel kernel (one workgroup, panel in LDS)
+// chooses the pivots of columns [k0, k0+b) by eliminating inside the panel
+// only, records the row swaps, and hands out the panel columns after the swaps
+// (O = A[:, K], n x b) and the inverse of their pivot block P = O[K, :].  The
+// update kernel then applies the same elimination to every column x still to
+// be reduced (columns >= k0+b of A, all of B): swaps, y = P^{-1} x_K,
+// x_K = y, x_i -= O[i, :] y for the other rows i.  Same pivots and SPD test as
+// the unblocked kernel above; a column's updates are grouped per panel.
+constexpr int GB = 32;
+constexpr int GPT = 512;
+constexpr int GCW = 16;  // columns per update workgroup
+
+__global__ __launch_bounds__(GPT) void k_gjb_panel(double *__restrict__ A, int lda, int n, int k0,
+                                                   int b, int spd, double *__restrict__ work,
+                                                   int *__restrict__ piv,
+                                                   int *__restrict__ status) {
+    extern __shared__ double gsm[];
+    double *W = gsm;          // working panel, column kk at W + kk * n
+    double *O = gsm + n * b;  // original panel after the row swaps
+    __shared__ double sval[GPT / 64];
+    __shared__ int sidx[GPT / 64];
+    __shared__ int piv_sh, fail_sh;
+    __shared__ double thr_sh;
+    const int tid = threadIdx.x;
+    if (*status) return;  // an earlier panel failed
+    double *scal = work + (size_t)n * GB + GB * GB;
+    if (tid == 0) {
+        fail_sh = 0;
+        if (k0 == 0) {
+            // SPD test threshold: 1e-13 of the largest diagonal entry of the input
+            double md = 0.0;
+            if (spd)
+                for (int i = 0; i < n; ++i) md = fmax(md, fabs(A[(long)i * lda + i]));
+            scal[0] = 1e-13 * md;
+        }
+        thr_sh = scal[0];
+    }
+    for (int e = tid; e < n * b; e += GPT) {
+        const int kk = e / n, i = e - kk * n;
+        const double v = A[(long)(k0 + kk) * lda + i];
+        W[e] = v;
+        O[e] = v;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < b; ++kk) {
+        const int k = k0 + kk;
+        const double *wc = W + kk * n;
+        if (spd) {
+            if (tid == 0) {
+                piv_sh = k;
+                const double d = wc[k];
+                if (!(d > thr_sh) || !isfinite(d)) fail_sh = isfinite(d) ? 5 : 7;
+            }
+        } else {
+            double best = -1.0;
+            int bi = k;
+            for (int i = k + tid; i < n; i += GPT) {
+                const double v = fabs(wc[i]);
+                if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+            }
+            if ((tid & 63) == 0) { sval[tid >> 6] = best; sidx[tid >> 6] = bi; }
+            __syncthreads();
+            if (tid == 0) {
+                double bv = sval[0];
+                int bix = sidx[0];
+                for (int w = 1; w < GPT / 64; ++w)
+                    if (sval[w] > bv || (sval[w] == bv && sidx[w] < bix)) { bv = sval[w]; bix = sidx[w]; }
+                piv_sh = bix;
+                if (!(bv > 0.0) || !isfinite(bv)) fail_sh = isfinite(bv) ? 5 : 7;
+            }
+        }
+        __syncthreads();
+        if (fail_sh) break;
+        const int p = piv_sh;
+        if (p != k) {
+            for (int j = tid; j < b; j += GPT) {
+                double t = W[j * n + k];
+                W[j * n + k] = W[j * n + p];
+                W[j * n + p] = t;
+                t = O[j * n + k];
+                O[j * n + k] = O[j * n + p];
+                O[j * n + p] = t;
+            }
+        }
+        if (tid == 0) piv[k] = p;
+        __syncthreads();
+        // scale the pivot row of the later panel columns, then eliminate
+        const double inv = 1.0 / W[kk * n + k];
+        for (int j = kk + 1 + tid; j < b; j += GPT) W[j * n + k] *= inv;
+        __syncthreads();
+        const int wcols = b - kk - 1;
+        for (int e = tid; e < n * wcols; e += GPT) {
+            const int jj = e / n, i = e - jj * n;
+            if (i == k) continue;
+            const int j = kk + 1 + jj;
+            W[j * n + i] -= W[kk * n + i] * W[j * n + k];
+        }
+        __syncthreads();
+    }
+    if (fail_sh) {
+        if (tid == 0) atomicMax(status, fail_sh);
+        return;
+    }
+    // P^{-1} for the pivot block P[r][c] = O[c * n + k0 + r]: Gauss-Jordan on [P | I]
+    // in the pivot order the panel used (no further pivoting), in LDS (reuses W)
+    double *G = gsm + 2 * n * b;  // b x 2b, column-major with leading dimension b
+    for (int e = tid; e < b * 2 * b; e += GPT) {
+        const int c = e / b, r = e - c * b;
+        G[e] = c < b ? O[c * n + k0 + r] : (c - b == r ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < b; ++kk) {
+        const double inv = 1.0 / G[kk * b + kk];
+        __syncthreads();
+        for (int c = kk + tid; c < 2 * b; c += GPT) G[c * b + kk] *= inv;
+        __syncthreads();
+        for (int e = tid; e < b * 2 * b; e += GPT) {
+            const int c = e / b, r = e - c * b;
+            if (r == kk || c <= kk) continue;
+            G[c * b + r] -= G[kk * b + r] * G[c * b + kk];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * b; e += GPT) work[e] = O[e];
+    for (int e = tid; e < b * b; e += GPT) {
+        const int c = e / b, r = e - c * b;
+        work[(size_t)n * GB + e] = G[(b + c) * b + r];  // P^{-1}[r][c], column-major b x b
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gjb_update(double *__restrict__ A, int lda,
+                                                    double *__restrict__ B, int ldb, int n,
+                                                    int m, int k0, int b,
+                                                    const double *__restrict__ work,
+                                                    const int *__restrict__ piv,
+                                                    const int *__restrict__ status) {
+    extern __shared__ double usm[];
+    double *X = usm;              // n x GCW, column c at X + c * n
+    double *Y = usm + n * GCW;    // b x GCW
+    if (*status) return;
+    const int tid = threadIdx.x;
+    const int jbeg = k0 + b;
+    const int ncol = (n - jbeg) + m;
+    const int c0 = blockIdx.x * GCW;
+    const int cw = min(GCW, ncol - c0);
+    auto colp = [&](int c) -> double * {
+        const int j = jbeg + c0 + c;
+        return j < n ? A + (long)j * lda : B + (long)(j - n) * ldb;
+    };
+    for (int e = tid; e < n * cw; e += 256) {
+        const int c = e / n, i = e - c * n;
+        X[c * n + i] = colp(c)[i];
+    }
+    __syncthreads();
+    if (tid < cw) {
+        double *x = X + tid * n;
+        for (int kk = 0; kk < b; ++kk) {
+            const int p = piv[k0 + kk];
+            if (p != k0 + kk) {
+                const double t = x[k0 + kk];
+                x[k0 + kk] = x[p];
+                x[p] = t;
+            }
+        }
+    }
+    __syncthreads();
+    const double *Pinv = work + (size_t)n * GB;
+    for (int e = tid; e < b * cw; e += 256) {
+        const int c = e / b, r = e - c * b;
+        const double *x = X + c * n + k0;
+        double s = 0.0;
+        for (int q = 0; q < b; ++q) s += Pinv[q * b + r] * x[q];
+        Y[c * b + r] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * cw; e += 256) {
+        const int c = e / n, i = e - c * n;
+        const double *y = Y + c * b;
+        double v;
+        if (i >= k0 && i < k0 + b) {
+            v = y[i - k0];
+        } else {
+            double s = 0.0;
+            for (int q = 0; q < b; ++q) s += work[(size_t)q * n + i] * y[q];
+            v = X[c * n + i] - s;
+        }
+        colp(c)[i] = v;
+    }
+}
+
 // Cyclic Jacobi with round-robin (circle) ordering: each round rotates n/2
 // disjoint pairs.  A <- J^T A J with J the Givens rotation zeroing A_pq.
 constexpr int JT = 1024;
@@ -397,13 +594,31 @@ hipError_t nn_axpby(double *C, int ldc, double a, const double *A, int lda, doub
 }
 
 hipError_t nn_gj_solve(double *A, int lda, double *B, int ldb, int n, int m, bool spd,
-                       int *status, hipStream_t st) {
+                       int *status, hipStream_t st, double *work, int *piv) {
     if (n <= 0) return hipSuccess;
-    const size_t smem = sizeof(double) * (size_t)(n + n + m);
-    hipLaunchKernelGGL(k_gj, dim3(1), dim3(GJT), smem, st, A, lda, B, ldb, n, m, (int)spd,
-                       status);
+    if (n > kGjBlockedMax || !work || !piv) {
+        const size_t smem = sizeof(double) * (size_t)(n + n + m);
+        hipLaunchKernelGGL(k_gj, dim3(1), dim3(GJT), smem, st, A, lda, B, ldb, n, m, (int)spd,
+                           status);
+        return hipGetLastError();
+    }
+    // LDS of the panel kernel: 2 n b + 2 b^2 doubles (<= 144 KiB)
+    const int bw = n <= 256 ? GB : GB / 2;
+    for (int k0 = 0; k0 < n; k0 += bw) {
+        const int b = min(bw, n - k0);
+        hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(GPT),
+                           sizeof(double) * (2 * (size_t)n * b + 2 * (size_t)b * b), st,
+                           A, lda, n, k0, b, (int)spd, work, piv, status);
+        const int ncol = (n - k0 - b) + m;
+        if (ncol > 0)
+            hipLaunchKernelGGL(k_gjb_update, dim3((ncol + GCW - 1) / GCW), dim3(256),
+                               sizeof(double) * (size_t)(n + b) * GCW, st, A, lda, B, ldb, n, m,
+                               k0, b, work, piv, status);
+    }
     return hipGetLastError();
 }
+
+size_t nn_gj_work_elems(int n) { return (size_t)n * GB + GB * GB + 8; }
 
 hipError_t nn_jacobi(double *A, int lda, int n, double *evals, double *V, int ldv, double *work,
                      hipStream_t st) {

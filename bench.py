@@ -9,10 +9,15 @@ matrices, the N x N predictor solve, the two block updates and the energy).
 
 value = steps/s of the mixed-precision path (FP32 PCG inside FP64 iterative
 refinement, BF16 Gram tiles with FP32 accumulation, FP64 N x N algebra and
-energy); the FP64 path is timed beside it.  The roofline object describes the
-dominant kernel of the mixed path, measured live with HIP events around every
-launch on the library's stream.  cpu_baseline times the FP64 oracle on a
-bounded sample of the same workload on the host cores.
+energy); the FP64 path is timed beside it.  The inverse operator is applied by
+PCG with the fast-Poisson preconditioner (DST-I inverse of kappa(-Lap_h) + vbar
+on FP16 matrix cores); the same step with the Jacobi preconditioner is timed
+beside it (--jacobi-steps).  The accuracy gate compares the mixed and FP64
+Ritz values of the converged pairs after the same number of steps.  The
+roofline object describes the dominant streaming kernel of the mixed path,
+measured live with HIP events around every launch on the library's stream.
+cpu_baseline times the FP64 oracle on a bounded sample of the same workload on
+the host cores.
 """
 from __future__ import annotations
 
@@ -30,15 +35,22 @@ if ROOT not in sys.path:
 
 METRIC = "steps/s at 96³,N=256: mixed vs FP64 at 1e-8 eig error; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per (grid point x column) of one launch; s = bytes per value
-#   two-sweep form  sweep1: read r, p_old; write p           -> 3 s
-#                   sweep2: read p, x, r;  write x, r        -> 5 s
-#   one-sweep form  cg:     read r, p_old, x; write r, p, x  -> 6 s
+# algorithmic bytes per (grid point x column) of one launch; s = bytes per value of the
+# PCG (8 in FP64, 4 in the mixed path's FP32 iteration); FP16 intermediates are 2 bytes
+#   two-sweep form  sweep1: read r (or z), p_old; write p     -> 3 s
+#                   sweep2: read p, x, r;  write x, r         -> 5 s
+#   one-sweep form  cg:     read r, p_old, x; write r, p, x   -> 6 s
+#   fast-Poisson    dst_fwd: read r; write t1 (FP16)          -> s + 2
+#                   dst_pencil: read t1, write t2 (FP16)      -> 4
+#                   dst_inv: read t2 (FP16), r; write z       -> 2 s + 2
 BYTES_PER_COLPT = {"sweep1_f64": 24, "sweep2_f64": 40, "sweep1_f32": 12, "sweep2_f32": 20,
                    "cg_f64": 48, "cg_f32": 24}
+DST_BYTES = {"dst_fwd": lambda s: s + 2, "dst_pencil": lambda s: 4,
+             "dst_inv": lambda s: 2 * s + 2}
 KERNEL_SYMBOL = {"sweep1_f64": "k_pcg_sweep1<double>", "sweep2_f64": "k_pcg_sweep2<double>",
                  "sweep1_f32": "k_pcg_sweep1<float>", "sweep2_f32": "k_pcg_sweep2<float>",
-                 "cg_f64": "k_cg_step<double>", "cg_f32": "k_cg_step<float>"}
+                 "cg_f64": "k_cg_step<double>", "cg_f32": "k_cg_step<float>",
+                 "dst_pencil": "k_dst_pencil"}
 
 
 def lambda1_estimate(n_coarse=32, seed=0):
@@ -60,19 +72,27 @@ def lambda1_estimate(n_coarse=32, seed=0):
     return float(vals[0])
 
 
-def run_gpu(precision, V, U0, n, N, tau, steps, warmup, inner_tol, log, variant=1):
-    import torch
-
+def make_solver(precision, n, N, inner_tol, variant, precond):
     from paper_2605_25149_amd import binding
 
-    s = binding.Solver(3, n, N, pcg_tol=1e-10, pcg_maxit=5000, pcg_check=8,
-                       precision=precision, refine_inner_tol=inner_tol, pcg_variant=variant)
+    # the fast-Poisson solve takes ~10 iterations: poll convergence after every one
+    check = 1 if precond == "fast_poisson" else 8
+    return binding.Solver(3, n, N, pcg_tol=1e-10, pcg_maxit=5000, pcg_check=check,
+                          precision=precision, refine_inner_tol=inner_tol, pcg_variant=variant,
+                          precond=precond)
+
+
+def run_gpu(precision, V, U0, n, N, tau, steps, warmup, inner_tol, log, variant=0,
+            precond="fast_poisson"):
+    import torch
+
+    s = make_solver(precision, n, N, inner_tol, variant, precond)
     try:
         s.set_potential(V)
         s.set_state(U0)
         for i in range(warmup):
             st = s.step(tau)
-            log(f"[{precision}] warmup step {i + 1}/{warmup}: iters {st['pcg_iters']} "
+            log(f"[{precision} {precond}] warmup step {i + 1}/{warmup}: iters {st['pcg_iters']} "
                 f"rounds {st['refine_rounds']} E {st['energy']:.10f}")
         s.profile(True)
         torch.cuda.synchronize()
@@ -81,7 +101,7 @@ def run_gpu(precision, V, U0, n, N, tau, steps, warmup, inner_tol, log, variant=
         for i in range(steps):
             st = s.step(tau)
             stats.append(st)
-            log(f"[{precision}] step {i + 1}/{steps}: iters {st['pcg_iters']} "
+            log(f"[{precision} {precond}] step {i + 1}/{steps}: iters {st['pcg_iters']} "
                 f"rounds {st['refine_rounds']} E {st['energy']:.10f} "
                 f"phases(ms) {[round(x, 1) for x in st['t_phase_ms']]}")
         torch.cuda.synchronize()
@@ -93,7 +113,8 @@ def run_gpu(precision, V, U0, n, N, tau, steps, warmup, inner_tol, log, variant=
         s.close()
 
 
-def accuracy_gate(V, U0, n, N, tau, K, inner_tol, variant, log, res_tol=1e-5):
+def accuracy_gate(V, U0, n, N, tau, K, inner_tol, variant, log, res_tol=1e-5,
+                  precond="fast_poisson"):
     """Mixed vs FP64 after the same K-step trajectory: Ritz values of the pairs that the FP64
     run has converged (relative residual ||H u - theta u|| / (|theta| ||u||) <= res_tol)."""
     import torch
@@ -102,8 +123,7 @@ def accuracy_gate(V, U0, n, N, tau, K, inner_tol, variant, log, res_tol=1e-5):
 
     out = {}
     for mode in ("fp64", "mixed"):
-        s = binding.Solver(3, n, N, pcg_tol=1e-10, pcg_maxit=5000, pcg_check=8, precision=mode,
-                           refine_inner_tol=inner_tol, pcg_variant=variant)
+        s = make_solver(mode, n, N, inner_tol, variant, precond)
         try:
             s.set_potential(V)
             s.set_state(U0)
@@ -162,10 +182,19 @@ def profile_traffic_ratios():
     return ratios
 
 
-def roofline_of(prof, ng):
-    """Dominant PCG sweep kernel: algorithmic bytes per launch / mean launch duration."""
+def bytes_per_colpt(prof_keys, value_bytes):
+    out = dict(BYTES_PER_COLPT)
+    for k, f in DST_BYTES.items():
+        out[k] = f(value_bytes)
+    return {k: v for k, v in out.items() if k in prof_keys}
+
+
+def roofline_of(prof, ng, value_bytes):
+    """Dominant streaming kernel (PCG sweeps and preconditioner passes, by total time):
+    algorithmic bytes per launch / mean launch duration."""
+    bpc = bytes_per_colpt(prof.keys(), value_bytes)
     best = None
-    for k, bpp in BYTES_PER_COLPT.items():
+    for k in bpc:
         d = prof[k]
         if d["launches"] == 0 or d["ms"] <= 0:
             continue
@@ -174,12 +203,15 @@ def roofline_of(prof, ng):
     if best is None:
         return None
     d = prof[best]
-    bytes_total = BYTES_PER_COLPT[best] * ng * d["work"]
+    bytes_total = bpc[best] * ng * d["work"]
     per_launch_bytes = bytes_total / d["launches"]
     mean_ms = d["ms"] / d["launches"]
     achieved = per_launch_bytes / (mean_ms * 1e-3) / 1e9
+    sym = KERNEL_SYMBOL.get(best) or {
+        "dst_fwd": "k_dst_plane<%s, false>", "dst_inv": "k_dst_plane<%s, true>"}[best] % (
+        "float" if value_bytes == 4 else "double")
     return {
-        "kernel": KERNEL_SYMBOL[best],
+        "kernel": sym,
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -193,25 +225,35 @@ def roofline_of(prof, ng):
     }
 
 
-def cpu_baseline(V, U0, n, N, tau, colits_per_step, log):
+def cpu_baseline(V, U0, n, N, tau, colits_per_step, log, precond="fast_poisson"):
     """FP64 oracle on the host: a bounded sample of the same workload, scaled to steps/s.
 
-    Sample: (a) oracle Jacobi-PCG on all N columns of the 96^3 grid for a fixed number of
-    iterations (its column-iteration rate); (b) one pass of the oracle's non-PCG stages
-    (three Gram matrices, the 2N x 2N predictor solve and the block update, the corrector
-    and the energy) on full-size blocks.  Steps/s = 1 / (column-iterations per step /
-    rate + time of (b)), with column-iterations per step taken from the FP64 GPU run
-    (same algorithm and stop rule)."""
+    Sample: (a) the oracle's PCG (same preconditioner as the GPU run) on all N columns of
+    the 96^3 grid for a fixed number of iterations, giving its column-iteration rate;
+    (b) one pass of the oracle's non-PCG stages (three Gram matrices, the 2N x 2N
+    predictor solve and the block update, the corrector and the energy) on full-size
+    blocks.  Steps/s = 1 / (column-iterations per step / rate + time of (b)), with
+    column-iterations per step taken from the FP64 GPU run (same algorithm and stop
+    rule)."""
     from oracle import oracle as orc
 
     prob = orc.Problem(3, n, V)
     Uf = np.asfortranarray(U0)
-    kit = int(os.environ.get("QO_CPU_PCG_ITERS", "6"))
-    t0 = time.perf_counter()
-    X, its, st, _ = prob.solve(Uf, tol=1e-30, maxit=kit)
-    t_pcg = time.perf_counter() - t0
-    rate = N * kit / t_pcg
-    log(f"[cpu] oracle PCG {N} columns x {kit} iterations: {t_pcg:.2f} s "
+    if precond == "fast_poisson":
+        # the oracle's transforms run column by column: a subset of the columns
+        ncs = min(N, int(os.environ.get("QO_CPU_COLS", "32")))
+        kit = int(os.environ.get("QO_CPU_PCG_ITERS", "2"))
+        t0 = time.perf_counter()
+        prob.solve_fast_poisson(np.asfortranarray(Uf[:, :ncs]), tol=1e-30, maxit=kit)
+        t_pcg = time.perf_counter() - t0
+    else:
+        ncs = N
+        kit = int(os.environ.get("QO_CPU_PCG_ITERS", "6"))
+        t0 = time.perf_counter()
+        prob.solve(Uf, tol=1e-30, maxit=kit)
+        t_pcg = time.perf_counter() - t0
+    rate = ncs * kit / t_pcg
+    log(f"[cpu] oracle {precond} PCG {ncs} columns x {kit} iterations: {t_pcg:.2f} s "
         f"({rate:.1f} column-iterations/s)")
     P = np.asfortranarray(0.1 * Uf)
     t0 = time.perf_counter()
@@ -227,7 +269,7 @@ def cpu_baseline(V, U0, n, N, tau, colits_per_step, log):
         "unit": "steps/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"96^3 x {N}: oracle PCG {kit} iterations on all columns "
+        "sample": (f"96^3 x {N}: oracle {precond} PCG, {kit} iterations on {ncs} columns "
                    f"({t_pcg:.1f} s) + one pass of the non-PCG stages ({t_rest:.1f} s); "
                    f"scaled by {colits_per_step:.0f} column-iterations per step"),
         "seconds_per_step": round(sec_per_step, 2),
@@ -246,8 +288,12 @@ def main():
     ap.add_argument("--pcg-variant", type=int, default=0,
                     help="0: two-sweep Hestenes-Stiefel PCG, 1: one-sweep Chronopoulos-Gear")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--accuracy-steps", type=int, default=0,
-                    help="also run the mixed-vs-FP64 eigenvalue gate over this many steps")
+    ap.add_argument("--precond", default="fast_poisson", choices=["fast_poisson", "jacobi"])
+    ap.add_argument("--jacobi-steps", type=int, default=2,
+                    help="also time this many steps (after one warm-up step) with the Jacobi "
+                         "preconditioner in each mode (0: skip)")
+    ap.add_argument("--accuracy-steps", type=int, default=100,
+                    help="mixed-vs-FP64 eigenvalue gate over this many steps (0: skip)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
@@ -292,7 +338,7 @@ def main():
     res = {}
     for mode in args.modes.split(","):
         res[mode] = run_gpu(mode, V, U0_dev, n, N, tau, args.steps, args.warmup,
-                            args.inner_tol, log, args.pcg_variant)
+                            args.inner_tol, log, args.pcg_variant, args.precond)
         r = res[mode]
         log(f"[{mode}] {args.steps} steps in {r['seconds']:.3f} s -> "
             f"{args.steps / r['seconds']:.4f} steps/s")
@@ -316,9 +362,11 @@ def main():
         "config": {
             "workload": (f"3-D {args.n}^3 Dirichlet 7-point grid (Ng={ng}), 8 Gaussian wells "
                          f"(seed 0), N={N}, random U0 (seed 1), tau=0.9*lambda_1={tau:.5f}, "
-                         f"PCG tol 1e-10, warm starts; {head} precision"),
+                         f"PCG tol 1e-10 ({args.precond} preconditioner), warm starts; "
+                         f"{head} precision"),
             "grid": list(n), "N": N, "tau": tau, "pcg_tol": 1e-10,
             "refine_inner_tol": args.inner_tol, "pcg_variant": args.pcg_variant,
+            "precond": args.precond,
             "parallelism": "single GPU",
         },
     }
@@ -330,7 +378,8 @@ def main():
                                   for k, v in r["profile"].items() if v["launches"]}
     if "fp64" in res and "mixed" in res:
         out["speedup_mixed_vs_fp64"] = round(res["fp64"]["seconds"] / res["mixed"]["seconds"], 4)
-    rf = roofline_of(rh["profile"], ng)
+    vbytes = 4 if head == "mixed" else 8
+    rf = roofline_of(rh["profile"], ng, vbytes)
     if rf:
         ratio = profile_traffic_ratios().get(rf["kernel"])
         if ratio is not None:
@@ -338,17 +387,26 @@ def main():
             rf["traffic_ratio"] = ratio
         out["roofline"] = rf
     if "fp64" in res:
-        rf64 = roofline_of(res["fp64"]["profile"], ng)
+        rf64 = roofline_of(res["fp64"]["profile"], ng, 8)
         if rf64:
             out["roofline_fp64"] = rf64
     if args.accuracy_steps > 0:
         out["accuracy"] = accuracy_gate(V, U0_dev, n, N, tau, args.accuracy_steps,
-                                        args.inner_tol, args.pcg_variant, log)
+                                        args.inner_tol, args.pcg_variant, log,
+                                        precond=args.precond)
+    if args.jacobi_steps > 0 and args.precond != "jacobi":
+        jac = {}
+        for mode in args.modes.split(","):
+            r = run_gpu(mode, V, U0_dev, n, N, tau, args.jacobi_steps, 1, args.inner_tol, log,
+                        args.pcg_variant, "jacobi")
+            jac[mode] = {"steps_per_s": round(args.jacobi_steps / r["seconds"], 6),
+                         "pcg_iters_per_step": [st["pcg_iters"] for st in r["stats"]]}
+        out["jacobi_preconditioner"] = jac
     if not args.no_cpu_baseline:
         ref = res["fp64"] if "fp64" in res else rh
         colits = max(ref["profile"][k]["work"] for k in ("sweep2_f64", "sweep2_f32", "cg_f64", "cg_f32"))
         colits_per_step = colits / args.steps
-        out["cpu_baseline"] = cpu_baseline(V, U0, n, N, tau, colits_per_step, log)
+        out["cpu_baseline"] = cpu_baseline(V, U0, n, N, tau, colits_per_step, log, args.precond)
     print(json.dumps(out), flush=True)
 
 

@@ -376,7 +376,8 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
                             "PCG iterations (tol %.3g)", what, nact, ncols, maxit, tol);
         }
         hipEvent_t eb = prof_begin(c);
-        HIPC(c, launch_pcg_sweep2<T>(g, vs, dinv, pbuf[k & 1], X, R, c->ld, ncols, k, s, st));
+        HIPC(c, launch_pcg_sweep2<T>(g, vs, dinv, pbuf[k & 1], X, R, c->ld, ncols, k, s, st,
+                                     Z == nullptr));
         prof_end(c, k2, eb);
     }
     HIPC(c, hipMemcpyAsync(c->h_poll, s.its, sizeof(int) * ncols, hipMemcpyDeviceToHost, st));
@@ -500,7 +501,7 @@ qo_status solve_mixed_rel(qo_ctx *c, const double *B, double *X, int ncols, int 
             prof_end(c, QO_KERNEL_SWEEP1_F32, ea);
             hipEvent_t eb = prof_begin(c);
             HIPC(c, launch_pcg_sweep2<float>(g, c->vs32, c->dinv32, pbuf[k & 1], c->d32, c->r32,
-                                             c->ld, ncols, k, s, st));
+                                             c->ld, ncols, k, s, st, !c->dst));
             prof_end(c, QO_KERNEL_SWEEP2_F32, eb);
             if ((k + 1) % check != 0 && k + 1 < maxit) continue;
             int *act = s.active + (k & 1) * ncols;

@@ -106,7 +106,8 @@ hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T 
                              const double *rzp = nullptr, int rzt = 0);
 template <typename T>
 hipError_t launch_pcg_sweep2(const Grid &g, const T *vs, const T *dinv, const T *Pn, T *X, T *R,
-                             long ld, int ncols, int k, PcgState s, hipStream_t st);
+                             long ld, int ncols, int k, PcgState s, hipStream_t st,
+                             bool jac = true);
 
 // One-reduction (Chronopoulos-Gear) PCG: delta0 = u.Hu with u = D r0 into
 // part[3] (after launch_pcg_init on the same grid), then one sweep per iteration.

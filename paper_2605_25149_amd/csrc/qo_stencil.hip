@@ -23,6 +23,10 @@
 #include "qo_internal.h"
 #include "qo_device.h"
 
+#ifndef QO_SWEEP2_NT
+#define QO_SWEEP2_NT 1
+#endif
+
 namespace qo {
 
 namespace {
@@ -493,7 +497,10 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__rest
     if (threadIdx.x == 0) s.part[3 * qs + (long)col * tiles + tile] = ep.acc[0];
 }
 
-template <typename T>
+// x += alpha p; r -= alpha H p; partials r.D r (JAC: Jacobi form only) and r.r.
+// x and r are each read and written once per sweep: non-temporal accesses keep
+// them from evicting the stencil operand's halo rows from the caches.
+template <typename T, bool JAC>
 struct EpSweep2 {
     struct Raw { T x, r, d; };
     T *__restrict__ x;
@@ -502,18 +509,30 @@ struct EpSweep2 {
     T alpha;
     double acc[2];
     __device__ static Raw zero() { return {T(0), T(0), T(0)}; }
-    __device__ Raw load(long i) const { return {x[i], r[i], dinv[i]}; }
+    __device__ Raw load(long i) const {
+#if QO_SWEEP2_NT
+        return {__builtin_nontemporal_load(x + i), __builtin_nontemporal_load(r + i),
+                JAC ? dinv[i] : T(0)};
+#else
+        return {x[i], r[i], JAC ? dinv[i] : T(0)};
+#endif
+    }
     __device__ void operator()(int, long i, T c, T hv, const Raw &e) {
-        x[i] = e.x + alpha * c;
         const T ri = e.r - alpha * hv;
+#if QO_SWEEP2_NT
+        __builtin_nontemporal_store(e.x + alpha * c, x + i);
+        __builtin_nontemporal_store(ri, r + i);
+#else
+        x[i] = e.x + alpha * c;
         r[i] = ri;
+#endif
         const double rd = (double)ri;
-        acc[0] += rd * (double)(e.d * ri);
+        if (JAC) acc[0] += rd * (double)(e.d * ri);
         acc[1] += rd * rd;
     }
 };
 
-template <typename T, int PPT>
+template <typename T, int PPT, bool JAC>
 __global__ __launch_bounds__(kThreads) void k_pcg_sweep2(Grid g, const T *__restrict__ vs,
                                                          const T *__restrict__ dinv,
                                                          const T *__restrict__ Pn,
@@ -542,7 +561,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep2(Grid g, const T *__rest
     if (sh_flag) return;
     const T alpha = (T)(s.rho[cur * ncols + col] / gam);
     LdPlain<T> l{Pn + (long)col * ld};
-    EpSweep2<T> ep{X + (long)col * ld, R + (long)col * ld, dinv, alpha, {0.0, 0.0}};
+    EpSweep2<T, JAC> ep{X + (long)col * ld, R + (long)col * ld, dinv, alpha, {0.0, 0.0}};
     engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
     block_sums<2>(ep.acc, red);
     if (threadIdx.x == 0) {
@@ -758,13 +777,19 @@ hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T 
 
 template <typename T>
 hipError_t launch_pcg_sweep2(const Grid &g, const T *vs, const T *dinv, const T *Pn, T *X, T *R,
-                             long ld, int ncols, int k, PcgState s, hipStream_t st) {
+                             long ld, int ncols, int k, PcgState s, hipStream_t st, bool jac) {
     if (ncols <= 0) return hipSuccess;
     const long qs = (long)ncols * g.tiles();
     const dim3 grid(ncols * g.tiles());
-    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep2<T, P>), grid, dim3(kThreads),
-                                               lds_bytes(g, sizeof(T)), st, g, vs, dinv, Pn, X, R,
-                                               ld, ncols, k, s, qs));
+    if (jac) {
+        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep2<T, P, true>), grid,
+                                                   dim3(kThreads), lds_bytes(g, sizeof(T)), st,
+                                                   g, vs, dinv, Pn, X, R, ld, ncols, k, s, qs));
+    } else {
+        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep2<T, P, false>), grid,
+                                                   dim3(kThreads), lds_bytes(g, sizeof(T)), st,
+                                                   g, vs, dinv, Pn, X, R, ld, ncols, k, s, qs));
+    }
     return hipGetLastError();
 }
 
@@ -784,10 +809,10 @@ template hipError_t launch_pcg_sweep1<float>(const Grid &, const float *, const 
                                              const float *, const double *, int);
 template hipError_t launch_pcg_sweep2<double>(const Grid &, const double *, const double *,
                                               const double *, double *, double *, long, int, int,
-                                              PcgState, hipStream_t);
+                                              PcgState, hipStream_t, bool);
 template hipError_t launch_pcg_sweep2<float>(const Grid &, const float *, const float *,
                                              const float *, float *, float *, long, int, int,
-                                             PcgState, hipStream_t);
+                                             PcgState, hipStream_t, bool);
 
 template <typename T>
 hipError_t launch_cg_delta0(const Grid &g, const T *vs, const T *dinv, const T *R, long ld,

@@ -46,30 +46,53 @@ __global__ __launch_bounds__(64) void k_tsgemm(double *__restrict__ Out, long ld
             }
         }
 
-    for (int pass = 0; pass < 2; ++pass) {
-        const double *T = pass == 0 ? A : B;
-        const double *S = pass == 0 ? Xr : Yr;
-        if (!T) continue;
-        for (int k0 = 0; k0 < n; k0 += 4) {
-            const int k = k0 + lg;
-            double sa[4], tb[4];
+    // One K range over [A | B] (length n, or 2n with B), in chunks of 16 k-values
+    // (4 MFMA k-steps); the next chunk's loads are issued before the current chunk's
+    // MFMAs, so the memory latency hides behind 64 MFMAs.
+    // Operand pairs present: (A, Xr) and/or (B, Yr); either may be absent.  The K
+    // range covers the present ones only, so no load ever goes through a null pointer.
+    const double *T0 = A ? A : B, *S0 = A ? Xr : Yr;
+    const double *T1 = A ? B : nullptr, *S1 = A ? Yr : nullptr;
+    const int ktot = (T0 ? n : 0) + (T1 ? n : 0);
+    auto load_chunk = [&](int kc, double (&sa)[4][4], double (&tb)[4][4]) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kg = kc + 4 * ks + lg;
+            const bool second = kg >= n;  // only reachable when T1 is present (ktot = 2n)
+            const int k = second ? kg - n : kg;
+            const double *T = second ? T1 : T0;
+            const double *S = second ? S1 : S0;
+            const bool kin = kg < ktot;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int c = c0 + 16 * j + lr;
-                sa[j] = (k < n && c < n) ? S[(long)k * n + c] : 0.0;
+                sa[ks][j] = (kin && c < n) ? S[(long)k * n + c] : 0.0;
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const long m = m0 + 16 * i + lr;
-                tb[i] = (k < n && m < ng) ? T[(long)k * ld + m] : 0.0;
+                tb[ks][i] = (kin && m < ng) ? T[(long)k * ld + m] : 0.0;
             }
+        }
+    };
+    auto mma_chunk = [&](const double (&sa)[4][4], const double (&tb)[4][4]) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    acc[j][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[j], tb[i], acc[j][i], 0,
-                                                                    0, 0);
-        }
+                    acc[j][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[ks][j], tb[ks][i],
+                                                                    acc[j][i], 0, 0, 0);
+    };
+    double sa0[4][4], tb0[4][4], sa1[4][4], tb1[4][4];
+    load_chunk(0, sa0, tb0);
+    for (int kc = 0; kc < ktot; kc += 32) {
+        if (kc + 16 < ktot) load_chunk(kc + 16, sa1, tb1);
+        mma_chunk(sa0, tb0);
+        if (kc + 16 >= ktot) break;
+        if (kc + 32 < ktot) load_chunk(kc + 32, sa0, tb0);
+        mma_chunk(sa1, tb1);
     }
     // FP64 16x16 accumulator layout: value v of lane l is row l/16 + 4v, column l%16,
     // so acc[j][i][v] = Out^T[c0 + 16j + lg + 4v][m0 + 16i + lr]
@@ -93,6 +116,9 @@ hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *
                          const double *Xr, const double *B, const double *Yr, long ld, long ng,
                          int n, hipStream_t st) {
     if (n <= 0 || ng <= 0) return hipSuccess;
+    // each big operand needs its small operand (and the reverse)
+    if ((A == nullptr) != (Xr == nullptr) || (B == nullptr) != (Yr == nullptr) || !Out)
+        return hipErrorInvalidValue;
     const dim3 grid((unsigned)((ng + 63) / 64), (unsigned)((n + 63) / 64));
     hipLaunchKernelGGL(k_tsgemm, grid, dim3(64), 0, st, Out, ldo, C0, A, Xr, B, Yr, ld, ng, n);
     return hipGetLastError();

@@ -66,6 +66,7 @@ struct qo_ctx {
     // reductions and small matrices
     double *part = nullptr;
     double *gpart = nullptr;
+    __bf16 *zb = nullptr;  // BF16 copy of [X | Y] for the mixed-precision Gram
     int gnsplit = 1;
     double *G1 = nullptr, *G2 = nullptr;
     double *mpool = nullptr;
@@ -617,7 +618,7 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
 qo_status gram(qo_ctx *c, const double *X, const double *Y, long ld, int n, double *G) {
     hipEvent_t e = prof_begin(c);
     if (c->mixed)
-        HIPC(c, launch_gram_bf16(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G, c->st));
+        HIPC(c, launch_gram_bf16(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G, c->zb, c->st));
     else
         HIPC(c, launch_gram_f64(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G, c->st));
     prof_end(c, QO_KERNEL_GRAM, e);
@@ -980,6 +981,7 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
     A(&h->part, (size_t)8 * h->qsmax);
     h->gnsplit = gram_nsplit(h->ng, N);
     A(&h->gpart, gram_part_elems(N, h->gnsplit));
+    if (h->mixed) A(&h->zb, 2 * blk);
     A(&h->G1, (size_t)4 * N * N);
     A(&h->G2, (size_t)4 * N * N);
     A(&h->mpool, (size_t)MP_COUNT * N * N);
@@ -1400,7 +1402,17 @@ qo_status qo_gram_pair(qo_handle h, const double *X, const double *Y, long ld, i
     if (!h) return QO_ERR_ARG;
     if (!X || !Y || !G || ld < h->ng || ncols < 1 || ncols > h->N)
         return fail(h, QO_ERR_ARG, "bad arguments to qo_gram_pair");
-    QOC(gram(h, X, Y, ld, ncols, h->G2));
+    if (h->mixed) {
+        // the BF16 path packs from the internal layout (leading dimension h->ld)
+        const size_t row = sizeof(double) * h->ng;
+        HIPC(h, hipMemcpy2DAsync(h->W, sizeof(double) * h->ld, X, sizeof(double) * ld, row, ncols,
+                                 hipMemcpyDeviceToDevice, h->st));
+        HIPC(h, hipMemcpy2DAsync(h->W2, sizeof(double) * h->ld, Y, sizeof(double) * ld, row,
+                                 ncols, hipMemcpyDeviceToDevice, h->st));
+        QOC(gram(h, h->W, h->W2, h->ld, ncols, h->G2));
+    } else {
+        QOC(gram(h, X, Y, ld, ncols, h->G2));
+    }
     HIPC(h, hipMemcpyAsync(G, h->G2, sizeof(double) * 4 * ncols * ncols, hipMemcpyDeviceToHost,
                            h->st));
     HIPC(h, hipStreamSynchronize(h->st));

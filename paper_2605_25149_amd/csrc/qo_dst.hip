@@ -32,6 +32,12 @@
 #include "qo_internal.h"
 #include "qo_device.h"
 
+#include <algorithm>
+
+#ifndef QO_PLANE_ALIAS
+#define QO_PLANE_ALIAS 1
+#endif
+
 namespace qo {
 
 namespace {
@@ -164,7 +170,11 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
     const int NXP = p.NXP, XP = NXP + 8;
     const int nx = p.nx;
     _Float16 *X = reinterpret_cast<_Float16 *>(smem);
+#if QO_PLANE_ALIAS
+    _Float16 *TT = X;  // T^T is written over X once every wave is past GEMM1
+#else
     _Float16 *TT = X + p.RP * XP;
+#endif
     const int TP = p.NYP + 8;
 
     const int row0 = slab * p.rows;
@@ -242,6 +252,9 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
 
     if (p.dim == 3) {
         // T^T into LDS, then Y = S_y T
+#if QO_PLANE_ALIAS
+        __syncthreads();
+#endif
 #pragma unroll
         for (int j = 0; j < NT; ++j) st4h(TT + (16 * j + lr) * TP + 16 * w + 4 * lg, acc[j], 1.f);
         __syncthreads();
@@ -258,28 +271,77 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
         }
     }
 
-    // ---- epilogue: rows 16w + 4lg + v, columns 16j + lr of the slab
-    double rz = 0.0;
-    const float unscale = INV ? 1.f / (sc * p.lmin) : 0.f;
+    // ---- epilogue: lane values are rows 16w + 4lg + v, columns 16j + lr of the slab.
+    // They are staged row-major in LDS, then each lane stores 16 contiguous bytes.
+    __syncthreads();  // every wave is done reading X (and TT)
+    if (!INV) {
+        _Float16 *ST = X;  // RP x XP halves
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int x = 16 * j + lr;
-        if (x >= nx) continue;
+        for (int j = 0; j < NT; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = 16 * w + 4 * lg + v;
-            if (r >= rows) continue;
-            const long i = base + (long)r * nx + x;
-            if (!INV) {
-                Hout[i] = (_Float16)acc[j][v];
+            for (int v = 0; v < 4; ++v)
+                ST[(16 * w + 4 * lg + v) * XP + 16 * j + lr] = (_Float16)acc[j][v];
+        __syncthreads();
+        const int g8 = NXP / 8;
+        const bool vec = (nx % 8) == 0;
+        for (int it = tid; it < rows * g8; it += nthr) {
+            const int r = it / g8;
+            const int x = (it - r * g8) * 8;
+            if (x >= nx) continue;
+            _Float16 *dst = Hout + base + (long)r * nx + x;
+            const _Float16 *src = ST + r * XP + x;
+            if (vec) {
+                *reinterpret_cast<v8h *>(dst) = *reinterpret_cast<const v8h *>(src);
             } else {
-                const T zv = (T)(acc[j][v] * unscale);
-                Z[i] = zv;
-                rz += (double)R[i] * (double)zv;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (x + i < nx) dst[i] = src[i];
             }
         }
-    }
-    if (INV) {
+    } else {
+        const int FP = NXP + 4;
+        float *SF = reinterpret_cast<float *>(smem);  // RP x FP floats
+        const float unscale = 1.f / (sc * p.lmin);
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                SF[(16 * w + 4 * lg + v) * FP + 16 * j + lr] = acc[j][v] * unscale;
+        __syncthreads();
+        double rz = 0.0;
+        const int g4 = NXP / 4;
+        const bool vec = (nx % 4) == 0;
+        for (int it = tid; it < rows * g4; it += nthr) {
+            const int r = it / g4;
+            const int x = (it - r * g4) * 4;
+            if (x >= nx) continue;
+            const long i0 = base + (long)r * nx + x;
+            const float *src = SF + r * FP + x;
+            if (vec) {
+                const float4 z4 = *reinterpret_cast<const float4 *>(src);
+                if constexpr (sizeof(T) == 4) {
+                    *reinterpret_cast<float4 *>(Z + i0) = z4;
+                    const float4 r4 = *reinterpret_cast<const float4 *>(R + i0);
+                    rz += (double)r4.x * z4.x + (double)r4.y * z4.y + (double)r4.z * z4.z +
+                          (double)r4.w * z4.w;
+                } else {
+                    const double2 za{z4.x, z4.y}, zb{z4.z, z4.w};
+                    *reinterpret_cast<double2 *>(Z + i0) = za;
+                    *reinterpret_cast<double2 *>(Z + i0 + 2) = zb;
+                    const double2 ra = *reinterpret_cast<const double2 *>(R + i0);
+                    const double2 rb = *reinterpret_cast<const double2 *>(R + i0 + 2);
+                    rz += ra.x * za.x + ra.y * za.y + rb.x * zb.x + rb.y * zb.y;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (x + i >= nx) break;
+                    const T zv = (T)src[i];
+                    Z[i0 + i] = zv;
+                    rz += (double)R[i0 + i] * (double)zv;
+                }
+            }
+        }
         rz = block_sum(rz, red);
         if (tid == 0) rzp[(long)col * p.nslab + slab] = rz;
     }
@@ -381,19 +443,40 @@ __global__ __launch_bounds__(1024) void k_dst_pencil(DstPlan p, const _Float16 *
             acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[j], 0, 0, 0);
         }
     }
+    // stage Z row-major ([s][m], pitch MB + 8) over XT and YT, then 16-byte stores
+    __syncthreads();  // every wave is done reading YT
+    constexpr int OP = MB + 8;
+    _Float16 *SO = XT;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const int m = m0 + 16 * j + lr;
-        if (m >= nf) continue;
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int s = 16 * w + 4 * lg + v;
-            if (s < ns) Hout[base + (long)s * nf + m] = (_Float16)acc[j][v];
+        for (int v = 0; v < 4; ++v) SO[(16 * w + 4 * lg + v) * OP + 16 * j + lr] = (_Float16)acc[j][v];
+    __syncthreads();
+    {
+        constexpr int G8 = MB / 8;
+        const bool vec = (nf % 8) == 0;
+        for (int it = tid; it < ns * G8; it += nthr) {
+            const int s = it / G8;
+            const int mm = (it - s * G8) * 8;
+            const int m = m0 + mm;
+            if (m >= nf) continue;
+            _Float16 *dst = Hout + base + (long)s * nf + m;
+            const _Float16 *src = SO + s * OP + mm;
+            if (vec) {
+                *reinterpret_cast<v8h *>(dst) = *reinterpret_cast<const v8h *>(src);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (m + i < nf) dst[i] = src[i];
+            }
         }
     }
 }
 
-constexpr int kPencilNJ = 4;  // MB = 64 positions per pencil workgroup
+#ifndef QO_PENCIL_NJ
+#define QO_PENCIL_NJ 4
+#endif
+constexpr int kPencilNJ = QO_PENCIL_NJ;  // MB = 16 NJ positions per pencil workgroup
 
 }  // namespace
 
@@ -436,9 +519,16 @@ void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz) {
     p.npen = (p.nf + 16 * kPencilNJ - 1) / (16 * kPencilNJ);
 }
 
-size_t dst_plane_lds(const DstPlan &p) {
+// X (RP x (NXP+8) halves) and, in 3-D, TT (NXP x (NYP+8) halves); the inverse pass
+// also stages its FP32 output (RP x (NXP+4) floats) over the same space.
+size_t dst_plane_lds(const DstPlan &p, bool inv) {
     size_t b = (size_t)p.RP * (p.NXP + 8) * 2;
+#if QO_PLANE_ALIAS
+    if (p.dim == 3) b = std::max(b, (size_t)p.NXP * (p.NYP + 8) * 2);
+#else
     if (p.dim == 3) b += (size_t)p.NXP * (p.NYP + 8) * 2;
+#endif
+    if (inv) b = std::max(b, (size_t)p.RP * (p.NXP + 4) * 4);
     return b;
 }
 
@@ -488,7 +578,7 @@ hipError_t launch_dst_fwd(const DstPlan &p, const T *R, long ld, int ncols, _Flo
     if (ncols <= 0) return hipSuccess;
     const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
     QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, false, NT>), grid, block,
-                                                  dst_plane_lds(p), st, p, R, nullptr, t1,
+                                                  dst_plane_lds(p, false), st, p, R, nullptr, t1,
                                                   nullptr, ld, pcs, nullptr));
     return hipGetLastError();
 }
@@ -508,7 +598,7 @@ hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, const T *R, T *Z
     if (ncols <= 0) return hipSuccess;
     const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
     QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, true, NT>), grid, block,
-                                                  dst_plane_lds(p), st, p, R, t2, nullptr, Z,
+                                                  dst_plane_lds(p, true), st, p, R, t2, nullptr, Z,
                                                   ld, pcs, rzp));
     return hipGetLastError();
 }

@@ -146,10 +146,42 @@ __global__ __launch_bounds__(64) void k_gram_f64(const double *__restrict__ X,
             }
 }
 
-__global__ __launch_bounds__(64) void k_gram_bf16(const double *__restrict__ X,
-                                                  const double *__restrict__ Y, long ld, long ng,
-                                                  int n, long kchunk, double *__restrict__ part,
-                                                  int vec_ok) {
+// Z = [X | Y] rounded to BF16 once: Zb[c * ld + r] for r < ld (rows ng..ld-1 zero), so
+// the Gram kernel reads whole 32-row steps with 16-byte loads and converts nothing.
+__global__ __launch_bounds__(256) void k_pack_bf16(const double *__restrict__ X,
+                                                   const double *__restrict__ Y, long ld,
+                                                   long ng, int n, __bf16 *__restrict__ Zb) {
+    const long per_col = ld / 8;
+    const long total = 2L * n * per_col;
+    for (long it = (long)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (long)gridDim.x * blockDim.x) {
+        const int c = (int)(it / per_col);
+        const long r = (it - (long)c * per_col) * 8;
+        const double *src = zcol(X, Y, ld, n, c) + r;
+        double v[8];
+        if (r + 8 <= ng) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const double2 q = reinterpret_cast<const double2 *>(src)[h];
+                v[2 * h] = q.x;
+                v[2 * h + 1] = q.y;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) v[s] = (r + s < ng) ? src[s] : 0.0;
+        }
+        v8bf o;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) o[s] = f64_to_bf16_rne(v[s]);
+        *reinterpret_cast<v8bf *>(Zb + (long)c * ld + r) = o;
+    }
+}
+
+// Gram tiles from the packed BF16 block: one wavefront, one 64 x 64 tile pair, one
+// K-chunk; the next 32-row step's fragments are loaded before the current step's MFMAs.
+__global__ __launch_bounds__(64) void k_gram_bf16(const __bf16 *__restrict__ Zb, long ld,
+                                                  long ng, int n, long kchunk,
+                                                  double *__restrict__ part) {
     const int nn = 2 * n;
     const int nt = (nn + TM - 1) / TM;
     // pairs of one K-chunk on one XCD: they read the same rows of the 2n columns
@@ -159,12 +191,13 @@ __global__ __launch_bounds__(64) void k_gram_bf16(const double *__restrict__ X,
     int ti, tj;
     tile_pair(L - split * npairs, nt, ti, tj);
     const long kb = (long)split * kchunk;
-    const long ke = min(ng, kb + kchunk);
+    // rows ng..ld-1 of Zb are zero and ld is a multiple of 64: whole 32-row steps
+    const long ke = min(ld, (min(ng, kb + kchunk) + 31) / 32 * 32);
     const int lane = threadIdx.x;
     const int lr = lane & 15, lg = lane >> 4;
 
-    const double *pa[4];
-    const double *pb[4];
+    const __bf16 *pa[4];
+    const __bf16 *pb[4];
     bool va[4], vb[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -172,51 +205,39 @@ __global__ __launch_bounds__(64) void k_gram_bf16(const double *__restrict__ X,
         const int cb = tj * TM + 16 * i + lr;
         va[i] = ca < nn;
         vb[i] = cb < nn;
-        pa[i] = va[i] ? zcol(X, Y, ld, n, ca) : X;
-        pb[i] = vb[i] ? zcol(X, Y, ld, n, cb) : X;
+        pa[i] = Zb + (long)(va[i] ? ca : 0) * ld + 8 * lg;
+        pb[i] = Zb + (long)(vb[i] ? cb : 0) * ld + 8 * lg;
     }
     v4f acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-
-    for (long k0 = kb; k0 < ke; k0 += 32) {
-        const long r0 = k0 + 8 * lg;
-        v8bf a[4], b[4];
-        const bool full = vec_ok && (r0 + 8 <= ke);
+    v8bf zero;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) zero[s] = (__bf16)0.f;
+    auto load = [&](long k0, v8bf (&a)[4], v8bf (&b)[4]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            double ta[8], tb[8];
-            if (full) {
-                const double2 *qa = reinterpret_cast<const double2 *>(pa[i] + r0);
-                const double2 *qb = reinterpret_cast<const double2 *>(pb[i] + r0);
-#pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    double2 x = va[i] ? qa[h] : double2{0.0, 0.0};
-                    double2 y = vb[i] ? qb[h] : double2{0.0, 0.0};
-                    ta[2 * h] = x.x; ta[2 * h + 1] = x.y;
-                    tb[2 * h] = y.x; tb[2 * h + 1] = y.y;
-                }
-            } else {
-#pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const bool in = (r0 + s) < ke;
-                    ta[s] = (va[i] && in) ? pa[i][r0 + s] : 0.0;
-                    tb[s] = (vb[i] && in) ? pb[i][r0 + s] : 0.0;
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                a[i][s] = f64_to_bf16_rne(ta[s]);
-                b[i][s] = f64_to_bf16_rne(tb[s]);
-            }
+            a[i] = va[i] ? *reinterpret_cast<const v8bf *>(pa[i] + k0) : zero;
+            b[i] = vb[i] ? *reinterpret_cast<const v8bf *>(pb[i] + k0) : zero;
         }
+    };
+    auto mma = [&](const v8bf (&a)[4], const v8bf (&b)[4]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    };
+    v8bf a0[4], b0[4], a1[4], b1[4];
+    if (kb < ke) load(kb, a0, b0);
+    for (long k0 = kb; k0 < ke; k0 += 64) {
+        if (k0 + 32 < ke) load(k0 + 32, a1, b1);
+        mma(a0, b0);
+        if (k0 + 32 >= ke) break;
+        if (k0 + 64 < ke) load(k0 + 64, a0, b0);
+        mma(a1, b1);
     }
     double *out = part + (long)split * nn * nn;
 #pragma unroll
@@ -264,9 +285,18 @@ int gram_nsplit(long ng, int n) {
 
 size_t gram_part_elems(int n, int nsplit) { return (size_t)nsplit * 4 * n * n; }
 
-static hipError_t gram_common(bool bf16, const double *X, const double *Y, long ld, long ng,
-                              int n, double w, double *part, int nsplit, double *G,
+static hipError_t gram_reduce(double *part, int nn, int nsplit, double w, double *G,
                               hipStream_t st) {
+    const long total = (long)nn * nn;
+    long blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)blocks), dim3(256), 0, st, part, nn, nsplit,
+                       w, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_f64(const double *X, const double *Y, long ld, long ng, int n, double w,
+                           double *part, int nsplit, double *G, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const int nt = (2 * n + TM - 1) / TM;
     const int npairs = nt * (nt + 1) / 2;
@@ -274,31 +304,35 @@ static hipError_t gram_common(bool bf16, const double *X, const double *Y, long 
     kchunk = (kchunk + 31) / 32 * 32;
     const int vec_ok = (ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
                        ((reinterpret_cast<uintptr_t>(Y) & 15) == 0);
-    const dim3 grid(npairs, nsplit);
-    if (bf16)
-        hipLaunchKernelGGL(k_gram_bf16, grid, dim3(64), 0, st, X, Y, ld, ng, n, kchunk, part,
-                           vec_ok);
-    else
-        hipLaunchKernelGGL(k_gram_f64, grid, dim3(64), 0, st, X, Y, ld, ng, n, kchunk, part,
-                           vec_ok);
+    hipLaunchKernelGGL(k_gram_f64, dim3(npairs, nsplit), dim3(64), 0, st, X, Y, ld, ng, n, kchunk,
+                       part, vec_ok);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const long total = 4L * n * n;
-    long blocks = (total + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)blocks), dim3(256), 0, st, part, 2 * n,
-                       nsplit, w, G);
-    return hipGetLastError();
-}
-
-hipError_t launch_gram_f64(const double *X, const double *Y, long ld, long ng, int n, double w,
-                           double *part, int nsplit, double *G, hipStream_t st) {
-    return gram_common(false, X, Y, ld, ng, n, w, part, nsplit, G, st);
+    return gram_reduce(part, 2 * n, nsplit, w, G, st);
 }
 
 hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, int n, double w,
-                            double *part, int nsplit, double *G, hipStream_t st) {
-    return gram_common(true, X, Y, ld, ng, n, w, part, nsplit, G, st);
+                            double *part, int nsplit, double *G, __bf16 *zb, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    // packed rows need 16-byte alignment: ld a multiple of 8, 16-byte aligned operands
+    if (ld % 8 != 0 || (reinterpret_cast<uintptr_t>(X) & 15) || (reinterpret_cast<uintptr_t>(Y) & 15) ||
+        (reinterpret_cast<uintptr_t>(zb) & 15))
+        return hipErrorInvalidValue;
+    const long items = 2L * n * (ld / 8);
+    long blocks = (items + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)blocks), dim3(256), 0, st, X, Y, ld, ng, n, zb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nt = (2 * n + TM - 1) / TM;
+    const int npairs = nt * (nt + 1) / 2;
+    long kchunk = (ng + nsplit - 1) / nsplit;
+    kchunk = (kchunk + 31) / 32 * 32;
+    hipLaunchKernelGGL(k_gram_bf16, dim3(npairs, nsplit), dim3(64), 0, st, zb, ld, ng, n, kchunk,
+                       part);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return gram_reduce(part, 2 * n, nsplit, w, G, st);
 }
 
 }  // namespace qo

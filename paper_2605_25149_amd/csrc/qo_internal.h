@@ -151,8 +151,11 @@ size_t gram_part_elems(int n, int nsplit);
 int gram_nsplit(long ng, int n);
 hipError_t launch_gram_f64(const double *X, const double *Y, long ld, long ng, int n,
                            double w, double *part, int nsplit, double *G, hipStream_t st);
+// BF16 tiles: [X Y] is first rounded to BF16 into zb (2n x ld, 16-byte aligned, ld a
+// multiple of 8; rows ng..ld-1 zero), then the tiles accumulate in FP32 per K-chunk.
 hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, int n,
-                            double w, double *part, int nsplit, double *G, hipStream_t st);
+                            double w, double *part, int nsplit, double *G, __bf16 *zb,
+                            hipStream_t st);
 
 // ---- tall-skinny update (qo_tsgemm.hip) ----
 // Out = C0 + A * Xs + B * Ys  (Ng x n, col-major), small operands given

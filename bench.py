@@ -374,7 +374,8 @@ def main():
         its = [st["pcg_iters"] for st in r["stats"]]
         out[f"{mode}_steps_per_s"] = round(args.steps / r["seconds"], 6)
         out[f"{mode}_pcg_iters_per_step"] = its
-        out[f"{mode}_kernels"] = {k: {"launches": v["launches"], "ms": round(v["ms"], 3)}
+        out[f"{mode}_kernels"] = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                                      "work": v["work"]}
                                   for k, v in r["profile"].items() if v["launches"]}
     if "fp64" in res and "mixed" in res:
         out["speedup_mixed_vs_fp64"] = round(res["fp64"]["seconds"] / res["mixed"]["seconds"], 4)

@@ -208,7 +208,7 @@ def roofline_of(prof, ng, value_bytes):
     mean_ms = d["ms"] / d["launches"]
     achieved = per_launch_bytes / (mean_ms * 1e-3) / 1e9
     sym = KERNEL_SYMBOL.get(best) or {
-        "dst_fwd": "k_dst_plane<%s, false>", "dst_inv": "k_dst_plane<%s, true>"}[best] % (
+        "dst_fwd": "k_dst_plane<%s,false>", "dst_inv": "k_dst_plane<%s,true>"}[best] % (
         "float" if value_bytes == 4 else "double")
     return {
         "kernel": sym,

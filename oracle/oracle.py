@@ -19,21 +19,21 @@ finite-difference grid): a grid function is a vector of interior values, the
 L2 inner product is the mass-weighted sum (u,v) = h^d * sum_i u_i v_i with
 h^d = prod(h_k), and the operator is H_sigma = -kappa*Lap_h + V + sigma.
 
-Readings of the paper taken here (each also listed in the design notes):
-  R1  G is applied to a block by per-column Jacobi-PCG (``solve``, Hestenes-Stiefel
-      or Chronopoulos-Gear form); a direct sparse factorisation (``solve_direct``) is
-      available for exact tests.
-  R2  In A_U V = G U <U,V> - U <U, G V> the second term is evaluated with the
+Readings of the paper taken here (numbered as in the design notes' table of readings):
+  R2  G is applied to a block by per-column PCG (``solve``: Jacobi preconditioner,
+      Hestenes-Stiefel or Chronopoulos-Gear form; ``solve_fast_poisson``: reading R13);
+      a direct sparse factorisation (``solve_direct``) is available for exact tests.
+  R3  In A_U V = G U <U,V> - U <U, G V> the second term is evaluated with the
       symmetry of G as U <G U, V> = U <P, V>, P the computed G U, so A_U is
       exactly skew for the computed P and no solve with G V is needed.
-  R3  The implicit predictor is solved exactly: since A_U maps into
+  R4  The implicit predictor is solved exactly: since A_U maps into
       span{U, P}, U_hat = U X + P Y and the scheme reduces to a linear system
       for the coefficient matrices (``predictor``).
-  R4  O_n in the corrector is the computed <U_hat, U_hat> - I (the literal
+  R5  O_n in the corrector is the computed <U_hat, U_hat> - I (the literal
       second line of the scheme).
-  R5  Warm starts: G U_n starts from the previous G U_hat; G U_hat starts from
+  R11 Warm starts: G U_n starts from the previous G U_hat; G U_hat starts from
       P (X + C Y) with C = <U,U>^{-1} <U,P> (exact when span U is invariant).
-  R6  The paper leaves the solver of G open and its concluding section asks for a
+  R13 The paper leaves the solver of G open and its concluding section asks for a
       better preconditioner than the diagonal one.  ``solve_fast_poisson`` runs PCG
       with M = kappa*(-Lap_h) + vbar, vbar = max(0, mean(V + sigma)): the operator
       with V replaced by a constant, inverted exactly by the orthonormal type-I
@@ -157,7 +157,7 @@ class Problem:
         return out
 
     def solve(self, B, X0=None, tol=1e-10, maxit=10000, variant=0):
-        """G B = H_sigma^{-1} B by per-column Jacobi-PCG (reading R1).
+        """G B = H_sigma^{-1} B by per-column Jacobi-PCG (reading R2).
 
         variant 0: Hestenes-Stiefel form; 1: Chronopoulos-Gear (one-reduction) form.
         Returns (X, iters, status, col_status)."""
@@ -175,7 +175,7 @@ class Problem:
                                      maxit, use_x0, _ip(iters), _ip(cst), int(variant))
         return X, iters, int(st), cst
 
-    # ---- fast-Poisson preconditioner (reading R6) ---------------------------
+    # ---- fast-Poisson preconditioner (reading R13) ---------------------------
     def laplace_eigs(self):
         """Per axis k: eigenvalues of the 1-D Dirichlet second difference -d^2/dx^2,
         mu_k[j] = (4 / h_k^2) sin^2(pi (j+1) / (2 (n_k + 1))), j = 0..n_k-1; the
@@ -211,7 +211,7 @@ class Problem:
         return Z
 
     def solve_fast_poisson(self, B, X0=None, tol=1e-10, maxit=1000):
-        """G B by per-column PCG with the fast-Poisson preconditioner (reading R6).
+        """G B by per-column PCG with the fast-Poisson preconditioner (reading R13).
 
         Hestenes-Stiefel form: r = b - H x0; until ||r|| <= tol ||b||: z = M^{-1} r,
         rho = r.z, p = z + (rho / rho_prev) p, q = H p, alpha = rho / p.q,
@@ -311,7 +311,7 @@ class Problem:
 def predictor(prob: Problem, U, P, tau):
     """First stage of the scheme: (U_hat - U)/tau = A_U U_tilde, U_tilde = (U_hat + U)/2.
 
-    A_U V = P <U,V> - U <P,V> (reading R2) maps into span{U, P}, so
+    A_U V = P <U,V> - U <P,V> (reading R3) maps into span{U, P}, so
     U_hat = U X + P Y.  With U_tilde = U (X+I)/2 + P Y/2 the stage reads
         Y = tau <U, U_tilde>,   X = I - tau <P, U_tilde>.
     Writing X = I + tau b, Y = tau a and alpha = tau/2 this is the linear system
@@ -335,7 +335,7 @@ def predictor(prob: Problem, U, P, tau):
 
 
 def corrector(prob: Problem, U_hat, Q, tau):
-    """Second stage: U_{n+1} = U_hat - tau G U_hat (<U_hat,U_hat> - I), Q = G U_hat (reading R4).
+    """Second stage: U_{n+1} = U_hat - tau G U_hat (<U_hat,U_hat> - I), Q = G U_hat (reading R5).
 
     Returns (U_next, O, A, B) with O = <U_hat,U_hat> - I, A = <U_hat, Q>, B = <Q, Q>
     (the auxiliary matrices of Sec. 4.1; O equals O_n when the first stage preserves

@@ -1,5 +1,5 @@
 """GPU parity of the fast-Poisson preconditioned solve (through the C ABI) against the
-oracle's exact FP64 version (reading R6 of the oracle) on the same seeded inputs.
+oracle's exact FP64 version (reading R13) on the same seeded inputs.
 
 The GPU applies M^{-1} with FP16 matrix-core transforms (FP32 accumulation), so the
 operator itself is compared at FP16 level: each FP16 rounding has relative error

@@ -416,7 +416,7 @@ def test_eigsum_gradient_finite_differences(oracle_mod):
 
 
 # ---------------------------------------------------------------------------
-# fast-Poisson preconditioner of the inverse-operator solve (reading R6)
+# fast-Poisson preconditioner of the inverse-operator solve (reading R13)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("dim,n,L,vshift", [(2, (9, 7), (1.0, 1.3), 3.0),

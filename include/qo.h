@@ -203,6 +203,35 @@ qo_status qo_gram_pair(qo_handle h, const double *X, const double *Y, long ld, i
 qo_status qo_get_block(qo_handle h, int which, double *out, long ld, int on_device);
 qo_status qo_get_matrix(qo_handle h, int which, double *out);
 
+/* ---- grouped batches of independent problems ----
+ * count instances, each with its own qo_config (grid, N, sigma, tolerance, potential and
+ * state), stepped together with the scheme of Sec. 4.1.  Instances whose grids agree (dim,
+ * n, L, kinetic, precond) form a group: the grid-sized kernels (stencil, PCG sweeps,
+ * preconditioner passes, energy) run once over all columns of a group, the Grams, block
+ * updates and N x N algebra once per group with one tile set or workgroup per instance.
+ * Restrictions: precision QO_FP64, pcg_variant 0, N <= 1024.  The PCG runs exactly
+ * pcg_maxit iterations per solve (the largest value in the group); columns freeze on
+ * convergence and a column still above its tolerance after them makes the step fail with
+ * QO_ERR_PCG_NOCONV.  The solve of G U_n always starts from the previous G U_hat (zero
+ * after qo_batch_set_state).  With use_graph != 0 each step is replayed from a HIP graph
+ * captured at its first use (one per parity of the P / Q buffers); the stream given to
+ * qo_batch_create must then not be the null stream (NULL creates a private stream).  At
+ * creation the band height of the stencil kernels is chosen per group by timing the
+ * candidates on the device (qo_batch_tile reports it).  A failed step leaves the states
+ * undefined (no undo).  Instances are numbered 0 .. count-1 in the order of cfgs. */
+typedef struct qo_batch_ctx *qo_batch;
+qo_status qo_batch_create(const qo_config *cfgs, int count, void *hip_stream, qo_batch *out);
+qo_status qo_batch_set_potential(qo_batch b, int i, const double *V, int on_device);
+qo_status qo_batch_set_state(qo_batch b, int i, const double *U, long ld, int on_device);
+qo_status qo_batch_get_state(qo_batch b, int i, double *U, long ld, int on_device);
+/* nsteps steps of every instance.  taus: count step sizes (NULL: the previous ones).
+ * stats (may be NULL): count entries, the last step's statistics per instance. */
+qo_status qo_batch_step(qo_batch b, const double *taus, int nsteps, int use_graph,
+                        qo_step_stats *stats);
+qo_status qo_batch_tile(qo_batch b, int i, int *ty);
+qo_status qo_batch_destroy(qo_batch b);
+const char *qo_batch_last_error(qo_batch b);
+
 /* ---- kernel timing (for roofline measurement) ----
  * When enabled, every launch of the kernels below is bracketed by HIP events
  * on the handle's stream; durations are harvested at the library's own

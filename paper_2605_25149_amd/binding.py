@@ -31,6 +31,8 @@ EXPORTS = [
     "qo_gram", "qo_eigenpairs", "qo_destroy", "qo_status_string", "qo_last_error", "qo_apply",
     "qo_solve", "qo_gram_pair", "qo_get_block", "qo_get_matrix", "qo_profile", "qo_profile_get",
     "qo_run", "qo_eigsum_gradient", "qo_precond",
+    "qo_batch_create", "qo_batch_set_potential", "qo_batch_set_state", "qo_batch_get_state",
+    "qo_batch_step", "qo_batch_tile", "qo_batch_destroy", "qo_batch_last_error",
 ]
 KERNELS = ["sweep1_f64", "sweep2_f64", "sweep1_f32", "sweep2_f32", "gram", "update", "resid",
            "cg_f64", "cg_f32", "dst_fwd", "dst_pencil", "dst_inv"]
@@ -116,6 +118,16 @@ def load_library(path: str = LIB_PATH):
                     dp, ip, ctypes.POINTER(QoStepStats)], ctypes.c_int),
         "qo_profile_get": ([H, ctypes.POINTER(QoProfileData)], ctypes.c_int),
         "qo_precond": ([H, vp, vp, ctypes.c_long, ctypes.c_int, vp], ctypes.c_int),
+        "qo_batch_create": ([ctypes.POINTER(QoConfig), ctypes.c_int, vp, ctypes.POINTER(H)],
+                            ctypes.c_int),
+        "qo_batch_set_potential": ([H, ctypes.c_int, vp, ctypes.c_int], ctypes.c_int),
+        "qo_batch_set_state": ([H, ctypes.c_int, vp, ctypes.c_long, ctypes.c_int], ctypes.c_int),
+        "qo_batch_get_state": ([H, ctypes.c_int, vp, ctypes.c_long, ctypes.c_int], ctypes.c_int),
+        "qo_batch_step": ([H, vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(QoStepStats)],
+                          ctypes.c_int),
+        "qo_batch_tile": ([H, ctypes.c_int, ip], ctypes.c_int),
+        "qo_batch_destroy": ([H], ctypes.c_int),
+        "qo_batch_last_error": ([H], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -159,6 +171,31 @@ def _check_block(t, ng, ncols=None):
     return t.stride(0) if t.shape[0] > 1 else ng
 
 
+def make_config(dim, n, N, L=(1.0, 1.0, 1.0), kinetic=0.5, sigma=0.0, pcg_tol=1e-10,
+                pcg_maxit=20000, pcg_check=8, precision="fp64", refine_inner_tol=1e-5,
+                warm_start=True, pcg_variant=0, precond="jacobi"):
+    """A qo_config from keyword arguments."""
+    cfg = QoConfig()
+    cfg.dim = dim
+    nn = list(n) + [1] * (3 - len(n))
+    LL = list(L) + [1.0] * (3 - len(L))
+    for k in range(3):
+        cfg.n[k] = int(nn[k])
+        cfg.L[k] = float(LL[k])
+    cfg.kinetic = kinetic
+    cfg.N = N
+    cfg.sigma = sigma
+    cfg.pcg_tol = pcg_tol
+    cfg.pcg_maxit = pcg_maxit
+    cfg.pcg_check = pcg_check
+    cfg.precision = {"fp64": QO_FP64, "mixed": QO_MIXED}[precision]
+    cfg.refine_inner_tol = refine_inner_tol
+    cfg.warm_start = 1 if warm_start else 0
+    cfg.pcg_variant = int(pcg_variant)
+    cfg.precond = PRECONDS[precond] if isinstance(precond, str) else int(precond)
+    return cfg
+
+
 class Solver:
     """One handle of the HIP library: grid, potential, iterate and workspace."""
 
@@ -168,24 +205,9 @@ class Solver:
         import torch
 
         self.lib = load_library()
-        cfg = QoConfig()
-        cfg.dim = dim
         nn = list(n) + [1] * (3 - len(n))
-        LL = list(L) + [1.0] * (3 - len(L))
-        for k in range(3):
-            cfg.n[k] = int(nn[k])
-            cfg.L[k] = float(LL[k])
-        cfg.kinetic = kinetic
-        cfg.N = N
-        cfg.sigma = sigma
-        cfg.pcg_tol = pcg_tol
-        cfg.pcg_maxit = pcg_maxit
-        cfg.pcg_check = pcg_check
-        cfg.precision = {"fp64": QO_FP64, "mixed": QO_MIXED}[precision]
-        cfg.refine_inner_tol = refine_inner_tol
-        cfg.warm_start = 1 if warm_start else 0
-        cfg.pcg_variant = int(pcg_variant)
-        cfg.precond = PRECONDS[precond] if isinstance(precond, str) else int(precond)
+        cfg = make_config(dim, n, N, L, kinetic, sigma, pcg_tol, pcg_maxit, pcg_check,
+                          precision, refine_inner_tol, warm_start, pcg_variant, precond)
         self.cfg = cfg
         self.dim, self.N = dim, N
         self.ng = int(np.prod(nn[:dim]))
@@ -380,3 +402,81 @@ class Solver:
         M = np.zeros((self.N, self.N), order="F")
         self._chk(self.lib.qo_get_matrix(self.h, MATRICES[name], M.ctypes.data_as(ctypes.c_void_p)))
         return M
+
+
+class Batch:
+    """Grouped batch of independent problems stepped together (qo_batch_* of the C ABI).
+
+    ``configs``: a list of keyword dicts for ``make_config`` (one per instance)."""
+
+    def __init__(self, configs, stream=None):
+        self.lib = load_library()
+        self.count = len(configs)
+        arr = (QoConfig * self.count)()
+        self.ng, self.N = [], []
+        for i, kw in enumerate(configs):
+            arr[i] = make_config(**kw)
+            n = list(kw["n"])
+            self.ng.append(int(np.prod(n[:kw["dim"]])))
+            self.N.append(int(kw["N"]))
+        self.cfgs = arr
+        self.h = ctypes.c_void_p()
+        sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else ctypes.c_void_p()
+        st = self.lib.qo_batch_create(arr, self.count, sp, ctypes.byref(self.h))
+        if st != QO_OK:
+            raise QOError(st, "qo_batch_create failed")
+
+    def _chk(self, st):
+        if st != QO_OK:
+            msg = self.lib.qo_batch_last_error(self.h)
+            raise QOError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if self.h:
+            self.lib.qo_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_potential(self, i, V):
+        V = np.ascontiguousarray(np.asarray(V, dtype=np.float64).reshape(-1))
+        if V.size != self.ng[i]:
+            raise ValueError("potential size does not match the grid")
+        self._chk(self.lib.qo_batch_set_potential(self.h, i, V.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def set_state(self, i, U):
+        U = np.asfortranarray(np.asarray(U, dtype=np.float64))
+        if U.shape != (self.ng[i], self.N[i]):
+            raise ValueError("state must be Ng x N")
+        self._chk(self.lib.qo_batch_set_state(self.h, i, U.ctypes.data_as(ctypes.c_void_p),
+                                              self.ng[i], 0))
+
+    def get_state(self, i):
+        U = np.zeros((self.ng[i], self.N[i]), order="F")
+        self._chk(self.lib.qo_batch_get_state(self.h, i, U.ctypes.data_as(ctypes.c_void_p),
+                                              self.ng[i], 0))
+        return U
+
+    def step(self, taus=None, nsteps=1, use_graph=True, stats=True):
+        t = None
+        if taus is not None:
+            t = np.ascontiguousarray(np.asarray(taus, dtype=np.float64).reshape(self.count))
+        out = (QoStepStats * self.count)() if stats else None
+        self._chk(self.lib.qo_batch_step(self.h, None if t is None else t.ctypes.data_as(
+            ctypes.c_void_p), int(nsteps), 1 if use_graph else 0, out))
+        return [o.as_dict() for o in out] if stats else None
+
+    def tile(self, i):
+        ty = ctypes.c_int()
+        self._chk(self.lib.qo_batch_tile(self.h, i, ctypes.byref(ty)))
+        return ty.value

@@ -159,14 +159,6 @@ qo_status dalloc(qo_ctx *c, T **p, size_t n) {
     return QO_OK;
 }
 
-int pick_ppt(int pts) {
-    const int raw = (pts + kThreads - 1) / kThreads;
-    const int opts[5] = {1, 2, 4, 6, 8};
-    for (int o : opts)
-        if (o >= raw) return o;
-    return -1;
-}
-
 int env_int(const char *name, int dflt) {
     const char *v = getenv(name);
     if (!v || !*v) return dflt;

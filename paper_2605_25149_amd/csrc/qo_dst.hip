@@ -301,7 +301,7 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
     } else {
         const int FP = NXP + 4;
         float *SF = reinterpret_cast<float *>(smem);  // RP x FP floats
-        const float unscale = 1.f / (sc * p.lmin);
+        const float unscale = 1.f / (sc * (p.clmin ? p.clmin[col] : p.lmin));
 #pragma unroll
         for (int j = 0; j < NT; ++j)
 #pragma unroll
@@ -364,6 +364,8 @@ __global__ __launch_bounds__(1024) void k_dst_pencil(DstPlan p, const _Float16 *
     const int col = L / p.npen;
     const int pen = L - col * p.npen;
     if (pcs[col] == 0.f) return;
+    const float vbar = p.cvbar ? p.cvbar[col] : p.vbar;
+    const float lmin = p.clmin ? p.clmin[col] : p.lmin;
     const int NSP = p.NSP, SP = NSP + 8;
     const int ns = p.ns, nf = p.nf;
     const int m0 = pen * MB;
@@ -427,7 +429,7 @@ __global__ __launch_bounds__(1024) void k_dst_pencil(DstPlan p, const _Float16 *
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             float f = 0.f;
-            if (muf >= 0.f && mus[v] >= 0.f) f = p.lmin / (p.kap * (muf + mus[v]) + p.vbar);
+            if (muf >= 0.f && mus[v] >= 0.f) f = lmin / (p.kap * (muf + mus[v]) + vbar);
             h[v] = (_Float16)(acc[j][v] * f);
         }
         *reinterpret_cast<v4h *>(YT + (16 * j + lr) * SP + 16 * w + 4 * lg) = h;

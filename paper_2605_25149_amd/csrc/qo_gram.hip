@@ -64,18 +64,15 @@ __device__ __forceinline__ void tile_pair(int p, int nt, int &ti, int &tj) {
     tj = i + rem;
 }
 
-__global__ __launch_bounds__(64) void k_gram_f64(const double *__restrict__ X,
-                                                 const double *__restrict__ Y, long ld, long ng,
-                                                 int n, long kchunk, double *__restrict__ part,
-                                                 int vec_ok) {
+// One 64 x 64 tile pair of one K-chunk, FP64 MFMA (one wavefront).
+__device__ __forceinline__ void gram_f64_tile(const double *__restrict__ X,
+                                              const double *__restrict__ Y, long ld, long ng,
+                                              int n, long kchunk, double *__restrict__ part,
+                                              int vec_ok, int pair, int split) {
     const int nn = 2 * n;
     const int nt = (nn + TM - 1) / TM;
-    // pairs of one K-chunk on one XCD: they read the same rows of the 2n columns
-    const int npairs = nt * (nt + 1) / 2;
-    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    const int split = L / npairs;
     int ti, tj;
-    tile_pair(L - split * npairs, nt, ti, tj);
+    tile_pair(pair, nt, ti, tj);
     const long kb = (long)split * kchunk;
     const long ke = min(ng, kb + kchunk);
     const int lane = threadIdx.x;
@@ -144,6 +141,30 @@ __global__ __launch_bounds__(64) void k_gram_f64(const double *__restrict__ X,
                 const int c = tj * TM + 16 * j + lr;
                 if (r < nn && c < nn) out[(long)c * nn + r] = acc[i][j][v];
             }
+}
+
+__global__ __launch_bounds__(64) void k_gram_f64(const double *__restrict__ X,
+                                                 const double *__restrict__ Y, long ld, long ng,
+                                                 int n, long kchunk, double *__restrict__ part,
+                                                 int vec_ok) {
+    // pairs of one K-chunk on one XCD: they read the same rows of the 2n columns
+    const int nt = (2 * n + TM - 1) / TM;
+    const int npairs = nt * (nt + 1) / 2;
+    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int split = L / npairs;
+    gram_f64_tile(X, Y, ld, ng, n, kchunk, part, vec_ok, L - split * npairs, split);
+}
+
+// Grouped batches: job blockIdx.z, (pair, split) from blockIdx.x.
+__global__ __launch_bounds__(64) void k_gram_f64_batch(const GramJob *__restrict__ jobs, long ld,
+                                                       long ng, int vec_ok) {
+    const GramJob J = jobs[blockIdx.z];
+    const int nt = (2 * J.n + TM - 1) / TM;
+    const int npairs = nt * (nt + 1) / 2;
+    if ((int)blockIdx.x >= npairs * J.nsplit) return;
+    const int split = blockIdx.x / npairs;
+    gram_f64_tile(J.X, J.Y, ld, ng, J.n, J.kchunk, J.part, vec_ok, blockIdx.x - split * npairs,
+                  split);
 }
 
 // Z = [X | Y] rounded to BF16 once: Zb[c * ld + r] for r < ld (rows ng..ld-1 zero), so
@@ -267,7 +288,44 @@ __global__ void k_gram_reduce(const double *__restrict__ part, int nn, int nspli
     }
 }
 
+__global__ void k_gram_reduce_batch(const GramJob *__restrict__ jobs, double w) {
+    const GramJob J = jobs[blockIdx.z];
+    const int nn = 2 * J.n;
+    const long total = (long)nn * nn;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int r = (int)(e % nn), c = (int)(e / nn);
+        const int a = min(r, c), b = max(r, c);
+        const long o = (long)b * nn + a;
+        double s = 0.0;
+        for (int k = 0; k < J.nsplit; ++k) s += J.part[(long)k * total + o];
+        J.G[e] = w * s;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_gram_f64_batch(const GramJob *jobs, int njobs, int max_grid, long ld, long ng,
+                                 double w, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gram_f64_batch, dim3((unsigned)max_grid, 1, (unsigned)njobs), dim3(64), 0,
+                       st, jobs, ld, ng, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gram_reduce_batch, dim3(64, 1, (unsigned)njobs), dim3(256), 0, st, jobs,
+                       w);
+    return hipGetLastError();
+}
+
+int gram_pairs(int n) {
+    const int nt = (2 * n + TM - 1) / TM;
+    return nt * (nt + 1) / 2;
+}
+
+long gram_kchunk(long ng, int nsplit) {
+    long kchunk = (ng + nsplit - 1) / nsplit;
+    return (kchunk + 31) / 32 * 32;
+}
 
 int gram_nsplit(long ng, int n) {
     const int nt = (2 * n + TM - 1) / TM;

@@ -18,6 +18,10 @@ struct Grid {
     double ihx2, ihy2, ihz2;  // 1/h_k^2 (ihz2 = 0 in 2-D)
     double kappa;
     double c0;           // 2 kappa (ihx2 + ihy2 + ihz2): stencil diagonal without V
+    // Grouped batches concatenate the columns of several instances on one grid:
+    // cinst[col] is a column's instance, whose per-point arrays (V + sigma,
+    // 1/diag) start at instance * ng.  nullptr for a single instance.
+    const int *cinst;
     __host__ __device__ int tiles() const { return nbands * nzc; }
 };
 
@@ -58,6 +62,7 @@ struct DstPlan {
     const _Float16 *Sx, *Sy, *Ss;   // DST-I matrices, FP16, row-major, padded with zeros
     const float *mux, *muy, *mus;   // eigenvalues of the 1-D -Lap_h along x, y, slowest axis
     float kap, vbar, lmin;          // lambda = kap (mu_x + mu_y + mu_z) + vbar; lmin its minimum
+    const float *cvbar, *clmin;     // per-column vbar, lmin (grouped batches), else nullptr
 };
 
 // null if the grid is supported, else the reason
@@ -157,10 +162,59 @@ hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, 
                             double w, double *part, int nsplit, double *G, __bf16 *zb,
                             hipStream_t st);
 
+// Grouped batches: one Gram per job (instance), FP64 MFMA; part holds nsplit x (2n)^2
+// doubles of the job; max_grid >= gram_pairs(n) * nsplit over the jobs.
+struct GramJob {
+    const double *X, *Y;
+    double *part, *G;
+    int n, nsplit;
+    long kchunk;
+};
+int gram_pairs(int n);
+long gram_kchunk(long ng, int nsplit);
+hipError_t launch_gram_f64_batch(const GramJob *jobs, int njobs, int max_grid, long ld, long ng,
+                                 double w, hipStream_t st);
+
+// ---- grouped batches: N x N algebra per instance (qo_batch.hip) ----
+struct NnJob {
+    const double *G1, *G2;  // Grams of [U P] and [U_hat Q], 2n x 2n, leading dimension 2n
+    double *pool;           // nn_pool_elems(n) doubles of coefficient matrices
+    double *scal;           // [0] squared gradient norm, [1] ||O||_F, [2] ||O_{n+1}||_F
+    int *status;            // 0, or the qo_status code of a failed N x N solve
+    int n;
+    double tau;
+};
+size_t nn_pool_elems(int n);
+int nn_slot_xr();
+int nn_slot_yr();
+int nn_slot_zr();
+int nn_slot_or();
+hipError_t launch_nn_predict(const NnJob *jobs, int njobs, int max_n, hipStream_t st);
+hipError_t launch_nn_correct(const NnJob *jobs, int njobs, hipStream_t st);
+hipError_t launch_instance_energy(const double *part, long qs, int tiles, const int *coff,
+                                  int ninst, double w, double *out, hipStream_t st);
+// vs = V + sigma, dinv = 1/(c0 + vs); status = 7 (non-finite) or 5 (diagonal <= 0)
+hipError_t launch_batch_potential(const double *V, long ng, double sigma, double c0, double *vs,
+                                  double *dinv, int *status, hipStream_t st);
+// its[c] = 0 for c < n
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st);
+// err: code 6 (PCG limit) for the first column still active
+hipError_t launch_noconv_check(const int *active, int n, int *err, hipStream_t st);
+
+int pick_ppt(int pts);
+
 // ---- tall-skinny update (qo_tsgemm.hip) ----
 // Out = C0 + A * Xs + B * Ys  (Ng x n, col-major), small operands given
 // transposed: XsT[i*n + k] = Xs[k][i] (i.e. Xs stored row-major).  Any of C0,
 // A, B may be null.  Out may alias C0 only.
+// Grouped batches: Out = C0 + A Xs + B Ys per job (shared ld, ng; job column count n).
+struct TsJob {
+    double *Out;
+    const double *C0, *A, *Xr, *B, *Yr;
+    int n;
+};
+hipError_t launch_tsgemm_batch(const TsJob *jobs, int njobs, int max_n, long ld, long ng,
+                               hipStream_t st);
 hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
                          const double *XsT, const double *B, const double *YsT, long ld,
                          long ng, int n, hipStream_t st);

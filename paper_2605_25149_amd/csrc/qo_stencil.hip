@@ -221,6 +221,12 @@ __device__ __forceinline__ void tile_of(const Grid &g, int &col, int &tile, int 
     zc = tile - band * g.nzc;
 }
 
+// Per-point array of a column's instance (see Grid::cinst).
+template <typename T>
+__device__ __forceinline__ const T *col_pt(const Grid &g, const T *p, int col) {
+    return (g.cinst && p) ? p + (long)g.cinst[col] * g.ng : p;
+}
+
 template <typename T>
 __device__ __forceinline__ T *lds_ptr() {
     extern __shared__ __align__(16) unsigned char qo_smem[];
@@ -235,6 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(Grid g, const double *__rest
                                                     double *__restrict__ Y, long ld) {
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
+    vs = col_pt(g, vs, col);
     struct Ep {
         using Raw = NoRaw;
         double *__restrict__ y;
@@ -253,6 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_quad(Grid g, const double *__restr
     __shared__ Red red;
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
+    vs = col_pt(g, vs, col);
     struct Ep {
         using Raw = NoRaw;
         double acc[2];
@@ -283,6 +291,7 @@ __global__ __launch_bounds__(kThreads) void k_resid(Grid g, const double *__rest
     __shared__ Red red;
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
+    vs = col_pt(g, vs, col);
     const long o = (long)col * g.tiles() + tile;
     if (mask && !mask[col]) {
         if (threadIdx.x == 0) part[qs + o] = part[2 * qs + o] = 0.0;
@@ -327,6 +336,8 @@ __global__ __launch_bounds__(kThreads) void k_resid_rel(Grid g, const double *__
     __shared__ Red red;
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
+    vs = col_pt(g, vs, col);
+    dinv32 = col_pt(g, dinv32, col);
     if (!mask[col]) return;
     struct Ep {
         struct Raw { double b; float d; };
@@ -397,6 +408,8 @@ __global__ __launch_bounds__(kThreads) void k_pcg_init(Grid g, const T *__restri
     __shared__ Red red;
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
+    vs = col_pt(g, vs, col);
+    dinv = col_pt(g, dinv, col);
     EpInit<T> ep{B + (long)col * ld, dinv, X + (long)col * ld, R + (long)col * ld,
                  use_x0 != 0, {0.0, 0.0, 0.0}};
     if (use_x0) {
@@ -446,6 +459,8 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__rest
     __shared__ int sh_flag;
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
+    vs = col_pt(g, vs, col);
+    dinv = col_pt(g, dinv, col);
     const bool lead = tile == 0;
     const int cur = k & 1, prv = cur ^ 1;
     const int tiles = g.tiles();
@@ -543,6 +558,8 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep2(Grid g, const T *__rest
     __shared__ int sh_flag;
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
+    vs = col_pt(g, vs, col);
+    dinv = col_pt(g, dinv, col);
     const int cur = k & 1;
     const int tiles = g.tiles();
     if (!s.active[cur * ncols + col]) return;
@@ -580,6 +597,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_delta0(Grid g, const T *__restr
     __shared__ Red red;
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
+    vs = col_pt(g, vs, col);
+    dinv = col_pt(g, dinv, col);
     LdPcgP<T> l{dinv, R + (long)col * ld, nullptr, T(0), true};
     struct Ep {
         using Raw = NoRaw;
@@ -709,6 +728,15 @@ inline size_t lds_bytes(const Grid &g, size_t elem) { return 2 * (size_t)(g.TY +
     }
 
 }  // namespace
+
+// Points per thread per plane of a band of `pts` points (the instantiated set), -1 if none.
+int pick_ppt(int pts) {
+    const int raw = (pts + kThreads - 1) / kThreads;
+    const int opts[5] = {1, 2, 4, 6, 8};
+    for (int o : opts)
+        if (o >= raw) return o;
+    return -1;
+}
 
 hipError_t launch_apply(const Grid &g, const double *vs, const double *X, double *Y, long ld,
                         int ncols, hipStream_t st) {

@@ -18,20 +18,16 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(64) void k_tsgemm(double *__restrict__ Out, long ldo,
-                                               const double *__restrict__ C0,
-                                               const double *__restrict__ A,
-                                               const double *__restrict__ Xr,
-                                               const double *__restrict__ B,
-                                               const double *__restrict__ Yr, long ld, long ng,
-                                               int n) {
+// One 64 (grid rows from m0) x 64 (columns from c0) tile of Out, one wavefront.
+__device__ __forceinline__ void tsgemm_tile(double *__restrict__ Out, long ldo,
+                                            const double *__restrict__ C0,
+                                            const double *__restrict__ A,
+                                            const double *__restrict__ Xr,
+                                            const double *__restrict__ B,
+                                            const double *__restrict__ Yr, long ld, long ng,
+                                            int n, long m0, int c0) {
     const int lane = threadIdx.x;
     const int lr = lane & 15, lg = lane >> 4;
-    // column tiles of one row panel on one XCD: they read the same rows of A and B
-    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    const int rt = L / gridDim.y;
-    const long m0 = (long)rt * 64;
-    const int c0 = (L - rt * gridDim.y) * 64;
 
     v4d acc[4][4];  // [column block j][row block i]
 #pragma unroll
@@ -110,7 +106,37 @@ __global__ __launch_bounds__(64) void k_tsgemm(double *__restrict__ Out, long ld
         }
 }
 
+__global__ __launch_bounds__(64) void k_tsgemm(double *__restrict__ Out, long ldo,
+                                               const double *__restrict__ C0,
+                                               const double *__restrict__ A,
+                                               const double *__restrict__ Xr,
+                                               const double *__restrict__ B,
+                                               const double *__restrict__ Yr, long ld, long ng,
+                                               int n) {
+    // column tiles of one row panel on one XCD: they read the same rows of A and B
+    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int rt = L / gridDim.y;
+    tsgemm_tile(Out, ldo, C0, A, Xr, B, Yr, ld, ng, n, (long)rt * 64, (L - rt * gridDim.y) * 64);
+}
+
+// Grouped batches: job blockIdx.z; row tile blockIdx.x, column tile blockIdx.y.
+__global__ __launch_bounds__(64) void k_tsgemm_batch(const TsJob *__restrict__ jobs, long ld,
+                                                     long ng) {
+    const TsJob J = jobs[blockIdx.z];
+    const int c0 = blockIdx.y * 64;
+    if (c0 >= J.n) return;
+    tsgemm_tile(J.Out, ld, J.C0, J.A, J.Xr, J.B, J.Yr, ld, ng, J.n, (long)blockIdx.x * 64, c0);
+}
+
 }  // namespace
+
+hipError_t launch_tsgemm_batch(const TsJob *jobs, int njobs, int max_n, long ld, long ng,
+                               hipStream_t st) {
+    if (njobs <= 0 || ng <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((ng + 63) / 64), (unsigned)((max_n + 63) / 64), (unsigned)njobs);
+    hipLaunchKernelGGL(k_tsgemm_batch, grid, dim3(64), 0, st, jobs, ld, ng);
+    return hipGetLastError();
+}
 
 hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
                          const double *Xr, const double *B, const double *Yr, long ld, long ng,

@@ -14,6 +14,10 @@ external eigensolvers; these synthetic families stand in for them):
         drawn in that order from numpy default_rng(seed)
   * random_block(ng, N, seed):          i.i.d. N(0,1) entries, column after column,
         from numpy default_rng(seed) (not orthonormal)
+  * batch_instances(count, seed):       the independent 2-D problems of a batch: side
+        ~ {64, 96, 128, 192, 256}, N ~ U{8..64}, V = harmonic (omega2 ~ U[50,150],
+        centre ~ U[0.3,0.7]^2) minus 4 Gaussian wells (depths U[2,8], widths
+        U[0.05,0.15], centres U[0.1,0.9]^2), drawn in that order per instance
 """
 from __future__ import annotations
 
@@ -61,3 +65,34 @@ def random_block(ng, N, seed=1):
     """(ng, N) column-major block with i.i.d. standard normal entries."""
     rng = np.random.default_rng(seed)
     return np.asfortranarray(rng.standard_normal((N, ng)).T)
+
+
+def harmonic_wells(n, omega2, centre, depths, widths, centres, L=(1.0, 1.0)):
+    """1/2 omega2 |x - c|^2 - sum_k d_k exp(-|x - c_k|^2 / (2 w_k^2))."""
+    dim = len(n)
+    xs = grid_coords(n, L)
+    V = 0.5 * omega2 * sum((xs[a] - centre[a]) ** 2 for a in range(dim))
+    for k in range(len(depths)):
+        r2 = sum((xs[a] - centres[k][a]) ** 2 for a in range(dim))
+        V = V - depths[k] * np.exp(-r2 / (2.0 * widths[k] ** 2))
+    return V
+
+
+def batch_instances(count, seed=0, sides=(64, 96, 128, 192, 256), nrange=(8, 64)):
+    """Descriptions of `count` independent 2-D problems: dicts with n, N, V and sigma.
+
+    sigma = max(0, 1 - min V) makes V + sigma >= 1, so H_sigma is positive definite."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        side = int(rng.choice(sides))
+        N = int(rng.integers(nrange[0], nrange[1] + 1))
+        omega2 = rng.uniform(50.0, 150.0)
+        centre = rng.uniform(0.3, 0.7, 2)
+        depths = rng.uniform(2.0, 8.0, 4)
+        widths = rng.uniform(0.05, 0.15, 4)
+        centres = rng.uniform(0.1, 0.9, (4, 2))
+        n = (side, side)
+        V = harmonic_wells(n, omega2, centre, depths, widths, centres)
+        out.append({"n": n, "N": N, "V": V, "sigma": max(0.0, 1.0 - float(V.min()))})
+    return out

@@ -1,0 +1,167 @@
+"""GPU parity of grouped batches (qo_batch_* of the C ABI): a batch of independent
+problems with uneven grids and N against the same problems stepped one by one through
+single-instance handles and against the oracle, graph replays against eager execution,
+and the error paths."""
+import numpy as np
+import pytest
+
+from paper_2605_25149_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2605_25149_amd import binding
+
+    binding.load_library()
+    return binding
+
+
+def _tau(n, V, sigma, kappa=0.5):
+    # 0.9 x a lower bound of lambda_1(H_sigma): min(V + sigma) + kappa (mu_x[0] + mu_y[0])
+    mu = sum(4.0 * (m + 1) ** 2 * np.sin(np.pi / (2.0 * (m + 1))) ** 2 for m in n)
+    return 0.9 * (float(np.min(V)) + sigma + kappa * mu)
+
+
+def _problems():
+    """Two grid groups, uneven N, ragged sizes (not multiples of 32)."""
+    probs = []
+    spec = [((32, 32), 4, 1), ((32, 32), 6, 2), ((48, 40), 5, 3), ((32, 32), 3, 4),
+            ((48, 40), 2, 5)]
+    for n, N, seed in spec:
+        rng = np.random.default_rng(100 + seed)
+        V = inputs.harmonic_wells(n, rng.uniform(50, 150), rng.uniform(0.3, 0.7, 2),
+                                  rng.uniform(2, 8, 4), rng.uniform(0.05, 0.15, 4),
+                                  rng.uniform(0.1, 0.9, (4, 2)))
+        sigma = max(0.0, 1.0 - float(V.min()))
+        U0 = inputs.random_block(n[0] * n[1], N, seed=seed)
+        probs.append(dict(n=n, N=N, V=V, sigma=sigma, U0=U0, tau=_tau(n, V, sigma)))
+    return probs
+
+
+def _batch(B, probs, precond="fast_poisson", tol=1e-12, maxit=40):
+    cfgs = [dict(dim=2, n=p["n"], N=p["N"], sigma=p["sigma"], pcg_tol=tol, pcg_maxit=maxit,
+                 precond=precond) for p in probs]
+    b = B.Batch(cfgs)
+    for i, p in enumerate(probs):
+        b.set_potential(i, p["V"])
+        b.set_state(i, p["U0"])
+    return b
+
+
+@pytest.mark.parametrize("precond,maxit", [("fast_poisson", 40), ("jacobi", 400)])
+def test_batch_matches_single_instances(torch, B, precond, maxit):
+    """12 steps of a 5-instance batch (two grids, N = 2..6) against the same problems stepped
+    by single-instance handles: energies within 1e-10 relative every step, states within
+    1e-9 at the end (the two differ only in summation order: band heights and launch
+    grouping)."""
+    probs = _problems()
+    K = 12
+    b = _batch(B, probs, precond, maxit=maxit)
+    ref = []
+    for p in probs:
+        s = B.Solver(2, p["n"], p["N"], sigma=p["sigma"], pcg_tol=1e-12, pcg_check=1,
+                     precond=precond)
+        s.set_potential(p["V"])
+        s.set_state(B.as_block(p["U0"]))
+        ref.append(s)
+    try:
+        taus = [p["tau"] for p in probs]
+        for k in range(K):
+            st = b.step(taus, use_graph=True)
+            for i, p in enumerate(probs):
+                r = ref[i].step(p["tau"])
+                assert abs(st[i]["energy"] - r["energy"]) <= 1e-10 * abs(r["energy"]), (k, i)
+                assert abs(st[i]["orth_err_fro"] - r["orth_err_fro"]) <= 1e-9 * max(
+                    1.0, r["orth_err_fro"]), (k, i)
+        for i in range(len(probs)):
+            U = b.get_state(i)
+            Ur = B.to_numpy(ref[i].get_state())
+            assert np.max(np.abs(U - Ur)) <= 1e-9 * np.max(np.abs(Ur)), i
+    finally:
+        b.close()
+        for s in ref:
+            s.close()
+
+
+def test_batch_graph_replay_equals_eager(torch, B):
+    """Steps replayed from the captured graphs (each parity replayed three times, with host
+    reads between replays) give bit-identical states and statistics to the same steps run
+    eagerly."""
+    probs = _problems()
+    taus = [p["tau"] for p in probs]
+    out = {}
+    for mode in (False, True):
+        b = _batch(B, probs)
+        try:
+            stats = [b.step(taus, use_graph=mode) for _ in range(6)]
+            out[mode] = (stats, [b.get_state(i) for i in range(len(probs))])
+        finally:
+            b.close()
+    (s0, u0), (s1, u1) = out[False], out[True]
+    for a, c in zip(s0, s1):
+        for i in range(len(probs)):
+            assert a[i]["energy"] == c[i]["energy"] and a[i]["grad_norm"] == c[i]["grad_norm"]
+            assert a[i]["pcg_iters"] == c[i]["pcg_iters"]
+    for a, c in zip(u0, u1):
+        assert np.array_equal(a, c)
+
+
+def test_batch_matches_oracle(torch, B, oracle_mod):
+    """One batch instance against the oracle's fast-Poisson step, 8 steps: energies within
+    1e-10 relative, final state within 1e-8."""
+    probs = _problems()
+    p = probs[2]
+    ref = oracle_mod.Oracle(oracle_mod.Problem(2, p["n"], p["V"], sigma=p["sigma"]), p["U0"],
+                            tol=1e-12, precond="fast_poisson")
+    b = _batch(B, probs)
+    try:
+        taus = [q["tau"] for q in probs]
+        for _ in range(8):
+            st = b.step(taus)
+            a = ref.step(p["tau"])
+            assert abs(st[2]["energy"] - a.energy) <= 1e-10 * abs(a.energy)
+        U = b.get_state(2)
+        assert np.max(np.abs(U - ref.U)) <= 1e-8 * np.max(np.abs(ref.U))
+    finally:
+        b.close()
+
+
+def test_batch_tiles_and_errors(torch, B):
+    """The tuned band height is a valid one per group; a solve cut short fails with
+    QO_ERR_PCG_NOCONV; stepping before the state is set fails with QO_ERR_STATE; mixed
+    precision is refused."""
+    probs = _problems()
+    b = _batch(B, probs)
+    try:
+        for i, p in enumerate(probs):
+            ty = b.tile(i)
+            assert 1 <= ty <= p["n"][1]
+    finally:
+        b.close()
+    b = _batch(B, probs, tol=1e-14, maxit=1)
+    try:
+        with pytest.raises(B.QOError, match="QO_ERR_PCG_NOCONV"):
+            b.step([p["tau"] for p in probs])
+    finally:
+        b.close()
+    cfgs = [dict(dim=2, n=(16, 16), N=2, precond="fast_poisson", pcg_maxit=30)]
+    b = B.Batch(cfgs)
+    try:
+        b.set_potential(0, np.zeros(256))
+        with pytest.raises(B.QOError, match="QO_ERR_STATE"):
+            b.step([1.0])
+    finally:
+        b.close()
+    with pytest.raises(B.QOError):
+        B.Batch([dict(dim=2, n=(16, 16), N=2, precision="mixed")])

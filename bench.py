@@ -276,6 +276,73 @@ def cpu_baseline(V, U0, n, N, tau, colits_per_step, log, precond="fast_poisson")
     }
 
 
+def batch_tau(p, kappa=0.5):
+    """0.9 x a lower bound of lambda_1(H_sigma) of a 2-D instance: min(V + sigma) plus kappa
+    times the smallest eigenvalue of -Lap_h."""
+    mu = sum(4.0 * (m + 1) ** 2 * np.sin(np.pi / (2.0 * (m + 1))) ** 2 for m in p["n"])
+    return 0.9 * (float(np.min(p["V"])) + p["sigma"] + kappa * mu)
+
+
+def run_batch(count, steps, log):
+    """Aggregate throughput of `count` independent 2-D problems (sides 64..256, N 8..64)
+    stepped as one grouped batch (eager launches and graph replay) against the same
+    problems stepped one single-instance handle at a time."""
+    import torch
+
+    from paper_2605_25149_amd import binding, inputs
+
+    probs = inputs.batch_instances(count, 0)
+    taus = [batch_tau(p) for p in probs]
+    cfgs = [dict(dim=2, n=p["n"], N=p["N"], sigma=p["sigma"], pcg_tol=1e-10, pcg_maxit=30,
+                 precond="fast_poisson") for p in probs]
+    out = {"instances": count, "columns": sum(p["N"] for p in probs),
+           "sides": sorted(set(p["n"][0] for p in probs)), "precision": "f64",
+           "precond": "fast_poisson", "steps": steps}
+    b = binding.Batch(cfgs)
+    try:
+        for i, p in enumerate(probs):
+            b.set_potential(i, p["V"])
+            b.set_state(i, inputs.random_block(p["n"][0] * p["n"][1], p["N"], seed=1000 + i))
+        out["tiles"] = {str(p["n"][0]): b.tile(i) for i, p in enumerate(probs)}
+        for mode in ("eager", "graph"):
+            b.step(taus, use_graph=mode == "graph")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = b.step(taus, nsteps=steps, use_graph=mode == "graph")
+            dt = time.perf_counter() - t0
+            out[f"{mode}_instance_steps_per_s"] = round(count * steps / dt, 2)
+            out["max_pcg_iters"] = max(max(x["pcg_iters"]) for x in st)
+            log(f"[batch {mode}] {count} instances, {steps} steps: {dt / steps * 1e3:.1f} ms/step")
+    finally:
+        b.close()
+    sol = []
+    try:
+        for i, p in enumerate(probs):
+            s = binding.Solver(2, p["n"], p["N"], sigma=p["sigma"], pcg_tol=1e-10, pcg_check=1,
+                               precond="fast_poisson")
+            s.set_potential(p["V"])
+            s.set_state(binding.as_block(inputs.random_block(p["n"][0] * p["n"][1], p["N"],
+                                                             seed=1000 + i)))
+            sol.append(s)
+        for i, s in enumerate(sol):
+            s.step(taus[i])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for i, s in enumerate(sol):
+                s.step(taus[i])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["sequential_instance_steps_per_s"] = round(count * steps / dt, 2)
+        log(f"[batch sequential] {count} single-instance handles: {dt / steps * 1e3:.1f} ms/round")
+    finally:
+        for s in sol:
+            s.close()
+    out["speedup_vs_sequential"] = round(out["eager_instance_steps_per_s"] /
+                                         out["sequential_instance_steps_per_s"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +361,9 @@ def main():
                          "preconditioner in each mode (0: skip)")
     ap.add_argument("--accuracy-steps", type=int, default=100,
                     help="mixed-vs-FP64 eigenvalue gate over this many steps (0: skip)")
+    ap.add_argument("--batch-instances", type=int, default=128,
+                    help="also time a grouped batch of this many 2-D problems (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
@@ -403,6 +473,8 @@ def main():
             jac[mode] = {"steps_per_s": round(args.jacobi_steps / r["seconds"], 6),
                          "pcg_iters_per_step": [st["pcg_iters"] for st in r["stats"]]}
         out["jacobi_preconditioner"] = jac
+    if args.batch_instances > 0:
+        out["batch"] = run_batch(args.batch_instances, args.batch_steps, log)
     if not args.no_cpu_baseline:
         ref = res["fp64"] if "fp64" in res else rh
         colits = max(ref["profile"][k]["work"] for k in ("sweep2_f64", "sweep2_f32", "cg_f64", "cg_f32"))

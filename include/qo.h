@@ -209,10 +209,11 @@ qo_status qo_get_matrix(qo_handle h, int which, double *out);
  * n, L, kinetic, precond) form a group: the grid-sized kernels (stencil, PCG sweeps,
  * preconditioner passes, energy) run once over all columns of a group, the Grams, block
  * updates and N x N algebra once per group with one tile set or workgroup per instance.
- * Restrictions: precision QO_FP64, pcg_variant 0, N <= 1024.  The PCG runs exactly
- * pcg_maxit iterations per solve (the largest value in the group); columns freeze on
- * convergence and a column still above its tolerance after them makes the step fail with
- * QO_ERR_PCG_NOCONV.  The solve of G U_n always starts from the previous G U_hat (zero
+ * Restrictions: precision QO_FP64, pcg_variant 0, N <= 1024.  The PCG runs a fixed
+ * number of iterations per solve: pcg_maxit (the largest value in the group) until
+ * iteration counts have been observed, then the largest count of the previous step plus
+ * a margin of 50% + 4, at most pcg_maxit; columns freeze on convergence, and a column
+ * still above its tolerance after them makes the step fail with QO_ERR_PCG_NOCONV.  The solve of G U_n always starts from the previous G U_hat (zero
  * after qo_batch_set_state).  With use_graph != 0 each step is replayed from a HIP graph
  * captured at its first use (one per parity of the P / Q buffers); the stream given to
  * qo_batch_create must then not be the null stream (NULL creates a private stream).  At

@@ -26,7 +26,7 @@ enum {
     BP_ZR, BP_O, BP_OR, BP_MS, BP_T1, BP_T2, BP_T3, BP_COUNT
 };
 
-constexpr int kWgThreads = 256;
+constexpr int kWgThreads = 1024;
 
 __device__ __forceinline__ double wg_sum(double v, double *red) {
 #pragma unroll

@@ -47,6 +47,7 @@ struct qo_batch_ctx {
         bool dst = false;
         long ng = 0, ld = 0, qs = 0;
         int C = 0, kmax = 0, ninst = 0, max_n = 0, max_gram_grid = 0, ty = 0;
+        int kuse = 0;  // iterations per solve in use: kmax until counts are observed
         double w = 1.0;
         std::vector<int> members;
         double *U = nullptr, *Uh = nullptr, *PQ[2] = {nullptr, nullptr}, *r = nullptr,
@@ -202,7 +203,8 @@ qo_status group_pcg(qo_batch_ctx *b, qo_batch_ctx::Group &G, const double *B, do
     BHIP(b, launch_fill_int(s.its, G.C, 0, st));
     BHIP(b, launch_pcg_init<double>(g, G.vs, G.dinv, B, X, G.r, G.ld, G.C, 1, s.part, st));
     double *pbuf[2] = {G.pa, G.pb};
-    for (int k = 0; k <= G.kmax; ++k) {
+    const int K = G.kuse;
+    for (int k = 0; k <= K; ++k) {
         if (G.dst) {
             BHIP(b, launch_pc_prep(k, G.C, nullptr, s, G.qs, tiles, 0.0, G.ng, G.pcs, st));
             BHIP(b, launch_dst_fwd<double>(G.dp, G.r, G.ld, G.C, G.t1, G.pcs, st));
@@ -212,12 +214,12 @@ qo_status group_pcg(qo_batch_ctx *b, qo_batch_ctx::Group &G, const double *B, do
         BHIP(b, launch_pcg_sweep1<double>(g, G.vs, G.dinv, G.r, pbuf[(k + 1) & 1], pbuf[k & 1],
                                           G.ld, G.C, k, 0.0, nullptr, s, st,
                                           G.dst ? G.z : nullptr, G.rzp, G.dp.nslab));
-        if (k == G.kmax) break;
+        if (k == K) break;
         BHIP(b, launch_pcg_sweep2<double>(g, G.vs, G.dinv, pbuf[k & 1], X, G.r, G.ld, G.C, k, s,
                                           st, !G.dst));
     }
     // a column still active after the final test did not converge
-    BHIP(b, launch_noconv_check(s.active + (G.kmax & 1) * G.C, G.C, b->err_dev, st));
+    BHIP(b, launch_noconv_check(s.active + (K & 1) * G.C, G.C, b->err_dev, st));
     return QO_OK;
 }
 
@@ -267,6 +269,7 @@ qo_status build_group(qo_batch_ctx *b, qo_batch_ctx::Group &G) {
     }
     coff[G.ninst] = G.C;
     G.kmax = kmax;
+    G.kuse = kmax;
     G.ng = (long)cf.n[0] * cf.n[1] * (cf.dim == 3 ? cf.n[2] : 1);
     G.ld = (G.ng + 63) / 64 * 64;
     const size_t blk = (size_t)G.ld * G.C;
@@ -356,7 +359,16 @@ qo_status build_group(qo_batch_ctx *b, qo_batch_ctx::Group &G) {
     std::vector<int> nsplit(G.ninst);
     for (int li = 0; li < G.ninst; ++li) {
         const int n = b->cfg[G.members[li]].N;
-        nsplit[li] = gram_nsplit(G.ng, n);
+        // K-chunks per Gram: about 8192 wavefronts over the whole group (the
+        // single-instance rule targets 4096 for one Gram), at least 256 rows each, and the
+        // instance's partials capped like the single-instance ones
+        {
+            const int np = gram_pairs(n);
+            long ns = 8192 / ((long)np * G.ninst);
+            ns = std::min(ns, (G.ng + 255) / 256);
+            ns = std::min(ns, (long)gram_nsplit(G.ng, n));
+            nsplit[li] = (int)std::max(1L, ns);
+        }
         pool_tot += nn_pool_elems(n);
         g_tot += (size_t)4 * n * n;
         gp_tot += gram_part_elems(n, nsplit[li]);
@@ -667,6 +679,10 @@ qo_status qo_batch_step(qo_batch b, const double *taus, int nsteps, int use_grap
                 }
                 if (ec != hipSuccess)
                     return bfail(b, QO_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+                if (b->gexec[par]) {
+                    (void)hipGraphExecDestroy(b->gexec[par]);
+                    b->gexec[par] = nullptr;
+                }
                 hipError_t ei = hipGraphInstantiate(&b->gexec[par], graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
                 if (ei != hipSuccess)
@@ -723,6 +739,18 @@ qo_status qo_batch_step(qo_batch b, const double *taus, int nsteps, int use_grap
                                  "instance %d: N x N predictor solve failed (code %d)", i,
                                  hst[k][li]);
                 }
+        }
+        // fixed iteration count for the next steps: the counts just observed with a margin
+        // of 50% + 4 (warm-started counts change slowly), at most pcg_maxit
+        for (size_t k = 0; k < b->groups.size(); ++k) {
+            auto &G = b->groups[k];
+            int m = 0;
+            for (int c = 0; c < G.C; ++c) m = std::max(m, std::max(hit0[k][c], hit1[k][c]));
+            const int want = std::min(G.kmax, m + std::max(4, m / 2));
+            if (want != G.kuse) {
+                G.kuse = want;
+                b->gvalid[0] = b->gvalid[1] = false;
+            }
         }
         for (size_t k = 0; k < b->groups.size(); ++k) {
             auto &G = b->groups[k];

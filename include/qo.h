@@ -250,6 +250,34 @@ typedef struct {
     double work[QO_KERNEL_COUNT];
 } qo_profile_data;
 
+/* ---- reverse mode through K steps -------------------------------------------------
+ *
+ * qo_tape_forward takes K steps of Sec. 4.1 (Algorithm 1 of Sec. 5 with a fixed tau) from
+ * the current state and records a checkpoint of every step's starting block U_0 .. U_K
+ * (K + 1 blocks of ld x N doubles held by the handle until it is destroyed; they grow
+ * with the largest K taped).  The linear solves start from zero while taping, so a step
+ * can be recomputed bit for bit from its checkpoint; the handle's warm_start setting is
+ * restored afterwards.  *L receives the loss of U_K:
+ *   loss 0: E(U_K) = h^d/2 sum_c u_c^T H u_c, the energy of Sec. 2.2;
+ *   loss 1: theta_1 + ... + theta_N, the sum of the Ritz values of span U_K (the
+ *           eigenvalue read-out of Sec. 5), = tr(S^{-1} K_sigma) - N sigma.
+ * FP64 only (QO_ERR_ARG for precision QO_MIXED); QO_ERR_STATE without potential or
+ * state; solver errors as qo_step.  On error the tape is invalid and the state is the
+ * last completed step's.
+ *
+ * qo_tape_backward returns seed * dL/dV (gV, Ng values) and seed * dL/dU_0 (gU0, N
+ * columns of Ng values with leading dimension ld >= Ng, the layout of qo_set_state);
+ * either may be NULL.  Device pointers when on_device, else host.  It goes back through
+ * the steps, recomputing each from its checkpoint, with the adjoints of the corrector,
+ * of the solves Q = G U_hat and P = G U (each an extra solve with the same symmetric
+ * H_sigma; dG/dV = -G diag(dV) G), of the predictor's N x N algebra and of the Gram
+ * matrices.  The result is the derivative of the computed K-step map (the solves taken
+ * as exact); it uses 2K solves of N columns more than the forward.  The state is U_K
+ * again afterwards.  QO_ERR_STATE before a successful qo_tape_forward. */
+qo_status qo_tape_forward(qo_handle h, double tau, int K, int loss, double *L);
+qo_status qo_tape_backward(qo_handle h, double seed, double *gV, double *gU0, long ld,
+                           int on_device);
+
 /* enable != 0 turns timing on and clears the counters; 0 turns it off. */
 qo_status qo_profile(qo_handle h, int enable);
 qo_status qo_profile_get(qo_handle h, qo_profile_data *out);

@@ -39,6 +39,10 @@ Readings of the paper taken here (numbered as in the design notes' table of read
       with V replaced by a constant, inverted exactly by the orthonormal type-I
       discrete sine transform, which diagonalises the 1-D Dirichlet second
       difference (``precond_apply``).  Only the iteration count depends on M.
+  R16 The paper does not differentiate the scheme.  ``steps_loss_grad`` gives the
+      exact derivative of the discrete K-step map (solves taken exact) composed
+      with a loss of U_K (the energy, or the sum of the Ritz values), with respect
+      to the potential V and the starting block U_0.
 """
 from __future__ import annotations
 
@@ -437,6 +441,111 @@ class Oracle:
                 return k, last
             last = st
         return max_steps, last
+
+
+# ---------------------------------------------------------------------------
+# Derivatives of K steps (reading R16)
+# ---------------------------------------------------------------------------
+
+def steps_loss(prob: Problem, U0, tau, K, loss="energy"):
+    """K steps of the scheme (Sec. 4.1) with exact solves, then the loss of U_K:
+    "energy": E(U_K) of Sec. 2.2; "ritz_sum": theta_1 + ... + theta_N of span U_K
+    (= tr(<U,U>^{-1} <U, H U>)).  Returns (L, U_K, tape) with one record per step."""
+    U = np.array(_fcols(U0, prob.ng), order="F", copy=True)
+    tape = []
+    for _ in range(K):
+        P = prob.solve_direct(U)
+        U_hat, X, Y, (S, M, R) = predictor(prob, U, P, tau)
+        Q = prob.solve_direct(U_hat)
+        U_next, O, _, _ = corrector(prob, U_hat, Q, tau)
+        tape.append(dict(U=U, P=P, S=S, M=M, R=R, X=X, Y=Y, U_hat=U_hat, Q=Q, O=O))
+        U = U_next
+    return _loss(prob, U, loss), U, tape
+
+
+def _loss(prob, U, loss):
+    if loss == "energy":
+        return prob.energy(U)[0]
+    S = prob.inner(U, U)
+    Kh = prob.inner(U, prob.apply(U))
+    return float(np.trace(np.linalg.solve(S, Kh))) - U.shape[1] * prob.sigma
+
+
+def _loss_grad(prob, U, loss):
+    """(dL/dU, dL/dV) of the loss at fixed U.  With H = H_sigma - sigma:
+    energy  L = w/2 tr(U^T H U):  dL/dU = w H U,  dL/dV_j = w/2 sum_c U_jc^2;
+    ritz    L = tr(S^{-1} K), S = w U^T U, K = w U^T H_sigma U (minus N sigma):
+            dL/dU = 2w (H_sigma U S^{-1} - U S^{-1} K S^{-1}),
+            dL/dV_j = w (U S^{-1} U^T)_jj."""
+    w = prob.w
+    HU = prob.apply(U)
+    if loss == "energy":
+        return w * (HU - prob.sigma * U), 0.5 * w * np.sum(U * U, axis=1)
+    S = prob.inner(U, U)
+    Kh = prob.inner(U, HU)
+    Si = np.linalg.inv(S)
+    gU = 2.0 * w * (HU @ Si - U @ Si @ Kh @ Si)
+    gV = w * np.sum((U @ Si) * U, axis=1)
+    return gU, gV
+
+
+def _predictor_adjoint(prob, S, M, R, tau, Xb, Yb):
+    """Adjoint of the predictor's coefficient system (see ``predictor``): given dL/dX and
+    dL/dY, return dL/dS, dL/dM, dL/dR.  The system is Kmat [a; b] = [S; -M^T] with
+    Kmat = [[I - alpha M, -alpha S], [alpha R, I + alpha M^T]], X = I + tau b,
+    Y = tau a.  For sol = Kmat^{-1} rhs: rhs_bar = Kmat^{-T} sol_bar and
+    Kmat_bar = -rhs_bar sol^T."""
+    N = S.shape[0]
+    alpha = 0.5 * tau
+    I = np.eye(N)
+    Kmat = np.block([[I - alpha * M, -alpha * S], [alpha * R, I + alpha * M.T]])
+    sol = np.linalg.solve(Kmat, np.vstack([S, -M.T]))
+    sol_bar = np.vstack([tau * Yb, tau * Xb])
+    rhs_bar = np.linalg.solve(Kmat.T, sol_bar)
+    K_bar = -rhs_bar @ sol.T
+    K11, K12 = K_bar[:N, :N], K_bar[:N, N:]
+    K21, K22 = K_bar[N:, :N], K_bar[N:, N:]
+    Sb = -alpha * K12 + rhs_bar[:N]
+    Mb = -alpha * K11 + alpha * K22.T - rhs_bar[N:].T
+    Rb = alpha * K21
+    return Sb, Mb, Rb
+
+
+def steps_loss_grad(prob: Problem, U0, tau, K, loss="energy"):
+    """L of ``steps_loss`` and its exact derivatives dL/dV (Ng,) and dL/dU0 (Ng, N), by
+    the chain rule taken backwards through the steps.  Per step, in reverse order:
+      corrector U' = U_hat - tau Q O, O = sym<U_hat,U_hat> - I:
+          Q_bar = -tau U'_bar O,  O_bar = -tau Q^T U'_bar,
+          U_hat_bar = U'_bar + 2w U_hat sym(O_bar);
+      Q = G U_hat (G = H_sigma^{-1} symmetric, dG/dV_j = -G e_j e_j^T G):
+          U_hat_bar += G Q_bar,  V_bar_j -= sum_c (G Q_bar)_jc Q_jc;
+      U_hat = U X + P Y:  U_bar = U_hat_bar X^T, P_bar = U_hat_bar Y^T,
+          X_bar = U^T U_hat_bar, Y_bar = P^T U_hat_bar, then the predictor's adjoint;
+      S = <U,U>, M = <U,P>, R = <P,P>:
+          U_bar += w U (S_bar + S_bar^T) + w P M_bar^T,
+          P_bar += w U M_bar + w P (R_bar + R_bar^T);
+      P = G U:  U_bar += G P_bar,  V_bar_j -= sum_c (G P_bar)_jc P_jc."""
+    L, UK, tape = steps_loss(prob, U0, tau, K, loss)
+    w = prob.w
+    Ub, Vb = _loss_grad(prob, UK, loss)
+    for t in reversed(tape):
+        U, P, Q, U_hat, O = t["U"], t["P"], t["Q"], t["U_hat"], t["O"]
+        Qb = -tau * Ub @ O
+        Ob = -tau * Q.T @ Ub
+        Uhb = Ub + 2.0 * w * U_hat @ (0.5 * (Ob + Ob.T))
+        W = prob.solve_direct(Qb)
+        Uhb = Uhb + W
+        Vb = Vb - np.sum(W * Q, axis=1)
+        Un = Uhb @ t["X"].T
+        Pb = Uhb @ t["Y"].T
+        Sb, Mb, Rb = _predictor_adjoint(prob, t["S"], t["M"], t["R"], tau, U.T @ Uhb,
+                                        P.T @ Uhb)
+        Un = Un + w * U @ (Sb + Sb.T) + w * P @ Mb.T
+        Pb = Pb + w * U @ Mb + w * P @ (Rb + Rb.T)
+        W = prob.solve_direct(Pb)
+        Ub = Un + W
+        Vb = Vb - np.sum(W * P, axis=1)
+    return L, Vb, np.asfortranarray(Ub)
 
 
 # ---------------------------------------------------------------------------

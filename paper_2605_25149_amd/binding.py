@@ -30,7 +30,7 @@ EXPORTS = [
     "qo_create", "qo_set_potential", "qo_set_state", "qo_get_state", "qo_step", "qo_energy",
     "qo_gram", "qo_eigenpairs", "qo_destroy", "qo_status_string", "qo_last_error", "qo_apply",
     "qo_solve", "qo_gram_pair", "qo_get_block", "qo_get_matrix", "qo_profile", "qo_profile_get",
-    "qo_run", "qo_eigsum_gradient", "qo_precond",
+    "qo_run", "qo_eigsum_gradient", "qo_precond", "qo_tape_forward", "qo_tape_backward",
     "qo_batch_create", "qo_batch_set_potential", "qo_batch_set_state", "qo_batch_get_state",
     "qo_batch_step", "qo_batch_tile", "qo_batch_destroy", "qo_batch_last_error",
 ]
@@ -118,6 +118,9 @@ def load_library(path: str = LIB_PATH):
                     dp, ip, ctypes.POINTER(QoStepStats)], ctypes.c_int),
         "qo_profile_get": ([H, ctypes.POINTER(QoProfileData)], ctypes.c_int),
         "qo_precond": ([H, vp, vp, ctypes.c_long, ctypes.c_int, vp], ctypes.c_int),
+        "qo_tape_forward": ([H, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp], ctypes.c_int),
+        "qo_tape_backward": ([H, ctypes.c_double, vp, vp, ctypes.c_long, ctypes.c_int],
+                             ctypes.c_int),
         "qo_batch_create": ([ctypes.POINTER(QoConfig), ctypes.c_int, vp, ctypes.POINTER(H)],
                             ctypes.c_int),
         "qo_batch_set_potential": ([H, ctypes.c_int, vp, ctypes.c_int], ctypes.c_int),
@@ -296,6 +299,26 @@ class Solver:
         g = torch.empty(self.ng, dtype=torch.float64, device="cuda")
         self._chk(self.lib.qo_eigsum_gradient(self.h, ctypes.c_void_p(g.data_ptr()), 1))
         return g
+
+    LOSSES = {"energy": 0, "ritz_sum": 1}
+
+    def tape_forward(self, tau, K, loss="energy"):
+        """K taped steps from the current state; returns the loss of U_K (energy, or the
+        sum of the Ritz values)."""
+        L = ctypes.c_double()
+        self._chk(self.lib.qo_tape_forward(self.h, float(tau), int(K), self.LOSSES[loss],
+                                           ctypes.byref(L)))
+        return L.value
+
+    def tape_backward(self, seed=1.0):
+        """(seed dL/dV as a CUDA tensor (Ng,), seed dL/dU_0 as a block (N, Ng))."""
+        import torch
+
+        gV = torch.empty(self.ng, dtype=torch.float64, device="cuda")
+        gU = torch.empty((self.N, self.ng), dtype=torch.float64, device="cuda")
+        self._chk(self.lib.qo_tape_backward(self.h, float(seed), ctypes.c_void_p(gV.data_ptr()),
+                                            ctypes.c_void_p(gU.data_ptr()), self.ng, 1))
+        return gV, gU
 
     def energy(self):
         e, es = ctypes.c_double(), ctypes.c_double()

@@ -90,6 +90,13 @@ struct qo_ctx {
     float *dmu = nullptr, *pcs = nullptr, *z32 = nullptr;
     double *z64 = nullptr, *rzp = nullptr, *dsum = nullptr;
     double mu0 = 0.0;  // mu_x[0] + mu_y[0] (+ mu_z[0]): smallest eigenvalue of -Lap_h
+    // reverse mode through taped steps (qo_tape_forward / qo_tape_backward)
+    std::vector<double *> tape;  // U_0 .. U_K
+    int tape_K = 0, tape_loss = 0;
+    double tape_tau = 0.0;
+    bool have_tape = false;
+    double *ab[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double *gVd = nullptr, *adpool = nullptr, *admat = nullptr;
     // pinned host
     int *h_poll = nullptr;
     double *h_scal = nullptr;
@@ -860,6 +867,46 @@ __global__ void k_rowdot(const double *__restrict__ Y, const double *__restrict_
     }
 }
 
+// g[j] += a sum_c Y[c][j] X[c][j]
+__global__ void k_rowdot_acc(const double *__restrict__ Y, const double *__restrict__ X, long ld,
+                             long ng, int n, double a, double *__restrict__ g) {
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < ng;
+         j += (long)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < n; ++c) s += Y[(long)c * ld + j] * X[(long)c * ld + j];
+        g[j] += a * s;
+    }
+}
+
+// Y = a X + b Y over ng rows of ncols columns (column c in blockIdx.y)
+__global__ void k_block_axpby(double *__restrict__ Y, const double *__restrict__ X, long ld,
+                              long ng, double a, double b) {
+    const long o = (long)blockIdx.y * ld;
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < ng;
+         j += (long)gridDim.x * blockDim.x)
+        Y[o + j] = a * X[o + j] + (b == 0.0 ? 0.0 : b * Y[o + j]);
+}
+
+// out[0] = tr(A B) for n x n column-major A, B (one block)
+__global__ void k_trace_prod(const double *__restrict__ A, int lda, const double *__restrict__ B,
+                             int ldb, int n, double *__restrict__ out) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e % n, j = e / n;
+        s += A[(long)j * lda + i] * B[(long)i * ldb + j];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        out[0] = t;
+    }
+}
+
 __global__ void k_scan_finite(const double *__restrict__ X, long ld, long ng, int ncols,
                               int *__restrict__ bad) {
     const int c = blockIdx.y;
@@ -1466,6 +1513,229 @@ qo_status qo_profile_get(qo_handle h, qo_profile_data *out) {
     prof_harvest(h);
     *out = h->pdata;
     return QO_OK;
+}
+
+}  // extern "C"
+
+// ---- reverse mode through K evolution steps ------------------------------------------
+//
+// qo_tape_forward takes K steps from the current state with cold-started solves (so every
+// step can be recomputed exactly from its starting state) and keeps U_0 .. U_K; the loss
+// is E(U_K) or the sum of the Ritz values of span U_K.  qo_tape_backward runs the adjoint
+// of the steps in reverse order: each step is recomputed from its checkpoint, then the
+// adjoints go back through the corrector, the solve Q = G U_hat, the predictor update,
+// the N x N algebra, the Grams and the solve P = G U.  The adjoint of a solve is a solve
+// with the same (symmetric) G; dG/dV = -G diag(dV) G gives the potential's share.
+namespace {
+
+enum { AM_XB, AM_YB, AM_SB, AM_MB, AM_RB, AM_SHB, AM_T, AM_T2, AM_T3, AM_G, AM_COUNT = AM_G + 4 };
+
+double *am(qo_ctx *c, int i) { return c->admat + (size_t)i * c->N * c->N; }
+
+qo_status tape_alloc(qo_ctx *c, int K) {
+    const size_t blk = (size_t)c->ld * c->N;
+    qo_status s = QO_OK;
+    while (s == QO_OK && (int)c->tape.size() < K + 1) {
+        double *p = nullptr;
+        s = dalloc(c, &p, blk);
+        if (s == QO_OK) c->tape.push_back(p);
+    }
+    for (int i = 0; i < 6 && s == QO_OK; ++i)
+        if (!c->ab[i]) s = dalloc(c, &c->ab[i], blk);
+    if (s == QO_OK && !c->gVd) s = dalloc(c, &c->gVd, (size_t)c->ng);
+    if (s == QO_OK && !c->adpool) s = dalloc(c, &c->adpool, nn_adjoint_pool_elems(c->N));
+    if (s == QO_OK && !c->admat) s = dalloc(c, &c->admat, (size_t)AM_COUNT * c->N * c->N);
+    return s;
+}
+
+qo_status blk_axpby(qo_ctx *c, double *Y, const double *X, double a, double b) {
+    long blocks = (c->ng + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_block_axpby, dim3((unsigned)blocks, (unsigned)c->N), dim3(256), 0, c->st,
+                       Y, X, c->ld, c->ng, a, b);
+    HIPC(c, hipGetLastError());
+    return QO_OK;
+}
+
+qo_status rowdot_acc(qo_ctx *c, const double *Y, const double *X, double a) {
+    long blocks = (c->ng + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_rowdot_acc, dim3((unsigned)blocks), dim3(256), 0, c->st, Y, X, c->ld,
+                       c->ng, c->N, a, c->gVd);
+    HIPC(c, hipGetLastError());
+    return QO_OK;
+}
+
+// Loss at U (the current state) and, when grad, seed times its gradient: Ubar into ab[0]
+// and the explicit potential term into gVd (overwritten).
+qo_status loss_and_grad(qo_ctx *c, int kind, double *L, bool grad, double seed = 1.0) {
+    hipStream_t st = c->st;
+    const int N = c->N, N2 = 2 * N;
+    const double w = c->w, sigma = c->cfg.sigma;
+    double *U = c->U, *HU = c->ab[4];
+    if (grad) HIPC(c, hipMemsetAsync(c->gVd, 0, sizeof(double) * c->ng, st));
+    if (kind == 0) {
+        double Es = 0.0, trS = 0.0;
+        QOC(energy_of(c, U, &Es, &trS));
+        *L = Es - 0.5 * sigma * trS;
+        if (!grad) return QO_OK;
+        HIPC(c, launch_apply(c->g, c->vs, U, HU, c->ld, N, st));
+        QOC(blk_axpby(c, c->ab[0], HU, seed * w, 0.0));
+        QOC(blk_axpby(c, c->ab[0], U, -seed * w * sigma, 1.0));
+        return rowdot_acc(c, U, U, 0.5 * seed * w);
+    }
+    // sum of the Ritz values: tr(S^{-1} K) - N sigma with S = <U,U>, K = <U, H_sigma U>
+    HIPC(c, launch_apply(c->g, c->vs, U, HU, c->ld, N, st));
+    QOC(gram64(c, U, HU, c->ld, N, am(c, AM_G)));
+    double *S = am(c, AM_G), *Kb = am(c, AM_G) + (size_t)N * N2;
+    HIPC(c, hipMemsetAsync(c->dstatus, 0, sizeof(int), st));
+    HIPC(c, nn_axpby(am(c, AM_T), N, 1.0, S, N2, 0.0, nullptr, N, false, 0.0, N, N, st));
+    HIPC(c, nn_axpby(am(c, AM_T2), N, 0.0, nullptr, N, 0.0, nullptr, N, false, 1.0, N, N, st));
+    HIPC(c, nn_gj_solve(am(c, AM_T), N, am(c, AM_T2), N, N, N, true, c->dstatus, st, c->gjw,
+                        c->gjpiv));
+    QOC(check_status(c, "Ritz-sum loss: <U,U> not positive definite"));
+    double *Si = am(c, AM_T3);
+    HIPC(c, nn_axpby(Si, N, 0.5, am(c, AM_T2), N, 0.5, am(c, AM_T2), N, true, 0.0, N, N, st));
+    hipLaunchKernelGGL(k_trace_prod, dim3(1), dim3(1024), 0, st, Si, N, Kb, N2, N, c->dscal + 8);
+    HIPC(c, hipGetLastError());
+    HIPC(c, hipMemcpyAsync(c->h_scal + 8, c->dscal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(c, hipStreamSynchronize(st));
+    *L = c->h_scal[8] - N * sigma;
+    if (!grad) return QO_OK;
+    // Ubar = 2w (H_sigma U S^{-1} - U S^{-1} K S^{-1}); gV = w diag(U S^{-1} U^T)
+    HIPC(c, nn_gemm(am(c, AM_T), N, Si, N, false, Kb, N2, false, N, N, N, 1.0, 0.0, 0.0, st));
+    HIPC(c, nn_gemm(am(c, AM_T2), N, am(c, AM_T), N, false, Si, N, false, N, N, N, 1.0, 0.0, 0.0, st));
+    HIPC(c, nn_axpby(am(c, AM_T), N, -seed * w, am(c, AM_T2), N, -seed * w, am(c, AM_T2), N, true,
+                     0.0, N, N, st));
+    HIPC(c, nn_axpby(am(c, AM_SHB), N, 2.0 * seed * w, Si, N, 0.0, nullptr, N, false, 0.0, N, N, st));
+    QOC(tsgemm(c, c->ab[0], nullptr, HU, am(c, AM_SHB), U, am(c, AM_T)));
+    QOC(tsgemm(c, c->ab[5], nullptr, U, Si, nullptr, nullptr));
+    return rowdot_acc(c, c->ab[5], U, seed * w);
+}
+
+}  // namespace
+
+extern "C" {
+
+qo_status qo_tape_forward(qo_handle h, double tau, int K, int loss, double *L) {
+    if (!h || !L) return h ? fail(h, QO_ERR_ARG, "null output") : QO_ERR_ARG;
+    if (!h->have_V || !h->have_U) return fail(h, QO_ERR_STATE, "set the potential and the state first");
+    if (h->mixed) return fail(h, QO_ERR_ARG, "the tape needs precision QO_FP64");
+    if (!(tau > 0.0) || K < 0 || K > 100000 || (loss != 0 && loss != 1))
+        return fail(h, QO_ERR_ARG, "bad tau, K or loss");
+    QOC(tape_alloc(h, K));
+    const size_t bytes = sizeof(double) * h->ld * h->N;
+    const int warm = h->cfg.warm_start;
+    h->cfg.warm_start = 0;
+    h->have_tape = false;
+    qo_status s = QO_OK;
+    if (hipMemcpyAsync(h->tape[0], h->U, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess)
+        s = fail(h, QO_ERR_DEVICE, "tape copy failed");
+    for (int n = 0; n < K && s == QO_OK; ++n) {
+        s = one_step(h, tau, nullptr);
+        if (s == QO_OK && hipMemcpyAsync(h->tape[n + 1], h->U, bytes, hipMemcpyDeviceToDevice,
+                                         h->st) != hipSuccess)
+            s = fail(h, QO_ERR_DEVICE, "tape copy failed");
+    }
+    h->cfg.warm_start = warm;
+    h->have_warm = false;
+    if (s != QO_OK) return s;
+    QOC(loss_and_grad(h, loss, L, false));
+    h->tape_K = K;
+    h->tape_tau = tau;
+    h->tape_loss = loss;
+    h->have_tape = true;
+    return QO_OK;
+}
+
+qo_status qo_tape_backward(qo_handle h, double seed, double *gV, double *gU0, long ld,
+                           int on_device) {
+    if (!h) return QO_ERR_ARG;
+    if (!h->have_tape) return fail(h, QO_ERR_STATE, "run qo_tape_forward first");
+    if (gU0 && ld < h->ng) return fail(h, QO_ERR_ARG, "ld %ld < Ng %ld", ld, h->ng);
+    hipStream_t st = h->st;
+    const int N = h->N, N2 = 2 * N, K = h->tape_K;
+    const double w = h->w, tau = h->tape_tau;
+    const size_t bytes = sizeof(double) * h->ld * N;
+    std::vector<int> its(N);
+    int rounds = 0;
+    const int warm = h->cfg.warm_start;
+    h->cfg.warm_start = 0;
+    auto body = [&]() -> qo_status {
+        double L = 0.0;
+        HIPC(h, hipMemcpyAsync(h->U, h->tape[K], bytes, hipMemcpyDeviceToDevice, st));
+        QOC(loss_and_grad(h, h->tape_loss, &L, true, seed));
+        for (int n = K - 1; n >= 0; --n) {
+            double *Un = h->tape[n];
+            // recompute step n (cold solves: the same arithmetic as the taped forward)
+            HIPC(h, hipMemcpyAsync(h->U, Un, bytes, hipMemcpyDeviceToDevice, st));
+            h->have_warm = false;
+            QOC(one_step(h, tau, nullptr));
+            const double *P = h->lastP, *Q = h->lastQ, *Uh = h->Uh;
+            double *Ub = h->ab[0], *Uhb = h->ab[1], *Pb = h->ab[2], *Qb = h->ab[3],
+                   *Wt = h->ab[4], *Unb = h->ab[5];
+            // corrector U' = U_hat - tau Q O:  Qb = Ub (-tau O), Shb = sym(-tau Q^T Ub)
+            QOC(tsgemm(h, Qb, nullptr, Ub, mp(h, MP_OR), nullptr, nullptr));
+            QOC(gram64(h, Q, Ub, h->ld, N, am(h, AM_G)));
+            const double *Bx = am(h, AM_G) + (size_t)N * N2;
+            HIPC(h, nn_axpby(am(h, AM_SHB), N, -0.5 * tau / w, Bx, N2, -0.5 * tau / w, Bx, N2,
+                             true, 0.0, N, N, st));
+            // O = sym <U_hat,U_hat> - I:  Uhb = Ub + 2 w U_hat Shb
+            HIPC(h, nn_axpby(am(h, AM_T), N, 2.0 * w, am(h, AM_SHB), N, 0.0, nullptr, N, false,
+                             0.0, N, N, st));
+            QOC(tsgemm(h, Uhb, Ub, Uh, am(h, AM_T), nullptr, nullptr));
+            // Q = G U_hat:  Uhb += G Qb, gV -= rowdot(G Qb, Q)
+            QOC(solve_block(h, Qb, Wt, N, 0, its.data(), &rounds, "adjoint solve G Q_bar"));
+            QOC(blk_axpby(h, Uhb, Wt, 1.0, 1.0));
+            QOC(rowdot_acc(h, Wt, Q, -1.0));
+            // U_hat = U X + P Y:  Xb = U^T Uhb, Yb = P^T Uhb
+            QOC(gram64(h, Un, Uhb, h->ld, N, am(h, AM_G)));
+            HIPC(h, nn_axpby(am(h, AM_XB), N, 1.0 / w, Bx, N2, 0.0, nullptr, N, false, 0.0, N, N,
+                             st));
+            QOC(gram64(h, P, Uhb, h->ld, N, am(h, AM_G)));
+            HIPC(h, nn_axpby(am(h, AM_YB), N, 1.0 / w, Bx, N2, 0.0, nullptr, N, false, 0.0, N, N,
+                             st));
+            HIPC(h, hipMemsetAsync(h->dstatus, 0, sizeof(int), st));
+            HIPC(h, launch_nn_adjoint(h->G1, N, tau, am(h, AM_XB), am(h, AM_YB), h->adpool,
+                                      am(h, AM_SB), h->dstatus, st));
+            QOC(check_status(h, "adjoint of the predictor algebra"));
+            // Ub <- Uhb X^T + U w(Sb + Sb^T) + P w Mb^T  (Ub itself is no longer needed)
+            HIPC(h, nn_axpby(am(h, AM_T), N, w, am(h, AM_SB), N, w, am(h, AM_SB), N, true, 0.0,
+                             N, N, st));
+            QOC(tsgemm(h, Unb, nullptr, Uhb, mp(h, MP_X), Un, am(h, AM_T)));
+            HIPC(h, nn_axpby(am(h, AM_T2), N, w, am(h, AM_MB), N, 0.0, nullptr, N, false, 0.0, N,
+                             N, st));
+            QOC(tsgemm(h, Ub, Unb, P, am(h, AM_T2), nullptr, nullptr));
+            // Pb = Uhb Y^T + U w Mb + P w(Rb + Rb^T), built in Pb then Qb
+            HIPC(h, nn_axpby(am(h, AM_T3), N, 0.0, nullptr, N, w, am(h, AM_MB), N, true, 0.0, N,
+                             N, st));
+            QOC(tsgemm(h, Pb, nullptr, Uhb, mp(h, MP_Y), Un, am(h, AM_T3)));
+            HIPC(h, nn_axpby(am(h, AM_T), N, w, am(h, AM_RB), N, w, am(h, AM_RB), N, true, 0.0,
+                             N, N, st));
+            QOC(tsgemm(h, Qb, Pb, P, am(h, AM_T), nullptr, nullptr));
+            // P = G U:  Ub += G Pb, gV -= rowdot(G Pb, P)
+            QOC(solve_block(h, Qb, Wt, N, 0, its.data(), &rounds, "adjoint solve G P_bar"));
+            QOC(blk_axpby(h, Ub, Wt, 1.0, 1.0));
+            QOC(rowdot_acc(h, Wt, P, -1.0));
+        }
+        // outputs, state back at U_K
+        if (gU0)
+            HIPC(h, hipMemcpy2DAsync(gU0, sizeof(double) * ld, h->ab[0], sizeof(double) * h->ld,
+                                     sizeof(double) * h->ng, N,
+                                     on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                     st));
+        if (gV)
+            HIPC(h, hipMemcpyAsync(gV, h->gVd, sizeof(double) * h->ng,
+                                   on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                   st));
+        HIPC(h, hipMemcpyAsync(h->U, h->tape[K], bytes, hipMemcpyDeviceToDevice, st));
+        HIPC(h, hipStreamSynchronize(st));
+        return QO_OK;
+    };
+    const qo_status s = body();
+    h->cfg.warm_start = warm;
+    h->have_warm = false;
+    return s;
 }
 
 }  // extern "C"

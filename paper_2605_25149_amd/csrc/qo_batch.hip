@@ -264,6 +264,110 @@ __global__ __launch_bounds__(kWgThreads) void k_nn_correct(const NnJob *__restri
     }
 }
 
+// Reverse mode of the predictor algebra (one instance, one workgroup): given the
+// adjoints Xb, Yb of X, Y (N x N, column-major), return Sb, Mb, Rb, the adjoints of
+// S = <U,U>, M = <U,P>, R = <P,P> (the forward intermediates are recomputed from S, M, R):
+//   Ab = tau Yb - tau C^T Xb,  Cb = -tau Xb A^T,  bb = tau Xb + a S Ab,  Sb = Ab + a Ab b^T,
+//   MAT^T RHSb = bb,  MATb = -RHSb b^T,  Kb = a^2 MATb - a RHSb,  Db = RHSb - a MATb,
+//   RWb = Kb S, Sb += RW Kb, Cb += Db S, Sb += C^T Db, Mb = -Db^T,
+//   Tb = sym(RWb), Rb = Tb, Mb -= C Tb, Cb -= M Tb,
+//   Z = S^{-1} Cb, Mb += Z, Sb -= Z C^T.
+// Work slots AD_* (N x N each); status as in the forward.
+enum {
+    AD_SW, AD_C, AD_T, AD_RW, AD_D, AD_K, AD_MAT, AD_MATT, AD_B, AD_A, AD_AB, AD_CB, AD_BB, AD_SB,
+    AD_RHSB, AD_MATB, AD_KB, AD_DB, AD_RWB, AD_TB, AD_MB, AD_RB, AD_Z, AD_COUNT
+};
+
+__global__ __launch_bounds__(kWgThreads) void k_nn_adjoint(const double *__restrict__ G1, int N,
+                                                           double tau, const double *__restrict__ Xb,
+                                                           const double *__restrict__ Yb,
+                                                           double *__restrict__ pool,
+                                                           double *__restrict__ out,
+                                                           int *__restrict__ status) {
+    extern __shared__ double nsm[];  // f[n], prow[2n]
+    __shared__ double sval[kWgThreads / 64];
+    __shared__ int sidx[kWgThreads / 64], ish[2];
+    const int N2 = 2 * N;
+    const double al = 0.5 * tau;
+    auto mp = [&](int i) { return pool + (size_t)i * N * N; };
+    const double *S = G1;
+    const double *M = G1 + (size_t)N * N2;
+    const double *R = G1 + (size_t)N * N2 + N;
+    // forward intermediates
+    wg_axpby(mp(AD_SW), N, 1.0, S, N2, 0.0, nullptr, N, false, 0.0, N, N);
+    wg_axpby(mp(AD_C), N, 1.0, M, N2, 0.0, nullptr, N, false, 0.0, N, N);
+    int st = wg_gj(mp(AD_SW), N, mp(AD_C), N, N, N, true, nsm, nsm + N, sval, sidx, ish);
+    if (st) {
+        if (threadIdx.x == 0) *status = st;
+        return;
+    }
+    double *C = mp(AD_C);
+    wg_axpby(mp(AD_T), N, 1.0, R, N2, 0.0, nullptr, N, false, 0.0, N, N);
+    wg_gemm(mp(AD_T), N, M, N2, true, C, N, false, N, N, N, -1.0, 1.0, 0.0);
+    wg_axpby(mp(AD_RW), N, 0.5, mp(AD_T), N, 0.5, mp(AD_T), N, true, 0.0, N, N);
+    wg_gemm(mp(AD_D), N, C, N, false, S, N2, false, N, N, N, 1.0, 0.0, 0.0);
+    wg_axpby(mp(AD_D), N, 1.0, mp(AD_D), N, -1.0, M, N2, true, 0.0, N, N);
+    wg_gemm(mp(AD_K), N, mp(AD_RW), N, false, S, N2, false, N, N, N, 1.0, 0.0, 0.0);
+    wg_axpby(mp(AD_MAT), N, al * al, mp(AD_K), N, -al, mp(AD_D), N, false, 1.0, N, N);
+    wg_axpby(mp(AD_MATT), N, 0.0, nullptr, N, 1.0, mp(AD_MAT), N, true, 0.0, N, N);
+    wg_axpby(mp(AD_B), N, 1.0, mp(AD_D), N, -al, mp(AD_K), N, false, 0.0, N, N);
+    st = wg_gj(mp(AD_MAT), N, mp(AD_B), N, N, N, false, nsm, nsm + N, sval, sidx, ish);
+    if (st) {
+        if (threadIdx.x == 0) *status = st;
+        return;
+    }
+    double *b = mp(AD_B);
+    wg_axpby(mp(AD_A), N, 1.0, S, N2, 0.0, nullptr, N, false, 0.0, N, N);
+    wg_gemm(mp(AD_A), N, S, N2, false, b, N, false, N, N, N, al, 1.0, 0.0);
+    // reverse sweep
+    double *Ab = mp(AD_AB), *Cb = mp(AD_CB), *bb = mp(AD_BB), *Sb = mp(AD_SB);
+    wg_axpby(Ab, N, tau, Yb, N, 0.0, nullptr, N, false, 0.0, N, N);
+    wg_gemm(Ab, N, C, N, true, Xb, N, false, N, N, N, -tau, 1.0, 0.0);
+    wg_gemm(Cb, N, Xb, N, false, mp(AD_A), N, true, N, N, N, -tau, 0.0, 0.0);
+    wg_axpby(bb, N, tau, Xb, N, 0.0, nullptr, N, false, 0.0, N, N);
+    wg_gemm(bb, N, S, N2, false, Ab, N, false, N, N, N, al, 1.0, 0.0);
+    wg_axpby(Sb, N, 1.0, Ab, N, 0.0, nullptr, N, false, 0.0, N, N);
+    wg_gemm(Sb, N, Ab, N, false, b, N, true, N, N, N, al, 1.0, 0.0);
+    // RHSb = MAT^{-T} bb
+    double *RHSb = mp(AD_RHSB);
+    wg_axpby(RHSb, N, 1.0, bb, N, 0.0, nullptr, N, false, 0.0, N, N);
+    st = wg_gj(mp(AD_MATT), N, RHSb, N, N, N, false, nsm, nsm + N, sval, sidx, ish);
+    if (st) {
+        if (threadIdx.x == 0) *status = st;
+        return;
+    }
+    double *MATb = mp(AD_MATB), *Kb = mp(AD_KB), *Db = mp(AD_DB);
+    wg_gemm(MATb, N, RHSb, N, false, b, N, true, N, N, N, -1.0, 0.0, 0.0);
+    wg_axpby(Kb, N, al * al, MATb, N, -al, RHSb, N, false, 0.0, N, N);
+    wg_axpby(Db, N, 1.0, RHSb, N, -al, MATb, N, false, 0.0, N, N);
+    double *RWb = mp(AD_RWB);
+    wg_gemm(RWb, N, Kb, N, false, S, N2, false, N, N, N, 1.0, 0.0, 0.0);
+    wg_gemm(Sb, N, mp(AD_RW), N, false, Kb, N, false, N, N, N, 1.0, 1.0, 0.0);
+    wg_gemm(Cb, N, Db, N, false, S, N2, false, N, N, N, 1.0, 1.0, 0.0);
+    wg_gemm(Sb, N, C, N, true, Db, N, false, N, N, N, 1.0, 1.0, 0.0);
+    double *Mb = mp(AD_MB), *Tb = mp(AD_TB), *Rb = mp(AD_RB);
+    wg_axpby(Mb, N, 0.0, nullptr, N, -1.0, Db, N, true, 0.0, N, N);
+    wg_axpby(Tb, N, 0.5, RWb, N, 0.5, RWb, N, true, 0.0, N, N);
+    wg_axpby(Rb, N, 1.0, Tb, N, 0.0, nullptr, N, false, 0.0, N, N);
+    wg_gemm(Mb, N, C, N, false, Tb, N, false, N, N, N, -1.0, 1.0, 0.0);
+    wg_gemm(Cb, N, M, N2, false, Tb, N, false, N, N, N, -1.0, 1.0, 0.0);
+    // C = S^{-1} M
+    double *Z = mp(AD_Z);
+    wg_axpby(Z, N, 1.0, Cb, N, 0.0, nullptr, N, false, 0.0, N, N);
+    wg_axpby(mp(AD_SW), N, 1.0, S, N2, 0.0, nullptr, N, false, 0.0, N, N);
+    st = wg_gj(mp(AD_SW), N, Z, N, N, N, true, nsm, nsm + N, sval, sidx, ish);
+    if (st) {
+        if (threadIdx.x == 0) *status = st;
+        return;
+    }
+    wg_axpby(Mb, N, 1.0, Mb, N, 1.0, Z, N, false, 0.0, N, N);
+    wg_gemm(Sb, N, Z, N, false, C, N, true, N, N, N, -1.0, 1.0, 0.0);
+    // outputs: [Sb | Mb | Rb], each N x N column-major
+    wg_axpby(out, N, 1.0, Sb, N, 0.0, nullptr, N, false, 0.0, N, N);
+    wg_axpby(out + (size_t)N * N, N, 1.0, Mb, N, 0.0, nullptr, N, false, 0.0, N, N);
+    wg_axpby(out + (size_t)2 * N * N, N, 1.0, Rb, N, 0.0, nullptr, N, false, 0.0, N, N);
+}
+
 // Per-instance energy from the quadratic-form partials of the group's columns:
 // out[i] = {E_sigma = 1/2 w sum x.Hx, w sum x.x} over the columns [coff[i], coff[i+1]).
 __global__ __launch_bounds__(256) void k_instance_energy(const double *__restrict__ part, long qs,
@@ -337,6 +441,16 @@ hipError_t launch_noconv_check(const int *active, int n, int *err, hipStream_t s
 }
 
 size_t nn_pool_elems(int n) { return (size_t)BP_COUNT * n * n; }
+
+size_t nn_adjoint_pool_elems(int n) { return (size_t)AD_COUNT * n * n; }
+
+hipError_t launch_nn_adjoint(const double *G1, int n, double tau, const double *Xb,
+                             const double *Yb, double *pool, double *out, int *status,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_nn_adjoint, dim3(1), dim3(kWgThreads), sizeof(double) * 3 * (size_t)n, st,
+                       G1, n, tau, Xb, Yb, pool, out, status);
+    return hipGetLastError();
+}
 
 hipError_t launch_nn_predict(const NnJob *jobs, int njobs, int max_n, hipStream_t st) {
     if (njobs <= 0) return hipSuccess;

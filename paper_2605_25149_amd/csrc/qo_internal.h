@@ -201,6 +201,13 @@ hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st);
 // err: code 6 (PCG limit) for the first column still active
 hipError_t launch_noconv_check(const int *active, int n, int *err, hipStream_t st);
 
+// Reverse mode of the predictor algebra: (Xb, Yb) -> out = [Sb | Mb | Rb] (3 n x n blocks,
+// column-major); G1 the 2n x 2n Gram of [U P]; pool nn_adjoint_pool_elems(n) doubles.
+size_t nn_adjoint_pool_elems(int n);
+hipError_t launch_nn_adjoint(const double *G1, int n, double tau, const double *Xb,
+                             const double *Yb, double *pool, double *out, int *status,
+                             hipStream_t st);
+
 int pick_ppt(int pts);
 
 // ---- tall-skinny update (qo_tsgemm.hip) ----

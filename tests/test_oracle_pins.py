@@ -484,3 +484,66 @@ def test_fast_poisson_pcg_error_paths(oracle_mod):
     Bn[3, 1] = np.nan
     _, _, st, cst = prob.solve_fast_poisson(Bn, tol=1e-12)
     assert st == O.ORC_NONFINITE and cst[1] == O.ORC_NONFINITE and cst[0] == O.ORC_OK
+
+
+@pytest.mark.parametrize("loss", ["energy", "ritz_sum"])
+@pytest.mark.parametrize("K", [0, 1, 4])
+def test_steps_grad_finite_differences(oracle_mod, loss, K):
+    """Reading R16: the reverse-mode derivative of K steps + loss against central
+    differences of the forward map along random directions of V and of U_0 (FP64,
+    eps = 1e-5: truncation and rounding both below 1e-7 relative here)."""
+    O = oracle_mod
+    n = (12, 10)
+    V = inputs.harmonic(n, 100.0) + inputs.gaussian_wells(n, seed=3, depth=(1.0, 4.0))
+    U0 = inputs.random_block(120, 3, seed=2)
+    prob = O.Problem(2, n, V, sigma=0.3)
+    L, gV, gU = O.steps_loss_grad(prob, U0, 8.0, K, loss)
+    assert L == pytest.approx(O.steps_loss(prob, U0, 8.0, K, loss)[0], rel=1e-14)
+    rng = np.random.default_rng(11)
+    eps = 1e-5
+
+    def f(VV, UU):
+        return O.steps_loss(O.Problem(2, n, VV, sigma=0.3), UU, 8.0, K, loss)[0]
+
+    for _ in range(2):
+        dV = rng.standard_normal(120)
+        dU = rng.standard_normal((120, 3))
+        fdV = (f(V + eps * dV, U0) - f(V - eps * dV, U0)) / (2 * eps)
+        fdU = (f(V, U0 + eps * dU) - f(V, U0 - eps * dU)) / (2 * eps)
+        assert gV @ dV == pytest.approx(fdV, rel=1e-6, abs=1e-9 * abs(L))
+        assert np.sum(gU * dU) == pytest.approx(fdU, rel=1e-6, abs=1e-9 * abs(L))
+
+
+def test_steps_grad_ritz_sum_scale_invariance(oracle_mod):
+    """The sum of the Ritz values depends on span U only, so at K = 0 its derivative along
+    U_0 C vanishes for every C (a dropped term in the S^{-1} K S^{-1} part breaks this)."""
+    O = oracle_mod
+    n = (9, 8)
+    prob = O.Problem(2, n, inputs.harmonic(n, 60.0), sigma=0.0)
+    U0 = inputs.random_block(72, 4, seed=6)
+    _, _, gU = O.steps_loss_grad(prob, U0, 5.0, 0, "ritz_sum")
+    C = np.random.default_rng(2).standard_normal((4, 4))
+    assert abs(np.sum(gU * (U0 @ C))) <= 1e-12 * np.linalg.norm(gU) * np.linalg.norm(U0 @ C)
+
+
+def test_steps_grad_hellmann_feynman_limit(oracle_mod):
+    """Reading R16 at convergence: after 80 steps U_K spans the lowest eigenspace of H, so
+    the derivative of the sum of the Ritz values w.r.t. V is the Hellmann-Feynman
+    gradient sum_i w phi_i(x_j)^2 of lambda_1 + ... + lambda_N (eigenvectors of the dense
+    H from numpy's eigh, normalised in the grid inner product), the energy's is half of
+    it (E = 1/2 sum lambda_i at an orthonormal eigenbasis) and dL/dU_0 vanishes."""
+    O = oracle_mod
+    n = (12, 10)
+    V = inputs.harmonic(n, 100.0)
+    prob = O.Problem(2, n, V, sigma=0.0)
+    H = dense_H(2, n, (1.0, 1.0), 0.5, 0.0, V)
+    lam, phi = np.linalg.eigh(H)
+    hf = np.sum(phi[:, :3] ** 2, axis=1)  # w phi_w^2 with phi_w = phi / sqrt(w)
+    U0 = inputs.random_block(120, 3, seed=2)
+    L, gV, gU = O.steps_loss_grad(prob, U0, 10.0, 80, "ritz_sum")
+    assert L == pytest.approx(lam[:3].sum(), rel=1e-8)
+    assert np.max(np.abs(gV - hf)) <= 1e-6 * np.max(hf)
+    assert np.max(np.abs(gU)) <= 1e-6
+    L, gV, gU = O.steps_loss_grad(prob, U0, 10.0, 80, "energy")
+    assert L == pytest.approx(0.5 * lam[:3].sum(), rel=1e-8)
+    assert np.max(np.abs(gV - 0.5 * hf)) <= 1e-6 * np.max(hf)

@@ -9,26 +9,27 @@ from __future__ import annotations
 
 import torch
 
-from . import binding
-
 
 class QOStepsLoss(torch.autograd.Function):
-    """L = loss(Phi^K(U_0; V)).  V: (Ng,) float64 CUDA tensor; U0: (N, Ng) float64 CUDA
-    block.  solver: a binding.Solver of the same grid and N (precision fp64); it holds the
-    tape between forward and backward, so it serves one graph at a time."""
+    """L = loss(Phi^K(U_0; V)).  V: (Ng,) CUDA tensor; U0: (N, Ng) CUDA block; either may
+    be float32 (a trainable float32 potential, say): the steps and the adjoint run in FP64
+    and the gradients come back in each input's dtype.  solver: a binding.Solver of the
+    same grid and N (precision fp64); it holds the tape between forward and backward, so
+    it serves one graph at a time."""
 
     @staticmethod
     def forward(ctx, V, U0, solver, tau, K, loss):
-        solver.set_potential(V)
-        solver.set_state(U0.detach().contiguous())
+        solver.set_potential(V.detach().to(torch.float64))
+        solver.set_state(U0.detach().to(torch.float64).contiguous())
         L = solver.tape_forward(tau, K, loss)
         ctx.solver = solver
+        ctx.dtypes = (V.dtype, U0.dtype)
         return torch.tensor(L, dtype=torch.float64, device=V.device)
 
     @staticmethod
     def backward(ctx, gL):
         gV, gU = ctx.solver.tape_backward(float(gL))
-        return gV, gU, None, None, None, None
+        return gV.to(ctx.dtypes[0]), gU.to(ctx.dtypes[1]), None, None, None, None
 
 
 def steps_loss(V, U0, solver, tau, K, loss="energy"):

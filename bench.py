@@ -343,6 +343,48 @@ def run_batch(count, steps, log):
     return out
 
 
+def run_adjoint(K, log, n=64, N=32, tau=6.0):
+    """Reverse mode through K taped steps on the 64^3 Gaussian-well grid with N = 32 (the
+    Ritz-sum loss, gradients w.r.t. V and U_0): time of the taped forward, of the backward
+    and of K plain (warm-started) steps for scale."""
+    import torch
+
+    from paper_2605_25149_amd import binding, inputs
+
+    grid = (n, n, n)
+    V = inputs.gaussian_wells(grid, seed=0)
+    sigma = max(0.0, 1.0 - float(V.min()))
+    U0 = inputs.random_block(n ** 3, N, seed=1)
+    out = {"workload": f"{n}^3 wells, N={N}, K={K}, loss=ritz_sum, d/dV and d/dU0",
+           "precision": "f64", "precond": "fast_poisson", "pcg_tol": 1e-10}
+    with binding.Solver(3, grid, N, sigma=sigma, pcg_tol=1e-10, pcg_check=8,
+                        precond="fast_poisson") as s:
+        s.set_potential(V)
+        for rep in range(2):  # the first pass allocates the tape
+            s.set_state(U0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L = s.tape_forward(tau, K, "ritz_sum")
+            t1 = time.perf_counter()
+            gV, gU = s.tape_backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        s.set_state(U0)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        s.step(tau, K)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+    out.update(loss=L, forward_s=round(t1 - t0, 4), backward_s=round(t2 - t1, 4),
+               plain_steps_s=round(t4 - t3, 4),
+               backward_over_forward=round((t2 - t1) / (t1 - t0), 3),
+               grad_V_norm=float(torch.linalg.vector_norm(gV)),
+               grad_U0_norm=float(torch.linalg.vector_norm(gU)))
+    log(f"[adjoint] {out['workload']}: forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s, "
+        f"plain {K} steps {t4 - t3:.3f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -364,6 +406,8 @@ def main():
     ap.add_argument("--batch-instances", type=int, default=128,
                     help="also time a grouped batch of this many 2-D problems (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--adjoint-steps", type=int, default=50,
+                    help="K of the reverse-mode leg (64^3, N=32); 0 skips it")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
@@ -475,6 +519,8 @@ def main():
         out["jacobi_preconditioner"] = jac
     if args.batch_instances > 0:
         out["batch"] = run_batch(args.batch_instances, args.batch_steps, log)
+    if args.adjoint_steps > 0:
+        out["adjoint"] = run_adjoint(args.adjoint_steps, log)
     if not args.no_cpu_baseline:
         ref = res["fp64"] if "fp64" in res else rh
         colits = max(ref["profile"][k]["work"] for k in ("sweep2_f64", "sweep2_f32", "cg_f64", "cg_f32"))

@@ -213,8 +213,9 @@ qo_status qo_get_matrix(qo_handle h, int which, double *out);
  * number of iterations per solve: pcg_maxit (the largest value in the group) until
  * iteration counts have been observed, then the largest count of the previous step plus
  * a margin of 50% + 4, at most pcg_maxit; columns freeze on convergence, and a column
- * still above its tolerance after them makes the step fail with QO_ERR_PCG_NOCONV.  The solve of G U_n always starts from the previous G U_hat (zero
- * after qo_batch_set_state).  With use_graph != 0 each step is replayed from a HIP graph
+ * still above its tolerance after them makes the step fail with QO_ERR_PCG_NOCONV.
+ * The solve of G U_n always starts from the previous G U_hat (zero after
+ * qo_batch_set_state).  With use_graph != 0 each step is replayed from a HIP graph
  * captured at its first use (one per parity of the P / Q buffers); the stream given to
  * qo_batch_create must then not be the null stream (NULL creates a private stream).  At
  * creation the band height of the stencil kernels is chosen per group by timing the

@@ -305,7 +305,7 @@ def run_batch(count, steps, log):
             b.set_state(i, inputs.random_block(p["n"][0] * p["n"][1], p["N"], seed=1000 + i))
         out["tiles"] = {str(p["n"][0]): b.tile(i) for i, p in enumerate(probs)}
         for mode in ("eager", "graph"):
-            b.step(taus, use_graph=mode == "graph")
+            b.step(taus, nsteps=2, use_graph=mode == "graph")  # both P/Q parities
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             st = b.step(taus, nsteps=steps, use_graph=mode == "graph")

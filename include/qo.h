@@ -211,9 +211,11 @@ qo_status qo_get_matrix(qo_handle h, int which, double *out);
  * updates and N x N algebra once per group with one tile set or workgroup per instance.
  * Restrictions: precision QO_FP64, pcg_variant 0, N <= 1024.  The PCG runs a fixed
  * number of iterations per solve: pcg_maxit (the largest value in the group) until
- * iteration counts have been observed, then the largest count of the previous step plus
- * a margin of 50% + 4, at most pcg_maxit; columns freeze on convergence, and a column
- * still above its tolerance after them makes the step fail with QO_ERR_PCG_NOCONV.
+ * iteration counts have been observed, then the largest count of a previous step plus
+ * a margin of 50% + 4, at most pcg_maxit (kept while it stays within max(2, 25%) above
+ * the observed counts and max(4, 25%) above that target); columns freeze on convergence,
+ * and a column still above its tolerance after them makes the step fail with
+ * QO_ERR_PCG_NOCONV.
  * The solve of G U_n always starts from the previous G U_hat (zero after
  * qo_batch_set_state).  With use_graph != 0 each step is replayed from a HIP graph
  * captured at its first use (one per parity of the P / Q buffers); the stream given to

@@ -741,13 +741,18 @@ qo_status qo_batch_step(qo_batch b, const double *taus, int nsteps, int use_grap
                 }
         }
         // fixed iteration count for the next steps: the counts just observed with a margin
-        // of 50% + 4 (warm-started counts change slowly), at most pcg_maxit
+        // of 50% + 4 (warm-started counts change slowly), at most pcg_maxit.  The count
+        // in use is kept while it still leaves a margin of max(2, 25%) over the observed
+        // counts and exceeds the target by no more than max(4, 25%), so that small
+        // fluctuations do not invalidate the captured graphs.
         for (size_t k = 0; k < b->groups.size(); ++k) {
             auto &G = b->groups[k];
             int m = 0;
             for (int c = 0; c < G.C; ++c) m = std::max(m, std::max(hit0[k][c], hit1[k][c]));
             const int want = std::min(G.kmax, m + std::max(4, m / 2));
-            if (want != G.kuse) {
+            const bool keep = G.kuse >= std::min(G.kmax, m + std::max(2, m / 4)) &&
+                              G.kuse <= want + std::max(4, want / 4);
+            if (!keep && want != G.kuse) {
                 G.kuse = want;
                 b->gvalid[0] = b->gvalid[1] = false;
             }

@@ -283,63 +283,71 @@ def batch_tau(p, kappa=0.5):
     return 0.9 * (float(np.min(p["V"])) + p["sigma"] + kappa * mu)
 
 
-def run_batch(count, steps, log):
+def run_batch(count, steps, log, precisions=("fp64", "mixed")):
     """Aggregate throughput of `count` independent 2-D problems (sides 64..256, N 8..64)
     stepped as one grouped batch (eager launches and graph replay) against the same
-    problems stepped one single-instance handle at a time."""
+    problems stepped one single-instance handle at a time, per precision (mixed: FP32
+    PCG in FP64 refinement with FP64 Grams in the batch; the single-instance mixed path
+    also uses BF16 Grams)."""
     import torch
 
     from paper_2605_25149_amd import binding, inputs
 
     probs = inputs.batch_instances(count, 0)
     taus = [batch_tau(p) for p in probs]
-    cfgs = [dict(dim=2, n=p["n"], N=p["N"], sigma=p["sigma"], pcg_tol=1e-10, pcg_maxit=30,
-                 precond="fast_poisson") for p in probs]
     out = {"instances": count, "columns": sum(p["N"] for p in probs),
-           "sides": sorted(set(p["n"][0] for p in probs)), "precision": "f64",
-           "precond": "fast_poisson", "steps": steps}
-    b = binding.Batch(cfgs)
-    try:
-        for i, p in enumerate(probs):
-            b.set_potential(i, p["V"])
-            b.set_state(i, inputs.random_block(p["n"][0] * p["n"][1], p["N"], seed=1000 + i))
-        out["tiles"] = {str(p["n"][0]): b.tile(i) for i, p in enumerate(probs)}
-        for mode in ("eager", "graph"):
-            b.step(taus, nsteps=2, use_graph=mode == "graph")  # both P/Q parities
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = b.step(taus, nsteps=steps, use_graph=mode == "graph")
-            dt = time.perf_counter() - t0
-            out[f"{mode}_instance_steps_per_s"] = round(count * steps / dt, 2)
-            out["max_pcg_iters"] = max(max(x["pcg_iters"]) for x in st)
-            log(f"[batch {mode}] {count} instances, {steps} steps: {dt / steps * 1e3:.1f} ms/step")
-    finally:
-        b.close()
-    sol = []
-    try:
-        for i, p in enumerate(probs):
-            s = binding.Solver(2, p["n"], p["N"], sigma=p["sigma"], pcg_tol=1e-10, pcg_check=1,
-                               precond="fast_poisson")
-            s.set_potential(p["V"])
-            s.set_state(binding.as_block(inputs.random_block(p["n"][0] * p["n"][1], p["N"],
-                                                             seed=1000 + i)))
-            sol.append(s)
-        for i, s in enumerate(sol):
-            s.step(taus[i])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
+           "sides": sorted(set(p["n"][0] for p in probs)), "precond": "fast_poisson",
+           "pcg_tol": 1e-10, "steps": steps}
+    for prec in precisions:
+        res = {}
+        cfgs = [dict(dim=2, n=p["n"], N=p["N"], sigma=p["sigma"], pcg_tol=1e-10, pcg_maxit=30,
+                     precond="fast_poisson", precision=prec) for p in probs]
+        b = binding.Batch(cfgs)
+        try:
+            for i, p in enumerate(probs):
+                b.set_potential(i, p["V"])
+                b.set_state(i, inputs.random_block(p["n"][0] * p["n"][1], p["N"], seed=1000 + i))
+            out["tiles"] = {str(p["n"][0]): b.tile(i) for i, p in enumerate(probs)}
+            for mode in ("eager", "graph"):
+                b.step(taus, nsteps=2, use_graph=mode == "graph")  # both P/Q parities
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = b.step(taus, nsteps=steps, use_graph=mode == "graph")
+                dt = time.perf_counter() - t0
+                res[f"{mode}_instance_steps_per_s"] = round(count * steps / dt, 2)
+                res["max_pcg_iters"] = max(max(x["pcg_iters"]) for x in st)
+                res["max_refine_rounds"] = max(max(x["refine_rounds"]) for x in st)
+                log(f"[batch {prec} {mode}] {count} instances, {steps} steps: "
+                    f"{dt / steps * 1e3:.1f} ms/step")
+        finally:
+            b.close()
+        sol = []
+        try:
+            for i, p in enumerate(probs):
+                s = binding.Solver(2, p["n"], p["N"], sigma=p["sigma"], pcg_tol=1e-10,
+                                   pcg_check=1, precond="fast_poisson", precision=prec)
+                s.set_potential(p["V"])
+                s.set_state(binding.as_block(inputs.random_block(p["n"][0] * p["n"][1], p["N"],
+                                                                 seed=1000 + i)))
+                sol.append(s)
             for i, s in enumerate(sol):
                 s.step(taus[i])
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        out["sequential_instance_steps_per_s"] = round(count * steps / dt, 2)
-        log(f"[batch sequential] {count} single-instance handles: {dt / steps * 1e3:.1f} ms/round")
-    finally:
-        for s in sol:
-            s.close()
-    out["speedup_vs_sequential"] = round(out["eager_instance_steps_per_s"] /
-                                         out["sequential_instance_steps_per_s"], 3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                for i, s in enumerate(sol):
+                    s.step(taus[i])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res["sequential_instance_steps_per_s"] = round(count * steps / dt, 2)
+            log(f"[batch {prec} sequential] {count} single-instance handles: "
+                f"{dt / steps * 1e3:.1f} ms/round")
+        finally:
+            for s in sol:
+                s.close()
+        res["speedup_vs_sequential"] = round(res["eager_instance_steps_per_s"] /
+                                             res["sequential_instance_steps_per_s"], 3)
+        out[prec] = res
     return out
 
 
@@ -406,6 +414,9 @@ def main():
     ap.add_argument("--batch-instances", type=int, default=128,
                     help="also time a grouped batch of this many 2-D problems (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-precisions", default="fp64,mixed")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batch leg and print its JSON (profiling aid)")
     ap.add_argument("--adjoint-steps", type=int, default=50,
                     help="K of the reverse-mode leg (64^3, N=32); 0 skips it")
     ap.add_argument("--quiet", action="store_true")
@@ -429,6 +440,11 @@ def main():
 
     binding.load_library()
     torch.cuda.set_device(0)
+    if args.batch_only:
+        print(json.dumps({"batch": run_batch(args.batch_instances, args.batch_steps, log,
+                                             tuple(args.batch_precisions.split(",")))}),
+              flush=True)
+        return
     n = (args.n,) * 3
     N = args.N
     ng = int(np.prod(n))
@@ -518,7 +534,8 @@ def main():
                          "pcg_iters_per_step": [st["pcg_iters"] for st in r["stats"]]}
         out["jacobi_preconditioner"] = jac
     if args.batch_instances > 0:
-        out["batch"] = run_batch(args.batch_instances, args.batch_steps, log)
+        out["batch"] = run_batch(args.batch_instances, args.batch_steps, log,
+                                 tuple(args.batch_precisions.split(",")))
     if args.adjoint_steps > 0:
         out["adjoint"] = run_adjoint(args.adjoint_steps, log)
     if not args.no_cpu_baseline:

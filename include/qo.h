@@ -209,13 +209,22 @@ qo_status qo_get_matrix(qo_handle h, int which, double *out);
  * n, L, kinetic, precond) form a group: the grid-sized kernels (stencil, PCG sweeps,
  * preconditioner passes, energy) run once over all columns of a group, the Grams, block
  * updates and N x N algebra once per group with one tile set or workgroup per instance.
- * Restrictions: precision QO_FP64, pcg_variant 0, N <= 1024.  The PCG runs a fixed
+ * Restrictions: pcg_variant 0, N <= 1024; instances of one group share precision (and
+ * refine_inner_tol).  The PCG runs a fixed
  * number of iterations per solve: pcg_maxit (the largest value in the group) until
  * iteration counts have been observed, then the largest count of a previous step plus
  * a margin of 50% + 4, at most pcg_maxit (kept while it stays within max(2, 25%) above
  * the observed counts and max(4, 25%) above that target); columns freeze on convergence,
  * and a column still above its tolerance after them makes the step fail with
  * QO_ERR_PCG_NOCONV.
+ * With precision QO_MIXED a solve is a fixed number of restarted refinement rounds
+ * (six until counts have been observed, then the most any column used plus one, at
+ * most 30): FP64 residual, FP32 PCG with a fixed iteration count per round (pcg_maxit
+ * at first, then the round's largest observed count plus max(2, 25%)) on the columns
+ * still above tolerance (inner tolerance as the single-instance mixed path), FP64
+ * update; the FP64 residual after the last round decides convergence.  Grams, N x N
+ * algebra and energy stay FP64 (BF16 Grams are single-instance only); pcg_iters then
+ * counts FP32 iterations summed over the rounds and refine_rounds the rounds used.
  * The solve of G U_n always starts from the previous G U_hat (zero after
  * qo_batch_set_state).  With use_graph != 0 each step is replayed from a HIP graph
  * captured at its first use (one per parity of the P / Q buffers); the stream given to

@@ -389,8 +389,11 @@ __global__ __launch_bounds__(256) void k_instance_energy(const double *__restric
     }
 }
 
+// V + sigma and 1 / diag(H_sigma); with vs32 also their FP32 copies (the FP32 stencil
+// forms its diagonal from the FP32 c0 and V + sigma, so 1/diag is taken from those).
 __global__ void k_batch_potential(const double *__restrict__ V, long ng, double sigma, double c0,
                                   double *__restrict__ vs, double *__restrict__ dinv,
+                                  float *__restrict__ vs32, float *__restrict__ dinv32,
                                   int *__restrict__ status) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ng;
          i += (long)gridDim.x * blockDim.x) {
@@ -400,6 +403,50 @@ __global__ void k_batch_potential(const double *__restrict__ V, long ng, double 
         else if (!(d > 0.0)) atomicMax(status, 5);
         vs[i] = v;
         dinv[i] = 1.0 / d;
+        if (vs32) {
+            vs32[i] = (float)v;
+            dinv32[i] = (float)(1.0 / ((double)(float)c0 + (double)(float)v));
+        }
+    }
+}
+
+// Bookkeeping of one FP32 refinement round (one workgroup): per column total += its and
+// rounds += mask (columns outside the mask ran no iteration); rstat[0] = the round's
+// largest iteration count, rstat[1] = the number of columns that took part.
+__global__ __launch_bounds__(256) void k_its_accum(const int *__restrict__ its,
+                                                   const int *__restrict__ mask, int n,
+                                                   int *__restrict__ total,
+                                                   int *__restrict__ rounds,
+                                                   int *__restrict__ rstat) {
+    __shared__ int smax[4], scnt[4];
+    int mk = 0, cnt = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int m = mask[i] ? 1 : 0;
+        const int k = m ? its[i] : 0;
+        total[i] += k;
+        rounds[i] += m;
+        mk = k > mk ? k : mk;
+        cnt += m;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(mk, off, 64);
+        mk = o > mk ? o : mk;
+        cnt += __shfl_xor(cnt, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        smax[threadIdx.x >> 6] = mk;
+        scnt[threadIdx.x >> 6] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = 0, c = 0;
+        for (int w = 0; w < 4; ++w) {
+            a = smax[w] > a ? smax[w] : a;
+            c += scnt[w];
+        }
+        rstat[0] = a;
+        rstat[1] = c;
     }
 }
 
@@ -417,12 +464,19 @@ __global__ void k_noconv_check(const int *__restrict__ active, int n, int *__res
 
 }  // namespace
 
+hipError_t launch_its_accum(const int *its, const int *mask, int n, int *total, int *rounds,
+                            int *rstat, hipStream_t st) {
+    hipLaunchKernelGGL(k_its_accum, dim3(1), dim3(256), 0, st, its, mask, n, total, rounds, rstat);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_potential(const double *V, long ng, double sigma, double c0, double *vs,
-                                  double *dinv, int *status, hipStream_t st) {
+                                  double *dinv, float *vs32, float *dinv32, int *status,
+                                  hipStream_t st) {
     long blocks = (ng + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_batch_potential, dim3((unsigned)blocks), dim3(256), 0, st, V, ng, sigma,
-                       c0, vs, dinv, status);
+                       c0, vs, dinv, vs32, dinv32, status);
     return hipGetLastError();
 }
 

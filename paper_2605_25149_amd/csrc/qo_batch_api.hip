@@ -10,6 +10,11 @@
 // converged columns frozen on the device, so a step needs no host synchronisation and is
 // captured once per parity of the P/Q ping-pong into a HIP graph that later steps
 // replay.  Band heights are chosen per group by timing the stencil on the device.
+//
+// In mixed precision a solve is a fixed number of restarted refinement rounds: the FP64
+// residual, a per-column mask and inner tolerance, a fixed-count FP32 PCG on the
+// residual (frozen columns skip their work) and the FP64 update; a final FP64 residual
+// decides convergence.  The Grams, the N x N algebra and the energy stay in FP64.
 #include "qo.h"
 #include "qo_internal.h"
 
@@ -48,6 +53,19 @@ struct qo_batch_ctx {
         long ng = 0, ld = 0, qs = 0;
         int C = 0, kmax = 0, ninst = 0, max_n = 0, max_gram_grid = 0, ty = 0;
         int kuse = 0;  // iterations per solve in use: kmax until counts are observed
+        // mixed precision: FP32 PCG inside restarted FP64 refinement rounds
+        bool mixed = false;
+        double inner_tol = 1e-5;
+        int ruse = 0;  // refinement rounds per solve in use
+        std::vector<int> kr;  // FP32 iterations of each round in use
+        float *vs32 = nullptr, *dinv32 = nullptr, *r32 = nullptr, *d32 = nullptr,
+              *rr32 = nullptr, *pa32 = nullptr, *pb32 = nullptr, *z32 = nullptr;
+        double *colsums = nullptr, *cin = nullptr;
+        int *mask = nullptr, *nact = nullptr, *its32 = nullptr;
+        // per solve: per column the FP32 iterations summed over the rounds and the rounds
+        // taken part in; per round the largest count and the columns taking part
+        int *itot[2] = {nullptr, nullptr}, *irounds[2] = {nullptr, nullptr},
+            *rstat[2] = {nullptr, nullptr};
         double w = 1.0;
         std::vector<int> members;
         double *U = nullptr, *Uh = nullptr, *PQ[2] = {nullptr, nullptr}, *r = nullptr,
@@ -63,6 +81,7 @@ struct qo_batch_ctx {
         TsJob *tjob[2][3] = {};
         NnJob *njob = nullptr;
         std::vector<NnJob> h_njob;
+        hipStream_t st = nullptr;  // stream of the group's step work
     };
     std::vector<Group> groups;
     std::vector<void *> allocs;
@@ -70,10 +89,15 @@ struct qo_batch_ctx {
     int *err_dev = nullptr;  // sticky PCG error flag pair of the batch (code, first column)
     int cur = 0;             // parity of the P/Q ping-pong (common to all groups)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    std::vector<hipStream_t> side;  // streams of groups 1.. (default priority)
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
     bool gvalid[2] = {false, false};
 };
 
 namespace {
+
+constexpr int kMaxRounds = 30;  // refinement rounds per mixed-precision solve, at most
 
 qo_status bfail(qo_batch_ctx *b, qo_status s, const char *fmt, ...) {
     if (b) {
@@ -116,6 +140,9 @@ qo_status balloc(qo_batch_ctx *b, T **p, size_t n) {
 
 bool same_grid(const qo_config &a, const qo_config &c) {
     if (a.dim != c.dim || a.kinetic != c.kinetic || a.precond != c.precond) return false;
+    if (a.precision != c.precision ||
+        (a.precision == QO_MIXED && a.refine_inner_tol != c.refine_inner_tol))
+        return false;
     for (int k = 0; k < a.dim; ++k)
         if (a.n[k] != c.n[k] || a.L[k] != c.L[k]) return false;
     return true;
@@ -193,7 +220,7 @@ void dst_tables_host(const qo_config &cf, const DstPlan &dp, std::vector<float> 
 
 qo_status group_pcg(qo_batch_ctx *b, qo_batch_ctx::Group &G, const double *B, double *X,
                     int which) {
-    hipStream_t st = b->st;
+    hipStream_t st = G.st;
     PcgState s = G.ps;
     s.its = G.its[which];
     s.coltol = G.coltol;
@@ -223,18 +250,80 @@ qo_status group_pcg(qo_batch_ctx *b, qo_batch_ctx::Group &G, const double *B, do
     return QO_OK;
 }
 
-// One step of every group, all on the batch stream (no host synchronisation).
+// Mixed-precision solve X = G B (X holds the starting guess): ruse restarted rounds of
+// FP64 residual -> FP32 PCG with kuse iterations on the columns still above their
+// tolerance -> X += d, then the final FP64 residual test.  which selects the solve's
+// bookkeeping arrays (per column the FP32 iterations summed over the rounds and the
+// rounds in which it took part; per round the largest count and the columns taking part).
+qo_status group_solve_mixed(qo_batch_ctx *b, qo_batch_ctx::Group &G, const double *B,
+                            double *X, int which) {
+    hipStream_t st = G.st;
+    const Grid &g = G.g;
+    const int tiles = g.tiles();
+    PcgState s = G.ps;
+    s.its = G.its32;
+    s.coltol = G.cin;
+    s.err = b->err_dev;
+    BHIP(b, launch_fill_int(G.itot[which], G.C, 0, st));
+    BHIP(b, launch_fill_int(G.irounds[which], G.C, 0, st));
+    BHIP(b, launch_fill_int(G.rstat[which], 2 * kMaxRounds, 0, st));
+    float *pbuf[2] = {G.pa32, G.pb32};
+    for (int round = 0; round <= G.ruse; ++round) {
+        BHIP(b, launch_resid(g, G.vs, B, X, G.ld, G.r32, G.ld, G.C, nullptr, G.part, st));
+        BHIP(b, launch_colsum(G.part + G.qs, tiles, G.C, 2, G.qs, G.colsums, st));
+        BHIP(b, launch_refine_mask(G.colsums, G.C, 0.0, G.inner_tol, G.mask, G.cin, G.nact,
+                                   b->err_dev, st, G.coltol));
+        if (round == G.ruse) break;
+        const int K = G.kr[round];
+        BHIP(b, launch_fill_int(G.its32, G.C, 0, st));
+        BHIP(b, launch_pcg_init<float>(g, G.vs32, G.dinv32, G.r32, G.d32, G.rr32, G.ld, G.C, 0,
+                                       s.part, st));
+        for (int k = 0; k <= K; ++k) {
+            if (G.dst) {
+                BHIP(b, launch_pc_prep(k, G.C, G.mask, s, G.qs, tiles, 0.0, G.ng, G.pcs, st));
+                BHIP(b, launch_dst_fwd<float>(G.dp, G.rr32, G.ld, G.C, G.t1, G.pcs, st));
+                BHIP(b, launch_dst_pencil(G.dp, G.t1, G.t2, G.ld, G.C, G.pcs, st));
+                BHIP(b, launch_dst_inv<float>(G.dp, G.t2, G.rr32, G.z32, G.ld, G.C, G.pcs, G.rzp,
+                                              st));
+            }
+            BHIP(b, launch_pcg_sweep1<float>(g, G.vs32, G.dinv32, G.rr32, pbuf[(k + 1) & 1],
+                                             pbuf[k & 1], G.ld, G.C, k, 0.0, G.mask, s, st,
+                                             G.dst ? G.z32 : nullptr, G.rzp, G.dp.nslab));
+            if (k == K) break;
+            BHIP(b, launch_pcg_sweep2<float>(g, G.vs32, G.dinv32, pbuf[k & 1], G.d32, G.rr32,
+                                             G.ld, G.C, k, s, st, !G.dst));
+        }
+        BHIP(b, launch_its_accum(G.its32, G.mask, G.C, G.itot[which], G.irounds[which],
+                                 G.rstat[which] + 2 * round, st));
+        BHIP(b, launch_refine_axpy(X, G.ld, G.d32, G.ld, G.ng, G.C, G.mask, 0, st));
+    }
+    // a column still above its tolerance after the last round did not converge
+    BHIP(b, launch_noconv_check(G.mask, G.C, b->err_dev, st));
+    return QO_OK;
+}
+
+// One step of every group without host synchronisation.  Groups are independent: the
+// first runs on the batch stream, every other one on a stream of its own that forks from
+// the batch stream and joins it again at the end, so the small groups' launches overlap
+// the large ones (captured graphs keep this as parallel branches).
 qo_status batch_step_enqueue(qo_batch_ctx *b, int par) {
-    hipStream_t st = b->st;
+    const size_t ng = b->groups.size();
+    if (ng > 1) {
+        BHIP(b, hipEventRecord(b->ev_fork, b->st));
+        for (size_t k = 1; k < ng; ++k) BHIP(b, hipStreamWaitEvent(b->groups[k].st, b->ev_fork, 0));
+    }
     for (auto &G : b->groups) {
+        hipStream_t st = G.st;
         double *P = G.PQ[par], *Q = G.PQ[par ^ 1];
-        BQO(group_pcg(b, G, G.U, P, 0));
+        if (G.mixed) BQO(group_solve_mixed(b, G, G.U, P, 0));
+        else BQO(group_pcg(b, G, G.U, P, 0));
         BHIP(b, launch_gram_f64_batch(G.gjob[par][0], G.ninst, G.max_gram_grid, G.ld, G.ng, G.w,
                                       st));
         BHIP(b, launch_nn_predict(G.njob, G.ninst, G.max_n, st));
         BHIP(b, launch_tsgemm_batch(G.tjob[par][0], G.ninst, G.max_n, G.ld, G.ng, st));
         BHIP(b, launch_tsgemm_batch(G.tjob[par][1], G.ninst, G.max_n, G.ld, G.ng, st));
-        BQO(group_pcg(b, G, G.Uh, Q, 1));
+        if (G.mixed) BQO(group_solve_mixed(b, G, G.Uh, Q, 1));
+        else BQO(group_pcg(b, G, G.Uh, Q, 1));
         BHIP(b, launch_gram_f64_batch(G.gjob[par][1], G.ninst, G.max_gram_grid, G.ld, G.ng, G.w,
                                       st));
         BHIP(b, launch_nn_correct(G.njob, G.ninst, st));
@@ -242,6 +331,10 @@ qo_status batch_step_enqueue(qo_batch_ctx *b, int par) {
         BHIP(b, launch_quad(G.g, G.vs, G.U, G.ld, G.C, G.part, st));
         BHIP(b, launch_instance_energy(G.part, G.qs, G.g.tiles(), G.coff, G.ninst, G.w, G.energy,
                                        st));
+    }
+    for (size_t k = 1; k < ng; ++k) {
+        BHIP(b, hipEventRecord(b->ev_join[k], b->groups[k].st));
+        BHIP(b, hipStreamWaitEvent(b->st, b->ev_join[k], 0));
     }
     return QO_OK;
 }
@@ -270,6 +363,10 @@ qo_status build_group(qo_batch_ctx *b, qo_batch_ctx::Group &G) {
     coff[G.ninst] = G.C;
     G.kmax = kmax;
     G.kuse = kmax;
+    G.mixed = cf.precision == QO_MIXED;
+    G.inner_tol = cf.refine_inner_tol;
+    G.ruse = 6;
+    G.kr.assign(kMaxRounds, kmax);
     G.ng = (long)cf.n[0] * cf.n[1] * (cf.dim == 3 ? cf.n[2] : 1);
     G.ld = (G.ng + 63) / 64 * 64;
     const size_t blk = (size_t)G.ld * G.C;
@@ -307,6 +404,26 @@ qo_status build_group(qo_batch_ctx *b, qo_batch_ctx::Group &G) {
     BQO(A(&G.scal, (size_t)3 * G.ninst));
     BQO(A(&G.nstatus, (size_t)G.ninst));
     G.ps.part = G.part;
+    if (G.mixed) {
+        BQO(A(&G.vs32, (size_t)G.ninst * G.ng));
+        BQO(A(&G.dinv32, (size_t)G.ninst * G.ng));
+        BQO(A(&G.r32, blk));
+        BQO(A(&G.d32, blk));
+        BQO(A(&G.rr32, blk));
+        BQO(A(&G.pa32, blk));
+        BQO(A(&G.pb32, blk));
+        if (cf.precond == 1) BQO(A(&G.z32, blk));
+        BQO(A(&G.colsums, (size_t)2 * G.C));
+        BQO(A(&G.cin, (size_t)G.C));
+        BQO(A(&G.mask, (size_t)G.C));
+        BQO(A(&G.nact, 1));
+        BQO(A(&G.its32, (size_t)G.C));
+        for (int k = 0; k < 2; ++k) {
+            BQO(A(&G.itot[k], (size_t)G.C));
+            BQO(A(&G.irounds[k], (size_t)G.C));
+            BQO(A(&G.rstat[k], (size_t)2 * kMaxRounds));
+        }
+    }
     BHIP(b, hipMemcpyAsync(G.cinst, cinst.data(), sizeof(int) * G.C, hipMemcpyHostToDevice, b->st));
     BHIP(b, hipMemcpyAsync(G.coff, coff.data(), sizeof(int) * (G.ninst + 1), hipMemcpyHostToDevice,
                            b->st));
@@ -486,7 +603,12 @@ qo_status qo_batch_destroy(qo_batch b) {
     if (b->st) (void)hipStreamSynchronize(b->st);
     for (int p = 0; p < 2; ++p)
         if (b->gexec[p]) (void)hipGraphExecDestroy(b->gexec[p]);
+    for (hipStream_t s : b->side) (void)hipStreamSynchronize(s);
     for (void *p : b->allocs) (void)hipFree(p);
+    for (hipEvent_t e : b->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
     if (b->own_stream && b->st) (void)hipStreamDestroy(b->st);
     delete b;
     return QO_OK;
@@ -507,7 +629,11 @@ qo_status qo_batch_create(const qo_config *cfgs, int count, void *hip_stream, qo
         if (c.n[0] > 1024 || c.N < 1 || c.N >= ng || c.N > 1024) return QO_ERR_ARG;
         if (!(c.kinetic > 0.0) || !std::isfinite(c.sigma)) return QO_ERR_ARG;
         if (!(c.pcg_tol > 0.0) || c.pcg_maxit < 1 || c.pcg_maxit > 100000) return QO_ERR_ARG;
-        if (c.precision != QO_FP64 || c.pcg_variant != 0) return QO_ERR_ARG;
+        if ((c.precision != QO_FP64 && c.precision != QO_MIXED) || c.pcg_variant != 0)
+            return QO_ERR_ARG;
+        if (c.precision == QO_MIXED &&
+            !(c.refine_inner_tol > 0.0 && c.refine_inner_tol < 1.0))
+            return QO_ERR_ARG;
         if (c.precond != 0 && c.precond != 1) return QO_ERR_ARG;
         if (c.precond == 1 && dst_plan_check(c.dim, c.n)) return QO_ERR_ARG;
     }
@@ -539,6 +665,25 @@ qo_status qo_batch_create(const qo_config *cfgs, int count, void *hip_stream, qo
         b->inst[i].group = gi;
     }
     qo_status s = balloc(b, &b->err_dev, 2);
+    b->ev_join.assign(b->groups.size(), nullptr);
+    if (s == QO_OK && b->groups.size() > 1 &&
+        hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess)
+        s = QO_ERR_DEVICE;
+    for (size_t k = 0; k < b->groups.size() && s == QO_OK; ++k) {
+        if (k == 0) {
+            b->groups[k].st = b->st;
+            continue;
+        }
+        hipStream_t hs = nullptr;
+        if (hipStreamCreate(&hs) != hipSuccess) {
+            s = QO_ERR_DEVICE;
+            break;
+        }
+        b->side.push_back(hs);
+        b->groups[k].st = hs;
+        if (hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming) != hipSuccess)
+            s = QO_ERR_DEVICE;
+    }
     for (auto &G : b->groups)
         if (s == QO_OK) s = build_group(b, G);
     for (auto &G : b->groups)
@@ -566,7 +711,10 @@ qo_status qo_batch_set_potential(qo_batch b, int i, const double *V, int on_devi
     }
     double *vs = G.vs + (size_t)I.local * G.ng, *dinv = G.dinv + (size_t)I.local * G.ng;
     BHIP(b, hipMemsetAsync(G.nstatus + I.local, 0, sizeof(int), st));
-    BHIP(b, launch_batch_potential(src, G.ng, c.sigma, G.g.c0, vs, dinv, G.nstatus + I.local, st));
+    float *vs32 = G.mixed ? G.vs32 + (size_t)I.local * G.ng : nullptr;
+    float *dinv32 = G.mixed ? G.dinv32 + (size_t)I.local * G.ng : nullptr;
+    BHIP(b, launch_batch_potential(src, G.ng, c.sigma, G.g.c0, vs, dinv, vs32, dinv32,
+                                   G.nstatus + I.local, st));
     int bad = 0;
     BHIP(b, hipMemcpyAsync(&bad, G.nstatus + I.local, sizeof(int), hipMemcpyDeviceToHost, st));
     if (G.dst) BHIP(b, launch_sum(vs, G.ng, G.dsum, st));
@@ -702,8 +850,11 @@ qo_status qo_batch_step(qo_batch b, const double *taus, int nsteps, int use_grap
         int herr[2];
         BHIP(b, hipMemcpyAsync(herr, b->err_dev, sizeof herr, hipMemcpyDeviceToHost, st));
         std::vector<std::vector<double>> hen(b->groups.size()), hsc(b->groups.size());
+        // per column and solve: iterations (FP32 ones summed over the rounds in mixed
+        // precision), and in mixed precision the per-round maximum and the rounds used
         std::vector<std::vector<int>> hst(b->groups.size()), hit0(b->groups.size()),
-            hit1(b->groups.size());
+            hit1(b->groups.size()), hrs0(b->groups.size()), hrs1(b->groups.size()),
+            hro0(b->groups.size()), hro1(b->groups.size());
         for (size_t k = 0; k < b->groups.size(); ++k) {
             auto &G = b->groups[k];
             hen[k].resize(2 * G.ninst);
@@ -717,10 +868,22 @@ qo_status qo_batch_step(qo_batch b, const double *taus, int nsteps, int use_grap
                                    hipMemcpyDeviceToHost, st));
             BHIP(b, hipMemcpyAsync(hst[k].data(), G.nstatus, sizeof(int) * G.ninst,
                                    hipMemcpyDeviceToHost, st));
-            BHIP(b, hipMemcpyAsync(hit0[k].data(), G.its[0], sizeof(int) * G.C,
-                                   hipMemcpyDeviceToHost, st));
-            BHIP(b, hipMemcpyAsync(hit1[k].data(), G.its[1], sizeof(int) * G.C,
-                                   hipMemcpyDeviceToHost, st));
+            BHIP(b, hipMemcpyAsync(hit0[k].data(), G.mixed ? G.itot[0] : G.its[0],
+                                   sizeof(int) * G.C, hipMemcpyDeviceToHost, st));
+            BHIP(b, hipMemcpyAsync(hit1[k].data(), G.mixed ? G.itot[1] : G.its[1],
+                                   sizeof(int) * G.C, hipMemcpyDeviceToHost, st));
+            if (G.mixed) {
+                for (auto *v : {&hro0[k], &hro1[k]}) v->resize(G.C);
+                for (auto *v : {&hrs0[k], &hrs1[k]}) v->resize(2 * kMaxRounds);
+                BHIP(b, hipMemcpyAsync(hrs0[k].data(), G.rstat[0], sizeof(int) * 2 * kMaxRounds,
+                                       hipMemcpyDeviceToHost, st));
+                BHIP(b, hipMemcpyAsync(hrs1[k].data(), G.rstat[1], sizeof(int) * 2 * kMaxRounds,
+                                       hipMemcpyDeviceToHost, st));
+                BHIP(b, hipMemcpyAsync(hro0[k].data(), G.irounds[0], sizeof(int) * G.C,
+                                       hipMemcpyDeviceToHost, st));
+                BHIP(b, hipMemcpyAsync(hro1[k].data(), G.irounds[1], sizeof(int) * G.C,
+                                       hipMemcpyDeviceToHost, st));
+            }
         }
         BHIP(b, hipStreamSynchronize(st));
         // PCG failures first: an unconverged solve can also spoil the N x N algebra
@@ -747,14 +910,45 @@ qo_status qo_batch_step(qo_batch b, const double *taus, int nsteps, int use_grap
         // fluctuations do not invalidate the captured graphs.
         for (size_t k = 0; k < b->groups.size(); ++k) {
             auto &G = b->groups[k];
-            int m = 0;
-            for (int c = 0; c < G.C; ++c) m = std::max(m, std::max(hit0[k][c], hit1[k][c]));
-            const int want = std::min(G.kmax, m + std::max(4, m / 2));
-            const bool keep = G.kuse >= std::min(G.kmax, m + std::max(2, m / 4)) &&
-                              G.kuse <= want + std::max(4, want / 4);
-            if (!keep && want != G.kuse) {
-                G.kuse = want;
-                b->gvalid[0] = b->gvalid[1] = false;
+            if (!G.mixed) {
+                int m = 0;
+                for (int c = 0; c < G.C; ++c) m = std::max(m, std::max(hit0[k][c], hit1[k][c]));
+                const int want = std::min(G.kmax, m + std::max(4, m / 2));
+                const bool keep = G.kuse >= std::min(G.kmax, m + std::max(2, m / 4)) &&
+                                  G.kuse <= want + std::max(4, want / 4);
+                if (!keep && want != G.kuse) {
+                    G.kuse = want;
+                    b->gvalid[0] = b->gvalid[1] = false;
+                }
+            } else {
+                // rounds: the most any column used plus one; iterations of a used round r:
+                // its largest count plus max(2, 25%) (a column cut short continues in the
+                // next round, so the margin only saves rounds), kept while within 2 of
+                // that; rounds not used get the last used round's count
+                bool changed = false;
+                int mr = 0;
+                for (int r = 0; r < G.ruse; ++r)
+                    if (hrs0[k][2 * r + 1] > 0 || hrs1[k][2 * r + 1] > 0) mr = r + 1;
+                const int rw = std::min(kMaxRounds, mr + 1);
+                if (G.ruse < rw || G.ruse > rw + 1) {
+                    G.ruse = rw;
+                    changed = true;
+                }
+                for (int r = 0; r < kMaxRounds; ++r) {
+                    int want;
+                    if (r < mr) {
+                        const int m = std::max(hrs0[k][2 * r], hrs1[k][2 * r]);
+                        want = std::min(G.kmax, m + std::max(2, m / 4));
+                        if (G.kr[r] >= std::min(G.kmax, m + 1) && G.kr[r] <= want + 2) continue;
+                    } else {
+                        want = mr > 0 ? G.kr[mr - 1] : G.kmax;
+                    }
+                    if (G.kr[r] != want) {
+                        G.kr[r] = want;
+                        if (r < G.ruse) changed = true;
+                    }
+                }
+                if (changed) b->gvalid[0] = b->gvalid[1] = false;
             }
         }
         for (size_t k = 0; k < b->groups.size(); ++k) {
@@ -779,6 +973,15 @@ qo_status qo_batch_step(qo_batch b, const double *taus, int nsteps, int use_grap
                     o.pcg_iters[0] = m0;
                     o.pcg_iters[1] = m1;
                     o.refine_rounds[0] = o.refine_rounds[1] = 1;
+                    if (G.mixed) {
+                        int r0 = 0, r1 = 0;
+                        for (int c = I.col0; c < I.col0 + I.N; ++c) {
+                            r0 = std::max(r0, hro0[k][c]);
+                            r1 = std::max(r1, hro1[k][c]);
+                        }
+                        o.refine_rounds[0] = r0;
+                        o.refine_rounds[1] = r1;
+                    }
                     o.energy_rose = (I.have_Es && Es > I.last_Es) ? 1 : 0;
                     o.step_index = (int)I.nstep;
                 }

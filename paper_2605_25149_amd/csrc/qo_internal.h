@@ -144,10 +144,11 @@ hipError_t launch_rel_finalize(const double *outer, int tiles, int ncols, const 
                                int *active, double *rref, double *bb64, double tol, int init,
                                int *nactive, int *err, hipStream_t st);
 // mask[c] = (sqrt(rr[c]) > tol * sqrt(bb[c])); counts into *nactive (device int);
-// coltol[c] (may be null): inner FP32 tolerance for the next round
+// coltol[c] (may be null): inner FP32 tolerance for the next round; ctol (may be null):
+// per-column outer tolerances in place of tol
 hipError_t launch_refine_mask(const double *sums, int ncols, double tol, double tol_in,
-                              int *mask, double *coltol, int *nactive, int *err,
-                              hipStream_t st);
+                              int *mask, double *coltol, int *nactive, int *err, hipStream_t st,
+                              const double *ctol = nullptr);
 
 // ---- Gram (qo_gram.hip) ----
 // G (2n x 2n, col-major, ld 2n) = w * [X Y]^T [X Y]; part: workspace of
@@ -195,7 +196,12 @@ hipError_t launch_instance_energy(const double *part, long qs, int tiles, const 
                                   int ninst, double w, double *out, hipStream_t st);
 // vs = V + sigma, dinv = 1/(c0 + vs); status = 7 (non-finite) or 5 (diagonal <= 0)
 hipError_t launch_batch_potential(const double *V, long ng, double sigma, double c0, double *vs,
-                                  double *dinv, int *status, hipStream_t st);
+                                  double *dinv, float *vs32, float *dinv32, int *status,
+                                  hipStream_t st);
+// per column total += its, rounds += mask (masked-out columns: its 0); rstat[0] = the
+// largest count, rstat[1] = the number of masked-in columns (one workgroup)
+hipError_t launch_its_accum(const int *its, const int *mask, int n, int *total, int *rounds,
+                            int *rstat, hipStream_t st);
 // its[c] = 0 for c < n
 hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st);
 // err: code 6 (PCG limit) for the first column still active

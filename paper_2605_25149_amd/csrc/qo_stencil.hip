@@ -686,15 +686,17 @@ __global__ void k_rel_finalize(const double *__restrict__ outer, int tiles, long
 // sums: [0..ncols) = rr, [ncols..2ncols) = bb.  For active columns the inner
 // tolerance is what the column still needs (with a safety factor), but no
 // tighter than the FP32 floor tol_in: coltol = clamp(0.3 tol ||b|| / ||r||, tol_in, 0.5).
-__global__ void k_refine_mask(const double *__restrict__ sums, int ncols, double tol,
+// tol is ctol[c] per column when ctol is given, else tol_all.
+__global__ void k_refine_mask(const double *__restrict__ sums, int ncols, double tol_all,
                               double tol_in, int *__restrict__ mask,
                               double *__restrict__ coltol, int *__restrict__ nactive,
-                              int *__restrict__ err) {
+                              int *__restrict__ err, const double *__restrict__ ctol) {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
         const double rr = sums[c], bb = sums[ncols + c];
+        const double tol = ctol ? ctol[c] : tol_all;
         int m = 0;
         if (!isfinite(rr) || !isfinite(bb)) {
             atomicMax(&err[0], 7);
@@ -907,9 +909,9 @@ hipError_t launch_rel_finalize(const double *outer, int tiles, int ncols, const 
 
 hipError_t launch_refine_mask(const double *sums, int ncols, double tol, double tol_in,
                               int *mask, double *coltol, int *nactive, int *err,
-                              hipStream_t st) {
+                              hipStream_t st, const double *ctol) {
     hipLaunchKernelGGL(k_refine_mask, dim3(1), dim3(256), 0, st, sums, ncols, tol, tol_in, mask,
-                       coltol, nactive, err);
+                       coltol, nactive, err, ctol);
     return hipGetLastError();
 }
 

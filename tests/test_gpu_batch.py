@@ -49,9 +49,9 @@ def _problems():
     return probs
 
 
-def _batch(B, probs, precond="fast_poisson", tol=1e-12, maxit=40):
+def _batch(B, probs, precond="fast_poisson", tol=1e-12, maxit=40, precision="fp64"):
     cfgs = [dict(dim=2, n=p["n"], N=p["N"], sigma=p["sigma"], pcg_tol=tol, pcg_maxit=maxit,
-                 precond=precond) for p in probs]
+                 precond=precond, precision=precision) for p in probs]
     b = B.Batch(cfgs)
     for i, p in enumerate(probs):
         b.set_potential(i, p["V"])
@@ -142,8 +142,8 @@ def test_batch_matches_oracle(torch, B, oracle_mod):
 
 def test_batch_tiles_and_errors(torch, B):
     """The tuned band height is a valid one per group; a solve cut short fails with
-    QO_ERR_PCG_NOCONV; stepping before the state is set fails with QO_ERR_STATE; mixed
-    precision is refused."""
+    QO_ERR_PCG_NOCONV; stepping before the state is set fails with QO_ERR_STATE; the
+    one-reduction PCG form is refused."""
     probs = _problems()
     b = _batch(B, probs)
     try:
@@ -167,4 +167,72 @@ def test_batch_tiles_and_errors(torch, B):
     finally:
         b.close()
     with pytest.raises(B.QOError):
-        B.Batch([dict(dim=2, n=(16, 16), N=2, precision="mixed")])
+        B.Batch([dict(dim=2, n=(16, 16), N=2, pcg_variant=1)])
+
+
+@pytest.mark.parametrize("precond,maxit", [("fast_poisson", 40), ("jacobi", 400)])
+def test_batch_mixed_matches_fp64(torch, B, precond, maxit):
+    """Mixed precision in a batch (FP32 PCG in restarted FP64 refinement rounds, fixed
+    counts) against the same problems stepped in FP64 by single-instance handles, 12 steps
+    at PCG tol 1e-12 on both sides: each solve meets the same FP64 residual test, so the
+    two runs differ by solves that agree to the tolerance: energies within 1e-10 relative
+    every step, final states within 1e-8.  Every solve needs at least two rounds (the FP32
+    inner tolerance floor is 1e-5)."""
+    probs = _problems()
+    K = 12
+    b = _batch(B, probs, precond, maxit=maxit, precision="mixed")
+    ref = []
+    for p in probs:
+        s = B.Solver(2, p["n"], p["N"], sigma=p["sigma"], pcg_tol=1e-12, pcg_check=1,
+                     precond=precond)
+        s.set_potential(p["V"])
+        s.set_state(B.as_block(p["U0"]))
+        ref.append(s)
+    try:
+        taus = [p["tau"] for p in probs]
+        for k in range(K):
+            st = b.step(taus, use_graph=True)
+            for i, p in enumerate(probs):
+                r = ref[i].step(p["tau"])
+                assert abs(st[i]["energy"] - r["energy"]) <= 1e-10 * abs(r["energy"]), (k, i)
+                assert min(st[i]["refine_rounds"]) >= 2, (k, i)
+        for i in range(len(probs)):
+            U = b.get_state(i)
+            Ur = B.to_numpy(ref[i].get_state())
+            assert np.max(np.abs(U - Ur)) <= 1e-8 * np.max(np.abs(Ur)), i
+    finally:
+        b.close()
+        for s in ref:
+            s.close()
+
+
+def test_batch_mixed_graph_equals_eager_and_noconv(torch, B):
+    """Mixed precision: graph replays give bit-identical states and statistics to eager
+    steps (same tuned tiles, same adapted counts); a solve whose rounds cannot reach the
+    tolerance (one FP32 iteration per round, tol 1e-14) fails with QO_ERR_PCG_NOCONV."""
+    probs = _problems()
+    taus = [p["tau"] for p in probs]
+    b = _batch(B, probs, precision="mixed")
+    out = {}
+    try:
+        for mode in (False, True):
+            for i, p in enumerate(probs):
+                b.set_state(i, p["U0"])
+            stats = [b.step(taus, use_graph=mode) for _ in range(6)]
+            out[mode] = (stats, [b.get_state(i) for i in range(len(probs))])
+    finally:
+        b.close()
+    (s0, u0), (s1, u1) = out[False], out[True]
+    for a, c in zip(s0, s1):
+        for i in range(len(probs)):
+            assert a[i]["energy"] == c[i]["energy"]
+            assert a[i]["pcg_iters"] == c[i]["pcg_iters"]
+            assert a[i]["refine_rounds"] == c[i]["refine_rounds"]
+    for a, c in zip(u0, u1):
+        assert np.array_equal(a, c)
+    b = _batch(B, probs, tol=1e-14, maxit=1, precision="mixed")
+    try:
+        with pytest.raises(B.QOError, match="QO_ERR_PCG_NOCONV"):
+            b.step(taus)
+    finally:
+        b.close()

@@ -16,6 +16,8 @@
 //         from FP64, FP32 accumulation within a chunk, FP64 across chunks.
 #include "qo_internal.h"
 
+#include <type_traits>
+
 namespace qo {
 
 namespace {
@@ -25,6 +27,14 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int TM = 64;  // output tile edge per wavefront
+
+// Global-address-space views.  Pointers read from a job table are generic; generic loads
+// count on both the vector-memory and the LDS/scalar counters, and the compiler then
+// waits for all of them before the MFMAs, which defeats the prefetch.
+typedef const double __attribute__((address_space(1))) gdouble;
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef const d2 __attribute__((address_space(1))) gd2;
+__device__ __forceinline__ gdouble *gptr(const double *p) { return (gdouble *)p; }
 
 __device__ __forceinline__ const double *zcol(const double *X, const double *Y, long ld, int n,
                                               int c) {
@@ -78,17 +88,17 @@ __device__ __forceinline__ void gram_f64_tile(const double *__restrict__ X,
     const int lane = threadIdx.x;
     const int lr = lane & 15, lg = lane >> 4;
 
-    const double *pa[4];
-    const double *pb[4];
-    bool va[4], vb[4];
+    // Columns beyond 2n read column 0: their products only reach entries that are never
+    // stored, so the loads need no guard.  (Guarded loads become branches, and the
+    // compiler then waits for every load in flight before the MFMAs.)
+    gdouble *pa[4];
+    gdouble *pb[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int ca = ti * TM + 16 * i + lr;
         const int cb = tj * TM + 16 * i + lr;
-        va[i] = ca < nn;
-        vb[i] = cb < nn;
-        pa[i] = va[i] ? zcol(X, Y, ld, n, ca) : X;
-        pb[i] = vb[i] ? zcol(X, Y, ld, n, cb) : X;
+        pa[i] = gptr(ca < nn ? zcol(X, Y, ld, n, ca) : X);
+        pb[i] = gptr(cb < nn ? zcol(X, Y, ld, n, cb) : X);
     }
     v4d acc[4][4];
 #pragma unroll
@@ -96,30 +106,7 @@ __device__ __forceinline__ void gram_f64_tile(const double *__restrict__ X,
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    for (long k0 = kb; k0 < ke; k0 += 16) {
-        const long r0 = k0 + 4 * lg;
-        double a[4][4], b[4][4];
-        const bool full = vec_ok && (r0 + 4 <= ke);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (full) {
-                const double2 *qa = reinterpret_cast<const double2 *>(pa[i] + r0);
-                const double2 *qb = reinterpret_cast<const double2 *>(pb[i] + r0);
-                double2 a0 = va[i] ? qa[0] : double2{0.0, 0.0};
-                double2 a1 = va[i] ? qa[1] : double2{0.0, 0.0};
-                double2 b0 = vb[i] ? qb[0] : double2{0.0, 0.0};
-                double2 b1 = vb[i] ? qb[1] : double2{0.0, 0.0};
-                a[i][0] = a0.x; a[i][1] = a0.y; a[i][2] = a1.x; a[i][3] = a1.y;
-                b[i][0] = b0.x; b[i][1] = b0.y; b[i][2] = b1.x; b[i][3] = b1.y;
-            } else {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const bool in = (r0 + s) < ke;
-                    a[i][s] = (va[i] && in) ? pa[i][r0 + s] : 0.0;
-                    b[i][s] = (vb[i] && in) ? pb[i][r0 + s] : 0.0;
-                }
-            }
-        }
+    auto mma_chunk = [&](const double (&a)[4][4], const double (&b)[4][4]) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -128,6 +115,68 @@ __device__ __forceinline__ void gram_f64_tile(const double *__restrict__ X,
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j],
                                                                     0, 0, 0);
+    };
+    // rows [kb, kend) in full chunks of 16, software-pipelined one chunk ahead (past the end
+    // the prefetch re-reads the final chunk); the scheduling barriers keep the prefetch
+    // ahead of the MFMAs it overlaps
+    const long len = ke > kb ? ke - kb : 0;
+    const long kend = kb + (len & ~15L);
+    auto run = [&](auto vec) {
+        auto load_chunk = [&](long k0, double (&a)[4][4], double (&b)[4][4]) {
+            const long r0 = k0 + 4 * lg;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if constexpr (decltype(vec)::value) {
+                    gd2 *qa = (gd2 *)(pa[i] + r0);
+                    gd2 *qb = (gd2 *)(pb[i] + r0);
+                    const d2 a0 = qa[0], a1 = qa[1], b0 = qb[0], b1 = qb[1];
+                    a[i][0] = a0.x; a[i][1] = a0.y; a[i][2] = a1.x; a[i][3] = a1.y;
+                    b[i][0] = b0.x; b[i][1] = b0.y; b[i][2] = b1.x; b[i][3] = b1.y;
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        a[i][s] = pa[i][r0 + s];
+                        b[i][s] = pb[i][r0 + s];
+                    }
+                }
+            }
+        };
+        if (kend > kb) {
+            double a0[4][4], b0[4][4], a1[4][4], b1[4][4];
+            const long last = kend - 16;
+            const long npairs = (kend - kb) >> 5;
+            load_chunk(kb, a0, b0);
+            for (long p = 0; p < npairs; ++p) {
+                const long k0 = kb + (p << 5);
+                load_chunk(k0 + 16, a1, b1);
+                __builtin_amdgcn_sched_barrier(0);
+                mma_chunk(a0, b0);
+                __builtin_amdgcn_sched_barrier(0);
+                load_chunk(min(k0 + 32, last), a0, b0);
+                __builtin_amdgcn_sched_barrier(0);
+                mma_chunk(a1, b1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if ((kend - kb) & 16) mma_chunk(a0, b0);
+        }
+    };
+    if (vec_ok) run(std::true_type{});
+    else run(std::false_type{});
+    // tail rows [kend, ke): rows past ke are zeroed (they belong to another chunk)
+    if (kend < ke) {
+        const long r0 = kend + 4 * lg;
+        double a[4][4], b[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const bool in = r0 + s < ke;
+                const long r = in ? r0 + s : ke - 1;
+                const double x = pa[i][r], y = pb[i][r];
+                a[i][s] = in ? x : 0.0;
+                b[i][s] = in ? y : 0.0;
+            }
+        mma_chunk(a, b);
     }
     // FP64 16x16 accumulator layout: value v of lane l is row l/16 + 4v, column l%16
     double *out = part + (long)split * nn * nn;
@@ -217,31 +266,29 @@ __global__ __launch_bounds__(64) void k_gram_bf16(const __bf16 *__restrict__ Zb,
     const int lane = threadIdx.x;
     const int lr = lane & 15, lg = lane >> 4;
 
-    const __bf16 *pa[4];
-    const __bf16 *pb[4];
-    bool va[4], vb[4];
+    // Columns beyond 2n read column 0 (their products only reach entries that are never
+    // stored), so the loads are unconditional and the compiler can keep them in flight.
+    typedef const v8bf __attribute__((address_space(1))) gv8bf;
+    gv8bf *pa[4];
+    gv8bf *pb[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int ca = ti * TM + 16 * i + lr;
         const int cb = tj * TM + 16 * i + lr;
-        va[i] = ca < nn;
-        vb[i] = cb < nn;
-        pa[i] = Zb + (long)(va[i] ? ca : 0) * ld + 8 * lg;
-        pb[i] = Zb + (long)(vb[i] ? cb : 0) * ld + 8 * lg;
+        pa[i] = (gv8bf *)(Zb + (long)(ca < nn ? ca : 0) * ld + 8 * lg);
+        pb[i] = (gv8bf *)(Zb + (long)(cb < nn ? cb : 0) * ld + 8 * lg);
     }
     v4f acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-    v8bf zero;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) zero[s] = (__bf16)0.f;
+    // k0 advances in bf16 elements; one v8bf covers 8 rows, so the row offset is k0 / 8
     auto load = [&](long k0, v8bf (&a)[4], v8bf (&b)[4]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            a[i] = va[i] ? *reinterpret_cast<const v8bf *>(pa[i] + k0) : zero;
-            b[i] = vb[i] ? *reinterpret_cast<const v8bf *>(pb[i] + k0) : zero;
+            a[i] = pa[i][k0 >> 3];
+            b[i] = pb[i][k0 >> 3];
         }
     };
     auto mma = [&](const v8bf (&a)[4], const v8bf (&b)[4]) {
@@ -251,14 +298,40 @@ __global__ __launch_bounds__(64) void k_gram_bf16(const __bf16 *__restrict__ Zb,
             for (int j = 0; j < 4; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     };
-    v8bf a0[4], b0[4], a1[4], b1[4];
-    if (kb < ke) load(kb, a0, b0);
-    for (long k0 = kb; k0 < ke; k0 += 64) {
-        if (k0 + 32 < ke) load(k0 + 32, a1, b1);
-        mma(a0, b0);
-        if (k0 + 32 >= ke) break;
-        if (k0 + 64 < ke) load(k0 + 64, a0, b0);
-        mma(a1, b1);
+    // 32-row chunks, four in flight: a chunk's 16 MFMAs are far shorter than a load's
+    // latency.  Past the end the prefetch re-reads the final chunk; the scheduling
+    // barriers keep the loads ahead of the MFMAs they overlap.
+    const long nch = ke > kb ? (ke - kb) >> 5 : 0;
+    auto chunk = [&](long c) { return kb + 32 * (c < nch ? c : nch - 1); };
+    if (nch > 0) {
+        v8bf a0[4], b0[4], a1[4], b1[4], a2[4], b2[4], a3[4], b3[4];
+        load(chunk(0), a0, b0);
+        load(chunk(1), a1, b1);
+        load(chunk(2), a2, b2);
+        const long nq = nch >> 2;
+        for (long q = 0; q < nq; ++q) {
+            const long c = q << 2;
+            load(chunk(c + 3), a3, b3);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(a0, b0);
+            __builtin_amdgcn_sched_barrier(0);
+            load(chunk(c + 4), a0, b0);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
+            load(chunk(c + 5), a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(a2, b2);
+            __builtin_amdgcn_sched_barrier(0);
+            load(chunk(c + 6), a2, b2);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(a3, b3);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const long rem = nch & 3;  // chunks 4 nq .. 4 nq + rem - 1 sit in a0, a1, a2
+        if (rem > 0) mma(a0, b0);
+        if (rem > 1) mma(a1, b1);
+        if (rem > 2) mma(a2, b2);
     }
     double *out = part + (long)split * nn * nn;
 #pragma unroll

@@ -18,6 +18,12 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// Global-address-space view: the batch kernel reads its operand pointers from a job
+// table, and generic loads through them would make the compiler wait for every load in
+// flight (they count on the LDS/scalar counter too) before the MFMAs.
+typedef const double __attribute__((address_space(1))) gdouble;
+__device__ __forceinline__ gdouble *gptr(const double *p) { return (gdouble *)p; }
+
 // One 64 (grid rows from m0) x 64 (columns from c0) tile of Out, one wavefront.
 __device__ __forceinline__ void tsgemm_tile(double *__restrict__ Out, long ldo,
                                             const double *__restrict__ C0,
@@ -42,54 +48,88 @@ __device__ __forceinline__ void tsgemm_tile(double *__restrict__ Out, long ldo,
             }
         }
 
-    // One K range over [A | B] (length n, or 2n with B), in chunks of 16 k-values
-    // (4 MFMA k-steps); the next chunk's loads are issued before the current chunk's
-    // MFMAs, so the memory latency hides behind 64 MFMAs.
-    // Operand pairs present: (A, Xr) and/or (B, Yr); either may be absent.  The K
-    // range covers the present ones only, so no load ever goes through a null pointer.
-    const double *T0 = A ? A : B, *S0 = A ? Xr : Yr;
-    const double *T1 = A ? B : nullptr, *S1 = A ? Yr : nullptr;
-    const int ktot = (T0 ? n : 0) + (T1 ? n : 0);
-    auto load_chunk = [&](int kc, double (&sa)[4][4], double (&tb)[4][4]) {
+    // One pipelined pass per operand pair (A, Xr) and (B, Yr), either of which may be
+    // absent, in chunks of 16 k-values (4 MFMA k-steps): the next chunk's loads are issued
+    // before the current chunk's 64 MFMAs.  The loads are unconditional, with row and
+    // column indices clamped into the operands: a product of a clamped row m >= ng or
+    // column c >= n only reaches an output that is never stored.  (Guarded loads become
+    // branches, and the compiler then waits for every load in flight before the MFMAs.)
+    // The scheduling barriers keep the prefetch ahead of the MFMAs it overlaps.  k beyond
+    // n occurs only in a tail chunk when n is not a multiple of 16; its loads are zeroed.
+    long moff[4];
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int kg = kc + 4 * ks + lg;
-            const bool second = kg >= n;  // only reachable when T1 is present (ktot = 2n)
-            const int k = second ? kg - n : kg;
-            const double *T = second ? T1 : T0;
-            const double *S = second ? S1 : S0;
-            const bool kin = kg < ktot;
+    for (int i = 0; i < 4; ++i) {
+        const long m = m0 + 16 * i + lr;
+        moff[i] = m < ng ? m : ng - 1;
+    }
+    int coff[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = c0 + 16 * j + lr;
-                sa[ks][j] = (kin && c < n) ? S[(long)k * n + c] : 0.0;
+    for (int j = 0; j < 4; ++j) {
+        const int c = c0 + 16 * j + lr;
+        coff[j] = c < n ? c : n - 1;
+    }
+    auto pass = [&](const double *Tp, const double *Sp) {
+        gdouble *__restrict__ T = gptr(Tp);
+        gdouble *__restrict__ S = gptr(Sp);
+        auto load_chunk = [&](int kc, double (&sa)[4][4], double (&tb)[4][4]) {
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const long k = kc + 4 * ks + lg;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) sa[ks][j] = S[k * n + coff[j]];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) tb[ks][i] = T[k * ld + moff[i]];
             }
+        };
+        auto mma_chunk = [&](const double (&sa)[4][4], const double (&tb)[4][4]) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const long m = m0 + 16 * i + lr;
-                tb[ks][i] = (kin && m < ng) ? T[(long)k * ld + m] : 0.0;
+            for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc[j][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[ks][j], tb[ks][i],
+                                                                        acc[j][i], 0, 0, 0);
+        };
+        const int nfull = n & ~15;
+        double sa0[4][4], tb0[4][4], sa1[4][4], tb1[4][4];
+        if (nfull > 0) {
+            // past the end the prefetch re-reads the final chunk
+            const int last = nfull - 16;
+            const int npairs = nfull >> 5;
+            load_chunk(0, sa0, tb0);
+            for (int p = 0; p < npairs; ++p) {
+                const int kc = p << 5;
+                load_chunk(kc + 16, sa1, tb1);
+                __builtin_amdgcn_sched_barrier(0);
+                mma_chunk(sa0, tb0);
+                __builtin_amdgcn_sched_barrier(0);
+                load_chunk(min(kc + 32, last), sa0, tb0);
+                __builtin_amdgcn_sched_barrier(0);
+                mma_chunk(sa1, tb1);
+                __builtin_amdgcn_sched_barrier(0);
             }
+            if (nfull & 16) mma_chunk(sa0, tb0);
+        }
+        if (nfull < n) {
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int k = nfull + 4 * ks + lg;
+                const bool kin = k < n;
+                const long kk = kin ? k : n - 1;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double v = S[kk * n + coff[j]];
+                    sa0[ks][j] = kin ? v : 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) tb0[ks][i] = T[kk * ld + moff[i]];
+            }
+            mma_chunk(sa0, tb0);
         }
     };
-    auto mma_chunk = [&](const double (&sa)[4][4], const double (&tb)[4][4]) {
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    acc[j][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[ks][j], tb[ks][i],
-                                                                    acc[j][i], 0, 0, 0);
-    };
-    double sa0[4][4], tb0[4][4], sa1[4][4], tb1[4][4];
-    load_chunk(0, sa0, tb0);
-    for (int kc = 0; kc < ktot; kc += 32) {
-        if (kc + 16 < ktot) load_chunk(kc + 16, sa1, tb1);
-        mma_chunk(sa0, tb0);
-        if (kc + 16 >= ktot) break;
-        if (kc + 32 < ktot) load_chunk(kc + 32, sa0, tb0);
-        mma_chunk(sa1, tb1);
-    }
+    if (A) pass(A, Xr);
+    if (B) pass(B, Yr);
     // FP64 16x16 accumulator layout: value v of lane l is row l/16 + 4v, column l%16,
     // so acc[j][i][v] = Out^T[c0 + 16j + lg + 4v][m0 + 16i + lr]
 #pragma unroll

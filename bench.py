@@ -396,7 +396,7 @@ def run_adjoint(K, log, n=64, N=32, tau=6.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=96)
     ap.add_argument("--N", type=int, default=256)
@@ -409,7 +409,7 @@ def main():
     ap.add_argument("--jacobi-steps", type=int, default=2,
                     help="also time this many steps (after one warm-up step) with the Jacobi "
                          "preconditioner in each mode (0: skip)")
-    ap.add_argument("--accuracy-steps", type=int, default=100,
+    ap.add_argument("--accuracy-steps", type=int, default=200,
                     help="mixed-vs-FP64 eigenvalue gate over this many steps (0: skip)")
     ap.add_argument("--batch-instances", type=int, default=128,
                     help="also time a grouped batch of this many 2-D problems (0: skip)")

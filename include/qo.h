@@ -262,6 +262,20 @@ typedef struct {
     double work[QO_KERNEL_COUNT];
 } qo_profile_data;
 
+/* How qo_step computes the energy it reports.  mode 0 (default): the stencil quadratic
+ * form of U_{n+1} (one pass over the block).  mode 1: K = <U, H_sigma U> is carried from
+ * step to step by exact identities of the two stages (Sec. 4.1; the second-stage energy
+ * identity of Sec. 4.2 is its trace): with the solves H_sigma P = U, H_sigma Q = U_hat,
+ *   K_hat   = X^T K X + X^T S Y + Y^T S X + Y^T M^T Y,
+ *   K_{n+1} = K_hat - tau (S_hat O + O S_hat) + tau^2 O A^T O,
+ * E_sigma = 1/2 tr K_{n+1}, tr <U,U> = tr O_{n+1} + N, all N x N work.  K is computed
+ * with the stencil at the first step after the mode is set or the state or potential
+ * changes, and again every `anchor` steps (anchor 0: never again).  The propagated value
+ * inherits the solves' tolerance each step.  mode 1 needs precision QO_FP64 (the BF16
+ * Grams of QO_MIXED would enter the identities); QO_ERR_ARG otherwise or for a bad mode
+ * or a negative anchor. */
+qo_status qo_energy_mode(qo_handle h, int mode, int anchor);
+
 /* ---- reverse mode through K steps -------------------------------------------------
  *
  * qo_tape_forward takes K steps of Sec. 4.1 (Algorithm 1 of Sec. 5 with a fixed tau) from

@@ -31,6 +31,7 @@ EXPORTS = [
     "qo_gram", "qo_eigenpairs", "qo_destroy", "qo_status_string", "qo_last_error", "qo_apply",
     "qo_solve", "qo_gram_pair", "qo_get_block", "qo_get_matrix", "qo_profile", "qo_profile_get",
     "qo_run", "qo_eigsum_gradient", "qo_precond", "qo_tape_forward", "qo_tape_backward",
+    "qo_energy_mode",
     "qo_batch_create", "qo_batch_set_potential", "qo_batch_set_state", "qo_batch_get_state",
     "qo_batch_step", "qo_batch_tile", "qo_batch_destroy", "qo_batch_last_error",
 ]
@@ -119,6 +120,7 @@ def load_library(path: str = LIB_PATH):
         "qo_profile_get": ([H, ctypes.POINTER(QoProfileData)], ctypes.c_int),
         "qo_precond": ([H, vp, vp, ctypes.c_long, ctypes.c_int, vp], ctypes.c_int),
         "qo_tape_forward": ([H, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp], ctypes.c_int),
+        "qo_energy_mode": ([H, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "qo_tape_backward": ([H, ctypes.c_double, vp, vp, ctypes.c_long, ctypes.c_int],
                              ctypes.c_int),
         "qo_batch_create": ([ctypes.POINTER(QoConfig), ctypes.c_int, vp, ctypes.POINTER(H)],
@@ -299,6 +301,11 @@ class Solver:
         g = torch.empty(self.ng, dtype=torch.float64, device="cuda")
         self._chk(self.lib.qo_eigsum_gradient(self.h, ctypes.c_void_p(g.data_ptr()), 1))
         return g
+
+    def energy_mode(self, mode, anchor=0):
+        """0: stencil energy each step; 1: energy carried by the Gram identities, re-taken
+        with the stencil every `anchor` steps (0: only at the start)."""
+        self._chk(self.lib.qo_energy_mode(self.h, int(mode), int(anchor)))
 
     LOSSES = {"energy": 0, "ritz_sum": 1}
 

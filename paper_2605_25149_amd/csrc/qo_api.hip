@@ -90,6 +90,11 @@ struct qo_ctx {
     float *dmu = nullptr, *pcs = nullptr, *z32 = nullptr;
     double *z64 = nullptr, *rzp = nullptr, *dsum = nullptr;
     double mu0 = 0.0;  // mu_x[0] + mu_y[0] (+ mu_z[0]): smallest eigenvalue of -Lap_h
+    // energy by the Gram identities (qo_energy_mode): K = <U, H_sigma U> carried from step
+    // to step, recomputed with the stencil every eanchor steps
+    int emode = 0, eanchor = 0;
+    bool have_K = false;
+    double *Kprop = nullptr, *epool = nullptr;
     // reverse mode through taped steps (qo_tape_forward / qo_tape_backward)
     std::vector<double *> tape;  // U_0 .. U_K
     int tape_K = 0, tape_loss = 0;
@@ -675,6 +680,71 @@ void rec(qo_ctx *c, int i) {
     if (c->ev_ok) (void)hipEventRecord(c->ev[i], c->st);
 }
 
+// out[0] = 1/2 tr(A) + a tr(B) + b for n x n column-major A, B (one block)
+__global__ void k_trace2(const double *__restrict__ A, const double *__restrict__ B, int n,
+                         double a, double b, double *__restrict__ out) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += 0.5 * A[(long)i * n + i] + a * B[(long)i * n + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        out[0] = t + b;
+    }
+}
+
+// K = <U, H_sigma U> of the current state from the stencil (FP64): apply into the residual
+// buffer (free between solves), Gram of [U | H U], block (0,1).
+qo_status anchor_K(qo_ctx *c) {
+    const int N = c->N, N2 = 2 * N;
+    HIPC(c, launch_apply(c->g, c->vs, c->U, c->r, c->ld, N, c->st));
+    QOC(gram64(c, c->U, c->r, c->ld, N, c->G2));
+    HIPC(c, nn_axpby(c->Kprop, N, 1.0, c->G2 + (size_t)N * N2, N2, 0.0, nullptr, N, false, 0.0,
+                     N, N, c->st));
+    c->have_K = true;
+    return QO_OK;
+}
+
+// K_{n+1} from K_n and the step's small matrices.  With H_sigma P = U and H_sigma Q = U_hat
+// (the solves), <U, H P> = <P, H U> = S and <P, H P> = M^T, so
+//   K_hat = X^T K X + X^T S Y + Y^T S X + Y^T M^T Y      (U_hat = U X + P Y),
+// and with <U_hat, H Q> = S_hat, <Q, H Q> = A^T (A = <U_hat, Q>),
+//   K_{n+1} = K_hat - tau (S_hat O + O S_hat) + tau^2 O A^T O   (U_{n+1} = U_hat - tau Q O).
+// E_sigma(U_{n+1}) = 1/2 tr K_{n+1} and tr S_{n+1} = tr O_{n+1} + N go to dscal[4..5].
+qo_status propagate_K(qo_ctx *c, double tau, const double *X, const double *Y,
+                      const double *O, const double *On) {
+    const int N = c->N, N2 = 2 * N;
+    hipStream_t st = c->st;
+    const double *S = c->G1, *M = c->G1 + (size_t)N * N2;
+    const double *Sh = c->G2, *A = c->G2 + (size_t)N * N2;
+    double *T1 = c->epool, *T2 = T1 + (size_t)N * N, *T3 = T2 + (size_t)N * N,
+           *Kh = T3 + (size_t)N * N, *Kn = Kh + (size_t)N * N;
+    HIPC(c, nn_gemm(T1, N, c->Kprop, N, false, X, N, false, N, N, N, 1.0, 0.0, 0.0, st));
+    HIPC(c, nn_gemm(Kh, N, X, N, true, T1, N, false, N, N, N, 1.0, 0.0, 0.0, st));
+    HIPC(c, nn_gemm(T2, N, S, N2, false, Y, N, false, N, N, N, 1.0, 0.0, 0.0, st));
+    HIPC(c, nn_gemm(T1, N, X, N, true, T2, N, false, N, N, N, 1.0, 0.0, 0.0, st));
+    HIPC(c, nn_axpby(T3, N, 1.0, T1, N, 1.0, T1, N, true, 0.0, N, N, st));
+    HIPC(c, nn_axpby(Kh, N, 1.0, Kh, N, 1.0, T3, N, false, 0.0, N, N, st));
+    HIPC(c, nn_gemm(T2, N, M, N2, true, Y, N, false, N, N, N, 1.0, 0.0, 0.0, st));
+    HIPC(c, nn_gemm(Kh, N, Y, N, true, T2, N, false, N, N, N, 1.0, 1.0, 0.0, st));
+    HIPC(c, nn_gemm(T1, N, Sh, N2, false, O, N, false, N, N, N, 1.0, 0.0, 0.0, st));
+    HIPC(c, nn_axpby(T3, N, 1.0, T1, N, 1.0, T1, N, true, 0.0, N, N, st));
+    HIPC(c, nn_axpby(Kn, N, 1.0, Kh, N, -tau, T3, N, false, 0.0, N, N, st));
+    HIPC(c, nn_gemm(T1, N, A, N2, true, O, N, false, N, N, N, 1.0, 0.0, 0.0, st));
+    HIPC(c, nn_gemm(Kn, N, O, N, false, T1, N, false, N, N, N, tau * tau, 1.0, 0.0, st));
+    HIPC(c, hipMemcpyAsync(c->Kprop, Kn, sizeof(double) * N * N, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_trace2, dim3(1), dim3(1024), 0, st, Kn, On, N, 0.0, 0.0, c->dscal + 4);
+    HIPC(c, hipGetLastError());
+    hipLaunchKernelGGL(k_trace2, dim3(1), dim3(1024), 0, st, On, On, N, 0.5, (double)N,
+                       c->dscal + 5);
+    HIPC(c, hipGetLastError());
+    return QO_OK;
+}
+
 // grad_stop > 0: after G U_n and the Gram matrix, stop (return QO_OK with
 // *stopped = 1, U_n untouched) when ||grad_G E_G(U_n)|| <= grad_stop.
 qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop = 0.0,
@@ -689,6 +759,8 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
     std::vector<int> itsP(N), itsQ(N);
     int rP = 0, rQ = 0;
 
+    if (c->emode == 1 && (!c->have_K || (c->eanchor > 0 && c->nstep % c->eanchor == 0)))
+        QOC(anchor_K(c));
     rec(c, 0);
     QOC(solve_block(c, c->U, P, N, warm && c->have_warm, itsP.data(), &rP, "solve G U_n"));
     rec(c, 1);
@@ -783,7 +855,16 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
     c->have_warm = warm != 0;
     c->nstep += 1;
     double Es = 0.0, trS = 0.0;
-    QOC(energy_of(c, c->U, &Es, &trS));
+    if (c->emode == 1) {
+        QOC(propagate_K(c, tau, mp(c, MP_X), mp(c, MP_Y), mp(c, MP_O), mp(c, MP_T3)));
+        HIPC(c, hipMemcpyAsync(c->h_scal + 4, c->dscal + 4, 2 * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+        HIPC(c, hipStreamSynchronize(st));
+        Es = c->h_scal[4];
+        trS = c->h_scal[5];
+    } else {
+        QOC(energy_of(c, c->U, &Es, &trS));
+    }
     rec(c, 8);
     HIPC(c, hipMemcpyAsync(c->h_scal, c->dscal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPC(c, hipStreamSynchronize(st));
@@ -1150,6 +1231,7 @@ qo_status qo_set_potential(qo_handle h, const double *V, int on_device) {
     }
     h->have_V = true;
     h->have_warm = false;
+    h->have_K = false;
     return QO_OK;
 }
 
@@ -1173,6 +1255,7 @@ qo_status qo_set_state(qo_handle h, const double *U, long ld, int on_device) {
     h->have_U = true;
     h->have_warm = false;
     h->have_Es = false;
+    h->have_K = false;
     h->nstep = 0;
     return QO_OK;
 }
@@ -1639,6 +1722,7 @@ qo_status qo_tape_forward(qo_handle h, double tau, int K, int loss, double *L) {
     }
     h->cfg.warm_start = warm;
     h->have_warm = false;
+    h->have_K = false;
     if (s != QO_OK) return s;
     QOC(loss_and_grad(h, loss, L, false));
     h->tape_K = K;
@@ -1735,7 +1819,25 @@ qo_status qo_tape_backward(qo_handle h, double seed, double *gV, double *gU0, lo
     const qo_status s = body();
     h->cfg.warm_start = warm;
     h->have_warm = false;
+    h->have_K = false;
     return s;
 }
 
 }  // extern "C"
+
+extern "C" qo_status qo_energy_mode(qo_handle h, int mode, int anchor) {
+    if (!h) return QO_ERR_ARG;
+    if (mode != 0 && mode != 1) return fail(h, QO_ERR_ARG, "energy mode must be 0 or 1");
+    if (anchor < 0) return fail(h, QO_ERR_ARG, "anchor must be >= 0");
+    if (mode == 1 && h->mixed)
+        return fail(h, QO_ERR_ARG, "the propagated energy needs precision QO_FP64 (BF16 Grams)");
+    if (mode == 1) {
+        const size_t nn = (size_t)h->N * h->N;
+        if (!h->Kprop) QOC(dalloc(h, &h->Kprop, nn));
+        if (!h->epool) QOC(dalloc(h, &h->epool, 5 * nn));
+    }
+    h->emode = mode;
+    h->eanchor = anchor;
+    h->have_K = false;
+    return QO_OK;
+}

@@ -547,3 +547,29 @@ def test_steps_grad_hellmann_feynman_limit(oracle_mod):
     L, gV, gU = O.steps_loss_grad(prob, U0, 10.0, 80, "energy")
     assert L == pytest.approx(0.5 * lam[:3].sum(), rel=1e-8)
     assert np.max(np.abs(gV - 0.5 * hf)) <= 1e-6 * np.max(hf)
+
+
+def test_energy_matrix_identities(oracle_mod):
+    """The identities behind the propagated energy (Sec. 4.1 stages; the trace of the second
+    is the second-stage energy identity of Sec. 4.2), checked with exact solves on a 3-D
+    wells grid: K_hat = <U_hat, H U_hat> = X^T K X + X^T S Y + Y^T S X + Y^T M^T Y and
+    K_{n+1} = K_hat - tau (S_hat O + O S_hat) + tau^2 O A^T O, each against a direct
+    evaluation with the stencil (1e-11 of the largest entry), over three steps."""
+    O_ = oracle_mod
+    n, N, tau = (9, 8, 7), 4, 6.0
+    V = inputs.gaussian_wells(n, seed=2, depth=(1.0, 4.0))
+    prob = O_.Problem(3, n, V, sigma=0.5)
+    orc = O_.Oracle(prob, inputs.random_block(int(np.prod(n)), N, seed=3), direct=True)
+    K = prob.inner(orc.U, prob.apply(orc.U))
+    for _ in range(3):
+        orc.step(tau)
+        L = orc.last
+        X, Y, S, M = L["X"], L["Y"], L["S"], L["M"]
+        Kh = X.T @ K @ X + X.T @ S @ Y + Y.T @ S @ X + Y.T @ M.T @ Y
+        Kh_ref = prob.inner(L["U_hat"], prob.apply(L["U_hat"]))
+        assert np.max(np.abs(Kh - Kh_ref)) <= 1e-11 * np.max(np.abs(Kh_ref))
+        Sh = prob.inner(L["U_hat"], L["U_hat"])
+        Oc = L["O"]
+        K = Kh - tau * (Sh @ Oc + Oc @ Sh) + tau ** 2 * Oc @ L["A"].T @ Oc
+        K_ref = prob.inner(orc.U, prob.apply(orc.U))
+        assert np.max(np.abs(K - K_ref)) <= 1e-11 * np.max(np.abs(K_ref))

@@ -71,7 +71,11 @@ typedef struct {
     int pcg_variant;         /* 0: Hestenes-Stiefel form, two sweeps per iteration;
                                 1: Chronopoulos-Gear form, one sweep per iteration
                                    (3-D, or 2-D with n_0 <= 256); same iterates in exact
-                                   arithmetic */
+                                   arithmetic;
+                                2: block CG (O'Leary): one search block for all
+                                   columns, N x N step matrices, converged columns
+                                   deflated, the column solver finishing if the block
+                                   loses rank; QO_FP64 with precond 0 only */
     int precond;             /* PCG preconditioner (the solver of G is left open by Sec. 4.1;
                                 the concluding section asks for a better one than the diagonal):
                                 0: Jacobi, M = diag(H_sigma);

@@ -39,6 +39,11 @@ Readings of the paper taken here (numbered as in the design notes' table of read
       with V replaced by a constant, inverted exactly by the orthonormal type-I
       discrete sine transform, which diagonalises the 1-D Dirichlet second
       difference (``precond_apply``).  Only the iteration count depends on M.
+  R19 Block CG (a variant of the solver of G, reading R2): O'Leary's block PCG with the
+      Jacobi preconditioner over all N columns at once; converged columns are deflated
+      (identity rows/columns in the s x s matrices, zero search directions); when the
+      search block loses rank with columns still active (singular P^T H P, or no halving
+      of the largest relative residual in 50 iterations) the column solver finishes.
   R16 The paper does not differentiate the scheme.  ``steps_loss_grad`` gives the
       exact derivative of the discrete K-step map (solves taken exact) composed
       with a loss of U_K (the energy, or the sum of the Ritz values), with respect
@@ -178,6 +183,85 @@ class Problem:
                                      self.sigma, _dp(self.V), _dp(B), _dp(X), B.shape[1], tol,
                                      maxit, use_x0, _ip(iters), _ip(cst), int(variant))
         return X, iters, int(st), cst
+
+    def diag(self):
+        """Diagonal of H_sigma: V + sigma + sum_k 2 kappa / h_k^2."""
+        return self.V + self.sigma + float(np.sum(2.0 * self.kappa / self.h ** 2))
+
+    def solve_block_cg(self, B, X0=None, tol=1e-10, maxit=10000, stall=50):
+        """G B by block PCG with the Jacobi preconditioner (O'Leary's block conjugate
+        gradients; reading R19): one search block P for all columns, with the s x s
+        coefficient matrices
+            alpha = (P^T H P)^{-1} (Z^T R),   beta = (Z^T R)_old^{-1} (Z^T R)_new,
+        X += P alpha, R -= H P alpha, Z = D^{-1} R, P = Z + P beta.  A column stops at the
+        first iteration with ||r|| <= tol ||b|| (recursive residual) and is then deflated:
+        its rows and columns of the s x s matrices become those of the identity and its
+        Z column zero, so it no longer moves and no longer steers the others.
+        The search block can lose rank while columns are still active (P^T H P singular,
+        or the largest relative residual not halved in `stall` iterations); the remaining
+        columns are then finished by the column solver (``solve``) from the current X.
+        Returns (X, iters per column, status); iters of columns finished by the column
+        solver add its count to the block iterations."""
+        B = _fcols(B, self.ng)
+        s = B.shape[1]
+        X = np.zeros_like(B, order="F") if X0 is None else np.array(_fcols(X0, self.ng),
+                                                                     order="F", copy=True)
+        dinv = 1.0 / self.diag()
+        bnorm = np.linalg.norm(B, axis=0)
+        R = B - self.apply(X) if X0 is not None else B.copy(order="F")
+        active = np.linalg.norm(R, axis=0) > tol * bnorm
+        iters = np.zeros(s, dtype=np.int32)
+
+        def masked(G, act):
+            G = G.copy()
+            G[~act, :] = 0.0
+            G[:, ~act] = 0.0
+            G[~act, ~act] = 1.0
+            return G
+
+        Z = R * dinv[:, None]
+        Z[:, ~active] = 0.0
+        P = Z.copy(order="F")
+        rho = masked(Z.T @ R, active)
+        k = 0
+        best, kbest = np.inf, 0
+        while active.any():
+            if k >= maxit:
+                return X, iters, ORC_NOCONV
+            worst = float(np.max(np.linalg.norm(R[:, active], axis=0) / bnorm[active]))
+            if worst < 0.5 * best:
+                best, kbest = worst, k
+            breakdown = k - kbest > stall
+            if not breakdown:
+                Q = self.apply(P)
+                try:
+                    alpha = np.linalg.solve(masked(P.T @ Q, active), rho)
+                except np.linalg.LinAlgError:
+                    breakdown = True
+            if breakdown or not np.all(np.isfinite(alpha)):
+                Xc, itc, st, _ = self.solve(B, X0=X, tol=tol, maxit=maxit - k)
+                iters[active] = k + itc[active]
+                return Xc, iters, st
+            X += P @ alpha
+            R -= Q @ alpha
+            k += 1
+            now = active & (np.linalg.norm(R, axis=0) > tol * bnorm)
+            iters[active & ~now] = k
+            if not np.all(np.isfinite(R)):
+                return X, iters, ORC_NONFINITE
+            Z = R * dinv[:, None]
+            Z[:, ~now] = 0.0
+            rho_new = masked(Z.T @ R, now)
+            try:
+                beta = np.linalg.solve(masked(rho, now), rho_new)
+            except np.linalg.LinAlgError:
+                Xc, itc, st, _ = self.solve(B, X0=X, tol=tol, maxit=maxit - k)
+                iters[now] = k + itc[now]
+                return Xc, iters, st
+            P = Z + P @ beta
+            rho = rho_new
+            active = now
+        return X, iters, ORC_OK
 
     # ---- fast-Poisson preconditioner (reading R13) ---------------------------
     def laplace_eigs(self):
@@ -391,6 +475,11 @@ class Oracle:
     def _G(self, B, X0):
         if self.direct:
             return self.prob.solve_direct(B), np.zeros(B.shape[1], dtype=np.int32)
+        if self.variant == 2:
+            X, it, st = self.prob.solve_block_cg(B, X0=X0, tol=self.tol, maxit=self.maxit)
+            if st != ORC_OK:
+                raise RuntimeError(f"oracle block CG failed with status {st}")
+            return X, it
         if self.precond == "fast_poisson":
             X, it, st, _ = self.prob.solve_fast_poisson(B, X0=X0, tol=self.tol,
                                                         maxit=min(self.maxit, 1000))

@@ -90,6 +90,11 @@ struct qo_ctx {
     float *dmu = nullptr, *pcs = nullptr, *z32 = nullptr;
     double *z64 = nullptr, *rzp = nullptr, *dsum = nullptr;
     double mu0 = 0.0;  // mu_x[0] + mu_y[0] (+ mu_z[0]): smallest eigenvalue of -Lap_h
+    // block CG (pcg_variant 2): Z and ping-pong partners of X, R, P; small matrices;
+    // per-column norms and active flags
+    double *bcgb[4] = {nullptr, nullptr, nullptr, nullptr};
+    double *bcgm = nullptr, *bcgv = nullptr;
+    int *bcga = nullptr;
     // energy by the Gram identities (qo_energy_mode): K = <U, H_sigma U> carried from step
     // to step, recomputed with the stencil every eanchor steps
     int emode = 0, eanchor = 0;
@@ -555,11 +560,236 @@ qo_status solve_mixed_rel(qo_ctx *c, const double *B, double *X, int ncols, int 
     return QO_OK;
 }
 
+
+// ---- block CG (O'Leary), Jacobi preconditioner, FP64 -----------------------------------
+
+qo_status check_status(qo_ctx *c, const char *what);
+__global__ void k_block_axpby(double *__restrict__ Y, const double *__restrict__ X, long ld,
+                              long ng, double a, double b);
+
+// out[c] = sum_i X[i][c]^2 (one block per column)
+__global__ void k_colnorm2(const double *__restrict__ X, long ld, long ng,
+                           double *__restrict__ out) {
+    __shared__ double red[16];
+    const double *x = X + (long)blockIdx.x * ld;
+    double s = 0.0;
+    for (long i = threadIdx.x; i < ng; i += blockDim.x) s += x[i] * x[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        out[blockIdx.x] = t;
+    }
+}
+
+// act_new[c] = act_old[c] (1 when null) and ||r_c|| > tol ||b_c||; a column that stops
+// records its iteration k; counts into nact; non-finite norms set err = 7.
+__global__ void k_bcg_active(const double *__restrict__ rr, const double *__restrict__ bb,
+                             double tol, const int *__restrict__ act_old,
+                             int *__restrict__ act_new, int *__restrict__ its, int k, int n,
+                             int *__restrict__ nact, int *__restrict__ err) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const int was = act_old ? act_old[c] : 1;
+        int a = 0;
+        if (!isfinite(rr[c]) || !isfinite(bb[c])) {
+            atomicMax(err, 7);
+        } else {
+            a = was && sqrt(rr[c]) > tol * sqrt(bb[c]);
+        }
+        if (was && !a) its[c] = k;
+        act_new[c] = a;
+        if (a) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *nact = cnt;
+}
+
+// Z = D^{-1} R on active columns, 0 elsewhere (column in blockIdx.y)
+__global__ void k_bcg_jacobi(double *__restrict__ Z, const double *__restrict__ R,
+                             const double *__restrict__ dinv, long ld, long ng,
+                             const int *__restrict__ act) {
+    const int c = blockIdx.y;
+    const long o = (long)c * ld;
+    const bool a = act[c] != 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ng;
+         i += (long)gridDim.x * blockDim.x)
+        Z[o + i] = a ? dinv[i] * R[o + i] : 0.0;
+}
+
+// dst = src on active rows and columns, the identity on the others (n x n)
+__global__ void k_bcg_mask(double *__restrict__ dst, const double *__restrict__ src, int n,
+                           const int *__restrict__ act) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+        const int i = e % n, j = e / n;
+        dst[e] = (act[i] && act[j]) ? src[e] : (i == j ? 1.0 : 0.0);
+    }
+}
+
+// X = G B for ncols columns by block PCG: one search block for all columns, s x s step
+// matrices alpha = (P^T H P)^{-1} (Z^T R) and beta = (Z^T R)_old^{-1} (Z^T R)_new, Jacobi
+// preconditioner; a column that meets ||r|| <= tol ||b|| is deflated (identity rows and
+// columns in the small matrices, zero search direction).  Converged columns' iteration
+// counts into its.  Host polls the active count after every iteration.
+qo_status solve_bcg(qo_ctx *c, const double *B, double *X, int n, int use_x0, double tol,
+                    int *its_out, const char *what) {
+    hipStream_t st = c->st;
+    const long ld = c->ld, ng = c->ng;
+    const int N = c->N;
+    const size_t blk = (size_t)ld * N, nn = (size_t)N * N;
+    for (int i = 0; i < 4; ++i)
+        if (!c->bcgb[i]) QOC(dalloc(c, &c->bcgb[i], blk));
+    if (!c->bcgm) QOC(dalloc(c, &c->bcgm, 8 * nn));
+    if (!c->bcgv) QOC(dalloc(c, &c->bcgv, (size_t)2 * N));
+    if (!c->bcga) QOC(dalloc(c, &c->bcga, (size_t)3 * N + 4));
+    double *Z = c->bcgb[0];
+    double *Xc = X, *Xn = c->bcgb[1];
+    double *Rc = c->r, *Rn = c->bcgb[2];
+    double *Pc = c->pa, *Pn = c->bcgb[3];
+    double *Q = c->pb;
+    double *Gt = c->bcgm, *Gm = Gt + nn, *rho = Gm + nn, *rhon = rho + nn, *alpha = rhon + nn,
+           *aT = alpha + nn, *naT = aT + nn, *rhom = naT + nn;
+    double *rr = c->bcgv, *bb = rr + N;
+    int *act = c->bcga, *actn = act + N, *its = actn + N, *nact = its + N, *err = nact + 1;
+    long vb = (ng + 255) / 256;
+    if (vb > 1024) vb = 1024;
+    const dim3 vgrid((unsigned)vb, (unsigned)n);
+    HIPC(c, hipMemsetAsync(its, 0, sizeof(int) * n, st));
+    HIPC(c, hipMemsetAsync(err, 0, sizeof(int), st));
+    if (use_x0) {
+        HIPC(c, launch_apply(c->g, c->vs, Xc, Rc, ld, n, st));
+        hipLaunchKernelGGL(k_block_axpby, vgrid, dim3(256), 0, st, Rc, B, ld, ng, 1.0, -1.0);
+        HIPC(c, hipGetLastError());
+    } else {
+        HIPC(c, hipMemsetAsync(Xc, 0, sizeof(double) * ld * n, st));
+        HIPC(c, hipMemcpyAsync(Rc, B, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, st));
+    }
+    hipLaunchKernelGGL(k_colnorm2, dim3(n), dim3(256), 0, st, B, ld, ng, bb);
+    hipLaunchKernelGGL(k_colnorm2, dim3(n), dim3(256), 0, st, Rc, ld, ng, rr);
+    hipLaunchKernelGGL(k_bcg_active, dim3(1), dim3(256), 0, st, rr, bb, tol, nullptr, act, its,
+                       0, n, nact, err);
+    hipLaunchKernelGGL(k_bcg_jacobi, vgrid, dim3(256), 0, st, Z, Rc, c->dinv, ld, ng, act);
+    HIPC(c, hipMemcpyAsync(Pc, Z, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, st));
+    HIPC(c, launch_gram_cross_f64(Z, Rc, ld, ng, n, 1.0, c->gpart, c->gnsplit, Gt, st));
+    hipLaunchKernelGGL(k_bcg_mask, dim3(64), dim3(256), 0, st, rho, Gt, n, act);
+    HIPC(c, hipGetLastError());
+    const int maxit = c->cfg.pcg_maxit;
+    const int stall = 50;
+    std::vector<double> h_rr(n), h_bb(n);
+    std::vector<int> h_act(n);
+    HIPC(c, hipMemcpyAsync(h_bb.data(), bb, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    double best = INFINITY;
+    int k = 0, kbest = 0;
+    bool breakdown = false;
+    // the search block can lose rank while columns are still active: singular P^T H P or
+    // (Z^T R)_old, or no halving of the largest relative residual in `stall` iterations;
+    // the column solver then finishes from the current X
+    auto status_clear = [&]() -> qo_status {
+        int hs = 0;
+        HIPC(c, hipMemcpyAsync(&hs, c->dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPC(c, hipStreamSynchronize(st));
+        if (hs == 7) return fail(c, QO_ERR_NONFINITE, "%s: non-finite block CG matrices", what);
+        breakdown = hs != 0;
+        return QO_OK;
+    };
+    for (;;) {
+        int poll[2] = {0, 0};
+        HIPC(c, hipMemcpyAsync(poll, nact, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPC(c, hipMemcpyAsync(h_rr.data(), rr, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        HIPC(c, hipMemcpyAsync(h_act.data(), act, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+        HIPC(c, hipStreamSynchronize(st));
+        if (poll[1]) return fail(c, QO_ERR_NONFINITE, "%s: non-finite residual in block CG", what);
+        if (poll[0] == 0) break;
+        if (k >= maxit)
+            return fail(c, QO_ERR_PCG_NOCONV, "%s: %d of %d columns not converged after %d "
+                        "block CG iterations (tol %.3g)", what, poll[0], n, maxit, tol);
+        double worst = 0.0;
+        for (int j = 0; j < n; ++j)
+            if (h_act[j]) worst = std::max(worst, std::sqrt(h_rr[j] / h_bb[j]));
+        if (worst < 0.5 * best) {
+            best = worst;
+            kbest = k;
+        }
+        if (k - kbest > stall) {
+            breakdown = true;
+            break;
+        }
+        ++k;
+        // Q = H P; alpha = mask(P^T Q)^{-1} rho
+        HIPC(c, launch_apply(c->g, c->vs, Pc, Q, ld, n, st));
+        HIPC(c, launch_gram_cross_f64(Pc, Q, ld, ng, n, 1.0, c->gpart, c->gnsplit, Gt, st));
+        hipLaunchKernelGGL(k_bcg_mask, dim3(64), dim3(256), 0, st, Gm, Gt, n, act);
+        HIPC(c, hipMemcpyAsync(alpha, rho, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st));
+        HIPC(c, hipMemsetAsync(c->dstatus, 0, sizeof(int), st));
+        HIPC(c, nn_gj_solve(Gm, n, alpha, n, n, n, false, c->dstatus, st, c->gjw, c->gjpiv));
+        QOC(status_clear());
+        if (breakdown) {
+            --k;
+            break;
+        }
+        // X += P alpha, R -= Q alpha (the small operand is passed row-major: alpha^T)
+        HIPC(c, nn_axpby(aT, n, 0.0, nullptr, n, 1.0, alpha, n, true, 0.0, n, n, st));
+        HIPC(c, nn_axpby(naT, n, 0.0, nullptr, n, -1.0, alpha, n, true, 0.0, n, n, st));
+        HIPC(c, launch_tsgemm(Xn, ld, Xc, Pc, aT, nullptr, nullptr, ld, ng, n, st));
+        HIPC(c, launch_tsgemm(Rn, ld, Rc, Q, naT, nullptr, nullptr, ld, ng, n, st));
+        std::swap(Xc, Xn);
+        std::swap(Rc, Rn);
+        // deflate the columns that met the tolerance
+        hipLaunchKernelGGL(k_colnorm2, dim3(n), dim3(256), 0, st, Rc, ld, ng, rr);
+        hipLaunchKernelGGL(k_bcg_active, dim3(1), dim3(256), 0, st, rr, bb, tol, act, actn, its,
+                           k, n, nact, err);
+        // Z = D^{-1} R; beta = mask(rho)^{-1} mask(Z^T R); P = Z + P beta
+        hipLaunchKernelGGL(k_bcg_jacobi, vgrid, dim3(256), 0, st, Z, Rc, c->dinv, ld, ng, actn);
+        HIPC(c, launch_gram_cross_f64(Z, Rc, ld, ng, n, 1.0, c->gpart, c->gnsplit, Gt, st));
+        hipLaunchKernelGGL(k_bcg_mask, dim3(64), dim3(256), 0, st, rhon, Gt, n, actn);
+        hipLaunchKernelGGL(k_bcg_mask, dim3(64), dim3(256), 0, st, rhom, rho, n, actn);
+        HIPC(c, hipMemcpyAsync(alpha, rhon, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st));
+        HIPC(c, hipMemsetAsync(c->dstatus, 0, sizeof(int), st));
+        HIPC(c, nn_gj_solve(rhom, n, alpha, n, n, n, false, c->dstatus, st, c->gjw, c->gjpiv));
+        std::swap(act, actn);
+        QOC(status_clear());
+        if (breakdown) break;
+        HIPC(c, nn_axpby(aT, n, 0.0, nullptr, n, 1.0, alpha, n, true, 0.0, n, n, st));
+        HIPC(c, launch_tsgemm(Pn, ld, Z, Pc, aT, nullptr, nullptr, ld, ng, n, st));
+        std::swap(Pc, Pn);
+        std::swap(rho, rhon);
+    }
+    if (breakdown) {
+        // finish with the column solver from the current X (it reuses r, pa, pb)
+        std::vector<int> h_its(n), col_its(n);
+        HIPC(c, hipMemcpyAsync(h_its.data(), its, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+        HIPC(c, hipMemcpyAsync(h_act.data(), act, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+        HIPC(c, hipStreamSynchronize(st));
+        QOC(pcg<double>(c, c->vs, c->dinv, B, Xc, c->r, c->pa, c->pb, n, 1, tol, nullptr,
+                        nullptr, col_its.data(), what));
+        if (Xc != X)
+            HIPC(c, hipMemcpyAsync(X, Xc, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, st));
+        HIPC(c, hipStreamSynchronize(st));
+        for (int j = 0; j < n; ++j) its_out[j] = h_act[j] ? k + col_its[j] : h_its[j];
+        return QO_OK;
+    }
+    if (Xc != X) HIPC(c, hipMemcpyAsync(X, Xc, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, st));
+    std::vector<int> h_its(n);
+    HIPC(c, hipMemcpyAsync(h_its.data(), its, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+    HIPC(c, hipStreamSynchronize(st));
+    for (int j = 0; j < n; ++j) its_out[j] = h_its[j];
+    return QO_OK;
+}
+
 // X = G B for ncols columns of internal-layout blocks.  its: per column.
 qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_x0, int *its,
                       int *rounds, const char *what) {
     const double tol = c->cfg.pcg_tol;
     const bool one_sweep = c->cfg.pcg_variant == 1;
+    if (!c->mixed && c->cfg.pcg_variant == 2) {
+        *rounds = 1;
+        return solve_bcg(c, B, X, ncols, use_x0, tol, its, what);
+    }
     if (!c->mixed) {
         *rounds = 1;
         if (one_sweep)
@@ -1049,7 +1279,9 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
         ng *= c.n[k];
     }
     if (c.n[0] > 1024) return QO_ERR_ARG;
-    if (c.pcg_variant != 0 && c.pcg_variant != 1) return QO_ERR_ARG;
+    if (c.pcg_variant < 0 || c.pcg_variant > 2) return QO_ERR_ARG;
+    // block CG: FP64 with the Jacobi preconditioner
+    if (c.pcg_variant == 2 && (c.precision != QO_FP64 || c.precond != 0)) return QO_ERR_ARG;
     if (c.pcg_variant == 1 && c.n[0] > 256) return QO_ERR_ARG;
     if (c.precond != 0 && c.precond != 1) return QO_ERR_ARG;
     if (c.precond == 1 && (c.pcg_variant != 0 || dst_plan_check(c.dim, c.n))) return QO_ERR_ARG;

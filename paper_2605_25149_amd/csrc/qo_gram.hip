@@ -75,14 +75,22 @@ __device__ __forceinline__ void tile_pair(int p, int nt, int &ti, int &tj) {
 }
 
 // One 64 x 64 tile pair of one K-chunk, FP64 MFMA (one wavefront).
+// CROSS: the n x n block X^T Y alone (tile (ti, tj) = pair / ntn, pair % ntn over X
+// columns x Y columns), partials n x n per split.
+template <bool CROSS = false>
 __device__ __forceinline__ void gram_f64_tile(const double *__restrict__ X,
                                               const double *__restrict__ Y, long ld, long ng,
                                               int n, long kchunk, double *__restrict__ part,
                                               int vec_ok, int pair, int split) {
-    const int nn = 2 * n;
+    const int nn = CROSS ? n : 2 * n;
     const int nt = (nn + TM - 1) / TM;
     int ti, tj;
-    tile_pair(pair, nt, ti, tj);
+    if (CROSS) {
+        ti = pair / nt;
+        tj = pair - ti * nt;
+    } else {
+        tile_pair(pair, nt, ti, tj);
+    }
     const long kb = (long)split * kchunk;
     const long ke = min(ng, kb + kchunk);
     const int lane = threadIdx.x;
@@ -97,8 +105,13 @@ __device__ __forceinline__ void gram_f64_tile(const double *__restrict__ X,
     for (int i = 0; i < 4; ++i) {
         const int ca = ti * TM + 16 * i + lr;
         const int cb = tj * TM + 16 * i + lr;
-        pa[i] = gptr(ca < nn ? zcol(X, Y, ld, n, ca) : X);
-        pb[i] = gptr(cb < nn ? zcol(X, Y, ld, n, cb) : X);
+        if (CROSS) {
+            pa[i] = gptr(X + (long)(ca < nn ? ca : 0) * ld);
+            pb[i] = gptr(Y + (long)(cb < nn ? cb : 0) * ld);
+        } else {
+            pa[i] = gptr(ca < nn ? zcol(X, Y, ld, n, ca) : X);
+            pb[i] = gptr(cb < nn ? zcol(X, Y, ld, n, cb) : X);
+        }
     }
     v4d acc[4][4];
 #pragma unroll
@@ -202,6 +215,29 @@ __global__ __launch_bounds__(64) void k_gram_f64(const double *__restrict__ X,
     const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int split = L / npairs;
     gram_f64_tile(X, Y, ld, ng, n, kchunk, part, vec_ok, L - split * npairs, split);
+}
+
+__global__ __launch_bounds__(64) void k_gram_cross_f64(const double *__restrict__ X,
+                                                       const double *__restrict__ Y, long ld,
+                                                       long ng, int n, long kchunk,
+                                                       double *__restrict__ part, int vec_ok) {
+    const int nt = (n + TM - 1) / TM;
+    const int npairs = nt * nt;
+    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int split = L / npairs;
+    gram_f64_tile<true>(X, Y, ld, ng, n, kchunk, part, vec_ok, L - split * npairs, split);
+}
+
+// G = w sum_s part[s] (n x n, no mirroring)
+__global__ void k_gram_cross_reduce(const double *__restrict__ part, int n, int nsplit, double w,
+                                    double *__restrict__ G) {
+    const long total = (long)n * n;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < nsplit; ++k) s += part[(long)k * total + e];
+        G[e] = w * s;
+    }
 }
 
 // Grouped batches: job blockIdx.z, (pair, split) from blockIdx.x.
@@ -440,6 +476,26 @@ hipError_t launch_gram_f64(const double *X, const double *Y, long ld, long ng, i
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return gram_reduce(part, 2 * n, nsplit, w, G, st);
+}
+
+hipError_t launch_gram_cross_f64(const double *X, const double *Y, long ld, long ng, int n,
+                                 double w, double *part, int nsplit, double *G, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int nt = (n + TM - 1) / TM;
+    long kchunk = (ng + nsplit - 1) / nsplit;
+    kchunk = (kchunk + 31) / 32 * 32;
+    const int vec_ok = (ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
+                       ((reinterpret_cast<uintptr_t>(Y) & 15) == 0);
+    hipLaunchKernelGGL(k_gram_cross_f64, dim3(nt * nt, nsplit), dim3(64), 0, st, X, Y, ld, ng, n,
+                       kchunk, part, vec_ok);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long total = (long)n * n;
+    long blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_gram_cross_reduce, dim3((unsigned)blocks), dim3(256), 0, st, part, n,
+                       nsplit, w, G);
+    return hipGetLastError();
 }
 
 hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, int n, double w,

@@ -155,6 +155,10 @@ hipError_t launch_refine_mask(const double *sums, int ncols, double tol, double 
 // gram_part_elems(n, nsplit) doubles.
 size_t gram_part_elems(int n, int nsplit);
 int gram_nsplit(long ng, int n);
+// G = w X^T Y (n x n, column-major), FP64 MFMA split over nsplit row chunks; part holds
+// nsplit n x n partials (gram_part_elems(n, nsplit) suffices)
+hipError_t launch_gram_cross_f64(const double *X, const double *Y, long ld, long ng, int n,
+                                 double w, double *part, int nsplit, double *G, hipStream_t st);
 hipError_t launch_gram_f64(const double *X, const double *Y, long ld, long ng, int n,
                            double w, double *part, int nsplit, double *G, hipStream_t st);
 // BF16 tiles: [X Y] is first rounded to BF16 into zb (2n x ld, 16-byte aligned, ld a

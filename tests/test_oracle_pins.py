@@ -573,3 +573,46 @@ def test_energy_matrix_identities(oracle_mod):
         K = Kh - tau * (Sh @ Oc + Oc @ Sh) + tau ** 2 * Oc @ L["A"].T @ Oc
         K_ref = prob.inner(orc.U, prob.apply(orc.U))
         assert np.max(np.abs(K - K_ref)) <= 1e-11 * np.max(np.abs(K_ref))
+
+
+def test_block_cg_pins(oracle_mod):
+    """Reading R19, O'Leary block PCG (Jacobi) in the oracle:
+    * the solution equals sparse LU within 1e-9 and every true residual is <= 5 tol (the
+      stop test reads the recursive residual, which drifts from the true one by a few
+      units of eps cond(H) over the iterations: ~3e-12 here at tol 1e-12);
+    * with one column it is textbook Jacobi-PCG: same iteration count as the oracle's
+      column solver and the same iterate (1e-12);
+    * finite termination: on a 24-point grid with 4 right-hand sides the block Krylov space
+      is full after ceil(24 / 4) = 6 iterations (two more allowed for rounding), where a
+      single column needs more;
+    * on a 2-D 32^2 grid its block iteration count is at most the largest column count."""
+    O_ = oracle_mod
+    n = (20, 17)
+    V = inputs.harmonic(n, 100.0) + inputs.gaussian_wells(n, seed=3, depth=(1.0, 4.0))
+    prob = O_.Problem(2, n, V, sigma=0.3)
+    Bm = inputs.random_block(prob.ng, 5, seed=4)
+    X, it, st = prob.solve_block_cg(Bm, tol=1e-12)
+    assert st == O_.ORC_OK
+    Xr = prob.solve_direct(Bm)
+    assert np.max(np.abs(X - Xr)) <= 1e-9 * np.max(np.abs(Xr))
+    res = np.linalg.norm(Bm - prob.apply(X), axis=0) / np.linalg.norm(Bm, axis=0)
+    assert np.all(res <= 5e-12)
+
+    b1 = Bm[:, :1]
+    X1, it1, st1 = prob.solve_block_cg(b1, tol=1e-10)
+    Xc, itc, stc, _ = prob.solve(b1, tol=1e-10)
+    assert st1 == O_.ORC_OK and stc == O_.ORC_OK
+    assert int(it1[0]) == int(itc[0])
+    assert np.max(np.abs(X1 - Xc)) <= 1e-12 * np.max(np.abs(Xc))
+
+    tiny = O_.Problem(2, (6, 4), inputs.harmonic((6, 4), 30.0), sigma=0.0)
+    Bt = inputs.random_block(24, 4, seed=5)
+    _, itb, stb = tiny.solve_block_cg(Bt, tol=1e-10)
+    _, itcol, _, _ = tiny.solve(Bt, tol=1e-10)
+    assert stb == O_.ORC_OK and int(itb.max()) <= 8 < int(itcol.max())
+
+    p32 = O_.Problem(2, (32, 32), inputs.harmonic((32, 32), 100.0))
+    B32 = inputs.random_block(1024, 8, seed=6)
+    _, itb, _ = p32.solve_block_cg(B32, tol=1e-10)
+    _, itcol, _, _ = p32.solve(B32, tol=1e-10)
+    assert int(itb.max()) <= int(itcol.max())

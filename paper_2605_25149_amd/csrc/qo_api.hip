@@ -90,6 +90,8 @@ struct qo_ctx {
     float *dmu = nullptr, *pcs = nullptr, *z32 = nullptr;
     double *z64 = nullptr, *rzp = nullptr, *dsum = nullptr;
     double mu0 = 0.0;  // mu_x[0] + mu_y[0] (+ mu_z[0]): smallest eigenvalue of -Lap_h
+    // the FP32 correction d32 is all zero (the fast-Poisson refinement relies on it)
+    bool d32_clean = true;
     // block CG (pcg_variant 2): Z and ping-pong partners of X, R, P; small matrices;
     // per-column norms and active flags
     double *bcgb[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -345,9 +347,12 @@ qo_status precondition(qo_ctx *c, const T *R, T *Z, int ncols, int k, double tol
 // PCG on all columns of B (ld c->ld) into X, precision T: Jacobi, or the
 // fast-Poisson preconditioner when c->dst.
 template <typename T>
+// skip_init: R already holds the residual, X is zero and the partial sums of ||r||^2 and
+// of the norm the stop test is relative to sit in s.part (+qs, +2qs); B is not read.
+// Only with the fast-Poisson preconditioner (the Jacobi form also needs r.D r).
 qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *P0, T *P1,
               int ncols, int use_x0, double tol, const int *mask, const double *coltol,
-              int *its_out, const char *what) {
+              int *its_out, const char *what, bool skip_init = false) {
     const Grid &g = c->g;
     hipStream_t st = c->st;
     PcgState s = c->ps;
@@ -355,7 +360,8 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
     HIPC(c, hipMemsetAsync(s.its, 0, sizeof(int) * ncols, st));
     int init_err[2] = {0, INT_MAX};
     HIPC(c, hipMemcpyAsync(s.err, init_err, sizeof init_err, hipMemcpyHostToDevice, st));
-    HIPC(c, launch_pcg_init<T>(g, vs, dinv, B, X, R, c->ld, ncols, use_x0, s.part, st));
+    if (!(skip_init && c->dst))
+        HIPC(c, launch_pcg_init<T>(g, vs, dinv, B, X, R, c->ld, ncols, use_x0, s.part, st));
     T *pbuf[2] = {P0, P1};
     const int check = c->cfg.pcg_check;
     const int maxit = c->cfg.pcg_maxit;
@@ -835,16 +841,32 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
         if (round >= max_rounds)
             return fail(c, QO_ERR_PCG_NOCONV, "%s: refinement did not reach tol %.3g in %d rounds",
                         what, tol, max_rounds);
-        if (one_sweep)
+        if (one_sweep) {
             QOC(pcg_cg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->rr32, c->rr32b, c->pa32,
                               c->pb32, ncols, 0, c->cfg.refine_inner_tol, c->mask, c->coltol,
                               inner.data(), what));
-        else
+        } else if (c->dst) {
+            // The FP32 solve works on r32 in place (the next round recomputes it) and skips
+            // its init pass: d32 is zero (cleared by the previous update), and ||r||^2 from
+            // the residual pass serves as both the starting residual and the norm the inner
+            // stop test is relative to.
+            if (!c->d32_clean)
+                HIPC(c, hipMemsetAsync(c->d32, 0, sizeof(float) * c->ld * c->N, st));
+            c->d32_clean = false;  // until the update below clears it again
+            HIPC(c, hipMemcpyAsync(c->part + 2 * qs, c->part + qs, sizeof(double) * qs,
+                                   hipMemcpyDeviceToDevice, st));
+            QOC(pcg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->r32, c->pa32, c->pb32,
+                           ncols, 0, c->cfg.refine_inner_tol, c->mask, c->coltol, inner.data(),
+                           what, true));
+        } else {
             QOC(pcg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->rr32, c->pa32, c->pb32,
                            ncols, 0, c->cfg.refine_inner_tol, c->mask, c->coltol, inner.data(),
                            what));
+        }
         for (int j = 0; j < ncols; ++j) its[j] += inner[j];
-        HIPC(c, launch_refine_axpy(X, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, 0, st));
+        HIPC(c, launch_refine_axpy(X, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, c->dst ? 1 : 0,
+                                   st));
+        if (c->dst) c->d32_clean = true;
     }
     return QO_OK;
 }

@@ -1572,6 +1572,7 @@ qo_status qo_run(qo_handle h, double tau, double tau_max, int max_steps, double 
             HIPC(h, hipStreamSynchronize(h->st));
             h->cur = cur0;
             h->have_warm = ss == QO_OK ? true : warm0;
+            h->have_K = false;  // a propagated K belongs to the undone step
             h->have_Es = hasE0;
             h->last_Es = E0;
             h->nstep = n0;

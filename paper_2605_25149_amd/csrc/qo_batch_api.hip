@@ -302,41 +302,50 @@ qo_status group_solve_mixed(qo_batch_ctx *b, qo_batch_ctx::Group &G, const doubl
     return QO_OK;
 }
 
+// One group's share of a step, on the group's stream.
+qo_status group_step_enqueue(qo_batch_ctx *b, qo_batch_ctx::Group &G, int par) {
+    hipStream_t st = G.st;
+    double *P = G.PQ[par], *Q = G.PQ[par ^ 1];
+    if (G.mixed) BQO(group_solve_mixed(b, G, G.U, P, 0));
+    else BQO(group_pcg(b, G, G.U, P, 0));
+    BHIP(b, launch_gram_f64_batch(G.gjob[par][0], G.ninst, G.max_gram_grid, G.ld, G.ng, G.w, st));
+    BHIP(b, launch_nn_predict(G.njob, G.ninst, G.max_n, st));
+    BHIP(b, launch_tsgemm_batch(G.tjob[par][0], G.ninst, G.max_n, G.ld, G.ng, st));
+    BHIP(b, launch_tsgemm_batch(G.tjob[par][1], G.ninst, G.max_n, G.ld, G.ng, st));
+    if (G.mixed) BQO(group_solve_mixed(b, G, G.Uh, Q, 1));
+    else BQO(group_pcg(b, G, G.Uh, Q, 1));
+    BHIP(b, launch_gram_f64_batch(G.gjob[par][1], G.ninst, G.max_gram_grid, G.ld, G.ng, G.w, st));
+    BHIP(b, launch_nn_correct(G.njob, G.ninst, st));
+    BHIP(b, launch_tsgemm_batch(G.tjob[par][2], G.ninst, G.max_n, G.ld, G.ng, st));
+    BHIP(b, launch_quad(G.g, G.vs, G.U, G.ld, G.C, G.part, st));
+    BHIP(b, launch_instance_energy(G.part, G.qs, G.g.tiles(), G.coff, G.ninst, G.w, G.energy, st));
+    return QO_OK;
+}
+
 // One step of every group without host synchronisation.  Groups are independent: the
 // first runs on the batch stream, every other one on a stream of its own that forks from
 // the batch stream and joins it again at the end, so the small groups' launches overlap
-// the large ones (captured graphs keep this as parallel branches).
+// the large ones (captured graphs keep this as parallel branches).  The joins are made
+// even when a group's enqueue fails, so no stream is left forked (or in a capture).
 qo_status batch_step_enqueue(qo_batch_ctx *b, int par) {
     const size_t ng = b->groups.size();
     if (ng > 1) {
         BHIP(b, hipEventRecord(b->ev_fork, b->st));
         for (size_t k = 1; k < ng; ++k) BHIP(b, hipStreamWaitEvent(b->groups[k].st, b->ev_fork, 0));
     }
+    qo_status first = QO_OK;
     for (auto &G : b->groups) {
-        hipStream_t st = G.st;
-        double *P = G.PQ[par], *Q = G.PQ[par ^ 1];
-        if (G.mixed) BQO(group_solve_mixed(b, G, G.U, P, 0));
-        else BQO(group_pcg(b, G, G.U, P, 0));
-        BHIP(b, launch_gram_f64_batch(G.gjob[par][0], G.ninst, G.max_gram_grid, G.ld, G.ng, G.w,
-                                      st));
-        BHIP(b, launch_nn_predict(G.njob, G.ninst, G.max_n, st));
-        BHIP(b, launch_tsgemm_batch(G.tjob[par][0], G.ninst, G.max_n, G.ld, G.ng, st));
-        BHIP(b, launch_tsgemm_batch(G.tjob[par][1], G.ninst, G.max_n, G.ld, G.ng, st));
-        if (G.mixed) BQO(group_solve_mixed(b, G, G.Uh, Q, 1));
-        else BQO(group_pcg(b, G, G.Uh, Q, 1));
-        BHIP(b, launch_gram_f64_batch(G.gjob[par][1], G.ninst, G.max_gram_grid, G.ld, G.ng, G.w,
-                                      st));
-        BHIP(b, launch_nn_correct(G.njob, G.ninst, st));
-        BHIP(b, launch_tsgemm_batch(G.tjob[par][2], G.ninst, G.max_n, G.ld, G.ng, st));
-        BHIP(b, launch_quad(G.g, G.vs, G.U, G.ld, G.C, G.part, st));
-        BHIP(b, launch_instance_energy(G.part, G.qs, G.g.tiles(), G.coff, G.ninst, G.w, G.energy,
-                                       st));
+        const qo_status s = group_step_enqueue(b, G, par);
+        if (s != QO_OK && first == QO_OK) first = s;
+        if (first != QO_OK) break;
     }
     for (size_t k = 1; k < ng; ++k) {
-        BHIP(b, hipEventRecord(b->ev_join[k], b->groups[k].st));
-        BHIP(b, hipStreamWaitEvent(b->st, b->ev_join[k], 0));
+        const hipError_t e1 = hipEventRecord(b->ev_join[k], b->groups[k].st);
+        const hipError_t e2 = hipStreamWaitEvent(b->st, b->ev_join[k], 0);
+        if ((e1 != hipSuccess || e2 != hipSuccess) && first == QO_OK)
+            first = bfail(b, QO_ERR_DEVICE, "stream join failed");
     }
-    return QO_OK;
+    return first;
 }
 
 qo_status build_group(qo_batch_ctx *b, qo_batch_ctx::Group &G) {

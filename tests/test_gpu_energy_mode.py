@@ -72,3 +72,32 @@ def test_energy_mode_errors(torch, B):
             s.energy_mode(1, -1)
         s.energy_mode(1, 3)
         s.energy_mode(0)
+
+
+def test_propagated_energy_with_adaptive_undo(torch, B):
+    """Algorithm 1 with the adaptive step (qo_run with tau_max, which undoes and halves a
+    step whose E_sigma rises or whose ||O|| grows): the propagated energy restarts from the
+    stencil after every undo, so each accepted step's E_sigma matches the stencil-energy
+    run within 1e-10 relative and the run reaches the same eigenvalues."""
+    n, N = (32, 32), 4
+    V = inputs.harmonic(n, 100.0)
+    U0 = inputs.random_block(1024, N, seed=1)
+    lam1 = 12.9544687
+    out = {}
+    for mode in (0, 1):
+        with B.Solver(2, n, N, pcg_tol=1e-12) as s:
+            s.set_potential(V)
+            s.set_state(U0)
+            if mode:
+                s.energy_mode(1, 0)
+            energies, tau, steps, conv = [], 0.3 * lam1, 0, False
+            while steps < 2000 and not conv:
+                k, tau, conv, st = s.run(tau, 1, grad_tol=1e-6, tau_max=3.0 * lam1)
+                steps += k
+                if k:
+                    energies.append(st["energy_shifted"])
+            out[mode] = (np.array(energies), s.eigenpairs("ritz"), conv)
+    (e0, l0, c0), (e1, l1, c1) = out[0], out[1]
+    assert c0 and c1 and len(e0) == len(e1)
+    assert np.max(np.abs(e1 - e0) / np.abs(e0)) <= 1e-10
+    np.testing.assert_allclose(l1, l0, rtol=1e-12)

@@ -1,6 +1,7 @@
-"""Parity at the benchmark's full size and launch configuration: 3-D 96^3 Gaussian wells
+"""Parity at full size: the benchmark's launch configuration, 3-D 96^3 Gaussian wells
 (Ng = 884,736), N = 256, fast-Poisson PCG at tol 1e-10 polled every iteration, warm starts,
-in FP64 and in mixed precision (FP32 PCG in FP64 refinement, BF16 Grams).
+in FP64 and in mixed precision (FP32 PCG in FP64 refinement, BF16 Grams); and the FP64
+Jacobi configuration, 64^3 wells (Ng = 262,144), N = 64, Jacobi PCG at tol 1e-10.
 
 The oracle cannot take such a step in seconds (its PCG alone would need minutes), so the
 third step from the random start is checked stage by stage against what it computes
@@ -26,10 +27,14 @@ from paper_2605_25149_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-N_SIDE, N_COLS = 96, 256
 TOL = 1e-10
 # 0.9 x the lowest eigenvalue of the same potential on a 32^3 grid (a lower bound here)
 TAU = 0.9 * 10.0685
+CASES = [  # side, N, precision, preconditioner
+    (96, 256, "fp64", "fast_poisson"),
+    (96, 256, "mixed", "fast_poisson"),
+    (64, 64, "fp64", "jacobi"),
+]
 
 
 @pytest.fixture(scope="module")
@@ -49,19 +54,25 @@ def B():
     return binding
 
 
-@pytest.fixture(scope="module")
-def data():
-    n = (N_SIDE,) * 3
-    V = inputs.gaussian_wells(n, seed=0)
-    U0 = inputs.random_block(int(np.prod(n)), N_COLS, seed=1)
-    return n, V, U0
+_DATA = {}
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_fullsize_step_stages(torch, B, oracle_mod, data, precision):
-    n, V, U0 = data
-    with B.Solver(3, n, N_COLS, pcg_tol=TOL, pcg_maxit=5000, pcg_check=1, precision=precision,
-                  refine_inner_tol=1e-5, precond="fast_poisson") as s:
+def _data(side, N):
+    if (side, N) not in _DATA:
+        _DATA.clear()
+        n = (side,) * 3
+        V = inputs.gaussian_wells(n, seed=0)
+        U0 = inputs.random_block(int(np.prod(n)), N, seed=1)
+        _DATA[(side, N)] = (n, V, U0)
+    return _DATA[(side, N)]
+
+
+@pytest.mark.parametrize("side,N_COLS,precision,precond", CASES)
+def test_fullsize_step_stages(torch, B, oracle_mod, side, N_COLS, precision, precond):
+    n, V, U0 = _data(side, N_COLS)
+    with B.Solver(3, n, N_COLS, pcg_tol=TOL, pcg_maxit=5000,
+                  pcg_check=1 if precond == "fast_poisson" else 8, precision=precision,
+                  refine_inner_tol=1e-5, precond=precond) as s:
         s.set_potential(V)
         s.set_state(U0)
         s.step(TAU, 2)

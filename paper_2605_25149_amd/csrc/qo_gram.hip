@@ -18,6 +18,7 @@
 
 #include <type_traits>
 
+
 namespace qo {
 
 namespace {
@@ -45,22 +46,18 @@ __device__ __forceinline__ const double *zcol(const double *X, const double *Y, 
 // bits (one rounding, no FP32 intermediate).  Magnitudes below the FP32
 // normal range flush to signed zero; beyond it saturate to infinity.
 __device__ __forceinline__ __bf16 f64_to_bf16_rne(double d) {
+    // Straight-line form: the rounded magnitude's bits 45..59 are the exponent and the
+    // 7 kept mantissa bits; rebiased to BF16, values below its normal range go to zero
+    // and values beyond it (infinity included) to infinity; NaN becomes the quiet NaN.
     const unsigned long long b = __double_as_longlong(d);
-    const unsigned int sign = (unsigned int)(b >> 63);
-    const int e = (int)((b >> 52) & 0x7ff);
-    unsigned short out;
-    if (e == 0x7ff) {  // inf / nan
-        out = (unsigned short)((sign << 15) | 0x7f80 | (((b & 0xfffffffffffffull) != 0) ? 0x40 : 0));
-    } else {
-        const unsigned long long lsb = (b >> 45) & 1ull;
-        const unsigned long long mag = (b & 0x7fffffffffffffffull) + 0xfffffffffffull + lsb;
-        int ef = (int)(mag >> 52) - 1023 + 127;
-        const unsigned int m7 = (unsigned int)((mag >> 45) & 0x7f);
-        if (e == 0 || ef <= 0) out = (unsigned short)(sign << 15);
-        else if (ef >= 255) out = (unsigned short)((sign << 15) | 0x7f80);
-        else out = (unsigned short)((sign << 15) | ((unsigned)ef << 7) | m7);
-    }
-    return __builtin_bit_cast(__bf16, out);
+    const unsigned long long mag =
+        (b & 0x7fffffffffffffffull) + 0xfffffffffffull + ((b >> 45) & 1ull);
+    int v = (int)(unsigned int)(mag >> 45) - ((1023 - 127) << 7);
+    v = v < 0x80 ? 0 : v;
+    v = min(v, 0x7f80);
+    v = __builtin_isnan(d) ? 0x7fc0 : v;
+    const unsigned int s16 = (unsigned int)(b >> 48) & 0x8000u;
+    return __builtin_bit_cast(__bf16, (unsigned short)(s16 | (unsigned int)v));
 }
 
 // Decode the upper-triangular tile pair index.
@@ -283,92 +280,107 @@ __global__ __launch_bounds__(256) void k_pack_bf16(const double *__restrict__ X,
     }
 }
 
-// Gram tiles from the packed BF16 block: one wavefront, one 64 x 64 tile pair, one
-// K-chunk; the next 32-row step's fragments are loaded before the current step's MFMAs.
-__global__ __launch_bounds__(64) void k_gram_bf16(const __bf16 *__restrict__ Zb, long ld,
-                                                  long ng, int n, long kchunk,
-                                                  double *__restrict__ part) {
-    const int nn = 2 * n;
-    const int nt = (nn + TM - 1) / TM;
-    // pairs of one K-chunk on one XCD: they read the same rows of the 2n columns
-    const int npairs = nt * (nt + 1) / 2;
-    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    const int split = L / npairs;
-    int ti, tj;
-    tile_pair(L - split * npairs, nt, ti, tj);
-    const long kb = (long)split * kchunk;
-    // rows ng..ld-1 of Zb are zero and ld is a multiple of 64: whole 32-row steps
-    const long ke = min(ld, (min(ng, kb + kchunk) + 31) / 32 * 32);
-    const int lane = threadIdx.x;
-    const int lr = lane & 15, lg = lane >> 4;
+// Gram tiles from the packed BF16 block, 256-column super-tiles: one 1024-thread
+// workgroup per (super-tile pair, K-chunk) stages each 32-row step of its two super-tiles
+// in LDS (each thread copies 16 rows of one column), and its 16 waves each run the 16
+// MFMAs of one 64 x 64 tile pair from LDS.  A column is fetched by the super-tile pairs it
+// belongs to (2 for 2n = 512) instead of by every tile pair (8 to 9), and two steps of
+// loads are in flight beyond the one in LDS.
+constexpr int kSuper = 256;  // columns per super-tile
 
-    // Columns beyond 2n read column 0 (their products only reach entries that are never
-    // stored), so the loads are unconditional and the compiler can keep them in flight.
+__global__ __launch_bounds__(1024) void k_gram_bf16_super(const __bf16 *__restrict__ Zb, long ld,
+                                                          long ng, int n, long kchunk,
+                                                          double *__restrict__ part) {
+    // [buffer][super-tile a/b][column][32 rows]: a column's step is 64 bytes
+    __shared__ __align__(16) __bf16 sm[2][2][kSuper][32];
+    const int nn = 2 * n;
+    const int nst = (nn + kSuper - 1) / kSuper;
+    const int nsp = nst * (nst + 1) / 2;
+    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int split = L / nsp;
+    int TI, TJ;
+    tile_pair(L - split * nsp, nst, TI, TJ);
+    // rows ng..ld-1 of Zb are zero and ld is a multiple of 64: whole 32-row steps
+    const long kb = (long)split * kchunk;
+    const long ke = min(ld, (min(ng, kb + kchunk) + 31) / 32 * 32);
+    const int nsteps = ke > kb ? (int)((ke - kb) >> 5) : 0;
+    const int tid = threadIdx.x;
+    const bool two = TI != TJ;
+    // copying: thread -> super-tile lt (the second one only off the diagonal), column lc,
+    // rows 16 lh .. 16 lh + 15 of the step (two 16-byte loads)
+    const int lt = tid >> 9, lc = (tid >> 1) & (kSuper - 1), lh = tid & 1;
+    const bool loader = lt == 0 || two;
     typedef const v8bf __attribute__((address_space(1))) gv8bf;
-    gv8bf *pa[4];
-    gv8bf *pb[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int ca = ti * TM + 16 * i + lr;
-        const int cb = tj * TM + 16 * i + lr;
-        pa[i] = (gv8bf *)(Zb + (long)(ca < nn ? ca : 0) * ld + 8 * lg);
-        pb[i] = (gv8bf *)(Zb + (long)(cb < nn ? cb : 0) * ld + 8 * lg);
+    gv8bf *src;
+    {
+        const int c = (lt ? TJ : TI) * kSuper + lc;
+        // columns past 2n read column 0: their products reach only entries never stored
+        src = (gv8bf *)(Zb + (long)(c < nn ? c : 0) * ld + kb + 16 * lh);
     }
+    // steps past the end re-read the last one (their values are never stored)
+    auto gload = [&](int s, v8bf (&r)[2]) {
+        const int sc = s < nsteps ? s : nsteps - 1;
+        r[0] = src[4 * sc];
+        r[1] = src[4 * sc + 1];
+    };
+    auto sstore = [&](int buf, const v8bf (&r)[2]) {
+        if (loader) {
+            *reinterpret_cast<v8bf *>(&sm[buf][lt][lc][16 * lh]) = r[0];
+            *reinterpret_cast<v8bf *>(&sm[buf][lt][lc][16 * lh + 8]) = r[1];
+        }
+    };
+    // compute: wave w -> tile pair (a, b) of the super-tile pair; on a diagonal super-tile
+    // pair only a <= b is needed
+    const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+    const int a = w >> 2, b = w & 3;
+    const int ti = TI * 4 + a, tj = TJ * 4 + b;
+    const bool active = (two || a <= b) && ti * TM < nn && tj * TM < nn;
+    const int sb = two ? 1 : 0;
     v4f acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-    // k0 advances in bf16 elements; one v8bf covers 8 rows, so the row offset is k0 / 8
-    auto load = [&](long k0, v8bf (&a)[4], v8bf (&b)[4]) {
+    auto mma = [&](int buf) {
+        if (!active) return;
+        v8bf fb[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            fb[j] = *reinterpret_cast<const v8bf *>(&sm[buf][sb][b * 64 + 16 * j + lr][8 * lg]);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            a[i] = pa[i][k0 >> 3];
-            b[i] = pb[i][k0 >> 3];
-        }
-    };
-    auto mma = [&](const v8bf (&a)[4], const v8bf (&b)[4]) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
+            const v8bf fa =
+                *reinterpret_cast<const v8bf *>(&sm[buf][0][a * 64 + 16 * i + lr][8 * lg]);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    };
-    // 32-row chunks, four in flight: a chunk's 16 MFMAs are far shorter than a load's
-    // latency.  Past the end the prefetch re-reads the final chunk; the scheduling
-    // barriers keep the loads ahead of the MFMAs they overlap.
-    const long nch = ke > kb ? (ke - kb) >> 5 : 0;
-    auto chunk = [&](long c) { return kb + 32 * (c < nch ? c : nch - 1); };
-    if (nch > 0) {
-        v8bf a0[4], b0[4], a1[4], b1[4], a2[4], b2[4], a3[4], b3[4];
-        load(chunk(0), a0, b0);
-        load(chunk(1), a1, b1);
-        load(chunk(2), a2, b2);
-        const long nq = nch >> 2;
-        for (long q = 0; q < nq; ++q) {
-            const long c = q << 2;
-            load(chunk(c + 3), a3, b3);
-            __builtin_amdgcn_sched_barrier(0);
-            mma(a0, b0);
-            __builtin_amdgcn_sched_barrier(0);
-            load(chunk(c + 4), a0, b0);
-            __builtin_amdgcn_sched_barrier(0);
-            mma(a1, b1);
-            __builtin_amdgcn_sched_barrier(0);
-            load(chunk(c + 5), a1, b1);
-            __builtin_amdgcn_sched_barrier(0);
-            mma(a2, b2);
-            __builtin_amdgcn_sched_barrier(0);
-            load(chunk(c + 6), a2, b2);
-            __builtin_amdgcn_sched_barrier(0);
-            mma(a3, b3);
-            __builtin_amdgcn_sched_barrier(0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
         }
-        const long rem = nch & 3;  // chunks 4 nq .. 4 nq + rem - 1 sit in a0, a1, a2
-        if (rem > 0) mma(a0, b0);
-        if (rem > 1) mma(a1, b1);
-        if (rem > 2) mma(a2, b2);
+    };
+    if (nsteps > 0) {
+        // step s sits in LDS buffer s & 1 while steps s + 1 (in r0 or r1) and s + 2 load
+        v8bf r0[2], r1[2];
+        gload(0, r0);
+        sstore(0, r0);
+        gload(1, r0);
+        __syncthreads();
+        int s = 0;
+        for (; s + 2 <= nsteps; s += 2) {
+            gload(s + 2, r1);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(0);
+            __builtin_amdgcn_sched_barrier(0);
+            sstore(1, r0);
+            __syncthreads();
+            gload(s + 3, r0);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(1);
+            __builtin_amdgcn_sched_barrier(0);
+            sstore(0, r1);
+            __syncthreads();
+        }
+        if (s < nsteps) mma(0);  // odd step count: the last step sits in buffer 0
     }
+    if (!active) return;
     double *out = part + (long)split * nn * nn;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -501,8 +513,9 @@ hipError_t launch_gram_cross_f64(const double *X, const double *Y, long ld, long
 hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, int n, double w,
                             double *part, int nsplit, double *G, __bf16 *zb, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    // packed rows need 16-byte alignment: ld a multiple of 8, 16-byte aligned operands
-    if (ld % 8 != 0 || (reinterpret_cast<uintptr_t>(X) & 15) || (reinterpret_cast<uintptr_t>(Y) & 15) ||
+    // packed rows are read in whole 32-row steps of 16-byte loads: ld a multiple of 32,
+    // 16-byte aligned operands
+    if (ld % 32 != 0 || (reinterpret_cast<uintptr_t>(X) & 15) || (reinterpret_cast<uintptr_t>(Y) & 15) ||
         (reinterpret_cast<uintptr_t>(zb) & 15))
         return hipErrorInvalidValue;
     const long items = 2L * n * (ld / 8);
@@ -511,12 +524,14 @@ hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, 
     hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)blocks), dim3(256), 0, st, X, Y, ld, ng, n, zb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nt = (2 * n + TM - 1) / TM;
-    const int npairs = nt * (nt + 1) / 2;
+    // one 1024-thread workgroup per CU: enough K-chunks for one round over 256 CUs
+    const int nst = (2 * n + kSuper - 1) / kSuper;
+    const int nsp = nst * (nst + 1) / 2;
+    nsplit = max(1, min(nsplit, 256 / nsp));
     long kchunk = (ng + nsplit - 1) / nsplit;
     kchunk = (kchunk + 31) / 32 * 32;
-    hipLaunchKernelGGL(k_gram_bf16, dim3(npairs, nsplit), dim3(64), 0, st, zb, ld, ng, n, kchunk,
-                       part);
+    hipLaunchKernelGGL(k_gram_bf16_super, dim3(nsp, nsplit), dim3(1024), 0, st, zb, ld, ng, n,
+                       kchunk, part);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return gram_reduce(part, 2 * n, nsplit, w, G, st);

@@ -162,7 +162,8 @@ hipError_t launch_gram_cross_f64(const double *X, const double *Y, long ld, long
 hipError_t launch_gram_f64(const double *X, const double *Y, long ld, long ng, int n,
                            double w, double *part, int nsplit, double *G, hipStream_t st);
 // BF16 tiles: [X Y] is first rounded to BF16 into zb (2n x ld, 16-byte aligned, ld a
-// multiple of 8; rows ng..ld-1 zero), then the tiles accumulate in FP32 per K-chunk.
+// multiple of 32; rows ng..ld-1 zero), then 256-column super-tile pairs accumulate in FP32
+// per K-chunk.
 hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, int n,
                             double w, double *part, int nsplit, double *G, __bf16 *zb,
                             hipStream_t st);

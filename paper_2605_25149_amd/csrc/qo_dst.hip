@@ -349,136 +349,226 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
 
 // ---------------------------------------------------------------- pencil pass
 //
-// Workgroup = MB consecutive in-plane positions m of one column, all ns
-// slices along the slowest axis.  Wave w owns slowest-axis rows [16w, 16w+16).
-//   GEMM1  Yh = S_s X   (X staged transposed: m-major, slice index contiguous)
+// Job = 64 consecutive in-plane positions m of one column, all ns slices along the
+// slowest axis.  A workgroup of NSP / 16 waves works through jobs (persistent: the
+// grid is sized to the resident workgroups); wave w owns slowest-axis rows
+// [16w, 16w+16) and keeps its rows of S_s (symmetric, so the same A operand serves
+// both products) in registers across jobs.
+//   GEMM1  Yh = S_s X   (X staged m-major: slice index contiguous per position)
 //   scale  Yh[s][m] *= lmin / (kappa (mu_f(m) + mu_s(s)) + vbar)
 //   GEMM2  Z  = S_s Yh
-template <int NJ>
-__global__ __launch_bounds__(1024) void k_dst_pencil(DstPlan p, const _Float16 *__restrict__ Hin,
-                                                     _Float16 *__restrict__ Hout, long ld,
-                                                     const float *__restrict__ pcs) {
+// Thread t moves slices 2 (t >> 3), 2 (t >> 3) + 1 of positions 8 (t & 7) .. + 7: two
+// 16-byte row accesses (eight lanes cover a 128-byte row segment), transposed in
+// registers into 4-byte LDS words.  The next job's rows are loaded during the current
+// job's products.  In the m-major LDS arrays the 16-byte blocks of row m are permuted by
+// XOR with (m >> 3) & 3, which spreads the transposing writes of rows 8 apart over the
+// banks and keeps the 16-byte operand reads contiguous.
+constexpr int kPenMB = 64;
+
+__device__ __forceinline__ int pen_off(int m, int s, int SP) {
+    return m * SP + ((((s >> 3) ^ (m >> 3)) & 3) | ((s >> 3) & ~3)) * 8 + (s & 7);
+}
+
+template <int KS>
+__global__ __launch_bounds__(128 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 3 ? 6 : 4))) void k_dst_pencil(DstPlan p, const _Float16 *__restrict__ Hin,
+                                                    _Float16 *__restrict__ Hout, long ld,
+                                                    int ncols, const float *__restrict__ pcs) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int MB = 16 * NJ;
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int col = L / p.npen;
-    const int pen = L - col * p.npen;
-    if (pcs[col] == 0.f) return;
-    const float vbar = p.cvbar ? p.cvbar[col] : p.vbar;
-    const float lmin = p.clmin ? p.clmin[col] : p.lmin;
-    const int NSP = p.NSP, SP = NSP + 8;
+    constexpr int NJ = kPenMB / 16;
+    constexpr int NSP = 32 * KS, SP = NSP + 8;
     const int ns = p.ns, nf = p.nf;
-    const int m0 = pen * MB;
     _Float16 *XT = reinterpret_cast<_Float16 *>(smem);
-    _Float16 *YT = XT + MB * SP;
-    const long base = (long)col * ld;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-
-    {
-        constexpr int G8 = MB / 8;
-        const int items = NSP * G8;
-        const bool vec = (nf % 8) == 0;
-        for (int it = tid; it < items; it += nthr) {
-            const int s = it / G8;
-            const int mm = (it - s * G8) * 8;
-            const int m = m0 + mm;
-            v8h h;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) h[i] = (_Float16)0.f;
-            if (s < ns) {
-                const _Float16 *src = Hin + base + (long)s * nf + m;
-                if (vec && m < nf) {
-                    h = *reinterpret_cast<const v8h *>(src);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (m + i < nf) h[i] = src[i];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) XT[(mm + i) * SP + s] = h[i];
-        }
-    }
+    _Float16 *YT = XT + kPenMB * SP;
+    // in-plane eigenvalues along x and y, copied once (the per-job lookups would otherwise
+    // each wait out a cache round trip)
+    float *MUX = reinterpret_cast<float *>(YT + kPenMB * SP);
+    float *MUY = MUX + 256;
+    // which columns this PCG iteration preconditions, so that finding the next job needs
+    // no global load
+    unsigned char *ACT = reinterpret_cast<unsigned char *>(MUY + 256);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < p.nx; i += blockDim.x) MUX[i] = p.mux[i];
+    if (p.dim == 3)
+        for (int i = tid; i < p.ny; i += blockDim.x) MUY[i] = p.muy[i];
+    for (int i = tid; i < ncols; i += blockDim.x) ACT[i] = pcs[i] != 0.f;
     __syncthreads();
-
     const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
-    const int KS = NSP / 32;
-    v4f acc[NJ];
+    const int mg = tid & 7, s0 = 2 * (tid >> 3);  // this thread's transfer item
+    const long njobs = (long)ncols * p.npen;
+    const bool vec = (nf % 8) == 0;
+
+    // S_s rows 16w + lr, k-chunks of 32: the A operand of both products
+    v8h A[KS];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < KS; ++ks) {
-        const v8h a = *reinterpret_cast<const v8h *>(p.Ss + (16 * w + lr) * NSP + 32 * ks + 8 * lg);
+    for (int ks = 0; ks < KS; ++ks)
+        A[ks] = *reinterpret_cast<const v8h *>(p.Ss + (16 * w + lr) * NSP + 32 * ks + 8 * lg);
+
+    // Jobs are dealt round-robin, so the workgroups resident at one time work on
+    // neighbouring positions of the same slices (DRAM pages stay open); columns the PCG
+    // skips are passed over.
+    auto next_active = [&](long job) {
+        while (job < njobs && !ACT[job / p.npen]) job += gridDim.x;
+        return job;
+    };
+    // rows s0, s0 + 1 at positions m .. m + 7 of a job; clamped unconditional loads in the
+    // vector case, the zeroing outside the grid happens at the LDS store (a select on a
+    // loaded value here would make the compiler wait for the prefetch at once)
+    v8h h0, h1;
+    auto job_m = [&](long job) {
+        const int col = (int)(job / p.npen);
+        return (int)(job - (long)col * p.npen) * kPenMB + 8 * mg;
+    };
+    auto load = [&](long job) {
+        const int col = (int)(job / p.npen);
+        const int m = job_m(job);
+        const _Float16 *src = Hin + (long)col * ld;
+        if (vec) {
+            const _Float16 *q = src + (m < nf ? m : 0);
+            h0 = *reinterpret_cast<const v8h *>(q + (long)min(s0, ns - 1) * nf);
+            h1 = *reinterpret_cast<const v8h *>(q + (long)min(s0 + 1, ns - 1) * nf);
+        } else {
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const v8h b = lds8(XT + (16 * j + lr) * SP + 32 * ks + 8 * lg);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[j], 0, 0, 0);
+            for (int i = 0; i < 8; ++i) {
+                const bool mi = m + i < nf;
+                h0[i] = (mi && s0 < ns) ? src[(long)s0 * nf + m + i] : (_Float16)0.f;
+                h1[i] = (mi && s0 + 1 < ns) ? src[(long)(s0 + 1) * nf + m + i] : (_Float16)0.f;
+            }
         }
-    }
-    // spectral scaling, then Yh^T into LDS
+    };
+    // slowest-axis eigenvalues of this thread's accumulator rows (the same for every job)
     float mus[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int s = 16 * w + 4 * lg + v;
         mus[v] = s < ns ? p.mus[s] : -1.f;
     }
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const int m = m0 + 16 * j + lr;
-        const float muf = m < nf ? mu_inplane(p, m) : -1.f;
-        v4h h;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            float f = 0.f;
-            if (muf >= 0.f && mus[v] >= 0.f) f = lmin / (p.kap * (muf + mus[v]) + vbar);
-            h[v] = (_Float16)(acc[j][v] * f);
-        }
-        *reinterpret_cast<v4h *>(YT + (16 * j + lr) * SP + 16 * w + 4 * lg) = h;
+
+    long job = next_active(blockIdx.x);
+    if (job >= njobs) return;
+    load(job);
+    float vb_next, lm_next;
+    {
+        const int c = (int)(job / p.npen);
+        vb_next = p.cvbar ? p.cvbar[c] : p.vbar;
+        lm_next = p.clmin ? p.clmin[c] : p.lmin;
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < KS; ++ks) {
-        const v8h a = *reinterpret_cast<const v8h *>(p.Ss + (16 * w + lr) * NSP + 32 * ks + 8 * lg);
+    while (true) {
+        // the next job is found before the barrier, so the prefetch after it need not
+        // wait for the activity flag
+        const long nxt = next_active(job + gridDim.x);
+        const int col = (int)(job / p.npen);
+        const int m0 = (int)(job - (long)col * p.npen) * kPenMB;
+        // per-column constants, read one job ahead (with the prefetch) and moved into
+        // scalar registers, so that no later use waits on the vector memory counter
+        const float vbar = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                         __builtin_bit_cast(int, vb_next)));
+        const float lmin = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                         __builtin_bit_cast(int, lm_next)));
+        if (nxt < njobs) {
+            const int cn = (int)(nxt / p.npen);
+            vb_next = p.cvbar ? p.cvbar[cn] : p.vbar;
+            lm_next = p.clmin ? p.clmin[cn] : p.lmin;
+        }
+        float muf[NJ];  // in-plane eigenvalue sums of this thread's positions (from LDS)
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const v8h b = lds8(YT + (16 * j + lr) * SP + 32 * ks + 8 * lg);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[j], 0, 0, 0);
-        }
-    }
-    // stage Z row-major ([s][m], pitch MB + 8) over XT and YT, then 16-byte stores
-    __syncthreads();  // every wave is done reading YT
-    constexpr int OP = MB + 8;
-    _Float16 *SO = XT;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) SO[(16 * w + 4 * lg + v) * OP + 16 * j + lr] = (_Float16)acc[j][v];
-    __syncthreads();
-    {
-        constexpr int G8 = MB / 8;
-        const bool vec = (nf % 8) == 0;
-        for (int it = tid; it < ns * G8; it += nthr) {
-            const int s = it / G8;
-            const int mm = (it - s * G8) * 8;
-            const int m = m0 + mm;
-            if (m >= nf) continue;
-            _Float16 *dst = Hout + base + (long)s * nf + m;
-            const _Float16 *src = SO + s * OP + mm;
-            if (vec) {
-                *reinterpret_cast<v8h *>(dst) = *reinterpret_cast<const v8h *>(src);
+            const int m = m0 + 16 * j + lr;
+            if (p.dim == 3) {
+                const int y = m / p.nx;
+                muf[j] = m < nf ? MUX[m - y * p.nx] + MUY[y] : -1.f;
             } else {
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    if (m + i < nf) dst[i] = src[i];
+                muf[j] = m < nf ? MUX[m] : -1.f;
             }
         }
+        // transpose into XT: word (s0, s0 + 1) of rows 8 mg + i
+        {
+            const bool mok = job_m(job) < nf;  // nf % 8 == 0 in the vector case
+            const bool oa = mok && s0 < ns, ob = mok && s0 + 1 < ns;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+                v2h pr;
+                pr[0] = oa ? h0[i] : (_Float16)0.f;
+                pr[1] = ob ? h1[i] : (_Float16)0.f;
+                *reinterpret_cast<v2h *>(XT + pen_off(8 * mg + i, s0, SP)) = pr;
+            }
+        }
+        __syncthreads();
+        if (nxt < njobs) load(nxt);  // in flight during the products below
+
+        v4f acc[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const v8h b = lds8(XT + pen_off(16 * j + lr, 32 * ks + 8 * lg, SP));
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[ks], b, acc[j], 0, 0, 0);
+            }
+        // spectral scaling, then Yh m-major into YT
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            v4h h;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float f = 0.f;
+                if (muf[j] >= 0.f && mus[v] >= 0.f) f = lmin / (p.kap * (muf[j] + mus[v]) + vbar);
+                h[v] = (_Float16)(acc[j][v] * f);
+            }
+            *reinterpret_cast<v4h *>(YT + pen_off(16 * j + lr, 16 * w + 4 * lg, SP)) = h;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const v8h b = lds8(YT + pen_off(16 * j + lr, 32 * ks + 8 * lg, SP));
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[ks], b, acc[j], 0, 0, 0);
+            }
+        // Z m-major into XT (every wave finished GEMM1 before the barrier above)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            v4h h;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) h[v] = (_Float16)acc[j][v];
+            *reinterpret_cast<v4h *>(XT + pen_off(16 * j + lr, 16 * w + 4 * lg, SP)) = h;
+        }
+        __syncthreads();
+        {
+            // rows s0, s0 + 1 of Z at positions m .. m + 7
+            const int m = m0 + 8 * mg;
+            v8h z0, z1;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+                const v2h pr = *reinterpret_cast<const v2h *>(XT + pen_off(8 * mg + i, s0, SP));
+                z0[i] = pr[0];
+                z1[i] = pr[1];
+            }
+            _Float16 *dst = Hout + (long)col * ld + m;
+            if (vec) {
+                if (m < nf) {
+                    if (s0 < ns) *reinterpret_cast<v8h *>(dst + (long)s0 * nf) = z0;
+                    if (s0 + 1 < ns) *reinterpret_cast<v8h *>(dst + (long)(s0 + 1) * nf) = z1;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    if (m + i >= nf) break;
+                    if (s0 < ns) dst[(long)s0 * nf + i] = z0[i];
+                    if (s0 + 1 < ns) dst[(long)(s0 + 1) * nf + i] = z1[i];
+                }
+            }
+        }
+        if (nxt >= njobs) break;
+        job = nxt;
+        __syncthreads();  // XT is rewritten by the next job
     }
 }
 
-#ifndef QO_PENCIL_NJ
-#define QO_PENCIL_NJ 4
-#endif
-constexpr int kPencilNJ = QO_PENCIL_NJ;  // MB = 16 NJ positions per pencil workgroup
 
 }  // namespace
 
@@ -518,7 +608,7 @@ void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz) {
         p.rows = 64;
         p.nslab = (ny + 63) / 64;
     }
-    p.npen = (p.nf + 16 * kPencilNJ - 1) / (16 * kPencilNJ);
+    p.npen = (p.nf + kPenMB - 1) / kPenMB;
 }
 
 // X (RP x (NXP+8) halves) and, in 3-D, TT (NXP x (NYP+8) halves); the inverse pass
@@ -534,7 +624,11 @@ size_t dst_plane_lds(const DstPlan &p, bool inv) {
     return b;
 }
 
-size_t dst_pencil_lds(const DstPlan &p) { return 2 * (size_t)16 * kPencilNJ * (p.NSP + 8) * 2; }
+// XT and YT (64 x (NSP + 8) halves each), the x and y eigenvalues (2 x 256 floats), then
+// one activity byte per column
+static size_t dst_pencil_lds(const DstPlan &p, int ncols) {
+    return 2 * (size_t)kPenMB * (p.NSP + 8) * 2 + 2 * 256 * 4 + (size_t)ncols;
+}
 
 hipError_t launch_dst_matrix(int n, int NP, _Float16 *S, hipStream_t st) {
     hipLaunchKernelGGL(k_dst_matrix, dim3(64), dim3(256), 0, st, n, NP, S);
@@ -585,13 +679,45 @@ hipError_t launch_dst_fwd(const DstPlan &p, const T *R, long ld, int ncols, _Flo
     return hipGetLastError();
 }
 
+// Persistent grid: as many workgroups as are resident at once (the runtime's occupancy for
+// this kernel and LDS size, times the CUs), cached per instantiation.
+template <int KS>
+static hipError_t launch_pencil_ks(const DstPlan &p, const _Float16 *t1, _Float16 *t2, long ld,
+                                   int ncols, const float *pcs, hipStream_t st) {
+    static int resident[2] = {0, 0};  // {dynamic LDS bytes it was taken for, workgroups}
+    const size_t lds = dst_pencil_lds(p, ncols);
+    const int block = 128 * KS;
+    if (resident[0] != (int)lds || resident[1] <= 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dst_pencil<KS>, block, lds);
+        if (e != hipSuccess) return e;
+        resident[0] = (int)lds;
+        resident[1] = std::max(1, per_cu) * std::max(1, cus);
+    }
+    const long njobs = (long)ncols * p.npen;
+    const unsigned grid = (unsigned)std::min<long>(njobs, resident[1]);
+    hipLaunchKernelGGL((k_dst_pencil<KS>), dim3(grid), dim3(block), lds, st, p, t1, t2, ld, ncols,
+                       pcs);
+    return hipGetLastError();
+}
+
 hipError_t launch_dst_pencil(const DstPlan &p, const _Float16 *t1, _Float16 *t2, long ld,
                              int ncols, const float *pcs, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
-    const dim3 grid((unsigned)(ncols * p.npen)), block((unsigned)(64 * (p.NSP / 16)));
-    hipLaunchKernelGGL((k_dst_pencil<kPencilNJ>), grid, block, dst_pencil_lds(p), st, p, t1, t2,
-                       ld, pcs);
-    return hipGetLastError();
+    switch (p.NSP / 32) {
+        case 1: return launch_pencil_ks<1>(p, t1, t2, ld, ncols, pcs, st);
+        case 2: return launch_pencil_ks<2>(p, t1, t2, ld, ncols, pcs, st);
+        case 3: return launch_pencil_ks<3>(p, t1, t2, ld, ncols, pcs, st);
+        case 4: return launch_pencil_ks<4>(p, t1, t2, ld, ncols, pcs, st);
+        case 5: return launch_pencil_ks<5>(p, t1, t2, ld, ncols, pcs, st);
+        case 6: return launch_pencil_ks<6>(p, t1, t2, ld, ncols, pcs, st);
+        case 7: return launch_pencil_ks<7>(p, t1, t2, ld, ncols, pcs, st);
+        case 8: return launch_pencil_ks<8>(p, t1, t2, ld, ncols, pcs, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>

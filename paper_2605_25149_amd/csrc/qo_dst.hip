@@ -144,6 +144,17 @@ __global__ __launch_bounds__(kThreads) void k_pc_prep(int k, int ncols, const in
     }
 }
 
+// Bytes of the plane pass's X (and, in 3-D, T^T) space in LDS, 16-byte aligned.
+__host__ __device__ inline size_t dst_plane_xt_bytes(const DstPlan &p) {
+    size_t b = (size_t)p.RP * (p.NXP + 8) * 2;
+#if QO_PLANE_ALIAS
+    if (p.dim == 3) b = b > (size_t)p.NXP * (p.NYP + 8) * 2 ? b : (size_t)p.NXP * (p.NYP + 8) * 2;
+#else
+    if (p.dim == 3) b += (size_t)p.NXP * (p.NYP + 8) * 2;
+#endif
+    return (b + 15) & ~(size_t)15;
+}
+
 // ---------------------------------------------------------------- plane pass
 //
 // Workgroup = one slab of one column: RP = 16 * waves padded rows of NXP
@@ -181,6 +192,23 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
     const int rows = min(p.rows, (p.dim == 3 ? p.ny : p.ny - row0));
     const long base = (long)col * ld + (p.dim == 3 ? (long)slab * nx * p.ny : (long)row0 * nx);
     const int tid = threadIdx.x, nthr = blockDim.x;
+
+    // S_x is the B operand of every wave: up to 128 points it is copied into LDS once per
+    // workgroup (pitch NXP + 8, conflict-free 16-byte reads) instead of each wave reading
+    // all of it through L2.  It sits after the X / T^T space; the inverse pass's FP32
+    // staging may later cover it (S_x is dead by then).
+    constexpr bool kSxLds = NT <= 8;
+    const _Float16 *SxL = nullptr;
+    if constexpr (kSxLds) {
+        _Float16 *dstS = reinterpret_cast<_Float16 *>(smem + dst_plane_xt_bytes(p));
+        const int g8 = NXP / 8;
+        for (int it = tid; it < NXP * g8; it += nthr) {
+            const int r = it / g8, c = (it - r * g8) * 8;
+            *reinterpret_cast<v8h *>(dstS + r * XP + c) =
+                *reinterpret_cast<const v8h *>(p.Sx + r * NXP + c);
+        }
+        SxL = dstS;  // the staging barrier below also covers this copy
+    }
 
     // ---- stage the slab into LDS as FP16 (zero padding)
     if (!INV) {
@@ -238,6 +266,15 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
 
     const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
     const int KX = NXP / 32;
+    // this wave's rows of S_y (the A operand of the y-transform; NYP <= 128 in 3-D),
+    // loaded now so that their latency overlaps the x-transform
+    v8h ay[4];
+    if (p.dim == 3) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            ay[ks] = *reinterpret_cast<const v8h *>(
+                p.Sy + (16 * w + lr) * p.NYP + 32 * min(ks, p.NYP / 32 - 1) + 8 * lg);
+    }
     v4f acc[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -245,7 +282,9 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
         const v8h a = lds8(X + (16 * w + lr) * XP + 32 * ks + 8 * lg);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const v8h b = *reinterpret_cast<const v8h *>(p.Sx + (16 * j + lr) * NXP + 32 * ks + 8 * lg);
+            const v8h b = kSxLds ? lds8(SxL + (16 * j + lr) * XP + 32 * ks + 8 * lg)
+                                 : *reinterpret_cast<const v8h *>(p.Sx + (16 * j + lr) * NXP +
+                                                                  32 * ks + 8 * lg);
             acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[j], 0, 0, 0);
         }
     }
@@ -261,12 +300,13 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
         const int KY = p.NYP / 32;
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-        for (int ks = 0; ks < KY; ++ks) {
-            const v8h a = *reinterpret_cast<const v8h *>(p.Sy + (16 * w + lr) * p.NYP + 32 * ks + 8 * lg);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            if (ks >= KY) break;
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
                 const v8h b = lds8(TT + (16 * j + lr) * TP + 32 * ks + 8 * lg);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ay[ks], b, acc[j], 0, 0, 0);
             }
         }
     }
@@ -614,12 +654,8 @@ void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz) {
 // X (RP x (NXP+8) halves) and, in 3-D, TT (NXP x (NYP+8) halves); the inverse pass
 // also stages its FP32 output (RP x (NXP+4) floats) over the same space.
 size_t dst_plane_lds(const DstPlan &p, bool inv) {
-    size_t b = (size_t)p.RP * (p.NXP + 8) * 2;
-#if QO_PLANE_ALIAS
-    if (p.dim == 3) b = std::max(b, (size_t)p.NXP * (p.NYP + 8) * 2);
-#else
-    if (p.dim == 3) b += (size_t)p.NXP * (p.NYP + 8) * 2;
-#endif
+    size_t b = dst_plane_xt_bytes(p);
+    if (p.NXP <= 128) b += (size_t)p.NXP * (p.NXP + 8) * 2;  // S_x copy
     if (inv) b = std::max(b, (size_t)p.RP * (p.NXP + 4) * 4);
     return b;
 }

@@ -553,7 +553,9 @@ __global__ __launch_bounds__(128 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 float f = 0.f;
-                if (muf[j] >= 0.f && mus[v] >= 0.f) f = lmin / (p.kap * (muf[j] + mus[v]) + vbar);
+                // hardware reciprocal (about 1 ulp): the product is rounded to FP16 next
+                if (muf[j] >= 0.f && mus[v] >= 0.f)
+                    f = lmin * __builtin_amdgcn_rcpf(p.kap * (muf[j] + mus[v]) + vbar);
                 h[v] = (_Float16)(acc[j][v] * f);
             }
             *reinterpret_cast<v4h *>(YT + pen_off(16 * j + lr, 16 * w + 4 * lg, SP)) = h;

@@ -734,7 +734,7 @@ inline size_t lds_bytes(const Grid &g, size_t elem) { return 2 * (size_t)(g.TY +
 // Points per thread per plane of a band of `pts` points (the instantiated set), -1 if none.
 int pick_ppt(int pts) {
     const int raw = (pts + kThreads - 1) / kThreads;
-    const int opts[5] = {1, 2, 4, 6, 8};
+    const int opts[6] = {1, 2, 3, 4, 6, 8};
     for (int o : opts)
         if (o >= raw) return o;
     return -1;

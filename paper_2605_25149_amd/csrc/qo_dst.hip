@@ -163,8 +163,12 @@ __host__ __device__ inline size_t dst_plane_xt_bytes(const DstPlan &p) {
 //   GEMM2  Y = S_y T     (3-D only; T staged transposed in LDS)
 // Forward: X = sc * r, output FP16.  Inverse: X = t2, output z = Y / (sc lmin)
 // in T, plus the slab's partial sum of r.z.
-template <typename T, bool INV, int NT>
-__global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restrict__ R,
+// VEC: rows are whole 16-byte groups (nx % 8 == 0): vector loads and stores throughout.
+// FP32 3-D planes (NT <= 8) are held to 80 registers: 6 waves per SIMD, four 6-wave
+// workgroups per CU, as many as their LDS allows.
+template <typename T, bool INV, int NT, bool VEC>
+__global__ __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_dst_plane(DstPlan p, const T *__restrict__ R,
                                                    const _Float16 *__restrict__ Hin,
                                                    _Float16 *__restrict__ Hout,
                                                    T *__restrict__ Z, long ld,
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
     const float sc = pcs[col];
     if (sc == 0.f) return;  // column converged or inactive (uniform over the block)
 
-    const int NXP = p.NXP, XP = NXP + 8;
+    constexpr int NXP = 16 * NT, XP = NXP + 8;  // the launch dispatches NT = NXP / 16
     const int nx = p.nx;
     _Float16 *X = reinterpret_cast<_Float16 *>(smem);
 #if QO_PLANE_ALIAS
@@ -193,72 +197,126 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
     const long base = (long)col * ld + (p.dim == 3 ? (long)slab * nx * p.ny : (long)row0 * nx);
     const int tid = threadIdx.x, nthr = blockDim.x;
 
+    // ---- stage the slab into LDS as FP16 (zero padding).  With nthr = 4 RP threads each
+    // thread owns exactly NT (forward, 4 values) or NT / 2 (inverse, 8 values) groups;
+    // all their loads are issued before the first value is used (unconditional loads
+    // from clamped addresses, out-of-grid groups zeroed at the conversion), so the slab
+    // costs one memory round trip instead of one per group.
+    constexpr int QF = NT, QI = NT / 2;
     // S_x is the B operand of every wave: up to 128 points it is copied into LDS once per
     // workgroup (pitch NXP + 8, conflict-free 16-byte reads) instead of each wave reading
-    // all of it through L2.  It sits after the X / T^T space; the inverse pass's FP32
-    // staging may later cover it (S_x is dead by then).
+    // all of it through L2.  Its first four rows of loads per thread go out with the
+    // slab's loads.  It sits after the X / T^T space; the inverse pass's FP32 staging may
+    // later cover it (S_x is dead by then).
     constexpr bool kSxLds = NT <= 8;
+    constexpr int kSxTotal = NXP * (NXP / 8);
+    _Float16 *dstS = reinterpret_cast<_Float16 *>(smem + dst_plane_xt_bytes(p));
+    v8h sxv[kSxLds ? 4 : 1];
+    if constexpr (kSxLds) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int it = min(tid + u * nthr, kSxTotal - 1);
+            const int r = it / (NXP / 8), c = (it - r * (NXP / 8)) * 8;
+            sxv[u] = *reinterpret_cast<const v8h *>(p.Sx + r * NXP + c);
+        }
+    }
+    T rv[INV ? 1 : QF][4];
+    v8h hv[INV ? QI : 1];
+    bool okq[INV ? QI : QF];
+    if constexpr (!INV) {
+        if constexpr (VEC) {
+#pragma unroll
+            for (int q = 0; q < QF; ++q) {
+                const int it = tid + q * nthr;
+                const int r = it / (NXP / 4);
+                const int x = (it - r * (NXP / 4)) * 4;
+                okq[q] = r < rows && x < nx;
+                const T *src = R + (okq[q] ? base + (long)r * nx + x : base);
+                if constexpr (sizeof(T) == 4) {
+                    const float4 v = *reinterpret_cast<const float4 *>(src);
+                    rv[q][0] = v.x; rv[q][1] = v.y; rv[q][2] = v.z; rv[q][3] = v.w;
+                } else {
+                    const double2 v0 = *reinterpret_cast<const double2 *>(src);
+                    const double2 v1 = *reinterpret_cast<const double2 *>(src + 2);
+                    rv[q][0] = v0.x; rv[q][1] = v0.y; rv[q][2] = v1.x; rv[q][3] = v1.y;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < QF; ++q) {
+                const int it = tid + q * nthr;
+                const int r = it / (NXP / 4);
+                const int x = (it - r * (NXP / 4)) * 4;
+                okq[q] = r < rows && x < nx;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    rv[q][i] = (okq[q] && x + i < nx) ? R[base + (long)r * nx + x + i] : T(0);
+            }
+        }
+    } else {
+        if constexpr (VEC) {
+#pragma unroll
+            for (int q = 0; q < QI; ++q) {
+                const int it = tid + q * nthr;
+                const int r = it / (NXP / 8);
+                const int x = (it - r * (NXP / 8)) * 8;
+                okq[q] = r < rows && x < nx;
+                hv[q] = *reinterpret_cast<const v8h *>(
+                    Hin + (okq[q] ? base + (long)r * nx + x : base));
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < QI; ++q) {
+                const int it = tid + q * nthr;
+                const int r = it / (NXP / 8);
+                const int x = (it - r * (NXP / 8)) * 8;
+                okq[q] = r < rows && x < nx;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    hv[q][i] = (okq[q] && x + i < nx) ? Hin[base + (long)r * nx + x + i]
+                                                      : (_Float16)0.f;
+            }
+        }
+    }
     const _Float16 *SxL = nullptr;
     if constexpr (kSxLds) {
-        _Float16 *dstS = reinterpret_cast<_Float16 *>(smem + dst_plane_xt_bytes(p));
-        const int g8 = NXP / 8;
-        for (int it = tid; it < NXP * g8; it += nthr) {
-            const int r = it / g8, c = (it - r * g8) * 8;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int it = tid + u * nthr;
+            if (it < kSxTotal) {
+                const int r = it / (NXP / 8), c = (it - r * (NXP / 8)) * 8;
+                *reinterpret_cast<v8h *>(dstS + r * XP + c) = sxv[u];
+            }
+        }
+        for (int it = tid + 4 * nthr; it < kSxTotal; it += nthr) {  // small workgroups only
+            const int r = it / (NXP / 8), c = (it - r * (NXP / 8)) * 8;
             *reinterpret_cast<v8h *>(dstS + r * XP + c) =
                 *reinterpret_cast<const v8h *>(p.Sx + r * NXP + c);
         }
         SxL = dstS;  // the staging barrier below also covers this copy
     }
 
-    // ---- stage the slab into LDS as FP16 (zero padding)
-    if (!INV) {
-        const int groups = p.RP * (NXP / 4);
-        const bool vec = (nx % 4) == 0;
-        for (int it = tid; it < groups; it += nthr) {
+    if constexpr (!INV) {
+#pragma unroll
+        for (int q = 0; q < QF; ++q) {
+            const int it = tid + q * nthr;
             const int r = it / (NXP / 4);
             const int x = (it - r * (NXP / 4)) * 4;
-            float v[4] = {0.f, 0.f, 0.f, 0.f};
-            if (r < rows) {
-                const T *src = R + base + (long)r * nx + x;
-                if (vec && x < nx) {
-                    if constexpr (sizeof(T) == 4) {
-                        const float4 q = *reinterpret_cast<const float4 *>(src);
-                        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-                    } else {
-                        const double2 q0 = *reinterpret_cast<const double2 *>(src);
-                        const double2 q1 = *reinterpret_cast<const double2 *>(src + 2);
-                        v[0] = (float)q0.x; v[1] = (float)q0.y; v[2] = (float)q1.x; v[3] = (float)q1.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        if (x + i < nx) v[i] = (float)src[i];
-                }
-            }
             v4h h;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) h[i] = (_Float16)(v[i] * sc);
+            for (int i = 0; i < 4; ++i)
+                h[i] = okq[q] ? (_Float16)((float)rv[q][i] * sc) : (_Float16)0.f;
             *reinterpret_cast<v4h *>(X + r * XP + x) = h;
         }
     } else {
-        const int groups = p.RP * (NXP / 8);
-        const bool vec = (nx % 8) == 0;
-        for (int it = tid; it < groups; it += nthr) {
+#pragma unroll
+        for (int q = 0; q < QI; ++q) {
+            const int it = tid + q * nthr;
             const int r = it / (NXP / 8);
             const int x = (it - r * (NXP / 8)) * 8;
             v8h h;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) h[i] = (_Float16)0.f;
-            if (r < rows) {
-                const _Float16 *src = Hin + base + (long)r * nx + x;
-                if (vec && x < nx) {
-                    h = *reinterpret_cast<const v8h *>(src);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (x + i < nx) h[i] = src[i];
-                }
-            }
+            for (int i = 0; i < 8; ++i) h[i] = okq[q] ? hv[q][i] : (_Float16)0.f;
             *reinterpret_cast<v8h *>(X + r * XP + x) = h;
         }
     }
@@ -323,14 +381,14 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
                 ST[(16 * w + 4 * lg + v) * XP + 16 * j + lr] = (_Float16)acc[j][v];
         __syncthreads();
         const int g8 = NXP / 8;
-        const bool vec = (nx % 8) == 0;
+        constexpr bool vec = VEC;
         for (int it = tid; it < rows * g8; it += nthr) {
             const int r = it / g8;
             const int x = (it - r * g8) * 8;
             if (x >= nx) continue;
             _Float16 *dst = Hout + base + (long)r * nx + x;
             const _Float16 *src = ST + r * XP + x;
-            if (vec) {
+            if constexpr (vec) {
                 *reinterpret_cast<v8h *>(dst) = *reinterpret_cast<const v8h *>(src);
             } else {
 #pragma unroll
@@ -350,29 +408,49 @@ __global__ __launch_bounds__(512) void k_dst_plane(DstPlan p, const T *__restric
         __syncthreads();
         double rz = 0.0;
         const int g4 = NXP / 4;
-        const bool vec = (nx % 4) == 0;
-        for (int it = tid; it < rows * g4; it += nthr) {
-            const int r = it / g4;
-            const int x = (it - r * g4) * 4;
-            if (x >= nx) continue;
-            const long i0 = base + (long)r * nx + x;
-            const float *src = SF + r * FP + x;
-            if (vec) {
-                const float4 z4 = *reinterpret_cast<const float4 *>(src);
+        if constexpr (VEC) {
+            // each thread owns at most NT groups of 4 (rows * NXP / 4 <= NT * nthr): their
+            // r loads are issued together (clamped into the slab), then z is stored and
+            // r.z accumulated
+            T rr[QF][4];
+#pragma unroll
+            for (int q = 0; q < QF; ++q) {
+                const int it = tid + q * nthr;
+                const int r = it / g4, x = (it - r * g4) * 4;
+                const bool ok = r < rows && x < nx;
+                const long i0 = ok ? base + (long)r * nx + x : base;
+                if constexpr (sizeof(T) == 4) {
+                    const float4 v = *reinterpret_cast<const float4 *>(R + i0);
+                    rr[q][0] = v.x; rr[q][1] = v.y; rr[q][2] = v.z; rr[q][3] = v.w;
+                } else {
+                    const double2 v0 = *reinterpret_cast<const double2 *>(R + i0);
+                    const double2 v1 = *reinterpret_cast<const double2 *>(R + i0 + 2);
+                    rr[q][0] = v0.x; rr[q][1] = v0.y; rr[q][2] = v1.x; rr[q][3] = v1.y;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < QF; ++q) {
+                const int it = tid + q * nthr;
+                const int r = it / g4, x = (it - r * g4) * 4;
+                if (r >= rows || x >= nx) continue;
+                const long i0 = base + (long)r * nx + x;
+                const float4 z4 = *reinterpret_cast<const float4 *>(SF + r * FP + x);
                 if constexpr (sizeof(T) == 4) {
                     *reinterpret_cast<float4 *>(Z + i0) = z4;
-                    const float4 r4 = *reinterpret_cast<const float4 *>(R + i0);
-                    rz += (double)r4.x * z4.x + (double)r4.y * z4.y + (double)r4.z * z4.z +
-                          (double)r4.w * z4.w;
                 } else {
-                    const double2 za{z4.x, z4.y}, zb{z4.z, z4.w};
-                    *reinterpret_cast<double2 *>(Z + i0) = za;
-                    *reinterpret_cast<double2 *>(Z + i0 + 2) = zb;
-                    const double2 ra = *reinterpret_cast<const double2 *>(R + i0);
-                    const double2 rb = *reinterpret_cast<const double2 *>(R + i0 + 2);
-                    rz += ra.x * za.x + ra.y * za.y + rb.x * zb.x + rb.y * zb.y;
+                    *reinterpret_cast<double2 *>(Z + i0) = double2{z4.x, z4.y};
+                    *reinterpret_cast<double2 *>(Z + i0 + 2) = double2{z4.z, z4.w};
                 }
-            } else {
+                rz += (double)rr[q][0] * (double)(T)z4.x + (double)rr[q][1] * (double)(T)z4.y +
+                      (double)rr[q][2] * (double)(T)z4.z + (double)rr[q][3] * (double)(T)z4.w;
+            }
+        } else {
+            for (int it = tid; it < rows * g4; it += nthr) {
+                const int r = it / g4;
+                const int x = (it - r * g4) * 4;
+                if (x >= nx) continue;
+                const long i0 = base + (long)r * nx + x;
+                const float *src = SF + r * FP + x;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     if (x + i >= nx) break;
@@ -711,9 +789,15 @@ hipError_t launch_dst_fwd(const DstPlan &p, const T *R, long ld, int ncols, _Flo
                           const float *pcs, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
     const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
-    QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, false, NT>), grid, block,
-                                                  dst_plane_lds(p, false), st, p, R, nullptr, t1,
-                                                  nullptr, ld, pcs, nullptr));
+    if (p.nx % 8 == 0) {
+        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, false, NT, true>), grid,
+                                                      block, dst_plane_lds(p, false), st, p, R,
+                                                      nullptr, t1, nullptr, ld, pcs, nullptr));
+    } else {
+        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, false, NT, false>), grid,
+                                                      block, dst_plane_lds(p, false), st, p, R,
+                                                      nullptr, t1, nullptr, ld, pcs, nullptr));
+    }
     return hipGetLastError();
 }
 
@@ -763,9 +847,15 @@ hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, const T *R, T *Z
                           int ncols, const float *pcs, double *rzp, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
     const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
-    QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, true, NT>), grid, block,
-                                                  dst_plane_lds(p, true), st, p, R, t2, nullptr, Z,
-                                                  ld, pcs, rzp));
+    if (p.nx % 8 == 0) {
+        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, true, NT, true>), grid,
+                                                      block, dst_plane_lds(p, true), st, p, R, t2,
+                                                      nullptr, Z, ld, pcs, rzp));
+    } else {
+        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, true, NT, false>), grid,
+                                                      block, dst_plane_lds(p, true), st, p, R, t2,
+                                                      nullptr, Z, ld, pcs, rzp));
+    }
     return hipGetLastError();
 }
 

@@ -188,22 +188,46 @@ __global__ __launch_bounds__(GPT) void k_gjb_panel(double *__restrict__ A, int l
     const int tid = threadIdx.x;
     if (*status) return;  // an earlier panel failed
     double *scal = work + (size_t)n * GB + GB * GB;
+    // The panel's loads (n b <= 8192 values: at most 16 per thread) are all issued before
+    // any is used, so the panel costs one memory round trip, not one per value.
+    constexpr int PQ = (GB * kGjBlockedMax / 2) / GPT;
+    const int nb = n * b;
+    double pv[PQ];
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+        const int e = min(tid + q * GPT, nb - 1);
+        const int kk = e / n, i = e - kk * n;
+        pv[q] = A[(long)(k0 + kk) * lda + i];
+    }
+    // SPD test threshold: 1e-13 of the largest diagonal entry of the input, reduced over
+    // the workgroup on the first panel and kept for the later ones
+    double md = 0.0;
+    if (k0 == 0 && spd) {
+        for (int i = tid; i < n; i += GPT) md = fmax(md, fabs(A[(long)i * lda + i]));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) md = fmax(md, __shfl_xor(md, off, 64));
+        if ((tid & 63) == 0) sval[tid >> 6] = md;
+    }
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+        const int e = tid + q * GPT;
+        if (e < nb) {
+            W[e] = pv[q];
+            O[e] = pv[q];
+        }
+    }
+    __syncthreads();
     if (tid == 0) {
         fail_sh = 0;
         if (k0 == 0) {
-            // SPD test threshold: 1e-13 of the largest diagonal entry of the input
-            double md = 0.0;
+            double m = 0.0;
             if (spd)
-                for (int i = 0; i < n; ++i) md = fmax(md, fabs(A[(long)i * lda + i]));
-            scal[0] = 1e-13 * md;
+                for (int w = 0; w < GPT / 64; ++w) m = fmax(m, sval[w]);
+            scal[0] = 1e-13 * m;
+            thr_sh = 1e-13 * m;
+        } else {
+            thr_sh = scal[0];
         }
-        thr_sh = scal[0];
-    }
-    for (int e = tid; e < n * b; e += GPT) {
-        const int kk = e / n, i = e - kk * n;
-        const double v = A[(long)(k0 + kk) * lda + i];
-        W[e] = v;
-        O[e] = v;
     }
     __syncthreads();
     for (int kk = 0; kk < b; ++kk) {
@@ -306,6 +330,8 @@ __global__ __launch_bounds__(256) void k_gjb_update(double *__restrict__ A, int 
     extern __shared__ double usm[];
     double *X = usm;              // n x GCW, column c at X + c * n
     double *Y = usm + n * GCW;    // b x GCW
+    double *OL = Y + b * GCW;     // the panel O (n x b), then P^{-1} (b x b)
+    double *PL = OL + n * b;
     if (*status) return;
     const int tid = threadIdx.x;
     const int jbeg = k0 + b;
@@ -316,10 +342,22 @@ __global__ __launch_bounds__(256) void k_gjb_update(double *__restrict__ A, int 
         const int j = jbeg + c0 + c;
         return j < n ? A + (long)j * lda : B + (long)(j - n) * ldb;
     };
-    for (int e = tid; e < n * cw; e += 256) {
-        const int c = e / n, i = e - c * n;
-        X[c * n + i] = colp(c)[i];
-    }
+    // Copies into LDS with eight loads per thread in flight before their stores (a load
+    // used at once would cost a memory round trip per value).  O and P^{-1} come from L2
+    // once per workgroup instead of once per product term.
+    auto stage = [&](double *dst, int count, auto src) {
+        for (int e0 = tid; e0 < count; e0 += 8 * 256) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src(min(e0 + u * 256, count - 1));
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e0 + u * 256 < count) dst[e0 + u * 256] = v[u];
+        }
+    };
+    stage(X, n * cw, [&](int e) { const int c = e / n; return colp(c)[e - c * n]; });
+    stage(OL, n * b, [&](int e) { return work[e]; });
+    stage(PL, b * b, [&](int e) { return work[(size_t)n * GB + e]; });
     __syncthreads();
     if (tid < cw) {
         double *x = X + tid * n;
@@ -333,12 +371,11 @@ __global__ __launch_bounds__(256) void k_gjb_update(double *__restrict__ A, int 
         }
     }
     __syncthreads();
-    const double *Pinv = work + (size_t)n * GB;
     for (int e = tid; e < b * cw; e += 256) {
         const int c = e / b, r = e - c * b;
         const double *x = X + c * n + k0;
         double s = 0.0;
-        for (int q = 0; q < b; ++q) s += Pinv[q * b + r] * x[q];
+        for (int q = 0; q < b; ++q) s += PL[q * b + r] * x[q];
         Y[c * b + r] = s;
     }
     __syncthreads();
@@ -350,7 +387,7 @@ __global__ __launch_bounds__(256) void k_gjb_update(double *__restrict__ A, int 
             v = y[i - k0];
         } else {
             double s = 0.0;
-            for (int q = 0; q < b; ++q) s += work[(size_t)q * n + i] * y[q];
+            for (int q = 0; q < b; ++q) s += OL[q * n + i] * y[q];
             v = X[c * n + i] - s;
         }
         colp(c)[i] = v;
@@ -612,8 +649,9 @@ hipError_t nn_gj_solve(double *A, int lda, double *B, int ldb, int n, int m, boo
         const int ncol = (n - k0 - b) + m;
         if (ncol > 0)
             hipLaunchKernelGGL(k_gjb_update, dim3((ncol + GCW - 1) / GCW), dim3(256),
-                               sizeof(double) * (size_t)(n + b) * GCW, st, A, lda, B, ldb, n, m,
-                               k0, b, work, piv, status);
+                               sizeof(double) * ((size_t)(n + b) * GCW + (size_t)n * b +
+                                                 (size_t)b * b),
+                               st, A, lda, B, ldb, n, m, k0, b, work, piv, status);
     }
     return hipGetLastError();
 }

@@ -12,6 +12,10 @@
 // 64 (grid rows) x 64 (columns) tile.
 #include "qo_internal.h"
 
+#ifndef QO_TSG_KSC
+#define QO_TSG_KSC 2
+#endif
+
 namespace qo {
 
 namespace {
@@ -69,11 +73,12 @@ __device__ __forceinline__ void tsgemm_tile(double *__restrict__ Out, long ldo,
         coff[j] = c < n ? c : n - 1;
     }
     auto pass = [&](const double *Tp, const double *Sp) {
+        constexpr int KSC = QO_TSG_KSC, KC = 4 * KSC;  // MFMA k-steps and k-values per chunk
         gdouble *__restrict__ T = gptr(Tp);
         gdouble *__restrict__ S = gptr(Sp);
-        auto load_chunk = [&](int kc, double (&sa)[4][4], double (&tb)[4][4]) {
+        auto load_chunk = [&](int kc, double (&sa)[KSC][4], double (&tb)[KSC][4]) {
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
+            for (int ks = 0; ks < KSC; ++ks) {
                 const long k = kc + 4 * ks + lg;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) sa[ks][j] = S[k * n + coff[j]];
@@ -81,9 +86,9 @@ __device__ __forceinline__ void tsgemm_tile(double *__restrict__ Out, long ldo,
                 for (int i = 0; i < 4; ++i) tb[ks][i] = T[k * ld + moff[i]];
             }
         };
-        auto mma_chunk = [&](const double (&sa)[4][4], const double (&tb)[4][4]) {
+        auto mma_chunk = [&](const double (&sa)[KSC][4], const double (&tb)[KSC][4]) {
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
+            for (int ks = 0; ks < KSC; ++ks)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -91,29 +96,29 @@ __device__ __forceinline__ void tsgemm_tile(double *__restrict__ Out, long ldo,
                         acc[j][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[ks][j], tb[ks][i],
                                                                         acc[j][i], 0, 0, 0);
         };
-        const int nfull = n & ~15;
-        double sa0[4][4], tb0[4][4], sa1[4][4], tb1[4][4];
+        const int nfull = n & ~(KC - 1);
+        double sa0[KSC][4], tb0[KSC][4], sa1[KSC][4], tb1[KSC][4];
         if (nfull > 0) {
             // past the end the prefetch re-reads the final chunk
-            const int last = nfull - 16;
-            const int npairs = nfull >> 5;
+            const int last = nfull - KC;
+            const int npairs = nfull / (2 * KC);
             load_chunk(0, sa0, tb0);
             for (int p = 0; p < npairs; ++p) {
-                const int kc = p << 5;
-                load_chunk(kc + 16, sa1, tb1);
+                const int kc = p * 2 * KC;
+                load_chunk(kc + KC, sa1, tb1);
                 __builtin_amdgcn_sched_barrier(0);
                 mma_chunk(sa0, tb0);
                 __builtin_amdgcn_sched_barrier(0);
-                load_chunk(min(kc + 32, last), sa0, tb0);
+                load_chunk(min(kc + 2 * KC, last), sa0, tb0);
                 __builtin_amdgcn_sched_barrier(0);
                 mma_chunk(sa1, tb1);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (nfull & 16) mma_chunk(sa0, tb0);
+            if (nfull & KC) mma_chunk(sa0, tb0);
         }
         if (nfull < n) {
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
+            for (int ks = 0; ks < KSC; ++ks) {
                 const int k = nfull + 4 * ks + lg;
                 const bool kin = k < n;
                 const long kk = kin ? k : n - 1;
@@ -146,7 +151,7 @@ __device__ __forceinline__ void tsgemm_tile(double *__restrict__ Out, long ldo,
         }
 }
 
-__global__ __launch_bounds__(64) void k_tsgemm(double *__restrict__ Out, long ldo,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_tsgemm(double *__restrict__ Out, long ldo,
                                                const double *__restrict__ C0,
                                                const double *__restrict__ A,
                                                const double *__restrict__ Xr,

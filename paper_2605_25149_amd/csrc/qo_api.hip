@@ -90,8 +90,6 @@ struct qo_ctx {
     float *dmu = nullptr, *pcs = nullptr, *z32 = nullptr;
     double *z64 = nullptr, *rzp = nullptr, *dsum = nullptr;
     double mu0 = 0.0;  // mu_x[0] + mu_y[0] (+ mu_z[0]): smallest eigenvalue of -Lap_h
-    // the FP32 correction d32 is all zero (the fast-Poisson refinement relies on it)
-    bool d32_clean = true;
     // block CG (pcg_variant 2): Z and ping-pong partners of X, R, P; small matrices;
     // per-column norms and active flags
     double *bcgb[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -393,20 +391,22 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
         }
         hipEvent_t eb = prof_begin(c);
         HIPC(c, launch_pcg_sweep2<T>(g, vs, dinv, pbuf[k & 1], X, R, c->ld, ncols, k, s, st,
-                                     Z == nullptr));
+                                     Z == nullptr, k == 0 && skip_init && Z != nullptr));
         prof_end(c, k2, eb);
     }
     HIPC(c, hipMemcpyAsync(c->h_poll, s.its, sizeof(int) * ncols, hipMemcpyDeviceToHost, st));
     HIPC(c, hipStreamSynchronize(st));
     prof_harvest(c);
     double colits = 0.0;
+    int started = 0;  // columns whose first second sweep ran (x = 0 then: 4 of 5 arrays)
     for (int j = 0; j < ncols; ++j) {
         its_out[j] = c->h_poll[j];
         colits += c->h_poll[j];
+        started += c->h_poll[j] > 0 ? 1 : 0;
     }
     if (c->prof) {
         c->pdata.work[k1] += colits;
-        c->pdata.work[k2] += colits;
+        c->pdata.work[k2] += colits - ((skip_init && Z) ? 0.2 * started : 0.0);
         if (Z)
             for (int kid : {(int)QO_KERNEL_DST_FWD, (int)QO_KERNEL_DST_PENCIL, (int)QO_KERNEL_DST_INV})
                 c->pdata.work[kid] += colits;
@@ -847,12 +847,10 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
                               inner.data(), what));
         } else if (c->dst) {
             // The FP32 solve works on r32 in place (the next round recomputes it) and skips
-            // its init pass: d32 is zero (cleared by the previous update), and ||r||^2 from
-            // the residual pass serves as both the starting residual and the norm the inner
-            // stop test is relative to.
-            if (!c->d32_clean)
-                HIPC(c, hipMemsetAsync(c->d32, 0, sizeof(float) * c->ld * c->N, st));
-            c->d32_clean = false;  // until the update below clears it again
+            // its init pass: it starts from d = 0 without clearing d (its first update
+            // writes d = alpha p instead of adding), and ||r||^2 from the residual pass
+            // serves as both the starting residual and the norm the inner stop test is
+            // relative to.
             HIPC(c, hipMemcpyAsync(c->part + 2 * qs, c->part + qs, sizeof(double) * qs,
                                    hipMemcpyDeviceToDevice, st));
             QOC(pcg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->r32, c->pa32, c->pb32,
@@ -864,9 +862,10 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
                            what));
         }
         for (int j = 0; j < ncols; ++j) its[j] += inner[j];
-        HIPC(c, launch_refine_axpy(X, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, c->dst ? 1 : 0,
-                                   st));
-        if (c->dst) c->d32_clean = true;
+        // With the fast-Poisson solve d was written only in columns that took at least one
+        // inner iteration (the others hold an older correction): those alone are updated.
+        HIPC(c, launch_refine_axpy(X, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, 0, st,
+                                   (c->dst && !one_sweep) ? c->ps.its : nullptr));
     }
     return QO_OK;
 }

@@ -110,9 +110,11 @@ hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T 
                              const int *mask, PcgState s, hipStream_t st, const T *Z = nullptr,
                              const double *rzp = nullptr, int rzt = 0);
 template <typename T>
+// xzero: X is zero on entry (first iteration without an init pass; preconditioned form
+// only): X = alpha p is written without reading X.
 hipError_t launch_pcg_sweep2(const Grid &g, const T *vs, const T *dinv, const T *Pn, T *X, T *R,
                              long ld, int ncols, int k, PcgState s, hipStream_t st,
-                             bool jac = true);
+                             bool jac = true, bool xzero = false);
 
 // One-reduction (Chronopoulos-Gear) PCG: delta0 = u.Hu with u = D r0 into
 // part[3] (after launch_pcg_init on the same grid), then one sweep per iteration.
@@ -130,9 +132,11 @@ size_t cg_lds_bytes(const Grid &g, size_t elem);
 hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long qstride,
                          double *out, hipStream_t st);
 
-// x += d (FP64 += FP32) for columns with mask != 0 (and d = 0 when zero_d).
+// x += d (FP64 += FP32) for columns with mask != 0 (and d = 0 when zero_d); with its, only
+// for the columns whose inner solve took at least one iteration (its[c] > 0).
 hipError_t launch_refine_axpy(double *X, long ld, float *D, long ld32, long ng, int ncols,
-                              const int *mask, int zero_d, hipStream_t st);
+                              const int *mask, int zero_d, hipStream_t st,
+                              const int *its = nullptr);
 // Reliable updates of the mixed-precision solve (see qo_stencil.hip).
 hipError_t launch_resid_rel(const Grid &g, const double *vs, const float *dinv32, const double *B,
                             const double *X, long ld, float *R32, int ncols, const int *mask,

@@ -515,7 +515,9 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__rest
 // x += alpha p; r -= alpha H p; partials r.D r (JAC: Jacobi form only) and r.r.
 // x and r are each read and written once per sweep: non-temporal accesses keep
 // them from evicting the stencil operand's halo rows from the caches.
-template <typename T, bool JAC>
+// XZ: x is known to be zero (the first iteration of a solve that starts from x = 0 without
+// an init pass): it is written, not read.
+template <typename T, bool JAC, bool XZ = false>
 struct EpSweep2 {
     struct Raw { T x, r, d; };
     T *__restrict__ x;
@@ -526,10 +528,10 @@ struct EpSweep2 {
     __device__ static Raw zero() { return {T(0), T(0), T(0)}; }
     __device__ Raw load(long i) const {
 #if QO_SWEEP2_NT
-        return {__builtin_nontemporal_load(x + i), __builtin_nontemporal_load(r + i),
+        return {XZ ? T(0) : __builtin_nontemporal_load(x + i), __builtin_nontemporal_load(r + i),
                 JAC ? dinv[i] : T(0)};
 #else
-        return {x[i], r[i], JAC ? dinv[i] : T(0)};
+        return {XZ ? T(0) : x[i], r[i], JAC ? dinv[i] : T(0)};
 #endif
     }
     __device__ void operator()(int, long i, T c, T hv, const Raw &e) {
@@ -547,7 +549,7 @@ struct EpSweep2 {
     }
 };
 
-template <typename T, int PPT, bool JAC>
+template <typename T, int PPT, bool JAC, bool XZ = false>
 __global__ __launch_bounds__(kThreads) void k_pcg_sweep2(Grid g, const T *__restrict__ vs,
                                                          const T *__restrict__ dinv,
                                                          const T *__restrict__ Pn,
@@ -578,7 +580,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep2(Grid g, const T *__rest
     if (sh_flag) return;
     const T alpha = (T)(s.rho[cur * ncols + col] / gam);
     LdPlain<T> l{Pn + (long)col * ld};
-    EpSweep2<T, JAC> ep{X + (long)col * ld, R + (long)col * ld, dinv, alpha, {0.0, 0.0}};
+    EpSweep2<T, JAC, XZ> ep{X + (long)col * ld, R + (long)col * ld, dinv, alpha, {0.0, 0.0}};
     engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
     block_sums<2>(ep.acc, red);
     if (threadIdx.x == 0) {
@@ -625,9 +627,10 @@ __global__ void k_colsum(const double *__restrict__ part, int tiles, int ncols, 
 }
 
 __global__ void k_refine_axpy(double *__restrict__ X, long ld, float *__restrict__ D,
-                              long ld32, long ng, const int *__restrict__ mask, int zero_d) {
+                              long ld32, long ng, const int *__restrict__ mask, int zero_d,
+                              const int *__restrict__ its) {
     const int c = blockIdx.y;
-    if (!mask[c]) return;
+    if (!mask[c] || (its && its[c] == 0)) return;
     double *x = X + (long)c * ld;
     float *d = D + (long)c * ld32;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ng;
@@ -807,10 +810,18 @@ hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T 
 
 template <typename T>
 hipError_t launch_pcg_sweep2(const Grid &g, const T *vs, const T *dinv, const T *Pn, T *X, T *R,
-                             long ld, int ncols, int k, PcgState s, hipStream_t st, bool jac) {
+                             long ld, int ncols, int k, PcgState s, hipStream_t st, bool jac,
+                             bool xzero) {
     if (ncols <= 0) return hipSuccess;
     const long qs = (long)ncols * g.tiles();
     const dim3 grid(ncols * g.tiles());
+    if (xzero && !jac) {
+        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep2<T, P, false, true>), grid,
+                                                   dim3(kThreads), lds_bytes(g, sizeof(T)), st,
+                                                   g, vs, dinv, Pn, X, R, ld, ncols, k, s, qs));
+        return hipGetLastError();
+    }
+    if (xzero) return hipErrorInvalidValue;  // only the preconditioned form is instantiated
     if (jac) {
         QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep2<T, P, true>), grid,
                                                    dim3(kThreads), lds_bytes(g, sizeof(T)), st,
@@ -839,10 +850,10 @@ template hipError_t launch_pcg_sweep1<float>(const Grid &, const float *, const 
                                              const float *, const double *, int);
 template hipError_t launch_pcg_sweep2<double>(const Grid &, const double *, const double *,
                                               const double *, double *, double *, long, int, int,
-                                              PcgState, hipStream_t, bool);
+                                              PcgState, hipStream_t, bool, bool);
 template hipError_t launch_pcg_sweep2<float>(const Grid &, const float *, const float *,
                                              const float *, float *, float *, long, int, int,
-                                             PcgState, hipStream_t, bool);
+                                             PcgState, hipStream_t, bool, bool);
 
 template <typename T>
 hipError_t launch_cg_delta0(const Grid &g, const T *vs, const T *dinv, const T *R, long ld,
@@ -869,12 +880,12 @@ hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long 
 }
 
 hipError_t launch_refine_axpy(double *X, long ld, float *D, long ld32, long ng, int ncols,
-                              const int *mask, int zero_d, hipStream_t st) {
+                              const int *mask, int zero_d, hipStream_t st, const int *its) {
     if (ncols <= 0) return hipSuccess;
     long blocks = (ng + 1023) / 1024;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_refine_axpy, dim3((unsigned)blocks, ncols), dim3(256), 0, st, X, ld, D,
-                       ld32, ng, mask, zero_d);
+                       ld32, ng, mask, zero_d, its);
     return hipGetLastError();
 }
 

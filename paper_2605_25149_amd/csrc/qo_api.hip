@@ -820,11 +820,25 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
     std::vector<int> inner(ncols);
     const long qs = (long)ncols * g.tiles();
     const int max_rounds = 30;
+    // With the fast-Poisson solve the update x += d of one round is taken by the residual
+    // pass of the next, which writes x + d out of place: the iterate moves between X and
+    // the spare FP64 block r (not used by the mixed solve otherwise).
+    const bool fused = c->dst && !one_sweep;
+    double *xc = X, *xs = c->r;
+    bool pending = false;
     for (int round = 0;; ++round) {
         int init_err[2] = {0, INT_MAX};
         HIPC(c, hipMemcpyAsync(c->ps.err, init_err, sizeof init_err, hipMemcpyHostToDevice, st));
         hipEvent_t er = prof_begin(c);
-        HIPC(c, launch_resid(g, c->vs, B, X, c->ld, c->r32, c->ld, ncols, nullptr, c->part, st));
+        if (pending) {
+            HIPC(c, launch_resid_next(g, c->vs, B, xc, c->d32, xs, c->ld, c->r32, ncols, c->mask,
+                                      c->ps.its, c->part, st));
+            std::swap(xc, xs);
+            pending = false;
+        } else {
+            HIPC(c, launch_resid(g, c->vs, B, xc, c->ld, c->r32, c->ld, ncols, nullptr, c->part,
+                                 st));
+        }
         prof_end(c, QO_KERNEL_RESID, er);
         HIPC(c, launch_colsum(c->part + qs, g.tiles(), ncols, 2, qs, c->colsums, st));
         HIPC(c, launch_refine_mask(c->colsums, ncols, tol, c->cfg.refine_inner_tol, c->mask,
@@ -836,6 +850,9 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
         if (c->h_poll[1]) return check_poll_err(c, c->h_poll[1], c->h_poll[2], what);
         if (c->h_poll[0] == 0) {
             *rounds = round;
+            if (xc != X)
+                HIPC(c, hipMemcpyAsync(X, xc, sizeof(double) * c->ld * ncols,
+                                       hipMemcpyDeviceToDevice, st));
             break;
         }
         if (round >= max_rounds)
@@ -864,8 +881,10 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
         for (int j = 0; j < ncols; ++j) its[j] += inner[j];
         // With the fast-Poisson solve d was written only in columns that took at least one
         // inner iteration (the others hold an older correction): those alone are updated.
-        HIPC(c, launch_refine_axpy(X, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, 0, st,
-                                   (c->dst && !one_sweep) ? c->ps.its : nullptr));
+        if (fused)
+            pending = true;
+        else
+            HIPC(c, launch_refine_axpy(xc, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, 0, st));
     }
     return QO_OK;
 }

@@ -132,11 +132,15 @@ size_t cg_lds_bytes(const Grid &g, size_t elem);
 hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long qstride,
                          double *out, hipStream_t st);
 
-// x += d (FP64 += FP32) for columns with mask != 0 (and d = 0 when zero_d); with its, only
-// for the columns whose inner solve took at least one iteration (its[c] > 0).
+// The refinement update fused into the next residual, out of place: Xn = X + D in the
+// columns with mask != 0 and its > 0 (the others: Xn = X), then the launch_resid outputs for
+// Xn.  X, D, Xn, R32 share the stride ld; Xn must not overlap X.
+hipError_t launch_resid_next(const Grid &g, const double *vs, const double *B, const double *X,
+                             const float *D, double *Xn, long ld, float *R32, int ncols,
+                             const int *mask, const int *its, double *part, hipStream_t st);
+// x += d (FP64 += FP32) for columns with mask != 0 (and d = 0 when zero_d).
 hipError_t launch_refine_axpy(double *X, long ld, float *D, long ld32, long ng, int ncols,
-                              const int *mask, int zero_d, hipStream_t st,
-                              const int *its = nullptr);
+                              const int *mask, int zero_d, hipStream_t st);
 // Reliable updates of the mixed-precision solve (see qo_stencil.hip).
 hipError_t launch_resid_rel(const Grid &g, const double *vs, const float *dinv32, const double *B,
                             const double *X, long ld, float *R32, int ncols, const int *mask,

@@ -320,6 +320,62 @@ __global__ __launch_bounds__(kThreads) void k_resid(Grid g, const double *__rest
     }
 }
 
+// The refinement update and the next residual in one pass, out of place: for every column
+// x_new = x + d where the last inner solve updated d (upd: mask[c] and its[c] > 0), else
+// x_new = x; then r = b - H x_new in FP64, r32 = (float) r, partials rr, bb.  x and d are
+// only read (the stencil forms x + d at the halo points too), x_new goes to its own block,
+// so no workgroup reads a value another one is changing.
+template <int PPT>
+__global__ __launch_bounds__(kThreads) void k_resid_next(Grid g, const double *__restrict__ vs,
+                                                         const double *__restrict__ B,
+                                                         const double *__restrict__ X,
+                                                         const float *__restrict__ D,
+                                                         double *__restrict__ Xn, long ld,
+                                                         float *__restrict__ R32,
+                                                         const int *__restrict__ mask,
+                                                         const int *__restrict__ its,
+                                                         double *__restrict__ part, long qs) {
+    __shared__ Red red;
+    int col, tile, band, zc;
+    tile_of(g, col, tile, band, zc);
+    vs = col_pt(g, vs, col);
+    const long o = (long)col * g.tiles() + tile;
+    struct LdNext {  // operand x + d (d dropped in the columns left alone; loaded anyway)
+        struct Raw { double x; float d; };
+        const double *__restrict__ x;
+        const float *__restrict__ d;
+        bool upd;
+        __device__ static Raw zero() { return {0.0, 0.f}; }
+        __device__ Raw load(long i) const { return {x[i], d[i]}; }
+        // a select, not a product with 0: d of a column left alone may hold anything
+        __device__ double make(const Raw &r) const { return r.x + (upd ? (double)r.d : 0.0); }
+    };
+    struct Ep {
+        struct Raw { double b; };
+        const double *__restrict__ b;
+        double *__restrict__ xn;
+        float *__restrict__ r32;
+        double acc[2];
+        __device__ static Raw zero() { return {0.0}; }
+        __device__ Raw load(long i) const { return {b[i]}; }
+        __device__ void operator()(int, long i, double c, double hv, const Raw &e) {
+            xn[i] = c;
+            const double r = e.b - hv;
+            r32[i] = (float)r;
+            acc[0] += r * r;
+            acc[1] += e.b * e.b;
+        }
+    } ep{B + (long)col * ld, Xn + (long)col * ld, R32 + (long)col * ld, {0.0, 0.0}};
+    const bool upd = mask[col] != 0 && its[col] > 0;
+    LdNext l{X + (long)col * ld, D + (long)col * ld, upd};
+    engine<double, PPT>(g, band, zc, vs, l, ep, lds_ptr<double>());
+    block_sums<2>(ep.acc, red);
+    if (threadIdx.x == 0) {
+        part[qs + o] = ep.acc[0];
+        part[2 * qs + o] = ep.acc[1];
+    }
+}
+
 // Residual replacement of the mixed-precision solve (reliable update): for the
 // columns with mask != 0, r = b - H x in FP64, r32 = (float) r.  Partials in the
 // FP32 PCG layout: q0 = r32 . D32 r32, q1 = q2 = ||r32||^2; and in `outer`:
@@ -627,10 +683,9 @@ __global__ void k_colsum(const double *__restrict__ part, int tiles, int ncols, 
 }
 
 __global__ void k_refine_axpy(double *__restrict__ X, long ld, float *__restrict__ D,
-                              long ld32, long ng, const int *__restrict__ mask, int zero_d,
-                              const int *__restrict__ its) {
+                              long ld32, long ng, const int *__restrict__ mask, int zero_d) {
     const int c = blockIdx.y;
-    if (!mask[c] || (its && its[c] == 0)) return;
+    if (!mask[c]) return;
     double *x = X + (long)c * ld;
     float *d = D + (long)c * ld32;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ng;
@@ -774,6 +829,18 @@ hipError_t launch_resid(const Grid &g, const double *vs, const double *B, const 
     return hipGetLastError();
 }
 
+hipError_t launch_resid_next(const Grid &g, const double *vs, const double *B, const double *X,
+                             const float *D, double *Xn, long ld, float *R32, int ncols,
+                             const int *mask, const int *its, double *part, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const long qs = (long)ncols * g.tiles();
+    const dim3 grid(ncols * g.tiles());
+    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL(k_resid_next<P>, grid, dim3(kThreads),
+                                               lds_bytes(g, 8), st, g, vs, B, X, D, Xn, ld, R32,
+                                               mask, its, part, qs));
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_pcg_init(const Grid &g, const T *vs, const T *dinv, const T *B, T *X, T *R,
                            long ld, int ncols, int use_x0, double *part, hipStream_t st) {
@@ -880,12 +947,12 @@ hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long 
 }
 
 hipError_t launch_refine_axpy(double *X, long ld, float *D, long ld32, long ng, int ncols,
-                              const int *mask, int zero_d, hipStream_t st, const int *its) {
+                              const int *mask, int zero_d, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
     long blocks = (ng + 1023) / 1024;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_refine_axpy, dim3((unsigned)blocks, ncols), dim3(256), 0, st, X, ld, D,
-                       ld32, ng, mask, zero_d, its);
+                       ld32, ng, mask, zero_d);
     return hipGetLastError();
 }
 

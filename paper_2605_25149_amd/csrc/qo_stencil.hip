@@ -45,7 +45,7 @@ using dev::col_sum;
 // z+2, and of V+sigma and the epilogue inputs of plane z+1 are in flight.  The
 // per-plane barrier waits on LDS only, so those loads overlap the barrier and
 // the next plane's arithmetic instead of stalling each plane.
-template <typename T, int PPT, class Ld, class Ep>
+template <typename T, int PPT, bool PP = true, class Ld, class Ep>
 __device__ __forceinline__ void engine(const Grid &g, int band, int zc,
                                        const T *__restrict__ vs, Ld &ld, Ep &ep,
                                        T *__restrict__ lds) {
@@ -74,10 +74,16 @@ __device__ __forceinline__ void engine(const Grid &g, int band, int zc,
         val[s] = t < npts;
         xs[s] = val[s] ? t % nx : 0;
     }
-    T om[PPT], oc[PPT], op[PPT], vsr[PPT];
-    LR rq[PPT];
-    ER er[PPT];
-    LR hlo = Ld::zero(), hhi = Ld::zero();
+    T om[PPT], oc[PPT], op[PPT];
+    // Prefetched values.  PP: two sets used in turn by even and odd planes, so that no
+    // loop-carried register is ever copied (a copy would wait for the load still in
+    // flight); otherwise one set (fewer registers, higher occupancy).
+    struct Pf {
+        T vsr[PPT];   // V + sigma of the next plane
+        ER er[PPT];   // epilogue inputs of the next plane
+        LR rq[PPT];   // operand of the plane after the one staged next
+        LR hlo, hhi;  // halo rows of the plane staged next
+    } pa, pb;
     const long b0 = (long)z0 * plane + (long)y0 * nx;
     // prologue: operands of planes z0-1, z0 (with halo rows), z0+1
 #pragma unroll
@@ -92,23 +98,38 @@ __device__ __forceinline__ void engine(const Grid &g, int band, int zc,
         lds[hh] = has_lo ? ld.make(ld.load(b0 + lo_off + hh)) : T(0);
         lds[(ty + 1) * nx + hh] = has_hi ? ld.make(ld.load(b0 + hi_off + hh)) : T(0);
     }
-    // prefetch for the first iteration
+    // Every load from here on is unconditional: a point past the tile's end reads the
+    // tile's first point, a plane past the column's end reads the last plane, a halo row
+    // that does not exist reads the tile's own row (halo columns past nx: column 0), and
+    // the value is dropped at its use.  (Lane offsets below 256 * PPT let the loads take
+    // a scalar base plus a 32-bit lane offset.)  Loads under a branch would end in registers
+    // merged at the join, and the copies of such a merge wait for the loads in flight.
+    int tc[PPT];
 #pragma unroll
-    for (int s = 0; s < PPT; ++s) {
-        const int t = tid + s * kThreads;
-        vsr[s] = val[s] ? vs[b0 + t] : T(0);
-        er[s] = val[s] ? ep.load(b0 + t) : Ep::zero();
-        rq[s] = (val[s] && z0 + 2 < nz && z0 + 1 < z1) ? ld.load(b0 + 2 * plane + t) : Ld::zero();
-    }
-    if (hown && z0 + 1 < z1) {
-        if (has_lo) hlo = ld.load(b0 + plane + lo_off + tid);
-        if (has_hi) hhi = ld.load(b0 + plane + hi_off + tid);
-    }
+    for (int s = 0; s < PPT; ++s) tc[s] = val[s] ? tid + s * kThreads : 0;
+    const int hx = hown ? tid : 0;
+    const long hlo_off = has_lo ? lo_off : 0, hhi_off = has_hi ? hi_off : 0;
+    const long yb = (long)y0 * nx;
+    // loads for the iteration after plane z: V + sigma and epilogue inputs of plane z+1,
+    // the operand of plane z+3 and the halo rows of plane z+2
+    auto prefetch = [&](int z, Pf &f) {
+        const long bv = (long)min(z + 1, nz - 1) * plane + yb;
+        const long bq = (long)min(z + 3, nz - 1) * plane + yb;
+        const long bh = (long)min(z + 2, nz - 1) * plane + yb;
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) {
+            f.vsr[s] = vs[bv + tc[s]];
+            f.er[s] = ep.load(bv + tc[s]);
+            f.rq[s] = ld.load(bq + tc[s]);
+        }
+        f.hlo = ld.load(bh + hlo_off + hx);
+        f.hhi = ld.load(bh + hhi_off + hx);
+    };
+    prefetch(z0 - 1, pa);
     __syncthreads();
-    for (int z = z0; z < z1; ++z) {
-        const int cur = (z - z0) & 1;
-        const T *__restrict__ L = lds + cur * ldsz;
-        const long b = (long)z * plane + (long)y0 * nx;
+    // the stencil at plane z from LDS buffer L and the z-registers, and the epilogue
+    auto plane_out = [&](int z, const T *__restrict__ L, const Pf &cu) {
+        const long b = (long)z * plane + yb;
 #pragma unroll
         for (int s = 0; s < PPT; ++s) {
             if (!val[s]) continue;
@@ -118,48 +139,63 @@ __device__ __forceinline__ void engine(const Grid &g, int band, int zc,
             const T xp = x < nx - 1 ? L[nx + t + 1] : T(0);
             const T ym = L[t];
             const T yp = L[t + 2 * nx];
-            const T hv = (c0 + vsr[s]) * oc[s] -
+            const T hv = (c0 + cu.vsr[s]) * oc[s] -
                          kap * (ihx2 * (xm + xp) + ihy2 * (ym + yp) + ihz2 * (om[s] + op[s]));
-            ep(s, b + t, oc[s], hv, er[s]);
+            ep(s, b + t, oc[s], hv, cu.er[s]);
+        }
+    };
+    if (z1 - z0 == 1) {  // a single plane (2-D grids)
+        plane_out(z0, lds, pa);
+        __syncthreads();
+        return;
+    }
+    // Plane z (epilogue only when live), then plane z+1 staged into the other LDS buffer,
+    // the z-registers moved on, and the next loads issued into set nx_.
+    auto step = [&](int z, bool live, const Pf &cu, Pf &nx_) {
+        const int cur = (z - z0) & 1;
+        const long b = (long)z * plane + yb;
+        if (live) plane_out(z, lds + cur * ldsz, cu);
+        // stage plane z+1 (past the last plane: into a buffer not read again)
+        T *__restrict__ Ln = lds + (cur ^ 1) * ldsz;
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) {
+            const int t = tid + s * kThreads;
+            if (val[s]) Ln[nx + t] = op[s];
+        }
+        if (hown) {
+            Ln[tid] = has_lo ? ld.make(cu.hlo) : T(0);
+            Ln[(ty + 1) * nx + tid] = has_hi ? ld.make(cu.hhi) : T(0);
+        }
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) {
+            om[s] = oc[s];
+            oc[s] = op[s];
+            op[s] = (val[s] && z + 2 < nz) ? ld.make(cu.rq[s]) : T(0);
         }
         if (z + 1 < z1) {
-            T *__restrict__ Ln = lds + (cur ^ 1) * ldsz;
             const long bn = b + plane;
-#pragma unroll
-            for (int s = 0; s < PPT; ++s) {
-                const int t = tid + s * kThreads;
-                if (val[s]) Ln[nx + t] = op[s];
-            }
-            if (hown) {
-                Ln[tid] = has_lo ? ld.make(hlo) : T(0);
-                Ln[(ty + 1) * nx + tid] = has_hi ? ld.make(hhi) : T(0);
-            }
             for (int hh = tid + kThreads; hh < nx; hh += kThreads) {  // nx > 256 only
                 Ln[hh] = has_lo ? ld.make(ld.load(bn + lo_off + hh)) : T(0);
                 Ln[(ty + 1) * nx + hh] = has_hi ? ld.make(ld.load(bn + hi_off + hh)) : T(0);
             }
-#pragma unroll
-            for (int s = 0; s < PPT; ++s) {
-                const int t = tid + s * kThreads;
-                om[s] = oc[s];
-                oc[s] = op[s];
-                op[s] = (val[s] && z + 2 < nz) ? ld.make(rq[s]) : T(0);
-            }
-            // issue the loads the next iterations consume
-#pragma unroll
-            for (int s = 0; s < PPT; ++s) {
-                const int t = tid + s * kThreads;
-                vsr[s] = val[s] ? vs[bn + t] : T(0);
-                er[s] = val[s] ? ep.load(bn + t) : Ep::zero();
-                rq[s] = (val[s] && z + 3 < nz && z + 2 < z1) ? ld.load(bn + 2 * plane + t)
-                                                              : Ld::zero();
-            }
-            if (hown && z + 2 < z1) {
-                if (has_lo) hlo = ld.load(bn + plane + lo_off + tid);
-                if (has_hi) hhi = ld.load(bn + plane + hi_off + tid);
-            }
         }
+        // one set: the loads must not be moved above the last uses of the old values
+        if constexpr (!PP) __builtin_amdgcn_sched_barrier(0);
+        prefetch(z, nx_);
         __syncthreads();
+    };
+    if constexpr (!PP) {
+        // One prefetch set, refilled in every iteration (the last one too: clamped,
+        // unused), so the back edge is reached only with freshly loaded registers.
+        for (int z = z0; z < z1; ++z) step(z, true, pa, pa);
+    } else {
+        // Two sets in turn: one plane's loads go to the set the previous plane has
+        // finished with.  Planes in pairs; an odd count ends with a pass whose epilogue is
+        // off (its loads are clamped, its staging goes to a buffer not read again).
+        for (int z = z0; z < z1; z += 2) {
+            step(z, true, pa, pb);
+            step(z + 1, z + 1 < z1, pb, pa);
+        }
     }
 }
 
@@ -606,7 +642,8 @@ struct EpSweep2 {
 };
 
 template <typename T, int PPT, bool JAC, bool XZ = false>
-__global__ __launch_bounds__(kThreads) void k_pcg_sweep2(Grid g, const T *__restrict__ vs,
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !JAC && PPT == 3 ? 6 : 1))) void k_pcg_sweep2(Grid g, const T *__restrict__ vs,
                                                          const T *__restrict__ dinv,
                                                          const T *__restrict__ Pn,
                                                          T *__restrict__ X, T *__restrict__ R,
@@ -637,7 +674,8 @@ __global__ __launch_bounds__(kThreads) void k_pcg_sweep2(Grid g, const T *__rest
     const T alpha = (T)(s.rho[cur * ncols + col] / gam);
     LdPlain<T> l{Pn + (long)col * ld};
     EpSweep2<T, JAC, XZ> ep{X + (long)col * ld, R + (long)col * ld, dinv, alpha, {0.0, 0.0}};
-    engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
+    // FP32: one prefetch set (measured faster here: the second set costs occupancy)
+    engine<T, PPT, sizeof(T) == 8>(g, band, zc, vs, l, ep, lds_ptr<T>());
     block_sums<2>(ep.acc, red);
     if (threadIdx.x == 0) {
         const long o = (long)col * tiles + tile;

@@ -35,6 +35,128 @@ using dev::Red;
 using dev::block_sums;
 using dev::col_sum;
 
+// The engine for wide tiles (PPT >= 4: the 2-D grids, one plane per tile).  Its prefetch
+// is issued under the tile's own bounds, which keeps the registers of those many points
+// per thread low; with one plane per tile the loop below runs once and nothing is
+// carried across planes.
+template <typename T, int PPT, class Ld, class Ep>
+__device__ __forceinline__ void engine_wide(const Grid &g, int band, int zc,
+                                            const T *__restrict__ vs, Ld &ld, Ep &ep,
+                                            T *__restrict__ lds) {
+    using LR = typename Ld::Raw;
+    using ER = typename Ep::Raw;
+    const int tid = threadIdx.x;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int y0 = band * g.TY;
+    const int ty = min(g.TY, ny - y0);
+    const int npts = ty * nx;
+    const int z0 = zc * g.ZC;
+    const int z1 = min(nz, z0 + g.ZC);
+    const long plane = (long)nx * ny;
+    const int ldsz = (g.TY + 2) * nx;
+    const bool has_lo = y0 > 0, has_hi = (y0 + ty) < ny;
+    const bool hown = tid < nx;  // this thread owns halo column tid (prefetched)
+    const T kap = (T)g.kappa, c0 = (T)g.c0;
+    const T ihx2 = (T)g.ihx2, ihy2 = (T)g.ihy2, ihz2 = (T)g.ihz2;
+    const long lo_off = -(long)nx, hi_off = (long)ty * nx;
+
+    int xs[PPT];
+    bool val[PPT];
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+        const int t = tid + s * kThreads;
+        val[s] = t < npts;
+        xs[s] = val[s] ? t % nx : 0;
+    }
+    T om[PPT], oc[PPT], op[PPT], vsr[PPT];
+    LR rq[PPT];
+    ER er[PPT];
+    LR hlo = Ld::zero(), hhi = Ld::zero();
+    const long b0 = (long)z0 * plane + (long)y0 * nx;
+    // prologue: operands of planes z0-1, z0 (with halo rows), z0+1
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+        const int t = tid + s * kThreads;
+        om[s] = (val[s] && z0 > 0) ? ld.make(ld.load(b0 - plane + t)) : T(0);
+        oc[s] = val[s] ? ld.make(ld.load(b0 + t)) : T(0);
+        op[s] = (val[s] && z0 + 1 < nz) ? ld.make(ld.load(b0 + plane + t)) : T(0);
+        if (val[s]) lds[nx + t] = oc[s];
+    }
+    for (int hh = tid; hh < nx; hh += kThreads) {
+        lds[hh] = has_lo ? ld.make(ld.load(b0 + lo_off + hh)) : T(0);
+        lds[(ty + 1) * nx + hh] = has_hi ? ld.make(ld.load(b0 + hi_off + hh)) : T(0);
+    }
+    // prefetch for the first iteration
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+        const int t = tid + s * kThreads;
+        vsr[s] = val[s] ? vs[b0 + t] : T(0);
+        er[s] = val[s] ? ep.load(b0 + t) : Ep::zero();
+        rq[s] = (val[s] && z0 + 2 < nz && z0 + 1 < z1) ? ld.load(b0 + 2 * plane + t) : Ld::zero();
+    }
+    if (hown && z0 + 1 < z1) {
+        if (has_lo) hlo = ld.load(b0 + plane + lo_off + tid);
+        if (has_hi) hhi = ld.load(b0 + plane + hi_off + tid);
+    }
+    __syncthreads();
+    for (int z = z0; z < z1; ++z) {
+        const int cur = (z - z0) & 1;
+        const T *__restrict__ L = lds + cur * ldsz;
+        const long b = (long)z * plane + (long)y0 * nx;
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) {
+            if (!val[s]) continue;
+            const int t = tid + s * kThreads;
+            const int x = xs[s];
+            const T xm = x > 0 ? L[nx + t - 1] : T(0);
+            const T xp = x < nx - 1 ? L[nx + t + 1] : T(0);
+            const T ym = L[t];
+            const T yp = L[t + 2 * nx];
+            const T hv = (c0 + vsr[s]) * oc[s] -
+                         kap * (ihx2 * (xm + xp) + ihy2 * (ym + yp) + ihz2 * (om[s] + op[s]));
+            ep(s, b + t, oc[s], hv, er[s]);
+        }
+        if (z + 1 < z1) {
+            T *__restrict__ Ln = lds + (cur ^ 1) * ldsz;
+            const long bn = b + plane;
+#pragma unroll
+            for (int s = 0; s < PPT; ++s) {
+                const int t = tid + s * kThreads;
+                if (val[s]) Ln[nx + t] = op[s];
+            }
+            if (hown) {
+                Ln[tid] = has_lo ? ld.make(hlo) : T(0);
+                Ln[(ty + 1) * nx + tid] = has_hi ? ld.make(hhi) : T(0);
+            }
+            for (int hh = tid + kThreads; hh < nx; hh += kThreads) {  // nx > 256 only
+                Ln[hh] = has_lo ? ld.make(ld.load(bn + lo_off + hh)) : T(0);
+                Ln[(ty + 1) * nx + hh] = has_hi ? ld.make(ld.load(bn + hi_off + hh)) : T(0);
+            }
+#pragma unroll
+            for (int s = 0; s < PPT; ++s) {
+                const int t = tid + s * kThreads;
+                om[s] = oc[s];
+                oc[s] = op[s];
+                op[s] = (val[s] && z + 2 < nz) ? ld.make(rq[s]) : T(0);
+            }
+            // issue the loads the next iterations consume
+#pragma unroll
+            for (int s = 0; s < PPT; ++s) {
+                const int t = tid + s * kThreads;
+                vsr[s] = val[s] ? vs[bn + t] : T(0);
+                er[s] = val[s] ? ep.load(bn + t) : Ep::zero();
+                rq[s] = (val[s] && z + 3 < nz && z + 2 < z1) ? ld.load(bn + 2 * plane + t)
+                                                              : Ld::zero();
+            }
+            if (hown && z + 2 < z1) {
+                if (has_lo) hlo = ld.load(bn + plane + lo_off + tid);
+                if (has_hi) hhi = ld.load(bn + plane + hi_off + tid);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // The streaming engine.
 //
 //   Ld: stencil operand.   Ld::Raw raw = ld.load(i);  T v = ld.make(raw)
@@ -49,6 +171,10 @@ template <typename T, int PPT, bool PP = true, class Ld, class Ep>
 __device__ __forceinline__ void engine(const Grid &g, int band, int zc,
                                        const T *__restrict__ vs, Ld &ld, Ep &ep,
                                        T *__restrict__ lds) {
+    if constexpr (PPT >= 4) {
+        engine_wide<T, PPT>(g, band, zc, vs, ld, ep, lds);
+        return;
+    }
     using LR = typename Ld::Raw;
     using ER = typename Ep::Raw;
     const int tid = threadIdx.x;

@@ -662,8 +662,12 @@ struct EpSweep1 {  // store p, gamma = p . H p
 // XZ: the preconditioned residual z is an input (fast-Poisson preconditioner)
 // and r.z comes from that pass's partials rzp (rzt per column); otherwise
 // z = D r is formed on the fly and r.z comes from sweep2's partials.
+// FP32 with z as input at 3 points per thread: capped to six waves per SIMD, which spills
+// a few registers of the two prefetch sets and is still faster than the five waves that
+// fit without spills (96^3 x 256: 423 against 456 us).
 template <typename T, int PPT, bool XZ>
-__global__ __launch_bounds__(kThreads) void k_pcg_sweep1(Grid g, const T *__restrict__ vs,
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && XZ && PPT == 3 ? 6 : 1))) void k_pcg_sweep1(Grid g, const T *__restrict__ vs,
                                                          const T *__restrict__ dinv,
                                                          const T *__restrict__ R,
                                                          const T *__restrict__ Pold,
@@ -767,6 +771,8 @@ struct EpSweep2 {
     }
 };
 
+// FP32 without the Jacobi term at 3 points per thread: one prefetch set, capped to six
+// waves per SIMD (80 registers; one spill).
 template <typename T, int PPT, bool JAC, bool XZ = false>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !JAC && PPT == 3 ? 6 : 1))) void k_pcg_sweep2(Grid g, const T *__restrict__ vs,

@@ -255,7 +255,9 @@ const char *qo_batch_last_error(qo_batch b);
  * synchronisation points.  work[k] counts column-iterations for the PCG sweeps
  * (bytes moved = bytes per point-column x Ng x work) and launches otherwise.  A second
  * sweep that starts a solve from x = 0 without reading x moves 4 of the 5 arrays of a
- * regular one and counts 0.8 of a column-iteration. */
+ * regular one and counts 0.8 of a column-iteration.  QO_KERNEL_RESID covers the FP64
+ * residual passes of QO_MIXED, the ones that also apply the previous round's correction
+ * x + d included. */
 typedef enum {
     QO_KERNEL_SWEEP1_F64 = 0, QO_KERNEL_SWEEP2_F64 = 1, QO_KERNEL_SWEEP1_F32 = 2,
     QO_KERNEL_SWEEP2_F32 = 3, QO_KERNEL_GRAM = 4, QO_KERNEL_UPDATE = 5, QO_KERNEL_RESID = 6,

@@ -169,3 +169,35 @@ def test_precond_errors(torch, B):
             s.precond(B.as_block(np.ones((256, 2))))
     with pytest.raises(B.QOError):
         B.Solver(2, (16, 16), 2, precond="fast_poisson", pcg_variant=1)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("tol", [1e-4, 1e-7, 1e-10, 1e-12])
+def test_solve_mixed_rounds_and_reuse(torch, B, oracle_mod, tol):
+    """Mixed fast-Poisson solves over a range of tolerances, twice on each handle.  Each
+    refinement round after the first writes the corrected iterate into the other of two
+    FP64 blocks, so the result ends in the caller's block or in the spare one (then copied
+    back) depending on the number of rounds; tolerances from 1e-4 to 1e-12 take one to
+    several rounds.  Every solve must meet its tolerance in the true FP64 residual, agree
+    with sparse LU, and not depend on what the previous solve left behind."""
+    dim, n, N = 3, (24, 21, 19), 4
+    V = _potential(dim, n)
+    prob = oracle_mod.Problem(dim, n, V)
+    Bm = inputs.random_block(prob.ng, N, seed=7)
+    Xr = prob.solve_direct(Bm)
+    with B.Solver(dim, n, N, pcg_tol=tol, pcg_check=1, precision="mixed",
+                  precond="fast_poisson") as s:
+        s.set_potential(V)
+        prev = None
+        for rep in range(2):
+            Xg, itg = s.solve(B.as_block(Bm))
+            Xg = B.to_numpy(Xg)
+            res = np.linalg.norm(Bm - prob.apply(Xg), axis=0) / np.linalg.norm(Bm, axis=0)
+            err = np.max(np.abs(Xg - Xr)) / np.max(np.abs(Xr))
+            print(f"tol {tol:g} solve {rep}: FP32 iterations {list(itg)}; residual {res}; "
+                  f"vs LU {err:.2e}")
+            assert np.all(res <= 2 * tol)
+            assert err <= max(1e4 * tol, 1e-9)
+            if prev is not None:
+                assert np.array_equal(Xg, prev)  # same inputs, same launches: same bits
+            prev = Xg

@@ -26,6 +26,9 @@
 #ifndef QO_SWEEP2_NT
 #define QO_SWEEP2_NT 1
 #endif
+#ifndef QO_SWEEP1_NT
+#define QO_SWEEP1_NT 1
+#endif
 
 namespace qo {
 
@@ -646,15 +649,21 @@ __global__ __launch_bounds__(kThreads) void k_pcg_init(Grid g, const T *__restri
     }
 }
 
+// store p, gamma = p . H p.  p is stored non-temporally: the next kernel reads it from
+// HBM anyway, and the store then leaves the cache to the halo rows of this sweep's operand.
 template <typename T>
-struct EpSweep1 {  // store p, gamma = p . H p
+struct EpSweep1 {
     using Raw = NoRaw;
     T *__restrict__ pn;
     double acc[1];
     __device__ static Raw zero() { return {}; }
     __device__ Raw load(long) const { return {}; }
     __device__ void operator()(int, long i, T c, T hv, const Raw &) {
+#if QO_SWEEP1_NT
+        __builtin_nontemporal_store(c, pn + i);
+#else
         pn[i] = c;
+#endif
         acc[0] += (double)c * (double)hv;
     }
 };

@@ -43,6 +43,23 @@ namespace qo {
 namespace {
 
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+#ifndef QO_DST_NT
+#define QO_DST_NT 1
+#endif
+// Global stores of the passes' outputs, non-temporal: each is read once, by the next
+// pass, from HBM (a block of 96^3 x 256 values is far larger than the caches), and the
+// stores then leave the cache to the inputs being read.
+template <class V>
+__device__ __forceinline__ void st_out(V *p, const V &v) {
+#if QO_DST_NT
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
 typedef _Float16 v4h __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -389,7 +406,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
             _Float16 *dst = Hout + base + (long)r * nx + x;
             const _Float16 *src = ST + r * XP + x;
             if constexpr (vec) {
-                *reinterpret_cast<v8h *>(dst) = *reinterpret_cast<const v8h *>(src);
+                st_out(reinterpret_cast<v8h *>(dst), *reinterpret_cast<const v8h *>(src));
             } else {
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
@@ -436,10 +453,10 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
                 const long i0 = base + (long)r * nx + x;
                 const float4 z4 = *reinterpret_cast<const float4 *>(SF + r * FP + x);
                 if constexpr (sizeof(T) == 4) {
-                    *reinterpret_cast<float4 *>(Z + i0) = z4;
+                    st_out(reinterpret_cast<v4f *>(Z + i0), v4f{z4.x, z4.y, z4.z, z4.w});
                 } else {
-                    *reinterpret_cast<double2 *>(Z + i0) = double2{z4.x, z4.y};
-                    *reinterpret_cast<double2 *>(Z + i0 + 2) = double2{z4.z, z4.w};
+                    st_out(reinterpret_cast<v2d *>(Z + i0), v2d{z4.x, z4.y});
+                    st_out(reinterpret_cast<v2d *>(Z + i0 + 2), v2d{z4.z, z4.w});
                 }
                 rz += (double)rr[q][0] * (double)(T)z4.x + (double)rr[q][1] * (double)(T)z4.y +
                       (double)rr[q][2] * (double)(T)z4.z + (double)rr[q][3] * (double)(T)z4.w;
@@ -671,8 +688,8 @@ __global__ __launch_bounds__(128 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 
             _Float16 *dst = Hout + (long)col * ld + m;
             if (vec) {
                 if (m < nf) {
-                    if (s0 < ns) *reinterpret_cast<v8h *>(dst + (long)s0 * nf) = z0;
-                    if (s0 + 1 < ns) *reinterpret_cast<v8h *>(dst + (long)(s0 + 1) * nf) = z1;
+                    if (s0 < ns) st_out(reinterpret_cast<v8h *>(dst + (long)s0 * nf), z0);
+                    if (s0 + 1 < ns) st_out(reinterpret_cast<v8h *>(dst + (long)(s0 + 1) * nf), z1);
                 }
             } else {
 #pragma unroll

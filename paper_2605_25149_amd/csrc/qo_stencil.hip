@@ -26,6 +26,9 @@
 #ifndef QO_SWEEP2_NT
 #define QO_SWEEP2_NT 1
 #endif
+#ifndef QO_RESID_NT
+#define QO_RESID_NT 1
+#endif
 #ifndef QO_SWEEP1_NT
 #define QO_SWEEP1_NT 1
 #endif
@@ -524,9 +527,14 @@ __global__ __launch_bounds__(kThreads) void k_resid_next(Grid g, const double *_
         __device__ static Raw zero() { return {0.0}; }
         __device__ Raw load(long i) const { return {b[i]}; }
         __device__ void operator()(int, long i, double c, double hv, const Raw &e) {
-            xn[i] = c;
             const double r = e.b - hv;
+#if QO_RESID_NT  // x' and r32 are read again only after the next passes over the block
+            __builtin_nontemporal_store(c, xn + i);
+            __builtin_nontemporal_store((float)r, r32 + i);
+#else
+            xn[i] = c;
             r32[i] = (float)r;
+#endif
             acc[0] += r * r;
             acc[1] += e.b * e.b;
         }

@@ -44,6 +44,8 @@ Readings of the paper taken here (numbered as in the design notes' table of read
       (identity rows/columns in the s x s matrices, zero search directions); when the
       search block loses rank with columns still active (singular P^T H P, or no halving
       of the largest relative residual in 50 iterations) the column solver finishes.
+  R20 The stop test of Alg. 1 measures grad_G E_G(U_n) = G U - U <G U, U> in the grid
+      L2 norm (``grad_norm``); the algorithm does not name the norm.
   R16 The paper does not differentiate the scheme.  ``steps_loss_grad`` gives the
       exact derivative of the discrete K-step map (solves taken exact) composed
       with a loss of U_K (the energy, or the sum of the Ritz values), with respect
@@ -439,7 +441,11 @@ def corrector(prob: Problem, U_hat, Q, tau):
 
 
 def grad_norm(prob: Problem, U, P):
-    """|| grad_G E_G(U) || = || G U - U <G U, U> || in the grid L2 norm (Sec. 3.1, Alg. 1)."""
+    """|| grad_G E_G(U) || = || G U - U <G U, U> || (Sec. 3.1; the stop test of Alg. 1).
+
+    Reading R20: Alg. 1 does not name the norm; it is taken as the grid L2 norm of the
+    block, sqrt(h^d sum_{i,c} g_ic^2) -- the weighted Frobenius norm matching the inner
+    product of Sec. 2.1 -- with P = G U the computed solve."""
     Mt = prob.inner(P, U)
     Gr = P - U @ Mt
     return float(np.sqrt(prob.w * np.sum(Gr * Gr)))

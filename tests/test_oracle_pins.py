@@ -616,3 +616,97 @@ def test_block_cg_pins(oracle_mod):
     _, itb, _ = p32.solve_block_cg(B32, tol=1e-10)
     _, itcol, _, _ = p32.solve(B32, tol=1e-10)
     assert int(itb.max()) <= int(itcol.max())
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.1 / Alg. 1: the norm of the Grassmann gradient, and the subspace checker
+# ---------------------------------------------------------------------------
+
+def _sine_basis(n, L, modes):
+    """Discrete sine modes prod_k sqrt(2/L_k) sin(m_k pi x_k / L_k): orthonormal in the
+    grid L2 inner product h^d sum_i u_i v_i (discrete orthogonality of the sine transform),
+    eigenvectors of H_sigma = -kappa Lap_h + sigma (V = 0)."""
+    xs = inputs.grid_coords(n, L)
+    cols = []
+    for m in modes:
+        u = np.ones_like(xs[0])
+        for k in range(len(n)):
+            u = u * np.sqrt(2.0 / L[k]) * np.sin(m[k] * np.pi * xs[k] / L[k])
+        cols.append(u)
+    return np.asfortranarray(np.stack(cols, axis=1))
+
+
+def _sine_eigs(n, L, kappa, sigma, modes):
+    h = [L[k] / (n[k] + 1) for k in range(len(n))]
+    return np.array([sigma + sum(4.0 * kappa / h[k] ** 2
+                                 * np.sin(m[k] * np.pi * h[k] / (2.0 * L[k])) ** 2
+                                 for k in range(len(n))) for m in modes])
+
+
+@pytest.mark.parametrize("dim,n,L", [(2, (11, 9), (1.0, 1.7)), (3, (7, 6, 5), (1.3, 0.8, 1.1))])
+def test_grad_norm_closed_form(oracle_mod, dim, n, L):
+    """||grad_G E_G(U)|| = ||G U - U <G U, U>|| (Sec. 3.1; the stop test of Alg. 1) in the
+    grid L2 norm.  For U = Phi C with Phi exact orthonormal eigenvectors of H_sigma
+    (eigenvalues Lambda): G U = Phi Lambda^{-1} C, <G U, U> = C^T Lambda^{-1} C, so
+      ||grad||^2 = ||Lambda^{-1} C - C C^T Lambda^{-1} C||_F^2,
+    and for diagonal C = diag(c_i): sum_i c_i^2 (1 - c_i^2)^2 / lambda_i^2.  The box is not
+    the unit box, so h^d != 1 and a dropped (or doubled) grid weight changes the value."""
+    O = oracle_mod
+    ng = int(np.prod(n))
+    kappa, sigma = 0.5, 0.7
+    prob = O.Problem(dim, n, np.zeros(ng), L=L, kappa=kappa, sigma=sigma)
+    assert abs(prob.w - 1.0) > 0.05 and abs(np.sqrt(prob.w) - 1.0) > 0.02
+    modes = [(1, 1, 1), (2, 1, 1), (1, 3, 2), (3, 2, 1)]
+    Phi = _sine_basis(n, L, modes)
+    lam = _sine_eigs(n, L, kappa, sigma, modes)
+    np.testing.assert_allclose(prob.w * Phi.T @ Phi, np.eye(len(modes)), atol=1e-13)
+    np.testing.assert_allclose(prob.apply(Phi), Phi * lam, atol=1e-11 * lam.max())
+    # diagonal coefficients: the verdict's closed form with two scaled eigenvectors
+    c = np.array([0.6, 1.3])
+    U = np.asfortranarray(Phi[:, :2] * c)
+    P = np.asfortranarray(Phi[:, :2] * (c / lam[:2]))
+    ref = np.sqrt(np.sum(c**2 * (1 - c**2) ** 2 / lam[:2] ** 2))
+    assert abs(O.grad_norm(prob, U, P) - ref) <= 1e-13 * ref
+    # a general coefficient matrix mixing four modes into three columns
+    rng = np.random.default_rng(7)
+    C = rng.standard_normal((4, 3))
+    U = np.asfortranarray(Phi @ C)
+    Li = np.diag(1.0 / lam)
+    P = np.asfortranarray(Phi @ Li @ C)
+    ref = np.linalg.norm(Li @ C - C @ (C.T @ Li @ C))
+    assert abs(O.grad_norm(prob, U, P) - ref) <= 1e-12 * ref
+    # the norm the step reports (P from the oracle's own solve, exact mode)
+    orc = O.Oracle(prob, U, direct=True)
+    st = orc.step(0.5 * lam[0])
+    assert abs(st.grad_norm - ref) <= 1e-10 * ref
+    # at an invariant subspace with orthonormal coefficients the gradient vanishes
+    Qo, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+    U = np.asfortranarray(Phi @ Qo[:, :4])
+    P = np.asfortranarray(Phi @ Li @ Qo[:, :4])
+    assert O.grad_norm(prob, U, P) <= 1e-13 * np.linalg.norm(Li)
+
+
+def test_subspace_sin_known_angles(oracle_mod):
+    """sin of the largest principal angle.  span{e1, cos a e2 + sin a e3, cos b e4 + sin b e5}
+    against span{e1, e2, e4} has principal angles 0, a, b; the checker must return
+    max(sin a, sin b) (not a Frobenius sum, not a cosine), for any bases of the two spans
+    (non-orthonormal, columns mixed), and 0 for equal spans."""
+    O = oracle_mod
+    m = 9
+    e = np.eye(m)
+    rng = np.random.default_rng(11)
+    for a, b in [(0.3, 0.1), (0.05, 1.2), (1e-6, 2e-7)]:
+        A = np.stack([e[0], np.cos(a) * e[1] + np.sin(a) * e[2],
+                      np.cos(b) * e[3] + np.sin(b) * e[4]], axis=1)
+        B = np.stack([e[0], e[1], e[3]], axis=1)
+        Q, _ = np.linalg.qr(rng.standard_normal((m, m)))  # same rotation of both: angles kept
+        G1 = rng.standard_normal((3, 3)) + 3 * np.eye(3)  # bases mixed and rescaled
+        G2 = rng.standard_normal((3, 3)) + 3 * np.eye(3)
+        ref = max(np.sin(a), np.sin(b))
+        for AA, BB in [(A, B), (Q @ A @ G1, Q @ B @ G2), (B @ G2, A @ G1)]:
+            s = O.subspace_sin(AA, BB)
+            assert abs(s - ref) <= 1e-12 + 1e-9 * ref, (a, b, s, ref)
+    A = rng.standard_normal((m, 4))
+    assert O.subspace_sin(A, A @ (rng.standard_normal((4, 4)) + 4 * np.eye(4))) <= 1e-13
+    # a vector outside the span gives sin = 1
+    assert abs(O.subspace_sin(e[:, :2], e[:, [0, 5]]) - 1.0) <= 1e-14

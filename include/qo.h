@@ -95,7 +95,9 @@ typedef struct {
     int pcg_iters[2];      /* max over columns of PCG iterations for G U_n and G U_hat
                               (QO_MIXED: summed over refinement rounds) */
     int refine_rounds[2];  /* QO_MIXED: refinement rounds per solve; 1 in QO_FP64 */
-    int energy_rose;       /* 1 if E_sigma increased in this step (tau too large) */
+    int energy_rose;       /* 1 if E_sigma(U_{n+1}) > E_sigma(U_n) (tau too large); 0 at
+                              the first step after qo_set_state / qo_set_potential, whose
+                              starting energy is not evaluated */
     int step_index;        /* n + 1 after the step */
     double orth_err_next;  /* ||O_{n+1}||_F from the Gram recurrence of Sec. 4.1,
                               O_{n+1} = O_n - tau (A_n O_n + O_n A_n) + tau^2 O_n B_n O_n */
@@ -116,10 +118,17 @@ typedef enum {
 } qo_matrix;
 
 /* Create a solver for the grid and options in cfg.  hip_stream is a
- * hipStream_t (NULL: the default stream).  Allocates the device workspace
- * (about 7 blocks of Ng x N doubles in QO_FP64, plus 3 FP32 blocks in
- * QO_MIXED).  Sizes: 1 <= N < Ng, n_0 <= 1024 (n_0 <= 256 with pcg_variant 1).
- * On error *out is NULL. */
+ * hipStream_t (NULL: the default stream).  Allocates the device workspace, in
+ * blocks of ld x N values with ld = Ng rounded up to a multiple of 64:
+ *   QO_FP64: 9 FP64 blocks (U, U_hat, the G U / G U_hat pair, r, two search
+ *            directions, two scratch blocks); 10 with pcg_variant 1;
+ *   QO_MIXED adds 5 FP32 blocks (6 with pcg_variant 1) and a BF16 copy of two
+ *            blocks for the Gram (the bytes of one FP32 block);
+ *   precond 1 adds two FP16 blocks and one block of the PCG's precision (z);
+ * plus O(Ng + N^2) per-point and N x N arrays.  At Ng = 96^3, N = 256 the mixed
+ * fast-Poisson workspace is about 25 GB.  qo_tape_forward adds K + 1 FP64 blocks
+ * when it is called.  Sizes: 1 <= N < Ng, n_0 <= 1024 (n_0 <= 256 with
+ * pcg_variant 1).  On error *out is NULL. */
 qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out);
 
 /* Potential V: Ng values, x fastest (the V of H = -kappa Lap + V, Sec. 2.1). */
@@ -230,7 +239,11 @@ qo_status qo_get_matrix(qo_handle h, int which, double *out);
  * algebra and energy stay FP64 (BF16 Grams are single-instance only); pcg_iters then
  * counts FP32 iterations summed over the rounds and refine_rounds the rounds used.
  * The solve of G U_n always starts from the previous G U_hat (zero after
- * qo_batch_set_state).  With use_graph != 0 each step is replayed from a HIP graph
+ * qo_batch_set_state).  qo_batch_set_state and qo_batch_set_potential return the
+ * instance's group to the counts of a fresh batch (pcg_maxit; six rounds in mixed
+ * precision) and drop its captured graphs, since a cold start or a new operator needs
+ * more iterations than the warm-started steps before it; a step that fails with
+ * QO_ERR_PCG_NOCONV does the same for every group.  With use_graph != 0 each step is replayed from a HIP graph
  * captured at its first use (one per parity of the P / Q buffers); the stream given to
  * qo_batch_create must then not be the null stream (NULL creates a private stream).  At
  * creation the band height of the stencil kernels is chosen per group by timing the

@@ -1504,6 +1504,7 @@ qo_status qo_set_potential(qo_handle h, const double *V, int on_device) {
     h->have_V = true;
     h->have_warm = false;
     h->have_K = false;
+    h->have_Es = false;  // energies of the old operator are not comparable
     return QO_OK;
 }
 

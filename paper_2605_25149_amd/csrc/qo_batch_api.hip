@@ -706,6 +706,19 @@ qo_status qo_batch_create(const qo_config *cfgs, int count, void *hip_stream, qo
     return QO_OK;
 }
 
+// Back to the counts of a fresh batch for group G: pcg_maxit iterations per solve (six
+// rounds of pcg_maxit FP32 iterations in mixed precision) until counts are observed
+// again, and the captured graphs re-recorded.  Taken when a new state or potential makes
+// the counts of earlier warm-started steps meaningless, and after a solve ran out of
+// iterations.
+static void reset_counts(qo_batch b, int group) {
+    auto &G = b->groups[group];
+    G.kuse = G.kmax;
+    G.ruse = 6;
+    G.kr.assign(kMaxRounds, G.kmax);
+    b->gvalid[0] = b->gvalid[1] = false;
+}
+
 qo_status qo_batch_set_potential(qo_batch b, int i, const double *V, int on_device) {
     if (!b) return QO_ERR_ARG;
     if (i < 0 || i >= b->count || !V) return bfail(b, QO_ERR_ARG, "bad instance or null potential");
@@ -746,6 +759,7 @@ qo_status qo_batch_set_potential(qo_batch b, int i, const double *V, int on_devi
         BHIP(b, hipStreamSynchronize(st));
     }
     I.have_V = true;
+    reset_counts(b, I.group);
     return QO_OK;
 }
 
@@ -766,6 +780,7 @@ qo_status qo_batch_set_state(qo_batch b, int i, const double *U, long ld, int on
     I.have_U = true;
     I.have_Es = false;
     I.nstep = 0;
+    reset_counts(b, I.group);
     return QO_OK;
 }
 
@@ -899,6 +914,10 @@ qo_status qo_batch_step(qo_batch b, const double *taus, int nsteps, int use_grap
         if (herr[0]) {
             const qo_status s = herr[0] == 6 ? QO_ERR_PCG_NOCONV
                                 : herr[0] == 5 ? QO_ERR_NOT_SPD : QO_ERR_NONFINITE;
+            // the fixed counts were too small for this step: the next steps start again
+            // from pcg_maxit
+            if (s == QO_ERR_PCG_NOCONV)
+                for (int k = 0; k < (int)b->groups.size(); ++k) reset_counts(b, k);
             return bfail(b, s, "PCG error code %d (first column %d of its group)", herr[0],
                          herr[1]);
         }

@@ -236,3 +236,48 @@ def test_batch_mixed_graph_equals_eager_and_noconv(torch, B):
             b.step(taus)
     finally:
         b.close()
+
+
+@pytest.mark.parametrize("what", ["state", "potential"])
+def test_batch_reseed_after_warm_steps(torch, B, what):
+    """Jacobi-PCG (cold solves need several times the warm-started count), pcg_maxit 400:
+    6 graph-replayed steps, then one instance gets a new random state (or a new potential
+    and a new state), then 6 more steps.  The cold solve after the re-seed must not run out
+    of the adapted fixed count: every step succeeds and matches single-instance handles
+    given the same inputs (energies 1e-10 relative, final states 1e-9)."""
+    probs = _problems()
+    taus = [p["tau"] for p in probs]
+    b = _batch(B, probs, "jacobi", maxit=400)
+    ref = []
+    for p in probs:
+        s = B.Solver(2, p["n"], p["N"], sigma=p["sigma"], pcg_tol=1e-12, pcg_check=1,
+                     precond="jacobi")
+        s.set_potential(p["V"])
+        s.set_state(B.as_block(p["U0"]))
+        ref.append(s)
+    try:
+        for _ in range(6):
+            b.step(taus, use_graph=True)
+            for i, p in enumerate(probs):
+                ref[i].step(p["tau"])
+        k = 1
+        U1 = inputs.random_block(probs[k]["n"][0] * probs[k]["n"][1], probs[k]["N"], seed=77)
+        if what == "potential":
+            V1 = probs[k]["V"] + 0.5 * inputs.harmonic(probs[k]["n"], 40.0)
+            b.set_potential(k, V1)
+            ref[k].set_potential(V1)
+        b.set_state(k, U1)
+        ref[k].set_state(B.as_block(U1))
+        for step in range(6):
+            st = b.step(taus, use_graph=True)
+            for i, p in enumerate(probs):
+                r = ref[i].step(p["tau"])
+                assert abs(st[i]["energy"] - r["energy"]) <= 1e-10 * abs(r["energy"]), (step, i)
+        for i in range(len(probs)):
+            U = b.get_state(i)
+            Ur = B.to_numpy(ref[i].get_state())
+            assert np.max(np.abs(U - Ur)) <= 1e-9 * np.max(np.abs(Ur)), i
+    finally:
+        b.close()
+        for s in ref:
+            s.close()

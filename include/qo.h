@@ -184,6 +184,8 @@ qo_status qo_eigsum_gradient(qo_handle h, double *g, int on_device);
 
 qo_status qo_destroy(qo_handle h);
 const char *qo_status_string(qo_status s);
+/* Message of the last failing call on h; with h == NULL, of the calling thread's last
+ * failing handle-free call (qo_gram_pair_noalloc). */
 const char *qo_last_error(qo_handle h);
 
 /* ---- kernel-level entry points (device pointers, ncols <= N, ld >= Ng) ---- */
@@ -210,6 +212,25 @@ qo_status qo_precond(qo_handle h, const double *R, double *Z, long ld, int ncols
  * in QO_MIXED, FP64 otherwise. */
 qo_status qo_gram_pair(qo_handle h, const double *X, const double *Y, long ld, int ncols,
                        double *G);
+
+/* Allocation-free variant of qo_gram_pair (FP64 path), for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Needs no handle and calls no allocating routine.  G = w [X | Y]^T [X | Y]
+ * (the 2 ncols x 2 ncols Gram matrix of Sec. 2.1 with the grid weight w = h^d), written
+ * column-major to the device array G; X, Y are device blocks of ncols columns of ng
+ * values with leading dimension ld >= ng; all three are owned by the caller.  The work is
+ * enqueued on hip_stream (a hipStream_t, NULL: the default stream) of the current device
+ * and the call returns without waiting for it.  The split-K partial sums live in a
+ * 32 MiB device array of the library (one per device, kept until the process ends,
+ * located at the first call on the device); 1 <= ncols <= QO_NOALLOC_MAX_COLS so that at
+ * least one row chunk of partials fits.  Every call on a device uses that device's one
+ * array: calls that overlap on one device (other streams or threads) race and must be
+ * serialised by the caller.  Errors: QO_ERR_ARG (null pointer, ng < 1, ld < ng, ncols out
+ * of range, w not positive and finite), QO_ERR_DEVICE (no current device, launch
+ * failure); nothing is enqueued then, and qo_last_error(NULL) gives the message. */
+#define QO_NOALLOC_MAX_COLS 1024
+qo_status qo_gram_pair_noalloc(const double *X, const double *Y, long ld, long ng, int ncols,
+                               double w, double *G, void *hip_stream);
 
 /* Diagnostics of the last step: a block (Ng x N into out with leading
  * dimension ld) or an N x N matrix (column-major host array). */

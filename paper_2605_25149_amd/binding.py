@@ -34,6 +34,7 @@ EXPORTS = [
     "qo_energy_mode",
     "qo_batch_create", "qo_batch_set_potential", "qo_batch_set_state", "qo_batch_get_state",
     "qo_batch_step", "qo_batch_tile", "qo_batch_destroy", "qo_batch_last_error",
+    "qo_gram_pair_noalloc",
 ]
 KERNELS = ["sweep1_f64", "sweep2_f64", "sweep1_f32", "sweep2_f32", "gram", "update", "resid",
            "cg_f64", "cg_f32", "dst_fwd", "dst_pencil", "dst_inv"]
@@ -133,6 +134,8 @@ def load_library(path: str = LIB_PATH):
         "qo_batch_tile": ([H, ctypes.c_int, ip], ctypes.c_int),
         "qo_batch_destroy": ([H], ctypes.c_int),
         "qo_batch_last_error": ([H], ctypes.c_char_p),
+        "qo_gram_pair_noalloc": ([vp, vp, ctypes.c_long, ctypes.c_long, ctypes.c_int,
+                                  ctypes.c_double, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -140,6 +143,33 @@ def load_library(path: str = LIB_PATH):
         f.restype = res
     _lib = lib
     return lib
+
+
+def gram_pair_noalloc(X, Y, w, G, stream=None):
+    """G = w [X | Y]^T [X | Y] through qo_gram_pair_noalloc (no allocation in the library).
+
+    X, Y: blocks (ncols, ng) on the GPU with equal strides; G: a float64 CUDA tensor of
+    (2 ncols)^2 elements that receives the column-major Gram matrix (symmetric, so its
+    row-major view is the same matrix).  Enqueued on `stream` (default: torch's current
+    stream); the call does not wait for the result."""
+    import torch
+
+    lib = load_library()
+    ncols, ng = X.shape
+    ld = _check_block(X, ng)
+    if _check_block(Y, ng, ncols) != ld:
+        raise ValueError("X and Y need the same shape and leading dimension")
+    if G.dtype != torch.float64 or not G.is_cuda or not G.is_contiguous() or \
+            G.numel() != 4 * ncols * ncols:
+        raise ValueError("G must be a contiguous float64 CUDA tensor of (2 ncols)^2 values")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    r = lib.qo_gram_pair_noalloc(ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                 ld, ng, ncols, float(w), ctypes.c_void_p(G.data_ptr()),
+                                 ctypes.c_void_p(st.cuda_stream))
+    if r != QO_OK:
+        msg = lib.qo_last_error(None)
+        raise QOError(r, msg.decode() if msg else "")
+    return G
 
 
 def _status_name(s):

@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqo_hip.so")
 SOURCES = ["qo_api.hip", "qo_stencil.hip", "qo_cg.hip", "qo_gram.hip", "qo_tsgemm.hip",
-           "qo_small.hip", "qo_dst.hip", "qo_batch.hip", "qo_batch_api.hip"]
+           "qo_small.hip", "qo_dst.hip", "qo_batch.hip", "qo_batch_api.hip",
+           "qo_noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -1287,7 +1287,7 @@ const char *qo_status_string(qo_status s) {
     return "QO_ERR_UNKNOWN";
 }
 
-const char *qo_last_error(qo_handle h) { return h ? h->err.c_str() : "null handle"; }
+const char *qo_last_error(qo_handle h) { return h ? h->err.c_str() : qo::noalloc_last_error(); }
 
 qo_status qo_destroy(qo_handle h) {
     if (!h) return QO_ERR_ARG;

@@ -163,6 +163,8 @@ hipError_t launch_refine_mask(const double *sums, int ncols, double tol, double 
 // gram_part_elems(n, nsplit) doubles.
 size_t gram_part_elems(int n, int nsplit);
 int gram_nsplit(long ng, int n);
+// message of the calling thread's last failing handle-free call (qo_last_error(NULL))
+const char *noalloc_last_error();
 // G = w X^T Y (n x n, column-major), FP64 MFMA split over nsplit row chunks; part holds
 // nsplit n x n partials (gram_part_elems(n, nsplit) suffices)
 hipError_t launch_gram_cross_f64(const double *X, const double *Y, long ld, long ng, int n,

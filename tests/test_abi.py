@@ -105,3 +105,23 @@ def test_create_rejects_bad_precond_before_device_work():
     cfg.pcg_variant = 0
     cfg.precond = 2
     assert lib.qo_create(ctypes.byref(cfg), None, ctypes.byref(h)) == binding.QO_ERR_ARG
+
+
+def test_noalloc_gram_validates_before_device_work():
+    """qo_gram_pair_noalloc checks its arguments before any HIP call: null pointers, ld < ng
+    and ncols beyond QO_NOALLOC_MAX_COLS give QO_ERR_ARG and a message from
+    qo_last_error(NULL) (runs without a GPU)."""
+    from paper_2605_25149_amd import binding
+
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libqo_hip.so not built")
+    lib = binding.load_library()
+    fake = ctypes.c_void_p(4096)  # never dereferenced: every call below fails validation
+    f = lib.qo_gram_pair_noalloc
+    assert f(None, fake, 100, 100, 4, 1.0, fake, None) == binding.QO_ERR_ARG
+    assert b"null pointer" in lib.qo_last_error(None)
+    assert f(fake, fake, 99, 100, 4, 1.0, fake, None) == binding.QO_ERR_ARG
+    assert f(fake, fake, 100, 100, 1025, 1.0, fake, None) == binding.QO_ERR_ARG
+    assert b"ncols 1025" in lib.qo_last_error(None)
+    assert f(fake, fake, 100, 100, 0, 1.0, fake, None) == binding.QO_ERR_ARG
+    assert f(fake, fake, 100, 100, 4, 0.0, fake, None) == binding.QO_ERR_ARG

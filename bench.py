@@ -37,16 +37,17 @@ METRIC = "steps/s at 96³,N=256: mixed vs FP64 at 1e-8 eig error; % HBM roofline
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per (grid point x column) of one launch; s = bytes per value of the
 # PCG (8 in FP64, 4 in the mixed path's FP32 iteration); FP16 intermediates are 2 bytes
-#   two-sweep form  sweep1: read r (or z), p_old; write p     -> 3 s
+#   two-sweep form  sweep1: read r, p_old; write p (Jacobi)   -> 3 s
+#                           read z (FP32), p_old; write p       -> 2 s + 4 (fast-Poisson)
 #                   sweep2: read p, x, r;  write x, r         -> 5 s
 #   one-sweep form  cg:     read r, p_old, x; write r, p, x   -> 6 s
 #   fast-Poisson    dst_fwd: read r; write t1 (FP16)          -> s + 2
 #                   dst_pencil: read t1, write t2 (FP16)      -> 4
-#                   dst_inv: read t2 (FP16), r; write z       -> 2 s + 2
+#                   dst_inv: read t2 (FP16), r; write z (FP32) -> s + 6
 BYTES_PER_COLPT = {"sweep1_f64": 24, "sweep2_f64": 40, "sweep1_f32": 12, "sweep2_f32": 20,
                    "cg_f64": 48, "cg_f32": 24}
 DST_BYTES = {"dst_fwd": lambda s: s + 2, "dst_pencil": lambda s: 4,
-             "dst_inv": lambda s: 2 * s + 2}
+             "dst_inv": lambda s: s + 6}
 KERNEL_SYMBOL = {"sweep1_f64": "k_pcg_sweep1<double>", "sweep2_f64": "k_pcg_sweep2<double>",
                  "sweep1_f32": "k_pcg_sweep1<float>", "sweep2_f32": "k_pcg_sweep2<float>",
                  "cg_f64": "k_cg_step<double>", "cg_f32": "k_cg_step<float>",
@@ -182,17 +183,21 @@ def profile_traffic_ratios():
     return ratios
 
 
-def bytes_per_colpt(prof_keys, value_bytes):
+def bytes_per_colpt(prof, value_bytes):
     out = dict(BYTES_PER_COLPT)
+    dst = prof.get("dst_inv", {}).get("launches", 0) > 0
     for k, f in DST_BYTES.items():
         out[k] = f(value_bytes)
-    return {k: v for k, v in out.items() if k in prof_keys}
+    if dst:  # the first sweep reads the FP32 preconditioned residual instead of r
+        out["sweep1_f64"] = 2 * 8 + 4
+        out["sweep1_f32"] = 2 * 4 + 4
+    return {k: v for k, v in out.items() if k in prof}
 
 
 def roofline_of(prof, ng, value_bytes):
     """Dominant streaming kernel (PCG sweeps and preconditioner passes, by total time):
     algorithmic bytes per launch / mean launch duration."""
-    bpc = bytes_per_colpt(prof.keys(), value_bytes)
+    bpc = bytes_per_colpt(prof, value_bytes)
     best = None
     for k in bpc:
         d = prof[k]

@@ -87,8 +87,9 @@ struct qo_ctx {
     bool dst = false;
     DstPlan dp{};
     _Float16 *dS = nullptr, *t1 = nullptr, *t2 = nullptr;
-    float *dmu = nullptr, *pcs = nullptr, *z32 = nullptr;
-    double *z64 = nullptr, *rzp = nullptr, *dsum = nullptr;
+    float *dmu = nullptr, *pcs = nullptr;
+    float *z32 = nullptr;  // preconditioned residual z = M^{-1} r (FP32 in either precision)
+    double *rzp = nullptr, *dsum = nullptr;
     double mu0 = 0.0;  // mu_x[0] + mu_y[0] (+ mu_z[0]): smallest eigenvalue of -Lap_h
     // block CG (pcg_variant 2): Z and ping-pong partners of X, R, P; small matrices;
     // per-column norms and active flags
@@ -107,9 +108,12 @@ struct qo_ctx {
     bool have_tape = false;
     double *ab[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     double *gVd = nullptr, *adpool = nullptr, *admat = nullptr;
-    // pinned host
+    // pinned host: PCG activity flags (two slots, by iteration parity), the refinement
+    // round's flags, the predictor's status, and one iteration-count slot per round
     int *h_poll = nullptr;
     double *h_scal = nullptr;
+    // events marking those read-backs (poll: by parity; round; predictor status)
+    hipEvent_t pev[2] = {nullptr, nullptr}, rev = nullptr, sev = nullptr;
 
     std::vector<void *> allocs;
     bool have_V = false, have_U = false, have_warm = false;
@@ -297,9 +301,13 @@ void prof_end(qo_ctx *c, int kid, hipEvent_t a) {
     c->pend.push_back({kid, a, b});
 }
 
-// call after the stream has been synchronised
+// Durations of the launches that have completed (in stream order: the first one still
+// running ends the harvest; it and the later ones are kept for the next harvest).
 void prof_harvest(qo_ctx *c) {
-    for (auto &p : c->pend) {
+    size_t i = 0;
+    for (; i < c->pend.size(); ++i) {
+        auto &p = c->pend[i];
+        if (hipEventQuery(p.b) != hipSuccess) break;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             c->pdata.ms[p.kid] += ms;
@@ -309,7 +317,33 @@ void prof_harvest(qo_ctx *c) {
         c->evpool.push_back(p.a);
         c->evpool.push_back(p.b);
     }
-    c->pend.clear();
+    c->pend.erase(c->pend.begin(), c->pend.begin() + (long)i);
+}
+
+// Layout of the pinned read-back area (ints).
+constexpr int kMaxRounds = 30;  // refinement rounds per mixed-precision solve, at most
+long poll_ints(int N) { return 2L * (N + 8) + 16 + (long)(kMaxRounds + 2) * N; }
+int *poll_slot(qo_ctx *c, int parity) { return c->h_poll + (long)parity * (c->N + 8); }
+int *round_slot(qo_ctx *c) { return c->h_poll + 2L * (c->N + 8); }
+int *stat_slot(qo_ctx *c) { return round_slot(c) + 8; }
+int *its_slot(qo_ctx *c, int round) { return round_slot(c) + 16 + (long)round * c->N; }
+
+// Kernel-time work counters of one PCG solve from its per-column iteration counts.
+void pcg_account(qo_ctx *c, bool f64, const int *its, int ncols, bool zero_start_dst, bool dst) {
+    if (!c->prof) return;
+    double colits = 0.0;
+    int started = 0;  // columns whose first second sweep ran (x = 0 then: 4 of 5 arrays)
+    for (int j = 0; j < ncols; ++j) {
+        colits += its[j];
+        started += its[j] > 0 ? 1 : 0;
+    }
+    const int k1 = f64 ? QO_KERNEL_SWEEP1_F64 : QO_KERNEL_SWEEP1_F32;
+    const int k2 = f64 ? QO_KERNEL_SWEEP2_F64 : QO_KERNEL_SWEEP2_F32;
+    c->pdata.work[k1] += colits;
+    c->pdata.work[k2] += colits - (zero_start_dst ? 0.2 * started : 0.0);
+    if (dst)
+        for (int kid : {(int)QO_KERNEL_DST_FWD, (int)QO_KERNEL_DST_PENCIL, (int)QO_KERNEL_DST_INV})
+            c->pdata.work[kid] += colits;
 }
 
 qo_status check_poll_err(qo_ctx *c, int code, int col, const char *what) {
@@ -325,7 +359,7 @@ qo_status check_poll_err(qo_ctx *c, int code, int col, const char *what) {
 // z = M^{-1} r (fast-Poisson preconditioner) for the columns that PCG iteration
 // k updates; partial sums of r.z into c->rzp.
 template <typename T>
-qo_status precondition(qo_ctx *c, const T *R, T *Z, int ncols, int k, double tol,
+qo_status precondition(qo_ctx *c, const T *R, float *Z, int ncols, int k, double tol,
                        const int *mask, const PcgState &s) {
     hipStream_t st = c->st;
     const long qs = (long)ncols * c->g.tiles();
@@ -342,15 +376,39 @@ qo_status precondition(qo_ctx *c, const T *R, T *Z, int ncols, int k, double tol
     return QO_OK;
 }
 
+// The flags of a refinement round (active columns, error code and column), copied back
+// asynchronously; ev completes when they have arrived.
+struct RoundPoll {
+    hipEvent_t ev;
+    const int *h;
+};
+
 // PCG on all columns of B (ld c->ld) into X, precision T: Jacobi, or the
 // fast-Poisson preconditioner when c->dst.
-template <typename T>
+//
+// The host learns that every column has converged from the activity flags of the first
+// sweep, copied back asynchronously every pcg_check iterations.  Those of iteration k are
+// read only after iteration k + 1 has been enqueued, so the device never waits for the
+// host: if iteration k was the last, the kernels of iteration k + 1 find every column
+// inactive and return at once (converged columns are frozen on the device; iteration
+// counts and results are those of a synchronous poll).  At pcg_maxit the flags are read
+// synchronously.
+//
 // skip_init: R already holds the residual, X is zero and the partial sums of ||r||^2 and
 // of the norm the stop test is relative to sit in s.part (+qs, +2qs); B is not read.
 // Only with the fast-Poisson preconditioner (the Jacobi form also needs r.D r).
+// outer (may be NULL): the flags of the refinement round that asked for this solve, not
+// yet read; they are read once the first iteration is enqueued, and when no column is
+// active *outer_done is set and nothing else is done (the enqueued kernels do nothing).
+// its_async (may be NULL): the per-column iteration counts are copied there (pinned host
+// memory) without waiting, its_out is not written and the caller accounts for the
+// work once the copy has completed; otherwise the counts are waited for.
+template <typename T>
 qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *P0, T *P1,
               int ncols, int use_x0, double tol, const int *mask, const double *coltol,
-              int *its_out, const char *what, bool skip_init = false) {
+              int *its_out, const char *what, bool skip_init = false,
+              const RoundPoll *outer = nullptr, bool *outer_done = nullptr,
+              int *its_async = nullptr) {
     const Grid &g = c->g;
     hipStream_t st = c->st;
     PcgState s = c->ps;
@@ -366,51 +424,74 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
     const bool f64 = sizeof(T) == 8;
     const int k1 = f64 ? QO_KERNEL_SWEEP1_F64 : QO_KERNEL_SWEEP1_F32;
     const int k2 = f64 ? QO_KERNEL_SWEEP2_F64 : QO_KERNEL_SWEEP2_F32;
-    T *Z = nullptr;
-    if (c->dst) Z = reinterpret_cast<T *>(f64 ? (void *)c->z64 : (void *)c->z32);
+    float *Z = c->dst ? c->z32 : nullptr;
+    // activity flags and error code of iteration k into the slot of its parity
+    auto post_poll = [&](int k) -> qo_status {
+        int *h = poll_slot(c, k & 1);
+        HIPC(c, hipMemcpyAsync(h, s.active + (k & 1) * ncols, sizeof(int) * ncols,
+                               hipMemcpyDeviceToHost, st));
+        HIPC(c, hipMemcpyAsync(h + ncols, s.err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPC(c, hipEventRecord(c->pev[k & 1], st));
+        return QO_OK;
+    };
+    // wait for the flags of iteration k; *nact: columns still active
+    auto read_poll = [&](int k, int *nact) -> qo_status {
+        HIPC(c, hipEventSynchronize(c->pev[k & 1]));
+        prof_harvest(c);
+        const int *h = poll_slot(c, k & 1);
+        if (h[ncols]) return check_poll_err(c, h[ncols], h[ncols + 1], what);
+        int n = 0;
+        for (int j = 0; j < ncols; ++j) n += h[j] ? 1 : 0;
+        *nact = n;
+        return QO_OK;
+    };
+    int pend = -1;  // the iteration whose flags are in flight
     for (int k = 0;; ++k) {
         if (Z) QOC(precondition<T>(c, R, Z, ncols, k, tol, mask, s));
         hipEvent_t ea = prof_begin(c);
         HIPC(c, launch_pcg_sweep1<T>(g, vs, dinv, R, pbuf[(k + 1) & 1], pbuf[k & 1], c->ld, ncols,
                                      k, tol, mask, s, st, Z, c->rzp, c->dp.nslab));
         prof_end(c, k1, ea);
-        if (k % check == 0 || k >= maxit) {
-            HIPC(c, hipMemcpyAsync(c->h_poll, s.active + (k & 1) * ncols, sizeof(int) * ncols,
-                                   hipMemcpyDeviceToHost, st));
-            HIPC(c, hipMemcpyAsync(c->h_poll + ncols, s.err, 2 * sizeof(int),
-                                   hipMemcpyDeviceToHost, st));
-            HIPC(c, hipStreamSynchronize(st));
+        if (outer && k == 0) {
+            HIPC(c, hipEventSynchronize(outer->ev));
             prof_harvest(c);
-            if (c->h_poll[ncols]) return check_poll_err(c, c->h_poll[ncols], c->h_poll[ncols + 1], what);
-            int nact = 0;
-            for (int j = 0; j < ncols; ++j) nact += c->h_poll[j] ? 1 : 0;
-            if (nact == 0) break;
-            if (k >= maxit)
-                return fail(c, QO_ERR_PCG_NOCONV, "%s: %d of %d columns not converged after %d "
-                            "PCG iterations (tol %.3g)", what, nact, ncols, maxit, tol);
+            if (outer->h[1]) return check_poll_err(c, outer->h[1], outer->h[2], what);
+            if (outer->h[0] == 0) {
+                *outer_done = true;
+                return QO_OK;
+            }
         }
+        if (k >= maxit) {
+            int nact = 0;
+            QOC(post_poll(k));
+            QOC(read_poll(k, &nact));
+            if (nact == 0) break;
+            return fail(c, QO_ERR_PCG_NOCONV, "%s: %d of %d columns not converged after %d "
+                        "PCG iterations (tol %.3g)", what, nact, ncols, maxit, tol);
+        }
+        const bool poll_now = k % check == 0;
+        if (poll_now) QOC(post_poll(k));
+        if (pend >= 0) {
+            int nact = 0;
+            QOC(read_poll(pend, &nact));
+            if (nact == 0) break;
+        }
+        pend = poll_now ? k : -1;
         hipEvent_t eb = prof_begin(c);
         HIPC(c, launch_pcg_sweep2<T>(g, vs, dinv, pbuf[k & 1], X, R, c->ld, ncols, k, s, st,
                                      Z == nullptr, k == 0 && skip_init && Z != nullptr));
         prof_end(c, k2, eb);
     }
-    HIPC(c, hipMemcpyAsync(c->h_poll, s.its, sizeof(int) * ncols, hipMemcpyDeviceToHost, st));
+    if (its_async) {
+        HIPC(c, hipMemcpyAsync(its_async, s.its, sizeof(int) * ncols, hipMemcpyDeviceToHost, st));
+        return QO_OK;
+    }
+    int *h = poll_slot(c, 0);
+    HIPC(c, hipMemcpyAsync(h, s.its, sizeof(int) * ncols, hipMemcpyDeviceToHost, st));
     HIPC(c, hipStreamSynchronize(st));
     prof_harvest(c);
-    double colits = 0.0;
-    int started = 0;  // columns whose first second sweep ran (x = 0 then: 4 of 5 arrays)
-    for (int j = 0; j < ncols; ++j) {
-        its_out[j] = c->h_poll[j];
-        colits += c->h_poll[j];
-        started += c->h_poll[j] > 0 ? 1 : 0;
-    }
-    if (c->prof) {
-        c->pdata.work[k1] += colits;
-        c->pdata.work[k2] += colits - ((skip_init && Z) ? 0.2 * started : 0.0);
-        if (Z)
-            for (int kid : {(int)QO_KERNEL_DST_FWD, (int)QO_KERNEL_DST_PENCIL, (int)QO_KERNEL_DST_INV})
-                c->pdata.work[kid] += colits;
-    }
+    for (int j = 0; j < ncols; ++j) its_out[j] = h[j];
+    pcg_account(c, f64, its_out, ncols, skip_init && Z, Z != nullptr);
     return QO_OK;
 }
 
@@ -819,13 +900,17 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
     for (int j = 0; j < ncols; ++j) its[j] = 0;
     std::vector<int> inner(ncols);
     const long qs = (long)ncols * g.tiles();
-    const int max_rounds = 30;
+    const int max_rounds = kMaxRounds;
     // With the fast-Poisson solve the update x += d of one round is taken by the residual
     // pass of the next, which writes x + d out of place: the iterate moves between X and
-    // the spare FP64 block r (not used by the mixed solve otherwise).
+    // the spare FP64 block r (not used by the mixed solve otherwise).  There the round's
+    // convergence flags are read only after the next inner solve's first iteration has
+    // been enqueued (that iteration does nothing when the round found every column
+    // converged), and the inner iteration counts are gathered at the end.
     const bool fused = c->dst && !one_sweep;
     double *xc = X, *xs = c->r;
     bool pending = false;
+    int done_rounds = 0;
     for (int round = 0;; ++round) {
         int init_err[2] = {0, INT_MAX};
         HIPC(c, hipMemcpyAsync(c->ps.err, init_err, sizeof init_err, hipMemcpyHostToDevice, st));
@@ -843,48 +928,73 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
         HIPC(c, launch_colsum(c->part + qs, g.tiles(), ncols, 2, qs, c->colsums, st));
         HIPC(c, launch_refine_mask(c->colsums, ncols, tol, c->cfg.refine_inner_tol, c->mask,
                                    c->coltol, c->nact, c->ps.err, st));
-        HIPC(c, hipMemcpyAsync(c->h_poll, c->nact, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPC(c, hipMemcpyAsync(c->h_poll + 1, c->ps.err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPC(c, hipStreamSynchronize(st));
-        prof_harvest(c);
-        if (c->h_poll[1]) return check_poll_err(c, c->h_poll[1], c->h_poll[2], what);
-        if (c->h_poll[0] == 0) {
+        int *hr = round_slot(c);
+        HIPC(c, hipMemcpyAsync(hr, c->nact, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPC(c, hipMemcpyAsync(hr + 1, c->ps.err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPC(c, hipEventRecord(c->rev, st));
+        bool done = false;
+        const bool speculate = fused && round < max_rounds;
+        if (!speculate) {
+            HIPC(c, hipEventSynchronize(c->rev));
+            prof_harvest(c);
+            if (hr[1]) return check_poll_err(c, hr[1], hr[2], what);
+            done = hr[0] == 0;
+            if (!done && round >= max_rounds)
+                return fail(c, QO_ERR_PCG_NOCONV,
+                            "%s: refinement did not reach tol %.3g in %d rounds", what, tol,
+                            max_rounds);
+        }
+        if (!done) {
+            if (one_sweep) {
+                QOC(pcg_cg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->rr32, c->rr32b,
+                                  c->pa32, c->pb32, ncols, 0, c->cfg.refine_inner_tol, c->mask,
+                                  c->coltol, inner.data(), what));
+            } else if (c->dst) {
+                // The FP32 solve works on r32 in place (the next round recomputes it) and
+                // skips its init pass: it starts from d = 0 without clearing d (its first
+                // update writes d = alpha p instead of adding), and ||r||^2 from the residual
+                // pass serves as both the starting residual and the norm the inner stop test
+                // is relative to.
+                HIPC(c, hipMemcpyAsync(c->part + 2 * qs, c->part + qs, sizeof(double) * qs,
+                                       hipMemcpyDeviceToDevice, st));
+                const RoundPoll rp{c->rev, hr};
+                bool outer_done = false;
+                QOC(pcg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->r32, c->pa32, c->pb32,
+                               ncols, 0, c->cfg.refine_inner_tol, c->mask, c->coltol,
+                               inner.data(), what, true, speculate ? &rp : nullptr, &outer_done,
+                               its_slot(c, round)));
+                done = outer_done;
+            } else {
+                QOC(pcg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->rr32, c->pa32, c->pb32,
+                               ncols, 0, c->cfg.refine_inner_tol, c->mask, c->coltol,
+                               inner.data(), what));
+            }
+        }
+        if (done) {
             *rounds = round;
+            done_rounds = round;
             if (xc != X)
                 HIPC(c, hipMemcpyAsync(X, xc, sizeof(double) * c->ld * ncols,
                                        hipMemcpyDeviceToDevice, st));
             break;
         }
-        if (round >= max_rounds)
-            return fail(c, QO_ERR_PCG_NOCONV, "%s: refinement did not reach tol %.3g in %d rounds",
-                        what, tol, max_rounds);
-        if (one_sweep) {
-            QOC(pcg_cg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->rr32, c->rr32b, c->pa32,
-                              c->pb32, ncols, 0, c->cfg.refine_inner_tol, c->mask, c->coltol,
-                              inner.data(), what));
-        } else if (c->dst) {
-            // The FP32 solve works on r32 in place (the next round recomputes it) and skips
-            // its init pass: it starts from d = 0 without clearing d (its first update
-            // writes d = alpha p instead of adding), and ||r||^2 from the residual pass
-            // serves as both the starting residual and the norm the inner stop test is
-            // relative to.
-            HIPC(c, hipMemcpyAsync(c->part + 2 * qs, c->part + qs, sizeof(double) * qs,
-                                   hipMemcpyDeviceToDevice, st));
-            QOC(pcg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->r32, c->pa32, c->pb32,
-                           ncols, 0, c->cfg.refine_inner_tol, c->mask, c->coltol, inner.data(),
-                           what, true));
-        } else {
-            QOC(pcg<float>(c, c->vs32, c->dinv32, c->r32, c->d32, c->rr32, c->pa32, c->pb32,
-                           ncols, 0, c->cfg.refine_inner_tol, c->mask, c->coltol, inner.data(),
-                           what));
-        }
-        for (int j = 0; j < ncols; ++j) its[j] += inner[j];
+        if (!c->dst || one_sweep)
+            for (int j = 0; j < ncols; ++j) its[j] += inner[j];
         // With the fast-Poisson solve d was written only in columns that took at least one
         // inner iteration (the others hold an older correction): those alone are updated.
         if (fused)
             pending = true;
         else
             HIPC(c, launch_refine_axpy(xc, c->ld, c->d32, c->ld, c->ng, ncols, c->mask, 0, st));
+    }
+    if (fused) {
+        // every round's counts were copied before the last round's flags, which have been
+        // read: the copies are complete
+        for (int r = 0; r < done_rounds; ++r) {
+            const int *h = its_slot(c, r);
+            for (int j = 0; j < ncols; ++j) its[j] += h[j];
+            pcg_account(c, false, h, ncols, true, true);
+        }
     }
     return QO_OK;
 }
@@ -933,6 +1043,13 @@ qo_status energy_of(qo_ctx *c, const double *U, double *Es, double *trS) {
     HIPC(c, hipStreamSynchronize(c->st));
     *Es = c->h_scal[4];
     *trS = c->h_scal[5];
+    return QO_OK;
+}
+
+qo_status status_error(qo_ctx *c, int hs, const char *what) {
+    if (hs == 5) return fail(c, QO_ERR_NOT_SPD, "%s: matrix not positive definite / singular", what);
+    if (hs == 7) return fail(c, QO_ERR_NONFINITE, "%s: non-finite matrix entries", what);
+    if (hs) return fail(c, QO_ERR_DEVICE, "%s: status %d", what, hs);
     return QO_OK;
 }
 
@@ -1089,12 +1206,19 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
     HIPC(c, nn_axpby(mp(c, MP_XR), N, 0.0, nullptr, N, 1.0, mp(c, MP_X), N, true, 0.0, N, N, st));
     HIPC(c, nn_axpby(mp(c, MP_YR), N, 0.0, nullptr, N, 1.0, mp(c, MP_Y), N, true, 0.0, N, N, st));
     HIPC(c, nn_axpby(mp(c, MP_ZR), N, 0.0, nullptr, N, 1.0, mp(c, MP_Z), N, true, 0.0, N, N, st));
-    QOC(check_status(c, "predictor N x N solve"));
+    // The predictor's status is read back without waiting; it is looked at once the second
+    // solve is done (before any error of that solve, which a failed N x N solve may cause).
+    // U_n is not written before then, so a failure still leaves the step undone.
+    HIPC(c, hipMemcpyAsync(stat_slot(c), c->dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPC(c, hipEventRecord(c->sev, st));
     rec(c, 3);
     QOC(tsgemm(c, c->Uh, nullptr, c->U, mp(c, MP_XR), P, mp(c, MP_YR)));
     if (warm) QOC(tsgemm(c, Q, nullptr, P, mp(c, MP_ZR), nullptr, nullptr));
     rec(c, 4);
-    QOC(solve_block(c, c->Uh, Q, N, warm, itsQ.data(), &rQ, "solve G U_hat"));
+    const qo_status sQ = solve_block(c, c->Uh, Q, N, warm, itsQ.data(), &rQ, "solve G U_hat");
+    HIPC(c, hipEventSynchronize(c->sev));
+    QOC(status_error(c, stat_slot(c)[0], "predictor N x N solve"));
+    if (sQ != QO_OK) return sQ;
     rec(c, 5);
     QOC(gram(c, c->Uh, Q, ld, N, c->G2));
     rec(c, 6);
@@ -1298,6 +1422,8 @@ qo_status qo_destroy(qo_handle h) {
     if (h->h_scal) (void)hipHostFree(h->h_scal);
     if (h->ev_ok)
         for (auto &e : h->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {h->pev[0], h->pev[1], h->rev, h->sev})
+        if (e) (void)hipEventDestroy(e);
     for (auto &p : h->pend) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -1412,8 +1538,7 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
         A(&h->pcs, (size_t)N);
         A(&h->rzp, (size_t)N * dp.nslab);
         A(&h->dsum, 1);
-        if (h->mixed) A(&h->z32, blk);
-        else A(&h->z64, blk);
+        A(&h->z32, blk);
         if (s == QO_OK) {
             dp.Sx = h->dS;
             dp.Sy = h->dS + sx;
@@ -1449,9 +1574,13 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
     }
     h->ps.part = h->part;
     if (s == QO_OK) {
-        if (hipHostMalloc((void **)&h->h_poll, sizeof(int) * (N + 8)) != hipSuccess ||
+        if (hipHostMalloc((void **)&h->h_poll, sizeof(int) * poll_ints(N)) != hipSuccess ||
             hipHostMalloc((void **)&h->h_scal, sizeof(double) * 16) != hipSuccess)
             s = QO_ERR_ALLOC;
+    }
+    if (s == QO_OK) {
+        for (hipEvent_t *e : {&h->pev[0], &h->pev[1], &h->rev, &h->sev})
+            if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) s = QO_ERR_DEVICE;
     }
     if (s == QO_OK) {
         h->ev_ok = true;
@@ -1769,7 +1898,9 @@ qo_status qo_precond(qo_handle h, const double *R, double *Z, long ld, int ncols
     HIPC(h, launch_col_scale(h->W, h->ld, h->ng, ncols, h->pcs, st));
     HIPC(h, launch_dst_fwd<double>(h->dp, h->W, h->ld, ncols, h->t1, h->pcs, st));
     HIPC(h, launch_dst_pencil(h->dp, h->t1, h->t2, h->ld, ncols, h->pcs, st));
-    HIPC(h, launch_dst_inv<double>(h->dp, h->t2, h->W, h->W2, h->ld, ncols, h->pcs, h->rzp, st));
+    HIPC(h, launch_dst_inv<double>(h->dp, h->t2, h->W, h->z32, h->ld, ncols, h->pcs, h->rzp,
+                                   st));
+    HIPC(h, launch_z_expand(h->z32, h->pcs, h->W2, h->ld, h->ng, ncols, st));
     HIPC(h, hipMemcpy2DAsync(Z, sizeof(double) * ld, h->W2, sizeof(double) * h->ld, row, ncols,
                              hipMemcpyDeviceToDevice, st));
     if (rz) {

@@ -59,7 +59,7 @@ struct qo_batch_ctx {
         int ruse = 0;  // refinement rounds per solve in use
         std::vector<int> kr;  // FP32 iterations of each round in use
         float *vs32 = nullptr, *dinv32 = nullptr, *r32 = nullptr, *d32 = nullptr,
-              *rr32 = nullptr, *pa32 = nullptr, *pb32 = nullptr, *z32 = nullptr;
+              *rr32 = nullptr, *pa32 = nullptr, *pb32 = nullptr;
         double *colsums = nullptr, *cin = nullptr;
         int *mask = nullptr, *nact = nullptr, *its32 = nullptr;
         // per solve: per column the FP32 iterations summed over the rounds and the rounds
@@ -69,8 +69,9 @@ struct qo_batch_ctx {
         double w = 1.0;
         std::vector<int> members;
         double *U = nullptr, *Uh = nullptr, *PQ[2] = {nullptr, nullptr}, *r = nullptr,
-               *pa = nullptr, *pb = nullptr, *z = nullptr;
+               *pa = nullptr, *pb = nullptr;
         _Float16 *t1 = nullptr, *t2 = nullptr, *dS = nullptr;
+        float *z = nullptr;  // preconditioned residual (FP32 in either precision)
         float *dmu = nullptr, *pcs = nullptr, *cvbar = nullptr, *clmin = nullptr;
         double *vs = nullptr, *dinv = nullptr, *coltol = nullptr, *part = nullptr, *rzp = nullptr;
         double *G1 = nullptr, *G2 = nullptr, *pool = nullptr, *gpart = nullptr, *scal = nullptr,
@@ -283,12 +284,12 @@ qo_status group_solve_mixed(qo_batch_ctx *b, qo_batch_ctx::Group &G, const doubl
                 BHIP(b, launch_pc_prep(k, G.C, G.mask, s, G.qs, tiles, 0.0, G.ng, G.pcs, st));
                 BHIP(b, launch_dst_fwd<float>(G.dp, G.rr32, G.ld, G.C, G.t1, G.pcs, st));
                 BHIP(b, launch_dst_pencil(G.dp, G.t1, G.t2, G.ld, G.C, G.pcs, st));
-                BHIP(b, launch_dst_inv<float>(G.dp, G.t2, G.rr32, G.z32, G.ld, G.C, G.pcs, G.rzp,
+                BHIP(b, launch_dst_inv<float>(G.dp, G.t2, G.rr32, G.z, G.ld, G.C, G.pcs, G.rzp,
                                               st));
             }
             BHIP(b, launch_pcg_sweep1<float>(g, G.vs32, G.dinv32, G.rr32, pbuf[(k + 1) & 1],
                                              pbuf[k & 1], G.ld, G.C, k, 0.0, G.mask, s, st,
-                                             G.dst ? G.z32 : nullptr, G.rzp, G.dp.nslab));
+                                             G.dst ? G.z : nullptr, G.rzp, G.dp.nslab));
             if (k == K) break;
             BHIP(b, launch_pcg_sweep2<float>(g, G.vs32, G.dinv32, pbuf[k & 1], G.d32, G.rr32,
                                              G.ld, G.C, k, s, st, !G.dst));
@@ -421,7 +422,6 @@ qo_status build_group(qo_batch_ctx *b, qo_batch_ctx::Group &G) {
         BQO(A(&G.rr32, blk));
         BQO(A(&G.pa32, blk));
         BQO(A(&G.pb32, blk));
-        if (cf.precond == 1) BQO(A(&G.z32, blk));
         BQO(A(&G.colsums, (size_t)2 * G.C));
         BQO(A(&G.cin, (size_t)G.C));
         BQO(A(&G.mask, (size_t)G.C));

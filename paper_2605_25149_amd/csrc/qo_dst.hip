@@ -25,8 +25,11 @@
 //   plane   (forward)  r (T) -> t1 (FP16): transform along x (and y in 3-D)
 //   pencil             t1 -> t2 (FP16):    along the slowest axis, scale by
 //                                          lambda_min/lambda, transform back
-//   plane   (inverse)  t2 -> z (T):        along x (and y), unscale; partial
-//                                          sums of r.z for the PCG step
+//   plane   (inverse)  t2 -> z (FP32):     along x (and y), unscale; partial sums
+//                                          of r.z for the PCG step.  z is FP32 in
+//                                          the FP64 PCG too: its values carry FP32
+//                                          precision (FP32 accumulation of FP16
+//                                          transforms), so nothing is lost.
 // "Plane" is one z-plane in 3-D and a batch of rows in 2-D; the slowest axis
 // is z in 3-D and y in 2-D.
 #include "qo_internal.h"
@@ -178,8 +181,8 @@ __host__ __device__ inline size_t dst_plane_xt_bytes(const DstPlan &p) {
 // padded x-points in LDS (FP16).  Wave w owns output rows [16w, 16w + 16).
 //   GEMM1  T = X S_x     (A = X rows from LDS, B = rows of S_x: S symmetric)
 //   GEMM2  Y = S_y T     (3-D only; T staged transposed in LDS)
-// Forward: X = sc * r, output FP16.  Inverse: X = t2, output z = Y / (sc lmin)
-// in T, plus the slab's partial sum of r.z.
+// Forward: X = sc * r, output FP16.  Inverse: X = t2, output z = Y / (sc lmin) in FP32,
+// plus the slab's partial sum of r.z (z taken in T).
 // VEC: rows are whole 16-byte groups (nx % 8 == 0): vector loads and stores throughout.
 // FP32 3-D planes (NT <= 8) are held to 80 registers: 6 waves per SIMD, four 6-wave
 // workgroups per CU, as many as their LDS allows.
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_dst_plane(DstPlan p, const T *__restrict__ R,
                                                    const _Float16 *__restrict__ Hin,
                                                    _Float16 *__restrict__ Hout,
-                                                   T *__restrict__ Z, long ld,
+                                                   float *__restrict__ Z, long ld,
                                                    const float *__restrict__ pcs,
                                                    double *__restrict__ rzp) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -452,12 +455,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
                 if (r >= rows || x >= nx) continue;
                 const long i0 = base + (long)r * nx + x;
                 const float4 z4 = *reinterpret_cast<const float4 *>(SF + r * FP + x);
-                if constexpr (sizeof(T) == 4) {
-                    st_out(reinterpret_cast<v4f *>(Z + i0), v4f{z4.x, z4.y, z4.z, z4.w});
-                } else {
-                    st_out(reinterpret_cast<v2d *>(Z + i0), v2d{z4.x, z4.y});
-                    st_out(reinterpret_cast<v2d *>(Z + i0 + 2), v2d{z4.z, z4.w});
-                }
+                st_out(reinterpret_cast<v4f *>(Z + i0), v4f{z4.x, z4.y, z4.z, z4.w});
                 rz += (double)rr[q][0] * (double)(T)z4.x + (double)rr[q][1] * (double)(T)z4.y +
                       (double)rr[q][2] * (double)(T)z4.z + (double)rr[q][3] * (double)(T)z4.w;
             }
@@ -471,9 +469,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     if (x + i >= nx) break;
-                    const T zv = (T)src[i];
+                    const float zv = src[i];
                     Z[i0 + i] = zv;
-                    rz += (double)R[i0 + i] * (double)zv;
+                    rz += (double)R[i0 + i] * (double)(T)zv;
                 }
             }
         }
@@ -748,8 +746,8 @@ void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz) {
     p.npen = (p.nf + kPenMB - 1) / kPenMB;
 }
 
-// X (RP x (NXP+8) halves) and, in 3-D, TT (NXP x (NYP+8) halves); the inverse pass
-// also stages its FP32 output (RP x (NXP+4) floats) over the same space.
+// X (RP x (NXP+8) halves) and, in 3-D, TT (NXP x (NYP+8) halves), then the S_x copy; the
+// inverse pass also stages its FP32 output (RP x (NXP+4) floats) over the same space.
 size_t dst_plane_lds(const DstPlan &p, bool inv) {
     size_t b = dst_plane_xt_bytes(p);
     if (p.NXP <= 128) b += (size_t)p.NXP * (p.NXP + 8) * 2;  // S_x copy
@@ -860,7 +858,7 @@ hipError_t launch_dst_pencil(const DstPlan &p, const _Float16 *t1, _Float16 *t2,
 }
 
 template <typename T>
-hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, const T *R, T *Z, long ld,
+hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, const T *R, float *Z, long ld,
                           int ncols, const float *pcs, double *rzp, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
     const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
@@ -876,12 +874,34 @@ hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, const T *R, T *Z
     return hipGetLastError();
 }
 
+namespace {
+// Z (FP64) = Z32 for columns with pcs[c] != 0, else 0.
+__global__ void k_z_expand(const float *__restrict__ Z32, const float *__restrict__ pcs,
+                           double *__restrict__ Z, long ld, long ng) {
+    const int c = blockIdx.y;
+    const bool on = pcs[c] != 0.f;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ng;
+         i += (long)gridDim.x * blockDim.x)
+        Z[(long)c * ld + i] = on ? (double)Z32[(long)c * ld + i] : 0.0;
+}
+}  // namespace
+
+hipError_t launch_z_expand(const float *Z32, const float *pcs, double *Z, long ld, long ng,
+                           int ncols, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    long bx = (ng + 255) / 256;
+    if (bx > 1024) bx = 1024;
+    hipLaunchKernelGGL(k_z_expand, dim3((unsigned)bx, (unsigned)ncols), dim3(256), 0, st, Z32,
+                       pcs, Z, ld, ng);
+    return hipGetLastError();
+}
+
 template hipError_t launch_dst_fwd<double>(const DstPlan &, const double *, long, int,
                                            _Float16 *, const float *, hipStream_t);
 template hipError_t launch_dst_fwd<float>(const DstPlan &, const float *, long, int, _Float16 *,
                                           const float *, hipStream_t);
 template hipError_t launch_dst_inv<double>(const DstPlan &, const _Float16 *, const double *,
-                                           double *, long, int, const float *, double *,
+                                           float *, long, int, const float *, double *,
                                            hipStream_t);
 template hipError_t launch_dst_inv<float>(const DstPlan &, const _Float16 *, const float *,
                                           float *, long, int, const float *, double *,

@@ -83,9 +83,14 @@ hipError_t launch_dst_fwd(const DstPlan &p, const T *R, long ld, int ncols, _Flo
                           const float *pcs, hipStream_t st);
 hipError_t launch_dst_pencil(const DstPlan &p, const _Float16 *t1, _Float16 *t2, long ld,
                              int ncols, const float *pcs, hipStream_t st);
+// z is FP32 in either precision (its values carry FP32 precision); launch_z_expand gives
+// an FP64 copy.
 template <typename T>
-hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, const T *R, T *Z, long ld,
+hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, const T *R, float *Z, long ld,
                           int ncols, const float *pcs, double *rzp, hipStream_t st);
+// Z (FP64) = Z32 for the columns with pcs[c] != 0, zero elsewhere.
+hipError_t launch_z_expand(const float *Z32, const float *pcs, double *Z, long ld, long ng,
+                           int ncols, hipStream_t st);
 
 // ---- stencil family (qo_stencil.hip) ----
 // All take a column count `ncols`, a column stride `ld` and per-point arrays
@@ -107,8 +112,9 @@ hipError_t launch_pcg_init(const Grid &g, const T *vs, const T *dinv, const T *B
 template <typename T>
 hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T *R,
                              const T *Pold, T *Pnew, long ld, int ncols, int k, double tol,
-                             const int *mask, PcgState s, hipStream_t st, const T *Z = nullptr,
-                             const double *rzp = nullptr, int rzt = 0);
+                             const int *mask, PcgState s, hipStream_t st,
+                             const float *Z = nullptr, const double *rzp = nullptr,
+                             int rzt = 0);
 template <typename T>
 // xzero: X is zero on entry (first iteration without an init pass; preconditioned form
 // only): X = alpha p is written without reading X.

@@ -367,15 +367,15 @@ struct LdPcgP {  // p = D r + beta p_old  (beta = 0: p = D r, p_old not read)
 };
 
 template <typename T>
-struct LdPcgZ {  // p = z + beta p_old with an explicit preconditioned residual z
-    struct Raw { T z, p; };
-    const T *__restrict__ z;
+struct LdPcgZ {  // p = z + beta p_old with an explicit preconditioned residual z (FP32)
+    struct Raw { float z; T p; };
+    const float *__restrict__ z;
     const T *__restrict__ po;
     T beta;
     bool first;
-    __device__ static Raw zero() { return {T(0), T(0)}; }
+    __device__ static Raw zero() { return {0.f, T(0)}; }
     __device__ Raw load(long i) const { return {z[i], first ? T(0) : po[i]}; }
-    __device__ T make(const Raw &a) const { return first ? a.z : a.z + beta * a.p; }
+    __device__ T make(const Raw &a) const { return first ? (T)a.z : (T)a.z + beta * a.p; }
 };
 
 struct NoRaw {};
@@ -692,7 +692,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && XZ && PPT == 3 ? 6 : 1))) v
                                                          int k, double tol,
                                                          const int *__restrict__ mask,
                                                          PcgState s, long qs,
-                                                         const T *__restrict__ Z,
+                                                         const float *__restrict__ Z,
                                                          const double *__restrict__ rzp, int rzt) {
     __shared__ Red red;
     __shared__ int sh_flag;
@@ -1043,7 +1043,7 @@ hipError_t launch_pcg_init(const Grid &g, const T *vs, const T *dinv, const T *B
 template <typename T>
 hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T *R,
                              const T *Pold, T *Pnew, long ld, int ncols, int k, double tol,
-                             const int *mask, PcgState s, hipStream_t st, const T *Z,
+                             const int *mask, PcgState s, hipStream_t st, const float *Z,
                              const double *rzp, int rzt) {
     if (ncols <= 0) return hipSuccess;
     const long qs = (long)ncols * g.tiles();
@@ -1097,7 +1097,7 @@ template hipError_t launch_pcg_init<float>(const Grid &, const float *, const fl
 template hipError_t launch_pcg_sweep1<double>(const Grid &, const double *, const double *,
                                               const double *, const double *, double *, long,
                                               int, int, double, const int *, PcgState,
-                                              hipStream_t, const double *, const double *, int);
+                                              hipStream_t, const float *, const double *, int);
 template hipError_t launch_pcg_sweep1<float>(const Grid &, const float *, const float *,
                                              const float *, const float *, float *, long, int,
                                              int, double, const int *, PcgState, hipStream_t,

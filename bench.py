@@ -43,11 +43,11 @@ HBM_PEAK_GBS = 8000.0
 #   one-sweep form  cg:     read r, p_old, x; write r, p, x   -> 6 s
 #   fast-Poisson    dst_fwd: read r; write t1 (FP16)          -> s + 2
 #                   dst_pencil: read t1, write t2 (FP16)      -> 4
-#                   dst_inv: read t2 (FP16), r; write z (FP32) -> s + 6
+#                   dst_inv: read t2 (FP16); write z (FP32)    -> 6
 BYTES_PER_COLPT = {"sweep1_f64": 24, "sweep2_f64": 40, "sweep1_f32": 12, "sweep2_f32": 20,
                    "cg_f64": 48, "cg_f32": 24}
 DST_BYTES = {"dst_fwd": lambda s: s + 2, "dst_pencil": lambda s: 4,
-             "dst_inv": lambda s: s + 6}
+             "dst_inv": lambda s: 6}
 KERNEL_SYMBOL = {"sweep1_f64": "k_pcg_sweep1<double>", "sweep2_f64": "k_pcg_sweep2<double>",
                  "sweep1_f32": "k_pcg_sweep1<float>", "sweep2_f32": "k_pcg_sweep2<float>",
                  "cg_f64": "k_cg_step<double>", "cg_f32": "k_cg_step<float>",
@@ -213,8 +213,8 @@ def roofline_of(prof, ng, value_bytes):
     mean_ms = d["ms"] / d["launches"]
     achieved = per_launch_bytes / (mean_ms * 1e-3) / 1e9
     sym = KERNEL_SYMBOL.get(best) or {
-        "dst_fwd": "k_dst_plane<%s,false>", "dst_inv": "k_dst_plane<%s,true>"}[best] % (
-        "float" if value_bytes == 4 else "double")
+        "dst_fwd": "k_dst_plane<%s,false>" % ("float" if value_bytes == 4 else "double"),
+        "dst_inv": "k_dst_plane<float,true>"}[best]
     return {
         "kernel": sym,
         "bound": "hbm",

@@ -357,7 +357,7 @@ qo_status check_poll_err(qo_ctx *c, int code, int col, const char *what) {
 }
 
 // z = M^{-1} r (fast-Poisson preconditioner) for the columns that PCG iteration
-// k updates; partial sums of r.z into c->rzp.
+// k updates; partial sums of r.z (from the spectral coefficients) into c->rzp.
 template <typename T>
 qo_status precondition(qo_ctx *c, const T *R, float *Z, int ncols, int k, double tol,
                        const int *mask, const PcgState &s) {
@@ -368,10 +368,10 @@ qo_status precondition(qo_ctx *c, const T *R, float *Z, int ncols, int k, double
     HIPC(c, launch_dst_fwd<T>(c->dp, R, c->ld, ncols, c->t1, c->pcs, st));
     prof_end(c, QO_KERNEL_DST_FWD, e0);
     hipEvent_t e1 = prof_begin(c);
-    HIPC(c, launch_dst_pencil(c->dp, c->t1, c->t2, c->ld, ncols, c->pcs, st));
+    HIPC(c, launch_dst_pencil(c->dp, c->t1, c->t2, c->ld, ncols, c->pcs, c->rzp, st));
     prof_end(c, QO_KERNEL_DST_PENCIL, e1);
     hipEvent_t e2 = prof_begin(c);
-    HIPC(c, launch_dst_inv<T>(c->dp, c->t2, R, Z, c->ld, ncols, c->pcs, c->rzp, st));
+    HIPC(c, launch_dst_inv(c->dp, c->t2, Z, c->ld, ncols, c->pcs, st));
     prof_end(c, QO_KERNEL_DST_INV, e2);
     return QO_OK;
 }
@@ -450,7 +450,7 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
         if (Z) QOC(precondition<T>(c, R, Z, ncols, k, tol, mask, s));
         hipEvent_t ea = prof_begin(c);
         HIPC(c, launch_pcg_sweep1<T>(g, vs, dinv, R, pbuf[(k + 1) & 1], pbuf[k & 1], c->ld, ncols,
-                                     k, tol, mask, s, st, Z, c->rzp, c->dp.nslab));
+                                     k, tol, mask, s, st, Z, c->rzp, c->dp.rzparts));
         prof_end(c, k1, ea);
         if (outer && k == 0) {
             HIPC(c, hipEventSynchronize(outer->ev));
@@ -594,7 +594,7 @@ qo_status solve_mixed_rel(qo_ctx *c, const double *B, double *X, int ncols, int 
             hipEvent_t ea = prof_begin(c);
             HIPC(c, launch_pcg_sweep1<float>(g, c->vs32, c->dinv32, c->r32, pbuf[(k + 1) & 1],
                                              pbuf[k & 1], c->ld, ncols, k, tol, c->mask, s, st,
-                                             c->dst ? c->z32 : nullptr, c->rzp, c->dp.nslab));
+                                             c->dst ? c->z32 : nullptr, c->rzp, c->dp.rzparts));
             prof_end(c, QO_KERNEL_SWEEP1_F32, ea);
             hipEvent_t eb = prof_begin(c);
             HIPC(c, launch_pcg_sweep2<float>(g, c->vs32, c->dinv32, pbuf[k & 1], c->d32, c->r32,
@@ -1536,7 +1536,7 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
         A(&h->t1, blk);
         A(&h->t2, blk);
         A(&h->pcs, (size_t)N);
-        A(&h->rzp, (size_t)N * dp.nslab);
+        A(&h->rzp, (size_t)N * dp.rzparts);
         A(&h->dsum, 1);
         A(&h->z32, blk);
         if (s == QO_OK) {
@@ -1897,14 +1897,13 @@ qo_status qo_precond(qo_handle h, const double *R, double *Z, long ld, int ncols
     HIPC(h, hipMemsetAsync(h->W2, 0, sizeof(double) * h->ld * ncols, st));
     HIPC(h, launch_col_scale(h->W, h->ld, h->ng, ncols, h->pcs, st));
     HIPC(h, launch_dst_fwd<double>(h->dp, h->W, h->ld, ncols, h->t1, h->pcs, st));
-    HIPC(h, launch_dst_pencil(h->dp, h->t1, h->t2, h->ld, ncols, h->pcs, st));
-    HIPC(h, launch_dst_inv<double>(h->dp, h->t2, h->W, h->z32, h->ld, ncols, h->pcs, h->rzp,
-                                   st));
+    HIPC(h, launch_dst_pencil(h->dp, h->t1, h->t2, h->ld, ncols, h->pcs, h->rzp, st));
+    HIPC(h, launch_dst_inv(h->dp, h->t2, h->z32, h->ld, ncols, h->pcs, st));
     HIPC(h, launch_z_expand(h->z32, h->pcs, h->W2, h->ld, h->ng, ncols, st));
     HIPC(h, hipMemcpy2DAsync(Z, sizeof(double) * ld, h->W2, sizeof(double) * h->ld, row, ncols,
                              hipMemcpyDeviceToDevice, st));
     if (rz) {
-        const int ns = h->dp.nslab;
+        const int ns = h->dp.rzparts;
         std::vector<double> part((size_t)ncols * ns);
         std::vector<float> sc(ncols);
         HIPC(h, hipMemcpyAsync(part.data(), h->rzp, sizeof(double) * part.size(),

@@ -236,12 +236,12 @@ qo_status group_pcg(qo_batch_ctx *b, qo_batch_ctx::Group &G, const double *B, do
         if (G.dst) {
             BHIP(b, launch_pc_prep(k, G.C, nullptr, s, G.qs, tiles, 0.0, G.ng, G.pcs, st));
             BHIP(b, launch_dst_fwd<double>(G.dp, G.r, G.ld, G.C, G.t1, G.pcs, st));
-            BHIP(b, launch_dst_pencil(G.dp, G.t1, G.t2, G.ld, G.C, G.pcs, st));
-            BHIP(b, launch_dst_inv<double>(G.dp, G.t2, G.r, G.z, G.ld, G.C, G.pcs, G.rzp, st));
+            BHIP(b, launch_dst_pencil(G.dp, G.t1, G.t2, G.ld, G.C, G.pcs, G.rzp, st));
+            BHIP(b, launch_dst_inv(G.dp, G.t2, G.z, G.ld, G.C, G.pcs, st));
         }
         BHIP(b, launch_pcg_sweep1<double>(g, G.vs, G.dinv, G.r, pbuf[(k + 1) & 1], pbuf[k & 1],
                                           G.ld, G.C, k, 0.0, nullptr, s, st,
-                                          G.dst ? G.z : nullptr, G.rzp, G.dp.nslab));
+                                          G.dst ? G.z : nullptr, G.rzp, G.dp.rzparts));
         if (k == K) break;
         BHIP(b, launch_pcg_sweep2<double>(g, G.vs, G.dinv, pbuf[k & 1], X, G.r, G.ld, G.C, k, s,
                                           st, !G.dst));
@@ -283,13 +283,12 @@ qo_status group_solve_mixed(qo_batch_ctx *b, qo_batch_ctx::Group &G, const doubl
             if (G.dst) {
                 BHIP(b, launch_pc_prep(k, G.C, G.mask, s, G.qs, tiles, 0.0, G.ng, G.pcs, st));
                 BHIP(b, launch_dst_fwd<float>(G.dp, G.rr32, G.ld, G.C, G.t1, G.pcs, st));
-                BHIP(b, launch_dst_pencil(G.dp, G.t1, G.t2, G.ld, G.C, G.pcs, st));
-                BHIP(b, launch_dst_inv<float>(G.dp, G.t2, G.rr32, G.z, G.ld, G.C, G.pcs, G.rzp,
-                                              st));
+                BHIP(b, launch_dst_pencil(G.dp, G.t1, G.t2, G.ld, G.C, G.pcs, G.rzp, st));
+                BHIP(b, launch_dst_inv(G.dp, G.t2, G.z, G.ld, G.C, G.pcs, st));
             }
             BHIP(b, launch_pcg_sweep1<float>(g, G.vs32, G.dinv32, G.rr32, pbuf[(k + 1) & 1],
                                              pbuf[k & 1], G.ld, G.C, k, 0.0, G.mask, s, st,
-                                             G.dst ? G.z : nullptr, G.rzp, G.dp.nslab));
+                                             G.dst ? G.z : nullptr, G.rzp, G.dp.rzparts));
             if (k == K) break;
             BHIP(b, launch_pcg_sweep2<float>(g, G.vs32, G.dinv32, pbuf[k & 1], G.d32, G.rr32,
                                              G.ld, G.C, k, s, st, !G.dst));
@@ -453,7 +452,7 @@ qo_status build_group(qo_batch_ctx *b, qo_batch_ctx::Group &G) {
         BQO(A(&G.pcs, (size_t)G.C));
         BQO(A(&G.cvbar, (size_t)G.C));
         BQO(A(&G.clmin, (size_t)G.C));
-        BQO(A(&G.rzp, (size_t)G.C * dp.nslab));
+        BQO(A(&G.rzp, (size_t)G.C * dp.rzparts));
         dp.Sx = G.dS;
         dp.Sy = G.dS + sx;
         dp.Ss = G.dS + sx + sy;

@@ -24,12 +24,18 @@
 // Three passes per application, each streaming the block once:
 //   plane   (forward)  r (T) -> t1 (FP16): transform along x (and y in 3-D)
 //   pencil             t1 -> t2 (FP16):    along the slowest axis, scale by
-//                                          lambda_min/lambda, transform back
-//   plane   (inverse)  t2 -> z (FP32):     along x (and y), unscale; partial sums
-//                                          of r.z for the PCG step.  z is FP32 in
+//                                          lambda_min/lambda, transform back; partial
+//                                          sums of r.z = sum rhat^2 / lambda over the
+//                                          spectral coefficients (Parseval: the
+//                                          transforms are orthonormal)
+//   plane   (inverse)  t2 -> z (FP32):     along x (and y), unscale.  z is FP32 in
 //                                          the FP64 PCG too: its values carry FP32
 //                                          precision (FP32 accumulation of FP16
 //                                          transforms), so nothing is lost.
+// r.z from the spectral coefficients differs from the product with the stored z only by
+// the FP16 roundings of the transforms (about 1e-3 relative); PCG needs no more than a
+// fixed, nearly symmetric preconditioner and a consistent step, and the iteration counts
+// match those of the product with z.  The inverse pass then never reads r.
 // "Plane" is one z-plane in 3-D and a batch of rows in 2-D; the slowest axis
 // is z in 3-D and y in 2-D.
 #include "qo_internal.h"
@@ -79,6 +85,25 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += red[w];
     return s;
+}
+
+// Sum of v over the 64 lanes of a wavefront, complete in lane 63, by DPP moves (no LDS
+// traffic, no address registers): pairs and quads by quad permutations, rows of 16 by
+// row shifts, then the row sums carried up by the row broadcasts of 15 and 31.  A lane
+// a move has no source for adds 0.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 CTRL, ROWS, 0xf, false));
+}
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+    v += dpp_move<0xb1>(v);          // quad_perm [1,0,3,2]
+    v += dpp_move<0x4e>(v);          // quad_perm [2,3,0,1]
+    v += dpp_move<0x114>(v);         // row_shr:4
+    v += dpp_move<0x118>(v);         // row_shr:8
+    v += dpp_move<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    return v;
 }
 
 __device__ __forceinline__ v8h lds8(const _Float16 *p) {
@@ -181,8 +206,7 @@ __host__ __device__ inline size_t dst_plane_xt_bytes(const DstPlan &p) {
 // padded x-points in LDS (FP16).  Wave w owns output rows [16w, 16w + 16).
 //   GEMM1  T = X S_x     (A = X rows from LDS, B = rows of S_x: S symmetric)
 //   GEMM2  Y = S_y T     (3-D only; T staged transposed in LDS)
-// Forward: X = sc * r, output FP16.  Inverse: X = t2, output z = Y / (sc lmin) in FP32,
-// plus the slab's partial sum of r.z (z taken in T).
+// Forward: X = sc * r, output FP16.  Inverse: X = t2, output z = Y / (sc lmin) in FP32.
 // VEC: rows are whole 16-byte groups (nx % 8 == 0): vector loads and stores throughout.
 // FP32 3-D planes (NT <= 8) are held to 80 registers: 6 waves per SIMD, four 6-wave
 // workgroups per CU, as many as their LDS allows.
@@ -192,10 +216,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
                                                    const _Float16 *__restrict__ Hin,
                                                    _Float16 *__restrict__ Hout,
                                                    float *__restrict__ Z, long ld,
-                                                   const float *__restrict__ pcs,
-                                                   double *__restrict__ rzp) {
+                                                   const float *__restrict__ pcs) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kMaxWaves];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int col = L / p.nslab;
     const int slab = L - col * p.nslab;
@@ -426,57 +448,24 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
             for (int v = 0; v < 4; ++v)
                 SF[(16 * w + 4 * lg + v) * FP + 16 * j + lr] = acc[j][v] * unscale;
         __syncthreads();
-        double rz = 0.0;
         const int g4 = NXP / 4;
-        if constexpr (VEC) {
-            // each thread owns at most NT groups of 4 (rows * NXP / 4 <= NT * nthr): their
-            // r loads are issued together (clamped into the slab), then z is stored and
-            // r.z accumulated
-            T rr[QF][4];
-#pragma unroll
-            for (int q = 0; q < QF; ++q) {
-                const int it = tid + q * nthr;
-                const int r = it / g4, x = (it - r * g4) * 4;
-                const bool ok = r < rows && x < nx;
-                const long i0 = ok ? base + (long)r * nx + x : base;
-                if constexpr (sizeof(T) == 4) {
-                    const float4 v = *reinterpret_cast<const float4 *>(R + i0);
-                    rr[q][0] = v.x; rr[q][1] = v.y; rr[q][2] = v.z; rr[q][3] = v.w;
-                } else {
-                    const double2 v0 = *reinterpret_cast<const double2 *>(R + i0);
-                    const double2 v1 = *reinterpret_cast<const double2 *>(R + i0 + 2);
-                    rr[q][0] = v0.x; rr[q][1] = v0.y; rr[q][2] = v1.x; rr[q][3] = v1.y;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < QF; ++q) {
-                const int it = tid + q * nthr;
-                const int r = it / g4, x = (it - r * g4) * 4;
-                if (r >= rows || x >= nx) continue;
-                const long i0 = base + (long)r * nx + x;
-                const float4 z4 = *reinterpret_cast<const float4 *>(SF + r * FP + x);
+        for (int it = tid; it < rows * g4; it += nthr) {
+            const int r = it / g4;
+            const int x = (it - r * g4) * 4;
+            if (x >= nx) continue;
+            const long i0 = base + (long)r * nx + x;
+            const float *src = SF + r * FP + x;
+            if constexpr (VEC) {
+                const float4 z4 = *reinterpret_cast<const float4 *>(src);
                 st_out(reinterpret_cast<v4f *>(Z + i0), v4f{z4.x, z4.y, z4.z, z4.w});
-                rz += (double)rr[q][0] * (double)(T)z4.x + (double)rr[q][1] * (double)(T)z4.y +
-                      (double)rr[q][2] * (double)(T)z4.z + (double)rr[q][3] * (double)(T)z4.w;
-            }
-        } else {
-            for (int it = tid; it < rows * g4; it += nthr) {
-                const int r = it / g4;
-                const int x = (it - r * g4) * 4;
-                if (x >= nx) continue;
-                const long i0 = base + (long)r * nx + x;
-                const float *src = SF + r * FP + x;
+            } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     if (x + i >= nx) break;
-                    const float zv = src[i];
-                    Z[i0 + i] = zv;
-                    rz += (double)R[i0 + i] * (double)(T)zv;
+                    Z[i0 + i] = src[i];
                 }
             }
         }
-        rz = block_sum(rz, red);
-        if (tid == 0) rzp[(long)col * p.nslab + slab] = rz;
     }
 }
 
@@ -490,6 +479,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
 //   GEMM1  Yh = S_s X   (X staged m-major: slice index contiguous per position)
 //   scale  Yh[s][m] *= lmin / (kappa (mu_f(m) + mu_s(s)) + vbar)
 //   GEMM2  Z  = S_s Yh
+// With A = S_s X = sc rhat and Yh its scaled FP16 copy, r.z = sum A Yh / (sc^2 lmin)
+// = sum X Z / (sc^2 lmin) (S_s is symmetric), Z = S_s Yh the second product: every wave
+// adds up its share of a job (FP32) as it replaces X by Z in LDS and writes it to
+// rzp[job * NSP / 16 + wave], job = column * npen + position block, so a column's
+// partials are reduced in a fixed order by the PCG sweep.
 // Thread t moves slices 2 (t >> 3), 2 (t >> 3) + 1 of positions 8 (t & 7) .. + 7: two
 // 16-byte row accesses (eight lanes cover a 128-byte row segment), transposed in
 // registers into 4-byte LDS words.  The next job's rows are loaded during the current
@@ -505,7 +499,8 @@ __device__ __forceinline__ int pen_off(int m, int s, int SP) {
 template <int KS>
 __global__ __launch_bounds__(128 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 3 ? 6 : 4))) void k_dst_pencil(DstPlan p, const _Float16 *__restrict__ Hin,
                                                     _Float16 *__restrict__ Hout, long ld,
-                                                    int ncols, const float *__restrict__ pcs) {
+                                                    int ncols, const float *__restrict__ pcs,
+                                                    double *__restrict__ rzp) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NJ = kPenMB / 16;
     constexpr int NSP = 32 * KS, SP = NSP + 8;
@@ -516,14 +511,18 @@ __global__ __launch_bounds__(128 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 
     // each wait out a cache round trip)
     float *MUX = reinterpret_cast<float *>(YT + kPenMB * SP);
     float *MUY = MUX + 256;
-    // which columns this PCG iteration preconditions, so that finding the next job needs
-    // no global load
-    unsigned char *ACT = reinterpret_cast<unsigned char *>(MUY + 256);
+    // per column: the forward scale sc (0: the column is skipped in this PCG iteration),
+    // vbar and lmin, so that finding the next job and its constants needs no global load
+    float *CSC = MUY + 256, *CVB = CSC + ncols, *CLM = CVB + ncols;
     const int tid = threadIdx.x;
     for (int i = tid; i < p.nx; i += blockDim.x) MUX[i] = p.mux[i];
     if (p.dim == 3)
         for (int i = tid; i < p.ny; i += blockDim.x) MUY[i] = p.muy[i];
-    for (int i = tid; i < ncols; i += blockDim.x) ACT[i] = pcs[i] != 0.f;
+    for (int i = tid; i < ncols; i += blockDim.x) {
+        CSC[i] = pcs[i];
+        CVB[i] = p.cvbar ? p.cvbar[i] : p.vbar;
+        CLM[i] = p.clmin ? p.clmin[i] : p.lmin;
+    }
     __syncthreads();
     const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
     const int mg = tid & 7, s0 = 2 * (tid >> 3);  // this thread's transfer item
@@ -540,7 +539,7 @@ __global__ __launch_bounds__(128 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 
     // neighbouring positions of the same slices (DRAM pages stay open); columns the PCG
     // skips are passed over.
     auto next_active = [&](long job) {
-        while (job < njobs && !ACT[job / p.npen]) job += gridDim.x;
+        while (job < njobs && CSC[job / p.npen] == 0.f) job += gridDim.x;
         return job;
     };
     // rows s0, s0 + 1 at positions m .. m + 7 of a job; clamped unconditional loads in the
@@ -579,29 +578,22 @@ __global__ __launch_bounds__(128 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 
     long job = next_active(blockIdx.x);
     if (job >= njobs) return;
     load(job);
-    float vb_next, lm_next;
-    {
-        const int c = (int)(job / p.npen);
-        vb_next = p.cvbar ? p.cvbar[c] : p.vbar;
-        lm_next = p.clmin ? p.clmin[c] : p.lmin;
-    }
+    const int nw = blockDim.x >> 6;
     while (true) {
         // the next job is found before the barrier, so the prefetch after it need not
         // wait for the activity flag
         const long nxt = next_active(job + gridDim.x);
         const int col = (int)(job / p.npen);
         const int m0 = (int)(job - (long)col * p.npen) * kPenMB;
-        // per-column constants, read one job ahead (with the prefetch) and moved into
-        // scalar registers, so that no later use waits on the vector memory counter
-        const float vbar = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                         __builtin_bit_cast(int, vb_next)));
-        const float lmin = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                         __builtin_bit_cast(int, lm_next)));
-        if (nxt < njobs) {
-            const int cn = (int)(nxt / p.npen);
-            vb_next = p.cvbar ? p.cvbar[cn] : p.vbar;
-            lm_next = p.clmin ? p.clmin[cn] : p.lmin;
-        }
+        // per-column constants from LDS into scalar registers (an LDS read does not wait
+        // for the prefetch on the vector memory counter)
+        auto sreg = [](float v) {
+            return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                 __builtin_bit_cast(int, v)));
+        };
+        const float vbar = sreg(CVB[col]);
+        const float lmin = sreg(CLM[col]);
+        const float scj = sreg(CSC[col]);
         float muf[NJ];  // in-plane eigenvalue sums of this thread's positions (from LDS)
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
@@ -663,13 +655,25 @@ __global__ __launch_bounds__(128 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 
                 const v8h b = lds8(YT + pen_off(16 * j + lr, 32 * ks + 8 * lg, SP));
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[ks], b, acc[j], 0, 0, 0);
             }
-        // Z m-major into XT (every wave finished GEMM1 before the barrier above)
+        // Z m-major into XT (every wave finished GEMM1 before the barrier above), each
+        // element after its product with the X it replaces: this lane's share of r.z
+        float rzl = 0.f;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
+            typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+            _Float16 *q = XT + pen_off(16 * j + lr, 16 * w + 4 * lg, SP);
+            const v4h x = *reinterpret_cast<const v4h *>(q);
             v4h h;
 #pragma unroll
             for (int v = 0; v < 4; ++v) h[v] = (_Float16)acc[j][v];
-            *reinterpret_cast<v4h *>(XT + pen_off(16 * j + lr, 16 * w + 4 * lg, SP)) = h;
+            // products of FP16 pairs summed in FP32 (v_dot2_f32_f16)
+            rzl = __builtin_amdgcn_fdot2(v2h{x[0], x[1]}, v2h{h[0], h[1]}, rzl, false);
+            rzl = __builtin_amdgcn_fdot2(v2h{x[2], x[3]}, v2h{h[2], h[3]}, rzl, false);
+            *reinterpret_cast<v4h *>(q) = h;
+        }
+        {
+            rzl = wave_sum_lane63(rzl);
+            if (lane == 63) rzp[job * nw + w] = (double)(rzl / (scj * scj * lmin));
         }
         __syncthreads();
         {
@@ -744,6 +748,7 @@ void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz) {
         p.nslab = (ny + 63) / 64;
     }
     p.npen = (p.nf + kPenMB - 1) / kPenMB;
+    p.rzparts = p.npen * (p.NSP / 16);
 }
 
 // X (RP x (NXP+8) halves) and, in 3-D, TT (NXP x (NYP+8) halves), then the S_x copy; the
@@ -756,9 +761,9 @@ size_t dst_plane_lds(const DstPlan &p, bool inv) {
 }
 
 // XT and YT (64 x (NSP + 8) halves each), the x and y eigenvalues (2 x 256 floats), then
-// one activity byte per column
+// three floats per column (sc, vbar, lmin)
 static size_t dst_pencil_lds(const DstPlan &p, int ncols) {
-    return 2 * (size_t)kPenMB * (p.NSP + 8) * 2 + 2 * 256 * 4 + (size_t)ncols;
+    return 2 * (size_t)kPenMB * (p.NSP + 8) * 2 + 2 * 256 * 4 + 3 * sizeof(float) * (size_t)ncols;
 }
 
 hipError_t launch_dst_matrix(int n, int NP, _Float16 *S, hipStream_t st) {
@@ -807,11 +812,11 @@ hipError_t launch_dst_fwd(const DstPlan &p, const T *R, long ld, int ncols, _Flo
     if (p.nx % 8 == 0) {
         QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, false, NT, true>), grid,
                                                       block, dst_plane_lds(p, false), st, p, R,
-                                                      nullptr, t1, nullptr, ld, pcs, nullptr));
+                                                      nullptr, t1, nullptr, ld, pcs));
     } else {
         QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, false, NT, false>), grid,
                                                       block, dst_plane_lds(p, false), st, p, R,
-                                                      nullptr, t1, nullptr, ld, pcs, nullptr));
+                                                      nullptr, t1, nullptr, ld, pcs));
     }
     return hipGetLastError();
 }
@@ -820,7 +825,7 @@ hipError_t launch_dst_fwd(const DstPlan &p, const T *R, long ld, int ncols, _Flo
 // this kernel and LDS size, times the CUs), cached per instantiation.
 template <int KS>
 static hipError_t launch_pencil_ks(const DstPlan &p, const _Float16 *t1, _Float16 *t2, long ld,
-                                   int ncols, const float *pcs, hipStream_t st) {
+                                   int ncols, const float *pcs, double *rzp, hipStream_t st) {
     static int resident[2] = {0, 0};  // {dynamic LDS bytes it was taken for, workgroups}
     const size_t lds = dst_pencil_lds(p, ncols);
     const int block = 128 * KS;
@@ -837,39 +842,38 @@ static hipError_t launch_pencil_ks(const DstPlan &p, const _Float16 *t1, _Float1
     const long njobs = (long)ncols * p.npen;
     const unsigned grid = (unsigned)std::min<long>(njobs, resident[1]);
     hipLaunchKernelGGL((k_dst_pencil<KS>), dim3(grid), dim3(block), lds, st, p, t1, t2, ld, ncols,
-                       pcs);
+                       pcs, rzp);
     return hipGetLastError();
 }
 
 hipError_t launch_dst_pencil(const DstPlan &p, const _Float16 *t1, _Float16 *t2, long ld,
-                             int ncols, const float *pcs, hipStream_t st) {
+                             int ncols, const float *pcs, double *rzp, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
     switch (p.NSP / 32) {
-        case 1: return launch_pencil_ks<1>(p, t1, t2, ld, ncols, pcs, st);
-        case 2: return launch_pencil_ks<2>(p, t1, t2, ld, ncols, pcs, st);
-        case 3: return launch_pencil_ks<3>(p, t1, t2, ld, ncols, pcs, st);
-        case 4: return launch_pencil_ks<4>(p, t1, t2, ld, ncols, pcs, st);
-        case 5: return launch_pencil_ks<5>(p, t1, t2, ld, ncols, pcs, st);
-        case 6: return launch_pencil_ks<6>(p, t1, t2, ld, ncols, pcs, st);
-        case 7: return launch_pencil_ks<7>(p, t1, t2, ld, ncols, pcs, st);
-        case 8: return launch_pencil_ks<8>(p, t1, t2, ld, ncols, pcs, st);
+        case 1: return launch_pencil_ks<1>(p, t1, t2, ld, ncols, pcs, rzp, st);
+        case 2: return launch_pencil_ks<2>(p, t1, t2, ld, ncols, pcs, rzp, st);
+        case 3: return launch_pencil_ks<3>(p, t1, t2, ld, ncols, pcs, rzp, st);
+        case 4: return launch_pencil_ks<4>(p, t1, t2, ld, ncols, pcs, rzp, st);
+        case 5: return launch_pencil_ks<5>(p, t1, t2, ld, ncols, pcs, rzp, st);
+        case 6: return launch_pencil_ks<6>(p, t1, t2, ld, ncols, pcs, rzp, st);
+        case 7: return launch_pencil_ks<7>(p, t1, t2, ld, ncols, pcs, rzp, st);
+        case 8: return launch_pencil_ks<8>(p, t1, t2, ld, ncols, pcs, rzp, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T>
-hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, const T *R, float *Z, long ld,
-                          int ncols, const float *pcs, double *rzp, hipStream_t st) {
+hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, float *Z, long ld, int ncols,
+                          const float *pcs, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
     const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
     if (p.nx % 8 == 0) {
-        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, true, NT, true>), grid,
-                                                      block, dst_plane_lds(p, true), st, p, R, t2,
-                                                      nullptr, Z, ld, pcs, rzp));
+        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<float, true, NT, true>), grid,
+                                                      block, dst_plane_lds(p, true), st, p,
+                                                      nullptr, t2, nullptr, Z, ld, pcs));
     } else {
-        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, true, NT, false>), grid,
-                                                      block, dst_plane_lds(p, true), st, p, R, t2,
-                                                      nullptr, Z, ld, pcs, rzp));
+        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<float, true, NT, false>),
+                                                      grid, block, dst_plane_lds(p, true), st, p,
+                                                      nullptr, t2, nullptr, Z, ld, pcs));
     }
     return hipGetLastError();
 }
@@ -900,11 +904,5 @@ template hipError_t launch_dst_fwd<double>(const DstPlan &, const double *, long
                                            _Float16 *, const float *, hipStream_t);
 template hipError_t launch_dst_fwd<float>(const DstPlan &, const float *, long, int, _Float16 *,
                                           const float *, hipStream_t);
-template hipError_t launch_dst_inv<double>(const DstPlan &, const _Float16 *, const double *,
-                                           float *, long, int, const float *, double *,
-                                           hipStream_t);
-template hipError_t launch_dst_inv<float>(const DstPlan &, const _Float16 *, const float *,
-                                          float *, long, int, const float *, double *,
-                                          hipStream_t);
 
 }  // namespace qo

@@ -59,6 +59,7 @@ struct DstPlan {
     int NXP, NYP, NSP;   // lengths padded to multiples of 32
     int RP, rows;        // padded / real grid rows per slab
     int nslab, npen;     // plane and pencil workgroups per column
+    int rzparts;         // partial sums of r.z per column: npen pencil jobs x NSP / 16 waves
     const _Float16 *Sx, *Sy, *Ss;   // DST-I matrices, FP16, row-major, padded with zeros
     const float *mux, *muy, *mus;   // eigenvalues of the 1-D -Lap_h along x, y, slowest axis
     float kap, vbar, lmin;          // lambda = kap (mu_x + mu_y + mu_z) + vbar; lmin its minimum
@@ -76,18 +77,18 @@ hipError_t launch_col_scale(const double *R, long ld, long ng, int ncols, float 
 // pcs[c] = sqrt(Ng / ||r_c||^2) for the columns the PCG iteration k updates, else 0
 hipError_t launch_pc_prep(int k, int ncols, const int *mask, PcgState s, long qs, int tiles,
                           double tol, long ng, float *pcs, hipStream_t st);
-// z = M^{-1} r in three passes: forward plane (r -> t1), pencil (t1 -> t2),
-// inverse plane (t2 -> z, partials rzp[c * nslab + slab] of r.z).
+// z = M^{-1} r in three passes: forward plane (r -> t1), pencil (t1 -> t2, and the
+// partials rzp[c * rzparts + i] of r.z, summed in the spectral domain), inverse plane
+// (t2 -> z).
 template <typename T>
 hipError_t launch_dst_fwd(const DstPlan &p, const T *R, long ld, int ncols, _Float16 *t1,
                           const float *pcs, hipStream_t st);
 hipError_t launch_dst_pencil(const DstPlan &p, const _Float16 *t1, _Float16 *t2, long ld,
-                             int ncols, const float *pcs, hipStream_t st);
+                             int ncols, const float *pcs, double *rzp, hipStream_t st);
 // z is FP32 in either precision (its values carry FP32 precision); launch_z_expand gives
 // an FP64 copy.
-template <typename T>
-hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, const T *R, float *Z, long ld,
-                          int ncols, const float *pcs, double *rzp, hipStream_t st);
+hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, float *Z, long ld, int ncols,
+                          const float *pcs, hipStream_t st);
 // Z (FP64) = Z32 for the columns with pcs[c] != 0, zero elsewhere.
 hipError_t launch_z_expand(const float *Z32, const float *pcs, double *Z, long ld, long ng,
                            int ncols, hipStream_t st);

@@ -38,16 +38,21 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per (grid point x column) of one launch; s = bytes per value of the
 # PCG (8 in FP64, 4 in the mixed path's FP32 iteration); FP16 intermediates are 2 bytes
 #   two-sweep form  sweep1: read r, p_old; write p (Jacobi)   -> 3 s
-#                           read z (FP32), p_old; write p       -> 2 s + 4 (fast-Poisson)
+#                           read z (FP32), p_old; write p       -> 2 s + 4 (fast-Poisson,
+#                                                                  FP64)
+#                           read p (formed by dst_inv)          -> 4 (fast-Poisson, FP32)
 #                   sweep2: read p, x, r;  write x, r         -> 5 s
 #   one-sweep form  cg:     read r, p_old, x; write r, p, x   -> 6 s
 #   fast-Poisson    dst_fwd: read r; write t1 (FP16)          -> s + 2
 #                   dst_pencil: read t1, write t2 (FP16)      -> 4
-#                   dst_inv: read t2 (FP16); write z (FP32)    -> 6
+#                   dst_inv: read t2 (FP16); write z (FP32)    -> 6 (FP64 PCG)
+#                            read t2, p_old; write p (FP32)    -> 10 (FP32 PCG; the first
+#                                                          iteration, without p_old, counts
+#                                                          0.6 of a column-iteration)
 BYTES_PER_COLPT = {"sweep1_f64": 24, "sweep2_f64": 40, "sweep1_f32": 12, "sweep2_f32": 20,
                    "cg_f64": 48, "cg_f32": 24}
 DST_BYTES = {"dst_fwd": lambda s: s + 2, "dst_pencil": lambda s: 4,
-             "dst_inv": lambda s: 6}
+             "dst_inv": lambda s: 10 if s == 4 else 6}
 KERNEL_SYMBOL = {"sweep1_f64": "k_pcg_sweep1<double>", "sweep2_f64": "k_pcg_sweep2<double>",
                  "sweep1_f32": "k_pcg_sweep1<float>", "sweep2_f32": "k_pcg_sweep2<float>",
                  "cg_f64": "k_cg_step<double>", "cg_f32": "k_cg_step<float>",
@@ -188,9 +193,9 @@ def bytes_per_colpt(prof, value_bytes):
     dst = prof.get("dst_inv", {}).get("launches", 0) > 0
     for k, f in DST_BYTES.items():
         out[k] = f(value_bytes)
-    if dst:  # the first sweep reads the FP32 preconditioned residual instead of r
+    if dst:  # the first sweep reads z (FP64 PCG) or only the finished p (FP32 PCG)
         out["sweep1_f64"] = 2 * 8 + 4
-        out["sweep1_f32"] = 2 * 4 + 4
+        out["sweep1_f32"] = 4
     return {k: v for k, v in out.items() if k in prof}
 
 

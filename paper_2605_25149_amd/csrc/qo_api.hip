@@ -89,6 +89,7 @@ struct qo_ctx {
     _Float16 *dS = nullptr, *t1 = nullptr, *t2 = nullptr;
     float *dmu = nullptr, *pcs = nullptr;
     float *z32 = nullptr;  // preconditioned residual z = M^{-1} r (FP32 in either precision)
+    float *pbeta = nullptr;  // beta of the FP32 PCG, formed before the inverse plane pass
     double *rzp = nullptr, *dsum = nullptr;
     double mu0 = 0.0;  // mu_x[0] + mu_y[0] (+ mu_z[0]): smallest eigenvalue of -Lap_h
     // block CG (pcg_variant 2): Z and ping-pong partners of X, R, P; small matrices;
@@ -329,7 +330,9 @@ int *stat_slot(qo_ctx *c) { return round_slot(c) + 8; }
 int *its_slot(qo_ctx *c, int round) { return round_slot(c) + 16 + (long)round * c->N; }
 
 // Kernel-time work counters of one PCG solve from its per-column iteration counts.
-void pcg_account(qo_ctx *c, bool f64, const int *its, int ncols, bool zero_start_dst, bool dst) {
+// pform: the FP32 form whose inverse pass reads P_old except at k = 0 (0.6 of its bytes).
+void pcg_account(qo_ctx *c, bool f64, const int *its, int ncols, bool zero_start_dst, bool dst,
+                 bool pform = false) {
     if (!c->prof) return;
     double colits = 0.0;
     int started = 0;  // columns whose first second sweep ran (x = 0 then: 4 of 5 arrays)
@@ -344,6 +347,7 @@ void pcg_account(qo_ctx *c, bool f64, const int *its, int ncols, bool zero_start
     if (dst)
         for (int kid : {(int)QO_KERNEL_DST_FWD, (int)QO_KERNEL_DST_PENCIL, (int)QO_KERNEL_DST_INV})
             c->pdata.work[kid] += colits;
+    if (pform) c->pdata.work[QO_KERNEL_DST_INV] -= 0.4 * started;
 }
 
 qo_status check_poll_err(qo_ctx *c, int code, int col, const char *what) {
@@ -382,6 +386,28 @@ struct RoundPoll {
     hipEvent_t ev;
     const int *h;
 };
+
+// The FP32 form: the same passes, with beta of the PCG step taken from the pencil's r.z
+// partials before the inverse plane pass, which then writes the search direction
+// P = z + beta P_old (P = z at k = 0) instead of z; the first sweep only reads P.
+qo_status precondition_p(qo_ctx *c, const float *R, const float *Pold, float *Pnew, int ncols,
+                         int k, double tol, const int *mask, const PcgState &s) {
+    hipStream_t st = c->st;
+    const long qs = (long)ncols * c->g.tiles();
+    HIPC(c, launch_pc_prep(k, ncols, mask, s, qs, c->g.tiles(), tol, c->ng, c->pcs, st));
+    hipEvent_t e0 = prof_begin(c);
+    HIPC(c, launch_dst_fwd<float>(c->dp, R, c->ld, ncols, c->t1, c->pcs, st));
+    prof_end(c, QO_KERNEL_DST_FWD, e0);
+    hipEvent_t e1 = prof_begin(c);
+    HIPC(c, launch_dst_pencil(c->dp, c->t1, c->t2, c->ld, ncols, c->pcs, c->rzp, st));
+    prof_end(c, QO_KERNEL_DST_PENCIL, e1);
+    HIPC(c, launch_rho_beta(k, ncols, c->pcs, c->rzp, c->dp.rzparts, s, c->pbeta, st));
+    hipEvent_t e2 = prof_begin(c);
+    HIPC(c, launch_dst_inv_p(c->dp, c->t2, k == 0 ? nullptr : Pold, c->pbeta, Pnew, c->ld, ncols,
+                             c->pcs, st));
+    prof_end(c, QO_KERNEL_DST_INV, e2);
+    return QO_OK;
+}
 
 // PCG on all columns of B (ld c->ld) into X, precision T: Jacobi, or the
 // fast-Poisson preconditioner when c->dst.
@@ -425,6 +451,7 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
     const int k1 = f64 ? QO_KERNEL_SWEEP1_F64 : QO_KERNEL_SWEEP1_F32;
     const int k2 = f64 ? QO_KERNEL_SWEEP2_F64 : QO_KERNEL_SWEEP2_F32;
     float *Z = c->dst ? c->z32 : nullptr;
+    const bool pform = !f64 && Z != nullptr;  // FP32 fast-Poisson: P formed by the inverse pass
     // activity flags and error code of iteration k into the slot of its parity
     auto post_poll = [&](int k) -> qo_status {
         int *h = poll_slot(c, k & 1);
@@ -447,10 +474,15 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
     };
     int pend = -1;  // the iteration whose flags are in flight
     for (int k = 0;; ++k) {
-        if (Z) QOC(precondition<T>(c, R, Z, ncols, k, tol, mask, s));
+        if (pform)
+            QOC(precondition_p(c, reinterpret_cast<const float *>(R),
+                               reinterpret_cast<const float *>(pbuf[(k + 1) & 1]),
+                               reinterpret_cast<float *>(pbuf[k & 1]), ncols, k, tol, mask, s));
+        else if (Z)
+            QOC(precondition<T>(c, R, Z, ncols, k, tol, mask, s));
         hipEvent_t ea = prof_begin(c);
         HIPC(c, launch_pcg_sweep1<T>(g, vs, dinv, R, pbuf[(k + 1) & 1], pbuf[k & 1], c->ld, ncols,
-                                     k, tol, mask, s, st, Z, c->rzp, c->dp.rzparts));
+                                     k, tol, mask, s, st, Z, c->rzp, c->dp.rzparts, pform));
         prof_end(c, k1, ea);
         if (outer && k == 0) {
             HIPC(c, hipEventSynchronize(outer->ev));
@@ -491,7 +523,7 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
     HIPC(c, hipStreamSynchronize(st));
     prof_harvest(c);
     for (int j = 0; j < ncols; ++j) its_out[j] = h[j];
-    pcg_account(c, f64, its_out, ncols, skip_init && Z, Z != nullptr);
+    pcg_account(c, f64, its_out, ncols, skip_init && Z, Z != nullptr, pform);
     return QO_OK;
 }
 
@@ -993,7 +1025,7 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
         for (int r = 0; r < done_rounds; ++r) {
             const int *h = its_slot(c, r);
             for (int j = 0; j < ncols; ++j) its[j] += h[j];
-            pcg_account(c, false, h, ncols, true, true);
+            pcg_account(c, false, h, ncols, true, true, true);
         }
     }
     return QO_OK;
@@ -1539,6 +1571,7 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
         A(&h->rzp, (size_t)N * dp.rzparts);
         A(&h->dsum, 1);
         A(&h->z32, blk);
+        A(&h->pbeta, (size_t)N);
         if (s == QO_OK) {
             dp.Sx = h->dS;
             dp.Sy = h->dS + sx;

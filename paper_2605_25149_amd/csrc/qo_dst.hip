@@ -210,13 +210,17 @@ __host__ __device__ inline size_t dst_plane_xt_bytes(const DstPlan &p) {
 // VEC: rows are whole 16-byte groups (nx % 8 == 0): vector loads and stores throughout.
 // FP32 3-D planes (NT <= 8) are held to 80 registers: 6 waves per SIMD, four 6-wave
 // workgroups per CU, as many as their LDS allows.
-template <typename T, bool INV, int NT, bool VEC>
+// PF (inverse only): store the search direction P = z + beta[c] P_old (P = z when Pold is
+// null) instead of z.
+template <typename T, bool INV, int NT, bool VEC, bool PF = false>
 __global__ __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_dst_plane(DstPlan p, const T *__restrict__ R,
                                                    const _Float16 *__restrict__ Hin,
                                                    _Float16 *__restrict__ Hout,
                                                    float *__restrict__ Z, long ld,
-                                                   const float *__restrict__ pcs) {
+                                                   const float *__restrict__ pcs,
+                                                   const float *__restrict__ Pold = nullptr,
+                                                   const float *__restrict__ beta = nullptr) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int col = L / p.nslab;
@@ -449,20 +453,51 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
                 SF[(16 * w + 4 * lg + v) * FP + 16 * j + lr] = acc[j][v] * unscale;
         __syncthreads();
         const int g4 = NXP / 4;
-        for (int it = tid; it < rows * g4; it += nthr) {
-            const int r = it / g4;
-            const int x = (it - r * g4) * 4;
-            if (x >= nx) continue;
-            const long i0 = base + (long)r * nx + x;
-            const float *src = SF + r * FP + x;
-            if constexpr (VEC) {
-                const float4 z4 = *reinterpret_cast<const float4 *>(src);
-                st_out(reinterpret_cast<v4f *>(Z + i0), v4f{z4.x, z4.y, z4.z, z4.w});
-            } else {
+        if constexpr (PF && VEC) {
+            // each thread owns at most NT groups of 4 (rows * NXP / 4 <= NT * nthr): the
+            // P_old loads are issued together (clamped into the slab), then P is stored
+            const bool first = Pold == nullptr;
+            const float b = first ? 0.f : beta[col];
+            float4 po[QF];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if (x + i >= nx) break;
-                    Z[i0 + i] = src[i];
+            for (int q = 0; q < QF; ++q) {
+                const int it = tid + q * nthr;
+                const int r = it / g4, x = (it - r * g4) * 4;
+                const bool ok = r < rows && x < nx;
+                const long i0 = ok ? base + (long)r * nx + x : base;
+                po[q] = first ? float4{0.f, 0.f, 0.f, 0.f}
+                              : *reinterpret_cast<const float4 *>(Pold + i0);
+            }
+#pragma unroll
+            for (int q = 0; q < QF; ++q) {
+                const int it = tid + q * nthr;
+                const int r = it / g4, x = (it - r * g4) * 4;
+                if (r >= rows || x >= nx) continue;
+                const long i0 = base + (long)r * nx + x;
+                const float4 z4 = *reinterpret_cast<const float4 *>(SF + r * FP + x);
+                const v4f pv = first ? v4f{z4.x, z4.y, z4.z, z4.w}
+                                     : v4f{z4.x + b * po[q].x, z4.y + b * po[q].y,
+                                           z4.z + b * po[q].z, z4.w + b * po[q].w};
+                st_out(reinterpret_cast<v4f *>(Z + i0), pv);
+            }
+        } else {
+            const bool first = !PF || Pold == nullptr;
+            const float b = first ? 0.f : beta[col];
+            for (int it = tid; it < rows * g4; it += nthr) {
+                const int r = it / g4;
+                const int x = (it - r * g4) * 4;
+                if (x >= nx) continue;
+                const long i0 = base + (long)r * nx + x;
+                const float *src = SF + r * FP + x;
+                if constexpr (VEC) {
+                    const float4 z4 = *reinterpret_cast<const float4 *>(src);
+                    st_out(reinterpret_cast<v4f *>(Z + i0), v4f{z4.x, z4.y, z4.z, z4.w});
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (x + i >= nx) break;
+                        Z[i0 + i] = first ? src[i] : src[i] + b * Pold[i0 + i];
+                    }
                 }
             }
         }
@@ -879,6 +914,20 @@ hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, float *Z, long l
 }
 
 namespace {
+// beta[c] = rho_k / rho_{k-1} (rho_k = r.z from the pencil's partials, summed by the same
+// block reduction as the first PCG sweep's), 0 at k = 0; columns with pcs[c] == 0 skipped.
+__global__ __launch_bounds__(kThreads) void k_rho_beta(int k, int ncols,
+                                                       const float *__restrict__ pcs,
+                                                       const double *__restrict__ rzp, int rzt,
+                                                       PcgState s, float *__restrict__ beta) {
+    __shared__ dev::Red red;
+    const int col = blockIdx.x;
+    if (pcs[col] == 0.f) return;
+    const double rz = dev::col_sum(rzp, col, rzt, red);
+    if (threadIdx.x == 0)
+        beta[col] = k == 0 ? 0.f : (float)(rz / s.rho[((k & 1) ^ 1) * ncols + col]);
+}
+
 // Z (FP64) = Z32 for columns with pcs[c] != 0, else 0.
 __global__ void k_z_expand(const float *__restrict__ Z32, const float *__restrict__ pcs,
                            double *__restrict__ Z, long ld, long ng) {
@@ -889,6 +938,33 @@ __global__ void k_z_expand(const float *__restrict__ Z32, const float *__restric
         Z[(long)c * ld + i] = on ? (double)Z32[(long)c * ld + i] : 0.0;
 }
 }  // namespace
+
+hipError_t launch_rho_beta(int k, int ncols, const float *pcs, const double *rzp, int rzt,
+                           PcgState s, float *beta, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rho_beta, dim3(ncols), dim3(kThreads), 0, st, k, ncols, pcs, rzp, rzt, s,
+                       beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_dst_inv_p(const DstPlan &p, const _Float16 *t2, const float *Pold,
+                            const float *beta, float *P, long ld, int ncols, const float *pcs,
+                            hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
+    if (p.nx % 8 == 0) {
+        QO_DISPATCH_NT(p.NXP / 16,
+                       hipLaunchKernelGGL((k_dst_plane<float, true, NT, true, true>), grid, block,
+                                          dst_plane_lds(p, true), st, p, nullptr, t2, nullptr, P,
+                                          ld, pcs, Pold, beta));
+    } else {
+        QO_DISPATCH_NT(p.NXP / 16,
+                       hipLaunchKernelGGL((k_dst_plane<float, true, NT, false, true>), grid, block,
+                                          dst_plane_lds(p, true), st, p, nullptr, t2, nullptr, P,
+                                          ld, pcs, Pold, beta));
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_z_expand(const float *Z32, const float *pcs, double *Z, long ld, long ng,
                            int ncols, hipStream_t st) {

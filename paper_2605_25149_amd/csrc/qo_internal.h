@@ -89,6 +89,15 @@ hipError_t launch_dst_pencil(const DstPlan &p, const _Float16 *t1, _Float16 *t2,
 // an FP64 copy.
 hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, float *Z, long ld, int ncols,
                           const float *pcs, hipStream_t st);
+// FP32 PCG with the fast-Poisson preconditioner, iteration k: beta[c] = rho_k / rho_{k-1}
+// (0 at k = 0) for the preconditioned columns, rho_k = r.z from the pencil's partials,
+// reduced exactly as the first sweep reduces them; then the inverse plane pass forms the
+// search direction P = z + beta P_old itself (P = z when Pold is null).
+hipError_t launch_rho_beta(int k, int ncols, const float *pcs, const double *rzp, int rzt,
+                           PcgState s, float *beta, hipStream_t st);
+hipError_t launch_dst_inv_p(const DstPlan &p, const _Float16 *t2, const float *Pold,
+                            const float *beta, float *P, long ld, int ncols, const float *pcs,
+                            hipStream_t st);
 // Z (FP64) = Z32 for the columns with pcs[c] != 0, zero elsewhere.
 hipError_t launch_z_expand(const float *Z32, const float *pcs, double *Z, long ld, long ng,
                            int ncols, hipStream_t st);
@@ -115,7 +124,7 @@ hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T 
                              const T *Pold, T *Pnew, long ld, int ncols, int k, double tol,
                              const int *mask, PcgState s, hipStream_t st,
                              const float *Z = nullptr, const double *rzp = nullptr,
-                             int rzt = 0);
+                             int rzt = 0, bool p_given = false);
 template <typename T>
 // xzero: X is zero on entry (first iteration without an init pass; preconditioned form
 // only): X = alpha p is written without reading X.

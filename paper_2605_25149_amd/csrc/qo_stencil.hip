@@ -676,15 +676,18 @@ struct EpSweep1 {
     }
 };
 
-// XZ: the preconditioned residual z is an input (fast-Poisson preconditioner)
-// and r.z comes from that pass's partials rzp (rzt per column); otherwise
-// z = D r is formed on the fly and r.z comes from sweep2's partials.
+// MODE 0: Jacobi, z = D r formed on the fly, r.z from sweep2's partials.
+// MODE 1: the preconditioned residual z is an input (fast-Poisson preconditioner) and
+//         r.z comes from the preconditioner's partials rzp (rzt per column).
+// MODE 2: as 1, but the inverse preconditioner pass has already formed p = z + beta p_old
+//         (in Pnew): the sweep only reads p for gamma and the bookkeeping; nothing is
+//         stored.
 // FP32 with z as input at 3 points per thread: capped to six waves per SIMD, which spills
 // a few registers of the two prefetch sets and is still faster than the five waves that
 // fit without spills (96^3 x 256: 423 against 456 us).
-template <typename T, int PPT, bool XZ>
+template <typename T, int PPT, int MODE>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && XZ && PPT == 3 ? 6 : 1))) void k_pcg_sweep1(Grid g, const T *__restrict__ vs,
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MODE == 1 && PPT == 3 ? 6 : 1))) void k_pcg_sweep1(Grid g, const T *__restrict__ vs,
                                                          const T *__restrict__ dinv,
                                                          const T *__restrict__ R,
                                                          const T *__restrict__ Pold,
@@ -719,6 +722,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && XZ && PPT == 3 ? 6 : 1))) v
     const double ctol = s.coltol ? s.coltol[col] : tol;
     // the convergence test first: a converged column's z is not computed
     const bool conv = sqrt(rr) <= ctol * sqrt(bb);
+    constexpr bool XZ = MODE != 0;
     const double rz = (XZ && conv) ? 0.0 : (XZ ? col_sum(rzp, col, rzt, red)
                                                 : col_sum(s.part, col, tiles, red));
     if (threadIdx.x == 0) {
@@ -738,6 +742,22 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && XZ && PPT == 3 ? 6 : 1))) v
     }
     __syncthreads();
     if (sh_flag != 0) return;
+    if constexpr (MODE == 2) {
+        struct Ep {
+            using Raw = NoRaw;
+            double acc[1];
+            __device__ static Raw zero() { return {}; }
+            __device__ Raw load(long) const { return {}; }
+            __device__ void operator()(int, long, T c, T hv, const Raw &) {
+                acc[0] += (double)c * (double)hv;
+            }
+        } ep{{0.0}};
+        LdPlain<T> l{Pnew + (long)col * ld};
+        engine<T, PPT>(g, band, zc, vs, l, ep, lds_ptr<T>());
+        block_sums<1>(ep.acc, red);
+        if (threadIdx.x == 0) s.part[3 * qs + (long)col * tiles + tile] = ep.acc[0];
+        return;
+    }
     const T beta = (k == 0) ? T(0) : (T)(rz / s.rho[prv * ncols + col]);
     EpSweep1<T> ep{Pnew + (long)col * ld, {0.0}};
     if constexpr (XZ) {
@@ -1044,17 +1064,22 @@ template <typename T>
 hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T *R,
                              const T *Pold, T *Pnew, long ld, int ncols, int k, double tol,
                              const int *mask, PcgState s, hipStream_t st, const float *Z,
-                             const double *rzp, int rzt) {
+                             const double *rzp, int rzt, bool p_given) {
     if (ncols <= 0) return hipSuccess;
     const long qs = (long)ncols * g.tiles();
     const dim3 grid(ncols * g.tiles());
-    if (Z) {
-        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep1<T, P, true>), grid,
+    if (p_given) {
+        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep1<T, P, 2>), grid,
+                                                   dim3(kThreads), lds_bytes(g, sizeof(T)), st,
+                                                   g, vs, dinv, R, Pold, Pnew, ld, ncols, k, tol,
+                                                   mask, s, qs, Z, rzp, rzt));
+    } else if (Z) {
+        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep1<T, P, 1>), grid,
                                                    dim3(kThreads), lds_bytes(g, sizeof(T)), st,
                                                    g, vs, dinv, R, Pold, Pnew, ld, ncols, k, tol,
                                                    mask, s, qs, Z, rzp, rzt));
     } else {
-        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep1<T, P, false>), grid,
+        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_pcg_sweep1<T, P, 0>), grid,
                                                    dim3(kThreads), lds_bytes(g, sizeof(T)), st,
                                                    g, vs, dinv, R, Pold, Pnew, ld, ncols, k, tol,
                                                    mask, s, qs, Z, rzp, rzt));
@@ -1097,11 +1122,12 @@ template hipError_t launch_pcg_init<float>(const Grid &, const float *, const fl
 template hipError_t launch_pcg_sweep1<double>(const Grid &, const double *, const double *,
                                               const double *, const double *, double *, long,
                                               int, int, double, const int *, PcgState,
-                                              hipStream_t, const float *, const double *, int);
+                                              hipStream_t, const float *, const double *, int,
+                                              bool);
 template hipError_t launch_pcg_sweep1<float>(const Grid &, const float *, const float *,
                                              const float *, const float *, float *, long, int,
                                              int, double, const int *, PcgState, hipStream_t,
-                                             const float *, const double *, int);
+                                             const float *, const double *, int, bool);
 template hipError_t launch_pcg_sweep2<double>(const Grid &, const double *, const double *,
                                               const double *, double *, double *, long, int, int,
                                               PcgState, hipStream_t, bool, bool);

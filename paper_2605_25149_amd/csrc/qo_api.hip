@@ -90,6 +90,7 @@ struct qo_ctx {
     float *dmu = nullptr, *pcs = nullptr;
     float *z32 = nullptr;  // preconditioned residual z = M^{-1} r (FP32 in either precision)
     float *pbeta = nullptr;  // beta of the FP32 PCG, formed before the inverse plane pass
+    double *rzc = nullptr;   // and r.z per column
     double *rzp = nullptr, *dsum = nullptr;
     double mu0 = 0.0;  // mu_x[0] + mu_y[0] (+ mu_z[0]): smallest eigenvalue of -Lap_h
     // block CG (pcg_variant 2): Z and ping-pong partners of X, R, P; small matrices;
@@ -401,7 +402,7 @@ qo_status precondition_p(qo_ctx *c, const float *R, const float *Pold, float *Pn
     hipEvent_t e1 = prof_begin(c);
     HIPC(c, launch_dst_pencil(c->dp, c->t1, c->t2, c->ld, ncols, c->pcs, c->rzp, st));
     prof_end(c, QO_KERNEL_DST_PENCIL, e1);
-    HIPC(c, launch_rho_beta(k, ncols, c->pcs, c->rzp, c->dp.rzparts, s, c->pbeta, st));
+    HIPC(c, launch_rho_beta(k, ncols, c->pcs, c->rzp, c->dp.rzparts, s, c->pbeta, c->rzc, st));
     hipEvent_t e2 = prof_begin(c);
     HIPC(c, launch_dst_inv_p(c->dp, c->t2, k == 0 ? nullptr : Pold, c->pbeta, Pnew, c->ld, ncols,
                              c->pcs, st));
@@ -482,7 +483,8 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
             QOC(precondition<T>(c, R, Z, ncols, k, tol, mask, s));
         hipEvent_t ea = prof_begin(c);
         HIPC(c, launch_pcg_sweep1<T>(g, vs, dinv, R, pbuf[(k + 1) & 1], pbuf[k & 1], c->ld, ncols,
-                                     k, tol, mask, s, st, Z, c->rzp, c->dp.rzparts, pform));
+                                     k, tol, mask, s, st, Z, pform ? c->rzc : c->rzp,
+                                     pform ? 1 : c->dp.rzparts, pform));
         prof_end(c, k1, ea);
         if (outer && k == 0) {
             HIPC(c, hipEventSynchronize(outer->ev));
@@ -1572,6 +1574,7 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
         A(&h->dsum, 1);
         A(&h->z32, blk);
         A(&h->pbeta, (size_t)N);
+        A(&h->rzc, (size_t)N);
         if (s == QO_OK) {
             dp.Sx = h->dS;
             dp.Sy = h->dS + sx;

@@ -914,18 +914,21 @@ hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, float *Z, long l
 }
 
 namespace {
-// beta[c] = rho_k / rho_{k-1} (rho_k = r.z from the pencil's partials, summed by the same
-// block reduction as the first PCG sweep's), 0 at k = 0; columns with pcs[c] == 0 skipped.
+// rzc[c] = rho_k = r.z from the pencil's partials (the first sweep takes it from here) and
+// beta[c] = rho_k / rho_{k-1}, 0 at k = 0; columns with pcs[c] == 0 skipped.
 __global__ __launch_bounds__(kThreads) void k_rho_beta(int k, int ncols,
                                                        const float *__restrict__ pcs,
                                                        const double *__restrict__ rzp, int rzt,
-                                                       PcgState s, float *__restrict__ beta) {
+                                                       PcgState s, float *__restrict__ beta,
+                                                       double *__restrict__ rzc) {
     __shared__ dev::Red red;
     const int col = blockIdx.x;
     if (pcs[col] == 0.f) return;
     const double rz = dev::col_sum(rzp, col, rzt, red);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
+        rzc[col] = rz;
         beta[col] = k == 0 ? 0.f : (float)(rz / s.rho[((k & 1) ^ 1) * ncols + col]);
+    }
 }
 
 // Z (FP64) = Z32 for columns with pcs[c] != 0, else 0.
@@ -940,10 +943,10 @@ __global__ void k_z_expand(const float *__restrict__ Z32, const float *__restric
 }  // namespace
 
 hipError_t launch_rho_beta(int k, int ncols, const float *pcs, const double *rzp, int rzt,
-                           PcgState s, float *beta, hipStream_t st) {
+                           PcgState s, float *beta, double *rzc, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_rho_beta, dim3(ncols), dim3(kThreads), 0, st, k, ncols, pcs, rzp, rzt, s,
-                       beta);
+                       beta, rzc);
     return hipGetLastError();
 }
 

@@ -89,12 +89,12 @@ hipError_t launch_dst_pencil(const DstPlan &p, const _Float16 *t1, _Float16 *t2,
 // an FP64 copy.
 hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, float *Z, long ld, int ncols,
                           const float *pcs, hipStream_t st);
-// FP32 PCG with the fast-Poisson preconditioner, iteration k: beta[c] = rho_k / rho_{k-1}
-// (0 at k = 0) for the preconditioned columns, rho_k = r.z from the pencil's partials,
-// reduced exactly as the first sweep reduces them; then the inverse plane pass forms the
-// search direction P = z + beta P_old itself (P = z when Pold is null).
+// FP32 PCG with the fast-Poisson preconditioner, iteration k: rzc[c] = rho_k = r.z from the
+// pencil's partials and beta[c] = rho_k / rho_{k-1} (0 at k = 0) for the preconditioned
+// columns; then the inverse plane pass forms the search direction P = z + beta P_old
+// itself (P = z when Pold is null), and the first sweep takes rho_k from rzc.
 hipError_t launch_rho_beta(int k, int ncols, const float *pcs, const double *rzp, int rzt,
-                           PcgState s, float *beta, hipStream_t st);
+                           PcgState s, float *beta, double *rzc, hipStream_t st);
 hipError_t launch_dst_inv_p(const DstPlan &p, const _Float16 *t2, const float *Pold,
                             const float *beta, float *P, long ld, int ncols, const float *pcs,
                             hipStream_t st);

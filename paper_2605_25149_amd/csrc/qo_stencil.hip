@@ -680,8 +680,8 @@ struct EpSweep1 {
 // MODE 1: the preconditioned residual z is an input (fast-Poisson preconditioner) and
 //         r.z comes from the preconditioner's partials rzp (rzt per column).
 // MODE 2: as 1, but the inverse preconditioner pass has already formed p = z + beta p_old
-//         (in Pnew): the sweep only reads p for gamma and the bookkeeping; nothing is
-//         stored.
+//         (in Pnew) and r.z per column is rzp[c] (rzt == 1): the sweep only reads p for
+//         gamma and the bookkeeping; nothing is stored.
 // FP32 with z as input at 3 points per thread: capped to six waves per SIMD, which spills
 // a few registers of the two prefetch sets and is still faster than the five waves that
 // fit without spills (96^3 x 256: 423 against 456 us).
@@ -723,8 +723,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MODE == 1 && PPT == 3 ? 6 :
     // the convergence test first: a converged column's z is not computed
     const bool conv = sqrt(rr) <= ctol * sqrt(bb);
     constexpr bool XZ = MODE != 0;
-    const double rz = (XZ && conv) ? 0.0 : (XZ ? col_sum(rzp, col, rzt, red)
-                                                : col_sum(s.part, col, tiles, red));
+    const double rz = (XZ && conv) ? 0.0
+                      : MODE == 2 ? rzp[col]
+                      : (XZ ? col_sum(rzp, col, rzt, red) : col_sum(s.part, col, tiles, red));
     if (threadIdx.x == 0) {
         int flag = 0;  // 0 run, 1 converged, 2 non-finite
         if (!isfinite(rz) || !isfinite(rr) || !isfinite(bb)) flag = 2;

@@ -89,34 +89,78 @@ def make_solver(precision, n, N, inner_tol, variant, precond):
 
 
 def run_gpu(precision, V, U0, n, N, tau, steps, warmup, inner_tol, log, variant=0,
-            precond="fast_poisson"):
+            precond="fast_poisson", dim_n=None):
+    """Two passes over the same trajectory from U0 (same warm-up): first with HIP events
+    around every launch (per-kernel times for the roofline), then the timed pass with no
+    events; `seconds` is the second pass's wall time over the timed steps."""
     import torch
 
     s = make_solver(precision, n, N, inner_tol, variant, precond)
+    out = {}
     try:
         s.set_potential(V)
-        s.set_state(U0)
-        for i in range(warmup):
-            st = s.step(tau)
-            log(f"[{precision} {precond}] warmup step {i + 1}/{warmup}: iters {st['pcg_iters']} "
-                f"rounds {st['refine_rounds']} E {st['energy']:.10f}")
-        s.profile(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        stats = []
-        for i in range(steps):
-            st = s.step(tau)
-            stats.append(st)
-            log(f"[{precision} {precond}] step {i + 1}/{steps}: iters {st['pcg_iters']} "
-                f"rounds {st['refine_rounds']} E {st['energy']:.10f} "
-                f"phases(ms) {[round(x, 1) for x in st['t_phase_ms']]}")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        prof = s.profile_data()
-        s.profile(False)
-        return {"seconds": t1 - t0, "stats": stats, "profile": prof}
+        for timed in (False, True):
+            tag = f"{precision} {precond}" + ("" if timed else " profiled")
+            s.set_state(U0)
+            for i in range(warmup):
+                st = s.step(tau)
+                log(f"[{tag}] warmup step {i + 1}/{warmup}: iters {st['pcg_iters']} "
+                    f"rounds {st['refine_rounds']} E {st['energy']:.10f}")
+            s.profile(not timed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            stats = []
+            for i in range(steps):
+                st = s.step(tau)
+                stats.append(st)
+                log(f"[{tag}] step {i + 1}/{steps}: iters {st['pcg_iters']} "
+                    f"rounds {st['refine_rounds']} E {st['energy']:.10f} "
+                    f"phases(ms) {[round(x, 1) for x in st['t_phase_ms']]}")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if timed:
+                out.update(seconds=t1 - t0, stats=stats)
+            else:
+                out.update(profile=s.profile_data(), profiled_seconds=t1 - t0)
+                s.profile(False)
+        return out
     finally:
         s.close()
+
+
+def kernel_rates(prof, ng, value_bytes):
+    """Achieved GB/s of every streaming kernel of a run (algorithmic bytes / time)."""
+    bpc = bytes_per_colpt(prof, value_bytes)
+    out = {}
+    for k, b in bpc.items():
+        d = prof[k]
+        if d["launches"] and d["ms"] > 0:
+            gbs = b * ng * d["work"] / (d["ms"] * 1e-3) / 1e9
+            out[k] = {"GB/s": round(gbs, 1), "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
+                      "bytes_per_point_column": b}
+    return out
+
+
+def run_jacobi_fp64_leg(V64, U064, tau, steps, warmup, log, n=64, N=64):
+    """The FP64 Jacobi configuration: 64^3 Gaussian wells, N = 64, Jacobi PCG at tol 1e-10
+    (polled every 8 iterations), warm starts: steps/s and per-kernel GB/s."""
+    from paper_2605_25149_amd import binding
+
+    grid = (n, n, n)
+    r = run_gpu("fp64", V64, binding.as_block(U064), grid, N, tau, steps, warmup, 1e-5, log,
+                0, "jacobi")
+    ng = n ** 3
+    return {
+        "workload": f"3-D {n}^3 Dirichlet 7-point grid, 8 Gaussian wells (seed 0), N={N}, "
+                    f"random U0 (seed 1), tau={tau:.5f}, Jacobi PCG tol 1e-10, warm starts, FP64",
+        "steps": steps, "warmup": warmup,
+        "steps_per_s": round(steps / r["seconds"], 4),
+        "ms_per_step": round(1e3 * r["seconds"] / steps, 2),
+        "pcg_iters_per_step": [st["pcg_iters"] for st in r["stats"]],
+        "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3), "work": v["work"]}
+                    for k, v in r["profile"].items() if v["launches"]},
+        "kernel_rates": kernel_rates(r["profile"], ng, 8),
+    }
 
 
 def accuracy_gate(V, U0, n, N, tau, K, inner_tol, variant, log, res_tol=1e-5,
@@ -156,6 +200,10 @@ def accuracy_gate(V, U0, n, N, tau, K, inner_tol, variant, log, res_tol=1e-5,
     return {
         "steps": K,
         "converged_pairs": m,
+        "pairs": int(len(lam64)),
+        "coverage": (f"the 1e-8 gate covers the {m} of {len(lam64)} pairs that the FP64 run has "
+                     f"converged (relative residual <= {res_tol:g}) after {K} steps; the others "
+                     "are still moving along the trajectory (max_rel_eig_diff_all)"),
         "residual_tol": res_tol,
         "max_rel_eig_diff_converged": float(rel[conv].max()) if m else None,
         "max_rel_eig_diff_all": float(rel.max()),
@@ -235,36 +283,62 @@ def roofline_of(prof, ng, value_bytes):
     }
 
 
-def cpu_baseline(V, U0, n, N, tau, colits_per_step, log, precond="fast_poisson"):
-    """FP64 oracle on the host: a bounded sample of the same workload, scaled to steps/s.
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    Sample: (a) the oracle's PCG (same preconditioner as the GPU run) on all N columns of
-    the 96^3 grid for a fixed number of iterations, giving its column-iteration rate;
-    (b) one pass of the oracle's non-PCG stages (three Gram matrices, the 2N x 2N
-    predictor solve and the block update, the corrector and the energy) on full-size
-    blocks.  Steps/s = 1 / (column-iterations per step / rate + time of (b)), with
-    column-iterations per step taken from the FP64 GPU run (same algorithm and stop
-    rule)."""
+
+def cpu_baseline(V, U0, n, N, tau, colits_per_step, log, precond="fast_poisson",
+                 jacobi_leg=None):
+    """FP64 oracle on the host cores.
+
+    value: the metric's configuration (96^3, N = 256), EXTRAPOLATED from a bounded sample:
+    (a) the oracle's PCG (same preconditioner as the GPU run) on a subset of the columns
+    for a fixed number of iterations, giving its column-iteration rate (also taken with
+    one thread); (b) one pass of the oracle's non-PCG stages (Grams, the 2N x 2N predictor
+    solve and the block update, the corrector, the energy) on full-size blocks.
+    Steps/s = 1 / (column-iterations per step / rate + time of (b)), column-iterations per
+    step from the FP64 GPU run (same algorithm and stop rule).
+    Measured in full beside it: the 2-D 32^2, N = 4 trajectory of 200 steps, and one step
+    of the 64^3, N = 64 FP64 Jacobi configuration (the GPU leg of the same configuration
+    gives the ratio at equal work).  threads: the OpenMP threads of the oracle's C loops;
+    its transforms (scipy) run on one thread."""
     from oracle import oracle as orc
 
+    from paper_2605_25149_amd import inputs
+
+    nthreads = orc.threads()
     prob = orc.Problem(3, n, V)
     Uf = np.asfortranarray(U0)
-    if precond == "fast_poisson":
-        # the oracle's transforms run column by column: a subset of the columns
-        ncs = min(N, int(os.environ.get("QO_CPU_COLS", "32")))
-        kit = int(os.environ.get("QO_CPU_PCG_ITERS", "2"))
-        t0 = time.perf_counter()
-        prob.solve_fast_poisson(np.asfortranarray(Uf[:, :ncs]), tol=1e-30, maxit=kit)
-        t_pcg = time.perf_counter() - t0
-    else:
-        ncs = N
-        kit = int(os.environ.get("QO_CPU_PCG_ITERS", "6"))
-        t0 = time.perf_counter()
-        prob.solve(Uf, tol=1e-30, maxit=kit)
-        t_pcg = time.perf_counter() - t0
+
+    def pcg_sample(threads):
+        orc.threads(threads)
+        if precond == "fast_poisson":
+            # the oracle's transforms run column by column: a subset of the columns
+            ncs = min(N, int(os.environ.get("QO_CPU_COLS", "32")))
+            kit = int(os.environ.get("QO_CPU_PCG_ITERS", "2"))
+            t0 = time.perf_counter()
+            prob.solve_fast_poisson(np.asfortranarray(Uf[:, :ncs]), tol=1e-30, maxit=kit)
+        else:
+            ncs = N
+            kit = int(os.environ.get("QO_CPU_PCG_ITERS", "6"))
+            t0 = time.perf_counter()
+            prob.solve(Uf, tol=1e-30, maxit=kit)
+        return ncs, kit, time.perf_counter() - t0
+
+    ncs, kit, t_pcg = pcg_sample(nthreads)
     rate = ncs * kit / t_pcg
     log(f"[cpu] oracle {precond} PCG {ncs} columns x {kit} iterations: {t_pcg:.2f} s "
-        f"({rate:.1f} column-iterations/s)")
+        f"({rate:.1f} column-iterations/s, {nthreads} threads)")
+    ncs1, kit1, t_pcg1 = pcg_sample(1)
+    rate1 = ncs1 * kit1 / t_pcg1
+    log(f"[cpu] same sample on 1 thread: {t_pcg1:.2f} s ({rate1:.1f} column-iterations/s)")
+    orc.threads(nthreads)
     P = np.asfortranarray(0.1 * Uf)
     t0 = time.perf_counter()
     Uh, Xm, Ym, _ = orc.predictor(prob, Uf, P, tau)
@@ -273,17 +347,46 @@ def cpu_baseline(V, U0, n, N, tau, colits_per_step, log, precond="fast_poisson")
     t_rest = time.perf_counter() - t0
     log(f"[cpu] oracle non-PCG stages: {t_rest:.2f} s")
     sec_per_step = colits_per_step / rate + t_rest
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {
+    sec_per_step1 = colits_per_step / rate1 + t_rest
+    # full runs beside the extrapolation
+    n1 = (32, 32)
+    p1 = orc.Problem(2, n1, inputs.harmonic(n1, 100.0))
+    o1 = orc.Oracle(p1, inputs.random_block(1024, 4, seed=1), tol=1e-12, variant=0)
+    t0 = time.perf_counter()
+    for _ in range(200):
+        o1.step(0.9 * 12.9544687)
+    t_cfg1 = time.perf_counter() - t0
+    log(f"[cpu] oracle 2-D 32^2 N=4, 200 steps (Jacobi, tol 1e-12): {t_cfg1:.2f} s")
+    n2 = (64, 64, 64)
+    p2 = orc.Problem(3, n2, inputs.gaussian_wells(n2, seed=0))
+    o2 = orc.Oracle(p2, inputs.random_block(64 ** 3, 64, seed=1), tol=1e-10, variant=0)
+    t0 = time.perf_counter()
+    st2 = o2.step(tau)
+    t_cfg2 = time.perf_counter() - t0
+    log(f"[cpu] oracle 64^3 N=64 FP64 Jacobi, one step: {t_cfg2:.2f} s "
+        f"(iterations {st2.pcg_iters})")
+    out = {
         "value": round(1.0 / sec_per_step, 6),
         "unit": "steps/s",
-        "cores": cores,
+        "cores": nthreads,
         "kind": "oracle",
-        "sample": (f"96^3 x {N}: oracle {precond} PCG, {kit} iterations on {ncs} columns "
-                   f"({t_pcg:.1f} s) + one pass of the non-PCG stages ({t_rest:.1f} s); "
-                   f"scaled by {colits_per_step:.0f} column-iterations per step"),
+        "sample": (f"EXTRAPOLATED to 96^3 x {N}: oracle {precond} PCG, {kit} iterations on "
+                   f"{ncs} of the {N} columns ({t_pcg:.1f} s) + one pass of the non-PCG stages "
+                   f"({t_rest:.1f} s), scaled by {colits_per_step:.0f} column-iterations per "
+                   "step; full runs in cfg1_full and cfg2_step"),
+        "cpu_model": cpu_model(),
+        "threads": nthreads,
         "seconds_per_step": round(sec_per_step, 2),
+        "value_1thread": round(1.0 / sec_per_step1, 6),
+        "cfg1_full": {"workload": "2-D 32^2, N=4, harmonic, 200 steps, Jacobi tol 1e-12",
+                      "seconds": round(t_cfg1, 3), "steps_per_s": round(200 / t_cfg1, 2)},
+        "cfg2_step": {"workload": "64^3 wells, N=64, FP64 Jacobi tol 1e-10, first step",
+                      "seconds": round(t_cfg2, 3), "steps_per_s": round(1 / t_cfg2, 4),
+                      "pcg_iters": list(st2.pcg_iters)},
     }
+    if jacobi_leg:
+        out["cfg2_gpu_over_cpu"] = round(jacobi_leg["steps_per_s"] * t_cfg2, 1)
+    return out
 
 
 def batch_tau(p, kappa=0.5):
@@ -427,6 +530,8 @@ def main():
     ap.add_argument("--batch-precisions", default="fp64,mixed")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batch leg and print its JSON (profiling aid)")
+    ap.add_argument("--cfg2-steps", type=int, default=20,
+                    help="timed steps of the 64^3, N=64 FP64 Jacobi leg (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=50,
                     help="K of the reverse-mode leg (64^3, N=32); 0 skips it")
     ap.add_argument("--quiet", action="store_true")
@@ -510,13 +615,18 @@ def main():
             "parallelism": "single GPU",
         },
     }
+    out["timing"] = ("value and ms_per_step: a pass without per-launch events; the kernel times "
+                     "come from a first pass over the same trajectory with HIP events around "
+                     "every launch (profiled_steps_per_s)")
     for mode, r in res.items():
         its = [st["pcg_iters"] for st in r["stats"]]
         out[f"{mode}_steps_per_s"] = round(args.steps / r["seconds"], 6)
+        out[f"{mode}_profiled_steps_per_s"] = round(args.steps / r["profiled_seconds"], 6)
         out[f"{mode}_pcg_iters_per_step"] = its
         out[f"{mode}_kernels"] = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                                       "work": v["work"]}
                                   for k, v in r["profile"].items() if v["launches"]}
+        out[f"{mode}_kernel_rates"] = kernel_rates(r["profile"], ng, 4 if mode == "mixed" else 8)
     if "fp64" in res and "mixed" in res:
         out["speedup_mixed_vs_fp64"] = round(res["fp64"]["seconds"] / res["mixed"]["seconds"], 4)
     vbytes = 4 if head == "mixed" else 8
@@ -535,6 +645,18 @@ def main():
         out["accuracy"] = accuracy_gate(V, U0_dev, n, N, tau, args.accuracy_steps,
                                         args.inner_tol, args.pcg_variant, log,
                                         precond=args.precond)
+        a = out["accuracy"]
+        out["config"]["accuracy_gate"] = (
+            f"mixed vs FP64 Ritz values after {a['steps']} steps from the same U0, on the "
+            f"{a['converged_pairs']}/{a['pairs']} pairs converged in the FP64 run")
+    jleg = None
+    if args.cfg2_steps > 0:
+        n2 = (64, 64, 64)
+        jleg = run_jacobi_fp64_leg(inputs.gaussian_wells(n2, seed=0),
+                                   inputs.random_block(64 ** 3, 64, seed=1), tau,
+                                   args.cfg2_steps, 2, log)
+        out["cfg2"] = jleg
+        log(f"[cfg2] 64^3 N=64 FP64 Jacobi: {jleg['steps_per_s']} steps/s")
     if args.jacobi_steps > 0 and args.precond != "jacobi":
         jac = {}
         for mode in args.modes.split(","):
@@ -552,7 +674,8 @@ def main():
         ref = res["fp64"] if "fp64" in res else rh
         colits = max(ref["profile"][k]["work"] for k in ("sweep2_f64", "sweep2_f32", "cg_f64", "cg_f32"))
         colits_per_step = colits / args.steps
-        out["cpu_baseline"] = cpu_baseline(V, U0, n, N, tau, colits_per_step, log, args.precond)
+        out["cpu_baseline"] = cpu_baseline(V, U0, n, N, tau, colits_per_step, log, args.precond,
+                                           jleg)
     print(json.dumps(out), flush=True)
 
 

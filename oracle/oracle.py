@@ -100,8 +100,20 @@ def _load():
         lib.orc_pcg.restype = ctypes.c_int
         lib.orc_pcg_variant.argtypes = lib.orc_pcg.argtypes + [ctypes.c_int]
         lib.orc_pcg_variant.restype = ctypes.c_int
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = None
         _lib = lib
     return _lib
+
+
+def threads(n=None):
+    """OpenMP threads of the C part (set first when n is given); for timing records."""
+    lib = _load()
+    if n is not None:
+        lib.orc_set_threads(int(n))
+    return int(lib.orc_threads())
 
 
 def _dp(a):

@@ -34,6 +34,7 @@
  * column a grid with x fastest: index i + n0*(j + n1*k).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -265,4 +266,11 @@ static int cg_one_reduction(int dim, const int *n, const double *h, double kappa
     }
     *iters = it;
     return ORC_OK;
+}
+
+/* Threads of the OpenMP loops above (for the record of a timing), and a way to change
+ * them (1: the single-thread rate).  Not part of the method. */
+int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
 }

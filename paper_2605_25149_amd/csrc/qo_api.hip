@@ -1043,10 +1043,11 @@ qo_status gram(qo_ctx *c, const double *X, const double *Y, long ld, int n, doub
     return QO_OK;
 }
 
+// fp32: the FP32-arithmetic update of the mixed-precision step (see launch_tsgemm)
 qo_status tsgemm(qo_ctx *c, double *Out, const double *C0, const double *A, const double *Xr,
-                 const double *Bm, const double *Yr) {
+                 const double *Bm, const double *Yr, bool fp32 = false) {
     hipEvent_t e = prof_begin(c);
-    HIPC(c, launch_tsgemm(Out, c->ld, C0, A, Xr, Bm, Yr, c->ld, c->ng, c->N, c->st));
+    HIPC(c, launch_tsgemm(Out, c->ld, C0, A, Xr, Bm, Yr, c->ld, c->ng, c->N, c->st, fp32));
     prof_end(c, QO_KERNEL_UPDATE, e);
     return QO_OK;
 }
@@ -1246,8 +1247,9 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
     HIPC(c, hipMemcpyAsync(stat_slot(c), c->dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(c, hipEventRecord(c->sev, st));
     rec(c, 3);
-    QOC(tsgemm(c, c->Uh, nullptr, c->U, mp(c, MP_XR), P, mp(c, MP_YR)));
-    if (warm) QOC(tsgemm(c, Q, nullptr, P, mp(c, MP_ZR), nullptr, nullptr));
+    // QO_MIXED: the block updates in FP32 arithmetic (the Grams of that path are BF16)
+    QOC(tsgemm(c, c->Uh, nullptr, c->U, mp(c, MP_XR), P, mp(c, MP_YR), c->mixed));
+    if (warm) QOC(tsgemm(c, Q, nullptr, P, mp(c, MP_ZR), nullptr, nullptr, c->mixed));
     rec(c, 4);
     const qo_status sQ = solve_block(c, c->Uh, Q, N, warm, itsQ.data(), &rQ, "solve G U_hat");
     HIPC(c, hipEventSynchronize(c->sev));
@@ -1274,7 +1276,7 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
                         st));
         HIPC(c, nn_fro(On, N, N, c->dscal + 2, st));
     }
-    QOC(tsgemm(c, c->U, c->Uh, nullptr, nullptr, Q, mp(c, MP_OR)));
+    QOC(tsgemm(c, c->U, c->Uh, nullptr, nullptr, Q, mp(c, MP_OR), c->mixed));
     rec(c, 7);
     // the state has moved: commit bookkeeping before the (non-failing) diagnostics
     c->lastP = P;

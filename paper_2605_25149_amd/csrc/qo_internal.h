@@ -259,9 +259,11 @@ struct TsJob {
 };
 hipError_t launch_tsgemm_batch(const TsJob *jobs, int njobs, int max_n, long ld, long ng,
                                hipStream_t st);
+// fp32: FP32 MFMA arithmetic (operands rounded to FP32, FP32 accumulation, C0 added in
+// FP64), for the mixed-precision path.
 hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
                          const double *XsT, const double *B, const double *YsT, long ld,
-                         long ng, int n, hipStream_t st);
+                         long ng, int n, hipStream_t st, bool fp32 = false);
 
 // ---- small dense FP64 (qo_small.hip), all column-major with explicit ld ----
 // C = alpha op(A) op(B) + beta C + gamma I

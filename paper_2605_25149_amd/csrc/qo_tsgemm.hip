@@ -2,7 +2,8 @@
 //   predictor   U_hat = U X + P Y          (P = G U_n)
 //   warm start  x0    = P (X + C Y)        for the solve G U_hat
 //   corrector   U_{n+1} = U_hat + Q (-tau O)   (Q = G U_hat, O = <U_hat,U_hat> - I)
-// as one FP64 MFMA kernel Out = C0 + A Xs + B Ys (Ng x n).
+// as one FP64 MFMA kernel Out = C0 + A Xs + B Ys (Ng x n), with an FP32-arithmetic twin
+// for the mixed-precision path.
 //
 // Computed transposed, Out^T = Xs^T A^T + Ys^T B^T, so that the MFMA output
 // rows run along the grid: lane l of a 16x16 block owns grid row m0 + l%16 of
@@ -21,6 +22,7 @@ namespace qo {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Global-address-space view: the batch kernel reads its operand pointers from a job
 // table, and generic loads through them would make the compiler wait for every load in
@@ -151,6 +153,143 @@ __device__ __forceinline__ void tsgemm_tile(double *__restrict__ Out, long ldo,
         }
 }
 
+// The same tile in FP32 arithmetic: operands rounded from FP64 to FP32 as they enter the
+// MFMA (v_mfma_f32_16x16x4f32, twice the FP64 rate), FP32 accumulation, and C0 added in FP64
+// when the tile is stored.  The prefetch keeps FP64 values, converted at their use, so
+// that no conversion waits for a load still in flight.  Used by the mixed-precision path,
+// whose Gram matrices are BF16: an FP32 block update (relative error ~1e-7 per entry, like
+// the FP32 PCG) is well inside what that path tolerates.
+__device__ __forceinline__ void tsgemm32_tile(double *__restrict__ Out, long ldo,
+                                              const double *__restrict__ C0,
+                                              const double *__restrict__ A,
+                                              const double *__restrict__ Xr,
+                                              const double *__restrict__ B,
+                                              const double *__restrict__ Yr, long ld, long ng,
+                                              int n, long m0, int c0) {
+    const int lane = threadIdx.x;
+    const int lr = lane & 15, lg = lane >> 4;
+
+    v4f acc[4][4];  // [column block j][row block i]
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[j][i] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    long moff[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const long m = m0 + 16 * i + lr;
+        moff[i] = m < ng ? m : ng - 1;
+    }
+    int coff[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = c0 + 16 * j + lr;
+        coff[j] = c < n ? c : n - 1;
+    }
+    auto pass = [&](const double *Tp, const double *Sp) {
+        // twice the MFMA rate of FP64: chunks of 16 k-values keep as much time between a
+        // chunk's loads and their use as the FP64 kernel's chunks of 8
+        constexpr int KSC = 2 * QO_TSG_KSC, KC = 4 * KSC;
+        gdouble *__restrict__ T = gptr(Tp);
+        gdouble *__restrict__ S = gptr(Sp);
+        auto load_chunk = [&](int kc, double (&sa)[KSC][4], double (&tb)[KSC][4]) {
+#pragma unroll
+            for (int ks = 0; ks < KSC; ++ks) {
+                const long k = kc + 4 * ks + lg;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) sa[ks][j] = S[k * n + coff[j]];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) tb[ks][i] = T[k * ld + moff[i]];
+            }
+        };
+        auto mma_chunk = [&](const double (&sa)[KSC][4], const double (&tb)[KSC][4]) {
+#pragma unroll
+            for (int ks = 0; ks < KSC; ++ks)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            (float)sa[ks][j], (float)tb[ks][i], acc[j][i], 0, 0, 0);
+        };
+        const int nfull = n & ~(KC - 1);
+        double sa0[KSC][4], tb0[KSC][4], sa1[KSC][4], tb1[KSC][4];
+        if (nfull > 0) {
+            const int last = nfull - KC;
+            const int npairs = nfull / (2 * KC);
+            load_chunk(0, sa0, tb0);
+            for (int p = 0; p < npairs; ++p) {
+                const int kc = p * 2 * KC;
+                load_chunk(kc + KC, sa1, tb1);
+                __builtin_amdgcn_sched_barrier(0);
+                mma_chunk(sa0, tb0);
+                __builtin_amdgcn_sched_barrier(0);
+                load_chunk(min(kc + 2 * KC, last), sa0, tb0);
+                __builtin_amdgcn_sched_barrier(0);
+                mma_chunk(sa1, tb1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (nfull & KC) mma_chunk(sa0, tb0);
+        }
+        if (nfull < n) {
+#pragma unroll
+            for (int ks = 0; ks < KSC; ++ks) {
+                const int k = nfull + 4 * ks + lg;
+                const bool kin = k < n;
+                const long kk = kin ? k : n - 1;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double v = S[kk * n + coff[j]];
+                    sa0[ks][j] = kin ? v : 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) tb0[ks][i] = T[kk * ld + moff[i]];
+            }
+            mma_chunk(sa0, tb0);
+        }
+    };
+    if (A) pass(A, Xr);
+    if (B) pass(B, Yr);
+    // FP32 16x16 accumulator layout: value v of lane l is row 4 (l/16) + v, column l%16,
+    // so acc[j][i][v] = Out^T[c0 + 16j + 4lg + v][m0 + 16i + lr]
+    // C0 for every value of the tile first (clamped, unconditional loads issued together),
+    // then the sums are stored
+    double c0v[4][4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = c0 + 16 * j + 4 * lg + v;
+                c0v[j][i][v] = C0 ? (double)gptr(C0)[(long)(c < n ? c : n - 1) * ld + moff[i]]
+                                  : 0.0;
+            }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long m = m0 + 16 * i + lr;
+            if (m >= ng) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = c0 + 16 * j + 4 * lg + v;
+                if (c < n) Out[(long)c * ldo + m] = c0v[j][i][v] + (double)acc[j][i][v];
+            }
+        }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_tsgemm32(
+    double *__restrict__ Out, long ldo, const double *__restrict__ C0,
+    const double *__restrict__ A, const double *__restrict__ Xr, const double *__restrict__ B,
+    const double *__restrict__ Yr, long ld, long ng, int n) {
+    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int rt = L / gridDim.y;
+    tsgemm32_tile(Out, ldo, C0, A, Xr, B, Yr, ld, ng, n, (long)rt * 64,
+                  (L - rt * gridDim.y) * 64);
+}
+
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_tsgemm(double *__restrict__ Out, long ldo,
                                                const double *__restrict__ C0,
                                                const double *__restrict__ A,
@@ -185,13 +324,17 @@ hipError_t launch_tsgemm_batch(const TsJob *jobs, int njobs, int max_n, long ld,
 
 hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
                          const double *Xr, const double *B, const double *Yr, long ld, long ng,
-                         int n, hipStream_t st) {
+                         int n, hipStream_t st, bool fp32) {
     if (n <= 0 || ng <= 0) return hipSuccess;
     // each big operand needs its small operand (and the reverse)
     if ((A == nullptr) != (Xr == nullptr) || (B == nullptr) != (Yr == nullptr) || !Out)
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)((ng + 63) / 64), (unsigned)((n + 63) / 64));
-    hipLaunchKernelGGL(k_tsgemm, grid, dim3(64), 0, st, Out, ldo, C0, A, Xr, B, Yr, ld, ng, n);
+    if (fp32)
+        hipLaunchKernelGGL(k_tsgemm32, grid, dim3(64), 0, st, Out, ldo, C0, A, Xr, B, Yr, ld, ng,
+                           n);
+    else
+        hipLaunchKernelGGL(k_tsgemm, grid, dim3(64), 0, st, Out, ldo, C0, A, Xr, B, Yr, ld, ng, n);
     return hipGetLastError();
 }
 

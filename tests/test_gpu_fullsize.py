@@ -18,7 +18,10 @@ directly at full size or column by column:
     S, M, R gives X, Y within 1e-9 of the GPU's (the 2N x 2N form is the worse
     conditioned one);
   * the block updates U_hat = U X + P Y and U_{n+1} = U_hat - tau Q O from the GPU's own
-    coefficients, full blocks, within 1e-12 of the largest entry;
+    coefficients, full blocks: FP64 within 1e-12 of the largest entry; mixed precision (FP32
+    arithmetic: operands rounded to FP32, FP32 accumulation over K terms) within the dot
+    product bound (K + 2) 2^-24 (|U| |X| + |P| |Y|) per entry (K = 2N), and for the
+    corrector (N + 2) 2^-24 tau |Q| |O| (the FP64 U_hat added exactly to rounding);
   * E(U_{n+1}) from the oracle's stencil quadratic form within 1e-12 relative."""
 import numpy as np
 import pytest
@@ -126,13 +129,24 @@ def test_fullsize_step_stages(torch, B, oracle_mod, side, N_COLS, precision, pre
         assert err <= 1e-9 * np.abs(ref).max(), name
 
     Uh_ref = Un @ mats["X"] + P @ mats["Y"]
-    err = np.abs(Uh - Uh_ref).max()
-    print(f"[{precision}] U_hat: max error {err:.3e}")
-    assert err <= 1e-12 * np.abs(Uh_ref).max()
+    err = np.abs(Uh - Uh_ref)
+    print(f"[{precision}] U_hat: max error {err.max():.3e}")
+    if precision == "fp64":
+        assert err.max() <= 1e-12 * np.abs(Uh_ref).max()
+    else:
+        bound = (2 * N_COLS + 2) * 2.0 ** -24 * (np.abs(Un) @ np.abs(mats["X"]) +
+                                                 np.abs(P) @ np.abs(mats["Y"]))
+        print(f"[{precision}] U_hat: max error / FP32 bound {np.max(err / bound):.3e}")
+        assert np.all(err <= bound + 1e-15 * np.abs(Uh_ref).max())
     U1_ref = Uh - TAU * (Q @ mats["O"])
-    err = np.abs(U1 - U1_ref).max()
-    print(f"[{precision}] U_1: max error {err:.3e}")
-    assert err <= 1e-12 * np.abs(U1_ref).max()
+    err = np.abs(U1 - U1_ref)
+    print(f"[{precision}] U_1: max error {err.max():.3e}")
+    if precision == "fp64":
+        assert err.max() <= 1e-12 * np.abs(U1_ref).max()
+    else:
+        bound = (N_COLS + 2) * 2.0 ** -24 * TAU * (np.abs(Q) @ np.abs(mats["O"]))
+        print(f"[{precision}] U_1: max error / FP32 bound {np.max(err / (bound + 1e-300)):.3e}")
+        assert np.all(err <= bound + 1e-15 * np.abs(U1_ref).max())
     E, _ = prob.energy(U1)
     print(f"[{precision}] energy {st['energy']:.15e} oracle {E:.15e}")
     assert abs(st["energy"] - E) <= 1e-12 * abs(E)

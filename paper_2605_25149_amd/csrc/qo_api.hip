@@ -91,6 +91,7 @@ struct qo_ctx {
     float *z32 = nullptr;  // preconditioned residual z = M^{-1} r (FP32 in either precision)
     float *pbeta = nullptr;  // beta of the FP32 PCG, formed before the inverse plane pass
     double *rzc = nullptr;   // and r.z per column
+    double *wzp = nullptr;   // partial sums of (V + sigma - vbar) z^2 per column and slab
     double *rzp = nullptr, *dsum = nullptr;
     double mu0 = 0.0;  // mu_x[0] + mu_y[0] (+ mu_z[0]): smallest eigenvalue of -Lap_h
     // block CG (pcg_variant 2): Z and ping-pong partners of X, R, P; small matrices;
@@ -331,7 +332,8 @@ int *stat_slot(qo_ctx *c) { return round_slot(c) + 8; }
 int *its_slot(qo_ctx *c, int round) { return round_slot(c) + 16 + (long)round * c->N; }
 
 // Kernel-time work counters of one PCG solve from its per-column iteration counts.
-// pform: the FP32 form whose inverse pass reads P_old except at k = 0 (0.6 of its bytes).
+// pform: the FP32 form whose inverse pass reads P_old except at k = 0 (0.6 of its bytes)
+// and which runs no first sweep.
 void pcg_account(qo_ctx *c, bool f64, const int *its, int ncols, bool zero_start_dst, bool dst,
                  bool pform = false) {
     if (!c->prof) return;
@@ -343,7 +345,7 @@ void pcg_account(qo_ctx *c, bool f64, const int *its, int ncols, bool zero_start
     }
     const int k1 = f64 ? QO_KERNEL_SWEEP1_F64 : QO_KERNEL_SWEEP1_F32;
     const int k2 = f64 ? QO_KERNEL_SWEEP2_F64 : QO_KERNEL_SWEEP2_F32;
-    c->pdata.work[k1] += colits;
+    if (!pform) c->pdata.work[k1] += colits;  // the FP32 form has no first sweep
     c->pdata.work[k2] += colits - (zero_start_dst ? 0.2 * started : 0.0);
     if (dst)
         for (int kid : {(int)QO_KERNEL_DST_FWD, (int)QO_KERNEL_DST_PENCIL, (int)QO_KERNEL_DST_INV})
@@ -390,7 +392,8 @@ struct RoundPoll {
 
 // The FP32 form: the same passes, with beta of the PCG step taken from the pencil's r.z
 // partials before the inverse plane pass, which then writes the search direction
-// P = z + beta P_old (P = z at k = 0) instead of z; the first sweep only reads P.
+// P = z + beta P_old (P = z at k = 0) instead of z, and the partial sums of w z^2 that give
+// gamma = P.H P without a pass over the grid (launch_pcg_gamma).
 qo_status precondition_p(qo_ctx *c, const float *R, const float *Pold, float *Pnew, int ncols,
                          int k, double tol, const int *mask, const PcgState &s) {
     hipStream_t st = c->st;
@@ -405,7 +408,7 @@ qo_status precondition_p(qo_ctx *c, const float *R, const float *Pold, float *Pn
     HIPC(c, launch_rho_beta(k, ncols, c->pcs, c->rzp, c->dp.rzparts, s, c->pbeta, c->rzc, st));
     hipEvent_t e2 = prof_begin(c);
     HIPC(c, launch_dst_inv_p(c->dp, c->t2, k == 0 ? nullptr : Pold, c->pbeta, Pnew, c->ld, ncols,
-                             c->pcs, st));
+                             c->pcs, c->vs32, c->wzp, st));
     prof_end(c, QO_KERNEL_DST_INV, e2);
     return QO_OK;
 }
@@ -481,11 +484,14 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
                                reinterpret_cast<float *>(pbuf[k & 1]), ncols, k, tol, mask, s));
         else if (Z)
             QOC(precondition<T>(c, R, Z, ncols, k, tol, mask, s));
-        hipEvent_t ea = prof_begin(c);
-        HIPC(c, launch_pcg_sweep1<T>(g, vs, dinv, R, pbuf[(k + 1) & 1], pbuf[k & 1], c->ld, ncols,
-                                     k, tol, mask, s, st, Z, pform ? c->rzc : c->rzp,
-                                     pform ? 1 : c->dp.rzparts, pform));
-        prof_end(c, k1, ea);
+        if (pform) {
+            HIPC(c, launch_pcg_gamma(g, k, ncols, tol, mask, s, c->rzc, c->wzp, c->dp.nslab, st));
+        } else {
+            hipEvent_t ea = prof_begin(c);
+            HIPC(c, launch_pcg_sweep1<T>(g, vs, dinv, R, pbuf[(k + 1) & 1], pbuf[k & 1], c->ld,
+                                         ncols, k, tol, mask, s, st, Z, c->rzp, c->dp.rzparts));
+            prof_end(c, k1, ea);
+        }
         if (outer && k == 0) {
             HIPC(c, hipEventSynchronize(outer->ev));
             prof_harvest(c);
@@ -1577,6 +1583,7 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
         A(&h->z32, blk);
         A(&h->pbeta, (size_t)N);
         A(&h->rzc, (size_t)N);
+        A(&h->wzp, (size_t)N * dp.nslab);
         if (s == QO_OK) {
             dp.Sx = h->dS;
             dp.Sy = h->dS + sx;

@@ -211,7 +211,8 @@ __host__ __device__ inline size_t dst_plane_xt_bytes(const DstPlan &p) {
 // FP32 3-D planes (NT <= 8) are held to 80 registers: 6 waves per SIMD, four 6-wave
 // workgroups per CU, as many as their LDS allows.
 // PF (inverse only): store the search direction P = z + beta[c] P_old (P = z when Pold is
-// null) instead of z.
+// null) instead of z, and the slab's partial sum of w z^2, w = V + sigma - vbar (vs holds
+// V + sigma per grid point), into wzp[c * nslab + slab].
 template <typename T, bool INV, int NT, bool VEC, bool PF = false>
 __global__ __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_dst_plane(DstPlan p, const T *__restrict__ R,
@@ -220,8 +221,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
                                                    float *__restrict__ Z, long ld,
                                                    const float *__restrict__ pcs,
                                                    const float *__restrict__ Pold = nullptr,
-                                                   const float *__restrict__ beta = nullptr) {
+                                                   const float *__restrict__ beta = nullptr,
+                                                   const float *__restrict__ vs = nullptr,
+                                                   double *__restrict__ wzp = nullptr) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kMaxWaves];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int col = L / p.nslab;
     const int slab = L - col * p.nslab;
@@ -455,19 +459,24 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
         const int g4 = NXP / 4;
         if constexpr (PF && VEC) {
             // each thread owns at most NT groups of 4 (rows * NXP / 4 <= NT * nthr): the
-            // P_old loads are issued together (clamped into the slab), then P is stored
+            // P_old and V + sigma loads are issued together (clamped into the slab), then P
+            // is stored and w z^2 summed
             const bool first = Pold == nullptr;
             const float b = first ? 0.f : beta[col];
-            float4 po[QF];
+            const float vb = p.cvbar ? p.cvbar[col] : p.vbar;
+            const long pbase = base - (long)col * ld;  // the slab's offset within a column
+            float4 po[QF], v4[QF];
 #pragma unroll
             for (int q = 0; q < QF; ++q) {
                 const int it = tid + q * nthr;
                 const int r = it / g4, x = (it - r * g4) * 4;
                 const bool ok = r < rows && x < nx;
-                const long i0 = ok ? base + (long)r * nx + x : base;
+                const long off = ok ? (long)r * nx + x : 0;
                 po[q] = first ? float4{0.f, 0.f, 0.f, 0.f}
-                              : *reinterpret_cast<const float4 *>(Pold + i0);
+                              : *reinterpret_cast<const float4 *>(Pold + base + off);
+                v4[q] = *reinterpret_cast<const float4 *>(vs + pbase + off);
             }
+            double wz = 0.0;
 #pragma unroll
             for (int q = 0; q < QF; ++q) {
                 const int it = tid + q * nthr;
@@ -479,10 +488,18 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
                                      : v4f{z4.x + b * po[q].x, z4.y + b * po[q].y,
                                            z4.z + b * po[q].z, z4.w + b * po[q].w};
                 st_out(reinterpret_cast<v4f *>(Z + i0), pv);
+                wz += (double)((v4[q].x - vb) * z4.x * z4.x + (v4[q].y - vb) * z4.y * z4.y) +
+                      (double)((v4[q].z - vb) * z4.z * z4.z + (v4[q].w - vb) * z4.w * z4.w);
             }
+            wz = block_sum(wz, red);
+            if (tid == 0) wzp[(long)col * p.nslab + slab] = wz;
         } else {
             const bool first = !PF || Pold == nullptr;
             const float b = first ? 0.f : beta[col];
+            float vb = 0.f;
+            if constexpr (PF) vb = p.cvbar ? p.cvbar[col] : p.vbar;
+            const long pbase = base - (long)col * ld;
+            double wz = 0.0;
             for (int it = tid; it < rows * g4; it += nthr) {
                 const int r = it / g4;
                 const int x = (it - r * g4) * 4;
@@ -497,8 +514,16 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
                     for (int i = 0; i < 4; ++i) {
                         if (x + i >= nx) break;
                         Z[i0 + i] = first ? src[i] : src[i] + b * Pold[i0 + i];
+                        if constexpr (PF) {
+                            const float w = vs[pbase + (long)r * nx + x + i] - vb;
+                            wz += (double)(w * src[i] * src[i]);
+                        }
                     }
                 }
+            }
+            if constexpr (PF) {
+                wz = block_sum(wz, red);
+                if (tid == 0) wzp[(long)col * p.nslab + slab] = wz;
             }
         }
     }
@@ -952,19 +977,19 @@ hipError_t launch_rho_beta(int k, int ncols, const float *pcs, const double *rzp
 
 hipError_t launch_dst_inv_p(const DstPlan &p, const _Float16 *t2, const float *Pold,
                             const float *beta, float *P, long ld, int ncols, const float *pcs,
-                            hipStream_t st) {
+                            const float *vs, double *wzp, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
     const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
     if (p.nx % 8 == 0) {
         QO_DISPATCH_NT(p.NXP / 16,
                        hipLaunchKernelGGL((k_dst_plane<float, true, NT, true, true>), grid, block,
                                           dst_plane_lds(p, true), st, p, nullptr, t2, nullptr, P,
-                                          ld, pcs, Pold, beta));
+                                          ld, pcs, Pold, beta, vs, wzp));
     } else {
         QO_DISPATCH_NT(p.NXP / 16,
                        hipLaunchKernelGGL((k_dst_plane<float, true, NT, false, true>), grid, block,
                                           dst_plane_lds(p, true), st, p, nullptr, t2, nullptr, P,
-                                          ld, pcs, Pold, beta));
+                                          ld, pcs, Pold, beta, vs, wzp));
     }
     return hipGetLastError();
 }

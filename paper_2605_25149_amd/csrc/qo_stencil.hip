@@ -772,7 +772,73 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MODE == 1 && PPT == 3 ? 6 :
     if (threadIdx.x == 0) s.part[3 * qs + (long)col * tiles + tile] = ep.acc[0];
 }
 
-// x += alpha p; r -= alpha H p; partials r.D r (JAC: Jacobi form only) and r.r.
+// The first sweep's work for the FP32 PCG whose preconditioner pass has formed
+// p = z + beta p_old, without a pass over the grid: one block per column takes the stop
+// test, the iteration count and activity flag, rho = r.z (rzc, from the preconditioner), and
+// gamma = p.Hp from identities of the iteration:
+//   H p_old = (r_old - r) / alpha_old (the residual recurrence), z.r_old = 0 (successive
+//   residuals are M^{-1}-orthogonal), z.M z = r.z (z = M^{-1} r) and H - M = diag(w),
+//   w = V + sigma - vbar, so that
+//   gamma = rho + sum w z^2 - 2 beta rho / alpha_old + beta^2 gamma_old,
+// with sum w z^2 from the preconditioner's inverse pass (wzp, nslab per column) and
+// gamma_old = p_old.H p_old from the previous second sweep (partials in section 0).  The
+// identities hold up to the preconditioner's FP16 rounding (about 1e-3 relative), like
+// the spectral r.z; the second sweep's update uses gamma as given.  gamma is written to
+// slot 0 of the column's partials (the others zero), so the second sweep's reduction
+// returns it unchanged, and alpha = rho / gamma is kept for the next iteration.
+__global__ __launch_bounds__(kThreads) void k_pcg_gamma(int k, int ncols, double tol,
+                                                        const int *__restrict__ mask,
+                                                        PcgState s, long qs, int tiles,
+                                                        const double *__restrict__ rzc,
+                                                        const double *__restrict__ wzp,
+                                                        int nslab) {
+    __shared__ Red red;
+    const int col = blockIdx.x;
+    const int cur = k & 1, prv = cur ^ 1;
+    const int prev_active = (k == 0) ? (mask ? mask[col] : 1) : s.active[prv * ncols + col];
+    if (!prev_active) {
+        if (threadIdx.x == 0) s.active[cur * ncols + col] = 0;
+        return;
+    }
+    const double rr = col_sum(s.part + qs, col, tiles, red);
+    double bb;
+    if (k == 0) {
+        bb = col_sum(s.part + 2 * qs, col, tiles, red);
+        if (threadIdx.x == 0) s.bb[col] = bb;
+    } else {
+        bb = s.bb[col];
+    }
+    const double ctol = s.coltol ? s.coltol[col] : tol;
+    const bool conv = sqrt(rr) <= ctol * sqrt(bb);
+    const double wz = conv ? 0.0 : col_sum(wzp, col, nslab, red);
+    const double gold = (conv || k == 0) ? 0.0 : col_sum(s.part, col, tiles, red);
+    if (threadIdx.x == 0) {
+        const double rz = conv ? 0.0 : rzc[col];
+        int flag = 0;  // 0 run, 1 converged, 2 non-finite
+        if (!isfinite(rz) || !isfinite(rr) || !isfinite(bb)) flag = 2;
+        else if (conv) flag = 1;
+        s.its[col] = k;
+        s.active[cur * ncols + col] = flag == 0 ? 1 : 0;
+        if (flag == 2) {
+            atomicMax(&s.err[0], 7);
+            atomicMin(&s.err[1], col);
+        }
+        if (flag == 0) {
+            double gam = rz + wz;
+            if (k > 0) {
+                const double b = rz / s.rho[prv * ncols + col];
+                gam += -2.0 * b * rz / s.alpha[prv * ncols + col] + b * b * gold;
+            }
+            s.rho[cur * ncols + col] = rz;
+            s.alpha[cur * ncols + col] = rz / gam;
+            double *g = s.part + 3 * qs + (long)col * tiles;
+            g[0] = gam;
+            for (int t = 1; t < tiles; ++t) g[t] = 0.0;
+        }
+    }
+}
+
+// x += alpha p; r -= alpha H p; partials r.D r (JAC: Jacobi form; else p.Hp) and r.r.
 // x and r are each read and written once per sweep: non-temporal accesses keep
 // them from evicting the stencil operand's halo rows from the caches.
 // XZ: x is known to be zero (the first iteration of a solve that starts from x = 0 without
@@ -804,7 +870,10 @@ struct EpSweep2 {
         r[i] = ri;
 #endif
         const double rd = (double)ri;
+        // Jacobi form: r.D r; preconditioned form: p.Hp with the Hp of this update, the
+        // exact gamma of the iteration (the next one's gamma identity uses it)
         if (JAC) acc[0] += rd * (double)(e.d * ri);
+        else acc[0] += (double)c * (double)hv;
         acc[1] += rd * rd;
     }
 };
@@ -1085,6 +1154,16 @@ hipError_t launch_pcg_sweep1(const Grid &g, const T *vs, const T *dinv, const T 
                                                    g, vs, dinv, R, Pold, Pnew, ld, ncols, k, tol,
                                                    mask, s, qs, Z, rzp, rzt));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_gamma(const Grid &g, int k, int ncols, double tol, const int *mask,
+                            PcgState s, const double *rzc, const double *wzp, int nslab,
+                            hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    const long qs = (long)ncols * g.tiles();
+    hipLaunchKernelGGL(k_pcg_gamma, dim3(ncols), dim3(kThreads), 0, st, k, ncols, tol, mask, s, qs,
+                       g.tiles(), rzc, wzp, nslab);
     return hipGetLastError();
 }
 

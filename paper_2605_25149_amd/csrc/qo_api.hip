@@ -91,7 +91,7 @@ struct qo_ctx {
     float *z32 = nullptr;  // preconditioned residual z = M^{-1} r (FP32 in either precision)
     float *pbeta = nullptr;  // beta of the FP32 PCG, formed before the inverse plane pass
     double *rzc = nullptr;   // and r.z per column
-    double *wzp = nullptr;   // partial sums of (V + sigma - vbar) z^2 per column and slab
+    double *wzp = nullptr;   // partial sums of (V + sigma - vbar) z^2: per column, slab, wave
     double *rzp = nullptr, *dsum = nullptr;
     double mu0 = 0.0;  // mu_x[0] + mu_y[0] (+ mu_z[0]): smallest eigenvalue of -Lap_h
     // block CG (pcg_variant 2): Z and ping-pong partners of X, R, P; small matrices;
@@ -485,7 +485,8 @@ qo_status pcg(qo_ctx *c, const T *vs, const T *dinv, const T *B, T *X, T *R, T *
         else if (Z)
             QOC(precondition<T>(c, R, Z, ncols, k, tol, mask, s));
         if (pform) {
-            HIPC(c, launch_pcg_gamma(g, k, ncols, tol, mask, s, c->rzc, c->wzp, c->dp.nslab, st));
+            HIPC(c, launch_pcg_gamma(g, k, ncols, tol, mask, s, c->rzc, c->wzp,
+                                     c->dp.nslab * (c->dp.RP / 16), st));
         } else {
             hipEvent_t ea = prof_begin(c);
             HIPC(c, launch_pcg_sweep1<T>(g, vs, dinv, R, pbuf[(k + 1) & 1], pbuf[k & 1], c->ld,
@@ -1583,7 +1584,7 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
         A(&h->z32, blk);
         A(&h->pbeta, (size_t)N);
         A(&h->rzc, (size_t)N);
-        A(&h->wzp, (size_t)N * dp.nslab);
+        A(&h->wzp, (size_t)N * dp.nslab * (dp.RP / 16));
         if (s == QO_OK) {
             dp.Sx = h->dS;
             dp.Sy = h->dS + sx;

@@ -106,6 +106,23 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
     return v;
 }
 
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_move_d(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_lane63(double v) {
+    v += dpp_move_d<0xb1>(v);
+    v += dpp_move_d<0x4e>(v);
+    v += dpp_move_d<0x114>(v);
+    v += dpp_move_d<0x118>(v);
+    v += dpp_move_d<0x142, 0xa>(v);
+    v += dpp_move_d<0x143, 0xc>(v);
+    return v;
+}
+
 __device__ __forceinline__ v8h lds8(const _Float16 *p) {
     return *reinterpret_cast<const v8h *>(p);
 }
@@ -211,8 +228,8 @@ __host__ __device__ inline size_t dst_plane_xt_bytes(const DstPlan &p) {
 // FP32 3-D planes (NT <= 8) are held to 80 registers: 6 waves per SIMD, four 6-wave
 // workgroups per CU, as many as their LDS allows.
 // PF (inverse only): store the search direction P = z + beta[c] P_old (P = z when Pold is
-// null) instead of z, and the slab's partial sum of w z^2, w = V + sigma - vbar (vs holds
-// V + sigma per grid point), into wzp[c * nslab + slab].
+// null) instead of z, and the partial sums of w z^2, w = V + sigma - vbar (vs holds
+// V + sigma per grid point), one per wave: wzp[(c * nslab + slab) * RP / 16 + wave].
 template <typename T, bool INV, int NT, bool VEC, bool PF = false>
 __global__ __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_dst_plane(DstPlan p, const T *__restrict__ R,
@@ -225,7 +242,6 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
                                                    const float *__restrict__ vs = nullptr,
                                                    double *__restrict__ wzp = nullptr) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kMaxWaves];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int col = L / p.nslab;
     const int slab = L - col * p.nslab;
@@ -491,8 +507,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
                 wz += (double)((v4[q].x - vb) * z4.x * z4.x + (v4[q].y - vb) * z4.y * z4.y) +
                       (double)((v4[q].z - vb) * z4.z * z4.z + (v4[q].w - vb) * z4.w * z4.w);
             }
-            wz = block_sum(wz, red);
-            if (tid == 0) wzp[(long)col * p.nslab + slab] = wz;
+            wz = wave_sum_lane63(wz);
+            if ((tid & 63) == 63) wzp[((long)col * p.nslab + slab) * (nthr >> 6) + (tid >> 6)] = wz;
         } else {
             const bool first = !PF || Pold == nullptr;
             const float b = first ? 0.f : beta[col];
@@ -522,8 +538,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
                 }
             }
             if constexpr (PF) {
-                wz = block_sum(wz, red);
-                if (tid == 0) wzp[(long)col * p.nslab + slab] = wz;
+                wz = wave_sum_lane63(wz);
+                if ((tid & 63) == 63)
+                    wzp[((long)col * p.nslab + slab) * (nthr >> 6) + (tid >> 6)] = wz;
             }
         }
     }

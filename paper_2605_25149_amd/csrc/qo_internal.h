@@ -98,11 +98,12 @@ hipError_t launch_rho_beta(int k, int ncols, const float *pcs, const double *rzp
 hipError_t launch_dst_inv_p(const DstPlan &p, const _Float16 *t2, const float *Pold,
                             const float *beta, float *P, long ld, int ncols, const float *pcs,
                             const float *vs, double *wzp, hipStream_t st);
-// ... and, with the inverse pass's partials wzp of sum (V + sigma - vbar) z^2, the first
+// ... and, with the inverse pass's partials wzp of sum (V + sigma - vbar) z^2 (nwz per
+// column), the first
 // sweep's bookkeeping and gamma = p.Hp from the identities of the iteration, one block per
 // column, no pass over the grid (qo_stencil.hip).
 hipError_t launch_pcg_gamma(const Grid &g, int k, int ncols, double tol, const int *mask,
-                            PcgState s, const double *rzc, const double *wzp, int nslab,
+                            PcgState s, const double *rzc, const double *wzp, int nwz,
                             hipStream_t st);
 // Z (FP64) = Z32 for the columns with pcs[c] != 0, zero elsewhere.
 hipError_t launch_z_expand(const float *Z32, const float *pcs, double *Z, long ld, long ng,

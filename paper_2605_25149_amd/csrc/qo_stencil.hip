@@ -780,7 +780,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MODE == 1 && PPT == 3 ? 6 :
 //   residuals are M^{-1}-orthogonal), z.M z = r.z (z = M^{-1} r) and H - M = diag(w),
 //   w = V + sigma - vbar, so that
 //   gamma = rho + sum w z^2 - 2 beta rho / alpha_old + beta^2 gamma_old,
-// with sum w z^2 from the preconditioner's inverse pass (wzp, nslab per column) and
+// with sum w z^2 from the preconditioner's inverse pass (wzp, nslab partials per column) and
 // gamma_old = p_old.H p_old from the previous second sweep (partials in section 0).  The
 // identities hold up to the preconditioner's FP16 rounding (about 1e-3 relative), like
 // the spectral r.z; the second sweep's update uses gamma as given.  gamma is written to

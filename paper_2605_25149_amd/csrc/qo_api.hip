@@ -66,7 +66,11 @@ struct qo_ctx {
     // reductions and small matrices
     double *part = nullptr;
     double *gpart = nullptr;
-    __bf16 *zb = nullptr;  // BF16 copy of [X | Y] for the mixed-precision Gram
+    // BF16 copies of the Gram operands (mixed precision): U (written by the corrector, or
+    // packed when it has changed otherwise), U_hat (written by its update) and the solution
+    // block of the current Gram (packed)
+    __bf16 *zbU = nullptr, *zbUh = nullptr, *zbPQ = nullptr;
+    bool zbU_ok = false;  // zbU holds U rounded to BF16
     int gnsplit = 1;
     double *G1 = nullptr, *G2 = nullptr;
     double *mpool = nullptr;
@@ -1040,21 +1044,30 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
     return QO_OK;
 }
 
+// Grams of [X | Y]; in a step [U | P] and [U_hat | Q].  Mixed precision takes the BF16
+// copies of U and U_hat that their producers wrote (U is packed if it has changed otherwise
+// since) and packs the solution block; any other X is packed into the U_hat copy, which
+// only the step's own U_hat update fills before its Gram.
 qo_status gram(qo_ctx *c, const double *X, const double *Y, long ld, int n, double *G) {
     hipEvent_t e = prof_begin(c);
-    if (c->mixed)
-        HIPC(c, launch_gram_bf16(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G, c->zb, c->st));
-    else
+    if (c->mixed) {
+        const bool xu = X == c->U && n == c->N, xh = X == c->Uh && n == c->N;
+        HIPC(c, launch_gram_bf16(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G,
+                                 xu ? c->zbU : c->zbUh, c->zbPQ, !xh && !(xu && c->zbU_ok), true,
+                                 c->st));
+        if (xu) c->zbU_ok = true;
+    } else
         HIPC(c, launch_gram_f64(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G, c->st));
     prof_end(c, QO_KERNEL_GRAM, e);
     return QO_OK;
 }
 
-// fp32: the FP32-arithmetic update of the mixed-precision step (see launch_tsgemm)
+// fp32: the FP32-arithmetic update of the mixed-precision step (see launch_tsgemm); zb
+// receives its BF16 copy
 qo_status tsgemm(qo_ctx *c, double *Out, const double *C0, const double *A, const double *Xr,
-                 const double *Bm, const double *Yr, bool fp32 = false) {
+                 const double *Bm, const double *Yr, bool fp32 = false, __bf16 *zb = nullptr) {
     hipEvent_t e = prof_begin(c);
-    HIPC(c, launch_tsgemm(Out, c->ld, C0, A, Xr, Bm, Yr, c->ld, c->ng, c->N, c->st, fp32));
+    HIPC(c, launch_tsgemm(Out, c->ld, C0, A, Xr, Bm, Yr, c->ld, c->ng, c->N, c->st, fp32, zb));
     prof_end(c, QO_KERNEL_UPDATE, e);
     return QO_OK;
 }
@@ -1255,7 +1268,8 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
     HIPC(c, hipEventRecord(c->sev, st));
     rec(c, 3);
     // QO_MIXED: the block updates in FP32 arithmetic (the Grams of that path are BF16)
-    QOC(tsgemm(c, c->Uh, nullptr, c->U, mp(c, MP_XR), P, mp(c, MP_YR), c->mixed));
+    QOC(tsgemm(c, c->Uh, nullptr, c->U, mp(c, MP_XR), P, mp(c, MP_YR), c->mixed,
+               c->mixed ? c->zbUh : nullptr));
     if (warm) QOC(tsgemm(c, Q, nullptr, P, mp(c, MP_ZR), nullptr, nullptr, c->mixed));
     rec(c, 4);
     const qo_status sQ = solve_block(c, c->Uh, Q, N, warm, itsQ.data(), &rQ, "solve G U_hat");
@@ -1283,7 +1297,10 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
                         st));
         HIPC(c, nn_fro(On, N, N, c->dscal + 2, st));
     }
-    QOC(tsgemm(c, c->U, c->Uh, nullptr, nullptr, Q, mp(c, MP_OR), c->mixed));
+    c->zbU_ok = false;
+    QOC(tsgemm(c, c->U, c->Uh, nullptr, nullptr, Q, mp(c, MP_OR), c->mixed,
+               c->mixed ? c->zbU : nullptr));
+    c->zbU_ok = c->mixed;
     rec(c, 7);
     // the state has moved: commit bookkeeping before the (non-failing) diagnostics
     c->lastP = P;
@@ -1542,7 +1559,11 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
     A(&h->part, (size_t)8 * h->qsmax);
     h->gnsplit = gram_nsplit(h->ng, N);
     A(&h->gpart, gram_part_elems(N, h->gnsplit));
-    if (h->mixed) A(&h->zb, 2 * blk);
+    if (h->mixed) {
+        A(&h->zbU, blk);
+        A(&h->zbUh, blk);
+        A(&h->zbPQ, blk);
+    }
     A(&h->G1, (size_t)4 * N * N);
     A(&h->G2, (size_t)4 * N * N);
     A(&h->mpool, (size_t)MP_COUNT * N * N);
@@ -1686,6 +1707,7 @@ qo_status qo_set_potential(qo_handle h, const double *V, int on_device) {
 qo_status qo_set_state(qo_handle h, const double *U, long ld, int on_device) {
     if (!h) return QO_ERR_ARG;
     if (!U || ld < h->ng) return fail(h, QO_ERR_ARG, "bad state pointer or ld");
+    h->zbU_ok = false;
     QOC(copy_block_in(h, h->U, U, ld, on_device));
     HIPC(h, hipMemsetAsync(h->dstatus, 0, sizeof(int), h->st));
     long blocks = (h->ng + 255) / 256;
@@ -1763,6 +1785,7 @@ qo_status qo_run(qo_handle h, double tau, double tau_max, int max_steps, double 
             // undo: U_n back, its G U_n (in PQ[cur0]) stays the warm start
             HIPC(h, hipMemcpyAsync(h->U, h->W2, sizeof(double) * h->ld * h->N,
                                    hipMemcpyDeviceToDevice, h->st));
+            h->zbU_ok = false;
             HIPC(h, hipStreamSynchronize(h->st));
             h->cur = cur0;
             h->have_warm = ss == QO_OK ? true : warm0;
@@ -2198,11 +2221,13 @@ qo_status qo_tape_backward(qo_handle h, double seed, double *gV, double *gU0, lo
     auto body = [&]() -> qo_status {
         double L = 0.0;
         HIPC(h, hipMemcpyAsync(h->U, h->tape[K], bytes, hipMemcpyDeviceToDevice, st));
+        h->zbU_ok = false;
         QOC(loss_and_grad(h, h->tape_loss, &L, true, seed));
         for (int n = K - 1; n >= 0; --n) {
             double *Un = h->tape[n];
             // recompute step n (cold solves: the same arithmetic as the taped forward)
             HIPC(h, hipMemcpyAsync(h->U, Un, bytes, hipMemcpyDeviceToDevice, st));
+            h->zbU_ok = false;
             h->have_warm = false;
             QOC(one_step(h, tau, nullptr));
             const double *P = h->lastP, *Q = h->lastQ, *Uh = h->Uh;
@@ -2263,6 +2288,7 @@ qo_status qo_tape_backward(qo_handle h, double seed, double *gV, double *gU0, lo
                                    on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                                    st));
         HIPC(h, hipMemcpyAsync(h->U, h->tape[K], bytes, hipMemcpyDeviceToDevice, st));
+        h->zbU_ok = false;
         HIPC(h, hipStreamSynchronize(st));
         return QO_OK;
     };

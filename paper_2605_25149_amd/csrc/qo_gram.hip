@@ -15,6 +15,7 @@
 //   BF16: v_mfma_f32_16x16x32_bf16, R = 8, inputs rounded to nearest-even
 //         from FP64, FP32 accumulation within a chunk, FP64 across chunks.
 #include "qo_internal.h"
+#include "qo_device.h"
 
 #include <type_traits>
 
@@ -42,23 +43,7 @@ __device__ __forceinline__ const double *zcol(const double *X, const double *Y, 
     return c < n ? X + (long)c * ld : Y + (long)(c - n) * ld;
 }
 
-// Round an FP64 value to bfloat16, nearest-even on the 45 dropped mantissa
-// bits (one rounding, no FP32 intermediate).  Magnitudes below the FP32
-// normal range flush to signed zero; beyond it saturate to infinity.
-__device__ __forceinline__ __bf16 f64_to_bf16_rne(double d) {
-    // Straight-line form: the rounded magnitude's bits 45..59 are the exponent and the
-    // 7 kept mantissa bits; rebiased to BF16, values below its normal range go to zero
-    // and values beyond it (infinity included) to infinity; NaN becomes the quiet NaN.
-    const unsigned long long b = __double_as_longlong(d);
-    const unsigned long long mag =
-        (b & 0x7fffffffffffffffull) + 0xfffffffffffull + ((b >> 45) & 1ull);
-    int v = (int)(unsigned int)(mag >> 45) - ((1023 - 127) << 7);
-    v = v < 0x80 ? 0 : v;
-    v = min(v, 0x7f80);
-    v = __builtin_isnan(d) ? 0x7fc0 : v;
-    const unsigned int s16 = (unsigned int)(b >> 48) & 0x8000u;
-    return __builtin_bit_cast(__bf16, (unsigned short)(s16 | (unsigned int)v));
-}
+using dev::f64_to_bf16_rne;
 
 // Decode the upper-triangular tile pair index.
 __device__ __forceinline__ void tile_pair(int p, int nt, int &ti, int &tj) {
@@ -249,18 +234,17 @@ __global__ __launch_bounds__(64) void k_gram_f64_batch(const GramJob *__restrict
                   split);
 }
 
-// Z = [X | Y] rounded to BF16 once: Zb[c * ld + r] for r < ld (rows ng..ld-1 zero), so
-// the Gram kernel reads whole 32-row steps with 16-byte loads and converts nothing.
-__global__ __launch_bounds__(256) void k_pack_bf16(const double *__restrict__ X,
-                                                   const double *__restrict__ Y, long ld,
+// One FP64 block rounded to BF16: Zb[c * ld + r] for r < ld (rows ng..ld-1 zero), so the
+// Gram kernel reads whole 32-row steps with 16-byte loads and converts nothing.
+__global__ __launch_bounds__(256) void k_pack_bf16(const double *__restrict__ X, long ld,
                                                    long ng, int n, __bf16 *__restrict__ Zb) {
     const long per_col = ld / 8;
-    const long total = 2L * n * per_col;
+    const long total = (long)n * per_col;
     for (long it = (long)blockIdx.x * blockDim.x + threadIdx.x; it < total;
          it += (long)gridDim.x * blockDim.x) {
         const int c = (int)(it / per_col);
         const long r = (it - (long)c * per_col) * 8;
-        const double *src = zcol(X, Y, ld, n, c) + r;
+        const double *src = X + (long)c * ld + r;
         double v[8];
         if (r + 8 <= ng) {
 #pragma unroll
@@ -280,7 +264,7 @@ __global__ __launch_bounds__(256) void k_pack_bf16(const double *__restrict__ X,
     }
 }
 
-// Gram tiles from the packed BF16 block, 256-column super-tiles: one 1024-thread
+// Gram tiles of [X | Y] from the BF16 copies ZX of X and ZY of Y, 256-column super-tiles: one 1024-thread
 // workgroup per (super-tile pair, K-chunk) stages each 32-row step of its two super-tiles
 // in LDS (each thread copies 16 rows of one column), and its 16 waves each run the 16
 // MFMAs of one 64 x 64 tile pair from LDS.  A column is fetched by the super-tile pairs it
@@ -288,7 +272,8 @@ __global__ __launch_bounds__(256) void k_pack_bf16(const double *__restrict__ X,
 // loads are in flight beyond the one in LDS.
 constexpr int kSuper = 256;  // columns per super-tile
 
-__global__ __launch_bounds__(1024) void k_gram_bf16_super(const __bf16 *__restrict__ Zb, long ld,
+__global__ __launch_bounds__(1024) void k_gram_bf16_super(const __bf16 *__restrict__ ZX,
+                                                          const __bf16 *__restrict__ ZY, long ld,
                                                           long ng, int n, long kchunk,
                                                           double *__restrict__ part) {
     // [buffer][super-tile a/b][column][32 rows]: a column's step is 64 bytes
@@ -300,7 +285,7 @@ __global__ __launch_bounds__(1024) void k_gram_bf16_super(const __bf16 *__restri
     const int split = L / nsp;
     int TI, TJ;
     tile_pair(L - split * nsp, nst, TI, TJ);
-    // rows ng..ld-1 of Zb are zero and ld is a multiple of 64: whole 32-row steps
+    // rows ng..ld-1 of ZX and ZY are zero and ld is a multiple of 64: whole 32-row steps
     const long kb = (long)split * kchunk;
     const long ke = min(ld, (min(ng, kb + kchunk) + 31) / 32 * 32);
     const int nsteps = ke > kb ? (int)((ke - kb) >> 5) : 0;
@@ -315,7 +300,8 @@ __global__ __launch_bounds__(1024) void k_gram_bf16_super(const __bf16 *__restri
     {
         const int c = (lt ? TJ : TI) * kSuper + lc;
         // columns past 2n read column 0: their products reach only entries never stored
-        src = (gv8bf *)(Zb + (long)(c < nn ? c : 0) * ld + kb + 16 * lh);
+        const __bf16 *col = c < n ? ZX + (long)c * ld : c < nn ? ZY + (long)(c - n) * ld : ZX;
+        src = (gv8bf *)(col + kb + 16 * lh);
     }
     // steps past the end re-read the last one (their values are never stored)
     auto gload = [&](int s, v8bf (&r)[2]) {
@@ -511,26 +497,33 @@ hipError_t launch_gram_cross_f64(const double *X, const double *Y, long ld, long
 }
 
 hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, int n, double w,
-                            double *part, int nsplit, double *G, __bf16 *zb, hipStream_t st) {
+                            double *part, int nsplit, double *G, __bf16 *zx, __bf16 *zy,
+                            bool pack_x, bool pack_y, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    // packed rows are read in whole 32-row steps of 16-byte loads: ld a multiple of 32,
+    // BF16 rows are read in whole 32-row steps of 16-byte loads: ld a multiple of 32,
     // 16-byte aligned operands
     if (ld % 32 != 0 || (reinterpret_cast<uintptr_t>(X) & 15) || (reinterpret_cast<uintptr_t>(Y) & 15) ||
-        (reinterpret_cast<uintptr_t>(zb) & 15))
+        (reinterpret_cast<uintptr_t>(zx) & 15) || (reinterpret_cast<uintptr_t>(zy) & 15))
         return hipErrorInvalidValue;
-    const long items = 2L * n * (ld / 8);
+    const long items = (long)n * (ld / 8);
     long blocks = (items + 255) / 256;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)blocks), dim3(256), 0, st, X, Y, ld, ng, n, zb);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (pack_x) {
+        hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)blocks), dim3(256), 0, st, X, ld, ng, n, zx);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (pack_y) {
+        hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)blocks), dim3(256), 0, st, Y, ld, ng, n, zy);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     // one 1024-thread workgroup per CU: enough K-chunks for one round over 256 CUs
     const int nst = (2 * n + kSuper - 1) / kSuper;
     const int nsp = nst * (nst + 1) / 2;
     nsplit = max(1, min(nsplit, 256 / nsp));
     long kchunk = (ng + nsplit - 1) / nsplit;
     kchunk = (kchunk + 31) / 32 * 32;
-    hipLaunchKernelGGL(k_gram_bf16_super, dim3(nsp, nsplit), dim3(1024), 0, st, zb, ld, ng, n,
+    hipLaunchKernelGGL(k_gram_bf16_super, dim3(nsp, nsplit), dim3(1024), 0, st, zx, zy, ld, ng, n,
                        kchunk, part);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -194,12 +194,13 @@ hipError_t launch_gram_cross_f64(const double *X, const double *Y, long ld, long
                                  double w, double *part, int nsplit, double *G, hipStream_t st);
 hipError_t launch_gram_f64(const double *X, const double *Y, long ld, long ng, int n,
                            double w, double *part, int nsplit, double *G, hipStream_t st);
-// BF16 tiles: [X Y] is first rounded to BF16 into zb (2n x ld, 16-byte aligned, ld a
-// multiple of 32; rows ng..ld-1 zero), then 256-column super-tile pairs accumulate in FP32
-// per K-chunk.
+// BF16 tiles from the BF16 copies zx of X and zy of Y (n x ld each, 16-byte aligned, ld a
+// multiple of 32; rows ng..ld-1 zero): 256-column super-tile pairs accumulate in FP32 per
+// K-chunk.  pack_x / pack_y: round that block into its copy first (false where its
+// producer has already written the copy).
 hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, int n,
-                            double w, double *part, int nsplit, double *G, __bf16 *zb,
-                            hipStream_t st);
+                            double w, double *part, int nsplit, double *G, __bf16 *zx,
+                            __bf16 *zy, bool pack_x, bool pack_y, hipStream_t st);
 
 // Grouped batches: one Gram per job (instance), FP64 MFMA; part holds nsplit x (2n)^2
 // doubles of the job; max_grid >= gram_pairs(n) * nsplit over the jobs.
@@ -267,10 +268,12 @@ struct TsJob {
 hipError_t launch_tsgemm_batch(const TsJob *jobs, int njobs, int max_n, long ld, long ng,
                                hipStream_t st);
 // fp32: FP32 MFMA arithmetic (operands rounded to FP32, FP32 accumulation, C0 added in
-// FP64), for the mixed-precision path.
+// FP64), for the mixed-precision path; there Zb (optional) receives Out rounded to BF16
+// (nearest-even from the stored FP64 value, same layout as Out).
 hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
                          const double *XsT, const double *B, const double *YsT, long ld,
-                         long ng, int n, hipStream_t st, bool fp32 = false);
+                         long ng, int n, hipStream_t st, bool fp32 = false,
+                         __bf16 *Zb = nullptr);
 
 // ---- small dense FP64 (qo_small.hip), all column-major with explicit ld ----
 // C = alpha op(A) op(B) + beta C + gamma I

@@ -11,7 +11,7 @@
 // values per column.  The small operand is passed row-major (Xr[k*n + i] =
 // Xs[k][i]) so that its loads are contiguous too.  One wavefront computes a
 // 64 (grid rows) x 64 (columns) tile.
-#include "qo_internal.h"
+#include "qo_device.h"
 
 #ifndef QO_TSG_KSC
 #define QO_TSG_KSC 2
@@ -165,7 +165,7 @@ __device__ __forceinline__ void tsgemm32_tile(double *__restrict__ Out, long ldo
                                               const double *__restrict__ Xr,
                                               const double *__restrict__ B,
                                               const double *__restrict__ Yr, long ld, long ng,
-                                              int n, long m0, int c0) {
+                                              int n, long m0, int c0, __bf16 *__restrict__ Zb) {
     const int lane = threadIdx.x;
     const int lr = lane & 15, lg = lane >> 4;
 
@@ -275,7 +275,11 @@ __device__ __forceinline__ void tsgemm32_tile(double *__restrict__ Out, long ldo
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int c = c0 + 16 * j + 4 * lg + v;
-                if (c < n) Out[(long)c * ldo + m] = c0v[j][i][v] + (double)acc[j][i][v];
+                if (c < n) {
+                    const double o = c0v[j][i][v] + (double)acc[j][i][v];
+                    Out[(long)c * ldo + m] = o;
+                    if (Zb) Zb[(long)c * ldo + m] = dev::f64_to_bf16_rne(o);
+                }
             }
         }
 }
@@ -283,11 +287,11 @@ __device__ __forceinline__ void tsgemm32_tile(double *__restrict__ Out, long ldo
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_tsgemm32(
     double *__restrict__ Out, long ldo, const double *__restrict__ C0,
     const double *__restrict__ A, const double *__restrict__ Xr, const double *__restrict__ B,
-    const double *__restrict__ Yr, long ld, long ng, int n) {
+    const double *__restrict__ Yr, long ld, long ng, int n, __bf16 *__restrict__ Zb) {
     const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int rt = L / gridDim.y;
     tsgemm32_tile(Out, ldo, C0, A, Xr, B, Yr, ld, ng, n, (long)rt * 64,
-                  (L - rt * gridDim.y) * 64);
+                  (L - rt * gridDim.y) * 64, Zb);
 }
 
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_tsgemm(double *__restrict__ Out, long ldo,
@@ -324,15 +328,17 @@ hipError_t launch_tsgemm_batch(const TsJob *jobs, int njobs, int max_n, long ld,
 
 hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
                          const double *Xr, const double *B, const double *Yr, long ld, long ng,
-                         int n, hipStream_t st, bool fp32) {
+                         int n, hipStream_t st, bool fp32, __bf16 *Zb) {
     if (n <= 0 || ng <= 0) return hipSuccess;
-    // each big operand needs its small operand (and the reverse)
-    if ((A == nullptr) != (Xr == nullptr) || (B == nullptr) != (Yr == nullptr) || !Out)
+    // each big operand needs its small operand (and the reverse); a BF16 copy only from the
+    // FP32 kernel
+    if ((A == nullptr) != (Xr == nullptr) || (B == nullptr) != (Yr == nullptr) || !Out ||
+        (Zb && !fp32))
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)((ng + 63) / 64), (unsigned)((n + 63) / 64));
     if (fp32)
         hipLaunchKernelGGL(k_tsgemm32, grid, dim3(64), 0, st, Out, ldo, C0, A, Xr, B, Yr, ld, ng,
-                           n);
+                           n, Zb);
     else
         hipLaunchKernelGGL(k_tsgemm, grid, dim3(64), 0, st, Out, ldo, C0, A, Xr, B, Yr, ld, ng, n);
     return hipGetLastError();

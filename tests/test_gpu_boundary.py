@@ -137,3 +137,57 @@ def test_grad_norm_closed_form(torch, B):
         s.set_state(U)
         st = s.step(0.5 * lam[0])
     assert abs(st["grad_norm"] - ref) <= 1e-9 * ref, (st["grad_norm"], ref)
+
+
+def _bf16_gram_ok(G, ref, diag_a, diag_b):
+    """Entry-wise bound of a Gram of BF16-rounded blocks: each product of two rounded
+    values is within 2^-8 (relative) of the exact one, so the sum is within
+    2^-8 |u| |v| <= 2^-8 sqrt(G_aa G_bb); 5e-3 leaves room for the FP32 accumulation."""
+    scale = np.sqrt(np.outer(diag_a, diag_b))
+    return np.all(np.abs(G - ref) <= 5e-3 * scale)
+
+
+def test_mixed_gram_operands_follow_the_state(torch, B, oracle_mod):
+    """Mixed precision takes the BF16 copy of U that the previous step's corrector wrote.
+    After qo_set_state and after an undone adaptive step (Algorithm 1's halving of tau) the
+    copy no longer matches U and must be replaced: S = <U,U> and M = <U,P> of the next step
+    are checked against the oracle's inner products of the state that step started from
+    (BF16 bound as in the full-size test)."""
+    n, N = (13, 11, 10), 5
+    V = inputs.gaussian_wells(n, seed=0)
+    prob = oracle_mod.Problem(3, n, V)
+    with B.Solver(3, n, N, precision="mixed", pcg_tol=1e-10) as s:
+        s.set_potential(V)
+        s.set_state(inputs.random_block(int(np.prod(n)), N, seed=1))
+        s.step(5.0, 3)
+        U1 = inputs.random_block(int(np.prod(n)), N, seed=5)
+        s.set_state(U1)
+        s.step(5.0)
+        P = B.to_numpy(s.get_block("P"))
+        S, M = s.get_matrix("S"), s.get_matrix("M")
+    S_ref, M_ref, R_ref = prob.inner(U1, U1), prob.inner(U1, P), prob.inner(P, P)
+    assert _bf16_gram_ok(S, S_ref, np.diag(S_ref), np.diag(S_ref))
+    assert _bf16_gram_ok(M, M_ref, np.diag(S_ref), np.diag(R_ref))
+
+    # adaptive steps from tau = 3 lambda_1: energy rises are undone and tau halved
+    n2, N2 = (32, 32), 4
+    V2 = inputs.harmonic(n2, 100.0)
+    prob2 = oracle_mod.Problem(2, n2, V2)
+    lam1 = 12.9544687
+    undone = taken = 0
+    with B.Solver(2, n2, N2, precision="mixed", pcg_tol=1e-10) as s:
+        s.set_potential(V2)
+        s.set_state(inputs.random_block(1024, N2, seed=1))
+        tau = 3.0 * lam1
+        for _ in range(12):
+            Ub = B.to_numpy(s.get_state())
+            k, tau_out, conv, _st = s.run(tau, 1, grad_tol=1e-12, tau_max=3.0 * lam1)
+            if tau_out < tau:
+                undone += 1
+            if k:
+                taken += 1
+                S = s.get_matrix("S")
+                S_ref = prob2.inner(Ub, Ub)
+                assert _bf16_gram_ok(S, S_ref, np.diag(S_ref), np.diag(S_ref))
+            tau = tau_out
+    assert taken > 0 and undone > 0, (taken, undone)

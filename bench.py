@@ -422,14 +422,18 @@ def run_batch(count, steps, log, precisions=("fp64", "mixed")):
                 b.set_state(i, inputs.random_block(p["n"][0] * p["n"][1], p["N"], seed=1000 + i))
             out["tiles"] = {str(p["n"][0]): b.tile(i) for i, p in enumerate(probs)}
             for mode in ("eager", "graph"):
-                b.step(taus, nsteps=2, use_graph=mode == "graph")  # both P/Q parities
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                st = b.step(taus, nsteps=steps, use_graph=mode == "graph")
-                dt = time.perf_counter() - t0
-                res[f"{mode}_instance_steps_per_s"] = round(count * steps / dt, 2)
+                # warm-up: both P/Q parities, and time for the fixed iteration counts to
+                # settle (a change re-captures the graphs); the statistics of the last
+                # warm-up step give the counts
+                st = b.step(taus, nsteps=4, use_graph=mode == "graph")
                 res["max_pcg_iters"] = max(max(x["pcg_iters"]) for x in st)
                 res["max_refine_rounds"] = max(max(x["refine_rounds"]) for x in st)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                # no per-step statistics: the host waits only at the end (error checks)
+                b.step(taus, nsteps=steps, use_graph=mode == "graph", stats=False)
+                dt = time.perf_counter() - t0
+                res[f"{mode}_instance_steps_per_s"] = round(count * steps / dt, 2)
                 log(f"[batch {prec} {mode}] {count} instances, {steps} steps: "
                     f"{dt / steps * 1e3:.1f} ms/step")
         finally:
@@ -458,8 +462,9 @@ def run_batch(count, steps, log, precisions=("fp64", "mixed")):
         finally:
             for s in sol:
                 s.close()
-        res["speedup_vs_sequential"] = round(res["eager_instance_steps_per_s"] /
-                                             res["sequential_instance_steps_per_s"], 3)
+        res["speedup_vs_sequential"] = round(
+            max(res["eager_instance_steps_per_s"], res["graph_instance_steps_per_s"]) /
+            res["sequential_instance_steps_per_s"], 3)
         out[prec] = res
     return out
 
@@ -526,7 +531,7 @@ def main():
                     help="mixed-vs-FP64 eigenvalue gate over this many steps (0: skip)")
     ap.add_argument("--batch-instances", type=int, default=128,
                     help="also time a grouped batch of this many 2-D problems (0: skip)")
-    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-precisions", default="fp64,mixed")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batch leg and print its JSON (profiling aid)")

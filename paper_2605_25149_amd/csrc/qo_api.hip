@@ -70,6 +70,7 @@ struct qo_ctx {
     // packed when it has changed otherwise), U_hat (written by its update) and the solution
     // block of the current Gram (packed)
     __bf16 *zbU = nullptr, *zbUh = nullptr, *zbPQ = nullptr;
+    __bf16 *split3 = nullptr;  // BF16 parts of the block update's small operands (mixed)
     bool zbU_ok = false;  // zbU holds U rounded to BF16
     int gnsplit = 1;
     double *G1 = nullptr, *G2 = nullptr;
@@ -1067,7 +1068,8 @@ qo_status gram(qo_ctx *c, const double *X, const double *Y, long ld, int n, doub
 qo_status tsgemm(qo_ctx *c, double *Out, const double *C0, const double *A, const double *Xr,
                  const double *Bm, const double *Yr, bool fp32 = false, __bf16 *zb = nullptr) {
     hipEvent_t e = prof_begin(c);
-    HIPC(c, launch_tsgemm(Out, c->ld, C0, A, Xr, Bm, Yr, c->ld, c->ng, c->N, c->st, fp32, zb));
+    HIPC(c, launch_tsgemm(Out, c->ld, C0, A, Xr, Bm, Yr, c->ld, c->ng, c->N, c->st, fp32, zb,
+                          fp32 ? c->split3 : nullptr));
     prof_end(c, QO_KERNEL_UPDATE, e);
     return QO_OK;
 }
@@ -1563,6 +1565,7 @@ qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out) {
         A(&h->zbU, blk);
         A(&h->zbUh, blk);
         A(&h->zbPQ, blk);
+        A(&h->split3, tsgemm_split_elems(N));
     }
     A(&h->G1, (size_t)4 * N * N);
     A(&h->G2, (size_t)4 * N * N);

@@ -267,13 +267,16 @@ struct TsJob {
 };
 hipError_t launch_tsgemm_batch(const TsJob *jobs, int njobs, int max_n, long ld, long ng,
                                hipStream_t st);
-// fp32: FP32 MFMA arithmetic (operands rounded to FP32, FP32 accumulation, C0 added in
-// FP64), for the mixed-precision path; there Zb (optional) receives Out rounded to BF16
-// (nearest-even from the stored FP64 value, same layout as Out).
+// fp32: FP32-accurate arithmetic (operands rounded to FP32, FP32 accumulation, C0 added
+// in FP64) on BF16 MFMA with each operand split into three BF16 parts, for the
+// mixed-precision path; needs `split` (tsgemm_split_elems(n) BF16 of scratch).  There Zb
+// (optional) receives Out rounded to BF16 (nearest-even from the stored FP64 value, same
+// layout as Out).
+size_t tsgemm_split_elems(int n);
 hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
                          const double *XsT, const double *B, const double *YsT, long ld,
                          long ng, int n, hipStream_t st, bool fp32 = false,
-                         __bf16 *Zb = nullptr);
+                         __bf16 *Zb = nullptr, __bf16 *split = nullptr);
 
 // ---- small dense FP64 (qo_small.hip), all column-major with explicit ld ----
 // C = alpha op(A) op(B) + beta C + gamma I

@@ -2,8 +2,8 @@
 //   predictor   U_hat = U X + P Y          (P = G U_n)
 //   warm start  x0    = P (X + C Y)        for the solve G U_hat
 //   corrector   U_{n+1} = U_hat + Q (-tau O)   (Q = G U_hat, O = <U_hat,U_hat> - I)
-// as one FP64 MFMA kernel Out = C0 + A Xs + B Ys (Ng x n), with an FP32-arithmetic twin
-// for the mixed-precision path.
+// as one FP64 MFMA kernel Out = C0 + A Xs + B Ys (Ng x n), with an FP32-accurate twin on
+// BF16 MFMA (three-part operand split) for the mixed-precision path.
 //
 // Computed transposed, Out^T = Xs^T A^T + Ys^T B^T, so that the MFMA output
 // rows run along the grid: lane l of a 16x16 block owns grid row m0 + l%16 of
@@ -12,6 +12,8 @@
 // Xs[k][i]) so that its loads are contiguous too.  One wavefront computes a
 // 64 (grid rows) x 64 (columns) tile.
 #include "qo_device.h"
+
+#include <algorithm>
 
 #ifndef QO_TSG_KSC
 #define QO_TSG_KSC 2
@@ -153,121 +155,232 @@ __device__ __forceinline__ void tsgemm_tile(double *__restrict__ Out, long ldo,
         }
 }
 
-// The same tile in FP32 arithmetic: operands rounded from FP64 to FP32 as they enter the
-// MFMA (v_mfma_f32_16x16x4f32, twice the FP64 rate), FP32 accumulation, and C0 added in FP64
-// when the tile is stored.  The prefetch keeps FP64 values, converted at their use, so
-// that no conversion waits for a load still in flight.  Used by the mixed-precision path,
-// whose Gram matrices are BF16: an FP32 block update (relative error ~1e-7 per entry, like
-// the FP32 PCG) is well inside what that path tolerates.
-__device__ __forceinline__ void tsgemm32_tile(double *__restrict__ Out, long ldo,
-                                              const double *__restrict__ C0,
-                                              const double *__restrict__ A,
-                                              const double *__restrict__ Xr,
-                                              const double *__restrict__ B,
-                                              const double *__restrict__ Yr, long ld, long ng,
-                                              int n, long m0, int c0, __bf16 *__restrict__ Zb) {
-    const int lane = threadIdx.x;
-    const int lr = lane & 15, lg = lane >> 4;
+// ---- FP32-accurate update on BF16 MFMA (mixed-precision path) --------------------------
+//
+// Every operand value is rounded to FP32 and split exactly into three BF16 parts,
+// a = a1 + a2 + a3 (8 significant bits each; an FP32 significand has 24).  Of the nine
+// part products, the six with a_i b_j, i + j <= 4, are accumulated (the others are below
+// 2^-24 |a b|); BF16 products are exact in the FP32 accumulator, so the result carries
+// FP32 input rounding and FP32 accumulation like an FP32 product, at six BF16 MFMAs
+// (16 cycles each per 32 k-values) instead of eight FP32 ones (32 cycles per 4).
 
-    v4f acc[4][4];  // [column block j][row block i]
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+// f = b1 + b2 + b3 exactly, each part rounded to nearest-even from what is left
+__device__ __forceinline__ void split3(float f, __bf16 &b1, __bf16 &b2, __bf16 &b3) {
+    __asm__("" : "+v"(f));  // see split3_pair
+    b1 = (__bf16)f;
+    const float r1 = f - (float)b1;
+    b2 = (__bf16)r1;
+    b3 = (__bf16)(r1 - (float)b2);
+}
+
+// Two FP64 values rounded to FP32 and split, with the packed FP32 -> BF16 conversion (one
+// instruction per pair and part).  The empty asm keeps the FP32 rounding a separate step:
+// the compiler would otherwise fuse it with the first BF16 rounding into one double ->
+// bfloat16 conversion, which needs a dozen instructions per value.
+__device__ __forceinline__ void split3_pair(double x0, double x1, v2bf &h1, v2bf &h2,
+                                            v2bf &h3) {
+    float f0 = (float)x0, f1 = (float)x1;
+    __asm__("" : "+v"(f0));
+    __asm__("" : "+v"(f1));
+    const v2f f = {f0, f1};
+    h1 = __builtin_convertvector(f, v2bf);
+    const v2f r1 = f - __builtin_convertvector(h1, v2f);
+    h2 = __builtin_convertvector(r1, v2bf);
+    h3 = __builtin_convertvector(r1 - __builtin_convertvector(h2, v2f), v2bf);
+}
+
+// Small operands, split, in chunks of 32 k: S[ch][p][g][c][e] = part p of the operand's
+// element (k, c) with k = 32 ch + 8 g + e over the concatenated k range of the nq operands
+// (operand q covers k in [q Kp, q Kp + n) of (q ? Yr : Xr), row-major n x n; zero for
+// k >= n within an operand; Kp = n rounded up to 64).  A workgroup's columns of one
+// (chunk, part, k group) are contiguous 16-byte pieces.
+__global__ __launch_bounds__(256) void k_split3(const double *__restrict__ Xr,
+                                                const double *__restrict__ Yr, int n, int Kp,
+                                                int nq, __bf16 *__restrict__ S) {
+    const long total = (long)n * nq * Kp;  // elements per part
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        // e = ((ch * 4 + g) * n + c) * 8 + x, part-major afterwards
+        const int x = (int)(e & 7);
+        const long r = e >> 3;
+        const int c = (int)(r % n);
+        const long cg = r / n;
+        const int g = (int)(cg & 3);
+        const int ch = (int)(cg >> 2);
+        const int kk = ch * 32 + g * 8 + x;
+        const int q = kk >= Kp ? 1 : 0;
+        const int k = kk - q * Kp;
+        const double *M = q ? Yr : Xr;
+        const float f = k < n ? (float)M[(long)k * n + c] : 0.0f;
+        __bf16 b1, b2, b3;
+        split3(f, b1, b2, b3);
+        const long o = (((long)ch * 3 * 4 + g) * n + c) * 8 + x;  // part 0
+        const long ps = 4L * n * 8;                               // part stride in a chunk
+        S[o] = b1;
+        S[o + ps] = b2;
+        S[o + 2 * ps] = b3;
+    }
+}
+
+// One workgroup: 64 grid rows from m0 x up to 128 columns (wave w: the 32-column tile
+// c0 = 128 blockIdx.y' + 32 w).  Each 32-k chunk of both operands passes through LDS: the
+// big operand's 64 rows x 32 FP64 values (512-byte coalesced rows), split and stored as
+// the MFMA B operand (8 consecutive k of one row per 16 bytes); the small operand's split
+// parts for the workgroup's columns (contiguous 16-byte pieces) as the A operand.  Every
+// global load belongs to the staging of a chunk two ahead of the one multiplied.  Output
+// layout (the 16x16 FP32 accumulator): value v of lane l is row 4 (l/16) + v, column l%16
+// of Out^T.
+constexpr int kB3Cols = 128;  // columns per workgroup
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tsgemm_b3(
+    double *__restrict__ Out, long ldo, const double *__restrict__ C0,
+    const double *__restrict__ A, const double *__restrict__ B, const v8bf *__restrict__ S,
+    int Kp, int nq, long ld, long ng, int n, __bf16 *__restrict__ Zb) {
+    __shared__ __align__(16) v8bf sb[2][3][4][64];         // [buffer][part][k group][row]
+    __shared__ __align__(16) v8bf sa[2][3][4][kB3Cols];    // [buffer][part][k group][column]
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the wave index is wave-uniform: in a scalar register, the big operand's k (and its
+    // column address) is scalar arithmetic
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lr = lane & 15, lg = lane >> 4;
+    // the column groups of one row panel on one XCD: they read the same big-operand rows
+    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int rt = L / gridDim.y;
+    const long m0 = (long)rt * 64;
+    const int cwg = (L - rt * (int)gridDim.y) * kB3Cols;  // the workgroup's first column
+    const int c0 = cwg + 32 * w;
+    const bool wact = c0 < n;
+    const int cpq = Kp >> 5;  // chunks per operand
+    const int nch = nq * cpq;
+    // big-operand staging: thread -> row (lane) of the tile; wave w holds k group w
+    const long mrow = min(m0 + lane, ng - 1);
+    auto gload = [&](int ch, double (&v)[8]) {
+        const int q = ch >= cpq ? 1 : 0;
+        const int kc = (ch - q * cpq) * 32 + 8 * w;
+        const double *T = q ? B : A;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+        for (int u = 0; u < 8; ++u) v[u] = T[(long)min(kc + u, n - 1) * ld + mrow];
+    };
+    // small-operand staging: thread -> column sc of the workgroup (clamped: columns past n
+    // reach only outputs never stored), k groups 2 sh and 2 sh + 1, all three parts
+    const int sc = tid & (kB3Cols - 1), sh = tid >> 7;
+    const long scol = min(cwg + sc, n - 1);
+    auto sload = [&](int ch, v8bf (&t)[6]) {
+        const v8bf *base = S + (long)ch * 3 * 4 * n + scol;
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) t[2 * p + x] = base[(long)(p * 4 + 2 * sh + x) * n];
+    };
+    auto sstore = [&](int buf, const double (&v)[8], const v8bf (&t)[6]) {
+        v8bf p0, p1, p2;
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+            v2bf h1, h2, h3;
+            split3_pair(v[u], v[u + 1], h1, h2, h3);
+            p0[u] = h1[0];
+            p0[u + 1] = h1[1];
+            p1[u] = h2[0];
+            p1[u + 1] = h2[1];
+            p2[u] = h3[0];
+            p2[u + 1] = h3[1];
+        }
+        sb[buf][0][w][lane] = p0;
+        sb[buf][1][w][lane] = p1;
+        sb[buf][2][w][lane] = p2;
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) sa[buf][p][2 * sh + x][sc] = t[2 * p + x];
+    };
+    v4f acc[2][4];  // [column block j][row block i]
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[j][i] = v4f{0.f, 0.f, 0.f, 0.f};
-
-    long moff[4];
+    auto mma = [&](int buf) {
+        v8bf a[2][3];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const long m = m0 + 16 * i + lr;
-        moff[i] = m < ng ? m : ng - 1;
-    }
-    int coff[4];
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int c = c0 + 16 * j + lr;
-        coff[j] = c < n ? c : n - 1;
-    }
-    auto pass = [&](const double *Tp, const double *Sp) {
-        // twice the MFMA rate of FP64: chunks of 16 k-values keep as much time between a
-        // chunk's loads and their use as the FP64 kernel's chunks of 8
-        constexpr int KSC = 2 * QO_TSG_KSC, KC = 4 * KSC;
-        gdouble *__restrict__ T = gptr(Tp);
-        gdouble *__restrict__ S = gptr(Sp);
-        auto load_chunk = [&](int kc, double (&sa)[KSC][4], double (&tb)[KSC][4]) {
+            for (int p = 0; p < 3; ++p) a[j][p] = sa[buf][p][lg][32 * w + 16 * j + lr];
 #pragma unroll
-            for (int ks = 0; ks < KSC; ++ks) {
-                const long k = kc + 4 * ks + lg;
+        for (int i = 0; i < 4; ++i) {
+            const v8bf b1 = sb[buf][0][lg][16 * i + lr];
+            const v8bf b2 = sb[buf][1][lg][16 * i + lr];
+            const v8bf b3 = sb[buf][2][lg][16 * i + lr];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) sa[ks][j] = S[k * n + coff[j]];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) tb[ks][i] = T[k * ld + moff[i]];
+            for (int j = 0; j < 2; ++j) {
+                // smallest terms first
+                v4f t = acc[j][i];
+                t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][2], b1, t, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][1], b2, t, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][0], b3, t, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][1], b1, t, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][0], b2, t, 0, 0, 0);
+                acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][0], b1, t, 0, 0, 0);
             }
-        };
-        auto mma_chunk = [&](const double (&sa)[KSC][4], const double (&tb)[KSC][4]) {
-#pragma unroll
-            for (int ks = 0; ks < KSC; ++ks)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            (float)sa[ks][j], (float)tb[ks][i], acc[j][i], 0, 0, 0);
-        };
-        const int nfull = n & ~(KC - 1);
-        double sa0[KSC][4], tb0[KSC][4], sa1[KSC][4], tb1[KSC][4];
-        if (nfull > 0) {
-            const int last = nfull - KC;
-            const int npairs = nfull / (2 * KC);
-            load_chunk(0, sa0, tb0);
-            for (int p = 0; p < npairs; ++p) {
-                const int kc = p * 2 * KC;
-                load_chunk(kc + KC, sa1, tb1);
-                __builtin_amdgcn_sched_barrier(0);
-                mma_chunk(sa0, tb0);
-                __builtin_amdgcn_sched_barrier(0);
-                load_chunk(min(kc + 2 * KC, last), sa0, tb0);
-                __builtin_amdgcn_sched_barrier(0);
-                mma_chunk(sa1, tb1);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if (nfull & KC) mma_chunk(sa0, tb0);
-        }
-        if (nfull < n) {
-#pragma unroll
-            for (int ks = 0; ks < KSC; ++ks) {
-                const int k = nfull + 4 * ks + lg;
-                const bool kin = k < n;
-                const long kk = kin ? k : n - 1;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const double v = S[kk * n + coff[j]];
-                    sa0[ks][j] = kin ? v : 0.0;
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) tb0[ks][i] = T[kk * ld + moff[i]];
-            }
-            mma_chunk(sa0, tb0);
         }
     };
-    if (A) pass(A, Xr);
-    if (B) pass(B, Yr);
-    // FP32 16x16 accumulator layout: value v of lane l is row 4 (l/16) + v, column l%16,
-    // so acc[j][i][v] = Out^T[c0 + 16j + 4lg + v][m0 + 16i + lr]
+    {
+        // Chunk ch is multiplied from LDS buffer ch & 1 while chunk ch + 1, staged into the
+        // other buffer just before, waits there, and the registers of one set load chunk
+        // ch + 3 (issued before the multiplication, so that each chunk's loads are in flight
+        // for two of them).  nch is even (Kp is a multiple of 64); loads past the end
+        // re-read the last chunk, so that every load and wait is unconditional.  The loop
+        // is entered unconditionally (nch >= 2), so that the prologue's loads stay where
+        // they are issued.
+        double v0[8], v1[8];
+        v8bf t0[6], t1[6];
+        const int last = nch - 1;
+        gload(0, v0);
+        sload(0, t0);
+        gload(1, v1);
+        sload(1, t1);
+        __builtin_amdgcn_sched_barrier(0);
+        sstore(0, v0, t0);
+        gload(min(2, last), v0);
+        sload(min(2, last), t0);
+        __syncthreads();
+        int ch = 0;
+        do {
+            // v1: chunk ch + 1, v0: chunk ch + 2 (loading)
+            sstore(1, v1, t1);
+            gload(min(ch + 3, last), v1);
+            sload(min(ch + 3, last), t1);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(0);
+            __syncthreads();
+            // v0: chunk ch + 2, v1: chunk ch + 3 (loading)
+            sstore(0, v0, t0);
+            gload(min(ch + 4, last), v0);
+            sload(min(ch + 4, last), t0);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(1);
+            __syncthreads();
+            ch += 2;
+        } while (ch < nch);
+    }
+    if (!wact) return;
     // C0 for every value of the tile first (clamped, unconditional loads issued together),
-    // then the sums are stored
-    double c0v[4][4][4];
+    // then the sums are stored: acc[j][i][v] = Out^T[c0 + 16j + 4lg + v][m0 + 16i + lr]
+    double c0v[2][4][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int c = c0 + 16 * j + 4 * lg + v;
-                c0v[j][i][v] = C0 ? (double)gptr(C0)[(long)(c < n ? c : n - 1) * ld + moff[i]]
-                                  : 0.0;
+                const long m = min(m0 + 16 * i + lr, ng - 1);
+                c0v[j][i][v] = C0 ? (double)gptr(C0)[(long)(c < n ? c : n - 1) * ld + m] : 0.0;
             }
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const long m = m0 + 16 * i + lr;
@@ -282,16 +395,6 @@ __device__ __forceinline__ void tsgemm32_tile(double *__restrict__ Out, long ldo
                 }
             }
         }
-}
-
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_tsgemm32(
-    double *__restrict__ Out, long ldo, const double *__restrict__ C0,
-    const double *__restrict__ A, const double *__restrict__ Xr, const double *__restrict__ B,
-    const double *__restrict__ Yr, long ld, long ng, int n, __bf16 *__restrict__ Zb) {
-    const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    const int rt = L / gridDim.y;
-    tsgemm32_tile(Out, ldo, C0, A, Xr, B, Yr, ld, ng, n, (long)rt * 64,
-                  (L - rt * gridDim.y) * 64, Zb);
 }
 
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_tsgemm(double *__restrict__ Out, long ldo,
@@ -326,21 +429,37 @@ hipError_t launch_tsgemm_batch(const TsJob *jobs, int njobs, int max_n, long ld,
     return hipGetLastError();
 }
 
+size_t tsgemm_split_elems(int n) { return (size_t)3 * n * 2 * ((n + 63) / 64 * 64); }
+
 hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
                          const double *Xr, const double *B, const double *Yr, long ld, long ng,
-                         int n, hipStream_t st, bool fp32, __bf16 *Zb) {
+                         int n, hipStream_t st, bool fp32, __bf16 *Zb, __bf16 *split) {
     if (n <= 0 || ng <= 0) return hipSuccess;
-    // each big operand needs its small operand (and the reverse); a BF16 copy only from the
-    // FP32 kernel
+    // each big operand needs its small operand (and the reverse); the FP32-accurate path
+    // needs its split scratch; a BF16 copy only from that path
     if ((A == nullptr) != (Xr == nullptr) || (B == nullptr) != (Yr == nullptr) || !Out ||
-        (Zb && !fp32))
+        (Zb && !fp32) || (fp32 && !split))
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)((ng + 63) / 64), (unsigned)((n + 63) / 64));
-    if (fp32)
-        hipLaunchKernelGGL(k_tsgemm32, grid, dim3(64), 0, st, Out, ldo, C0, A, Xr, B, Yr, ld, ng,
-                           n, Zb);
-    else
+    if (fp32) {
+        // the split small operands (k padded with zeros to a multiple of 64: an even number
+        // of 32-k chunks), then 128-column workgroups
+        const int Kp = (n + 63) / 64 * 64;
+        const int nq = (A ? 1 : 0) + (B ? 1 : 0);
+        if (nq == 0) return hipErrorInvalidValue;
+        const double *X1 = A ? Xr : Yr, *X2 = A ? Yr : nullptr;
+        const double *T1 = A ? A : B, *T2 = A ? B : nullptr;
+        const long items = (long)n * nq * Kp;
+        const unsigned blocks = (unsigned)std::min<long>((items + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_split3, dim3(blocks), dim3(256), 0, st, X1, X2, n, Kp, nq, split);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const dim3 g3((unsigned)((ng + 63) / 64), (unsigned)((n + kB3Cols - 1) / kB3Cols));
+        hipLaunchKernelGGL(k_tsgemm_b3, g3, dim3(256), 0, st, Out, ldo, C0, T1, T2,
+                           reinterpret_cast<const v8bf *>(split), Kp, nq, ld, ng, n, Zb);
+    } else {
         hipLaunchKernelGGL(k_tsgemm, grid, dim3(64), 0, st, Out, ldo, C0, A, Xr, B, Yr, ld, ng, n);
+    }
     return hipGetLastError();
 }
 

@@ -18,10 +18,12 @@ directly at full size or column by column:
     S, M, R gives X, Y within 1e-9 of the GPU's (the 2N x 2N form is the worse
     conditioned one);
   * the block updates U_hat = U X + P Y and U_{n+1} = U_hat - tau Q O from the GPU's own
-    coefficients, full blocks: FP64 within 1e-12 of the largest entry; mixed precision (FP32
-    arithmetic: operands rounded to FP32, FP32 accumulation over K terms) within the dot
-    product bound (K + 2) 2^-24 (|U| |X| + |P| |Y|) per entry (K = 2N), and for the
-    corrector (N + 2) 2^-24 tau |Q| |O| (the FP64 U_hat added exactly to rounding);
+    coefficients, full blocks: FP64 within 1e-12 of the largest entry; mixed precision
+    (FP32-accurate arithmetic: operands rounded to FP32 and split exactly into three BF16
+    parts, the six part products above 2^-24 accumulated in FP32 over K terms; the dropped
+    ones add at most 3 2^-24 |u| |x| per term) within the dot product bound
+    (K + 2) 2^-24 (|U| |X| + |P| |Y|) per entry (K = 2N), and for the corrector
+    (N + 2) 2^-24 tau |Q| |O| (the FP64 U_hat added exactly to rounding);
   * E(U_{n+1}) from the oracle's stencil quadratic form within 1e-12 relative."""
 import numpy as np
 import pytest

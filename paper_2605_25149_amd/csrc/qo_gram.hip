@@ -234,39 +234,43 @@ __global__ __launch_bounds__(64) void k_gram_f64_batch(const GramJob *__restrict
                   split);
 }
 
-// One FP64 block rounded to BF16: Zb[c * ld + r] for r < ld (rows ng..ld-1 zero), so the
-// Gram kernel reads whole 32-row steps with 16-byte loads and converts nothing.
+// One FP64 block (n columns, leading dimension ld) rounded to BF16 in the row-blocked
+// layout of the BF16 Gram operands: element (r, c) at ((r / 32) n + c) 32 + r % 32, rows
+// ng..ld-1 zero.  A 32-row step of any set of consecutive columns is then one contiguous
+// run (64 bytes per column), which the Gram kernel reads with 16-byte loads.  One thread
+// per 8 rows of a (row block, column): four consecutive threads read a column's 256
+// contiguous bytes, and consecutive threads write consecutive 16 bytes.
 __global__ __launch_bounds__(256) void k_pack_bf16(const double *__restrict__ X, long ld,
                                                    long ng, int n, __bf16 *__restrict__ Zb) {
-    const long per_col = ld / 8;
-    const long total = (long)n * per_col;
+    const long total = (ld >> 5) * n * 4;
     for (long it = (long)blockIdx.x * blockDim.x + threadIdx.x; it < total;
          it += (long)gridDim.x * blockDim.x) {
-        const int c = (int)(it / per_col);
-        const long r = (it - (long)c * per_col) * 8;
-        const double *src = X + (long)c * ld + r;
-        double v[8];
-        if (r + 8 <= ng) {
+        const long bc = it >> 2;  // (row block, column)
+        const int q = (int)(it & 3);
+        const long rb = bc / n;
+        const int c = (int)(bc - rb * n);
+        const long r0 = rb * 32 + 8 * q;
+        const double *src = X + (long)c * ld + r0;
+        v8bf o;
+        if (r0 + 8 <= ng) {
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
-                const double2 q = reinterpret_cast<const double2 *>(src)[h];
-                v[2 * h] = q.x;
-                v[2 * h + 1] = q.y;
+                const double2 v = reinterpret_cast<const double2 *>(src)[h];
+                o[2 * h] = f64_to_bf16_rne(v.x);
+                o[2 * h + 1] = f64_to_bf16_rne(v.y);
             }
         } else {
 #pragma unroll
-            for (int s = 0; s < 8; ++s) v[s] = (r + s < ng) ? src[s] : 0.0;
+            for (int e = 0; e < 8; ++e) o[e] = f64_to_bf16_rne(r0 + e < ng ? src[e] : 0.0);
         }
-        v8bf o;
-#pragma unroll
-        for (int s = 0; s < 8; ++s) o[s] = f64_to_bf16_rne(v[s]);
-        *reinterpret_cast<v8bf *>(Zb + (long)c * ld + r) = o;
+        reinterpret_cast<v8bf *>(Zb)[it] = o;
     }
 }
 
-// Gram tiles of [X | Y] from the BF16 copies ZX of X and ZY of Y, 256-column super-tiles: one 1024-thread
-// workgroup per (super-tile pair, K-chunk) stages each 32-row step of its two super-tiles
-// in LDS (each thread copies 16 rows of one column), and its 16 waves each run the 16
+// Gram tiles of [X | Y] from the row-blocked BF16 copies ZX of X and ZY of Y, 256-column
+// super-tiles: one 1024-thread workgroup per (super-tile pair, K-chunk) stages each 32-row
+// step of its two super-tiles (a contiguous run per copy) in LDS (each thread copies 16
+// rows of one column), and its 16 waves each run the 16
 // MFMAs of one 64 x 64 tile pair from LDS.  A column is fetched by the super-tile pairs it
 // belongs to (2 for 2n = 512) instead of by every tile pair (8 to 9), and two steps of
 // loads are in flight beyond the one in LDS.
@@ -285,7 +289,8 @@ __global__ __launch_bounds__(1024) void k_gram_bf16_super(const __bf16 *__restri
     const int split = L / nsp;
     int TI, TJ;
     tile_pair(L - split * nsp, nst, TI, TJ);
-    // rows ng..ld-1 of ZX and ZY are zero and ld is a multiple of 64: whole 32-row steps
+    // ZX and ZY are row-blocked (element (r, c) at ((r / 32) n + c) 32 + r % 32), rows
+    // ng..ld-1 are zero and ld is a multiple of 64: whole 32-row steps
     const long kb = (long)split * kchunk;
     const long ke = min(ld, (min(ng, kb + kchunk) + 31) / 32 * 32);
     const int nsteps = ke > kb ? (int)((ke - kb) >> 5) : 0;
@@ -300,14 +305,16 @@ __global__ __launch_bounds__(1024) void k_gram_bf16_super(const __bf16 *__restri
     {
         const int c = (lt ? TJ : TI) * kSuper + lc;
         // columns past 2n read column 0: their products reach only entries never stored
-        const __bf16 *col = c < n ? ZX + (long)c * ld : c < nn ? ZY + (long)(c - n) * ld : ZX;
-        src = (gv8bf *)(col + kb + 16 * lh);
+        const __bf16 *col = c < n ? ZX + (long)c * 32 : c < nn ? ZY + (long)(c - n) * 32 : ZX;
+        src = (gv8bf *)(col + (kb >> 5) * n * 32 + 16 * lh);
     }
     // steps past the end re-read the last one (their values are never stored)
+    // one step is one row block: n 32-row column pieces further
+    const long step = (long)n * 4;  // in 16-byte units
     auto gload = [&](int s, v8bf (&r)[2]) {
         const int sc = s < nsteps ? s : nsteps - 1;
-        r[0] = src[4 * sc];
-        r[1] = src[4 * sc + 1];
+        r[0] = src[step * sc];
+        r[1] = src[step * sc + 1];
     };
     auto sstore = [&](int buf, const v8bf (&r)[2]) {
         if (loader) {
@@ -383,15 +390,16 @@ __global__ __launch_bounds__(1024) void k_gram_bf16_super(const __bf16 *__restri
 // G[r][c] = w * sum_s part[s][min(r,c)][max(r,c)]
 __global__ void k_gram_reduce(const double *__restrict__ part, int nn, int nsplit, double w,
                               double *__restrict__ G) {
+    // each partial entry (r <= c) is read once and gives both G[r][c] and G[c][r]
     const long total = (long)nn * nn;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
         const int r = (int)(e % nn), c = (int)(e / nn);
-        const int a = min(r, c), b = max(r, c);
-        const long o = (long)b * nn + a;
+        if (r > c) continue;
         double s = 0.0;
-        for (int k = 0; k < nsplit; ++k) s += part[(long)k * total + o];
+        for (int k = 0; k < nsplit; ++k) s += part[(long)k * total + e];
         G[e] = w * s;
+        G[(long)r * nn + c] = w * s;
     }
 }
 

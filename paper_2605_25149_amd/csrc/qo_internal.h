@@ -194,10 +194,11 @@ hipError_t launch_gram_cross_f64(const double *X, const double *Y, long ld, long
                                  double w, double *part, int nsplit, double *G, hipStream_t st);
 hipError_t launch_gram_f64(const double *X, const double *Y, long ld, long ng, int n,
                            double w, double *part, int nsplit, double *G, hipStream_t st);
-// BF16 tiles from the BF16 copies zx of X and zy of Y (n x ld each, 16-byte aligned, ld a
-// multiple of 32; rows ng..ld-1 zero): 256-column super-tile pairs accumulate in FP32 per
-// K-chunk.  pack_x / pack_y: round that block into its copy first (false where its
-// producer has already written the copy).
+// BF16 tiles from the BF16 copies zx of X and zy of Y (ld x n each, row-blocked: element
+// (r, c) at ((r / 32) n + c) 32 + r % 32; 16-byte aligned, ld a multiple of 32; rows
+// ng..ld-1 zero): 256-column super-tile pairs accumulate in FP32 per K-chunk.
+// pack_x / pack_y: round that block into its copy first (false where its producer has
+// already written the copy).
 hipError_t launch_gram_bf16(const double *X, const double *Y, long ld, long ng, int n,
                             double w, double *part, int nsplit, double *G, __bf16 *zx,
                             __bf16 *zy, bool pack_x, bool pack_y, hipStream_t st);
@@ -270,8 +271,8 @@ hipError_t launch_tsgemm_batch(const TsJob *jobs, int njobs, int max_n, long ld,
 // fp32: FP32-accurate arithmetic (operands rounded to FP32, FP32 accumulation, C0 added
 // in FP64) on BF16 MFMA with each operand split into three BF16 parts, for the
 // mixed-precision path; needs `split` (tsgemm_split_elems(n) BF16 of scratch).  There Zb
-// (optional) receives Out rounded to BF16 (nearest-even from the stored FP64 value, same
-// layout as Out).
+// (optional) receives Out rounded to BF16 (nearest-even from the stored FP64 value) in the
+// row-blocked layout of the BF16 Gram operands (see launch_gram_bf16).
 size_t tsgemm_split_elems(int n);
 hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
                          const double *XsT, const double *B, const double *YsT, long ld,

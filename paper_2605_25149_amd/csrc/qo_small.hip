@@ -187,6 +187,8 @@ __global__ __launch_bounds__(GPT) void k_gjb_panel(double *__restrict__ A, int l
     __shared__ double thr_sh;
     const int tid = threadIdx.x;
     if (*status) return;  // an earlier panel failed
+    // elimination: thread -> row eri, columns ecg, ecg + encg, ... of the panel (n <= GPT)
+    const int eri = tid % n, ecg = tid / n, encg = GPT / n;
     double *scal = work + (size_t)n * GB + GB * GB;
     // The panel's loads (n b <= 8192 values: at most 16 per thread) are all issued before
     // any is used, so the panel costs one memory round trip, not one per value.
@@ -281,12 +283,9 @@ __global__ __launch_bounds__(GPT) void k_gjb_panel(double *__restrict__ A, int l
         const double inv = 1.0 / W[kk * n + k];
         for (int j = kk + 1 + tid; j < b; j += GPT) W[j * n + k] *= inv;
         __syncthreads();
-        const int wcols = b - kk - 1;
-        for (int e = tid; e < n * wcols; e += GPT) {
-            const int jj = e / n, i = e - jj * n;
-            if (i == k) continue;
-            const int j = kk + 1 + jj;
-            W[j * n + i] -= W[kk * n + i] * W[j * n + k];
+        if (ecg < encg && eri != k) {
+            const double f = W[kk * n + eri];
+            for (int j = kk + 1 + ecg; j < b; j += encg) W[j * n + eri] -= f * W[j * n + k];
         }
         __syncthreads();
     }

@@ -168,6 +168,11 @@ __global__ void k_sum(const double *__restrict__ v, long n, double *__restrict__
     if (threadIdx.x == 0) *out = s;
 }
 
+// The per-column scale is held in FP32; below ||r|| ~ 3e-39 sqrt(Ng) it is capped at
+// 1e38 (the FP16 transform input r sc then falls below O(1) and loses digits to FP16
+// subnormals: a weaker preconditioner, not a wrong solve).
+constexpr double kMaxColScale = 1e38;
+
 // pcs[c] = sqrt(Ng / ||r_c||^2), 0 for a zero (or non-finite) column.
 __global__ __launch_bounds__(kThreads) void k_col_scale(const double *__restrict__ R, long ld,
                                                         long ng, float *__restrict__ pcs) {
@@ -177,7 +182,8 @@ __global__ __launch_bounds__(kThreads) void k_col_scale(const double *__restrict
     double s = 0.0;
     for (long i = threadIdx.x; i < ng; i += blockDim.x) s += r[i] * r[i];
     s = block_sum(s, red);
-    if (threadIdx.x == 0) pcs[col] = (s > 0.0 && isfinite(s)) ? (float)sqrt((double)ng / s) : 0.f;
+    if (threadIdx.x == 0)
+        pcs[col] = (s > 0.0 && isfinite(s)) ? (float)fmin(sqrt((double)ng / s), kMaxColScale) : 0.f;
 }
 
 // Per-column scale of the forward transform for PCG iteration k, 0 for the
@@ -201,7 +207,8 @@ __global__ __launch_bounds__(kThreads) void k_pc_prep(int k, int ncols, const in
     if (threadIdx.x == 0) {
         float sc = 0.f;
         const bool fin = isfinite(rr) && isfinite(bb);
-        if (fin && !(sqrt(rr) <= ctol * sqrt(bb)) && rr > 0.0) sc = (float)sqrt((double)ng / rr);
+        if (fin && !(sqrt(rr) <= ctol * sqrt(bb)) && rr > 0.0)
+            sc = (float)fmin(sqrt((double)ng / rr), kMaxColScale);
         pcs[col] = sc;
     }
 }
@@ -465,7 +472,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
     } else {
         const int FP = NXP + 4;
         float *SF = reinterpret_cast<float *>(smem);  // RP x FP floats
-        const float unscale = 1.f / (sc * (p.clmin ? p.clmin[col] : p.lmin));
+        // in FP64: sc lmin exceeds the FP32 range for residuals below ~1e-37 sqrt(Ng)
+        const float unscale =
+            (float)(1.0 / ((double)sc * (double)(p.clmin ? p.clmin[col] : p.lmin)));
 #pragma unroll
         for (int j = 0; j < NT; ++j)
 #pragma unroll
@@ -750,7 +759,9 @@ __global__ __launch_bounds__(128 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 
         }
         {
             rzl = wave_sum_lane63(rzl);
-            if (lane == 63) rzp[job * nw + w] = (double)(rzl / (scj * scj * lmin));
+            // in FP64: sc^2 leaves the FP32 range once ||r|| < ~5e-20 sqrt(Ng)
+            if (lane == 63)
+                rzp[job * nw + w] = (double)rzl / ((double)scj * (double)scj * (double)lmin);
         }
         __syncthreads();
         {

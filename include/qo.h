@@ -139,6 +139,35 @@ qo_status qo_set_potential(qo_handle h, const double *V, int on_device);
 qo_status qo_set_state(qo_handle h, const double *U, long ld, int on_device);
 qo_status qo_get_state(qo_handle h, double *U, long ld, int on_device);
 
+/* Checkpoint of the iteration of Sec. 4.1 at step n, for a resume that continues
+ * bit for bit (qo_set_state restarts cold instead).  Besides U_n it holds what the
+ * next step reads from earlier steps: the warm start of the solve G U_n (the block
+ * G U_hat_{n-1} of the previous step; warm starts are not part of the paper's scheme),
+ * E_sigma(U_n) for the energy_rose flag, and, in energy mode 1, the carried matrix
+ * K = <U_n, H_sigma U_n>. */
+typedef struct {
+    long step_index;       /* n */
+    int has_warm;          /* 1: warm holds the warm-start block (warm starts on, n > 0) */
+    int has_energy;        /* 1: energy_shifted is E_sigma(U_n) from the last step */
+    double energy_shifted;
+    int has_K;             /* 1: K holds the carried N x N matrix (energy mode 1) */
+} qo_checkpoint;
+
+/* Writes U_n into U and, when info->has_warm comes back 1 and warm is not NULL, the
+ * warm-start block into warm (both Ng x N, leading dimension ld >= Ng, device pointers
+ * when on_device), and the carried K into K (N x N column-major host array; may be
+ * NULL).  info (not NULL) receives the scalars.  QO_ERR_STATE without a state. */
+qo_status qo_get_checkpoint(qo_handle h, double *U, double *warm, long ld, double *K,
+                            int on_device, qo_checkpoint *info);
+
+/* Restores a checkpoint taken by qo_get_checkpoint on a handle of the same
+ * configuration and potential (set the potential first).  warm must be given when
+ * info->has_warm, K when info->has_K (it is then used only in energy mode 1).
+ * QO_ERR_ARG for missing blocks or a negative step index, QO_ERR_NONFINITE for
+ * non-finite values (the handle then has no state). */
+qo_status qo_set_checkpoint(qo_handle h, const double *U, const double *warm, long ld,
+                            const double *K, int on_device, const qo_checkpoint *info);
+
 /* nsteps evolution steps of the two-stage scheme of Sec. 4.1 (Alg. 1 with a
  * fixed step tau): P = G U_n; U_hat = Cayley transform of U_n by the skew
  * operator A V = P<U_n,V> - U_n<P,V> (solved exactly through an N x N

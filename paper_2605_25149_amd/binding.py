@@ -34,7 +34,7 @@ EXPORTS = [
     "qo_energy_mode",
     "qo_batch_create", "qo_batch_set_potential", "qo_batch_set_state", "qo_batch_get_state",
     "qo_batch_step", "qo_batch_tile", "qo_batch_destroy", "qo_batch_last_error",
-    "qo_gram_pair_noalloc",
+    "qo_gram_pair_noalloc", "qo_get_checkpoint", "qo_set_checkpoint",
 ]
 KERNELS = ["sweep1_f64", "sweep2_f64", "sweep1_f32", "sweep2_f32", "gram", "update", "resid",
            "cg_f64", "cg_f32", "dst_fwd", "dst_pencil", "dst_inv"]
@@ -72,6 +72,12 @@ class QoStepStats(ctypes.Structure):
         }
 
 
+class QoCheckpoint(ctypes.Structure):
+    _fields_ = [("step_index", ctypes.c_long), ("has_warm", ctypes.c_int),
+                ("has_energy", ctypes.c_int), ("energy_shifted", ctypes.c_double),
+                ("has_K", ctypes.c_int)]
+
+
 class QoProfileData(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_long * 12), ("ms", ctypes.c_double * 12),
                 ("work", ctypes.c_double * 12)]
@@ -102,6 +108,10 @@ def load_library(path: str = LIB_PATH):
         "qo_set_potential": ([H, vp, ctypes.c_int], ctypes.c_int),
         "qo_set_state": ([H, vp, ctypes.c_long, ctypes.c_int], ctypes.c_int),
         "qo_get_state": ([H, vp, ctypes.c_long, ctypes.c_int], ctypes.c_int),
+        "qo_get_checkpoint": ([H, vp, vp, ctypes.c_long, vp, ctypes.c_int,
+                               ctypes.POINTER(QoCheckpoint)], ctypes.c_int),
+        "qo_set_checkpoint": ([H, vp, vp, ctypes.c_long, vp, ctypes.c_int,
+                               ctypes.POINTER(QoCheckpoint)], ctypes.c_int),
         "qo_step": ([H, ctypes.c_double, ctypes.c_int, ctypes.POINTER(QoStepStats)], ctypes.c_int),
         "qo_energy": ([H, dp, dp], ctypes.c_int),
         "qo_gram": ([H, vp, vp], ctypes.c_int),
@@ -306,6 +316,41 @@ class Solver:
         out = torch.empty((self.N, self.ng), dtype=torch.float64, device="cuda")
         self._chk(self.lib.qo_get_state(self.h, ctypes.c_void_p(out.data_ptr()), self.ng, 1))
         return out
+
+    def get_checkpoint(self):
+        """(U, warm or None, K or None, info dict): everything a resume reads."""
+        import torch
+
+        U = torch.empty((self.N, self.ng), dtype=torch.float64, device="cuda")
+        W = torch.empty((self.N, self.ng), dtype=torch.float64, device="cuda")
+        K = np.zeros((self.N, self.N), dtype=np.float64, order="F")
+        ck = QoCheckpoint()
+        self._chk(self.lib.qo_get_checkpoint(self.h, ctypes.c_void_p(U.data_ptr()),
+                                             ctypes.c_void_p(W.data_ptr()), self.ng,
+                                             K.ctypes.data_as(ctypes.c_void_p), 1,
+                                             ctypes.byref(ck)))
+        info = {"step_index": ck.step_index, "has_warm": ck.has_warm,
+                "has_energy": ck.has_energy, "energy_shifted": ck.energy_shifted,
+                "has_K": ck.has_K}
+        return U, (W if ck.has_warm else None), (K if ck.has_K else None), info
+
+    def set_checkpoint(self, U, warm, K, info):
+        ld = _check_block(U, self.ng, self.N)
+        wp = None
+        if warm is not None:
+            _check_block(warm, self.ng, self.N)
+            if warm.stride(0) != ld:
+                raise ValueError("U and warm must have the same leading dimension")
+            wp = ctypes.c_void_p(warm.data_ptr())
+        kp = None
+        if K is not None:
+            K = np.asfortranarray(np.asarray(K, dtype=np.float64))
+            kp = K.ctypes.data_as(ctypes.c_void_p)
+        ck = QoCheckpoint(int(info["step_index"]), int(info["has_warm"]),
+                          int(info["has_energy"]), float(info["energy_shifted"]),
+                          int(info["has_K"]))
+        self._chk(self.lib.qo_set_checkpoint(self.h, ctypes.c_void_p(U.data_ptr()), wp, ld, kp,
+                                             1, ctypes.byref(ck)))
 
     # -- the method
     def step(self, tau, nsteps=1):

@@ -1460,7 +1460,12 @@ __global__ void k_scan_finite(const double *__restrict__ X, long ld, long ng, in
 extern "C" {
 
 const char *qo_status_string(qo_status s) {
-    switch (s) {
+    // read as int: a C caller may pass any int, and a C++ load of an out-of-range value as
+    // the enum type is undefined
+    static_assert(sizeof(qo_status) == sizeof(int), "qo_status is passed as an int");
+    int v;
+    memcpy(&v, &s, sizeof v);
+    switch (v) {
         case QO_OK: return "QO_OK";
         case QO_ERR_ARG: return "QO_ERR_ARG";
         case QO_ERR_ALLOC: return "QO_ERR_ALLOC";
@@ -1738,6 +1743,71 @@ qo_status qo_get_state(qo_handle h, double *U, long ld, int on_device) {
     if (!U || ld < h->ng) return fail(h, QO_ERR_ARG, "bad output pointer or ld");
     if (!h->have_U) return fail(h, QO_ERR_STATE, "no state set");
     return copy_block_out(h, U, ld, h->U, on_device, h->N);
+}
+
+// The warm start of the next first solve sits in that solve's output block PQ[cur] (the
+// previous step's G U_hat); the BF16 copy of U (mixed) is re-derived from U, bit for bit.
+qo_status qo_get_checkpoint(qo_handle h, double *U, double *warm, long ld, double *K,
+                            int on_device, qo_checkpoint *info) {
+    if (!h) return QO_ERR_ARG;
+    if (!U || !info || ld < h->ng) return fail(h, QO_ERR_ARG, "bad output pointer or ld");
+    if (!h->have_U) return fail(h, QO_ERR_STATE, "no state set");
+    QOC(copy_block_out(h, U, ld, h->U, on_device, h->N));
+    qo_checkpoint ck{};
+    ck.step_index = h->nstep;
+    ck.has_warm = h->have_warm ? 1 : 0;
+    if (h->have_warm && warm) QOC(copy_block_out(h, warm, ld, h->PQ[h->cur], on_device, h->N));
+    ck.has_energy = h->have_Es ? 1 : 0;
+    ck.energy_shifted = h->have_Es ? h->last_Es : 0.0;
+    ck.has_K = (h->emode == 1 && h->have_K) ? 1 : 0;
+    if (ck.has_K && K) {
+        HIPC(h, hipMemcpyAsync(K, h->Kprop, sizeof(double) * h->N * h->N, hipMemcpyDeviceToHost,
+                               h->st));
+        HIPC(h, hipStreamSynchronize(h->st));
+    }
+    *info = ck;
+    return QO_OK;
+}
+
+qo_status qo_set_checkpoint(qo_handle h, const double *U, const double *warm, long ld,
+                            const double *K, int on_device, const qo_checkpoint *info) {
+    if (!h) return QO_ERR_ARG;
+    if (!info || info->step_index < 0 || (info->has_warm && !warm) || (info->has_K && !K) ||
+        (info->has_energy && !std::isfinite(info->energy_shifted)))
+        return fail(h, QO_ERR_ARG, "incomplete checkpoint (warm, K, energy or step index)");
+    QOC(qo_set_state(h, U, ld, on_device));  // validates U; resets the carried quantities
+    if (info->has_warm) {
+        QOC(copy_block_in(h, h->PQ[h->cur], warm, ld, on_device));
+        HIPC(h, hipMemsetAsync(h->dstatus, 0, sizeof(int), h->st));
+        long blocks = (h->ng + 255) / 256;
+        if (blocks > 1024) blocks = 1024;
+        hipLaunchKernelGGL(k_scan_finite, dim3((unsigned)blocks, h->N), dim3(256), 0, h->st,
+                           h->PQ[h->cur], h->ld, h->ng, h->N, h->dstatus);
+        HIPC(h, hipGetLastError());
+        int bad = 0;
+        HIPC(h, hipMemcpyAsync(&bad, h->dstatus, sizeof(int), hipMemcpyDeviceToHost, h->st));
+        HIPC(h, hipStreamSynchronize(h->st));
+        if (bad) {
+            h->have_U = false;
+            return fail(h, QO_ERR_NONFINITE, "warm-start block has non-finite values");
+        }
+        h->have_warm = true;
+    }
+    if (info->has_K && h->emode == 1) {
+        for (long i = 0; i < (long)h->N * h->N; ++i)
+            if (!std::isfinite(K[i])) {
+                h->have_U = false;
+                return fail(h, QO_ERR_NONFINITE, "carried K has non-finite values");
+            }
+        HIPC(h, hipMemcpyAsync(h->Kprop, K, sizeof(double) * h->N * h->N,
+                               hipMemcpyHostToDevice, h->st));
+        HIPC(h, hipStreamSynchronize(h->st));
+        h->have_K = true;
+    }
+    h->have_Es = info->has_energy != 0;
+    h->last_Es = info->has_energy ? info->energy_shifted : 0.0;
+    h->nstep = info->step_index;
+    return QO_OK;
 }
 
 qo_status qo_step(qo_handle h, double tau, int nsteps, qo_step_stats *last) {

@@ -146,6 +146,101 @@ struct qo_ctx {
 };
 
 namespace {
+int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    if (!v || !*v) return dflt;
+    return atoi(v);
+}
+}  // namespace
+
+// Tiling of the stencil family (g) and of the one-sweep PCG kernels (q) for a grid of
+// dim / n[] interior points with N columns: band height, z-chunks, points per thread.
+// Host code, also called by the CPU checks of the kernels' index arithmetic.
+void qo::plan_grid(int dim, const int n[3], const double L[3], double kinetic, int N, Grid &g,
+                   Grid &q) {
+    g.cinst = nullptr;
+    g.dim = dim;
+    g.nx = n[0];
+    g.ny = n[1];
+    g.nz = dim == 3 ? n[2] : 1;
+    g.ng = (long)g.nx * g.ny * g.nz;
+    double h[3];
+    for (int k = 0; k < 3; ++k) h[k] = (k < dim) ? L[k] / (n[k] + 1) : 1.0;
+    g.ihx2 = 1.0 / (h[0] * h[0]);
+    g.ihy2 = 1.0 / (h[1] * h[1]);
+    g.ihz2 = dim == 3 ? 1.0 / (h[2] * h[2]) : 0.0;
+    g.kappa = kinetic;
+    g.c0 = 2.0 * kinetic * (g.ihx2 + g.ihy2 + g.ihz2);
+
+    // band height: ~1536 points per plane in 2-D; 3-D bands are kept near 768
+    // points (measured faster for the FP32 sweeps at 96^3 because of occupancy)
+    int TY = (dim == 3 ? 768 : 1536) / g.nx;
+    if (TY < 1) TY = 1;
+    TY = env_int("QO_TY", TY);
+    if (TY > g.ny) TY = g.ny;
+    if (TY < 1) TY = 1;
+    while (pick_ppt(TY * g.nx) < 0 && TY > 1) --TY;
+    g.TY = TY;
+    g.ppt = pick_ppt(TY * g.nx);
+    // The engine for fewer than 4 points per thread stages one halo column per thread
+    // between planes, so a 3-D grid (several planes per tile) wider than a workgroup takes
+    // the engine for 4 or more, which loops over the halo columns.
+    if (dim == 3 && g.nx > kThreads && g.ppt < 4) g.ppt = 4;
+    g.nbands = (g.ny + TY - 1) / TY;
+    if (dim == 2) {
+        g.ZC = 1;
+        g.nzc = 1;
+    } else {
+        long want = (2048 + (long)N * g.nbands - 1) / ((long)N * g.nbands);
+        int maxc = g.nz / 16;
+        if (maxc < 1) maxc = 1;
+        if (want > maxc) want = maxc;
+        if (want < 1) want = 1;
+        int ZC = (g.nz + (int)want - 1) / (int)want;
+        ZC = env_int("QO_ZC", ZC);
+        if (ZC < 1) ZC = 1;
+        if (ZC > g.nz) ZC = g.nz;
+        g.ZC = ZC;
+        g.nzc = (g.nz + ZC - 1) / ZC;
+    }
+    // one-sweep PCG: rows [-2, TY+1] per plane in at most 5 (8 for wide rows) points per
+    // thread, and 3 + 3 LDS planes of (TY+4) and (TY+2) rows within 64 KiB in FP64
+    q = g;
+    {
+        const int target = g.nx <= 128 ? 5 : 8;
+        int ty = kThreads * target / g.nx - 4;
+        const int ty_lds = ((65536 / (24 * g.nx)) - 6) / 2;
+        if (ty > ty_lds) ty = ty_lds;
+        ty = env_int("QO_CG_TY", ty);
+        if (ty > g.ny) ty = g.ny;
+        if (ty < 1) ty = 1;
+        q.TY = ty;
+        const int raw = ((ty + 4) * g.nx + kThreads - 1) / kThreads;
+        const int opts[6] = {2, 3, 4, 5, 6, 8};
+        q.ppt = -1;
+        for (int o : opts)
+            if (o >= raw) { q.ppt = o; break; }
+        q.nbands = (g.ny + ty - 1) / ty;
+        if (dim == 2) {
+            q.ZC = 1;
+            q.nzc = 1;
+        } else {
+            long want = (2048 + (long)N * q.nbands - 1) / ((long)N * q.nbands);
+            int maxc = g.nz / 16;
+            if (maxc < 1) maxc = 1;
+            if (want > maxc) want = maxc;
+            if (want < 1) want = 1;
+            int ZC = (g.nz + (int)want - 1) / (int)want;
+            ZC = env_int("QO_CG_ZC", ZC);
+            if (ZC < 1) ZC = 1;
+            if (ZC > g.nz) ZC = g.nz;
+            q.ZC = ZC;
+            q.nzc = (g.nz + ZC - 1) / ZC;
+        }
+    }
+}
+
+namespace {
 
 qo_status fail(qo_ctx *c, qo_status s, const char *fmt, ...) {
     if (c) {
@@ -188,92 +283,14 @@ qo_status dalloc(qo_ctx *c, T **p, size_t n) {
     return QO_OK;
 }
 
-int env_int(const char *name, int dflt) {
-    const char *v = getenv(name);
-    if (!v || !*v) return dflt;
-    return atoi(v);
-}
 
 void setup_grid(qo_ctx *c) {
-    Grid &g = c->g;
     const qo_config &cf = c->cfg;
-    g.dim = cf.dim;
-    g.nx = cf.n[0];
-    g.ny = cf.n[1];
-    g.nz = cf.dim == 3 ? cf.n[2] : 1;
-    g.ng = (long)g.nx * g.ny * g.nz;
+    plan_grid(cf.dim, cf.n, cf.L, cf.kinetic, c->N, c->g, c->gcg);
     double h[3];
     for (int k = 0; k < 3; ++k) h[k] = (k < cf.dim) ? cf.L[k] / (cf.n[k] + 1) : 1.0;
-    g.ihx2 = 1.0 / (h[0] * h[0]);
-    g.ihy2 = 1.0 / (h[1] * h[1]);
-    g.ihz2 = cf.dim == 3 ? 1.0 / (h[2] * h[2]) : 0.0;
-    g.kappa = cf.kinetic;
-    g.c0 = 2.0 * cf.kinetic * (g.ihx2 + g.ihy2 + g.ihz2);
     c->w = h[0] * h[1] * (cf.dim == 3 ? h[2] : 1.0);
-
-    // band height: ~1536 points per plane in 2-D; 3-D bands are kept near 768
-    // points (measured faster for the FP32 sweeps at 96^3 because of occupancy)
-    int TY = (cf.dim == 3 ? 768 : 1536) / g.nx;
-    if (TY < 1) TY = 1;
-    TY = env_int("QO_TY", TY);
-    if (TY > g.ny) TY = g.ny;
-    if (TY < 1) TY = 1;
-    while (pick_ppt(TY * g.nx) < 0 && TY > 1) --TY;
-    g.TY = TY;
-    g.ppt = pick_ppt(TY * g.nx);
-    g.nbands = (g.ny + TY - 1) / TY;
-    if (cf.dim == 2) {
-        g.ZC = 1;
-        g.nzc = 1;
-    } else {
-        long want = (2048 + (long)c->N * g.nbands - 1) / ((long)c->N * g.nbands);
-        int maxc = g.nz / 16;
-        if (maxc < 1) maxc = 1;
-        if (want > maxc) want = maxc;
-        if (want < 1) want = 1;
-        int ZC = (g.nz + (int)want - 1) / (int)want;
-        ZC = env_int("QO_ZC", ZC);
-        if (ZC < 1) ZC = 1;
-        if (ZC > g.nz) ZC = g.nz;
-        g.ZC = ZC;
-        g.nzc = (g.nz + ZC - 1) / ZC;
-    }
-    // one-sweep PCG: rows [-2, TY+1] per plane in at most 5 (8 for wide rows) points per
-    // thread, and 3 + 3 LDS planes of (TY+4) and (TY+2) rows within 64 KiB in FP64
-    Grid &q = c->gcg;
-    q = g;
-    {
-        const int target = g.nx <= 128 ? 5 : 8;
-        int ty = kThreads * target / g.nx - 4;
-        const int ty_lds = ((65536 / (24 * g.nx)) - 6) / 2;
-        if (ty > ty_lds) ty = ty_lds;
-        ty = env_int("QO_CG_TY", ty);
-        if (ty > g.ny) ty = g.ny;
-        if (ty < 1) ty = 1;
-        q.TY = ty;
-        const int raw = ((ty + 4) * g.nx + kThreads - 1) / kThreads;
-        const int opts[6] = {2, 3, 4, 5, 6, 8};
-        q.ppt = -1;
-        for (int o : opts)
-            if (o >= raw) { q.ppt = o; break; }
-        q.nbands = (g.ny + ty - 1) / ty;
-        if (cf.dim == 2) {
-            q.ZC = 1;
-            q.nzc = 1;
-        } else {
-            long want = (2048 + (long)c->N * q.nbands - 1) / ((long)c->N * q.nbands);
-            int maxc = g.nz / 16;
-            if (maxc < 1) maxc = 1;
-            if (want > maxc) want = maxc;
-            if (want < 1) want = 1;
-            int ZC = (g.nz + (int)want - 1) / (int)want;
-            ZC = env_int("QO_CG_ZC", ZC);
-            if (ZC < 1) ZC = 1;
-            if (ZC > g.nz) ZC = g.nz;
-            q.ZC = ZC;
-            q.nzc = (g.nz + ZC - 1) / ZC;
-        }
-    }
+    const Grid &g = c->g, &q = c->gcg;
     c->qsmax = (long)c->N * (g.tiles() > q.tiles() ? g.tiles() : q.tiles());
 }
 

@@ -170,6 +170,9 @@ Grid group_grid(const qo_config &cf, int ncols, int TY, double *w) {
     while (pick_ppt(TY * g.nx) < 0 && TY > 1) --TY;
     g.TY = TY;
     g.ppt = pick_ppt(TY * g.nx);
+    // as in the single-instance plan: several planes per tile and rows wider than a
+    // workgroup need the engine for 4 or more points per thread (it loops over halo columns)
+    if (cf.dim == 3 && g.nx > kThreads && g.ppt < 4) g.ppt = 4;
     g.nbands = (g.ny + TY - 1) / TY;
     if (cf.dim == 2) {
         g.ZC = 1;

@@ -64,10 +64,9 @@ __global__ __launch_bounds__(kThreads) void k_cg_step(CgArgs<T> a) {
     const Grid &g = a.g;
     const int tiles = g.tiles();
     const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int col = L / tiles;
-    const int tile = L - col * tiles;
-    const int band = tile / g.nzc;
-    const int zc = tile - band * g.nzc;
+    int col, tile;
+    stencil_tile_of(L, (int)(gridDim.x / tiles), tiles, col, tile);
+    const TileExtent te = g.extent(tile);
     const bool lead = tile == 0;
     const int k = a.k;
     const int cur = k & 1, prv = cur ^ 1;
@@ -133,10 +132,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_step(CgArgs<T> a) {
     const int tid = threadIdx.x;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int TY = g.TY;
-    const int y0 = band * TY;
-    const int ty = min(TY, ny - y0);
-    const int z0 = zc * g.ZC;
-    const int z1 = min(nz, z0 + g.ZC);
+    const int y0 = te.y0, ty = te.ty, z0 = te.z0, z1 = te.z1;
     const long plane = (long)nx * ny;
     const int nP = (ty + 4) * nx, nU = (ty + 2) * nx, nO = ty * nx;
     const int slotP = (TY + 4) * nx, slotU = (TY + 2) * nx;

@@ -250,8 +250,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
                                                    double *__restrict__ wzp = nullptr) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int col = L / p.nslab;
-    const int slab = L - col * p.nslab;
+    int col, slab;
+    plane_slab_of(L, p.nslab, col, slab);
     const float sc = pcs[col];
     if (sc == 0.f) return;  // column converged or inactive (uniform over the block)
 

@@ -5,6 +5,11 @@
 
 namespace qo {
 
+// Rows [y0, y0 + ty) and planes [z0, z1) of one tile of a Grid.
+struct TileExtent {
+    int band, zc, y0, ty, z0, z1;
+};
+
 // Geometry of one column grid and of its band/z-chunk tiling.
 //   A tile is TY consecutive y-rows (full x extent) of ZC consecutive z-planes;
 //   one workgroup of 256 threads streams one tile of one column, marching in z.
@@ -23,6 +28,16 @@ struct Grid {
     // 1/diag) start at instance * ng.  nullptr for a single instance.
     const int *cinst;
     __host__ __device__ int tiles() const { return nbands * nzc; }
+    __host__ __device__ TileExtent extent(int tile) const {
+        TileExtent e;
+        e.band = tile / nzc;
+        e.zc = tile - e.band * nzc;
+        e.y0 = e.band * TY;
+        e.ty = min(TY, ny - e.y0);
+        e.z0 = e.zc * ZC;
+        e.z1 = min(nz, e.z0 + ZC);
+        return e;
+    }
 };
 
 constexpr int kThreads = 256;
@@ -31,10 +46,40 @@ constexpr int kThreads = 256;
 // dispatch index b runs on XCD b % 8.  Remap so that XCD x works through one
 // contiguous range of logical indices in order; neighbouring tiles (which share
 // halo rows or operand panels) then meet in the same L2.  A bijection of [0, B).
-__device__ __forceinline__ int xcd_remap(int b, int B) {
+// The index maps below are host-callable so that a CPU program can check them
+// (bijections, coverage, bounds) for every launch shape without a GPU.
+__host__ __device__ __forceinline__ int xcd_remap(int b, int B) {
     const int x = b & 7, s = b >> 3;
     const int q = B >> 3, r = B & 7;
     return x * q + (x < r ? x : r) + s;
+}
+
+// Stencil-family launches: logical workgroup L of an ncols x tiles grid -> (column,
+// tile), column-major: an XCD works through whole columns, so a column's neighbouring
+// bands (whose rows are its halo) run side by side and meet in the same L2.  (Grouping a
+// few columns tile-major, to share the per-point V + sigma of a tile in L2, measured 2%
+// slower for the sweeps.)
+__host__ __device__ __forceinline__ void stencil_tile_of(int L, int ncols, int tiles, int &col,
+                                                         int &tile) {
+    (void)ncols;
+    col = L / tiles;
+    tile = L - col * tiles;
+}
+
+// DST plane passes: logical workgroup L of an ncols x nslab grid -> (column, slab),
+// column-major: consecutive workgroups of an XCD stream consecutive slabs of one column.
+// (Column-fastest order, which shares the per-point V + sigma of a slab in L2, measured no
+// faster for the inverse pass and 7% slower for the forward pass.)
+__host__ __device__ __forceinline__ void plane_slab_of(int L, int nslab, int &col, int &slab) {
+    col = L / nslab;
+    slab = L - col * nslab;
+}
+
+// Row-blocked BF16 layout of a Gram operand with n columns: grid row m of column c sits
+// at ((m / 32) * n + c) * 32 + m % 32, so a 32-row step of consecutive columns is
+// contiguous.  Rows are padded to the block's leading dimension (a multiple of 64).
+__host__ __device__ __forceinline__ long bf16_rowblock_index(long m, int c, int n) {
+    return ((m >> 5) * n + c) * 32 + (m & 31);
 }
 
 // Per-column PCG bookkeeping on the device (double-buffered by iteration parity).
@@ -255,6 +300,10 @@ hipError_t launch_nn_adjoint(const double *G1, int n, double tau, const double *
                              hipStream_t st);
 
 int pick_ppt(int pts);
+// Tiling of the stencil family (g) and of the one-sweep PCG kernels (q) for a grid of
+// dim / n[] interior points on a box with sides L[] and N columns (qo_api.hip).
+void plan_grid(int dim, const int n[3], const double L[3], double kinetic, int N, Grid &g,
+               Grid &q);
 
 // ---- tall-skinny update (qo_tsgemm.hip) ----
 // Out = C0 + A * Xs + B * Ys  (Ng x n, col-major), small operands given

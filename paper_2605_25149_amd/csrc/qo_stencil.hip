@@ -53,11 +53,9 @@ __device__ __forceinline__ void engine_wide(const Grid &g, int band, int zc,
     using ER = typename Ep::Raw;
     const int tid = threadIdx.x;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const int y0 = band * g.TY;
-    const int ty = min(g.TY, ny - y0);
+    const TileExtent te = g.extent(band * g.nzc + zc);
+    const int y0 = te.y0, ty = te.ty, z0 = te.z0, z1 = te.z1;
     const int npts = ty * nx;
-    const int z0 = zc * g.ZC;
-    const int z1 = min(nz, z0 + g.ZC);
     const long plane = (long)nx * ny;
     const int ldsz = (g.TY + 2) * nx;
     const bool has_lo = y0 > 0, has_hi = (y0 + ty) < ny;
@@ -185,11 +183,9 @@ __device__ __forceinline__ void engine(const Grid &g, int band, int zc,
     using ER = typename Ep::Raw;
     const int tid = threadIdx.x;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const int y0 = band * g.TY;
-    const int ty = min(g.TY, ny - y0);
+    const TileExtent te = g.extent(band * g.nzc + zc);
+    const int y0 = te.y0, ty = te.ty, z0 = te.z0, z1 = te.z1;
     const int npts = ty * nx;
-    const int z0 = zc * g.ZC;
-    const int z1 = min(nz, z0 + g.ZC);
     const long plane = (long)nx * ny;
     const int ldsz = (g.TY + 2) * nx;
     const bool has_lo = y0 > 0, has_hi = (y0 + ty) < ny;
@@ -380,13 +376,14 @@ struct LdPcgZ {  // p = z + beta p_old with an explicit preconditioned residual 
 
 struct NoRaw {};
 
+// Workgroup -> (column, tile) of an ncols x tiles launch (stencil_tile_of).
 __device__ __forceinline__ void tile_of(const Grid &g, int &col, int &tile, int &band, int &zc) {
     const int tiles = g.tiles();
     const int L = xcd_remap(blockIdx.x, gridDim.x);
-    col = L / tiles;
-    tile = L - col * tiles;
-    band = tile / g.nzc;
-    zc = tile - band * g.nzc;
+    stencil_tile_of(L, (int)(gridDim.x / tiles), tiles, col, tile);
+    const TileExtent e = g.extent(tile);
+    band = e.band;
+    zc = e.zc;
 }
 
 // Per-point array of a column's instance (see Grid::cinst).

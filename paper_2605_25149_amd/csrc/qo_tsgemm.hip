@@ -391,7 +391,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 if (c < n) {
                     const double o = c0v[j][i][v] + (double)acc[j][i][v];
                     Out[(long)c * ldo + m] = o;
-                    if (Zb) Zb[((m >> 5) * n + c) * 32 + (m & 31)] = dev::f64_to_bf16_rne(o);
+                    if (Zb) Zb[bf16_rowblock_index(m, c, n)] = dev::f64_to_bf16_rne(o);
                 }
             }
         }

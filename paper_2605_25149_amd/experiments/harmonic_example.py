@@ -36,14 +36,16 @@ def fd_reference(m, N, half=HALF):
     return np.sort(np.add.outer(mu, mu).ravel())[: N + 1]
 
 
-def run(m, tau, N=15, max_steps=40000, seed=1, stop=1e-5, variant=0, log=None):
+def run(m, tau, N=15, max_steps=40000, seed=1, stop=1e-5, variant=0, log=None,
+        precond="jacobi"):
     n = (m, m)
     L = (2 * HALF, 2 * HALF)
     V = inputs.harmonic(n, 1.0, centre=(HALF, HALF), L=L)
     U0 = inputs.random_block(m * m, N, seed=seed) / (2 * HALF)  # E<U0,U0> = I
     lam_ref = fd_reference(m, N)
     t0 = time.perf_counter()
-    with binding.Solver(2, n, N, L=L, pcg_tol=1e-12, pcg_check=4, pcg_variant=variant) as s:
+    with binding.Solver(2, n, N, L=L, pcg_tol=1e-12, pcg_check=4, pcg_variant=variant,
+                        precond=precond) as s:
         s.set_potential(V)
         s.set_state(U0)
         # Algorithm 1 through qo_run (the stop test is taken on U_n before its step), in
@@ -81,6 +83,8 @@ def main():
     ap.add_argument("--tau", type=float, nargs="+", default=[0.05, 0.1, 0.5, 0.9, 1.0, 1.5])
     ap.add_argument("--max-steps", type=int, default=40000)
     ap.add_argument("--N", type=int, default=15)
+    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "fast_poisson"],
+                    help="solver of G (the solves are taken to 1e-12 either way)")
     args = ap.parse_args()
 
     def log(msg):
@@ -88,10 +92,12 @@ def main():
 
     for m in args.n:
         for tau in args.tau:
-            r = run(m, tau, N=args.N, max_steps=args.max_steps, log=log)
+            r = run(m, tau, N=args.N, max_steps=args.max_steps, log=log,
+                    precond=args.precond)
             log(f"m={m} tau={tau}: {r['steps']} steps (converged {r['converged']}), "
                 f"tau*steps={r['tau_times_steps']:.1f}, max err {r['max_err_ritz']:.2e}, "
                 f"|O| {r['orth_err_last_step']:.1e} ({r['seconds']:.1f} s)")
+            r["precond"] = args.precond
             print(json.dumps(r), flush=True)
 
 

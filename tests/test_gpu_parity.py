@@ -51,6 +51,10 @@ CASES_APPLY = [
     (3, (13, 11, 10), 5, {"QO_TY": 3, "QO_ZC": 4}),
     (3, (24, 20, 18), 3, None),
     (3, (64, 64, 64), 2, None),
+    # rows wider than a workgroup with several planes per tile: the engine that loops over
+    # the halo columns (the one-halo-column-per-thread engine would leave columns >= 256)
+    (3, (300, 5, 7), 2, None),
+    (3, (520, 3, 4), 3, None),
 ]
 
 

@@ -126,8 +126,8 @@ typedef enum {
  *            blocks for the Gram (the bytes of one FP32 block);
  *   precond 1 adds two FP16 blocks and one block of the PCG's precision (z);
  * plus O(Ng + N^2) per-point and N x N arrays.  At Ng = 96^3, N = 256 the mixed
- * fast-Poisson workspace is about 25 GB.  qo_tape_forward adds K + 1 FP64 blocks
- * when it is called.  Sizes: 1 <= N < Ng, n_0 <= 1024 (n_0 <= 256 with
+ * fast-Poisson workspace is about 25 GB.  qo_tape_forward adds K + 1 FP64 blocks when
+ * it is called (fewer under qo_tape_budget).  Sizes: 1 <= N < Ng, n_0 <= 1024 (n_0 <= 256 with
  * pcg_variant 1).  On error *out is NULL. */
 qo_status qo_create(const qo_config *cfg, void *hip_stream, qo_handle *out);
 
@@ -372,6 +372,16 @@ qo_status qo_energy_mode(qo_handle h, int mode, int anchor);
  * as exact); it uses 2K solves of N columns more than the forward.  The state is U_K
  * again afterwards.  QO_ERR_STATE before a successful qo_tape_forward. */
 qo_status qo_tape_forward(qo_handle h, double tau, int K, int loss, double *L);
+
+/* Memory bound of the tape: at most `blocks` FP64 blocks of ld x N for the states
+ * (0, the default: every one of U_0 .. U_K).  With a bound, qo_tape_forward keeps every
+ * s-th state and U_K, with the smallest stride s for which those checkpoints and the s - 1
+ * states of one segment fit (s ~ sqrt(K): about 2 sqrt(K) blocks); qo_tape_backward
+ * recomputes each segment's states from its checkpoint once, just before the adjoint goes
+ * through it (about K extra steps), and returns the same gradients bit for bit.
+ * QO_ERR_ARG for blocks < 0 or 1 <= blocks < 3; qo_tape_forward returns QO_ERR_ARG when
+ * no stride fits K in the bound. */
+qo_status qo_tape_budget(qo_handle h, int blocks);
 qo_status qo_tape_backward(qo_handle h, double seed, double *gV, double *gU0, long ld,
                            int on_device);
 

@@ -34,7 +34,7 @@ EXPORTS = [
     "qo_energy_mode",
     "qo_batch_create", "qo_batch_set_potential", "qo_batch_set_state", "qo_batch_get_state",
     "qo_batch_step", "qo_batch_tile", "qo_batch_destroy", "qo_batch_last_error",
-    "qo_gram_pair_noalloc", "qo_get_checkpoint", "qo_set_checkpoint",
+    "qo_gram_pair_noalloc", "qo_get_checkpoint", "qo_set_checkpoint", "qo_tape_budget",
 ]
 KERNELS = ["sweep1_f64", "sweep2_f64", "sweep1_f32", "sweep2_f32", "gram", "update", "resid",
            "cg_f64", "cg_f32", "dst_fwd", "dst_pencil", "dst_inv"]
@@ -131,6 +131,7 @@ def load_library(path: str = LIB_PATH):
         "qo_profile_get": ([H, ctypes.POINTER(QoProfileData)], ctypes.c_int),
         "qo_precond": ([H, vp, vp, ctypes.c_long, ctypes.c_int, vp], ctypes.c_int),
         "qo_tape_forward": ([H, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp], ctypes.c_int),
+        "qo_tape_budget": ([H, ctypes.c_int], ctypes.c_int),
         "qo_energy_mode": ([H, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "qo_tape_backward": ([H, ctypes.c_double, vp, vp, ctypes.c_long, ctypes.c_int],
                              ctypes.c_int),
@@ -383,6 +384,10 @@ class Solver:
         self._chk(self.lib.qo_energy_mode(self.h, int(mode), int(anchor)))
 
     LOSSES = {"energy": 0, "ritz_sum": 1}
+
+    def tape_budget(self, blocks):
+        """Bound the tape to `blocks` state blocks (0: keep every state)."""
+        self._chk(self.lib.qo_tape_budget(self.h, int(blocks)))
 
     def tape_forward(self, tau, K, loss="energy"):
         """K taped steps from the current state; returns the loss of U_K (energy, or the

@@ -110,7 +110,10 @@ struct qo_ctx {
     bool have_K = false;
     double *Kprop = nullptr, *epool = nullptr;
     // reverse mode through taped steps (qo_tape_forward / qo_tape_backward)
-    std::vector<double *> tape;  // U_0 .. U_K
+    std::vector<double *> tape;  // checkpoints U_0, U_s, U_2s, ... and U_K (s = tape_s)
+    std::vector<double *> tseg;  // the s - 1 recomputed states of one segment (s > 1)
+    int tape_budget = 0;         // at most this many state blocks (0: no bound)
+    int tape_s = 1;              // checkpoint stride of the last tape
     int tape_K = 0, tape_loss = 0;
     double tape_tau = 0.0;
     bool have_tape = false;
@@ -2178,20 +2181,37 @@ enum { AM_XB, AM_YB, AM_SB, AM_MB, AM_RB, AM_SHB, AM_T, AM_T2, AM_T3, AM_G, AM_C
 
 double *am(qo_ctx *c, int i) { return c->admat + (size_t)i * c->N * c->N; }
 
-qo_status tape_alloc(qo_ctx *c, int K) {
+// Checkpoints of a tape of K steps with stride s: U_0, U_s, ..., U_{floor(K/s) s}, and U_K.
+int tape_points(int K, int s) { return K / s + 1 + (K % s ? 1 : 0); }
+// Slot of checkpoint n (a multiple of s, or K).
+int tape_slot(int K, int s, int n) { return n % s ? K / s + 1 : n / s; }
+
+// The smallest stride whose checkpoints and one segment's s - 1 states fit the budget.
+int tape_stride(int K, int budget) {
+    if (budget <= 0) return 1;
+    for (int s = 1; s <= K + 1; ++s)
+        if (tape_points(K, s) + (s - 1) <= budget) return s;
+    return 0;
+}
+
+qo_status tape_alloc(qo_ctx *c, int K, int s) {
     const size_t blk = (size_t)c->ld * c->N;
-    qo_status s = QO_OK;
-    while (s == QO_OK && (int)c->tape.size() < K + 1) {
-        double *p = nullptr;
-        s = dalloc(c, &p, blk);
-        if (s == QO_OK) c->tape.push_back(p);
-    }
-    for (int i = 0; i < 6 && s == QO_OK; ++i)
-        if (!c->ab[i]) s = dalloc(c, &c->ab[i], blk);
-    if (s == QO_OK && !c->gVd) s = dalloc(c, &c->gVd, (size_t)c->ng);
-    if (s == QO_OK && !c->adpool) s = dalloc(c, &c->adpool, nn_adjoint_pool_elems(c->N));
-    if (s == QO_OK && !c->admat) s = dalloc(c, &c->admat, (size_t)AM_COUNT * c->N * c->N);
-    return s;
+    qo_status st = QO_OK;
+    auto grow = [&](std::vector<double *> &v, int count) {
+        while (st == QO_OK && (int)v.size() < count) {
+            double *p = nullptr;
+            st = dalloc(c, &p, blk);
+            if (st == QO_OK) v.push_back(p);
+        }
+    };
+    grow(c->tape, tape_points(K, s));
+    grow(c->tseg, s - 1);
+    for (int i = 0; i < 6 && st == QO_OK; ++i)
+        if (!c->ab[i]) st = dalloc(c, &c->ab[i], blk);
+    if (st == QO_OK && !c->gVd) st = dalloc(c, &c->gVd, (size_t)c->ng);
+    if (st == QO_OK && !c->adpool) st = dalloc(c, &c->adpool, nn_adjoint_pool_elems(c->N));
+    if (st == QO_OK && !c->admat) st = dalloc(c, &c->admat, (size_t)AM_COUNT * c->N * c->N);
+    return st;
 }
 
 qo_status blk_axpby(qo_ctx *c, double *Y, const double *X, double a, double b) {
@@ -2269,18 +2289,23 @@ qo_status qo_tape_forward(qo_handle h, double tau, int K, int loss, double *L) {
     if (h->mixed) return fail(h, QO_ERR_ARG, "the tape needs precision QO_FP64");
     if (!(tau > 0.0) || K < 0 || K > 100000 || (loss != 0 && loss != 1))
         return fail(h, QO_ERR_ARG, "bad tau, K or loss");
-    QOC(tape_alloc(h, K));
+    const int stride = tape_stride(K, h->tape_budget);
+    if (stride < 1)
+        return fail(h, QO_ERR_ARG, "no checkpoint stride fits %d steps in %d blocks", K,
+                    h->tape_budget);
+    h->have_tape = false;
+    QOC(tape_alloc(h, K, stride));
     const size_t bytes = sizeof(double) * h->ld * h->N;
     const int warm = h->cfg.warm_start;
     h->cfg.warm_start = 0;
-    h->have_tape = false;
     qo_status s = QO_OK;
     if (hipMemcpyAsync(h->tape[0], h->U, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess)
         s = fail(h, QO_ERR_DEVICE, "tape copy failed");
     for (int n = 0; n < K && s == QO_OK; ++n) {
         s = one_step(h, tau, nullptr);
-        if (s == QO_OK && hipMemcpyAsync(h->tape[n + 1], h->U, bytes, hipMemcpyDeviceToDevice,
-                                         h->st) != hipSuccess)
+        if (s == QO_OK && ((n + 1) % stride == 0 || n + 1 == K) &&
+            hipMemcpyAsync(h->tape[tape_slot(K, stride, n + 1)], h->U, bytes,
+                           hipMemcpyDeviceToDevice, h->st) != hipSuccess)
             s = fail(h, QO_ERR_DEVICE, "tape copy failed");
     }
     h->cfg.warm_start = warm;
@@ -2289,9 +2314,19 @@ qo_status qo_tape_forward(qo_handle h, double tau, int K, int loss, double *L) {
     if (s != QO_OK) return s;
     QOC(loss_and_grad(h, loss, L, false));
     h->tape_K = K;
+    h->tape_s = stride;
     h->tape_tau = tau;
     h->tape_loss = loss;
     h->have_tape = true;
+    return QO_OK;
+}
+
+qo_status qo_tape_budget(qo_handle h, int blocks) {
+    if (!h) return QO_ERR_ARG;
+    if (blocks < 0 || (blocks > 0 && blocks < 3))
+        return fail(h, QO_ERR_ARG, "tape budget must be 0 or at least 3 blocks");
+    h->tape_budget = blocks;
+    h->have_tape = false;  // a tape taken under another bound is not reused
     return QO_OK;
 }
 
@@ -2308,13 +2343,29 @@ qo_status qo_tape_backward(qo_handle h, double seed, double *gV, double *gU0, lo
     int rounds = 0;
     const int warm = h->cfg.warm_start;
     h->cfg.warm_start = 0;
+    const int sd = h->tape_s;
+    double *const UK = h->tape[tape_slot(K, sd, K)];
     auto body = [&]() -> qo_status {
         double L = 0.0;
-        HIPC(h, hipMemcpyAsync(h->U, h->tape[K], bytes, hipMemcpyDeviceToDevice, st));
+        HIPC(h, hipMemcpyAsync(h->U, UK, bytes, hipMemcpyDeviceToDevice, st));
         h->zbU_ok = false;
         QOC(loss_and_grad(h, h->tape_loss, &L, true, seed));
         for (int n = K - 1; n >= 0; --n) {
-            double *Un = h->tape[n];
+            // U_n: a checkpoint, or a state of the segment [n0, n0 + sd) recomputed from
+            // checkpoint U_n0 (all of them when the adjoint enters the segment from above)
+            const int n0 = n - n % sd;
+            if (n % sd && (n == K - 1 || (n + 1) % sd == 0)) {
+                HIPC(h, hipMemcpyAsync(h->U, h->tape[n0 / sd], bytes, hipMemcpyDeviceToDevice,
+                                       st));
+                for (int m = n0; m < n; ++m) {
+                    h->zbU_ok = false;
+                    h->have_warm = false;
+                    QOC(one_step(h, tau, nullptr));
+                    HIPC(h, hipMemcpyAsync(h->tseg[m - n0], h->U, bytes,
+                                           hipMemcpyDeviceToDevice, st));
+                }
+            }
+            double *Un = n % sd ? h->tseg[n % sd - 1] : h->tape[n / sd];
             // recompute step n (cold solves: the same arithmetic as the taped forward)
             HIPC(h, hipMemcpyAsync(h->U, Un, bytes, hipMemcpyDeviceToDevice, st));
             h->zbU_ok = false;
@@ -2377,7 +2428,7 @@ qo_status qo_tape_backward(qo_handle h, double seed, double *gV, double *gU0, lo
             HIPC(h, hipMemcpyAsync(gV, h->gVd, sizeof(double) * h->ng,
                                    on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                                    st));
-        HIPC(h, hipMemcpyAsync(h->U, h->tape[K], bytes, hipMemcpyDeviceToDevice, st));
+        HIPC(h, hipMemcpyAsync(h->U, UK, bytes, hipMemcpyDeviceToDevice, st));
         h->zbU_ok = false;
         HIPC(h, hipStreamSynchronize(st));
         return QO_OK;

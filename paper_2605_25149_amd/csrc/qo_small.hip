@@ -172,7 +172,7 @@ __global__ __launch_bounds__(GJT) void k_gj(double *__restrict__ A, int lda,
 // the unblocked kernel above; a column's updates are grouped per panel.
 constexpr int GB = 32;
 constexpr int GPT = 512;
-constexpr int GCW = 16;  // columns per update workgroup
+constexpr int GCW = 4;  // columns per update workgroup (many workgroups: the update is spread over the CUs)
 
 __global__ __launch_bounds__(GPT) void k_gjb_panel(double *__restrict__ A, int lda, int n, int k0,
                                                    int b, int spd, double *__restrict__ work,

@@ -227,21 +227,21 @@ __global__ __launch_bounds__(256) void k_split3(const double *__restrict__ Xr,
 }
 
 // One workgroup: 64 grid rows from m0 x up to 128 columns (wave w: the 32-column tile
-// c0 = 128 blockIdx.y' + 32 w).  Each 32-k chunk of both operands passes through LDS: the
-// big operand's 64 rows x 32 FP64 values (512-byte coalesced rows), split and stored as
-// the MFMA B operand (8 consecutive k of one row per 16 bytes); the small operand's split
-// parts for the workgroup's columns (contiguous 16-byte pieces) as the A operand.  Every
-// global load belongs to the staging of a chunk two ahead of the one multiplied.  Output
-// layout (the 16x16 FP32 accumulator): value v of lane l is row 4 (l/16) + v, column l%16
-// of Out^T.
+// c0 = 128 blockIdx.y' + 32 w).  The big operand passes through LDS in 32-k chunks: 64 rows
+// x 32 FP64 values (512-byte coalesced rows), split and stored as the MFMA B operand (8
+// consecutive k of one row per 16 bytes), shared by the four waves.  The small operand's
+// split parts are read by each wave straight from global memory (L2) into its A fragments:
+// no wave uses another's columns, so an LDS round trip would only add LDS traffic (the
+// limit of this kernel).  Big-operand chunks are loaded three chunks ahead of their
+// product and staged one ahead; a wave's A fragments two ahead.  Output layout (the 16x16
+// FP32 accumulator): value v of lane l is row 4 (l/16) + v, column l%16 of Out^T.
 constexpr int kB3Cols = 128;  // columns per workgroup
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tsgemm_b3(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_tsgemm_b3(
     double *__restrict__ Out, long ldo, const double *__restrict__ C0,
     const double *__restrict__ A, const double *__restrict__ B, const v8bf *__restrict__ S,
     int Kp, int nq, long ld, long ng, int n, __bf16 *__restrict__ Zb) {
-    __shared__ __align__(16) v8bf sb[2][3][4][64];         // [buffer][part][k group][row]
-    __shared__ __align__(16) v8bf sa[2][3][4][kB3Cols];    // [buffer][part][k group][column]
+    __shared__ __align__(16) v8bf sb[2][3][4][64];  // [buffer][part][k group][row]
     const int tid = threadIdx.x, lane = tid & 63;
     // the wave index is wave-uniform: in a scalar register, the big operand's k (and its
     // column address) is scalar arithmetic
@@ -265,18 +265,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int u = 0; u < 8; ++u) v[u] = T[(long)min(kc + u, n - 1) * ld + mrow];
     };
-    // small-operand staging: thread -> column sc of the workgroup (clamped: columns past n
-    // reach only outputs never stored), k groups 2 sh and 2 sh + 1, all three parts
-    const int sc = tid & (kB3Cols - 1), sh = tid >> 7;
-    const long scol = min(cwg + sc, n - 1);
-    auto sload = [&](int ch, v8bf (&t)[6]) {
-        const v8bf *base = S + (long)ch * 3 * 4 * n + scol;
+    // A fragments of chunk ch: parts p of columns c0 + 16 j + lr, k group lg (16 lanes read
+    // 256 contiguous bytes).  Clamped columns past n reach only outputs never stored.
+    const int ca0 = min(c0 + lr, n - 1), ca1 = min(c0 + 16 + lr, n - 1);
+    auto aload = [&](int ch, v8bf (&a)[2][3]) {
+        const v8bf *base = S + ((long)ch * 3 * 4 + lg) * n;
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
-#pragma unroll
-            for (int x = 0; x < 2; ++x) t[2 * p + x] = base[(long)(p * 4 + 2 * sh + x) * n];
+        for (int p = 0; p < 3; ++p) {
+            a[0][p] = base[(long)p * 4 * n + ca0];
+            a[1][p] = base[(long)p * 4 * n + ca1];
+        }
     };
-    auto sstore = [&](int buf, const double (&v)[8], const v8bf (&t)[6]) {
+    auto sstore = [&](int buf, const double (&v)[8]) {
         v8bf p0, p1, p2;
 #pragma unroll
         for (int u = 0; u < 8; u += 2) {
@@ -292,22 +292,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         sb[buf][0][w][lane] = p0;
         sb[buf][1][w][lane] = p1;
         sb[buf][2][w][lane] = p2;
-#pragma unroll
-        for (int p = 0; p < 3; ++p)
-#pragma unroll
-            for (int x = 0; x < 2; ++x) sa[buf][p][2 * sh + x][sc] = t[2 * p + x];
     };
     v4f acc[2][4];  // [column block j][row block i]
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[j][i] = v4f{0.f, 0.f, 0.f, 0.f};
-    auto mma = [&](int buf) {
-        v8bf a[2][3];
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int p = 0; p < 3; ++p) a[j][p] = sa[buf][p][lg][32 * w + 16 * j + lr];
+    auto mma = [&](int buf, const v8bf (&a)[2][3]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const v8bf b1 = sb[buf][0][lg][16 * i + lr];
@@ -327,40 +318,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
     };
     {
-        // Chunk ch is multiplied from LDS buffer ch & 1 while chunk ch + 1, staged into the
-        // other buffer just before, waits there, and the registers of one set load chunk
-        // ch + 3 (issued before the multiplication, so that each chunk's loads are in flight
-        // for two of them).  nch is even (Kp is a multiple of 64); loads past the end
-        // re-read the last chunk, so that every load and wait is unconditional.  The loop
-        // is entered unconditionally (nch >= 2), so that the prologue's loads stay where
-        // they are issued.
+        // Chunk ch is multiplied from LDS buffer ch & 1 with the A fragments of register
+        // set ch & 1, while the big operand of chunk ch + 1 waits staged in the other
+        // buffer and the big-operand registers of one set load chunk ch + 3 (issued before
+        // the product); after the product its A set loads chunk ch + 2.  nch is even (Kp
+        // is a multiple of 64); loads past the end re-read the last chunk, so that every
+        // load and wait is unconditional.  The loop is entered unconditionally (nch >= 2),
+        // so that the prologue's loads stay where they are issued.
         double v0[8], v1[8];
-        v8bf t0[6], t1[6];
+        v8bf a0[2][3], a1[2][3];
         const int last = nch - 1;
         gload(0, v0);
-        sload(0, t0);
+        aload(0, a0);
         gload(1, v1);
-        sload(1, t1);
+        aload(1, a1);
         __builtin_amdgcn_sched_barrier(0);
-        sstore(0, v0, t0);
+        sstore(0, v0);
         gload(min(2, last), v0);
-        sload(min(2, last), t0);
         __syncthreads();
         int ch = 0;
         do {
             // v1: chunk ch + 1, v0: chunk ch + 2 (loading)
-            sstore(1, v1, t1);
+            sstore(1, v1);
             gload(min(ch + 3, last), v1);
-            sload(min(ch + 3, last), t1);
             __builtin_amdgcn_sched_barrier(0);
-            mma(0);
+            mma(0, a0);
+            __builtin_amdgcn_sched_barrier(0);
+            aload(min(ch + 2, last), a0);
             __syncthreads();
             // v0: chunk ch + 2, v1: chunk ch + 3 (loading)
-            sstore(0, v0, t0);
+            sstore(0, v0);
             gload(min(ch + 4, last), v0);
-            sload(min(ch + 4, last), t0);
             __builtin_amdgcn_sched_barrier(0);
-            mma(1);
+            mma(1, a1);
+            __builtin_amdgcn_sched_barrier(0);
+            aload(min(ch + 3, last), a1);
             __syncthreads();
             ch += 2;
         } while (ch < nch);

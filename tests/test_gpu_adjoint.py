@@ -215,3 +215,42 @@ def test_tape_full_size_directional(torch, B, loss):
             worst = max(worst, rV, rU)
     print(f"L {L:.12e}; worst relative difference over 16 directions {worst:.2e}")
     assert worst <= 1e-4
+
+
+@pytest.mark.parametrize("dim,n,K,budget,loss,precond", [
+    (2, (20, 17), 11, 7, "ritz_sum", "fast_poisson"),  # stride 3, a partial last segment
+    (3, (10, 9, 8), 9, 6, "energy", "jacobi"),         # stride 3, full segments
+])
+def test_tape_budget_is_bit_identical(torch, B, dim, n, K, budget, loss, precond):
+    """qo_tape_budget: with the tape bounded to `budget` state blocks (checkpoints every
+    s-th step plus one recomputed segment) the gradients w.r.t. V and U_0 and the loss are
+    bit for bit those of the unbounded tape, and the state afterwards is U_K.  A bound too
+    small for K steps is refused by qo_tape_forward, a bound of 1 or 2 by qo_tape_budget."""
+    N, tau = 3, 8.0
+    V = _problem(dim, n)
+    ng = int(np.prod(n))
+    U0 = inputs.random_block(ng, N, seed=2)
+    out = []
+    for b in (0, budget):
+        with B.Solver(dim, n, N, sigma=0.3, pcg_tol=TOL, pcg_check=1, precond=precond) as s:
+            s.set_potential(V)
+            s.set_state(U0)
+            s.tape_budget(b)
+            L = s.tape_forward(tau, K, loss)
+            UK = s.get_state().clone()
+            gV, gU = s.tape_backward()
+            assert torch.equal(s.get_state(), UK)
+            out.append((L, gV.clone(), gU.clone(), UK))
+    (L0, gV0, gU0, UK0), (L1, gV1, gU1, UK1) = out
+    assert L0 == L1
+    assert torch.equal(UK0, UK1)
+    assert torch.equal(gV0, gV1)
+    assert torch.equal(gU0, gU1)
+    with B.Solver(dim, n, N, sigma=0.3, pcg_tol=TOL, pcg_check=1, precond=precond) as s:
+        s.set_potential(V)
+        s.set_state(U0)
+        with pytest.raises(B.QOError, match="QO_ERR_ARG"):
+            s.tape_budget(2)
+        s.tape_budget(3)
+        with pytest.raises(B.QOError, match="QO_ERR_ARG"):
+            s.tape_forward(tau, K, loss)  # 3 blocks hold no stride for K >= 3

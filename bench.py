@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -501,13 +502,32 @@ def run_adjoint(K, log, n=64, N=32, tau=6.0):
         s.step(tau, K)
         torch.cuda.synchronize()
         t4 = time.perf_counter()
+        # the same tape bounded to about 2 sqrt(K) + 1 state blocks (checkpoints every s-th
+        # state, one segment recomputed during the backward pass): same gradients bit for bit
+        budget = int(2 * math.isqrt(K) + 1)
+        s.tape_budget(budget)
+        for rep in range(2):
+            s.set_state(U0)
+            torch.cuda.synchronize()
+            t5 = time.perf_counter()
+            Lb = s.tape_forward(tau, K, "ritz_sum")
+            t6 = time.perf_counter()
+            gVb, gUb = s.tape_backward()
+            torch.cuda.synchronize()
+            t7 = time.perf_counter()
+        s.tape_budget(0)
     out.update(loss=L, forward_s=round(t1 - t0, 4), backward_s=round(t2 - t1, 4),
                plain_steps_s=round(t4 - t3, 4),
                backward_over_forward=round((t2 - t1) / (t1 - t0), 3),
                grad_V_norm=float(torch.linalg.vector_norm(gV)),
-               grad_U0_norm=float(torch.linalg.vector_norm(gU)))
+               grad_U0_norm=float(torch.linalg.vector_norm(gU)),
+               bounded_tape={"state_blocks": budget, "full_tape_blocks": K + 1,
+                             "forward_s": round(t6 - t5, 4), "backward_s": round(t7 - t6, 4),
+                             "gradients_bit_identical": bool(Lb == L and torch.equal(gVb, gV)
+                                                             and torch.equal(gUb, gU))})
     log(f"[adjoint] {out['workload']}: forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s, "
-        f"plain {K} steps {t4 - t3:.3f} s")
+        f"plain {K} steps {t4 - t3:.3f} s; bounded tape ({budget} blocks): forward "
+        f"{t6 - t5:.3f} s, backward {t7 - t6:.3f} s")
     return out
 
 

@@ -466,6 +466,21 @@ def run_batch(count, steps, log, precisions=("fp64", "mixed")):
         res["speedup_vs_sequential"] = round(
             max(res["eager_instance_steps_per_s"], res["graph_instance_steps_per_s"]) /
             res["sequential_instance_steps_per_s"], 3)
+        # Step roofline of the batch, an UPPER bound of the achieved HBM rate: every column
+        # counted for its instance's largest PCG count in both solves (converged columns are
+        # frozen on the device and move nothing), at the algorithmic bytes per point-column
+        # of one PCG iteration (FP64: 80; mixed FP32 PCG: 40, plus one FP64 residual pass of
+        # 32 per round) and 13 FP64 block streams per step for the rest (Grams, updates,
+        # corrector, energy).
+        colpts = sum(p["n"][0] * p["n"][1] * p["N"] for p in probs)
+        per_it = 80 if prec == "fp64" else 40
+        rounds = res["max_refine_rounds"] if prec != "fp64" else 0
+        bytes_step = colpts * (2 * res["max_pcg_iters"] * per_it + 2 * rounds * 32 + 13 * 8)
+        best = max(res["eager_instance_steps_per_s"], res["graph_instance_steps_per_s"])
+        gbs = bytes_step * best / count / 1e9
+        res["step_roofline_upper"] = {"bytes_per_step": int(bytes_step), "GB/s": round(gbs, 1),
+                                      "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
+                                      "point_columns": int(colpts)}
         out[prec] = res
     return out
 

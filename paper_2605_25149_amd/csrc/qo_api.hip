@@ -1086,10 +1086,11 @@ qo_status gram(qo_ctx *c, const double *X, const double *Y, long ld, int n, doub
 // fp32: the FP32-arithmetic update of the mixed-precision step (see launch_tsgemm); zb
 // receives its BF16 copy
 qo_status tsgemm(qo_ctx *c, double *Out, const double *C0, const double *A, const double *Xr,
-                 const double *Bm, const double *Yr, bool fp32 = false, __bf16 *zb = nullptr) {
+                 const double *Bm, const double *Yr, bool fp32 = false, __bf16 *zb = nullptr,
+                 double *Out2 = nullptr, const double *Zr = nullptr) {
     hipEvent_t e = prof_begin(c);
     HIPC(c, launch_tsgemm(Out, c->ld, C0, A, Xr, Bm, Yr, c->ld, c->ng, c->N, c->st, fp32, zb,
-                          fp32 ? c->split3 : nullptr));
+                          fp32 ? c->split3 : nullptr, Out2, Zr));
     prof_end(c, QO_KERNEL_UPDATE, e);
     return QO_OK;
 }
@@ -1289,10 +1290,11 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
     HIPC(c, hipMemcpyAsync(stat_slot(c), c->dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(c, hipEventRecord(c->sev, st));
     rec(c, 3);
-    // QO_MIXED: the block updates in FP32 arithmetic (the Grams of that path are BF16)
+    // U_hat = U X + P Y and, with warm starts, x0 = P Z in one launch that reads P once
+    // (QO_MIXED: FP32-accurate arithmetic; the Grams of that path are BF16)
     QOC(tsgemm(c, c->Uh, nullptr, c->U, mp(c, MP_XR), P, mp(c, MP_YR), c->mixed,
-               c->mixed ? c->zbUh : nullptr));
-    if (warm) QOC(tsgemm(c, Q, nullptr, P, mp(c, MP_ZR), nullptr, nullptr, c->mixed));
+               c->mixed ? c->zbUh : nullptr, warm ? Q : nullptr,
+               warm ? mp(c, MP_ZR) : nullptr));
     rec(c, 4);
     const qo_status sQ = solve_block(c, c->Uh, Q, N, warm, itsQ.data(), &rQ, "solve G U_hat");
     HIPC(c, hipEventSynchronize(c->sev));

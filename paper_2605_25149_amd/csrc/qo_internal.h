@@ -321,12 +321,16 @@ hipError_t launch_tsgemm_batch(const TsJob *jobs, int njobs, int max_n, long ld,
 // in FP64) on BF16 MFMA with each operand split into three BF16 parts, for the
 // mixed-precision path; needs `split` (tsgemm_split_elems(n) BF16 of scratch).  There Zb
 // (optional) receives Out rounded to BF16 (nearest-even from the stored FP64 value) in the
-// row-blocked layout of the BF16 Gram operands (see launch_gram_bf16).
+// row-blocked layout of the BF16 Gram operands (see launch_gram_bf16).  Out2 (with its
+// small operand ZsT; both big operands given, no C0) receives the second product B Zs in
+// the same launch, so that B is read from HBM once for both (the predictor update U_hat =
+// U X + P Y with the warm start P (X + C Y) of the next solve).
 size_t tsgemm_split_elems(int n);
 hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
                          const double *XsT, const double *B, const double *YsT, long ld,
                          long ng, int n, hipStream_t st, bool fp32 = false,
-                         __bf16 *Zb = nullptr, __bf16 *split = nullptr);
+                         __bf16 *Zb = nullptr, __bf16 *split = nullptr,
+                         double *Out2 = nullptr, const double *ZsT = nullptr);
 
 // ---- small dense FP64 (qo_small.hip), all column-major with explicit ld ----
 // C = alpha op(A) op(B) + beta C + gamma I

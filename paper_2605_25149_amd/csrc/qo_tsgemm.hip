@@ -39,7 +39,7 @@ __device__ __forceinline__ void tsgemm_tile(double *__restrict__ Out, long ldo,
                                             const double *__restrict__ Xr,
                                             const double *__restrict__ B,
                                             const double *__restrict__ Yr, long ld, long ng,
-                                            int n, long m0, int c0) {
+                                            int n, long m0, int c0, bool b_first = false) {
     const int lane = threadIdx.x;
     const int lr = lane & 15, lg = lane >> 4;
 
@@ -137,8 +137,11 @@ __device__ __forceinline__ void tsgemm_tile(double *__restrict__ Out, long ldo,
             mma_chunk(sa0, tb0);
         }
     };
+    // b_first: the second operand pair first (the predictor update with its warm start, whose
+    // tiles of one row panel then read P at about the same time)
+    if (b_first && B) pass(B, Yr);
     if (A) pass(A, Xr);
-    if (B) pass(B, Yr);
+    if (!b_first && B) pass(B, Yr);
     // FP64 16x16 accumulator layout: value v of lane l is row l/16 + 4v, column l%16,
     // so acc[j][i][v] = Out^T[c0 + 16j + lg + 4v][m0 + 16i + lr]
 #pragma unroll
@@ -196,30 +199,34 @@ __device__ __forceinline__ void split3_pair(double x0, double x1, v2bf &h1, v2bf
 // Small operands, split, in chunks of 32 k: S[ch][p][g][c][e] = part p of the operand's
 // element (k, c) with k = 32 ch + 8 g + e over the concatenated k range of the nq operands
 // (operand q covers k in [q Kp, q Kp + n) of (q ? Yr : Xr), row-major n x n; zero for
-// k >= n within an operand; Kp = n rounded up to 64).  A workgroup's columns of one
-// (chunk, part, k group) are contiguous 16-byte pieces.
+// k >= n within an operand; Kp = n rounded up to 64), c < nc.  With a second output
+// (Zr != nullptr, nq = 2, nc = 2n) columns n .. 2n - 1 hold its operand [0; Zr]: the first
+// big operand does not enter it.  A workgroup's columns of one (chunk, part, k group) are
+// contiguous 16-byte pieces.
 __global__ __launch_bounds__(256) void k_split3(const double *__restrict__ Xr,
-                                                const double *__restrict__ Yr, int n, int Kp,
-                                                int nq, __bf16 *__restrict__ S) {
-    const long total = (long)n * nq * Kp;  // elements per part
+                                                const double *__restrict__ Yr,
+                                                const double *__restrict__ Zr, int n, int nc,
+                                                int Kp, int nq, __bf16 *__restrict__ S) {
+    const long total = (long)nc * nq * Kp;  // elements per part
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
-        // e = ((ch * 4 + g) * n + c) * 8 + x, part-major afterwards
+        // e = ((ch * 4 + g) * nc + c) * 8 + x, part-major afterwards
         const int x = (int)(e & 7);
         const long r = e >> 3;
-        const int c = (int)(r % n);
-        const long cg = r / n;
+        const int c = (int)(r % nc);
+        const long cg = r / nc;
         const int g = (int)(cg & 3);
         const int ch = (int)(cg >> 2);
         const int kk = ch * 32 + g * 8 + x;
         const int q = kk >= Kp ? 1 : 0;
         const int k = kk - q * Kp;
-        const double *M = q ? Yr : Xr;
-        const float f = k < n ? (float)M[(long)k * n + c] : 0.0f;
+        const bool second = c >= n;  // only with Zr
+        const double *M = second ? (q ? Zr : nullptr) : (q ? Yr : Xr);
+        const float f = (k < n && M) ? (float)M[(long)k * n + (second ? c - n : c)] : 0.0f;
         __bf16 b1, b2, b3;
         split3(f, b1, b2, b3);
-        const long o = (((long)ch * 3 * 4 + g) * n + c) * 8 + x;  // part 0
-        const long ps = 4L * n * 8;                               // part stride in a chunk
+        const long o = (((long)ch * 3 * 4 + g) * nc + c) * 8 + x;  // part 0
+        const long ps = 4L * nc * 8;                                // part stride in a chunk
         S[o] = b1;
         S[o + ps] = b2;
         S[o + 2 * ps] = b3;
@@ -240,7 +247,8 @@ constexpr int kB3Cols = 128;  // columns per workgroup
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_tsgemm_b3(
     double *__restrict__ Out, long ldo, const double *__restrict__ C0,
     const double *__restrict__ A, const double *__restrict__ B, const v8bf *__restrict__ S,
-    int Kp, int nq, long ld, long ng, int n, __bf16 *__restrict__ Zb) {
+    int Kp, int nq, long ld, long ng, int n, __bf16 *__restrict__ Zb,
+    double *__restrict__ Out2, int gn) {
     __shared__ __align__(16) v8bf sb[2][3][4][64];  // [buffer][part][k group][row]
     const int tid = threadIdx.x, lane = tid & 63;
     // the wave index is wave-uniform: in a scalar register, the big operand's k (and its
@@ -251,11 +259,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int rt = L / gridDim.y;
     const long m0 = (long)rt * 64;
-    const int cwg = (L - rt * (int)gridDim.y) * kB3Cols;  // the workgroup's first column
+    // Column groups gn and up (only with Out2) compute the second output B Zs: columns
+    // n .. 2n - 1 of the split operand, and only the second big operand's chunks.
+    const int gy = L - rt * (int)gridDim.y;
+    const bool second = Out2 != nullptr && gy >= gn;
+    const int nc = Out2 ? 2 * n : n;                           // columns of the split operand
+    const int cbase = second ? n : 0;                          // this group's first of them
+    const int cwg = (second ? gy - gn : gy) * kB3Cols;         // the group's first output column
     const int c0 = cwg + 32 * w;
     const bool wact = c0 < n;
     const int cpq = Kp >> 5;  // chunks per operand
     const int nch = nq * cpq;
+    // With a second output every group of a row panel starts with the second big operand's
+    // chunks, so that the panel's groups read its rows at about the same time (one HBM
+    // read, the rest from L2); the first output's groups then take the first operand's.
+    // Chunk i of the group is (rot + i) mod nch, for i < cnt (cnt even).
+    const int rot = Out2 ? cpq : 0;
+    const int cnt = second ? cpq : nch;
     // big-operand staging: thread -> row (lane) of the tile; wave w holds k group w
     const long mrow = min(m0 + lane, ng - 1);
     auto gload = [&](int ch, double (&v)[8]) {
@@ -267,13 +287,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     };
     // A fragments of chunk ch: parts p of columns c0 + 16 j + lr, k group lg (16 lanes read
     // 256 contiguous bytes).  Clamped columns past n reach only outputs never stored.
-    const int ca0 = min(c0 + lr, n - 1), ca1 = min(c0 + 16 + lr, n - 1);
+    const int ca0 = cbase + min(c0 + lr, n - 1), ca1 = cbase + min(c0 + 16 + lr, n - 1);
     auto aload = [&](int ch, v8bf (&a)[2][3]) {
-        const v8bf *base = S + ((long)ch * 3 * 4 + lg) * n;
+        const v8bf *base = S + ((long)ch * 3 * 4 + lg) * nc;
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            a[0][p] = base[(long)p * 4 * n + ca0];
-            a[1][p] = base[(long)p * 4 * n + ca1];
+            a[0][p] = base[(long)p * 4 * nc + ca0];
+            a[1][p] = base[(long)p * 4 * nc + ca1];
         }
     };
     auto sstore = [&](int buf, const double (&v)[8]) {
@@ -327,35 +347,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         // so that the prologue's loads stay where they are issued.
         double v0[8], v1[8];
         v8bf a0[2][3], a1[2][3];
-        const int last = nch - 1;
-        gload(0, v0);
-        aload(0, a0);
-        gload(1, v1);
-        aload(1, a1);
+        const int last = cnt - 1;
+        auto chk = [&](int i) {  // actual chunk of loop position i (past the end: the last)
+            const int j = rot + min(i, last);
+            return j >= nch ? j - nch : j;
+        };
+        gload(chk(0), v0);
+        aload(chk(0), a0);
+        gload(chk(1), v1);
+        aload(chk(1), a1);
         __builtin_amdgcn_sched_barrier(0);
         sstore(0, v0);
-        gload(min(2, last), v0);
+        gload(chk(2), v0);
         __syncthreads();
         int ch = 0;
         do {
             // v1: chunk ch + 1, v0: chunk ch + 2 (loading)
             sstore(1, v1);
-            gload(min(ch + 3, last), v1);
+            gload(chk(ch + 3), v1);
             __builtin_amdgcn_sched_barrier(0);
             mma(0, a0);
             __builtin_amdgcn_sched_barrier(0);
-            aload(min(ch + 2, last), a0);
+            aload(chk(ch + 2), a0);
             __syncthreads();
             // v0: chunk ch + 2, v1: chunk ch + 3 (loading)
             sstore(0, v0);
-            gload(min(ch + 4, last), v0);
+            gload(chk(ch + 4), v0);
             __builtin_amdgcn_sched_barrier(0);
             mma(1, a1);
             __builtin_amdgcn_sched_barrier(0);
-            aload(min(ch + 3, last), a1);
+            aload(chk(ch + 3), a1);
             __syncthreads();
             ch += 2;
-        } while (ch < nch);
+        } while (ch < cnt);
     }
     if (!wact) return;
     // C0 for every value of the tile first (clamped, unconditional loads issued together),
@@ -382,8 +406,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 const int c = c0 + 16 * j + 4 * lg + v;
                 if (c < n) {
                     const double o = c0v[j][i][v] + (double)acc[j][i][v];
-                    Out[(long)c * ldo + m] = o;
-                    if (Zb) Zb[bf16_rowblock_index(m, c, n)] = dev::f64_to_bf16_rne(o);
+                    if (second) {
+                        Out2[(long)c * ldo + m] = o;
+                    } else {
+                        Out[(long)c * ldo + m] = o;
+                        if (Zb) Zb[bf16_rowblock_index(m, c, n)] = dev::f64_to_bf16_rne(o);
+                    }
                 }
             }
         }
@@ -395,11 +423,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                                const double *__restrict__ Xr,
                                                const double *__restrict__ B,
                                                const double *__restrict__ Yr, long ld, long ng,
-                                               int n) {
-    // column tiles of one row panel on one XCD: they read the same rows of A and B
+                                               int n, double *__restrict__ Out2,
+                                               const double *__restrict__ Zr, int tn) {
+    // column tiles of one row panel on one XCD: they read the same rows of A and B; tiles
+    // tn and up (only with Out2) compute the second output B Zr
     const int L = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int rt = L / gridDim.y;
-    tsgemm_tile(Out, ldo, C0, A, Xr, B, Yr, ld, ng, n, (long)rt * 64, (L - rt * gridDim.y) * 64);
+    const int ct = L - rt * (int)gridDim.y;
+    if (Out2 && ct >= tn)
+        tsgemm_tile(Out2, ldo, nullptr, nullptr, nullptr, B, Zr, ld, ng, n, (long)rt * 64,
+                    (ct - tn) * 64);
+    else
+        tsgemm_tile(Out, ldo, C0, A, Xr, B, Yr, ld, ng, n, (long)rt * 64, ct * 64,
+                    Out2 != nullptr);
 }
 
 // Grouped batches: job blockIdx.z; row tile blockIdx.x, column tile blockIdx.y.
@@ -421,36 +457,45 @@ hipError_t launch_tsgemm_batch(const TsJob *jobs, int njobs, int max_n, long ld,
     return hipGetLastError();
 }
 
-size_t tsgemm_split_elems(int n) { return (size_t)3 * n * 2 * ((n + 63) / 64 * 64); }
+size_t tsgemm_split_elems(int n) { return (size_t)3 * (2 * n) * 2 * ((n + 63) / 64 * 64); }
 
 hipError_t launch_tsgemm(double *Out, long ldo, const double *C0, const double *A,
                          const double *Xr, const double *B, const double *Yr, long ld, long ng,
-                         int n, hipStream_t st, bool fp32, __bf16 *Zb, __bf16 *split) {
+                         int n, hipStream_t st, bool fp32, __bf16 *Zb, __bf16 *split,
+                         double *Out2, const double *Zr) {
     if (n <= 0 || ng <= 0) return hipSuccess;
     // each big operand needs its small operand (and the reverse); the FP32-accurate path
-    // needs its split scratch; a BF16 copy only from that path
+    // needs its split scratch; a BF16 copy only from that path; a second output needs both
+    // big operands, its small operand and no C0
     if ((A == nullptr) != (Xr == nullptr) || (B == nullptr) != (Yr == nullptr) || !Out ||
-        (Zb && !fp32) || (fp32 && !split))
+        (Zb && !fp32) || (fp32 && !split) || ((Out2 == nullptr) != (Zr == nullptr)) ||
+        (Out2 && (!A || !B || C0)))
         return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((ng + 63) / 64), (unsigned)((n + 63) / 64));
     if (fp32) {
         // the split small operands (k padded with zeros to a multiple of 64: an even number
-        // of 32-k chunks), then 128-column workgroups
+        // of 32-k chunks), then 128-column workgroups (twice as many with a second output)
         const int Kp = (n + 63) / 64 * 64;
         const int nq = (A ? 1 : 0) + (B ? 1 : 0);
         if (nq == 0) return hipErrorInvalidValue;
         const double *X1 = A ? Xr : Yr, *X2 = A ? Yr : nullptr;
         const double *T1 = A ? A : B, *T2 = A ? B : nullptr;
-        const long items = (long)n * nq * Kp;
+        const int nc = Out2 ? 2 * n : n;
+        const long items = (long)nc * nq * Kp;
         const unsigned blocks = (unsigned)std::min<long>((items + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_split3, dim3(blocks), dim3(256), 0, st, X1, X2, n, Kp, nq, split);
+        hipLaunchKernelGGL(k_split3, dim3(blocks), dim3(256), 0, st, X1, X2, Zr, n, nc, Kp, nq,
+                           split);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const dim3 g3((unsigned)((ng + 63) / 64), (unsigned)((n + kB3Cols - 1) / kB3Cols));
+        const int gn = (n + kB3Cols - 1) / kB3Cols;
+        const dim3 g3((unsigned)((ng + 63) / 64), (unsigned)(Out2 ? 2 * gn : gn));
         hipLaunchKernelGGL(k_tsgemm_b3, g3, dim3(256), 0, st, Out, ldo, C0, T1, T2,
-                           reinterpret_cast<const v8bf *>(split), Kp, nq, ld, ng, n, Zb);
+                           reinterpret_cast<const v8bf *>(split), Kp, nq, ld, ng, n, Zb, Out2,
+                           gn);
     } else {
-        hipLaunchKernelGGL(k_tsgemm, grid, dim3(64), 0, st, Out, ldo, C0, A, Xr, B, Yr, ld, ng, n);
+        const int tn = (n + 63) / 64;
+        const dim3 grid((unsigned)((ng + 63) / 64), (unsigned)(Out2 ? 2 * tn : tn));
+        hipLaunchKernelGGL(k_tsgemm, grid, dim3(64), 0, st, Out, ldo, C0, A, Xr, B, Yr, ld, ng, n,
+                           Out2, Zr, tn);
     }
     return hipGetLastError();
 }

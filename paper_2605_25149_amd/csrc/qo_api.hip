@@ -935,8 +935,13 @@ qo_status solve_bcg(qo_ctx *c, const double *B, double *X, int n, int use_x0, do
 }
 
 // X = G B for ncols columns of internal-layout blocks.  its: per column.
+// zb (optional, mixed fast-Poisson solves of all N columns): the row-blocked BF16 copy of
+// X that the Gram of the solution block reads; *zb_ok says whether the solve left it
+// holding X (its last residual pass formed X), so the Gram need not pack X itself.
 qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_x0, int *its,
-                      int *rounds, const char *what) {
+                      int *rounds, const char *what, __bf16 *zb = nullptr,
+                      bool *zb_ok = nullptr) {
+    if (zb_ok) *zb_ok = false;
     const double tol = c->cfg.pcg_tol;
     const bool one_sweep = c->cfg.pcg_variant == 1;
     if (!c->mixed && c->cfg.pcg_variant == 2) {
@@ -983,7 +988,8 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
         hipEvent_t er = prof_begin(c);
         if (pending) {
             HIPC(c, launch_resid_next(g, c->vs, B, xc, c->d32, xs, c->ld, c->r32, ncols, c->mask,
-                                      c->ps.its, c->part, st));
+                                      c->ps.its, c->part, st, ncols == c->N ? zb : nullptr,
+                                      c->N));
             std::swap(xc, xs);
             pending = false;
         } else {
@@ -1039,6 +1045,8 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
         if (done) {
             *rounds = round;
             done_rounds = round;
+            // round >= 1: the last pass was a fused residual pass, which formed X
+            if (zb_ok) *zb_ok = zb && fused && ncols == c->N && round >= 1;
             if (xc != X)
                 HIPC(c, hipMemcpyAsync(X, xc, sizeof(double) * c->ld * ncols,
                                        hipMemcpyDeviceToDevice, st));
@@ -1069,13 +1077,14 @@ qo_status solve_block(qo_ctx *c, const double *B, double *X, int ncols, int use_
 // copies of U and U_hat that their producers wrote (U is packed if it has changed otherwise
 // since) and packs the solution block; any other X is packed into the U_hat copy, which
 // only the step's own U_hat update fills before its Gram.
-qo_status gram(qo_ctx *c, const double *X, const double *Y, long ld, int n, double *G) {
+qo_status gram(qo_ctx *c, const double *X, const double *Y, long ld, int n, double *G,
+               bool y_packed = false) {
     hipEvent_t e = prof_begin(c);
     if (c->mixed) {
         const bool xu = X == c->U && n == c->N, xh = X == c->Uh && n == c->N;
         HIPC(c, launch_gram_bf16(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G,
-                                 xu ? c->zbU : c->zbUh, c->zbPQ, !xh && !(xu && c->zbU_ok), true,
-                                 c->st));
+                                 xu ? c->zbU : c->zbUh, c->zbPQ, !xh && !(xu && c->zbU_ok),
+                                 !(y_packed && n == c->N), c->st));
         if (xu) c->zbU_ok = true;
     } else
         HIPC(c, launch_gram_f64(X, Y, ld, c->ng, n, c->w, c->gpart, c->gnsplit, G, c->st));
@@ -1227,9 +1236,11 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
     if (c->emode == 1 && (!c->have_K || (c->eanchor > 0 && c->nstep % c->eanchor == 0)))
         QOC(anchor_K(c));
     rec(c, 0);
-    QOC(solve_block(c, c->U, P, N, warm && c->have_warm, itsP.data(), &rP, "solve G U_n"));
+    bool pP = false, pQ = false;  // the solves left the BF16 Gram copies of P, Q (mixed)
+    QOC(solve_block(c, c->U, P, N, warm && c->have_warm, itsP.data(), &rP, "solve G U_n",
+                    c->mixed ? c->zbPQ : nullptr, &pP));
     rec(c, 1);
-    QOC(gram(c, c->U, P, ld, N, c->G1));
+    QOC(gram(c, c->U, P, ld, N, c->G1, pP));
     rec(c, 2);
     double *S = c->G1;
     double *M = c->G1 + (size_t)N * N2;
@@ -1296,12 +1307,13 @@ qo_status one_step(qo_ctx *c, double tau, qo_step_stats *stats, double grad_stop
                c->mixed ? c->zbUh : nullptr, warm ? Q : nullptr,
                warm ? mp(c, MP_ZR) : nullptr));
     rec(c, 4);
-    const qo_status sQ = solve_block(c, c->Uh, Q, N, warm, itsQ.data(), &rQ, "solve G U_hat");
+    const qo_status sQ = solve_block(c, c->Uh, Q, N, warm, itsQ.data(), &rQ, "solve G U_hat",
+                                     c->mixed ? c->zbPQ : nullptr, &pQ);
     HIPC(c, hipEventSynchronize(c->sev));
     QOC(status_error(c, stat_slot(c)[0], "predictor N x N solve"));
     if (sQ != QO_OK) return sQ;
     rec(c, 5);
-    QOC(gram(c, c->Uh, Q, ld, N, c->G2));
+    QOC(gram(c, c->Uh, Q, ld, N, c->G2, pQ));
     rec(c, 6);
     // O = sym(<U_hat,U_hat>) - I ; corrector coefficient -tau O (symmetric => its own transpose)
     HIPC(c, nn_axpby(mp(c, MP_O), N, 0.5, c->G2, N2, 0.5, c->G2, N2, true, -1.0, N, N, st));

@@ -203,9 +203,11 @@ hipError_t launch_colsum(const double *part, int tiles, int ncols, int nq, long 
 // The refinement update fused into the next residual, out of place: Xn = X + D in the
 // columns with mask != 0 and its > 0 (the others: Xn = X), then the launch_resid outputs for
 // Xn.  X, D, Xn, R32 share the stride ld; Xn must not overlap X.
+// zb (optional): x_new rounded to BF16 into the row-blocked copy of a zn-column block.
 hipError_t launch_resid_next(const Grid &g, const double *vs, const double *B, const double *X,
                              const float *D, double *Xn, long ld, float *R32, int ncols,
-                             const int *mask, const int *its, double *part, hipStream_t st);
+                             const int *mask, const int *its, double *part, hipStream_t st,
+                             __bf16 *zb = nullptr, int zn = 0);
 // x += d (FP64 += FP32) for columns with mask != 0 (and d = 0 when zero_d).
 hipError_t launch_refine_axpy(double *X, long ld, float *D, long ld32, long ng, int ncols,
                               const int *mask, int zero_d, hipStream_t st);

@@ -490,7 +490,10 @@ __global__ __launch_bounds__(kThreads) void k_resid(Grid g, const double *__rest
 // x_new = x; then r = b - H x_new in FP64, r32 = (float) r, partials rr, bb.  x and d are
 // only read (the stencil forms x + d at the halo points too), x_new goes to its own block,
 // so no workgroup reads a value another one is changing.
-template <int PPT>
+// With zb, x_new rounded to BF16 (nearest-even) also goes to the row-blocked BF16 copy of
+// an zn-column block (the Gram operand of the solution block: the last pass of a solve
+// leaves it holding the solution).
+template <int PPT, bool ZB>
 __global__ __launch_bounds__(kThreads) void k_resid_next(Grid g, const double *__restrict__ vs,
                                                          const double *__restrict__ B,
                                                          const double *__restrict__ X,
@@ -499,7 +502,8 @@ __global__ __launch_bounds__(kThreads) void k_resid_next(Grid g, const double *_
                                                          float *__restrict__ R32,
                                                          const int *__restrict__ mask,
                                                          const int *__restrict__ its,
-                                                         double *__restrict__ part, long qs) {
+                                                         double *__restrict__ part, long qs,
+                                                         __bf16 *__restrict__ zb, int zn) {
     __shared__ Red red;
     int col, tile, band, zc;
     tile_of(g, col, tile, band, zc);
@@ -520,6 +524,8 @@ __global__ __launch_bounds__(kThreads) void k_resid_next(Grid g, const double *_
         const double *__restrict__ b;
         double *__restrict__ xn;
         float *__restrict__ r32;
+        __bf16 *__restrict__ zb;
+        int col, zn;
         double acc[2];
         __device__ static Raw zero() { return {0.0}; }
         __device__ Raw load(long i) const { return {b[i]}; }
@@ -532,10 +538,11 @@ __global__ __launch_bounds__(kThreads) void k_resid_next(Grid g, const double *_
             xn[i] = c;
             r32[i] = (float)r;
 #endif
+            if constexpr (ZB) zb[bf16_rowblock_index(i, col, zn)] = dev::f64_to_bf16_rne(c);
             acc[0] += r * r;
             acc[1] += e.b * e.b;
         }
-    } ep{B + (long)col * ld, Xn + (long)col * ld, R32 + (long)col * ld, {0.0, 0.0}};
+    } ep{B + (long)col * ld, Xn + (long)col * ld, R32 + (long)col * ld, zb, col, zn, {0.0, 0.0}};
     const bool upd = mask[col] != 0 && its[col] > 0;
     LdNext l{X + (long)col * ld, D + (long)col * ld, upd};
     engine<double, PPT>(g, band, zc, vs, l, ep, lds_ptr<double>());
@@ -1105,13 +1112,21 @@ hipError_t launch_resid(const Grid &g, const double *vs, const double *B, const 
 
 hipError_t launch_resid_next(const Grid &g, const double *vs, const double *B, const double *X,
                              const float *D, double *Xn, long ld, float *R32, int ncols,
-                             const int *mask, const int *its, double *part, hipStream_t st) {
+                             const int *mask, const int *its, double *part, hipStream_t st,
+                             __bf16 *zb, int zn) {
     if (ncols <= 0) return hipSuccess;
+    if (zb && zn < ncols) return hipErrorInvalidValue;
     const long qs = (long)ncols * g.tiles();
     const dim3 grid(ncols * g.tiles());
-    QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL(k_resid_next<P>, grid, dim3(kThreads),
-                                               lds_bytes(g, 8), st, g, vs, B, X, D, Xn, ld, R32,
-                                               mask, its, part, qs));
+    if (zb) {
+        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_resid_next<P, true>), grid, dim3(kThreads),
+                                                   lds_bytes(g, 8), st, g, vs, B, X, D, Xn, ld,
+                                                   R32, mask, its, part, qs, zb, zn));
+    } else {
+        QO_DISPATCH_PPT(g.ppt, hipLaunchKernelGGL((k_resid_next<P, false>), grid, dim3(kThreads),
+                                                   lds_bytes(g, 8), st, g, vs, B, X, D, Xn, ld,
+                                                   R32, mask, its, part, qs, zb, zn));
+    }
     return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@
 #include "qo_device.h"
 
 #include <algorithm>
+#include <climits>
 
 #ifndef QO_PLANE_ALIAS
 #define QO_PLANE_ALIAS 1
@@ -52,6 +53,8 @@ namespace qo {
 namespace {
 
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 
@@ -558,49 +561,63 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
 // ---------------------------------------------------------------- pencil pass
 //
 // Job = 64 consecutive in-plane positions m of one column, all ns slices along the
-// slowest axis.  A workgroup of NSP / 16 waves works through jobs (persistent: the
+// slowest axis.  A workgroup of NSP / 32 waves works through jobs (persistent: the
 // grid is sized to the resident workgroups); wave w owns slowest-axis rows
-// [16w, 16w+16) and keeps its rows of S_s (symmetric, so the same A operand serves
-// both products) in registers across jobs.
+// [32w, 32w+32) as two blocks of 16 and keeps its rows of S_s (symmetric, so the same
+// A operand serves both products) in registers across jobs.  Each B fragment read from
+// LDS feeds both row blocks, so a product reads the staged tile once per 32 rows.  The
+// 16 columns of position tile j are the positions 4 c + j (c = 0 .. 15): the tile index
+// then moves an LDS address by a constant, so one address register serves every tile.
 //   GEMM1  Yh = S_s X   (X staged m-major: slice index contiguous per position)
 //   scale  Yh[s][m] *= lmin / (kappa (mu_f(m) + mu_s(s)) + vbar)
 //   GEMM2  Z  = S_s Yh
 // With A = S_s X = sc rhat and Yh its scaled FP16 copy, r.z = sum A Yh / (sc^2 lmin)
 // = sum X Z / (sc^2 lmin) (S_s is symmetric), Z = S_s Yh the second product: every wave
 // adds up its share of a job (FP32) as it replaces X by Z in LDS and writes it to
-// rzp[job * NSP / 16 + wave], job = column * npen + position block, so a column's
+// rzp[job * NSP / 32 + wave], job = column * npen + position block, so a column's
 // partials are reduced in a fixed order by the PCG sweep.
-// Thread t moves slices 2 (t >> 3), 2 (t >> 3) + 1 of positions 8 (t & 7) .. + 7: two
-// 16-byte row accesses (eight lanes cover a 128-byte row segment), transposed in
-// registers into 4-byte LDS words.  The next job's rows are loaded during the current
-// job's products.  In the m-major LDS arrays the 16-byte blocks of row m are permuted by
-// XOR with (m >> 3) & 3, which spreads the transposing writes of rows 8 apart over the
-// banks and keeps the 16-byte operand reads contiguous.
+// Thread t moves slices 4 (t >> 3) .. + 3 of positions 8 (t & 7) .. + 7: four 16-byte
+// row accesses (eight lanes cover a 128-byte row segment), transposed in registers into
+// 8-byte LDS words.  The next job's rows are loaded during the current job's products.
+// In the m-major LDS arrays the 16-byte blocks of row m are permuted by XOR with
+// (m >> 3) & 3, which spreads the transposing writes of rows 8 apart over the banks and
+// keeps the 16-byte operand reads contiguous.
 constexpr int kPenMB = 64;
 
-__device__ __forceinline__ int pen_off(int m, int s, int SP) {
-    return m * SP + ((((s >> 3) ^ (m >> 3)) & 3) | ((s >> 3) & ~3)) * 8 + (s & 7);
+// Buffer resource of a byte range [base, base + bytes) for buffer loads and stores on
+// gfx9-class chips (dword 3: 32-bit data format, no swizzle).  An access whose offset
+// lies outside the range returns zeros (load) or is dropped (store), so a store that must
+// not happen is given an out-of-range offset instead of a branch around it.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes,
+                                             0x00020000);
 }
+constexpr int kBufOff = (int)0x80000000u;  // beyond every range used here
+constexpr int kBufNT = 2;                  // cache policy: non-temporal
 
-template <int KS>
-__global__ __launch_bounds__(128 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 3 ? 6 : 4))) void k_dst_pencil(DstPlan p, const _Float16 *__restrict__ Hin,
+template <int KS, bool VEC>
+__global__ __launch_bounds__(64 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 3 ? 4 : KS <= 6 ? 3 : 2))) void k_dst_pencil(DstPlan p, const _Float16 *__restrict__ Hin,
                                                     _Float16 *__restrict__ Hout, long ld,
                                                     int ncols, const float *__restrict__ pcs,
                                                     double *__restrict__ rzp) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int NJ = kPenMB / 16;
+    constexpr int NJ = kPenMB / 16;  // position tiles of 16
+    constexpr int RB = 2;            // row blocks of 16 per wave
     constexpr int NSP = 32 * KS, SP = NSP + 8;
+    constexpr int nw = KS;           // waves per workgroup (the launch uses 64 KS threads)
     const int ns = p.ns, nf = p.nf;
     _Float16 *XT = reinterpret_cast<_Float16 *>(smem);
     _Float16 *YT = XT + kPenMB * SP;
-    // in-plane eigenvalues along x and y, copied once (the per-job lookups would otherwise
-    // each wait out a cache round trip)
-    float *MUX = reinterpret_cast<float *>(YT + kPenMB * SP);
-    float *MUY = MUX + 256;
+    // slowest-axis eigenvalues (-1 past ns), then the in-plane ones along x and y, copied
+    // once (per-job lookups in global memory would each wait out a cache round trip)
+    float *MUS = reinterpret_cast<float *>(YT + kPenMB * SP);
+    float *MUX = MUS + NSP;
+    float *MUY = MUX + ((p.nx + 3) & ~3);
     // per column: the forward scale sc (0: the column is skipped in this PCG iteration),
     // vbar and lmin, so that finding the next job and its constants needs no global load
-    float *CSC = MUY + 256, *CVB = CSC + ncols, *CLM = CVB + ncols;
+    float *CSC = MUS + pen_mu_floats(NSP, p.nx, p.ny), *CVB = CSC + ncols, *CLM = CVB + ncols;
     const int tid = threadIdx.x;
+    for (int i = tid; i < NSP; i += blockDim.x) MUS[i] = i < ns ? p.mus[i] : -1.f;
     for (int i = tid; i < p.nx; i += blockDim.x) MUX[i] = p.mux[i];
     if (p.dim == 3)
         for (int i = tid; i < p.ny; i += blockDim.x) MUY[i] = p.muy[i];
@@ -611,182 +628,227 @@ __global__ __launch_bounds__(128 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 
     }
     __syncthreads();
     const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
-    const int mg = tid & 7, s0 = 2 * (tid >> 3);  // this thread's transfer item
+    const int mg = tid & 7, s0 = 4 * (tid >> 3);  // this thread's transfer item
     const long njobs = (long)ncols * p.npen;
-    const bool vec = (nf % 8) == 0;
+    // LDS offsets (halves) of this lane's accesses at tile 0 / item 0; the tile index j,
+    // the k-chunk ks and the item i add j SP, 32 ks and i SP (the swizzle depends on
+    // bits of the position that these do not change)
+    const int xg = pen_off(4 * lr, 8 * lg, SP);                   // product operands
+    const int xw0 = pen_off(4 * lr, 32 * w + 4 * lg, SP);         // row block 0 results
+    const int xw1 = pen_off(4 * lr, 32 * w + 16 + 4 * lg, SP);    // row block 1 results
+    const int xs = pen_off(8 * mg, s0, SP);                       // transfer items
 
-    // S_s rows 16w + lr, k-chunks of 32: the A operand of both products
-    v8h A[KS];
+    // S_s rows 32w + 16rb + lr, k-chunks of 32: the A operands of both products
+    v8h A[RB][KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-        A[ks] = *reinterpret_cast<const v8h *>(p.Ss + (16 * w + lr) * NSP + 32 * ks + 8 * lg);
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            A[rb][ks] = *reinterpret_cast<const v8h *>(p.Ss + (32 * w + 16 * rb + lr) * NSP +
+                                                       32 * ks + 8 * lg);
 
+    // per-column constants from LDS into scalar registers (an LDS read does not wait for
+    // the prefetch on the vector memory counter, and a job index that stays in scalar
+    // registers keeps the loop's control flow uniform)
+    auto sreg = [](float v) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+    };
     // Jobs are dealt round-robin, so the workgroups resident at one time work on
     // neighbouring positions of the same slices (DRAM pages stay open); columns the PCG
     // skips are passed over.
     auto next_active = [&](long job) {
-        while (job < njobs && CSC[job / p.npen] == 0.f) job += gridDim.x;
-        return job;
+        while (job < njobs && sreg(CSC[job / p.npen]) == 0.f) job += gridDim.x;
+        const unsigned long u = (unsigned long)job;
+        return (long)(((unsigned long)(unsigned)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                      (unsigned)__builtin_amdgcn_readfirstlane((int)u));
     };
-    // rows s0, s0 + 1 at positions m .. m + 7 of a job; clamped unconditional loads in the
-    // vector case, the zeroing outside the grid happens at the LDS store (a select on a
-    // loaded value here would make the compiler wait for the prefetch at once)
-    v8h h0, h1;
+    // rows s0 .. s0 + 3 at positions m .. m + 7 of a job
+    v8h h[4];
     auto job_m = [&](long job) {
         const int col = (int)(job / p.npen);
         return (int)(job - (long)col * p.npen) * kPenMB + 8 * mg;
     };
-    auto load = [&](long job) {
+    // Vector case: buffer accesses relative to the job's first position, so that the
+    // per-thread byte offsets (row s0 + r, positions 8 mg ..) stay fixed across jobs;
+    // rows past ns lie outside the range (loads return 0, stores are dropped)
+    auto row_off = [&](int r) { return ((s0 + r) * nf + 8 * mg) * (int)sizeof(_Float16); };
+    auto job_rsrc = [&](const _Float16 *H, long job) {
         const int col = (int)(job / p.npen);
-        const int m = job_m(job);
-        const _Float16 *src = Hin + (long)col * ld;
-        if (vec) {
-            const _Float16 *q = src + (m < nf ? m : 0);
-            h0 = *reinterpret_cast<const v8h *>(q + (long)min(s0, ns - 1) * nf);
-            h1 = *reinterpret_cast<const v8h *>(q + (long)min(s0 + 1, ns - 1) * nf);
-        } else {
+        const int m0 = (int)(job - (long)col * p.npen) * kPenMB;
+        return buf_rsrc(H + (long)col * ld + m0, (ns * nf - m0) * (int)sizeof(_Float16));
+    };
+    auto load = [&](long job) {
+        if constexpr (VEC) {
+            const __amdgpu_buffer_rsrc_t ri = job_rsrc(Hin, job);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const bool mi = m + i < nf;
-                h0[i] = (mi && s0 < ns) ? src[(long)s0 * nf + m + i] : (_Float16)0.f;
-                h1[i] = (mi && s0 + 1 < ns) ? src[(long)(s0 + 1) * nf + m + i] : (_Float16)0.f;
-            }
+            for (int r = 0; r < 4; ++r)
+                h[r] = __builtin_bit_cast(v8h, __builtin_amdgcn_raw_buffer_load_b128(ri, row_off(r), 0, 0));
+        } else {
+            const int col = (int)(job / p.npen);
+            const int m = job_m(job);
+            const _Float16 *src = Hin + (long)col * ld;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    h[r][i] = (m + i < nf && s0 + r < ns) ? src[(long)(s0 + r) * nf + m + i]
+                                                          : (_Float16)0.f;
         }
     };
-    // slowest-axis eigenvalues of this thread's accumulator rows (the same for every job)
-    float mus[4];
+    // transpose a job's rows into XT: slices s0 .. s0 + 3 of rows 8 mg + i
+    auto stage = [&](long job) {
+        const bool mok = job_m(job) < nf;  // nf % 8 == 0 in the vector case
+        bool ok[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int s = 16 * w + 4 * lg + v;
-        mus[v] = s < ns ? p.mus[s] : -1.f;
-    }
+        for (int r = 0; r < 4; ++r) ok[r] = mok && s0 + r < ns;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            v4h q;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) q[r] = ok[r] ? h[r][i] : (_Float16)0.f;
+            *reinterpret_cast<v4h *>(XT + xs + i * SP) = q;
+        }
+    };
+    // the partial sums of r.z: one per (job, wave); lanes other than 63 store out of range
+    const int offR = lane == 63 ? w * (int)sizeof(double) : kBufOff;
 
     long job = next_active(blockIdx.x);
     if (job >= njobs) return;
     load(job);
-    const int nw = blockDim.x >> 6;
+    // In the vector case every global access of the loop is unconditional: per job four
+    // loads (the next job's rows) followed by five stores (an r.z partial, four rows of Z).
+    // Five stores that the hardware drops (out-of-range offsets) follow the first loads
+    // as well, so on every path into the staging the rows are followed by exactly five
+    // stores and its wait leaves the previous job's stores in flight.
+    if constexpr (VEC) {
+        const v2u zero2 = {0u, 0u};
+        const v4u zero4 = {0u, 0u, 0u, 0u};
+        const __amdgpu_buffer_rsrc_t ro = buf_rsrc(Hout, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(zero2, ro, kBufOff, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            __builtin_amdgcn_raw_buffer_store_b128(zero4, ro, kBufOff + 64 * (r + 1), 0, kBufNT);
+    }
     while (true) {
         // the next job is found before the barrier, so the prefetch after it need not
         // wait for the activity flag
         const long nxt = next_active(job + gridDim.x);
         const int col = (int)(job / p.npen);
         const int m0 = (int)(job - (long)col * p.npen) * kPenMB;
-        // per-column constants from LDS into scalar registers (an LDS read does not wait
-        // for the prefetch on the vector memory counter)
-        auto sreg = [](float v) {
-            return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                 __builtin_bit_cast(int, v)));
-        };
         const float vbar = sreg(CVB[col]);
         const float lmin = sreg(CLM[col]);
         const float scj = sreg(CSC[col]);
-        float muf[NJ];  // in-plane eigenvalue sums of this thread's positions (from LDS)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int m = m0 + 16 * j + lr;
-            if (p.dim == 3) {
-                const int y = m / p.nx;
-                muf[j] = m < nf ? MUX[m - y * p.nx] + MUY[y] : -1.f;
-            } else {
-                muf[j] = m < nf ? MUX[m] : -1.f;
-            }
-        }
-        // transpose into XT: word (s0, s0 + 1) of rows 8 mg + i
-        {
-            const bool mok = job_m(job) < nf;  // nf % 8 == 0 in the vector case
-            const bool oa = mok && s0 < ns, ob = mok && s0 + 1 < ns;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                typedef _Float16 v2h __attribute__((ext_vector_type(2)));
-                v2h pr;
-                pr[0] = oa ? h0[i] : (_Float16)0.f;
-                pr[1] = ob ? h1[i] : (_Float16)0.f;
-                *reinterpret_cast<v2h *>(XT + pen_off(8 * mg + i, s0, SP)) = pr;
-            }
-        }
+        stage(job);
         __syncthreads();
-        if (nxt < njobs) load(nxt);  // in flight during the products below
+        load(nxt < njobs ? nxt : job);  // in flight during the products below
 
-        v4f acc[NJ];
+        v4f acc[RB][NJ];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[rb][j] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
-                const v8h b = lds8(XT + pen_off(16 * j + lr, 32 * ks + 8 * lg, SP));
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[ks], b, acc[j], 0, 0, 0);
+                const v8h b = lds8(XT + xg + j * SP + 32 * ks);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+                    acc[rb][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[rb][ks], b, acc[rb][j], 0, 0, 0);
             }
         // spectral scaling, then Yh m-major into YT
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            v4h h;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float f = 0.f;
-                // hardware reciprocal (about 1 ulp): the product is rounded to FP16 next
-                if (muf[j] >= 0.f && mus[v] >= 0.f)
-                    f = lmin * __builtin_amdgcn_rcpf(p.kap * (muf[j] + mus[v]) + vbar);
-                h[v] = (_Float16)(acc[j][v] * f);
+            // in-plane eigenvalue sum of position m0 + 4 lr + j (-1 past nf)
+            const int m = m0 + 4 * lr + j;
+            float muf;
+            if (p.dim == 3) {
+                const int y = m / p.nx;
+                muf = m < nf ? MUX[m - y * p.nx] + MUY[y] : -1.f;
+            } else {
+                muf = m < nf ? MUX[m] : -1.f;
             }
-            *reinterpret_cast<v4h *>(YT + pen_off(16 * j + lr, 16 * w + 4 * lg, SP)) = h;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int sb = 32 * w + 16 * rb + 4 * lg;
+                const v4f mus = *reinterpret_cast<const v4f *>(MUS + sb);
+                v4h hv;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float f = 0.f;
+                    // hardware reciprocal (about 1 ulp): the product is rounded to FP16 next
+                    if (muf >= 0.f && mus[v] >= 0.f)
+                        f = lmin * __builtin_amdgcn_rcpf(p.kap * (muf + mus[v]) + vbar);
+                    hv[v] = (_Float16)(acc[rb][j][v] * f);
+                }
+                *reinterpret_cast<v4h *>(YT + (rb ? xw1 : xw0) + j * SP) = hv;
+            }
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[rb][j] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
-                const v8h b = lds8(YT + pen_off(16 * j + lr, 32 * ks + 8 * lg, SP));
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[ks], b, acc[j], 0, 0, 0);
+                const v8h b = lds8(YT + xg + j * SP + 32 * ks);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+                    acc[rb][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[rb][ks], b, acc[rb][j], 0, 0, 0);
             }
         // Z m-major into XT (every wave finished GEMM1 before the barrier above), each
         // element after its product with the X it replaces: this lane's share of r.z
         float rzl = 0.f;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            typedef _Float16 v2h __attribute__((ext_vector_type(2)));
-            _Float16 *q = XT + pen_off(16 * j + lr, 16 * w + 4 * lg, SP);
-            const v4h x = *reinterpret_cast<const v4h *>(q);
-            v4h h;
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) h[v] = (_Float16)acc[j][v];
-            // products of FP16 pairs summed in FP32 (v_dot2_f32_f16)
-            rzl = __builtin_amdgcn_fdot2(v2h{x[0], x[1]}, v2h{h[0], h[1]}, rzl, false);
-            rzl = __builtin_amdgcn_fdot2(v2h{x[2], x[3]}, v2h{h[2], h[3]}, rzl, false);
-            *reinterpret_cast<v4h *>(q) = h;
-        }
+            for (int j = 0; j < NJ; ++j) {
+                typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+                _Float16 *q = XT + (rb ? xw1 : xw0) + j * SP;
+                const v4h x = *reinterpret_cast<const v4h *>(q);
+                v4h hv;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) hv[v] = (_Float16)acc[rb][j][v];
+                // products of FP16 pairs summed in FP32 (v_dot2_f32_f16)
+                rzl = __builtin_amdgcn_fdot2(v2h{x[0], x[1]}, v2h{hv[0], hv[1]}, rzl, false);
+                rzl = __builtin_amdgcn_fdot2(v2h{x[2], x[3]}, v2h{hv[2], hv[3]}, rzl, false);
+                *reinterpret_cast<v4h *>(q) = hv;
+            }
         {
             rzl = wave_sum_lane63(rzl);
             // in FP64: sc^2 leaves the FP32 range once ||r|| < ~5e-20 sqrt(Ng)
-            if (lane == 63)
-                rzp[job * nw + w] = (double)rzl / ((double)scj * (double)scj * (double)lmin);
+            const double rz = (double)rzl / ((double)scj * (double)scj * (double)lmin);
+            const __amdgpu_buffer_rsrc_t rr = buf_rsrc(rzp + job * nw, nw * (int)sizeof(double));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, rz), rr, offR, 0, 0);
         }
         __syncthreads();
         {
-            // rows s0, s0 + 1 of Z at positions m .. m + 7
+            // rows s0 .. s0 + 3 of Z at positions m .. m + 7
             const int m = m0 + 8 * mg;
-            v8h z0, z1;
+            v8h z[4];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                typedef _Float16 v2h __attribute__((ext_vector_type(2)));
-                const v2h pr = *reinterpret_cast<const v2h *>(XT + pen_off(8 * mg + i, s0, SP));
-                z0[i] = pr[0];
-                z1[i] = pr[1];
+                const v4h q = *reinterpret_cast<const v4h *>(XT + xs + i * SP);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) z[r][i] = q[r];
             }
-            _Float16 *dst = Hout + (long)col * ld + m;
-            if (vec) {
-                if (m < nf) {
-                    if (s0 < ns) st_out(reinterpret_cast<v8h *>(dst + (long)s0 * nf), z0);
-                    if (s0 + 1 < ns) st_out(reinterpret_cast<v8h *>(dst + (long)(s0 + 1) * nf), z1);
-                }
+            if constexpr (VEC) {
+                // positions past nf (a ragged last job) would land in the next row
+                const __amdgpu_buffer_rsrc_t ro = job_rsrc(Hout, job);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, z[r]), ro,
+                                                           m < nf ? row_off(r) : kBufOff, 0, kBufNT);
             } else {
+                _Float16 *dst = Hout + (long)col * ld + m;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     if (m + i >= nf) break;
-                    if (s0 < ns) dst[(long)s0 * nf + i] = z0[i];
-                    if (s0 + 1 < ns) dst[(long)(s0 + 1) * nf + i] = z1[i];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (s0 + r < ns) dst[(long)(s0 + r) * nf + i] = z[r][i];
                 }
             }
         }
@@ -836,7 +898,7 @@ void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz) {
         p.nslab = (ny + 63) / 64;
     }
     p.npen = (p.nf + kPenMB - 1) / kPenMB;
-    p.rzparts = p.npen * (p.NSP / 16);
+    p.rzparts = p.npen * (p.NSP / 32);
 }
 
 // X (RP x (NXP+8) halves) and, in 3-D, TT (NXP x (NYP+8) halves), then the S_x copy; the
@@ -848,10 +910,11 @@ size_t dst_plane_lds(const DstPlan &p, bool inv) {
     return b;
 }
 
-// XT and YT (64 x (NSP + 8) halves each), the x and y eigenvalues (2 x 256 floats), then
+// XT and YT (64 x (NSP + 8) halves each), the slowest-axis, x and y eigenvalues, then
 // three floats per column (sc, vbar, lmin)
 static size_t dst_pencil_lds(const DstPlan &p, int ncols) {
-    return 2 * (size_t)kPenMB * (p.NSP + 8) * 2 + 2 * 256 * 4 + 3 * sizeof(float) * (size_t)ncols;
+    return 2 * (size_t)kPenMB * (p.NSP + 8) * 2 +
+           sizeof(float) * ((size_t)pen_mu_floats(p.NSP, p.nx, p.ny) + 3 * (size_t)ncols);
 }
 
 hipError_t launch_dst_matrix(int n, int NP, _Float16 *S, hipStream_t st) {
@@ -916,21 +979,31 @@ static hipError_t launch_pencil_ks(const DstPlan &p, const _Float16 *t1, _Float1
                                    int ncols, const float *pcs, double *rzp, hipStream_t st) {
     static int resident[2] = {0, 0};  // {dynamic LDS bytes it was taken for, workgroups}
     const size_t lds = dst_pencil_lds(p, ncols);
-    const int block = 128 * KS;
+    const int block = 64 * KS;
     if (resident[0] != (int)lds || resident[1] <= 0) {
         int dev = 0, cus = 0, per_cu = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dst_pencil<KS>, block, lds);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dst_pencil<KS, true>, block,
+                                                             lds);
         if (e != hipSuccess) return e;
         resident[0] = (int)lds;
         resident[1] = std::max(1, per_cu) * std::max(1, cus);
     }
     const long njobs = (long)ncols * p.npen;
+    // the kernel's buffer ranges (a column of the output, the r.z partials) are addressed
+    // with 32-bit byte offsets
+    if ((long)p.ns * p.nf * (long)sizeof(_Float16) > INT_MAX ||
+        njobs * (block / 64) * (long)sizeof(double) > INT_MAX)
+        return hipErrorInvalidValue;
     const unsigned grid = (unsigned)std::min<long>(njobs, resident[1]);
-    hipLaunchKernelGGL((k_dst_pencil<KS>), dim3(grid), dim3(block), lds, st, p, t1, t2, ld, ncols,
-                       pcs, rzp);
+    if (p.nf % 8 == 0)
+        hipLaunchKernelGGL((k_dst_pencil<KS, true>), dim3(grid), dim3(block), lds, st, p, t1, t2,
+                           ld, ncols, pcs, rzp);
+    else
+        hipLaunchKernelGGL((k_dst_pencil<KS, false>), dim3(grid), dim3(block), lds, st, p, t1,
+                           t2, ld, ncols, pcs, rzp);
     return hipGetLastError();
 }
 

@@ -82,6 +82,20 @@ __host__ __device__ __forceinline__ long bf16_rowblock_index(long m, int c, int 
     return ((m >> 5) * n + c) * 32 + (m & 31);
 }
 
+// Fast-Poisson pencil pass: offset (in halves) of slowest-axis index s of in-plane
+// position m (0 <= m < 64) in an m-major LDS tile with row pitch SP.  The 16-byte blocks
+// of row m are permuted by XOR with (m >> 3) & 3, so rows 8 apart start in different
+// banks while 8 consecutive s (s a multiple of 8) stay contiguous.
+__host__ __device__ __forceinline__ int pen_off(int m, int s, int SP) {
+    return m * SP + ((((s >> 3) ^ (m >> 3)) & 3) | ((s >> 3) & ~3)) * 8 + (s & 7);
+}
+
+// Floats of the pencil pass's LDS ahead of its per-column constants: the slowest-axis
+// eigenvalues (NSP), then those along x and y, each padded to a multiple of 4.
+__host__ __device__ constexpr int pen_mu_floats(int NSP, int nx, int ny) {
+    return NSP + ((nx + 3) & ~3) + ((ny + 3) & ~3);
+}
+
 // Per-column PCG bookkeeping on the device (double-buffered by iteration parity).
 struct PcgState {
     double *rho;    // [2][ncap]

@@ -11,6 +11,9 @@
 //    points when a tile has several planes; the same for the one-sweep PCG tiling.
 //  * dst_plan_geometry: slabs cover the rows, pencil jobs cover the in-plane positions,
 //    padded lengths are multiples of 32 and cover the grid, the LDS of both passes fits.
+//  * pen_off (the pencil pass's swizzled LDS tiles): one to one within a row, contiguous
+//    over 8 indices, and equal to the per-lane base offsets plus the constant steps the
+//    kernel adds for its position tiles, k-chunks and transfer items.
 //  * bf16_rowblock_index is a bijection of [0, ld) x [0, n) onto [0, ld n).
 // Exit status 0 when every check holds; the first failures are printed.
 #include <cstdio>
@@ -129,7 +132,7 @@ static void check_dst(int dim, int nx, int ny, int nz, int ncols) {
     if (dim == 3) CHECK(p.nslab == nz && p.rows == ny, "dst 3-D slabs");
     CHECK((long)p.npen * 64 >= p.nf && (long)(p.npen - 1) * 64 < p.nf, "dst pencils %d for %d",
           p.npen, p.nf);
-    CHECK(p.rzparts == p.npen * (p.NSP / 16), "dst rzparts");
+    CHECK(p.rzparts == p.npen * (p.NSP / 32), "dst rzparts");
     // LDS: plane pass (X, T^T, S_x copy; FP32 staging of the inverse), pencil pass
     size_t xt = (size_t)p.RP * (p.NXP + 8) * 2;
     const size_t tt = (size_t)p.NXP * (p.NYP + 8) * 2;
@@ -138,10 +141,57 @@ static void check_dst(int dim, int nx, int ny, int nz, int ncols) {
     const size_t inv = (size_t)p.RP * (p.NXP + 4) * 4;
     pl = pl > inv ? pl : inv;
     CHECK(pl <= 163840, "dst plane LDS %zu bytes (%dx%dx%d)", pl, nx, ny, nz);
-    const size_t pen = 2 * 64 * (size_t)(p.NSP + 8) * 2 + 2 * 256 * 4 + 12 * (size_t)ncols;
+    const size_t pen = 2 * 64 * (size_t)(p.NSP + 8) * 2 +
+                       4 * ((size_t)pen_mu_floats(p.NSP, nx, ny) + 3 * (size_t)ncols);
     CHECK(pen <= 163840, "dst pencil LDS %zu bytes (%dx%dx%d, %d columns)", pen, nx, ny, nz,
           ncols);
     check_tile_map(ncols < 40 ? ncols : 40, p.nslab);
+}
+
+// The pencil pass's LDS tiles (64 positions x NSP slowest-axis indices, pitch NSP + 8):
+// pen_off maps row m onto [m SP, m SP + NSP) one to one, keeps 8 consecutive indices from
+// a multiple of 8 contiguous, and the kernel's per-lane base offsets plus constant steps
+// (tile j: positions 4 c + j; k-chunk ks; transfer item i) equal pen_off of the element.
+static void check_pencil_lds(int KS) {
+    const int NSP = 32 * KS, SP = NSP + 8;
+    for (int m = 0; m < 64; ++m) {
+        std::vector<char> seen(NSP, 0);
+        for (int s = 0; s < NSP; ++s) {
+            const int o = pen_off(m, s, SP) - m * SP;
+            const bool ok = o >= 0 && o < NSP;
+            CHECK(ok, "pen_off(%d, %d; NSP %d) leaves its row", m, s, NSP);
+            if (!ok) continue;
+            CHECK(!seen[o], "pen_off(%d, .; NSP %d) hits %d twice", m, NSP, o);
+            seen[o] = 1;
+            if (s % 8 == 0)
+                for (int t = 1; t < 8; ++t)
+                    CHECK(pen_off(m, s + t, SP) == pen_off(m, s, SP) + t,
+                          "pen_off(%d, %d..+7; NSP %d) not contiguous", m, s, NSP);
+        }
+    }
+    for (int lane = 0; lane < 64; ++lane) {
+        const int lr = lane & 15, lg = lane >> 4;
+        for (int j = 0; j < 4; ++j) {
+            for (int ks = 0; ks < KS; ++ks)
+                CHECK(pen_off(4 * lr, 8 * lg, SP) + j * SP + 32 * ks ==
+                          pen_off(4 * lr + j, 32 * ks + 8 * lg, SP),
+                      "pencil operand offset (lane %d, j %d, ks %d; NSP %d)", lane, j, ks, NSP);
+            for (int w = 0; w < KS; ++w)
+                for (int rb = 0; rb < 2; ++rb)
+                    CHECK(pen_off(4 * lr, 32 * w + 16 * rb + 4 * lg, SP) + j * SP ==
+                              pen_off(4 * lr + j, 32 * w + 16 * rb + 4 * lg, SP),
+                          "pencil result offset (lane %d, j %d, w %d, rb %d; NSP %d)", lane, j,
+                          w, rb, NSP);
+        }
+    }
+    for (int tid = 0; tid < 64 * KS; ++tid) {
+        const int mg = tid & 7, s0 = 4 * (tid >> 3);
+        CHECK(s0 + 3 < NSP, "pencil transfer rows (tid %d; NSP %d)", tid, NSP);
+        for (int i = 0; i < 8; ++i)
+            CHECK(pen_off(8 * mg, s0, SP) + i * SP == pen_off(8 * mg + i, s0, SP) &&
+                      pen_off(8 * mg + i, s0 + 3, SP) == pen_off(8 * mg + i, s0, SP) + 3,
+                  "pencil transfer offset (tid %d, i %d; NSP %d)", tid, i, NSP);
+    }
 }
 
 static void check_bf16(long ld, int n) {
@@ -199,6 +249,7 @@ int main() {
     for (int nx : {1, 31, 64, 65, 199, 256})
         for (int ny : {1, 2, 63, 64, 65, 199, 256}) check_dst(2, nx, ny, 1, 4096);
     check_dst(3, 96, 96, 96, 4096);
+    for (int KS = 1; KS <= 8; ++KS) check_pencil_lds(KS);
     // row-blocked BF16 operands
     for (long ld : {64L, 128L, 640L, 4096L})
         for (int n : {1, 2, 3, 31, 64, 100}) check_bf16(ld, n);

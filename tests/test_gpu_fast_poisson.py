@@ -49,6 +49,10 @@ CASES_OP = [
     (2, (70, 45), 3),
     (2, (256, 200), 2),
     (2, (17, 130), 3),
+    # slowest axis 97..256: the pencil pass's wider workgroups (4, 6 and 8 waves)
+    (2, (40, 120), 3),
+    (3, (16, 8, 180), 2),
+    (2, (24, 250), 2),
 ]
 
 

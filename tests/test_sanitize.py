@@ -76,7 +76,7 @@ def test_library_host_code_under_asan_ubsan(tmp_path):
     _run([clang + "++", "-fsanitize=address,undefined", drv, *objs, "-L/opt/rocm/lib",
           "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-o", exe])
     env = _cpu_env()
-    env["HIP_VISIBLE_DEVICES"] = ""  # host code only: no device is used even on a GPU machine
+    env["HIP_VISIBLE_DEVICES"] = ""  # host code only: no device is used even where one is present
     env["ROCR_VISIBLE_DEVICES"] = ""
     r = _run([exe], env=env)
     assert "all checks passed" in r.stdout

@@ -653,6 +653,10 @@ def main():
             "refine_inner_tol": args.inner_tol, "pcg_variant": args.pcg_variant,
             "precond": args.precond,
             "parallelism": "single GPU",
+            **({"precond_arithmetic": "DST-I transforms on FP16 MFMA in both the mixed and the "
+                                      "FP64 path; the 1e-10 stop test is on an FP64 residual (the "
+                                      "PCG's in the FP64 path, the refinement's true residual in "
+                                      "the mixed path)"} if args.precond == "fast_poisson" else {}),
         },
     }
     out["timing"] = ("value and ms_per_step: a pass without per-launch events; the kernel times "

@@ -854,7 +854,9 @@ __global__ __launch_bounds__(64 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 3
         }
         if (nxt >= njobs) break;
         job = nxt;
-        __syncthreads();  // XT is rewritten by the next job
+        // no barrier: the next staging writes exactly the XT words this thread has just read
+        // (the same transfer item), and every other access to XT and YT of this job came
+        // before the barrier above
     }
 }
 

@@ -83,8 +83,8 @@ typedef struct {
                                    vbar = max(0, mean(V + sigma)), inverted exactly by type-I
                                    discrete sine transforms (FP16 matrix cores, FP32
                                    accumulation); iteration count independent of h.  Needs
-                                   pcg_variant 0 and n_0, n_1 <= 128, n_2 <= 256 (3-D) or
-                                   n_0, n_1 <= 256 (2-D) */
+                                   pcg_variant 0 and every axis of at most 256 points
+                                   (qo_create returns QO_ERR_ARG otherwise) */
 } qo_config;
 
 typedef struct {

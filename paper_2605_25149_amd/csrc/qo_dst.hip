@@ -216,6 +216,9 @@ __global__ __launch_bounds__(kThreads) void k_pc_prep(int k, int ncols, const in
     }
 }
 
+// 3-D planes of more than 128 padded rows take the plane kernel's BIG form.
+__host__ __device__ inline bool dst_plane_big(const DstPlan &p) { return p.dim == 3 && p.RP > 128; }
+
 // Bytes of the plane pass's X (and, in 3-D, T^T) space in LDS, 16-byte aligned.
 __host__ __device__ inline size_t dst_plane_xt_bytes(const DstPlan &p) {
     size_t b = (size_t)p.RP * (p.NXP + 8) * 2;
@@ -237,12 +240,15 @@ __host__ __device__ inline size_t dst_plane_xt_bytes(const DstPlan &p) {
 // VEC: rows are whole 16-byte groups (nx % 8 == 0): vector loads and stores throughout.
 // FP32 3-D planes (NT <= 8) are held to 80 registers: 6 waves per SIMD, four 6-wave
 // workgroups per CU, as many as their LDS allows.
+// BIG (3-D planes of more than 128 padded rows, up to 256): up to 16 waves per workgroup,
+// S_y fragments for up to 256 rows, and the inverse pass stages its FP32 output in two
+// halves of the rows (the whole slab in FP32 would not fit the LDS).
 // PF (inverse only): store the search direction P = z + beta[c] P_old (P = z when Pold is
 // null) instead of z, and the partial sums of w z^2, w = V + sigma - vbar (vs holds
 // V + sigma per grid point), one per wave: wzp[(c * nslab + slab) * RP / 16 + wave].
-template <typename T, bool INV, int NT, bool VEC, bool PF = false>
-__global__ __launch_bounds__(512)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_dst_plane(DstPlan p, const T *__restrict__ R,
+template <typename T, bool INV, int NT, bool VEC, bool PF = false, bool BIG = false>
+__global__ __launch_bounds__(BIG ? 1024 : 512)
+__attribute__((amdgpu_waves_per_eu(!BIG && sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_dst_plane(DstPlan p, const T *__restrict__ R,
                                                    const _Float16 *__restrict__ Hin,
                                                    _Float16 *__restrict__ Hout,
                                                    float *__restrict__ Z, long ld,
@@ -400,12 +406,13 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
 
     const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
     const int KX = NXP / 32;
-    // this wave's rows of S_y (the A operand of the y-transform; NYP <= 128 in 3-D),
+    // this wave's rows of S_y (the A operand of the y-transform; NYP <= 32 KYM in 3-D),
     // loaded now so that their latency overlaps the x-transform
-    v8h ay[4];
+    constexpr int KYM = BIG ? 8 : 4;
+    v8h ay[KYM];
     if (p.dim == 3) {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
+        for (int ks = 0; ks < KYM; ++ks)
             ay[ks] = *reinterpret_cast<const v8h *>(
                 p.Sy + (16 * w + lr) * p.NYP + 32 * min(ks, p.NYP / 32 - 1) + 8 * lg);
     }
@@ -435,7 +442,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
+        for (int ks = 0; ks < KYM; ++ks) {
             if (ks >= KY) break;
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
@@ -474,86 +481,90 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_d
         }
     } else {
         const int FP = NXP + 4;
-        float *SF = reinterpret_cast<float *>(smem);  // RP x FP floats
+        float *SF = reinterpret_cast<float *>(smem);  // RP / NH x FP floats
         // in FP64: sc lmin exceeds the FP32 range for residuals below ~1e-37 sqrt(Ng)
         const float unscale =
             (float)(1.0 / ((double)sc * (double)(p.clmin ? p.clmin[col] : p.lmin)));
-#pragma unroll
-        for (int j = 0; j < NT; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                SF[(16 * w + 4 * lg + v) * FP + 16 * j + lr] = acc[j][v] * unscale;
-        __syncthreads();
         const int g4 = NXP / 4;
-        if constexpr (PF && VEC) {
-            // each thread owns at most NT groups of 4 (rows * NXP / 4 <= NT * nthr): the
-            // P_old and V + sigma loads are issued together (clamped into the slab), then P
-            // is stored and w z^2 summed
-            const bool first = Pold == nullptr;
-            const float b = first ? 0.f : beta[col];
-            const float vb = p.cvbar ? p.cvbar[col] : p.vbar;
-            const long pbase = base - (long)col * ld;  // the slab's offset within a column
-            float4 po[QF], v4[QF];
+        const bool first = !PF || Pold == nullptr;
+        const float b = first ? 0.f : beta[col];
+        float vb = 0.f;
+        if constexpr (PF) vb = p.cvbar ? p.cvbar[col] : p.vbar;
+        const long pbase = base - (long)col * ld;  // the slab's offset within a column
+        double wz = 0.0;
+        // the slab's rows are staged and stored in NH parts of RH rows (whole waves each)
+        constexpr int NH = BIG ? 2 : 1;
+        const int RH = p.RP / NH;
 #pragma unroll
-            for (int q = 0; q < QF; ++q) {
-                const int it = tid + q * nthr;
-                const int r = it / g4, x = (it - r * g4) * 4;
-                const bool ok = r < rows && x < nx;
-                const long off = ok ? (long)r * nx + x : 0;
-                po[q] = first ? float4{0.f, 0.f, 0.f, 0.f}
-                              : *reinterpret_cast<const float4 *>(Pold + base + off);
-                v4[q] = *reinterpret_cast<const float4 *>(vs + pbase + off);
+        for (int h = 0; h < NH; ++h) {
+            const int r0 = h * RH;
+            if (h) __syncthreads();  // every thread has stored the previous part
+            if (NH == 1 || (16 * w >= r0 && 16 * w < r0 + RH)) {
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        SF[(16 * w - r0 + 4 * lg + v) * FP + 16 * j + lr] = acc[j][v] * unscale;
             }
-            double wz = 0.0;
+            __syncthreads();
+            const int hrows = min(rows - r0, RH);
+            if constexpr (PF && VEC) {
+                // each thread owns at most QH groups of 4 (RH * NXP / 4 <= QH * nthr): the
+                // P_old and V + sigma loads are issued together (clamped into the slab),
+                // then P is stored and w z^2 summed
+                constexpr int QH = QF / NH;
+                float4 po[QH], v4[QH];
 #pragma unroll
-            for (int q = 0; q < QF; ++q) {
-                const int it = tid + q * nthr;
-                const int r = it / g4, x = (it - r * g4) * 4;
-                if (r >= rows || x >= nx) continue;
-                const long i0 = base + (long)r * nx + x;
-                const float4 z4 = *reinterpret_cast<const float4 *>(SF + r * FP + x);
-                const v4f pv = first ? v4f{z4.x, z4.y, z4.z, z4.w}
-                                     : v4f{z4.x + b * po[q].x, z4.y + b * po[q].y,
-                                           z4.z + b * po[q].z, z4.w + b * po[q].w};
-                st_out(reinterpret_cast<v4f *>(Z + i0), pv);
-                wz += (double)((v4[q].x - vb) * z4.x * z4.x + (v4[q].y - vb) * z4.y * z4.y) +
-                      (double)((v4[q].z - vb) * z4.z * z4.z + (v4[q].w - vb) * z4.w * z4.w);
-            }
-            wz = wave_sum_lane63(wz);
-            if ((tid & 63) == 63) wzp[((long)col * p.nslab + slab) * (nthr >> 6) + (tid >> 6)] = wz;
-        } else {
-            const bool first = !PF || Pold == nullptr;
-            const float b = first ? 0.f : beta[col];
-            float vb = 0.f;
-            if constexpr (PF) vb = p.cvbar ? p.cvbar[col] : p.vbar;
-            const long pbase = base - (long)col * ld;
-            double wz = 0.0;
-            for (int it = tid; it < rows * g4; it += nthr) {
-                const int r = it / g4;
-                const int x = (it - r * g4) * 4;
-                if (x >= nx) continue;
-                const long i0 = base + (long)r * nx + x;
-                const float *src = SF + r * FP + x;
-                if constexpr (VEC) {
-                    const float4 z4 = *reinterpret_cast<const float4 *>(src);
-                    st_out(reinterpret_cast<v4f *>(Z + i0), v4f{z4.x, z4.y, z4.z, z4.w});
-                } else {
+                for (int q = 0; q < QH; ++q) {
+                    const int it = tid + q * nthr;
+                    const int rl = it / g4, x = (it - rl * g4) * 4;
+                    const bool ok = rl < hrows && x < nx;
+                    const long off = ok ? (long)(r0 + rl) * nx + x : 0;
+                    po[q] = first ? float4{0.f, 0.f, 0.f, 0.f}
+                                  : *reinterpret_cast<const float4 *>(Pold + base + off);
+                    v4[q] = *reinterpret_cast<const float4 *>(vs + pbase + off);
+                }
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        if (x + i >= nx) break;
-                        Z[i0 + i] = first ? src[i] : src[i] + b * Pold[i0 + i];
-                        if constexpr (PF) {
-                            const float w = vs[pbase + (long)r * nx + x + i] - vb;
-                            wz += (double)(w * src[i] * src[i]);
+                for (int q = 0; q < QH; ++q) {
+                    const int it = tid + q * nthr;
+                    const int rl = it / g4, x = (it - rl * g4) * 4;
+                    if (rl >= hrows || x >= nx) continue;
+                    const long i0 = base + (long)(r0 + rl) * nx + x;
+                    const float4 z4 = *reinterpret_cast<const float4 *>(SF + rl * FP + x);
+                    const v4f pv = first ? v4f{z4.x, z4.y, z4.z, z4.w}
+                                         : v4f{z4.x + b * po[q].x, z4.y + b * po[q].y,
+                                               z4.z + b * po[q].z, z4.w + b * po[q].w};
+                    st_out(reinterpret_cast<v4f *>(Z + i0), pv);
+                    wz += (double)((v4[q].x - vb) * z4.x * z4.x + (v4[q].y - vb) * z4.y * z4.y) +
+                          (double)((v4[q].z - vb) * z4.z * z4.z + (v4[q].w - vb) * z4.w * z4.w);
+                }
+            } else {
+                for (int it = tid; it < hrows * g4; it += nthr) {
+                    const int rl = it / g4;
+                    const int x = (it - rl * g4) * 4;
+                    if (x >= nx) continue;
+                    const long i0 = base + (long)(r0 + rl) * nx + x;
+                    const float *src = SF + rl * FP + x;
+                    if constexpr (VEC) {
+                        const float4 z4 = *reinterpret_cast<const float4 *>(src);
+                        st_out(reinterpret_cast<v4f *>(Z + i0), v4f{z4.x, z4.y, z4.z, z4.w});
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            if (x + i >= nx) break;
+                            Z[i0 + i] = first ? src[i] : src[i] + b * Pold[i0 + i];
+                            if constexpr (PF) {
+                                const float wv = vs[pbase + (long)(r0 + rl) * nx + x + i] - vb;
+                                wz += (double)(wv * src[i] * src[i]);
+                            }
                         }
                     }
                 }
             }
-            if constexpr (PF) {
-                wz = wave_sum_lane63(wz);
-                if ((tid & 63) == 63)
-                    wzp[((long)col * p.nslab + slab) * (nthr >> 6) + (tid >> 6)] = wz;
-            }
+        }
+        if constexpr (PF) {
+            wz = wave_sum_lane63(wz);
+            if ((tid & 63) == 63) wzp[((long)col * p.nslab + slab) * (nthr >> 6) + (tid >> 6)] = wz;
         }
     }
 }
@@ -867,15 +878,8 @@ __global__ __launch_bounds__(64 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 3
 
 static int pad32(int n) { return (n + 31) / 32 * 32; }
 
-const char *dst_plan_check(int dim, const int n[3]) {
-    if (dim == 3) {
-        if (n[0] > 128 || n[1] > 128) return "DST preconditioner: nx, ny must be <= 128 in 3-D";
-        if (n[2] > 256) return "DST preconditioner: nz must be <= 256";
-    } else {
-        if (n[0] > 256 || n[1] > 256) return "DST preconditioner: nx, ny must be <= 256 in 2-D";
-    }
-    return nullptr;
-}
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one CU (gfx950)
+
 
 void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz) {
     p.dim = dim;
@@ -908,8 +912,23 @@ void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz) {
 size_t dst_plane_lds(const DstPlan &p, bool inv) {
     size_t b = dst_plane_xt_bytes(p);
     if (p.NXP <= 128) b += (size_t)p.NXP * (p.NXP + 8) * 2;  // S_x copy
-    if (inv) b = std::max(b, (size_t)p.RP * (p.NXP + 4) * 4);
+    if (inv) b = std::max(b, (size_t)(p.RP / (dst_plane_big(p) ? 2 : 1)) * (p.NXP + 4) * 4);
     return b;
+}
+
+// A 3-D z-plane is transformed by one workgroup of 4 NYP threads with the plane in LDS: the
+// LDS of both plane passes must fit the CU's 160 KiB.
+const char *dst_plan_check(int dim, const int n[3]) {
+    if (n[0] > 256 || n[1] > 256) return "DST preconditioner: nx, ny must be <= 256";
+    if (dim == 3) {
+        if (n[2] > 256) return "DST preconditioner: nz must be <= 256";
+        DstPlan p{};
+        dst_plan_geometry(p, dim, n[0], n[1], n[2]);
+        if (std::max(dst_plane_lds(p, false), dst_plane_lds(p, true)) > kLdsBytes)
+            return "DST preconditioner: a 3-D z-plane (nx x ny, padded to multiples of 32) "
+                   "does not fit the LDS of one workgroup";
+    }
+    return nullptr;
 }
 
 // XT and YT (64 x (NSP + 8) halves each), the slowest-axis, x and y eigenvalues, then
@@ -957,21 +976,30 @@ hipError_t launch_pc_prep(int k, int ncols, const int *mask, PcgState s, long qs
         default: return hipErrorInvalidValue;                 \
     }
 
+// One plane-pass launch: a workgroup of 4 RP threads per (column, slab); the row-vector
+// form when rows are whole 16-byte groups, the BIG form for 3-D planes of more than 128 rows.
+template <typename T, bool INV, bool PF, typename... A>
+static hipError_t launch_plane(const DstPlan &p, int ncols, size_t lds, hipStream_t st, A... args) {
+    const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
+    const bool vec = p.nx % 8 == 0, big = dst_plane_big(p);
+#define QO_PLANE_GO(V, B)                                                                  \
+    QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, INV, NT, V, PF, B>), grid, \
+                                                  block, lds, st, p, args...))
+    if (vec) {
+        if (big) QO_PLANE_GO(true, true) else QO_PLANE_GO(true, false)
+    } else {
+        if (big) QO_PLANE_GO(false, true) else QO_PLANE_GO(false, false)
+    }
+#undef QO_PLANE_GO
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_dst_fwd(const DstPlan &p, const T *R, long ld, int ncols, _Float16 *t1,
                           const float *pcs, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
-    const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
-    if (p.nx % 8 == 0) {
-        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, false, NT, true>), grid,
-                                                      block, dst_plane_lds(p, false), st, p, R,
-                                                      nullptr, t1, nullptr, ld, pcs));
-    } else {
-        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, false, NT, false>), grid,
-                                                      block, dst_plane_lds(p, false), st, p, R,
-                                                      nullptr, t1, nullptr, ld, pcs));
-    }
-    return hipGetLastError();
+    return launch_plane<T, false, false>(p, ncols, dst_plane_lds(p, false), st, R,
+                                         (const _Float16 *)nullptr, t1, (float *)nullptr, ld, pcs);
 }
 
 // Persistent grid: as many workgroups as are resident at once (the runtime's occupancy for
@@ -1028,17 +1056,9 @@ hipError_t launch_dst_pencil(const DstPlan &p, const _Float16 *t1, _Float16 *t2,
 hipError_t launch_dst_inv(const DstPlan &p, const _Float16 *t2, float *Z, long ld, int ncols,
                           const float *pcs, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
-    const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
-    if (p.nx % 8 == 0) {
-        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<float, true, NT, true>), grid,
-                                                      block, dst_plane_lds(p, true), st, p,
-                                                      nullptr, t2, nullptr, Z, ld, pcs));
-    } else {
-        QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<float, true, NT, false>),
-                                                      grid, block, dst_plane_lds(p, true), st, p,
-                                                      nullptr, t2, nullptr, Z, ld, pcs));
-    }
-    return hipGetLastError();
+    return launch_plane<float, true, false>(p, ncols, dst_plane_lds(p, true), st,
+                                            (const float *)nullptr, t2, (_Float16 *)nullptr, Z, ld,
+                                            pcs);
 }
 
 namespace {
@@ -1082,19 +1102,9 @@ hipError_t launch_dst_inv_p(const DstPlan &p, const _Float16 *t2, const float *P
                             const float *beta, float *P, long ld, int ncols, const float *pcs,
                             const float *vs, double *wzp, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
-    const dim3 grid((unsigned)(ncols * p.nslab)), block((unsigned)(64 * (p.RP / 16)));
-    if (p.nx % 8 == 0) {
-        QO_DISPATCH_NT(p.NXP / 16,
-                       hipLaunchKernelGGL((k_dst_plane<float, true, NT, true, true>), grid, block,
-                                          dst_plane_lds(p, true), st, p, nullptr, t2, nullptr, P,
-                                          ld, pcs, Pold, beta, vs, wzp));
-    } else {
-        QO_DISPATCH_NT(p.NXP / 16,
-                       hipLaunchKernelGGL((k_dst_plane<float, true, NT, false, true>), grid, block,
-                                          dst_plane_lds(p, true), st, p, nullptr, t2, nullptr, P,
-                                          ld, pcs, Pold, beta, vs, wzp));
-    }
-    return hipGetLastError();
+    return launch_plane<float, true, true>(p, ncols, dst_plane_lds(p, true), st,
+                                           (const float *)nullptr, t2, (_Float16 *)nullptr, P, ld,
+                                           pcs, Pold, beta, vs, wzp);
 }
 
 hipError_t launch_z_expand(const float *Z32, const float *pcs, double *Z, long ld, long ng,

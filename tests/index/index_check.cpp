@@ -16,6 +16,7 @@
 //    kernel adds for its position tiles, k-chunks and transfer items.
 //  * bf16_rowblock_index is a bijection of [0, ld) x [0, n) onto [0, ld n).
 // Exit status 0 when every check holds; the first failures are printed.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -138,9 +139,13 @@ static void check_dst(int dim, int nx, int ny, int nz, int ncols) {
     const size_t tt = (size_t)p.NXP * (p.NYP + 8) * 2;
     if (dim == 3) xt = xt > tt ? xt : tt;
     size_t pl = xt + (p.NXP <= 128 ? (size_t)p.NXP * (p.NXP + 8) * 2 : 0);
-    const size_t inv = (size_t)p.RP * (p.NXP + 4) * 4;
+    // planes of more than 128 rows (3-D) stage the inverse's FP32 output in two halves
+    const bool big = dim == 3 && p.RP > 128;
+    const size_t inv = (size_t)(p.RP / (big ? 2 : 1)) * (p.NXP + 4) * 4;
     pl = pl > inv ? pl : inv;
     CHECK(pl <= 163840, "dst plane LDS %zu bytes (%dx%dx%d)", pl, nx, ny, nz);
+    CHECK(4 * p.RP <= (big ? 1024 : 512) && (!big || (p.RP / 2) % 16 == 0),
+          "dst plane workgroup of %d threads (%dx%dx%d)", 4 * p.RP, nx, ny, nz);
     const size_t pen = 2 * 64 * (size_t)(p.NSP + 8) * 2 +
                        4 * ((size_t)pen_mu_floats(p.NSP, nx, ny) + 3 * (size_t)ncols);
     CHECK(pen <= 163840, "dst pencil LDS %zu bytes (%dx%dx%d, %d columns)", pen, nx, ny, nz,
@@ -242,10 +247,27 @@ int main() {
                 if (nx <= 256) check_tiling(q, "2-D one-sweep", N, true);
             }
         }
-    // fast-Poisson plans over every admitted size class
-    for (int nx : {1, 2, 7, 31, 32, 33, 64, 96, 100, 127, 128})
-        for (int ny : {1, 5, 32, 96, 128})
-            for (int nz : {1, 3, 32, 96, 200, 256}) check_dst(3, nx, ny, nz, 256);
+    // fast-Poisson plans over every admitted size class.  3-D: admitted exactly when every
+    // axis has at most 256 points and both plane passes fit the LDS, by the padded sizes
+    // (workgroup = 4 padded rows of threads; X and T^T share their space; the S_x copy up to
+    // 128 points; the inverse's FP32 output staged in halves above 128 rows).
+    auto pad32 = [](int v) { return (v + 31) / 32 * 32; };
+    auto lds3 = [&](int nx, int ny) {
+        const size_t X = (size_t)pad32(nx), Y = (size_t)pad32(ny);
+        size_t xt = std::max(Y * (X + 8) * 2, X * (Y + 8) * 2);
+        xt = (xt + 15) / 16 * 16 + (X <= 128 ? X * (X + 8) * 2 : 0);
+        return std::max(xt, (Y > 128 ? Y / 2 : Y) * (X + 4) * 4);
+    };
+    for (int nx : {1, 2, 7, 31, 32, 33, 64, 96, 100, 127, 128, 129, 160, 192, 193, 224, 256, 257})
+        for (int ny : {1, 5, 32, 96, 128, 129, 160, 192, 193, 224, 256, 257})
+            for (int nz : {1, 3, 32, 96, 200, 256, 257}) {
+                const int n[3] = {nx, ny, nz};
+                const bool want = nx <= 256 && ny <= 256 && nz <= 256 && lds3(nx, ny) <= 163840;
+                const bool got = dst_plan_check(3, n) == nullptr;
+                CHECK(want == got, "3-D %dx%dx%d: admitted %d, expected %d", nx, ny, nz, got, want);
+                if (got) check_dst(3, nx, ny, nz, 256);
+            }
+    CHECK(lds3(256, 256) <= 163840, "a 256 x 256 plane exceeds the LDS");
     for (int nx : {1, 31, 64, 65, 199, 256})
         for (int ny : {1, 2, 63, 64, 65, 199, 256}) check_dst(2, nx, ny, 1, 4096);
     check_dst(3, 96, 96, 96, 4096);

@@ -76,7 +76,7 @@ int main(void) {
     c = base(); c.pcg_variant = 2; c.precond = 0; c.precision = QO_MIXED;
     expect_arg(c, "block CG mixed");
     c = base(); c.precond = 2; expect_arg(c, "precond 2");
-    c = base(); c.n[0] = 200; expect_arg(c, "fast-Poisson plane too wide");
+    c = base(); c.n[0] = 257; expect_arg(c, "fast-Poisson axis of more than 256 points");
     c = base(); c.N = 0; expect_arg(c, "N = 0");
     c = base(); c.N = 16 * 12 * 10; expect_arg(c, "N = Ng");
     c = base(); c.kinetic = 0.0; expect_arg(c, "kinetic 0");

@@ -91,7 +91,7 @@ def test_create_rejects_bad_precond_before_device_work():
     lib = binding.load_library()
     cfg = binding.QoConfig()
     cfg.dim = 3
-    cfg.n[0] = cfg.n[1] = cfg.n[2] = 200  # > 128 per in-plane axis in 3-D
+    cfg.n[0], cfg.n[1], cfg.n[2] = 257, 200, 200  # an axis of more than 256 points
     for k in range(3):
         cfg.L[k] = 1.0
     cfg.kinetic, cfg.N = 0.5, 4

@@ -53,6 +53,12 @@ CASES_OP = [
     (2, (40, 120), 3),
     (3, (16, 8, 180), 2),
     (2, (24, 250), 2),
+    # 3-D planes wider or taller than 128 points: 16-wave workgroups above 128 padded rows
+    # (the inverse stages its output in two halves), the largest plane, ragged rows
+    (3, (200, 150, 6), 2),
+    (3, (256, 256, 4), 2),
+    (3, (130, 229, 5), 2),
+    (3, (256, 100, 7), 2),
 ]
 
 
@@ -106,6 +112,34 @@ def test_solve_fast_poisson(torch, B, oracle_mod, dim, n, N, x0, precision):
     assert np.all(res <= 2 * tol)
     Xr = prob.solve_direct(Bm)
     assert np.max(np.abs(Xg - Xr)) <= 1e-8 * np.max(np.abs(Xr))
+    assert np.all(itg <= 25)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_fast_poisson_wide_planes(torch, B, oracle_mod, precision):
+    """A 3-D grid of 184 x 168 planes (more than 128 rows: the plane passes' 16-wave form,
+    with the search-direction epilogue of the PCG): true FP64 residual <= 2 tol per column,
+    at most 25 iterations, and the solution within 1e-5 of the oracle's exact-M PCG
+    solution at the same tolerance (both are 1e-10-residual solutions: their difference is
+    bounded by the condition number, below 1e5 here, times twice the tolerance)."""
+    tol = 1e-10
+    n = (184, 168, 5)
+    V = _potential(3, n)
+    prob = oracle_mod.Problem(3, n, V)
+    Bm = inputs.random_block(prob.ng, 2, seed=4)
+    Xo, it_orc, st, _ = prob.solve_fast_poisson(Bm, tol=tol)
+    assert st == 0
+    with B.Solver(3, n, 2, pcg_tol=tol, pcg_check=1, precision=precision,
+                  precond="fast_poisson") as s:
+        s.set_potential(V)
+        Xg, itg = s.solve(B.as_block(Bm), None)
+        Xg = B.to_numpy(Xg)
+    res = np.linalg.norm(Bm - prob.apply(Xg), axis=0) / np.linalg.norm(Bm, axis=0)
+    print(f"{precision}: iterations gpu {list(itg)} oracle {list(it_orc)}; residual {res}")
+    assert np.all(res <= 2 * tol)
+    dx = np.max(np.abs(Xg - Xo)) / np.max(np.abs(Xo))
+    print(f"max |X_gpu - X_oracle| / max |X_oracle| = {dx:.3e}")
+    assert dx <= 1e-5
     assert np.all(itg <= 25)
 
 
@@ -163,7 +197,8 @@ def test_step_fast_poisson_mixed_matches_fp64(torch, B, oracle_mod):
 
 
 def test_precond_errors(torch, B):
-    """qo_precond needs precond = 1 and a potential; precond needs pcg_variant 0."""
+    """qo_precond needs precond = 1 and a potential; precond needs pcg_variant 0 and
+    axes of at most 256 points."""
     with B.Solver(2, (16, 16), 2) as s:
         s.set_potential(np.zeros(256))
         with pytest.raises(B.QOError, match="QO_ERR_ARG"):
@@ -173,6 +208,9 @@ def test_precond_errors(torch, B):
             s.precond(B.as_block(np.ones((256, 2))))
     with pytest.raises(B.QOError):
         B.Solver(2, (16, 16), 2, precond="fast_poisson", pcg_variant=1)
+    # an axis of more than 256 points
+    with pytest.raises(B.QOError, match="QO_ERR_ARG"):
+        B.Solver(3, (257, 8, 8), 2, precond="fast_poisson")
 
 
 @pytest.mark.gpu

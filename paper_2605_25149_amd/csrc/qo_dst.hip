@@ -242,11 +242,13 @@ __host__ __device__ inline size_t dst_plane_xt_bytes(const DstPlan &p) {
 // workgroups per CU, as many as their LDS allows.
 // BIG (3-D planes of more than 128 padded rows, up to 256): up to 16 waves per workgroup,
 // S_y fragments for up to 256 rows, and the inverse pass stages its FP32 output in two
-// halves of the rows (the whole slab in FP32 would not fit the LDS).
+// halves of the rows (the whole slab in FP32 would not fit the LDS).  SXB: the BIG form
+// with the S_x copy in LDS for planes of 160 or 192 columns (where it fits).
 // PF (inverse only): store the search direction P = z + beta[c] P_old (P = z when Pold is
 // null) instead of z, and the partial sums of w z^2, w = V + sigma - vbar (vs holds
 // V + sigma per grid point), one per wave: wzp[(c * nslab + slab) * RP / 16 + wave].
-template <typename T, bool INV, int NT, bool VEC, bool PF = false, bool BIG = false>
+template <typename T, bool INV, int NT, bool VEC, bool PF = false, bool BIG = false,
+          bool SXB = false>
 __global__ __launch_bounds__(BIG ? 1024 : 512)
 __attribute__((amdgpu_waves_per_eu(!BIG && sizeof(T) == 4 && NT <= 8 ? 6 : 1))) void k_dst_plane(DstPlan p, const T *__restrict__ R,
                                                    const _Float16 *__restrict__ Hin,
@@ -285,12 +287,12 @@ __attribute__((amdgpu_waves_per_eu(!BIG && sizeof(T) == 4 && NT <= 8 ? 6 : 1))) 
     // from clamped addresses, out-of-grid groups zeroed at the conversion), so the slab
     // costs one memory round trip instead of one per group.
     constexpr int QF = NT, QI = NT / 2;
-    // S_x is the B operand of every wave: up to 128 points it is copied into LDS once per
-    // workgroup (pitch NXP + 8, conflict-free 16-byte reads) instead of each wave reading
-    // all of it through L2.  Its first four rows of loads per thread go out with the
+    // S_x is the B operand of every wave: up to 128 points (and with SXB) it is copied into
+    // LDS once per workgroup (pitch NXP + 8, conflict-free 16-byte reads) instead of each
+    // wave reading all of it through L2.  Its first four rows of loads per thread go out with the
     // slab's loads.  It sits after the X / T^T space; the inverse pass's FP32 staging may
     // later cover it (S_x is dead by then).
-    constexpr bool kSxLds = NT <= 8;
+    constexpr bool kSxLds = NT <= 8 || (BIG && SXB);
     constexpr int kSxTotal = NXP * (NXP / 8);
     _Float16 *dstS = reinterpret_cast<_Float16 *>(smem + dst_plane_xt_bytes(p));
     v8h sxv[kSxLds ? 4 : 1];
@@ -878,8 +880,6 @@ __global__ __launch_bounds__(64 * KS) __attribute__((amdgpu_waves_per_eu(KS <= 3
 
 static int pad32(int n) { return (n + 31) / 32 * 32; }
 
-constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one CU (gfx950)
-
 
 void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz) {
     p.dim = dim;
@@ -907,11 +907,21 @@ void dst_plan_geometry(DstPlan &p, int dim, int nx, int ny, int nz) {
     p.rzparts = p.npen * (p.NSP / 32);
 }
 
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one CU (gfx950)
+
+// The plane pass copies S_x into LDS up to 128 points, and in the BIG form up to 192
+// points where the copy fits beside X / T^T.
+static bool dst_plane_sx_lds(const DstPlan &p) {
+    if (p.NXP <= 128) return true;
+    return dst_plane_big(p) && p.NXP <= 192 &&
+           dst_plane_xt_bytes(p) + (size_t)p.NXP * (p.NXP + 8) * 2 <= kLdsBytes;
+}
+
 // X (RP x (NXP+8) halves) and, in 3-D, TT (NXP x (NYP+8) halves), then the S_x copy; the
 // inverse pass also stages its FP32 output (RP x (NXP+4) floats) over the same space.
 size_t dst_plane_lds(const DstPlan &p, bool inv) {
     size_t b = dst_plane_xt_bytes(p);
-    if (p.NXP <= 128) b += (size_t)p.NXP * (p.NXP + 8) * 2;  // S_x copy
+    if (dst_plane_sx_lds(p)) b += (size_t)p.NXP * (p.NXP + 8) * 2;  // S_x copy
     if (inv) b = std::max(b, (size_t)(p.RP / (dst_plane_big(p) ? 2 : 1)) * (p.NXP + 4) * 4);
     return b;
 }
@@ -985,11 +995,21 @@ static hipError_t launch_plane(const DstPlan &p, int ncols, size_t lds, hipStrea
 #define QO_PLANE_GO(V, B)                                                                  \
     QO_DISPATCH_NT(p.NXP / 16, hipLaunchKernelGGL((k_dst_plane<T, INV, NT, V, PF, B>), grid, \
                                                   block, lds, st, p, args...))
+#define QO_PLANE_SX(V)                                                                     \
+    if (p.NXP == 160)                                                                      \
+        hipLaunchKernelGGL((k_dst_plane<T, INV, 10, V, PF, true, true>), grid, block, lds,  \
+                           st, p, args...);                                                \
+    else                                                                                   \
+        hipLaunchKernelGGL((k_dst_plane<T, INV, 12, V, PF, true, true>), grid, block, lds,  \
+                           st, p, args...);
+    // the BIG form with the S_x copy: 160 or 192 columns where it fits (dst_plane_sx_lds)
+    const bool sxb = big && p.NXP > 128 && dst_plane_sx_lds(p);
     if (vec) {
-        if (big) QO_PLANE_GO(true, true) else QO_PLANE_GO(true, false)
+        if (sxb) { QO_PLANE_SX(true) } else if (big) QO_PLANE_GO(true, true) else QO_PLANE_GO(true, false)
     } else {
-        if (big) QO_PLANE_GO(false, true) else QO_PLANE_GO(false, false)
+        if (sxb) { QO_PLANE_SX(false) } else if (big) QO_PLANE_GO(false, true) else QO_PLANE_GO(false, false)
     }
+#undef QO_PLANE_SX
 #undef QO_PLANE_GO
     return hipGetLastError();
 }

@@ -138,9 +138,12 @@ static void check_dst(int dim, int nx, int ny, int nz, int ncols) {
     size_t xt = (size_t)p.RP * (p.NXP + 8) * 2;
     const size_t tt = (size_t)p.NXP * (p.NYP + 8) * 2;
     if (dim == 3) xt = xt > tt ? xt : tt;
-    size_t pl = xt + (p.NXP <= 128 ? (size_t)p.NXP * (p.NXP + 8) * 2 : 0);
-    // planes of more than 128 rows (3-D) stage the inverse's FP32 output in two halves
+    // planes of more than 128 rows (3-D) stage the inverse's FP32 output in two halves;
+    // S_x is copied into LDS up to 128 points, and for such planes up to 192 where it fits
     const bool big = dim == 3 && p.RP > 128;
+    xt = (xt + 15) / 16 * 16;
+    const size_t sx = (size_t)p.NXP * (p.NXP + 8) * 2;
+    size_t pl = xt + (p.NXP <= 128 || (big && p.NXP <= 192 && xt + sx <= 163840) ? sx : 0);
     const size_t inv = (size_t)(p.RP / (big ? 2 : 1)) * (p.NXP + 4) * 4;
     pl = pl > inv ? pl : inv;
     CHECK(pl <= 163840, "dst plane LDS %zu bytes (%dx%dx%d)", pl, nx, ny, nz);
@@ -250,12 +253,15 @@ int main() {
     // fast-Poisson plans over every admitted size class.  3-D: admitted exactly when every
     // axis has at most 256 points and both plane passes fit the LDS, by the padded sizes
     // (workgroup = 4 padded rows of threads; X and T^T share their space; the S_x copy up to
-    // 128 points; the inverse's FP32 output staged in halves above 128 rows).
+    // 128 points, above 128 rows up to 192 where it fits; the inverse's FP32 output staged
+    // in halves above 128 rows).
     auto pad32 = [](int v) { return (v + 31) / 32 * 32; };
     auto lds3 = [&](int nx, int ny) {
         const size_t X = (size_t)pad32(nx), Y = (size_t)pad32(ny);
         size_t xt = std::max(Y * (X + 8) * 2, X * (Y + 8) * 2);
-        xt = (xt + 15) / 16 * 16 + (X <= 128 ? X * (X + 8) * 2 : 0);
+        xt = (xt + 15) / 16 * 16;
+        const size_t sx = X * (X + 8) * 2;
+        xt += X <= 128 || (Y > 128 && X <= 192 && xt + sx <= 163840) ? sx : 0;
         return std::max(xt, (Y > 128 ? Y / 2 : Y) * (X + 4) * 4);
     };
     for (int nx : {1, 2, 7, 31, 32, 33, 64, 96, 100, 127, 128, 129, 160, 192, 193, 224, 256, 257})

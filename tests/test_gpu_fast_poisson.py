@@ -54,11 +54,15 @@ CASES_OP = [
     (3, (16, 8, 180), 2),
     (2, (24, 250), 2),
     # 3-D planes wider or taller than 128 points: 16-wave workgroups above 128 padded rows
-    # (the inverse stages its output in two halves), the largest plane, ragged rows
+    # (the inverse stages its output in two halves), the largest plane, ragged rows (130 x
+    # 229 also takes the S_x copy in LDS)
     (3, (200, 150, 6), 2),
     (3, (256, 256, 4), 2),
     (3, (130, 229, 5), 2),
     (3, (256, 100, 7), 2),
+    # 160 and 192 columns above 128 rows: the 16-wave form with S_x in LDS
+    (3, (192, 176, 5), 2),
+    (3, (160, 144, 6), 2),
 ]
 
 
